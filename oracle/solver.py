@@ -1,0 +1,182 @@
+"""The D2Q9 time step in FP64 (test infrastructure; see ``oracle/__init__``).
+
+State: the pre-collision populations f(t) of Eq. 1, array f[q, y, x].
+One step t -> t+1, in the order the paper's method implies:
+
+  1. moments (Eq. 4) and collision (BGK Eq. 2, or MRT) on fluid nodes -> f*;
+  2. pull streaming f_i(x, t+1) = f*_i(x - c_i, t) (Eq. 1), where
+       * a source left of column 0 or right of column nx-1 is an unknown
+         population, filled in step 4 (this wins at corners);
+       * a source outside rows [0, ny) bounces back off a wall (half-way) or
+         wraps round (periodic laterals, Fig. 2);
+       * a solid source bounces back half-way: f_i(x, t+1) = f*_ibar(x, t)
+         (Eq. 12 read as the half-way variant);
+  3. the momentum-exchange force of Eq. 14 over every fluid-to-body link,
+     F(t) = Delta P / Delta t (Eq. 15), lattice units (Delta x = Delta t = 1);
+  4. boundary columns: Zou & He velocity inlet at x = 0; at x = nx-1 the
+     Zou & He pressure outlet or the neural reconstruction of Eq. 16 with a
+     per-node Zou & He fallback.
+
+Geometry mask values: 0 fluid, 1 body (links to it are force-summed),
+2 inert solid (bounce-back only).  Solid nodes are never updated.
+"""
+import numpy as np
+
+from . import d2q9
+from .d2q9 import C, OPP, W
+from .mlp import forward_bf16
+from .splitmix64 import velocity_noise
+from .zouhe import inlet_velocity, outlet_pressure
+
+
+class Lattice:
+    def __init__(self, mask, tau, *, collision="bgk", s_e=1.0, s_eps=1.0,
+                 s_q=None, lateral="walls", xbc="inout", u_in=0.05,
+                 inlet_profile=None, rho_out=1.0, noise_amp=0.0, seed=0):
+        self.mask = np.ascontiguousarray(mask, dtype=np.uint8)
+        self.ny, self.nx = self.mask.shape
+        self.fluid = self.mask == 0
+        self.tau = float(tau)
+        self.collision = collision
+        self.mrt = (s_e, s_eps, s_q)
+        assert lateral in ("walls", "periodic") and xbc in ("inout", "periodic")
+        self.lateral, self.xbc = lateral, xbc
+        self.u_in = float(u_in)
+        self.inlet_profile = None if inlet_profile is None else \
+            np.asarray(inlet_profile, dtype=np.float64)
+        self.rho_out = float(rho_out)
+        self.outflow = "zouhe"
+        self.mlp = None
+        self.mass_bound = 1e-2
+        self.t = 0
+        self.fx_hist, self.fy_hist, self.mass_hist = [], [], []
+        self.n_fallback = 0
+        # Initial state: f^eq(1, (u_in, 0) + noise) on fluid, f^eq(1, 0) on
+        # solid nodes.
+        nux, nuy = velocity_noise(seed, self.nx, self.ny, noise_amp)
+        ux = np.where(self.fluid, self.u_in + nux, 0.0)
+        uy = np.where(self.fluid, nuy, 0.0)
+        self.f = d2q9.equilibrium(np.ones((self.ny, self.nx)), ux, uy)
+
+    # -- configuration ------------------------------------------------------
+    def set_equilibrium(self, rho, ux, uy):
+        """Replace the state by f^eq(rho, u) (solid nodes: f^eq(1, 0))."""
+        rho = np.where(self.fluid, rho, 1.0)
+        self.f = d2q9.equilibrium(rho, np.where(self.fluid, ux, 0.0),
+                                  np.where(self.fluid, uy, 0.0))
+
+    def set_outflow_nn(self, P, mass_bound=1e-2):
+        """Use the neural reconstruction (Eq. 16) at the outlet column."""
+        self.outflow, self.mlp, self.mass_bound = "nn", P, float(mass_bound)
+
+    def set_outflow_zouhe(self):
+        self.outflow, self.mlp = "zouhe", None
+
+    # -- the step -----------------------------------------------------------
+    def collide(self, f=None):
+        """Post-collision populations f* on fluid nodes (solid nodes copied)."""
+        f = self.f if f is None else f
+        if self.collision == "bgk":
+            fs = d2q9.bgk_collide(f, self.tau)
+        else:
+            fs = d2q9.mrt_collide(f, self.tau, *self.mrt)
+        return np.where(self.fluid[None], fs, f)
+
+    def _source(self, cx, cy):
+        """Source indices of the pull x - c for every node, with the flags
+        'x outside' and 'y outside' after the lateral/periodic rules."""
+        Y, X = np.mgrid[0:self.ny, 0:self.nx]
+        sx, sy = X - cx, Y - cy
+        if self.xbc == "periodic":
+            sx, xout = sx % self.nx, np.zeros_like(sx, dtype=bool)
+        else:
+            xout = (sx < 0) | (sx >= self.nx)
+        if self.lateral == "periodic":
+            sy, yout = sy % self.ny, np.zeros_like(sy, dtype=bool)
+        else:
+            yout = (sy < 0) | (sy >= self.ny)
+        return np.clip(sx, 0, self.nx - 1), np.clip(sy, 0, self.ny - 1), xout, yout
+
+    def stream(self, fstar):
+        """Pull streaming with half-way bounce-back.  Unknown entries (source
+        outside the x-range) are returned as NaN."""
+        fnew = np.empty_like(fstar)
+        for i in range(9):
+            sx, sy, xout, yout = self._source(C[i, 0], C[i, 1])
+            solid_src = (self.mask[sy, sx] != 0) & ~xout & ~yout
+            bounce = (yout | solid_src) & ~xout
+            val = np.where(bounce, fstar[OPP[i]], fstar[i][sy, sx])
+            fnew[i] = np.where(xout, np.nan, val)
+        return fnew
+
+    def _links(self, i):
+        """Fluid nodes whose neighbour x + c_i is a body node."""
+        # x + c_i is the pull source of direction OPP[i].
+        cx, cy = C[OPP[i]]
+        sx, sy, xout, yout = self._source(cx, cy)
+        return self.fluid & ~xout & ~yout & (self.mask[sy, sx] == 1)
+
+    def momentum_exchange(self, fstar, fnew):
+        """Eq. 14-15: Delta P = sum over links (f_i^in c_i - f_ibar^out c_ibar),
+        f^in the post-collision population moving into the body, f^out the
+        population that comes back to the same fluid node."""
+        dP = np.zeros(2)
+        for i in range(1, 9):
+            link = self._links(i)
+            if not link.any():
+                continue
+            f_in = fstar[i][link].sum()
+            f_out = fnew[OPP[i]][link].sum()
+            dP += f_in * C[i] - f_out * C[OPP[i]]
+        return dP          # / Delta t = 1
+
+    def _outlet_nn(self, fnew):
+        L = self.nx - 1
+        feats = np.concatenate([(fnew[:, :, L - 1 - j] - W[:, None]).T
+                                for j in range(3)], axis=1)      # (ny, 27)
+        s = forward_bf16(feats, self.mlp)                        # (ny, 3)
+        g = fnew[:, :, L].copy()
+        for k, q in enumerate((3, 6, 7)):
+            g[q] = fnew[q, :, L - 1] + s[:, k]
+        zh, _ = outlet_pressure(fnew[:, :, L], self.rho_out)
+        # Fallback test, in FP32 like the fused kernel: positivity of the
+        # reconstructed populations and the density jump to column L-1.
+        g32 = g.astype(np.float32)
+        rho_g = g.sum(0).astype(np.float32)
+        rho_prev = fnew[:, :, L - 1].sum(0).astype(np.float32)
+        ok = np.all(g32[[3, 6, 7]] > 0, axis=0) & \
+            (np.abs(rho_g - rho_prev) < np.float32(self.mass_bound))
+        self.n_fallback += int((~ok).sum())
+        return np.where(ok[None], g, zh)
+
+    def step(self, n=1):
+        for _ in range(n):
+            fstar = self.collide()
+            fnew = self.stream(fstar)
+            F = self.momentum_exchange(fstar, fnew)
+            if self.xbc == "inout":
+                ux = self.u_in if self.inlet_profile is None else self.inlet_profile
+                fnew[:, :, 0], _ = inlet_velocity(fnew[:, :, 0], ux, 0.0)
+                if self.outflow == "nn":
+                    fnew[:, :, -1] = self._outlet_nn(fnew)
+                else:
+                    fnew[:, :, -1], _ = outlet_pressure(fnew[:, :, -1], self.rho_out)
+            self.f = np.where(self.fluid[None], fnew, self.f)
+            self.fx_hist.append(F[0])
+            self.fy_hist.append(F[1])
+            self.mass_hist.append(self.f[:, self.fluid].sum())
+            self.t += 1
+        return self
+
+    # -- read-out -------------------------------------------------------------
+    def post_collision(self):
+        """f*(t): the collided state (fluid nodes), solid nodes as stored."""
+        return self.collide()
+
+    def macroscopic(self):
+        return d2q9.moments(self.f)
+
+    def momentum(self):
+        """Total momentum sum_x sum_i c_i f_i over fluid nodes."""
+        fl = self.f[:, self.fluid]
+        return np.array([(C[:, 0, None] * fl).sum(), (C[:, 1, None] * fl).sum()])
