@@ -149,24 +149,36 @@ class Lattice:
         self.n_fallback += int((~ok).sum())
         return np.where(ok[None], g, zh)
 
+    def _advance(self, fstar):
+        """Streaming, force and boundary columns from the post-collision
+        state fstar: returns the pre-collision populations of the next step
+        and the force F of this step."""
+        fnew = self.stream(fstar)
+        F = self.momentum_exchange(fstar, fnew)
+        if self.xbc == "inout":
+            ux = self.u_in if self.inlet_profile is None else self.inlet_profile
+            fnew[:, :, 0], _ = inlet_velocity(fnew[:, :, 0], ux, 0.0)
+            if self.outflow == "nn":
+                fnew[:, :, -1] = self._outlet_nn(fnew)
+            else:
+                fnew[:, :, -1], _ = outlet_pressure(fnew[:, :, -1], self.rho_out)
+        return np.where(self.fluid[None], fnew, fstar), F
+
     def step(self, n=1):
         for _ in range(n):
-            fstar = self.collide()
-            fnew = self.stream(fstar)
-            F = self.momentum_exchange(fstar, fnew)
-            if self.xbc == "inout":
-                ux = self.u_in if self.inlet_profile is None else self.inlet_profile
-                fnew[:, :, 0], _ = inlet_velocity(fnew[:, :, 0], ux, 0.0)
-                if self.outflow == "nn":
-                    fnew[:, :, -1] = self._outlet_nn(fnew)
-                else:
-                    fnew[:, :, -1], _ = outlet_pressure(fnew[:, :, -1], self.rho_out)
+            fnew, F = self._advance(self.collide())
             self.f = np.where(self.fluid[None], fnew, self.f)
             self.fx_hist.append(F[0])
             self.fy_hist.append(F[1])
             self.mass_hist.append(self.f[:, self.fluid].sum())
             self.t += 1
         return self
+
+    def advance_post(self, fstar):
+        """One step expressed on post-collision states: f*(t) -> f*(t+1)
+        (and F(t)).  Does not touch the stored state."""
+        fnew, F = self._advance(np.asarray(fstar, dtype=np.float64))
+        return self.collide(fnew), F
 
     # -- read-out -------------------------------------------------------------
     def post_collision(self):

@@ -1,0 +1,192 @@
+// D2Q9 node arithmetic for gfx950, in offset form.
+//
+// Populations are stored as offsets g_i = f_i - w_i (FP64, FP32 or FP16
+// storage; FP32 arithmetic for the last two).  Every formula below is written
+// on offsets so that no large constant is ever added to a small one:
+//   rho = 1 + sum_i g_i,  j = sum_i c_i g_i  (sum_i w_i c_i = 0),
+//   g_i^eq = w_i (drho + rho (3 c.u + 9/2 (c.u)^2 - 3/2 u.u))      (Eq. 3)
+// Numbering q: 0 (0,0) 1 (1,0) 2 (0,1) 3 (-1,0) 4 (0,-1) 5 (1,1) 6 (-1,1)
+// 7 (-1,-1) 8 (1,-1).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <hip/hip_fp16.h>
+#include <stdint.h>
+
+namespace lbm {
+
+__host__ __device__ constexpr int cx(int q) {
+  return q == 1 || q == 5 || q == 8 ? 1 : (q == 3 || q == 6 || q == 7 ? -1 : 0);
+}
+__host__ __device__ constexpr int cy(int q) {
+  return q == 2 || q == 5 || q == 6 ? 1 : (q == 4 || q == 7 || q == 8 ? -1 : 0);
+}
+__host__ __device__ constexpr int opp(int q) {
+  return q == 0 ? 0 : (q <= 4 ? ((q + 1) & 3) + 1 : ((q - 3) & 3) + 5);
+}
+template <typename T>
+__host__ __device__ constexpr T wgt(int q) {
+  return q == 0 ? T(4) / T(9) : (q <= 4 ? T(1) / T(9) : T(1) / T(36));
+}
+
+static_assert(opp(1) == 3 && opp(2) == 4 && opp(3) == 1 && opp(4) == 2, "opp");
+static_assert(opp(5) == 7 && opp(6) == 8 && opp(7) == 5 && opp(8) == 6, "opp");
+
+// Per-node link word (uint32) built on the host from the geometry mask.
+enum : uint32_t {
+  LINK_BB_SHIFT = 0,      // bit q: population q is pulled by bounce-back
+  LINK_FORCE_SHIFT = 9,   // bit 9+q: ... and its source is a body node
+  LINK_SOLID = 1u << 24,  // the node itself is solid: not updated
+  LINK_INLET = 1u << 25,  // Zou & He velocity column x = 0
+  LINK_OUTLET = 1u << 26  // outflow column x = nx-1
+};
+
+// ---- storage conversion -----------------------------------------------------
+template <typename S> struct Store;
+template <> struct Store<double> {
+  using T = double;
+  __device__ static T ld(const double* p) { return *p; }
+  __device__ static void st(double* p, T v) { __builtin_nontemporal_store(v, p); }
+  __device__ static void st_cached(double* p, T v) { *p = v; }
+};
+template <> struct Store<float> {
+  using T = float;
+  __device__ static T ld(const float* p) { return *p; }
+  __device__ static void st(float* p, T v) { __builtin_nontemporal_store(v, p); }
+  __device__ static void st_cached(float* p, T v) { *p = v; }
+};
+template <> struct Store<__half> {
+  using T = float;
+  __device__ static T ld(const __half* p) { return __half2float(*p); }
+  __device__ static void st(__half* p, T v) {
+    __half h = __float2half_rn(v);
+    __builtin_nontemporal_store(__half_as_ushort(h), reinterpret_cast<unsigned short*>(p));
+  }
+  __device__ static void st_cached(__half* p, T v) { *p = __float2half_rn(v); }
+};
+
+// ---- moments -----------------------------------------------------------------
+template <typename T>
+struct Macro {
+  T drho, rho, jx, jy;
+};
+
+template <typename T>
+__device__ __forceinline__ Macro<T> macro(const T g[9]) {
+  Macro<T> m;
+  m.drho = ((g[0] + g[2] + g[4]) + (g[1] + g[3])) + ((g[5] + g[7]) + (g[6] + g[8]));
+  m.rho = T(1) + m.drho;
+  m.jx = (g[1] - g[3]) + ((g[5] - g[7]) + (g[8] - g[6]));
+  m.jy = (g[2] - g[4]) + ((g[5] - g[7]) + (g[6] - g[8]));
+  return m;
+}
+
+// ---- BGK (Eq. 2) in offset form -------------------------------------------------
+template <typename T>
+__device__ __forceinline__ void collide_bgk(T g[9], T omega) {
+  const Macro<T> m = macro(g);
+  const T inv = T(1) / m.rho;
+  const T ux = m.jx * inv, uy = m.jy * inv;
+  const T usq = T(1.5) * (ux * ux + uy * uy);
+#pragma unroll
+  for (int q = 0; q < 9; ++q) {
+    const T cu = T(cx(q)) * ux + T(cy(q)) * uy;
+    const T geq = wgt<T>(q) * (m.drho + m.rho * (T(3) * cu + T(4.5) * cu * cu - usq));
+    g[q] = g[q] - omega * (g[q] - geq);
+  }
+}
+
+// ---- MRT in offset form ---------------------------------------------------------
+// Orthogonal basis rho, e, eps, jx, qx, jy, qy, pxx, pxy with squared norms
+// 9, 36, 36, 6, 12, 6, 12, 4, 4.  Offsets shift e by -2 and eps by +1 (the
+// moments of the weights), so the equilibria below are offsets as well:
+//   e^eq = -2 drho + 3 |j|^2/rho,  eps^eq = drho - 3 |j|^2/rho,
+//   qx^eq = -jx, qy^eq = -jy, pxx^eq = (jx^2 - jy^2)/rho, pxy^eq = jx jy/rho.
+// Only the six non-conserved moments relax; the change is mapped back by
+// M^T diag(1/norm^2).
+template <typename T>
+struct MrtRates {
+  T s_e, s_eps, s_q, s_nu;
+};
+
+template <typename T>
+__device__ __forceinline__ void collide_mrt(T g[9], const MrtRates<T>& r) {
+  const Macro<T> m = macro(g);
+  const T inv = T(1) / m.rho;
+  const T j2 = (m.jx * m.jx + m.jy * m.jy) * inv;
+  const T sa = g[1] + g[2] + g[3] + g[4];
+  const T sd = g[5] + g[6] + g[7] + g[8];
+  const T e = T(-4) * g[0] - sa + T(2) * sd;
+  const T eps = T(4) * g[0] - T(2) * sa + sd;
+  const T d57 = g[5] - g[7], d86 = g[8] - g[6], d68 = g[6] - g[8];
+  const T qx = T(2) * (g[3] - g[1]) + d57 + d86;
+  const T qy = T(2) * (g[4] - g[2]) + d57 + d68;
+  const T pxx = (g[1] + g[3]) - (g[2] + g[4]);
+  const T pxy = (g[5] + g[7]) - (g[6] + g[8]);
+  const T de = r.s_e * (e - (T(-2) * m.drho + T(3) * j2)) * T(1.0 / 36.0);
+  const T dp = r.s_eps * (eps - (m.drho - T(3) * j2)) * T(1.0 / 36.0);
+  const T dqx = r.s_q * (qx + m.jx) * T(1.0 / 12.0);
+  const T dqy = r.s_q * (qy + m.jy) * T(1.0 / 12.0);
+  const T dxx = r.s_nu * (pxx - (m.jx * m.jx - m.jy * m.jy) * inv) * T(0.25);
+  const T dxy = r.s_nu * (pxy - m.jx * m.jy * inv) * T(0.25);
+  const T a = -de - T(2) * dp;          // shared by q = 1..4
+  const T b = T(2) * de + dp;           // shared by q = 5..8
+  g[0] -= T(4) * (dp - de);
+  g[1] -= a - T(2) * dqx + dxx;
+  g[2] -= a - T(2) * dqy - dxx;
+  g[3] -= a + T(2) * dqx + dxx;
+  g[4] -= a + T(2) * dqy - dxx;
+  g[5] -= b + dqx + dqy + dxy;
+  g[6] -= b - dqx + dqy - dxy;
+  g[7] -= b - dqx - dqy + dxy;
+  g[8] -= b + dqx - dqy - dxy;
+}
+
+// ---- Zou & He columns (Sec. 2.2), offsets ----------------------------------------
+// Velocity inlet at x = 0, prescribed (u, 0), unknowns 1, 5, 8.  The weight
+// part of rho_0 + 2 rho_- is exactly 1, so
+//   rho = (1 + drho_0 + 2 drho_-) / (1 - u),
+//   g1 = g3 + (2/3) rho u,  g5 = g7 + (g4 - g2)/2 + rho u/6,
+//   g8 = g6 - (g4 - g2)/2 + rho u/6.
+template <typename T>
+__device__ __forceinline__ void zouhe_inlet(T g[9], T u) {
+  const T d0 = g[0] + g[2] + g[4];
+  const T dm = g[3] + g[6] + g[7];
+  const T drho = (d0 + T(2) * dm + u) / (T(1) - u);
+  const T ru = (T(1) + drho) * u;
+  const T h = T(0.5) * (g[4] - g[2]);
+  g[1] = g[3] + ru * T(2.0 / 3.0);
+  g[5] = g[7] + h + ru * T(1.0 / 6.0);
+  g[8] = g[6] - h + ru * T(1.0 / 6.0);
+}
+
+// Pressure outlet at x = nx-1, prescribed rho_out and v = 0, unknowns 3, 6, 7:
+//   rho u = rho_0 + 2 rho_+ - rho_out = drho_0 + 2 drho_+ + (1 - rho_out),
+//   g3 = g1 - (2/3) rho u,  g6 = g8 + (g4 - g2)/2 - rho u/6,
+//   g7 = g5 - (g4 - g2)/2 - rho u/6.
+template <typename T>
+__device__ __forceinline__ void zouhe_outlet(T g[9], T one_minus_rho_out) {
+  const T d0 = g[0] + g[2] + g[4];
+  const T dp = g[1] + g[5] + g[8];
+  const T ru = d0 + T(2) * dp + one_minus_rho_out;
+  const T h = T(0.5) * (g[4] - g[2]);
+  g[3] = g[1] - ru * T(2.0 / 3.0);
+  g[6] = g[8] + h - ru * T(1.0 / 6.0);
+  g[7] = g[5] - h - ru * T(1.0 / 6.0);
+}
+
+// ---- SplitMix64, counter form ------------------------------------------------------
+// Output k (k >= 1) of the stream seeded with s is the finaliser applied to
+// s + k * 0x9e3779b97f4a7c15 (Steele, Lea & Flood 2014).
+__host__ __device__ inline uint64_t splitmix64_at(uint64_t seed, uint64_t k) {
+  uint64_t z = seed + k * 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+__host__ __device__ inline double unit_double(uint64_t r) {
+  return double(r >> 11) * (1.0 / 9007199254740992.0);  // 2^-53
+}
+
+}  // namespace lbm

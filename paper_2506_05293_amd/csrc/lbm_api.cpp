@@ -1,0 +1,531 @@
+// Host side of the C ABI declared in include/lbm.h.
+//
+// The context borrows a caller-owned device workspace and stream; it carves
+// the workspace into the two population buffers, the per-node link words,
+// the partial-sum buffers, the FP64 accumulators, the force history and the
+// network image, and enqueues the kernels of lbm_kernels.hip.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/lbm.h"
+#include "d2q9_dev.hpp"
+#include "lbm_internal.hpp"
+
+using namespace lbm;
+
+namespace {
+
+thread_local std::string g_err;
+
+lbm_status fail(lbm_status code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+lbm_status hip_fail(hipError_t e, const char* what) {
+  return fail(LBM_EHIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+#define HIP_TRY(expr)                                  \
+  do {                                                 \
+    hipError_t e_ = (expr);                            \
+    if (e_ != hipSuccess) return hip_fail(e_, #expr);  \
+  } while (0)
+
+size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+size_t elem_size(int precision) {
+  return precision == LBM_FP64 ? 8 : (precision == LBM_FP32_OFFSET ? 4 : 2);
+}
+
+int rows_per_block() {
+  const char* e = getenv("LBM_ROWS_PER_BLOCK");
+  int r = e ? atoi(e) : 1;
+  return r < 1 ? 1 : (r > 64 ? 64 : r);
+}
+
+struct Layout {
+  int pitch, nchunk, rows, ntx, nty, nn_max, nblocks_max;
+  int64_t plane;
+  size_t A, B, links, chunk, inlet, part0, part1, acc, hist, mlp, total;
+};
+
+Layout make_layout(const lbm_params& p) {
+  Layout L{};
+  L.pitch = int(align_up(size_t(p.nx), 64));
+  L.nchunk = (p.nx + kChunk - 1) / kChunk;
+  L.rows = rows_per_block();
+  L.ntx = L.nchunk;
+  L.nty = (p.ny + L.rows - 1) / L.rows;
+  L.nn_max = (p.ny + kNnRows - 1) / kNnRows;
+  L.nblocks_max = 1 + L.nn_max + L.ntx * L.nty;
+  L.plane = int64_t(p.ny) * L.pitch;
+  const size_t pop = size_t(9) * size_t(L.plane) * elem_size(p.precision);
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    size_t at = o;
+    o = align_up(o + bytes, 256);
+    return at;
+  };
+  L.A = take(pop);
+  L.B = take(pop);
+  L.links = take(size_t(L.plane) * 4);
+  L.chunk = take(size_t(p.ny) * L.nchunk);
+  L.inlet = take(size_t(p.ny) * 8);
+  L.part0 = take(size_t(L.nblocks_max) * kPartials * 8);
+  L.part1 = take(size_t(L.nblocks_max) * kPartials * 8);
+  L.acc = take(sizeof(Acc));
+  L.hist = take(size_t(std::max<int64_t>(p.history_cap, 0)) * 3 * 8);
+  L.mlp = take(sizeof(MlpDev));
+  L.total = o;
+  return L;
+}
+
+lbm_status check_params(const lbm_params* p) {
+  if (!p) return fail(LBM_EINVAL, "params is NULL");
+  if (p->nx < 8 || p->ny < 8) return fail(LBM_EINVAL, "nx, ny must be >= 8 (got %d, %d)", p->nx, p->ny);
+  if (int64_t(p->nx) * p->ny > (int64_t(1) << 31))
+    return fail(LBM_EINVAL, "lattice too large (%d x %d)", p->nx, p->ny);
+  if (p->precision < LBM_FP64 || p->precision > LBM_FP16_OFFSET)
+    return fail(LBM_EINVAL, "bad precision %d", p->precision);
+  if (p->collision != LBM_BGK && p->collision != LBM_MRT)
+    return fail(LBM_EINVAL, "bad collision %d", p->collision);
+  if (p->lateral != LBM_LATERAL_WALLS && p->lateral != LBM_LATERAL_PERIODIC)
+    return fail(LBM_EINVAL, "bad lateral %d", p->lateral);
+  if (p->xbc != LBM_X_INOUT && p->xbc != LBM_X_PERIODIC) return fail(LBM_EINVAL, "bad xbc %d", p->xbc);
+  if (!(p->tau > 0.5) || !std::isfinite(p->tau)) return fail(LBM_EINVAL, "tau must be > 0.5 (got %g)", p->tau);
+  if (!std::isfinite(p->u_in) || std::fabs(p->u_in) >= 0.5)
+    return fail(LBM_EINVAL, "|u_in| must be < 0.5 (got %g)", p->u_in);
+  if (!(p->rho_out > 0)) return fail(LBM_EINVAL, "rho_out must be > 0");
+  if (p->history_cap < 0) return fail(LBM_EINVAL, "history_cap must be >= 0");
+  return LBM_OK;
+}
+
+uint16_t bf16_bits(float f) {
+  uint32_t u;
+  memcpy(&u, &f, 4);
+  if ((u & 0x7F800000u) == 0x7F800000u && (u & 0x007FFFFFu)) return 0x7FC0;
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return uint16_t(u >> 16);
+}
+
+}  // namespace
+
+struct lbm_ctx {
+  lbm_params p;
+  Layout lay;
+  hipStream_t stream;
+  char* ws;
+  void* buf[2];
+  int cur;          // buf[cur] holds the post-collision state
+  void* part[2];
+  int pcur;         // part[pcur] is written by the next step
+  bool pending;     // part[pcur ^ 1] holds partials not yet reduced
+  bool geometry;
+  bool has_profile;
+  int outflow;
+  int n_nn;
+  double n_fluid;
+  int64_t steps;
+
+  uint32_t* links() { return reinterpret_cast<uint32_t*>(ws + lay.links); }
+  uint8_t* chunk() { return reinterpret_cast<uint8_t*>(ws + lay.chunk); }
+  double* inlet() { return reinterpret_cast<double*>(ws + lay.inlet); }
+  Acc* acc() { return reinterpret_cast<Acc*>(ws + lay.acc); }
+  double* hist() { return reinterpret_cast<double*>(ws + lay.hist); }
+  MlpDev* mlp() { return reinterpret_cast<MlpDev*>(ws + lay.mlp); }
+  size_t pop_bytes() const { return size_t(9) * size_t(lay.plane) * elem_size(p.precision); }
+
+  StepLaunch launch() {
+    StepLaunch L{};
+    L.precision = p.precision;
+    L.collision = p.collision;
+    L.A = buf[cur];
+    L.B = buf[cur ^ 1];
+    L.links = links();
+    L.chunk = chunk();
+    L.inlet = has_profile ? inlet() : nullptr;
+    L.part_w = part[pcur];
+    L.part_r = part[pcur ^ 1];
+    L.acc = acc();
+    L.hist = hist();
+    L.hist_cap = p.history_cap;
+    L.mlp = mlp();
+    L.nx = p.nx;
+    L.ny = p.ny;
+    L.pitch = lay.pitch;
+    L.nchunk = lay.nchunk;
+    L.plane = lay.plane;
+    L.rows = lay.rows;
+    L.ntx = lay.ntx;
+    L.nty = lay.nty;
+    L.n_nn = n_nn;
+    L.nblocks = 1 + n_nn + lay.ntx * lay.nty;
+    L.xper = p.xbc == LBM_X_PERIODIC;
+    L.yper = p.lateral == LBM_LATERAL_PERIODIC;
+    L.reduce_prev = pending;
+    L.omega = 1.0 / p.tau;
+    L.s_e = p.s_e;
+    L.s_eps = p.s_eps;
+    L.s_q = p.s_q > 0 ? p.s_q : 1.0 / (0.5 + (3.0 / 16.0) / (p.tau - 0.5));
+    L.u_in = p.u_in;
+    L.one_minus_rho_out = 1.0 - p.rho_out;
+    L.n_fluid = n_fluid;
+    return L;
+  }
+
+  // rows of a staging chunk of `per_node` doubles per node that fit in the
+  // spare population buffer
+  int stage_rows(int per_node) const {
+    const size_t bytes = pop_bytes();
+    const size_t row = size_t(per_node) * size_t(p.nx) * 8;
+    return int(std::max<size_t>(1, std::min<size_t>(size_t(p.ny), bytes / row)));
+  }
+};
+
+namespace {
+
+lbm_status reset_counters(lbm_ctx* c) {
+  HIP_TRY(hipMemsetAsync(c->acc(), 0, sizeof(Acc), c->stream));
+  c->steps = 0;
+  c->pending = false;
+  c->pcur = 0;
+  return LBM_OK;
+}
+
+// A was just written; give B the same content (solid nodes are never
+// rewritten by a step, so both buffers must hold them).
+lbm_status mirror_state(lbm_ctx* c) {
+  HIP_TRY(hipMemcpyAsync(c->buf[c->cur ^ 1], c->buf[c->cur], c->pop_bytes(),
+                         hipMemcpyDeviceToDevice, c->stream));
+  return LBM_OK;
+}
+
+lbm_status init_state(lbm_ctx* c, const double* rho, const double* ux, const double* uy) {
+  InitLaunch I{};
+  I.precision = c->p.precision;
+  I.A = c->buf[c->cur];
+  I.B = c->buf[c->cur ^ 1];
+  I.links = c->links();
+  I.nx = c->p.nx;
+  I.ny = c->p.ny;
+  I.pitch = c->lay.pitch;
+  I.plane = c->lay.plane;
+  I.u_in = c->p.u_in;
+  I.noise_amp = c->p.noise_amp;
+  I.seed = c->p.seed;
+  if (!rho) {
+    I.y0 = 0;
+    I.rows = c->p.ny;
+    I.fields = nullptr;
+    HIP_TRY(launch_init(I, c->stream));
+    return LBM_OK;
+  }
+  // host fields are staged through the spare buffer, which the init kernel
+  // does not write; the state is mirrored afterwards
+  double* stage = static_cast<double*>(c->buf[c->cur ^ 1]);
+  I.B = c->buf[c->cur];
+  const int chunk = c->stage_rows(3);
+  const size_t nx = size_t(c->p.nx);
+  for (int y0 = 0; y0 < c->p.ny; y0 += chunk) {
+    const int rows = std::min(chunk, c->p.ny - y0);
+    const size_t n = size_t(rows) * nx;
+    HIP_TRY(hipMemcpyAsync(stage, rho + y0 * nx, n * 8, hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(hipMemcpyAsync(stage + n, ux + y0 * nx, n * 8, hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(hipMemcpyAsync(stage + 2 * n, uy + y0 * nx, n * 8, hipMemcpyHostToDevice, c->stream));
+    I.y0 = y0;
+    I.rows = rows;
+    I.fields = stage;
+    HIP_TRY(launch_init(I, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));   // the stage is reused
+  }
+  return mirror_state(c);
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* lbm_last_error(void) { return g_err.c_str(); }
+
+size_t lbm_workspace_bytes(const lbm_params* p) {
+  if (check_params(p) != LBM_OK) return 0;
+  return make_layout(*p).total;
+}
+
+lbm_status lbm_create(const lbm_params* p, void* dev_workspace, size_t bytes, lbm_ctx** out) {
+  if (!out) return fail(LBM_EINVAL, "out is NULL");
+  *out = nullptr;
+  lbm_status st = check_params(p);
+  if (st) return st;
+  if (!dev_workspace) return fail(LBM_EINVAL, "workspace is NULL");
+  if (reinterpret_cast<uintptr_t>(dev_workspace) % 256)
+    return fail(LBM_EINVAL, "workspace must be 256-byte aligned");
+  const Layout lay = make_layout(*p);
+  if (bytes < lay.total)
+    return fail(LBM_ENOSPACE, "workspace has %zu bytes, needs %zu", bytes, lay.total);
+  lbm_ctx* c = new lbm_ctx();
+  c->p = *p;
+  c->lay = lay;
+  c->stream = static_cast<hipStream_t>(p->stream);
+  c->ws = static_cast<char*>(dev_workspace);
+  c->buf[0] = c->ws + lay.A;
+  c->buf[1] = c->ws + lay.B;
+  c->part[0] = c->ws + lay.part0;
+  c->part[1] = c->ws + lay.part1;
+  c->cur = 0;
+  c->outflow = LBM_OUT_ZOUHE;
+  c->n_nn = 0;
+  *out = c;
+  return LBM_OK;
+}
+
+lbm_status lbm_destroy(lbm_ctx* c) {
+  delete c;
+  return LBM_OK;
+}
+
+lbm_status lbm_set_geometry(lbm_ctx* c, const uint8_t* mask) {
+  if (!c || !mask) return fail(LBM_EINVAL, "NULL argument");
+  const int nx = c->p.nx, ny = c->p.ny, pitch = c->lay.pitch, nch = c->lay.nchunk;
+  const bool xper = c->p.xbc == LBM_X_PERIODIC, yper = c->p.lateral == LBM_LATERAL_PERIODIC;
+  for (int64_t i = 0; i < int64_t(nx) * ny; ++i)
+    if (mask[i] > 2) return fail(LBM_EINVAL, "mask value %d at node %lld", mask[i], (long long)i);
+  if (!xper)
+    for (int y = 0; y < ny; ++y)
+      if (mask[int64_t(y) * nx] || mask[int64_t(y) * nx + nx - 1])
+        return fail(LBM_EINVAL, "columns 0 and nx-1 must be fluid (row %d)", y);
+  std::vector<uint32_t> links(size_t(c->lay.plane), 0u);
+  std::vector<uint8_t> chunk(size_t(ny) * nch, 0);
+  int64_t n_fluid = 0;
+  for (int y = 0; y < ny; ++y) {
+    for (int x = 0; x < nx; ++x) {
+      uint32_t w = 0;
+      if (mask[int64_t(y) * nx + x]) {
+        w = LINK_SOLID;
+      } else {
+        ++n_fluid;
+        if (!xper && x == 0) w |= LINK_INLET;
+        if (!xper && x == nx - 1) w |= LINK_OUTLET;
+        for (int q = 1; q < 9; ++q) {
+          int sx = x - cx(q), sy = y - cy(q);
+          if (sx < 0 || sx >= nx) {
+            if (!xper) continue;               // unknown: inlet / outlet column
+            sx = (sx + nx) % nx;
+          }
+          if (sy < 0 || sy >= ny) {
+            if (!yper) {
+              w |= 1u << (LINK_BB_SHIFT + q);  // wall
+              continue;
+            }
+            sy = (sy + ny) % ny;
+          }
+          const uint8_t m = mask[int64_t(sy) * nx + sx];
+          if (m) w |= 1u << (LINK_BB_SHIFT + q);
+          if (m == 1) w |= 1u << (LINK_FORCE_SHIFT + q);
+        }
+      }
+      links[size_t(y) * pitch + x] = w;
+      if (w) chunk[size_t(y) * nch + (x / kChunk)] = 1;
+    }
+  }
+  HIP_TRY(hipMemcpyAsync(c->links(), links.data(), links.size() * 4, hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(hipMemcpyAsync(c->chunk(), chunk.data(), chunk.size(), hipMemcpyHostToDevice, c->stream));
+  c->n_fluid = double(n_fluid);
+  lbm_status st = init_state(c, nullptr, nullptr, nullptr);
+  if (st) return st;
+  st = reset_counters(c);
+  if (st) return st;
+  HIP_TRY(hipStreamSynchronize(c->stream));     // host vectors go out of scope
+  c->geometry = true;
+  return LBM_OK;
+}
+
+lbm_status lbm_init_fields(lbm_ctx* c, const double* rho, const double* ux, const double* uy) {
+  if (!c || !rho || !ux || !uy) return fail(LBM_EINVAL, "NULL argument");
+  if (!c->geometry) return fail(LBM_ESTATE, "lbm_set_geometry first");
+  lbm_status st = init_state(c, rho, ux, uy);
+  if (st) return st;
+  return reset_counters(c);
+}
+
+lbm_status lbm_set_inlet_profile(lbm_ctx* c, const double* ux) {
+  if (!c) return fail(LBM_EINVAL, "NULL context");
+  if (!ux) {
+    c->has_profile = false;
+    return LBM_OK;
+  }
+  for (int y = 0; y < c->p.ny; ++y)
+    if (!std::isfinite(ux[y]) || std::fabs(ux[y]) >= 0.5)
+      return fail(LBM_EINVAL, "inlet velocity %g at row %d", ux[y], y);
+  HIP_TRY(hipMemcpyAsync(c->inlet(), ux, size_t(c->p.ny) * 8, hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  c->has_profile = true;
+  return LBM_OK;
+}
+
+lbm_status lbm_step(lbm_ctx* c, int64_t nsteps) {
+  if (!c) return fail(LBM_EINVAL, "NULL context");
+  if (!c->geometry) return fail(LBM_ESTATE, "lbm_step before lbm_set_geometry");
+  if (nsteps < 0) return fail(LBM_EINVAL, "nsteps < 0");
+  if (nsteps == 0) return LBM_OK;
+  for (int64_t s = 0; s < nsteps; ++s) {
+    const StepLaunch L = c->launch();
+    HIP_TRY(launch_step(L, c->stream));
+    c->pending = true;
+    c->pcur ^= 1;
+    c->cur ^= 1;
+  }
+  StepLaunch F = c->launch();
+  HIP_TRY(launch_finalize(F, c->stream));
+  c->pending = false;
+  c->steps += nsteps;
+  return LBM_OK;
+}
+
+lbm_status lbm_sync(lbm_ctx* c) {
+  if (!c) return fail(LBM_EINVAL, "NULL context");
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  return LBM_OK;
+}
+
+lbm_status lbm_forces(lbm_ctx* c, lbm_force_out* out) {
+  if (!c || !out) return fail(LBM_EINVAL, "NULL argument");
+  Acc a;
+  HIP_TRY(hipMemcpyAsync(&a, c->acc(), sizeof a, hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  out->fx = a.fx;
+  out->fy = a.fy;
+  out->fx_sum = a.fx_sum;
+  out->fy_sum = a.fy_sum;
+  out->mass = a.mass;
+  out->step = c->steps;
+  out->n_fallback = int64_t(std::llround(a.fallback));
+  out->nonfinite = a.nonfinite;
+  out->reserved = 0;
+  if (a.nonfinite) return fail(LBM_EUNSTABLE, "non-finite force or mass after step %lld", (long long)c->steps);
+  return LBM_OK;
+}
+
+lbm_status lbm_force_history(lbm_ctx* c, double* fx, double* fy, int64_t cap, int64_t* n) {
+  if (!c || !n || (cap > 0 && (!fx || !fy))) return fail(LBM_EINVAL, "NULL argument");
+  const int64_t m = std::min(std::min(c->steps, c->p.history_cap), cap);
+  *n = std::max<int64_t>(m, 0);
+  if (m <= 0) return LBM_OK;
+  std::vector<double> h(size_t(m) * 3);
+  HIP_TRY(hipMemcpyAsync(h.data(), c->hist(), h.size() * 8, hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  for (int64_t t = 0; t < m; ++t) {
+    fx[t] = h[3 * t];
+    fy[t] = h[3 * t + 1];
+  }
+  return LBM_OK;
+}
+
+lbm_status lbm_set_outflow_model(lbm_ctx* c, int32_t kind, const lbm_mlp* w) {
+  if (!c) return fail(LBM_EINVAL, "NULL context");
+  if (kind == LBM_OUT_ZOUHE) {
+    c->outflow = kind;
+    c->n_nn = 0;
+    return LBM_OK;
+  }
+  if (kind != LBM_OUT_NN) return fail(LBM_EINVAL, "bad outflow kind %d", kind);
+  if (c->p.xbc != LBM_X_INOUT) return fail(LBM_EINVAL, "neural outflow needs LBM_X_INOUT");
+  if (!w) return fail(LBM_EINVAL, "weights are NULL");
+  if (w->n_in != 27 || w->n_h1 != 64 || w->n_h2 != 64 || w->n_out != 3)
+    return fail(LBM_EINVAL, "network must be 27-64-64-3 (got %d-%d-%d-%d)", w->n_in, w->n_h1,
+                w->n_h2, w->n_out);
+  if (!w->w1 || !w->b1 || !w->w2 || !w->b2 || !w->w3 || !w->b3 || !w->mu_in || !w->sd_in ||
+      !w->mu_out || !w->sd_out)
+    return fail(LBM_EINVAL, "a weight array is NULL");
+  MlpDev* h = new MlpDev();
+  memset(h, 0, sizeof *h);
+  for (int o = 0; o < 64; ++o)
+    for (int i = 0; i < 27; ++i) h->w1[o * 32 + i] = bf16_bits(w->w1[o * 27 + i]);
+  for (int o = 0; o < 64; ++o)
+    for (int i = 0; i < 64; ++i) h->w2[o * 64 + i] = bf16_bits(w->w2[o * 64 + i]);
+  for (int o = 0; o < 3; ++o)
+    for (int i = 0; i < 64; ++i) h->w3[o * 64 + i] = bf16_bits(w->w3[o * 64 + i]);
+  for (int o = 0; o < 64; ++o) {
+    h->b1[o] = w->b1[o];
+    h->b2[o] = w->b2[o];
+  }
+  for (int o = 0; o < 3; ++o) {
+    h->b3[o] = w->b3[o];
+    h->mu_out[o] = w->mu_out[o];
+    h->sd_out[o] = w->sd_out[o];
+  }
+  for (int i = 0; i < 27; ++i) {
+    h->mu_in[i] = w->mu_in[i];
+    h->inv_sd_in[i] = 1.0f / w->sd_in[i];
+  }
+  h->mass_bound = float(w->mass_bound);
+  hipError_t e = hipMemcpyAsync(c->mlp(), h, sizeof *h, hipMemcpyHostToDevice, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  delete h;
+  if (e != hipSuccess) return hip_fail(e, "upload of the network");
+  c->outflow = kind;
+  c->n_nn = c->lay.nn_max;
+  return LBM_OK;
+}
+
+lbm_status lbm_mlp_forward(lbm_ctx* c, const float* x, float* s, int64_t n) {
+  if (!c || (n > 0 && (!x || !s))) return fail(LBM_EINVAL, "NULL argument");
+  if (c->outflow != LBM_OUT_NN) return fail(LBM_ESTATE, "no network set");
+  if (n < 0) return fail(LBM_EINVAL, "n < 0");
+  HIP_TRY(launch_mlp_forward(c->mlp(), x, s, n, c->stream));
+  return LBM_OK;
+}
+
+lbm_status lbm_read_populations(lbm_ctx* c, double* host) {
+  if (!c || !host) return fail(LBM_EINVAL, "NULL argument");
+  if (!c->geometry) return fail(LBM_ESTATE, "lbm_set_geometry first");
+  double* stage = static_cast<double*>(c->buf[c->cur ^ 1]);
+  const int chunk = c->stage_rows(9);
+  const size_t nx = size_t(c->p.nx), plane = nx * size_t(c->p.ny);
+  for (int y0 = 0; y0 < c->p.ny; y0 += chunk) {
+    const int rows = std::min(chunk, c->p.ny - y0);
+    const size_t n = size_t(rows) * nx;
+    HIP_TRY(launch_read(c->p.precision, c->buf[c->cur], stage, c->p.nx, c->lay.pitch, c->lay.plane,
+                        y0, rows, c->stream));
+    for (int q = 0; q < 9; ++q)
+      HIP_TRY(hipMemcpyAsync(host + q * plane + y0 * nx, stage + q * n, n * 8,
+                             hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+  }
+  return LBM_OK;
+}
+
+lbm_status lbm_write_populations(lbm_ctx* c, const double* host) {
+  if (!c || !host) return fail(LBM_EINVAL, "NULL argument");
+  if (!c->geometry) return fail(LBM_ESTATE, "lbm_set_geometry first");
+  double* stage = static_cast<double*>(c->buf[c->cur ^ 1]);
+  const int chunk = c->stage_rows(9);
+  const size_t nx = size_t(c->p.nx), plane = nx * size_t(c->p.ny);
+  for (int y0 = 0; y0 < c->p.ny; y0 += chunk) {
+    const int rows = std::min(chunk, c->p.ny - y0);
+    const size_t n = size_t(rows) * nx;
+    for (int q = 0; q < 9; ++q)
+      HIP_TRY(hipMemcpyAsync(stage + q * n, host + q * plane + y0 * nx, n * 8,
+                             hipMemcpyHostToDevice, c->stream));
+    // the write-back kernel targets A twice (its B argument is A as well)
+    HIP_TRY(launch_write(c->p.precision, c->buf[c->cur], c->buf[c->cur], stage, c->p.nx,
+                         c->lay.pitch, c->lay.plane, y0, rows, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+  }
+  return mirror_state(c);
+}
+
+}  // extern "C"

@@ -1,0 +1,92 @@
+// Internal declarations shared by the host library and the kernel launchers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "../../include/lbm.h"
+
+namespace lbm {
+
+constexpr int kBlock = 256;        // threads per workgroup (4 wave64)
+constexpr int kChunk = 256;        // x-extent of a bulk tile (one row of a block)
+constexpr int kNnRows = 64;        // outlet rows handled by one neural block
+constexpr int kPartials = 4;       // fx, fy, sum of (rho - 1), fallback count
+
+// Accumulators written only by the reducing workgroup (fixed-order FP64).
+struct Acc {
+  double fx, fy, fx_sum, fy_sum, mass;
+  double fallback;
+  int64_t n_reduced;
+  int32_t nonfinite;
+  int32_t pad;
+};
+
+// Device image of the outflow MLP: BF16 weights padded for 16x16x32 MFMA
+// tiles, FP32 biases and affine maps.
+struct MlpDev {
+  uint16_t w1[64 * 32];   // [out][in], in padded 27 -> 32 with zeros
+  uint16_t w2[64 * 64];   // [out][in]
+  uint16_t w3[16 * 64];   // [out][in], out padded 3 -> 16 with zeros
+  float b1[64], b2[64], b3[16];
+  float mu_in[32], inv_sd_in[32];   // padded entries: mu 0, inv 0
+  float mu_out[4], sd_out[4];
+  float mass_bound;
+  float pad[3];
+};
+
+struct StepLaunch {
+  int precision, collision;
+  const void* A;
+  void* B;
+  const uint32_t* links;
+  const uint8_t* chunk;
+  const double* inlet;
+  void* part_w;
+  const void* part_r;
+  Acc* acc;
+  double* hist;
+  int64_t hist_cap;
+  const MlpDev* mlp;
+  int nx, ny, pitch, nchunk;
+  int64_t plane;
+  int rows;             // rows per bulk block
+  int ntx, nty;         // bulk tiles
+  int n_nn;             // neural outlet blocks (0 for Zou & He)
+  int nblocks;          // whole grid: 1 reducer + n_nn + ntx*nty
+  int xper, yper;
+  int reduce_prev;
+  double omega, s_e, s_eps, s_q, u_in, one_minus_rho_out, n_fluid;
+};
+
+hipError_t launch_step(const StepLaunch& L, hipStream_t s);
+hipError_t launch_finalize(const StepLaunch& L, hipStream_t s);
+
+struct InitLaunch {
+  int precision;
+  void* A;
+  void* B;
+  const uint32_t* links;
+  int nx, ny, pitch;
+  int64_t plane;
+  int y0, rows;              // row range
+  const double* fields;      // staged rho, ux, uy [3][rows][nx], or null
+  double u_in, noise_amp;
+  uint64_t seed;
+};
+hipError_t launch_init(const InitLaunch& L, hipStream_t s);
+
+// Copy rows [y0, y0+rows) of A to/from a dense FP64 staging array
+// [9][rows][nx] of absolute populations.
+hipError_t launch_read(int precision, const void* A, double* out, int nx, int pitch,
+                       int64_t plane, int y0, int rows, hipStream_t s);
+hipError_t launch_write(int precision, void* A, void* B, const double* in, int nx,
+                        int pitch, int64_t plane, int y0, int rows, hipStream_t s);
+
+// Standalone MLP evaluation on n feature rows (same device code as the fused
+// outflow).
+hipError_t launch_mlp_forward(const MlpDev* mlp, const float* x, float* s, int64_t n,
+                              hipStream_t st);
+
+}  // namespace lbm

@@ -1,0 +1,72 @@
+"""The C-ABI library loads and exports every entry point that include/*.h
+declares; argument checks that need no GPU."""
+import ctypes
+import glob
+import os
+import re
+
+import pytest
+
+from paper_2506_05293_amd import lbm
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    names = set()
+    for h in glob.glob(os.path.join(ROOT, "include", "*.h")):
+        src = re.sub(r"/\*.*?\*/", "", open(h).read(), flags=re.S)
+        names |= set(re.findall(r"\b(lbm_[a-z0-9_]+)\s*\(", src))
+    return names
+
+
+def test_every_declared_symbol_is_exported():
+    lib = lbm.library()
+    names = _declared()
+    assert "lbm_step" in names and "lbm_set_outflow_model" in names
+    missing = [n for n in sorted(names) if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def _params(**kw):
+    p = lbm.lbm_params(200, 80, lbm.LBM_FP32_OFFSET, lbm.LBM_MRT, lbm.LBM_LATERAL_WALLS,
+                       lbm.LBM_X_INOUT, 0.56, 1.0, 1.0, 0.0, 0.05, 1.0, 1e-4, 1, 100, None)
+    for k, v in kw.items():
+        setattr(p, k, v)
+    return p
+
+
+def test_workspace_size_scales_with_precision():
+    b64 = lbm.lbm_workspace_bytes(_params(precision=lbm.LBM_FP64))
+    b32 = lbm.lbm_workspace_bytes(_params(precision=lbm.LBM_FP32_OFFSET))
+    b16 = lbm.lbm_workspace_bytes(_params(precision=lbm.LBM_FP16_OFFSET))
+    pop32 = 2 * 9 * 80 * 256 * 4        # two buffers, pitch 256
+    assert b64 > b32 > b16 and b32 >= pop32 and b64 - b32 == pop32
+
+
+@pytest.mark.parametrize("field,value", [("tau", 0.5), ("tau", float("nan")), ("nx", 4),
+                                         ("precision", 7), ("collision", 3), ("u_in", 0.6),
+                                         ("rho_out", 0.0), ("history_cap", -1)])
+def test_bad_parameters_are_rejected(field, value):
+    with pytest.raises(lbm.LbmError) as e:
+        lbm.lbm_workspace_bytes(_params(**{field: value}))
+    assert e.value.status == lbm.LBM_EINVAL
+
+
+def test_create_checks_workspace_without_touching_it():
+    p = _params()
+    need = lbm.lbm_workspace_bytes(p)
+    with pytest.raises(lbm.LbmError) as e:
+        lbm.lbm_create(p, 1 << 20, need - 1)
+    assert e.value.status == lbm.LBM_ENOSPACE
+    with pytest.raises(lbm.LbmError) as e:
+        lbm.lbm_create(p, (1 << 20) + 8, need)
+    assert e.value.status == lbm.LBM_EINVAL      # alignment
+    ctx = lbm.lbm_create(p, 1 << 20, need)        # never dereferenced
+    with pytest.raises(lbm.LbmError) as e:
+        lbm.lbm_step(ctx, 1)
+    assert e.value.status == lbm.LBM_ESTATE
+    with pytest.raises(lbm.LbmError) as e:
+        lbm.lbm_set_outflow_model(ctx, lbm.LBM_OUT_NN, None)
+    assert e.value.status == lbm.LBM_EINVAL
+    lbm.lbm_destroy(ctx)

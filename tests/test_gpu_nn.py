@@ -1,0 +1,178 @@
+"""GPU parity of the neural outflow (Eq. 16) fused into the step, and of the
+MFMA network evaluation, against the oracle's BF16-emulating forward pass.
+
+Tolerance of the network output: both sides round the same standardised
+inputs and the same weights to BF16; the GPU accumulates in FP32 and the
+oracle in FP64, so a hidden activation can land on the other side of a BF16
+rounding boundary.  The bound below lets every hidden unit move by one BF16
+unit in the last place (2^-8 relative) plus FP32 accumulation error (1e-5 of
+the absolute sum), propagated through |W|; most outputs must agree to
+within the FP32 part alone."""
+import numpy as np
+import pytest
+import torch
+
+import cases
+from oracle import mlp as omlp
+from oracle.solver import Lattice as Oracle
+from paper_2506_05293_amd import geometry, lbm
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print("[gpu case]", *a, flush=True)
+
+
+def random_params(seed, w_scale=1.0, out_sd=1e-3):
+    rng = np.random.default_rng(seed)
+
+    def glorot(o, i):
+        a = np.sqrt(6.0 / (o + i)) * w_scale
+        return rng.uniform(-a, a, (o, i))
+    return {"w1": glorot(64, 27), "b1": 0.1 * rng.standard_normal(64),
+            "w2": glorot(64, 64), "b2": 0.1 * rng.standard_normal(64),
+            "w3": glorot(3, 64), "b3": 0.1 * rng.standard_normal(3),
+            "mu_in": 0.002 * rng.standard_normal(27), "sd_in": 0.01 + 0.01 * rng.random(27),
+            "mu_out": 1e-4 * rng.standard_normal(3), "sd_out": out_sd * (1 + rng.random(3))}
+
+
+def _f32(P):
+    return {k: np.asarray(v, np.float32).astype(np.float64) for k, v in P.items()}
+
+
+def output_bound(x, P):
+    """Per-output error bound for the BF16 network (see module docstring)."""
+    b = omlp.bf16_round
+    z = b(omlp.standardise_f32(x, P["mu_in"], P["sd_in"]))
+    W1, W2, W3 = b(P["w1"]), b(P["w2"]), b(P["w3"])
+    a1 = z @ W1.T + P["b1"]
+    h1 = np.tanh(a1)
+    e1 = 2.0**-8 * np.abs(h1) + 1e-5 * (np.abs(z) @ np.abs(W1).T + np.abs(P["b1"]))
+    a2 = b(h1) @ W2.T + P["b2"]
+    h2 = np.tanh(a2)
+    e2 = e1 @ np.abs(W2).T + 2.0**-8 * np.abs(h2) + 1e-5 * (np.abs(h1) @ np.abs(W2).T)
+    e3 = e2 @ np.abs(W3).T + 1e-5 * (np.abs(h2) @ np.abs(W3).T + np.abs(P["b3"]))
+    return e3 * P["sd_out"], 1e-5 * (np.abs(b(h2)) @ np.abs(W3).T + np.abs(P["b3"])) * P["sd_out"]
+
+
+def _lattice_with_net(P, mass_bound=1e9, **kw):
+    case = cases.c1(75.0)
+    args = dict(tau=case["tau"], precision="fp32", collision="bgk", lateral="walls")
+    args.update(kw)
+    g = lbm.Lattice(case["mask"], **args)
+    g.set_outflow_nn(P, mass_bound)
+    return g
+
+
+@pytest.mark.parametrize("n", [1, 63, 64, 1000, 4097])
+def test_mlp_forward_matches_oracle(n):
+    P = _f32(random_params(1))
+    rng = np.random.default_rng(n)
+    x = (0.01 * rng.standard_normal((n, 27))).astype(np.float32)
+    _say("mlp forward", n)
+    g = _lattice_with_net(P)
+    xd = torch.from_numpy(x).cuda()
+    sd = torch.zeros((n, 3), dtype=torch.float32, device="cuda")
+    lbm.lbm_mlp_forward(g.ctx, xd.data_ptr(), sd.data_ptr(), n)
+    torch.cuda.synchronize()
+    s = sd.cpu().numpy().astype(np.float64)
+    ref = omlp.forward_bf16(x.astype(np.float64), P)
+    bound, tight = output_bound(x.astype(np.float64), P)
+    err = np.abs(s - ref)
+    assert np.all(err <= bound + 1e-12), np.max(err / (bound + 1e-30))
+    assert np.mean(err <= tight + 1e-12) > 0.9
+
+
+def test_zero_network_is_copy_outflow_fp64():
+    case = cases.c1(100.0, "mrt")
+    P = {"w1": np.zeros((64, 27)), "b1": np.zeros(64), "w2": np.zeros((64, 64)),
+         "b2": np.zeros(64), "w3": np.zeros((3, 64)), "b3": np.zeros(3),
+         "mu_in": np.zeros(27), "sd_in": np.ones(27), "mu_out": np.zeros(3), "sd_out": np.ones(3)}
+    _say("zero network fp64 c1")
+    g = lbm.Lattice(case["mask"], case["tau"], precision="fp64", collision="mrt",
+                    lateral="walls", u_in=0.05, noise_amp=1e-4, seed=1, history_cap=500)
+    g.set_outflow_nn(P, mass_bound=1e9)
+    g.step(500)
+    o = Oracle(case["mask"], **cases.oracle_kwargs(case))
+    o.set_outflow_nn(P, mass_bound=1e9)
+    o.step(500)
+    fl = case["mask"] == 0
+    f = g.populations()
+    ref = o.post_collision()
+    assert np.max(np.abs(f[:, fl] - ref[:, fl]) / np.abs(ref[:, fl])) < 1e-12
+    assert g.forces().n_fallback == 0 == o.n_fallback
+
+
+@pytest.mark.parametrize("how", ["mass_bound_zero", "nan_weights"])
+def test_forced_fallback_equals_zouhe_bitwise(how):
+    case = cases.ragged("mrt", "periodic")
+    P = _f32(random_params(2))
+    bound = 0.0
+    if how == "nan_weights":
+        P["w2"] = P["w2"].copy()
+        P["w2"][5, 7] = np.nan
+        bound = 1e9
+    _say("forced fallback", how)
+    a = lbm.Lattice(case["mask"], case["tau"], precision="fp32", collision="mrt",
+                    lateral="periodic", u_in=case["u_in"], noise_amp=case["noise_amp"],
+                    seed=case["seed"])
+    b = lbm.Lattice(case["mask"], case["tau"], precision="fp32", collision="mrt",
+                    lateral="periodic", u_in=case["u_in"], noise_amp=case["noise_amp"],
+                    seed=case["seed"])
+    b.set_outflow_nn(P, mass_bound=bound)
+    a.step(120)
+    b.step(120)
+    np.testing.assert_array_equal(a.populations(), b.populations())
+    ny = case["mask"].shape[0]
+    assert b.forces().n_fallback == 120 * ny
+
+
+def test_nn_outflow_run_matches_oracle():
+    case = cases.ragged("bgk", "periodic")
+    P = _f32(random_params(3, w_scale=0.5, out_sd=2e-4))
+    _say("nn outflow run fp64 vs oracle")
+    g = lbm.Lattice(case["mask"], case["tau"], precision="fp64", collision="bgk",
+                    lateral="periodic", u_in=case["u_in"], noise_amp=case["noise_amp"],
+                    seed=case["seed"], history_cap=40)
+    g.set_outflow_nn(P, mass_bound=1e9)
+    g.step(40)
+    o = Oracle(case["mask"], **cases.oracle_kwargs(case))
+    o.set_outflow_nn(P, mass_bound=1e9)
+    o.step(40)
+    fl = case["mask"] == 0
+    f = g.populations()
+    ref = o.post_collision()
+    err = np.max(np.abs(f[:, fl] - ref[:, fl]))
+    print("nn run max abs error", err, flush=True)
+    # corrections are ~1e-4; a BF16 flip moves one by <= 2^-8 of that
+    assert err < 5e-6
+    assert g.forces().n_fallback == 0 == o.n_fallback
+    # the outlet really differs from Zou & He
+    z = Oracle(case["mask"], **cases.oracle_kwargs(case))
+    z.step(40)
+    assert np.max(np.abs(z.post_collision()[:, :, -1] - ref[:, :, -1])) > 1e-5
+
+
+def test_nn_outflow_full_size_one_step():
+    # truncated cylinder lattice 4096 x 512 (D = 64, periodic laterals, MRT,
+    # FP32) with the neural outflow, in the configuration the bench times
+    nx, ny, D = 4096, 512, 64
+    mask = geometry.cylinder(nx, ny, nx - 1 - 8 * D, ny // 2, D)
+    tau = 3 * 0.05 * D / 200 + 0.5
+    P = _f32(random_params(4, w_scale=0.5, out_sd=2e-4))
+    _say("nn full size 4096x512 fp32")
+    g = lbm.Lattice(mask, tau, precision="fp32", collision="mrt", lateral="periodic",
+                    u_in=0.05, noise_amp=1e-4, seed=4)
+    g.set_outflow_nn(P, mass_bound=1e9)
+    g.step(30)
+    f30 = g.populations()
+    g.step(1)
+    f31 = g.populations()
+    o = Oracle(mask, tau, collision="mrt", lateral="periodic", u_in=0.05)
+    o.set_outflow_nn(P, mass_bound=1e9)
+    ref, _ = o.advance_post(f30)
+    fl = mask == 0
+    err = np.max(np.abs(f31[:, fl] - ref[:, fl]))
+    print("nn full-size one-step error", err, flush=True)
+    assert err < 1e-6

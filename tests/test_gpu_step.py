@@ -1,0 +1,220 @@
+"""GPU parity of the fused D2Q9 step against the FP64 oracle, through the
+C ABI.  Tolerances: FP64 storage within 1e-12 relative per population after
+2000 steps; FP32 offsets within 1e-5 in density and 1e-4 in velocity
+(absolute) against the FP64 oracle; FP16 offsets reported with a loose gate."""
+import numpy as np
+import pytest
+
+import cases
+from oracle.solver import Lattice as Oracle
+from paper_2506_05293_amd import geometry, lbm
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print("[gpu case]", *a, flush=True)
+
+
+def _gpu(case, precision="fp64", history_cap=0, **kw):
+    args = dict(tau=case["tau"], precision=precision, collision=case["collision"],
+                lateral=case["lateral"], u_in=case["u_in"], noise_amp=case["noise_amp"],
+                seed=case["seed"], history_cap=history_cap)
+    args.update(kw)
+    return lbm.Lattice(case["mask"], **args)
+
+
+def _rel_err(a, b, fluid):
+    return np.max(np.abs(a[:, fluid] - b[:, fluid]) / np.abs(b[:, fluid]))
+
+
+def test_init_matches_oracle():
+    case = cases.c1()
+    _say("init c1 fp64")
+    g = _gpu(case)
+    o = Oracle(case["mask"], **cases.oracle_kwargs(case))
+    f = g.populations()
+    assert np.max(np.abs(f - o.f) / o.f) < 1e-15
+    # the FP32 state is the FP64 one rounded
+    g32 = _gpu(case, "fp32")
+    f32 = g32.populations()
+    assert np.max(np.abs(f32 - o.f)) < 2e-9
+
+
+def _c1_parity(case, steps):
+    g = _gpu(case, history_cap=steps)
+    g.step(steps)
+    o = Oracle(case["mask"], **cases.oracle_kwargs(case))
+    o.step(steps)
+    fl = case["mask"] == 0
+    err = _rel_err(g.populations(), o.post_collision(), fl)
+    print(f"max relative population error after {steps} steps: {err:.3e}", flush=True)
+    assert err < 1e-12, err
+    fx, fy = g.force_history()
+    assert len(fx) == steps
+    scale = np.max(np.abs(o.fx_hist))
+    assert np.max(np.abs(fx - o.fx_hist)) < 1e-12 * scale
+    assert np.max(np.abs(fy - o.fy_hist)) < 1e-12 * scale
+    out = g.forces()
+    assert out.step == steps and out.nonfinite == 0
+    assert abs(out.fx_sum - np.sum(o.fx_hist)) < 1e-11 * steps * scale
+    assert abs(out.mass - o.mass_hist[-1]) < 1e-12 * o.mass_hist[-1]
+
+
+@pytest.mark.parametrize("steps", [1, 200])
+def test_c1_literal_fp64_parity(steps):
+    # BGK, Re = 100: parity while the literal case is still finite
+    _say("c1 literal fp64 bgk", steps)
+    _c1_parity(cases.c1(), steps)
+
+
+@pytest.mark.parametrize("re,collision", [(75.0, "bgk"), (100.0, "mrt")])
+def test_c1_fp64_parity_2000_steps(re, collision):
+    _say("c1 fp64", collision, "Re", re, 2000)
+    _c1_parity(cases.c1(re, collision), 2000)
+
+
+def test_c1_literal_divergence_is_flagged():
+    # the literal BGK case blows up in the oracle and on the GPU alike; the
+    # library reports it at the next synchronising call
+    case = cases.c1()
+    _say("c1 literal divergence")
+    g = _gpu(case, "fp32")
+    g.step(2000)
+    with pytest.raises(lbm.LbmError) as e:
+        g.forces()
+    assert e.value.status == lbm.LBM_EUNSTABLE
+    assert g.forces(allow_unstable=True).nonfinite == 1
+
+
+@pytest.mark.parametrize("collision,lateral", [("mrt", "periodic"), ("bgk", "walls"),
+                                               ("mrt", "walls"), ("bgk", "periodic")])
+def test_ragged_fp64_parity(collision, lateral):
+    case = cases.ragged(collision, lateral)
+    _say("ragged fp64", collision, lateral)
+    g = _gpu(case, history_cap=300)
+    g.step(300)
+    o = Oracle(case["mask"], **cases.oracle_kwargs(case))
+    o.step(300)
+    fl = case["mask"] == 0
+    assert _rel_err(g.populations(), o.post_collision(), fl) < 1e-12
+    fx, fy = g.force_history()
+    scale = np.max(np.abs(o.fx_hist))
+    assert np.max(np.abs(fx - o.fx_hist)) < 1e-12 * scale
+    assert np.max(np.abs(fy - o.fy_hist)) < 1e-12 * scale
+
+
+def test_fully_periodic_taylor_green_parity():
+    n = 96
+    k = 2 * np.pi / n
+    Y, X = np.mgrid[0:n, 0:n].astype(float)
+    ux = -0.02 * np.cos(k * X) * np.sin(k * Y)
+    uy = 0.02 * np.sin(k * X) * np.cos(k * Y)
+    rho = 1 - 0.25 * 0.02**2 * 3 * (np.cos(2 * k * X) + np.cos(2 * k * Y))
+    mask = np.zeros((n, n), np.uint8)
+    _say("taylor-green fp64 mrt xper")
+    g = lbm.Lattice(mask, 0.6, precision="fp64", collision="mrt", lateral="periodic", xbc="periodic")
+    g.init_fields(rho, ux, uy)
+    g.step(200)
+    o = Oracle(mask, 0.6, collision="mrt", lateral="periodic", xbc="periodic")
+    o.set_equilibrium(rho, ux, uy)
+    o.step(200)
+    assert _rel_err(g.populations(), o.post_collision(), mask == 0) < 1e-12
+
+
+def test_inlet_profile_parity():
+    ny, nx = 24, 64
+    y = np.arange(ny)
+    prof = 4 * 0.03 * (y + 0.5) * (ny - 0.5 - y) / ny**2
+    mask = np.zeros((ny, nx), np.uint8)
+    _say("poiseuille inlet profile fp64")
+    g = lbm.Lattice(mask, 0.8, precision="fp64", collision="mrt", lateral="walls", u_in=0.0)
+    g.set_inlet_profile(prof)
+    g.step(400)
+    o = Oracle(mask, 0.8, collision="mrt", lateral="walls", u_in=0.0, inlet_profile=prof)
+    o.step(400)
+    assert _rel_err(g.populations(), o.post_collision(), mask == 0) < 1e-12
+
+
+@pytest.mark.parametrize("precision,drho_tol,du_tol", [("fp32", 1e-5, 1e-4), ("fp16", 2e-2, 2e-2)])
+@pytest.mark.parametrize("re,collision", [(75.0, "bgk"), (100.0, "mrt")])
+def test_c1_offset_storage(precision, drho_tol, du_tol, re, collision):
+    case = cases.c1(re, collision)
+    _say("c1", precision, collision, re, 2000)
+    g = _gpu(case, precision, history_cap=2000)
+    g.step(2000)
+    o = Oracle(case["mask"], **cases.oracle_kwargs(case))
+    o.step(2000)
+    fl = case["mask"] == 0
+    rho, ux, uy = g.macroscopic()
+    orho, oux, ouy = o.macroscopic()
+    drho = np.max(np.abs(rho - orho)[fl])
+    du = max(np.max(np.abs(ux - oux)[fl]), np.max(np.abs(uy - ouy)[fl]))
+    print(f"{precision}: max|drho| {drho:.3e}  max|du| {du:.3e}", flush=True)
+    assert drho < drho_tol and du < du_tol
+    fx, fy = g.force_history()
+    assert np.all(np.isfinite(fx)) and np.all(np.isfinite(fy))
+
+
+def test_checkpoint_roundtrip_is_bitwise():
+    case = cases.ragged("mrt", "walls")
+    _say("checkpoint fp32")
+    a = _gpu(case, "fp32")
+    b = _gpu(case, "fp32")
+    a.step(200)
+    b.step(100)
+    f = b.populations()
+    b.write_populations(f)
+    b.step(100)
+    np.testing.assert_array_equal(a.populations(), b.populations())
+
+
+def test_runs_are_deterministic():
+    case = cases.ragged("mrt", "periodic")
+    _say("determinism fp32")
+    a = _gpu(case, "fp32", history_cap=150)
+    b = _gpu(case, "fp32", history_cap=150)
+    a.step(150)
+    b.step(70)
+    b.step(80)
+    np.testing.assert_array_equal(a.populations(), b.populations())
+    np.testing.assert_array_equal(a.force_history()[0], b.force_history()[0])
+    fa, fb = a.forces(), b.forces()
+    assert fa.fx_sum == fb.fx_sum and fa.mass == fb.mass
+
+
+def test_zero_steps_and_state_errors():
+    case = cases.ragged()
+    _say("errors")
+    g = _gpu(case, "fp32")
+    f0 = g.populations()
+    g.step(0)
+    np.testing.assert_array_equal(g.populations(), f0)
+    bad = case["mask"].copy()
+    bad[5, 0] = 1
+    with pytest.raises(lbm.LbmError) as e:
+        lbm.lbm_set_geometry(g.ctx, bad)
+    assert e.value.status == lbm.LBM_EINVAL
+    with pytest.raises(lbm.LbmError):
+        lbm.lbm_step(g.ctx, -1)
+
+
+def test_full_size_c2_one_step_against_oracle():
+    # the bench lattice (4096 x 1024, MRT, FP32 offsets) in the bench's launch
+    # configuration: one step checked node by node against the oracle's step
+    # from the same post-collision state
+    case = cases.c2()
+    _say("c2 full size fp32 mrt")
+    g = _gpu(case, "fp32")
+    g.step(50)
+    f50 = g.populations()
+    g.step(1)
+    f51 = g.populations()
+    o = Oracle(case["mask"], **cases.oracle_kwargs(case))
+    ref, F = o.advance_post(f50)
+    fl = case["mask"] == 0
+    err = np.max(np.abs(f51[:, fl] - ref[:, fl]))
+    print("c2 one-step max abs error", err, flush=True)
+    assert err < 5e-8, err
+    out = g.forces()
+    assert abs(out.fx - F[0]) < 1e-5 * abs(F[0]) + 1e-9 and out.step == 51
