@@ -42,25 +42,34 @@ enum : uint32_t {
 };
 
 // ---- storage conversion -----------------------------------------------------
+// ld: plain load; ld_nt: load with the non-temporal hint; st: store with the
+// non-temporal hint (each population is written once per step); st_cached:
+// plain store (set-up kernels).
 template <typename S> struct Store;
 template <> struct Store<double> {
   using T = double;
   __device__ static T ld(const double* p) { return *p; }
+  __device__ static T ld_nt(const double* p) { return __builtin_nontemporal_load(p); }
   __device__ static void st(double* p, T v) { __builtin_nontemporal_store(v, p); }
   __device__ static void st_cached(double* p, T v) { *p = v; }
 };
 template <> struct Store<float> {
   using T = float;
   __device__ static T ld(const float* p) { return *p; }
+  __device__ static T ld_nt(const float* p) { return __builtin_nontemporal_load(p); }
   __device__ static void st(float* p, T v) { __builtin_nontemporal_store(v, p); }
   __device__ static void st_cached(float* p, T v) { *p = v; }
 };
 template <> struct Store<__half> {
   using T = float;
   __device__ static T ld(const __half* p) { return __half2float(*p); }
+  __device__ static T ld_nt(const __half* p) {
+    return __half2float(__ushort_as_half(
+        __builtin_nontemporal_load(reinterpret_cast<const unsigned short*>(p))));
+  }
   __device__ static void st(__half* p, T v) {
-    __half h = __float2half_rn(v);
-    __builtin_nontemporal_store(__half_as_ushort(h), reinterpret_cast<unsigned short*>(p));
+    __builtin_nontemporal_store(__half_as_ushort(__float2half_rn(v)),
+                                reinterpret_cast<unsigned short*>(p));
   }
   __device__ static void st_cached(__half* p, T v) { *p = __float2half_rn(v); }
 };

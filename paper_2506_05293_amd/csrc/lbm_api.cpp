@@ -50,27 +50,35 @@ size_t elem_size(int precision) {
   return precision == LBM_FP64 ? 8 : (precision == LBM_FP32_OFFSET ? 4 : 2);
 }
 
-int rows_per_block() {
-  const char* e = getenv("LBM_ROWS_PER_BLOCK");
-  int r = e ? atoi(e) : 1;
-  return r < 1 ? 1 : (r > 64 ? 64 : r);
+// Bulk path: the vector tile pays off once the grid holds many waves per
+// resident slot (large lattices); small lattices use the scalar tile.
+// LBM_BULK_PATH=scalar|vector overrides the choice.
+constexpr int64_t kVectorPathMinNodes = int64_t(12) << 20;
+
+int choose_path(const lbm_params& p) {
+  const char* e = getenv("LBM_BULK_PATH");
+  if (e && !strcmp(e, "scalar")) return PATH_SCALAR;
+  if (e && !strcmp(e, "vector")) return PATH_VECTOR;
+  return int64_t(p.nx) * p.ny >= kVectorPathMinNodes ? PATH_VECTOR : PATH_SCALAR;
 }
 
 struct Layout {
-  int pitch, nchunk, rows, ntx, nty, nn_max, nblocks_max;
+  int path;
+  int pitch, nchunk, rows, ntx, nty, nn_max, nslots_max;
   int64_t plane;
-  size_t A, B, links, chunk, inlet, part0, part1, acc, hist, mlp, total;
+  size_t A, B, links, chunk, inlet, part0, part1, lvl0, lvl1, acc, hist, mlp, total;
 };
 
 Layout make_layout(const lbm_params& p) {
   Layout L{};
-  L.pitch = int(align_up(size_t(p.nx), 64));
-  L.nchunk = (p.nx + kChunk - 1) / kChunk;
-  L.rows = rows_per_block();
+  L.path = choose_path(p);
+  L.pitch = int(align_up(size_t(p.nx), kChunk));   // whole tiles per row
+  L.nchunk = L.pitch / kChunk;
+  L.rows = tile_rows(L.path);
   L.ntx = L.nchunk;
   L.nty = (p.ny + L.rows - 1) / L.rows;
   L.nn_max = (p.ny + kNnRows - 1) / kNnRows;
-  L.nblocks_max = 1 + L.nn_max + L.ntx * L.nty;
+  L.nslots_max = (L.nn_max + L.ntx * L.nty) * kWaves;
   L.plane = int64_t(p.ny) * L.pitch;
   const size_t pop = size_t(9) * size_t(L.plane) * elem_size(p.precision);
   size_t o = 0;
@@ -84,8 +92,10 @@ Layout make_layout(const lbm_params& p) {
   L.links = take(size_t(L.plane) * 4);
   L.chunk = take(size_t(p.ny) * L.nchunk);
   L.inlet = take(size_t(p.ny) * 8);
-  L.part0 = take(size_t(L.nblocks_max) * kPartials * 8);
-  L.part1 = take(size_t(L.nblocks_max) * kPartials * 8);
+  L.part0 = take(size_t(L.nslots_max) * kPartials * 8);   // one slot per wave
+  L.part1 = take(size_t(L.nslots_max) * kPartials * 8);
+  L.lvl0 = take(size_t(kReducers) * 4 * 8);
+  L.lvl1 = take(size_t(kReducers) * 4 * 8);
   L.acc = take(sizeof(Acc));
   L.hist = take(size_t(std::max<int64_t>(p.history_cap, 0)) * 3 * 8);
   L.mlp = take(sizeof(MlpDev));
@@ -96,7 +106,8 @@ Layout make_layout(const lbm_params& p) {
 lbm_status check_params(const lbm_params* p) {
   if (!p) return fail(LBM_EINVAL, "params is NULL");
   if (p->nx < 8 || p->ny < 8) return fail(LBM_EINVAL, "nx, ny must be >= 8 (got %d, %d)", p->nx, p->ny);
-  if (int64_t(p->nx) * p->ny > (int64_t(1) << 31))
+  // one population plane must stay below 4 GiB (32-bit byte offsets)
+  if ((int64_t(p->nx) + 255) * p->ny * 8 >= (int64_t(1) << 32))
     return fail(LBM_EINVAL, "lattice too large (%d x %d)", p->nx, p->ny);
   if (p->precision < LBM_FP64 || p->precision > LBM_FP16_OFFSET)
     return fail(LBM_EINVAL, "bad precision %d", p->precision);
@@ -131,8 +142,10 @@ struct lbm_ctx {
   void* buf[2];
   int cur;          // buf[cur] holds the post-collision state
   void* part[2];
-  int pcur;         // part[pcur] is written by the next step
-  bool pending;     // part[pcur ^ 1] holds partials not yet reduced
+  double* lvl[2];
+  int pcur;         // part[pcur] and lvl[pcur] are written by the next step
+  bool pend1;       // part[pcur ^ 1] holds the slots of the previous step
+  bool pend2;       // lvl[pcur ^ 1] holds the level-1 sums of the step before
   bool geometry;
   bool has_profile;
   int outflow;
@@ -152,6 +165,7 @@ struct lbm_ctx {
     StepLaunch L{};
     L.precision = p.precision;
     L.collision = p.collision;
+    L.path = lay.path;
     L.A = buf[cur];
     L.B = buf[cur ^ 1];
     L.links = links();
@@ -159,6 +173,10 @@ struct lbm_ctx {
     L.inlet = has_profile ? inlet() : nullptr;
     L.part_w = part[pcur];
     L.part_r = part[pcur ^ 1];
+    L.lvl_w = lvl[pcur];
+    L.lvl_r = lvl[pcur ^ 1];
+    L.reduce1 = pend1;
+    L.reduce2 = pend2;
     L.acc = acc();
     L.hist = hist();
     L.hist_cap = p.history_cap;
@@ -172,10 +190,10 @@ struct lbm_ctx {
     L.ntx = lay.ntx;
     L.nty = lay.nty;
     L.n_nn = n_nn;
-    L.nblocks = 1 + n_nn + lay.ntx * lay.nty;
+    L.nblocks = 1 + kReducers + n_nn + lay.ntx * lay.nty;
+    L.nslots = (n_nn + lay.ntx * lay.nty) * kWaves;
     L.xper = p.xbc == LBM_X_PERIODIC;
     L.yper = p.lateral == LBM_LATERAL_PERIODIC;
-    L.reduce_prev = pending;
     L.omega = 1.0 / p.tau;
     L.s_e = p.s_e;
     L.s_eps = p.s_eps;
@@ -200,7 +218,7 @@ namespace {
 lbm_status reset_counters(lbm_ctx* c) {
   HIP_TRY(hipMemsetAsync(c->acc(), 0, sizeof(Acc), c->stream));
   c->steps = 0;
-  c->pending = false;
+  c->pend1 = c->pend2 = false;
   c->pcur = 0;
   return LBM_OK;
 }
@@ -285,6 +303,8 @@ lbm_status lbm_create(const lbm_params* p, void* dev_workspace, size_t bytes, lb
   c->buf[1] = c->ws + lay.B;
   c->part[0] = c->ws + lay.part0;
   c->part[1] = c->ws + lay.part1;
+  c->lvl[0] = reinterpret_cast<double*>(c->ws + lay.lvl0);
+  c->lvl[1] = reinterpret_cast<double*>(c->ws + lay.lvl1);
   c->cur = 0;
   c->outflow = LBM_OUT_ZOUHE;
   c->n_nn = 0;
@@ -384,13 +404,14 @@ lbm_status lbm_step(lbm_ctx* c, int64_t nsteps) {
   for (int64_t s = 0; s < nsteps; ++s) {
     const StepLaunch L = c->launch();
     HIP_TRY(launch_step(L, c->stream));
-    c->pending = true;
+    c->pend2 = c->pend1;
+    c->pend1 = true;
     c->pcur ^= 1;
     c->cur ^= 1;
   }
   StepLaunch F = c->launch();
   HIP_TRY(launch_finalize(F, c->stream));
-  c->pending = false;
+  c->pend1 = c->pend2 = false;
   c->steps += nsteps;
   return LBM_OK;
 }

@@ -9,10 +9,22 @@
 
 namespace lbm {
 
-constexpr int kBlock = 256;        // threads per workgroup (4 wave64)
-constexpr int kChunk = 256;        // x-extent of a bulk tile (one row of a block)
+// Two shapes of bulk tile, chosen per lattice when the context is created:
+//   scalar (PATH_SCALAR): one node per thread, a workgroup covers 256 columns
+//     of one row, each pull is a (possibly misaligned) 4-byte load;
+//   vector (PATH_VECTOR): kVec = 4 consecutive nodes per lane, one row per
+//     wave, four rows per workgroup, aligned 16-byte loads and a cross-lane
+//     shift for the +-1 columns.
+// Both cover kChunk = 256 columns per row.
+enum { PATH_SCALAR = 0, PATH_VECTOR = 1 };
+constexpr int kBlock = 256;                          // threads per workgroup
+constexpr int kVec = 4;
+constexpr int kChunk = 256;                          // x-extent of a bulk tile
+constexpr int tile_rows(int path) { return path == PATH_SCALAR ? 1 : kBlock / 64; }
 constexpr int kNnRows = 64;        // outlet rows handled by one neural block
 constexpr int kPartials = 4;       // fx, fy, sum of (rho - 1), fallback count
+constexpr int kWaves = kBlock / 64;
+constexpr int kReducers = 32;      // workgroups reducing the previous step's partials
 
 // Accumulators written only by the reducing workgroup (fixed-order FP64).
 struct Acc {
@@ -36,15 +48,23 @@ struct MlpDev {
   float pad[3];
 };
 
+// Reduction pipeline: step t writes one partial slot per wave (part_w); the
+// kReducers reducer workgroups of step t+1 sum fixed slices of them into
+// level-2 sums (lvl_w); workgroup 0 of step t+2 sums those into the FP64
+// accumulators.  Every sum runs in a fixed order.
 struct StepLaunch {
-  int precision, collision;
+  int precision, collision, path;
   const void* A;
   void* B;
   const uint32_t* links;
   const uint8_t* chunk;
   const double* inlet;
-  void* part_w;
-  const void* part_r;
+  void* part_w;             // slots of this step
+  const void* part_r;       // slots of the previous step (reduced by this launch)
+  double* lvl_w;            // level-2 sums written by this launch
+  const double* lvl_r;      // level-2 sums of the step before the previous
+  int reduce1;              // previous step's slots pending
+  int reduce2;              // level-2 sums pending
   Acc* acc;
   double* hist;
   int64_t hist_cap;
@@ -54,9 +74,10 @@ struct StepLaunch {
   int rows;             // rows per bulk block
   int ntx, nty;         // bulk tiles
   int n_nn;             // neural outlet blocks (0 for Zou & He)
-  int nblocks;          // whole grid: 1 reducer + n_nn + ntx*nty
+  int nblocks;          // whole grid: 1 + kReducers + n_nn + ntx*nty
+  int nslots;           // partial slots written per step (waves of the
+                        // neural and bulk workgroups)
   int xper, yper;
-  int reduce_prev;
   double omega, s_e, s_eps, s_q, u_in, one_minus_rho_out, n_fluid;
 };
 

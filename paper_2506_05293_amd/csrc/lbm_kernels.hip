@@ -9,10 +9,11 @@
 // (Eqs. 14-15) and the mass, as per-workgroup partial sums.
 //
 // Grid layout (virtual block ids after the XCD remap, see xcd_remap):
-//   v = 0                 reduces the partials of the previous step, in a
-//                         fixed order, in FP64, into the accumulators;
-//   v = 1 .. n_nn         neural outlet blocks, 64 outlet rows each;
-//   v > n_nn              bulk tiles of 256 x `rows` nodes, x fastest.
+//   v = 0                 level-2 reduction (FP64, fixed order) of the step
+//                         before the previous one into the accumulators;
+//   v = 1 .. kReducers    level-1 reduction of the previous step's slots;
+//   next n_nn             neural outlet blocks, 64 outlet rows each;
+//   the rest              bulk tiles, x fastest.
 //
 // Memory layout: population q of node (x, y) at q*plane + y*pitch + x, with
 // pitch a multiple of 64 elements; offsets f - w stored in S.
@@ -26,10 +27,21 @@ namespace lbm {
 // each XCD a contiguous range of tiles so that the cache lines two x-adjacent
 // tiles share (the pull reads one element past each tile edge) meet in the
 // same L2.
+#ifndef LBM_XCD_REMAP
+#define LBM_XCD_REMAP 1
+#endif
 __device__ __forceinline__ int xcd_remap(int bid, int n) {
+  if constexpr (!LBM_XCD_REMAP) return bid;
   const int q = n >> 3, r = n & 7, x = bid & 7;
   return x * q + min(x, r) + (bid >> 3);
 }
+
+// Optional occupancy request for the step kernel (waves per SIMD).
+#ifdef LBM_WAVES_PER_EU
+#define LBM_STEP_ATTR __attribute__((amdgpu_waves_per_eu(LBM_WAVES_PER_EU, LBM_WAVES_PER_EU)))
+#else
+#define LBM_STEP_ATTR
+#endif
 
 template <typename T>
 __device__ __forceinline__ T wave_sum(T v) {
@@ -38,38 +50,26 @@ __device__ __forceinline__ T wave_sum(T v) {
   return v;
 }
 
-// Fixed-order sum of four values over the workgroup; thread 0 writes them.
+// Partial sums are kept per wave: lane 0 of wave w of workgroup v writes
+// slot 4 v + w (no barrier, so waves retire independently).
 template <typename T>
-__device__ __forceinline__ void block_partials(T a, T b, T c, T d, T* out) {
-  __shared__ T red[kBlock / 64][4];
+__device__ __forceinline__ void wave_partials(T a, T b, T c, T d, T* block_slots) {
   a = wave_sum(a);
   b = wave_sum(b);
   c = wave_sum(c);
   d = wave_sum(d);
-  const int w = threadIdx.x >> 6;
   if ((threadIdx.x & 63) == 0) {
-    red[w][0] = a;
-    red[w][1] = b;
-    red[w][2] = c;
-    red[w][3] = d;
-  }
-  __syncthreads();
-  if (threadIdx.x < 4) {
-    const int k = threadIdx.x;
-    out[k] = ((red[0][k] + red[1][k]) + red[2][k]) + red[3][k];
+    T* out = block_slots + kPartials * (threadIdx.x >> 6);
+    out[0] = a;
+    out[1] = b;
+    out[2] = c;
+    out[3] = d;
   }
 }
 
-// Sum the per-workgroup partials of one step in FP64 and fixed order, then
-// update the accumulators and the force history.
-template <typename T>
-__device__ void reduce_into_acc(const T* __restrict__ part, const StepLaunch& L) {
-  __shared__ double red[kBlock / 64][4];
-  double s[4] = {0.0, 0.0, 0.0, 0.0};
-  for (int b = threadIdx.x; b < L.nblocks; b += kBlock) {
-#pragma unroll
-    for (int k = 0; k < 4; ++k) s[k] += double(part[b * kPartials + k]);
-  }
+// Block sum of four FP64 values in a fixed order; thread 0 gets the result.
+__device__ __forceinline__ void block_sum4(double s[4], double out[4]) {
+  __shared__ double red[kWaves][4];
 #pragma unroll
   for (int k = 0; k < 4; ++k) s[k] = wave_sum(s[k]);
   if ((threadIdx.x & 63) == 0) {
@@ -78,24 +78,70 @@ __device__ void reduce_into_acc(const T* __restrict__ part, const StepLaunch& L)
   }
   __syncthreads();
   if (threadIdx.x == 0) {
-    double t[4];
 #pragma unroll
-    for (int k = 0; k < 4; ++k) t[k] = ((red[0][k] + red[1][k]) + red[2][k]) + red[3][k];
-    Acc* acc = L.acc;
-    acc->fx = t[0];
-    acc->fy = t[1];
-    acc->fx_sum += t[0];
-    acc->fy_sum += t[1];
-    acc->mass = L.n_fluid + t[2];
-    acc->fallback += t[3];
-    if (!isfinite(t[0]) || !isfinite(t[1]) || !isfinite(t[2])) acc->nonfinite = 1;
-    const int64_t n = acc->n_reduced;
-    if (n < L.hist_cap) {
-      L.hist[3 * n + 0] = t[0];
-      L.hist[3 * n + 1] = t[1];
-      L.hist[3 * n + 2] = L.n_fluid + t[2];
-    }
-    acc->n_reduced = n + 1;
+    for (int k = 0; k < 4; ++k) out[k] = ((red[0][k] + red[1][k]) + red[2][k]) + red[3][k];
+  }
+}
+
+// FP64 sum of slots [b0, b1) of one step's partials: thread t adds slots
+// b0 + t, b0 + t + 256, ... in that order (one vector load per slot), then
+// the workgroup combines the threads in a fixed order, so the result does
+// not depend on timing.
+template <typename T>
+__device__ void sum_slots(const T* __restrict__ part, int b0, int b1, double out[4]) {
+  typedef T v4 __attribute__((ext_vector_type(4)));
+  const v4* slot = reinterpret_cast<const v4*>(part);
+  double s[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll 4
+  for (int b = b0 + int(threadIdx.x); b < b1; b += kBlock) {
+    const v4 p = slot[b];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) s[k] += double(p[k]);
+  }
+  block_sum4(s, out);
+}
+
+// Fold one step's total (fx, fy, sum of rho - 1, fallbacks) into the
+// accumulators and the force history (thread 0 only).
+__device__ void commit_step(const double t[4], const StepLaunch& L) {
+  Acc* acc = L.acc;
+  acc->fx = t[0];
+  acc->fy = t[1];
+  acc->fx_sum += t[0];
+  acc->fy_sum += t[1];
+  acc->mass = L.n_fluid + t[2];
+  acc->fallback += t[3];
+  if (!isfinite(t[0]) || !isfinite(t[1]) || !isfinite(t[2])) acc->nonfinite = 1;
+  const int64_t n = acc->n_reduced;
+  if (n < L.hist_cap) {
+    L.hist[3 * n + 0] = t[0];
+    L.hist[3 * n + 1] = t[1];
+    L.hist[3 * n + 2] = L.n_fluid + t[2];
+  }
+  acc->n_reduced = n + 1;
+}
+
+// Level 2: the kReducers sums of one step -> accumulators.
+__device__ void reduce_level2(const double* __restrict__ lvl, const StepLaunch& L) {
+  double s[4] = {0.0, 0.0, 0.0, 0.0}, t[4];
+  if (threadIdx.x < kReducers) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) s[k] = lvl[threadIdx.x * 4 + k];
+  }
+  block_sum4(s, t);
+  if (threadIdx.x == 0) commit_step(t, L);
+}
+
+// Level 1: reducer r sums its slice of the previous step's slots.
+template <typename T>
+__device__ void reduce_level1(const T* __restrict__ part, int r, const StepLaunch& L) {
+  const int per = (L.nslots + kReducers - 1) / kReducers;
+  const int b0 = min(r * per, L.nslots), b1 = min(b0 + per, L.nslots);
+  double t[4];
+  sum_slots(part, b0, b1, t);
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) L.lvl_w[r * 4 + k] = t[k];
   }
 }
 
@@ -127,16 +173,201 @@ __device__ __forceinline__ void add_force(uint32_t lk, const T g[9], T& fx, T& f
 }
 
 // ---- bulk tile ------------------------------------------------------------------
+// A bulk workgroup is four wave64, one lattice row each, over the same
+// kChunk columns: every lane owns kVec consecutive nodes.  Each population
+// plane is read with one aligned vector load per lane; the +-1 column shift of the
+// pull is done across lanes (one neighbour element per lane through
+// ds_bpermute, plus one halo element at each wave edge), so all global
+// traffic is 8- to 32-byte wide per lane and fully coalesced.
+//
+// Loads and stores address a plane through a wave-uniform base pointer plus a
+// 32-bit offset, so no 64-bit address is built per lane.
+static_assert(kChunk == 64 * kVec, "one vector row per wave spans a chunk");
+constexpr int kV = kVec;
+
+// Vector load / store of kV consecutive elements of one plane: plain loads,
+// non-temporal stores.
+template <typename V>
+__device__ __forceinline__ V ld_vec(const V* p) { return *p; }
+template <typename V>
+__device__ __forceinline__ void st_vec_nt(V* p, V v) { __builtin_nontemporal_store(v, p); }
+
+template <typename S> struct VecIO;
+template <> struct VecIO<float> {
+  typedef float v __attribute__((ext_vector_type(kV)));
+  __device__ static void ld(const float* p, float* e) {
+    const v a = ld_vec(reinterpret_cast<const v*>(p));
+#pragma unroll
+    for (int i = 0; i < kV; ++i) e[i] = a[i];
+  }
+  __device__ static void st(float* p, const float* e) {
+    v a;
+#pragma unroll
+    for (int i = 0; i < kV; ++i) a[i] = e[i];
+    st_vec_nt(reinterpret_cast<v*>(p), a);
+  }
+};
+template <> struct VecIO<double> {
+  typedef double v __attribute__((ext_vector_type(2)));
+  __device__ static void ld(const double* p, double* e) {
+#pragma unroll
+    for (int k = 0; k < kV / 2; ++k) {
+      const v a = ld_vec(reinterpret_cast<const v*>(p) + k);
+      e[2 * k] = a[0];
+      e[2 * k + 1] = a[1];
+    }
+  }
+  __device__ static void st(double* p, const double* e) {
+#pragma unroll
+    for (int k = 0; k < kV / 2; ++k) {
+      const v a = {e[2 * k], e[2 * k + 1]};
+      st_vec_nt(reinterpret_cast<v*>(p) + k, a);
+    }
+  }
+};
+template <> struct VecIO<__half> {
+  typedef unsigned short v __attribute__((ext_vector_type(kV)));
+  __device__ static void ld(const __half* p, float* e) {
+    const v a = ld_vec(reinterpret_cast<const v*>(p));
+#pragma unroll
+    for (int i = 0; i < kV; ++i) e[i] = __half2float(__ushort_as_half(a[i]));
+  }
+  __device__ static void st(__half* p, const float* e) {
+    v a;
+#pragma unroll
+    for (int i = 0; i < kV; ++i) a[i] = __half_as_ushort(__float2half_rn(e[i]));
+    st_vec_nt(reinterpret_cast<v*>(p), a);
+  }
+};
+
 template <typename S, int MRT>
-__device__ __forceinline__ void bulk_node(const StepLaunch& L, int x, int y,
+__device__ __forceinline__ void bulk_row(const StepLaunch& L, int tx, int y, int lane,
+                                         typename Store<S>::T& fx, typename Store<S>::T& fy,
+                                         typename Store<S>::T& dm) {
+  using T = typename Store<S>::T;
+  const S* __restrict__ A = static_cast<const S*>(L.A);
+  S* __restrict__ B = static_cast<S*>(L.B);
+  const uint32_t pitch = uint32_t(L.pitch);
+  const int xw = tx * kChunk;                 // first column of this wave
+  const int x0 = xw + lane * kV;              // first column of this lane
+
+  int ym = y - 1, yp = y + 1;
+  if (ym < 0) ym = L.yper ? L.ny - 1 : 0;
+  if (yp >= L.ny) yp = L.yper ? 0 : L.ny - 1;
+  const uint32_t r0 = uint32_t(y) * pitch, rm = uint32_t(ym) * pitch, rp = uint32_t(yp) * pitch;
+  int hm = xw - 1, hp = xw + kChunk;          // halo columns of the wave
+  if (hm < 0) hm = L.xper ? L.nx - 1 : 0;
+  if (hp >= L.nx) hp = L.xper ? 0 : L.nx - 1;
+
+  // 1. pull every plane: g[i][q] = A_q(x0 + i - cx_q, y - cy_q)
+  T g[kV][9];
+#pragma unroll
+  for (int q = 0; q < 9; ++q) {
+    const S* Aq = A + int64_t(q) * L.plane;
+    const uint32_t ro = cy(q) == 1 ? rm : (cy(q) == -1 ? rp : r0);
+    T e[kV];
+    VecIO<S>::ld(Aq + ro + uint32_t(x0), e);
+    if (cx(q) == 0) {
+#pragma unroll
+      for (int i = 0; i < kV; ++i) g[i][q] = e[i];
+    } else if (cx(q) == 1) {
+      T prev = __shfl_up(e[kV - 1], 1, 64);
+      if (lane == 0) prev = Store<S>::ld(Aq + ro + uint32_t(hm));
+      g[0][q] = prev;
+#pragma unroll
+      for (int i = 1; i < kV; ++i) g[i][q] = e[i - 1];
+    } else {
+      T next = __shfl_down(e[0], 1, 64);
+      if (lane == 63) next = Store<S>::ld(Aq + ro + uint32_t(hp));
+      g[kV - 1][q] = next;
+#pragma unroll
+      for (int i = 0; i < kV - 1; ++i) g[i][q] = e[i + 1];
+    }
+  }
+
+  // 2. link words of the lane's nodes (only in chunks that have any)
+  uint32_t lk[kV];
+#pragma unroll
+  for (int i = 0; i < kV; ++i) lk[i] = 0u;
+  if (L.chunk[y * L.nchunk + tx]) {
+#pragma unroll
+    for (int i = 0; i < kV; ++i) lk[i] = L.links[r0 + uint32_t(x0 + i)];
+  }
+
+  // 3. per node: fix-ups, boundary columns, force, collision
+  bool keep[kV];
+  bool all = true;
+#pragma unroll
+  for (int i = 0; i < kV; ++i) {
+    const int x = x0 + i;
+    keep[i] = x < L.nx && !(lk[i] & LINK_SOLID) && !((lk[i] & LINK_OUTLET) && L.n_nn);
+    all = all && keep[i];
+    if (!keep[i]) continue;
+    if (L.xper && x == L.nx - 1) {            // last column wraps to column 0
+#pragma unroll
+      for (int q = 0; q < 9; ++q)
+        if (cx(q) == -1)
+          g[i][q] = Store<S>::ld(A + int64_t(q) * L.plane +
+                                 (cy(q) == 1 ? rm : (cy(q) == -1 ? rp : r0)));
+    }
+    if (lk[i] & 0x1FFu) {                     // half-way bounce-back
+#pragma unroll
+      for (int q = 1; q < 9; ++q)
+        if ((lk[i] >> q) & 1u) g[i][q] = Store<S>::ld(A + int64_t(opp(q)) * L.plane + r0 + uint32_t(x));
+    }
+    if (lk[i] & (LINK_INLET | LINK_OUTLET)) {
+      if (lk[i] & LINK_INLET)
+        zouhe_inlet(g[i], L.inlet ? T(L.inlet[y]) : T(L.u_in));
+      else
+        zouhe_outlet(g[i], T(L.one_minus_rho_out));
+    }
+    add_force(lk[i], g[i], fx, fy);
+    dm += macro(g[i]).drho;
+    collide<T, MRT>(g[i], L);
+  }
+
+  // 4. store: one vector store per plane, or per node where some are skipped
+#pragma unroll
+  for (int q = 0; q < 9; ++q) {
+    S* Bq = B + int64_t(q) * L.plane + r0 + uint32_t(x0);
+    T e[kV];
+#pragma unroll
+    for (int i = 0; i < kV; ++i) e[i] = g[i][q];
+    if (all) {
+      VecIO<S>::st(Bq, e);
+    } else {
+#pragma unroll
+      for (int i = 0; i < kV; ++i)
+        if (keep[i]) Store<S>::st(Bq + i, e[i]);
+    }
+  }
+}
+
+// Element access through a wave-uniform plane pointer and a 32-bit byte offset.
+template <typename S>
+__device__ __forceinline__ typename Store<S>::T ld_at(const S* plane, uint32_t byte_off) {
+  return Store<S>::ld_nt(reinterpret_cast<const S*>(reinterpret_cast<const char*>(plane) + byte_off));
+}
+template <typename S>
+__device__ __forceinline__ void st_at(S* plane, uint32_t byte_off, typename Store<S>::T v) {
+  Store<S>::st(reinterpret_cast<S*>(reinterpret_cast<char*>(plane) + byte_off), v);
+}
+
+// One node per thread: the pull reads each plane at x - c_q directly (one
+// element off alignment for c_x != 0; the neighbouring wave's cache line),
+// with the non-temporal hint.
+template <typename S, int MRT>
+__device__ __forceinline__ void bulk_node(const StepLaunch& L, int tx, int x, int y,
                                           typename Store<S>::T& fx, typename Store<S>::T& fy,
                                           typename Store<S>::T& dm) {
   using T = typename Store<S>::T;
   const S* __restrict__ A = static_cast<const S*>(L.A);
   S* __restrict__ B = static_cast<S*>(L.B);
-  const int64_t row = int64_t(y) * L.pitch;
+  constexpr uint32_t es = sizeof(S);
+  const uint32_t pitch = uint32_t(L.pitch);
+  const uint32_t self = (uint32_t(y) * pitch + uint32_t(x)) * es;
   uint32_t lk = 0;
-  if (L.chunk[y * L.nchunk + (x >> 8)]) lk = L.links[row + x];
+  if (L.chunk[y * L.nchunk + tx]) lk = L.links[uint32_t(y) * pitch + uint32_t(x)];
   if (lk & LINK_SOLID) return;
   if ((lk & LINK_OUTLET) && L.n_nn) return;   // done by the neural blocks
 
@@ -145,16 +376,19 @@ __device__ __forceinline__ void bulk_node(const StepLaunch& L, int x, int y,
   if (xp >= L.nx) xp = L.xper ? 0 : L.nx - 1;
   if (ym < 0) ym = L.yper ? L.ny - 1 : 0;
   if (yp >= L.ny) yp = L.yper ? 0 : L.ny - 1;
-  const int64_t rm = int64_t(ym) * L.pitch, rp = int64_t(yp) * L.pitch;
+  const uint32_t rm = uint32_t(ym) * pitch, r0 = uint32_t(y) * pitch, rp = uint32_t(yp) * pitch;
 
   T g[9];
 #pragma unroll
   for (int q = 0; q < 9; ++q) {
-    const int sx = cx(q) == 1 ? xm : (cx(q) == -1 ? xp : x);
-    const int64_t sr = cy(q) == 1 ? rm : (cy(q) == -1 ? rp : row);
-    const int64_t pull = int64_t(q) * L.plane + sr + sx;
-    const int64_t back = int64_t(opp(q)) * L.plane + row + x;
-    g[q] = Store<S>::ld(A + (((lk >> q) & 1u) ? back : pull));
+    const uint32_t sx = uint32_t(cx(q) == 1 ? xm : (cx(q) == -1 ? xp : x));
+    const uint32_t sr = cy(q) == 1 ? rm : (cy(q) == -1 ? rp : r0);
+    g[q] = ld_at(A + int64_t(q) * L.plane, (sr + sx) * es);
+  }
+  if (lk & 0x1FFu) {
+#pragma unroll
+    for (int q = 1; q < 9; ++q)
+      if ((lk >> q) & 1u) g[q] = ld_at(A + int64_t(opp(q)) * L.plane, self);
   }
   if (lk & (LINK_INLET | LINK_OUTLET)) {
     if (lk & LINK_INLET)
@@ -166,21 +400,24 @@ __device__ __forceinline__ void bulk_node(const StepLaunch& L, int x, int y,
   dm += macro(g).drho;
   collide<T, MRT>(g, L);
 #pragma unroll
-  for (int q = 0; q < 9; ++q) Store<S>::st(B + int64_t(q) * L.plane + row + x, g[q]);
+  for (int q = 0; q < 9; ++q) st_at(B + int64_t(q) * L.plane, self, g[q]);
 }
 
-template <typename S, int MRT>
+template <typename S, int MRT, int PATH>
 __device__ __forceinline__ void bulk_block(const StepLaunch& L, int tile,
                                            typename Store<S>::T* part) {
   using T = typename Store<S>::T;
   const int tx = tile % L.ntx, ty = tile / L.ntx;
-  const int x = tx * kChunk + threadIdx.x;
-  const int yb = ty * L.rows;
-  const int ye = min(yb + L.rows, L.ny);
   T fx = T(0), fy = T(0), dm = T(0);
-  if (x < L.nx)
-    for (int y = yb; y < ye; ++y) bulk_node<S, MRT>(L, x, y, fx, fy, dm);
-  block_partials(fx, fy, dm, T(0), part);
+  if constexpr (PATH == PATH_SCALAR) {
+    const int x = tx * kChunk + threadIdx.x;
+    if (x < L.nx) bulk_node<S, MRT>(L, tx, x, ty, fx, fy, dm);
+  } else {
+    const int lane = threadIdx.x & 63;
+    const int y = ty * tile_rows(PATH) + (threadIdx.x >> 6);
+    if (y < L.ny) bulk_row<S, MRT>(L, tx, y, lane, fx, fy, dm);   // wave-uniform
+  }
+  wave_partials(fx, fy, dm, T(0), part);
 }
 
 // ---- neural outlet block ----------------------------------------------------------
@@ -288,35 +525,62 @@ __device__ void nn_block(const StepLaunch& L, int nb, typename Store<S>::T* part
 #pragma unroll
     for (int q = 0; q < 9; ++q) Store<S>::st(B + int64_t(q) * L.plane + row, g[q]);
   }
-  block_partials(fx, fy, dm, nfb, part);
+  wave_partials(fx, fy, dm, nfb, part);
 }
 
 // ---- the step kernel --------------------------------------------------------------
-template <typename S, int MRT>
-__global__ void __launch_bounds__(kBlock) k_step(const StepLaunch L) {
+// NN selects the variant with neural outlet blocks; the Zou & He variant
+// carries none of their registers or LDS.
+template <typename S, int MRT, bool NN, int PATH>
+__global__ void __launch_bounds__(kBlock) LBM_STEP_ATTR k_step(const StepLaunch L) {
   using T = typename Store<S>::T;
+  constexpr int kFirst = 1 + kReducers;          // first workgroup with slots
   const int v = xcd_remap(blockIdx.x, L.nblocks);
-  T* part = static_cast<T*>(L.part_w) + kPartials * v;
-  if (v == 0) {
-    if (L.reduce_prev) reduce_into_acc<T>(static_cast<const T*>(L.part_r), L);
-    if (threadIdx.x < kPartials) part[threadIdx.x] = T(0);
+  if (v < kFirst) {
+    if (v == 0) {
+      if (L.reduce2) reduce_level2(L.lvl_r, L);
+    } else if (L.reduce1) {
+      reduce_level1(static_cast<const T*>(L.part_r), v - 1, L);
+    }
     return;
   }
-  if (v <= L.n_nn) {
-    nn_block<S, MRT>(L, v - 1, part);
-    return;
+  T* part = static_cast<T*>(L.part_w) + kPartials * kWaves * (v - kFirst);
+  if constexpr (NN) {
+    if (v < kFirst + L.n_nn) {
+      nn_block<S, MRT>(L, v - kFirst, part);
+      return;
+    }
   }
-  bulk_block<S, MRT>(L, v - 1 - L.n_nn, part);
+  bulk_block<S, MRT, PATH>(L, v - kFirst - L.n_nn, part);
 }
 
+// Flush the pipeline after the last step: level 2 of the step before, then
+// the last step's slots in one workgroup.
 template <typename T>
 __global__ void __launch_bounds__(kBlock) k_finalize(const StepLaunch L) {
-  reduce_into_acc<T>(static_cast<const T*>(L.part_r), L);
+  if (L.reduce2) reduce_level2(L.lvl_r, L);
+  __syncthreads();
+  if (L.reduce1) {
+    double t[4];
+    sum_slots(static_cast<const T*>(L.part_r), 0, L.nslots, t);
+    if (threadIdx.x == 0) commit_step(t, L);
+  }
+}
+
+template <typename S, int MRT, bool NN>
+static void launch_path(const StepLaunch& L, hipStream_t s) {
+  if (L.path == PATH_VECTOR)
+    hipLaunchKernelGGL((k_step<S, MRT, NN, PATH_VECTOR>), dim3(L.nblocks), dim3(kBlock), 0, s, L);
+  else
+    hipLaunchKernelGGL((k_step<S, MRT, NN, PATH_SCALAR>), dim3(L.nblocks), dim3(kBlock), 0, s, L);
 }
 
 template <typename S, int MRT>
 static hipError_t launch_step_t(const StepLaunch& L, hipStream_t s) {
-  hipLaunchKernelGGL((k_step<S, MRT>), dim3(L.nblocks), dim3(kBlock), 0, s, L);
+  if (L.n_nn)
+    launch_path<S, MRT, true>(L, s);
+  else
+    launch_path<S, MRT, false>(L, s);
   return hipGetLastError();
 }
 

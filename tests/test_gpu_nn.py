@@ -105,7 +105,7 @@ def test_zero_network_is_copy_outflow_fp64():
 
 
 @pytest.mark.parametrize("how", ["mass_bound_zero", "nan_weights"])
-def test_forced_fallback_equals_zouhe_bitwise(how):
+def test_forced_fallback_equals_zouhe_bitwise(how, bulk_path):
     case = cases.ragged("mrt", "periodic")
     P = _f32(random_params(2))
     bound = 0.0
@@ -128,7 +128,7 @@ def test_forced_fallback_equals_zouhe_bitwise(how):
     assert b.forces().n_fallback == 120 * ny
 
 
-def test_nn_outflow_run_matches_oracle():
+def test_nn_outflow_run_matches_oracle(bulk_path):
     case = cases.ragged("bgk", "periodic")
     P = _f32(random_params(3, w_scale=0.5, out_sd=2e-4))
     _say("nn outflow run fp64 vs oracle")
@@ -154,7 +154,7 @@ def test_nn_outflow_run_matches_oracle():
     assert np.max(np.abs(z.post_collision()[:, :, -1] - ref[:, :, -1])) > 1e-5
 
 
-def test_nn_outflow_full_size_one_step():
+def test_nn_outflow_full_size_one_step(bulk_path):
     # truncated cylinder lattice 4096 x 512 (D = 64, periodic laterals, MRT,
     # FP32) with the neural outflow, in the configuration the bench times
     nx, ny, D = 4096, 512, 64

@@ -69,7 +69,7 @@ def test_c1_literal_fp64_parity(steps):
 
 
 @pytest.mark.parametrize("re,collision", [(75.0, "bgk"), (100.0, "mrt")])
-def test_c1_fp64_parity_2000_steps(re, collision):
+def test_c1_fp64_parity_2000_steps(re, collision, bulk_path):
     _say("c1 fp64", collision, "Re", re, 2000)
     _c1_parity(cases.c1(re, collision), 2000)
 
@@ -89,7 +89,7 @@ def test_c1_literal_divergence_is_flagged():
 
 @pytest.mark.parametrize("collision,lateral", [("mrt", "periodic"), ("bgk", "walls"),
                                                ("mrt", "walls"), ("bgk", "periodic")])
-def test_ragged_fp64_parity(collision, lateral):
+def test_ragged_fp64_parity(collision, lateral, bulk_path):
     case = cases.ragged(collision, lateral)
     _say("ragged fp64", collision, lateral)
     g = _gpu(case, history_cap=300)
@@ -104,7 +104,7 @@ def test_ragged_fp64_parity(collision, lateral):
     assert np.max(np.abs(fy - o.fy_hist)) < 1e-12 * scale
 
 
-def test_fully_periodic_taylor_green_parity():
+def test_fully_periodic_taylor_green_parity(bulk_path):
     n = 96
     k = 2 * np.pi / n
     Y, X = np.mgrid[0:n, 0:n].astype(float)
@@ -138,7 +138,7 @@ def test_inlet_profile_parity():
 
 @pytest.mark.parametrize("precision,drho_tol,du_tol", [("fp32", 1e-5, 1e-4), ("fp16", 2e-2, 2e-2)])
 @pytest.mark.parametrize("re,collision", [(75.0, "bgk"), (100.0, "mrt")])
-def test_c1_offset_storage(precision, drho_tol, du_tol, re, collision):
+def test_c1_offset_storage(precision, drho_tol, du_tol, re, collision, bulk_path):
     case = cases.c1(re, collision)
     _say("c1", precision, collision, re, 2000)
     g = _gpu(case, precision, history_cap=2000)
@@ -156,7 +156,7 @@ def test_c1_offset_storage(precision, drho_tol, du_tol, re, collision):
     assert np.all(np.isfinite(fx)) and np.all(np.isfinite(fy))
 
 
-def test_checkpoint_roundtrip_is_bitwise():
+def test_checkpoint_roundtrip_is_bitwise(bulk_path):
     case = cases.ragged("mrt", "walls")
     _say("checkpoint fp32")
     a = _gpu(case, "fp32")
@@ -169,7 +169,7 @@ def test_checkpoint_roundtrip_is_bitwise():
     np.testing.assert_array_equal(a.populations(), b.populations())
 
 
-def test_runs_are_deterministic():
+def test_runs_are_deterministic(bulk_path):
     case = cases.ragged("mrt", "periodic")
     _say("determinism fp32")
     a = _gpu(case, "fp32", history_cap=150)
@@ -199,12 +199,12 @@ def test_zero_steps_and_state_errors():
         lbm.lbm_step(g.ctx, -1)
 
 
-def test_full_size_c2_one_step_against_oracle():
+def test_full_size_c2_one_step_against_oracle(bulk_path):
     # the bench lattice (4096 x 1024, MRT, FP32 offsets) in the bench's launch
     # configuration: one step checked node by node against the oracle's step
     # from the same post-collision state
     case = cases.c2()
-    _say("c2 full size fp32 mrt")
+    _say("c2 full size fp32 mrt", bulk_path)
     g = _gpu(case, "fp32")
     g.step(50)
     f50 = g.populations()
