@@ -9,10 +9,20 @@ momentum-exchange force and mass reduction.  The same lattice is then timed
 with the neural outflow active (MLP 27-64-64-3 fused into the step).
 
 Prints one JSON line.  Usage: python bench.py [--steps K] [--warmup W]
+
+Counter figures for roofline.traffic are taken with rocprofv3 (see
+profiles/step_kernel_4096x1024_traffic.txt for the commands): the HBM
+counters FETCH_SIZE and WRITE_SIZE of the step kernel, each scaled by what
+the same counter reads for a plain copy of known size (``--calibration-copy``).
+``--write-traffic`` turns those CSV files into that summary, stamped with a
+hash of the kernel sources; traffic is reported only while the hash matches.
 """
 import argparse
+import csv
+import hashlib
 import json
 import os
+import statistics
 import sys
 import time
 
@@ -23,6 +33,66 @@ sys.path.insert(0, ROOT)
 
 BYTES_PER_NODE = {"fp64": 144, "fp32": 72, "fp16": 36}   # 9 loads + 9 stores
 HBM_PEAK_GBS = 8000.0
+CSRC = os.path.join(ROOT, "paper_2506_05293_amd", "csrc")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "step_kernel_4096x1024_traffic.txt")
+CALIB_BYTES = 151 * 1024 * 1024     # bytes read (and written) by the calibration copy
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for name in sorted(os.listdir(CSRC)):
+        if name.endswith((".hip", ".hpp", ".cpp")):
+            with open(os.path.join(CSRC, name), "rb") as f:
+                h.update(name.encode() + f.read())
+    return h.hexdigest()[:16]
+
+
+def calibration_copy():
+    """A plain device copy of CALIB_BYTES (torch copy_), five dispatches."""
+    import torch
+    a = torch.ones(CALIB_BYTES // 4, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(5):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print("calibration copy done", flush=True)
+
+
+def _median_counter(path, name_part):
+    vals = [float(r["Counter_Value"]) for r in csv.DictReader(open(path))
+            if name_part in r["Kernel_Name"]]
+    if not vals:
+        raise SystemExit(f"no dispatch of {name_part!r} in {path}")
+    return statistics.median(vals)
+
+
+def write_traffic(step_fetch, step_write, copy_fetch, copy_write, command_note):
+    """Scale the step kernel's FETCH_SIZE / WRITE_SIZE (KiB per dispatch) by
+    the copy's reading of CALIB_BYTES and store bytes per launch."""
+    kib = CALIB_BYTES / 1024.0
+    f_scale = kib / _median_counter(copy_fetch, "copyBuffer")
+    w_scale = kib / _median_counter(copy_write, "copyBuffer")
+    fetch = _median_counter(step_fetch, "k_step") * f_scale * 1024
+    write = _median_counter(step_write, "k_step") * w_scale * 1024
+    lines = [f"source_hash={kernel_source_hash()}",
+             f"fetch_bytes_per_launch={fetch:.0f}",
+             f"write_bytes_per_launch={write:.0f}",
+             f"fetch_scale={f_scale:.4f}", f"write_scale={w_scale:.4f}",
+             f"commands={command_note}"]
+    with open(TRAFFIC_FILE, "w") as f:
+        f.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
+def stored_traffic():
+    """HBM bytes per launch from the counter summary, or None when the kernel
+    sources changed since the counters were taken."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    kv = dict(l.strip().split("=", 1) for l in open(TRAFFIC_FILE) if "=" in l)
+    if kv.get("source_hash") != kernel_source_hash():
+        return None
+    return float(kv["fetch_bytes_per_launch"]) + float(kv["write_bytes_per_launch"])
 
 
 def c2_case(nx, ny):
@@ -88,7 +158,13 @@ def main():
     ap.add_argument("--precision", default="fp32", choices=list(BYTES_PER_NODE))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-nn", action="store_true")
+    ap.add_argument("--calibration-copy", action="store_true")
+    ap.add_argument("--write-traffic", nargs=4, metavar="CSV")
     args = ap.parse_args()
+    if args.calibration_copy:
+        return calibration_copy()
+    if args.write_traffic:
+        return write_traffic(*args.write_traffic, command_note=os.environ.get("TRAFFIC_NOTE", ""))
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               "(the lattice would shard in x-slabs with a per-step halo exchange)", file=sys.stderr)
@@ -104,6 +180,7 @@ def main():
     out = lat.forces()
     assert out.nonfinite == 0
     nodes = nx * ny
+    traffic = stored_traffic()
     mlups = nodes / (ms * 1e-3) / 1e6
     bpn = BYTES_PER_NODE[args.precision]
     gbs = bpn * nodes / (ms * 1e-3) / 1e9
@@ -129,7 +206,9 @@ def main():
                                f"{args.precision} offset storage, Zou-He inlet/outlet, walls, Re=200",
                    "nx": nx, "ny": ny, "precision": args.precision, "collision": "mrt"},
         "roofline": {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": gbs / HBM_PEAK_GBS, "traffic": None,
+                     "frac": gbs / HBM_PEAK_GBS,
+                     "traffic": (None if traffic is None or (nx, ny, args.precision) != (4096, 1024, "fp32")
+                                 else traffic / (ms * 1e-3) / 1e9),
                      "bytes_per_node": bpn, "kernel": "k_step (fused pull stream-collide)"},
         "hbm_fraction": gbs / HBM_PEAK_GBS,
         "nn_outflow": nn,
