@@ -85,6 +85,37 @@ def backward_f64(cache, o, y, P):
 PARAM_NAMES = ("w1", "b1", "w2", "b2", "w3", "b3")
 
 
+def grad_bf16(x, t, P):
+    """Loss (Eq. 17 on standardised outputs) and gradients of the training
+    pass as the MFMA kernels evaluate it: the forward of ``forward_bf16``
+    with standardised targets y = (t - mu_out) (1/sd_out) (FP32), and the
+    chain rule in FP64 where every matrix product takes its operands rounded
+    to BF16 as the MFMA path does (dL/do, dL/dz2, dL/dz1, activations,
+    weights; dL/dh2 uses the FP32 weights of layer 3, an elementwise product
+    on the GPU).  tanh' is 1 - h^2 of the unrounded activation; bias
+    gradients sum unrounded values."""
+    b = bf16_round
+    z = b(standardise_f32(x, P["mu_in"], P["sd_in"]))
+    y = standardise_f32(t, P["mu_out"], P["sd_out"])
+    W1, W2, W3 = b(P["w1"]), b(P["w2"]), b(P["w3"])
+    h1 = np.tanh(z @ W1.T + P["b1"])
+    h1b = b(h1)
+    h2 = np.tanh(h1b @ W2.T + P["b2"])
+    h2b = b(h2)
+    o = h2b @ W3.T + P["b3"]
+    n = x.shape[0]
+    loss = float(np.mean((o - y) ** 2))
+    d_o = 2.0 * (o - y) / (3 * n)
+    g = {"w3": b(d_o).T @ h2b, "b3": d_o.sum(0)}
+    dz2 = (d_o @ np.asarray(P["w3"], np.float64)) * (1.0 - h2 * h2)
+    g["w2"] = b(dz2).T @ h1b
+    g["b2"] = dz2.sum(0)
+    dz1 = (b(dz2) @ W2) * (1.0 - h1 * h1)
+    g["w1"] = b(dz1).T @ z
+    g["b1"] = dz1.sum(0)
+    return loss, g
+
+
 class Adam:
     """Adam (Kingma & Ba 2015): first and second moment estimates with bias
     correction; theta <- theta - lr mhat / (sqrt(vhat) + eps)."""

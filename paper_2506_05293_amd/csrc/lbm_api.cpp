@@ -21,10 +21,11 @@
 using namespace lbm;
 
 namespace {
-
 thread_local std::string g_err;
+}
 
-lbm_status fail(lbm_status code, const char* fmt, ...) {
+namespace lbm {
+lbm_status set_error(lbm_status code, const char* fmt, ...) {
   char buf[512];
   va_list ap;
   va_start(ap, fmt);
@@ -33,6 +34,11 @@ lbm_status fail(lbm_status code, const char* fmt, ...) {
   g_err = buf;
   return code;
 }
+}  // namespace lbm
+
+namespace {
+
+#define fail lbm::set_error
 
 lbm_status hip_fail(hipError_t e, const char* what) {
   return fail(LBM_EHIP, "%s: %s", what, hipGetErrorString(e));

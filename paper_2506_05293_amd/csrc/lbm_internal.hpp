@@ -82,6 +82,9 @@ struct StepLaunch {
 };
 
 hipError_t launch_step(const StepLaunch& L, hipStream_t s);
+
+// Record an error for lbm_last_error() (thread-local) and return `code`.
+lbm_status set_error(lbm_status code, const char* fmt, ...);
 hipError_t launch_finalize(const StepLaunch& L, hipStream_t s);
 
 struct InitLaunch {

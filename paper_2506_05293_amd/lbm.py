@@ -52,6 +52,21 @@ class lbm_mlp(ctypes.Structure):
                 ("mass_bound", ctypes.c_double)]
 
 
+class lbm_train_params(ctypes.Structure):
+    _fields_ = [("batch", ctypes.c_int32), ("lr", ctypes.c_double), ("beta1", ctypes.c_double),
+                ("beta2", ctypes.c_double), ("eps", ctypes.c_double), ("seed", ctypes.c_uint64),
+                ("stream", ctypes.c_void_p)]
+
+
+class lbm_mlp_host(ctypes.Structure):
+    _fields_ = [(k, _FP) for k in ("w1", "b1", "w2", "b2", "w3", "b3",
+                                   "mu_in", "sd_in", "mu_out", "sd_out")]
+
+
+PARAM_SHAPES = {"w1": (64, 27), "b1": (64,), "w2": (64, 64), "b2": (64,), "w3": (3, 64), "b3": (3,)}
+N_PARAMS = 6147
+
+
 class LbmError(RuntimeError):
     def __init__(self, status, where, message):
         super().__init__(f"{where}: status {status}: {message}")
@@ -86,6 +101,16 @@ def library():
             "lbm_sync": (I32, [VP]),
             "lbm_mlp_forward": (I32, [VP, VP, VP, I64]),
             "lbm_last_error": (ctypes.c_char_p, []),
+            "lbm_train_workspace_bytes": (ctypes.c_size_t, [P(lbm_train_params)]),
+            "lbm_train_create": (I32, [P(lbm_train_params), VP, ctypes.c_size_t, P(VP)]),
+            "lbm_train_destroy": (I32, [VP]),
+            "lbm_train_set_data": (I32, [VP, VP, VP, I64]),
+            "lbm_train_set_weights": (I32, [VP, P(lbm_mlp)]),
+            "lbm_train_step": (I32, [VP, I64]),
+            "lbm_train_loss": (I32, [VP, DP]),
+            "lbm_train_get_weights": (I32, [VP, P(lbm_mlp_host)]),
+            "lbm_train_gradient": (I32, [VP, VP, ctypes.c_int32, _FP, DP]),
+            "lbm_train_sample_rows": (I32, [VP, I64, P(ctypes.c_int32)]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(lib, name)
@@ -210,6 +235,129 @@ def lbm_mlp_forward(ctx, x_ptr, s_ptr, n):
 
 def lbm_last_error():
     return library().lbm_last_error().decode()
+
+
+# --- training of the outflow network (include/lbm_train.h) -----------------------
+
+def lbm_train_workspace_bytes(params):
+    n = library().lbm_train_workspace_bytes(ctypes.byref(params))
+    if n == 0:
+        raise LbmError(LBM_EINVAL, "lbm_train_workspace_bytes", library().lbm_last_error().decode())
+    return n
+
+
+def lbm_train_create(params, workspace_ptr, nbytes):
+    tr = ctypes.c_void_p()
+    _check(library().lbm_train_create(ctypes.byref(params), ctypes.c_void_p(workspace_ptr), nbytes,
+                                      ctypes.byref(tr)), "lbm_train_create")
+    return tr
+
+
+def lbm_train_destroy(tr):
+    return _check(library().lbm_train_destroy(tr), "lbm_train_destroy")
+
+
+def lbm_train_set_data(tr, x_ptr, t_ptr, n):
+    return _check(library().lbm_train_set_data(tr, ctypes.c_void_p(x_ptr), ctypes.c_void_p(t_ptr), n),
+                  "lbm_train_set_data")
+
+
+def lbm_train_set_weights(tr, P):
+    full = dict(P)
+    for k in ("mu_in", "sd_in", "mu_out", "sd_out"):
+        full.setdefault(k, np.zeros(27 if k.endswith("in") else 3))
+    s, keep = _mlp_struct(full, 0.0)
+    st = library().lbm_train_set_weights(tr, ctypes.byref(s))
+    del keep
+    return _check(st, "lbm_train_set_weights")
+
+
+def lbm_train_step(tr, nsteps):
+    return _check(library().lbm_train_step(tr, int(nsteps)), "lbm_train_step")
+
+
+def lbm_train_loss(tr):
+    v = ctypes.c_double()
+    _check(library().lbm_train_loss(tr, ctypes.byref(v)), "lbm_train_loss")
+    return v.value
+
+
+def lbm_train_get_weights(tr):
+    out = {k: np.zeros(v, np.float32) for k, v in PARAM_SHAPES.items()}
+    out.update(mu_in=np.zeros(27, np.float32), sd_in=np.zeros(27, np.float32),
+               mu_out=np.zeros(3, np.float32), sd_out=np.zeros(3, np.float32))
+    h = lbm_mlp_host(*[out[k].ctypes.data_as(_FP) for k in
+                       ("w1", "b1", "w2", "b2", "w3", "b3", "mu_in", "sd_in", "mu_out", "sd_out")])
+    _check(library().lbm_train_get_weights(tr, ctypes.byref(h)), "lbm_train_get_weights")
+    return out
+
+
+def lbm_train_gradient(tr, rows_ptr, n_rows):
+    g = np.zeros(N_PARAMS, np.float32)
+    loss = ctypes.c_double()
+    _check(library().lbm_train_gradient(tr, ctypes.c_void_p(rows_ptr), n_rows, g.ctypes.data_as(_FP),
+                                        ctypes.byref(loss)), "lbm_train_gradient")
+    return g, loss.value
+
+
+def lbm_train_sample_rows(tr, step, batch):
+    rows = np.zeros(batch, np.int32)
+    _check(library().lbm_train_sample_rows(tr, step, rows.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))),
+           "lbm_train_sample_rows")
+    return rows
+
+
+def unflatten_params(g):
+    """Split a flat 6147-vector (w1, b1, w2, b2, w3, b3 order) into arrays."""
+    out, o = {}, 0
+    for k, shp in PARAM_SHAPES.items():
+        n = int(np.prod(shp))
+        out[k] = np.asarray(g[o:o + n]).reshape(shp)
+        o += n
+    return out
+
+
+class Trainer:
+    """Training state on the current device; x [n][27] and t [n][3] are
+    float32 torch tensors on that device, kept alive by this object."""
+
+    def __init__(self, x, t, batch=4096, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, seed=0):
+        import torch
+        self.x, self.t = x.contiguous(), t.contiguous()
+        self.stream = torch.cuda.current_stream(x.device)
+        self.params = lbm_train_params(batch, lr, beta1, beta2, eps, seed,
+                                       ctypes.c_void_p(self.stream.cuda_stream))
+        nbytes = lbm_train_workspace_bytes(self.params)
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=x.device)
+        self.tr = lbm_train_create(self.params, self.workspace.data_ptr(), nbytes)
+        lbm_train_set_data(self.tr, self.x.data_ptr(), self.t.data_ptr(), self.x.shape[0])
+        self.batch = batch
+
+    def __del__(self):
+        tr = getattr(self, "tr", None)
+        if tr is not None and _lib is not None:
+            _lib.lbm_train_destroy(tr)
+            self.tr = None
+
+    def set_weights(self, P):
+        lbm_train_set_weights(self.tr, P)
+
+    def step(self, n=1):
+        lbm_train_step(self.tr, n)
+
+    def loss(self):
+        return lbm_train_loss(self.tr)
+
+    def weights(self):
+        return lbm_train_get_weights(self.tr)
+
+    def gradient(self, rows):
+        import torch
+        r = torch.as_tensor(np.asarray(rows, np.int32), device=self.x.device)
+        return lbm_train_gradient(self.tr, r.data_ptr(), len(rows))
+
+    def sample_rows(self, step):
+        return lbm_train_sample_rows(self.tr, step, self.batch)
 
 
 # --- convenience: one lattice with a torch-owned workspace --------------------------

@@ -219,3 +219,29 @@ def test_oracle_default_init_uses_the_noise():
     np.testing.assert_allclose(ux[fl], 0.05 + nux[fl], atol=1e-16)
     np.testing.assert_allclose(uy[fl], nuy[fl], atol=1e-16)
     assert np.all(ux[~fl] == 0)
+
+
+def test_bf16_gradient_reduces_to_chain_rule(monkeypatch):
+    # with the roundings taken out, the MFMA-emulating gradient is the plain
+    # FP64 chain rule (itself pinned to autograd above); with them it stays
+    # within BF16 accuracy of it
+    rng = np.random.default_rng(8)
+    P = _params(rng, 0.3)
+    P.update(mu_in=0.01 * rng.standard_normal(27), sd_in=0.02 + 0.01 * rng.random(27),
+             mu_out=1e-4 * rng.standard_normal(3), sd_out=1e-3 * (1 + rng.random(3)))
+    x = 0.02 * rng.standard_normal((128, 27))
+    t = 1e-3 * rng.standard_normal((128, 3))
+    loss_b, gb = mlp.grad_bf16(x, t, P)
+    z = (x - P["mu_in"]) / P["sd_in"]
+    y = (t - P["mu_out"]) / P["sd_out"]
+    cache, o = mlp.forward_f64(z, P)
+    ref = mlp.backward_f64(cache, o, y, P)
+    for k in mlp.PARAM_NAMES:
+        assert np.linalg.norm(gb[k] - ref[k]) < 0.03 * np.linalg.norm(ref[k]), k
+    monkeypatch.setattr(mlp, "bf16_round", lambda v: np.asarray(v, np.float64))
+    monkeypatch.setattr(mlp, "standardise_f32",
+                        lambda v, mu, sd: (np.asarray(v, np.float64) - mu) / sd)
+    loss_e, ge = mlp.grad_bf16(x, t, P)
+    assert abs(loss_e - mlp.mse_loss(o, y)) < 1e-12 * loss_e
+    for k in mlp.PARAM_NAMES:
+        np.testing.assert_allclose(ge[k], ref[k], rtol=1e-10, atol=1e-14)
