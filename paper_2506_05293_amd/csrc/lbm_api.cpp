@@ -34,6 +34,44 @@ lbm_status set_error(lbm_status code, const char* fmt, ...) {
   g_err = buf;
   return code;
 }
+
+int64_t build_links(const uint8_t* mask, int nx, int ny, int pitch, int nchunk, bool xper,
+                    bool yper, uint32_t* links, uint8_t* chunk) {
+  int64_t n_fluid = 0;
+  for (int y = 0; y < ny; ++y) {
+    for (int x = 0; x < nx; ++x) {
+      uint32_t w = 0;
+      if (mask[int64_t(y) * nx + x]) {
+        w = LINK_SOLID;
+      } else {
+        ++n_fluid;
+        if (!xper && x == 0) w |= LINK_INLET;
+        if (!xper && x == nx - 1) w |= LINK_OUTLET;
+        for (int q = 1; q < 9; ++q) {
+          int sx = x - cx(q), sy = y - cy(q);
+          if (sx < 0 || sx >= nx) {
+            if (!xper) continue;               // unknown: inlet / outlet column
+            sx = (sx + nx) % nx;
+          }
+          if (sy < 0 || sy >= ny) {
+            if (!yper) {
+              w |= 1u << (LINK_BB_SHIFT + q);  // wall
+              continue;
+            }
+            sy = (sy + ny) % ny;
+          }
+          const uint8_t m = mask[int64_t(sy) * nx + sx];
+          if (m) w |= 1u << (LINK_BB_SHIFT + q);
+          if (m == 1) w |= 1u << (LINK_FORCE_SHIFT + q);
+        }
+      }
+      links[size_t(y) * pitch + x] = w;
+      if (w) chunk[size_t(y) * nchunk + (x / kChunk)] = 1;
+    }
+  }
+  return n_fluid;
+}
+
 }  // namespace lbm
 
 namespace {
@@ -335,38 +373,7 @@ lbm_status lbm_set_geometry(lbm_ctx* c, const uint8_t* mask) {
         return fail(LBM_EINVAL, "columns 0 and nx-1 must be fluid (row %d)", y);
   std::vector<uint32_t> links(size_t(c->lay.plane), 0u);
   std::vector<uint8_t> chunk(size_t(ny) * nch, 0);
-  int64_t n_fluid = 0;
-  for (int y = 0; y < ny; ++y) {
-    for (int x = 0; x < nx; ++x) {
-      uint32_t w = 0;
-      if (mask[int64_t(y) * nx + x]) {
-        w = LINK_SOLID;
-      } else {
-        ++n_fluid;
-        if (!xper && x == 0) w |= LINK_INLET;
-        if (!xper && x == nx - 1) w |= LINK_OUTLET;
-        for (int q = 1; q < 9; ++q) {
-          int sx = x - cx(q), sy = y - cy(q);
-          if (sx < 0 || sx >= nx) {
-            if (!xper) continue;               // unknown: inlet / outlet column
-            sx = (sx + nx) % nx;
-          }
-          if (sy < 0 || sy >= ny) {
-            if (!yper) {
-              w |= 1u << (LINK_BB_SHIFT + q);  // wall
-              continue;
-            }
-            sy = (sy + ny) % ny;
-          }
-          const uint8_t m = mask[int64_t(sy) * nx + sx];
-          if (m) w |= 1u << (LINK_BB_SHIFT + q);
-          if (m == 1) w |= 1u << (LINK_FORCE_SHIFT + q);
-        }
-      }
-      links[size_t(y) * pitch + x] = w;
-      if (w) chunk[size_t(y) * nch + (x / kChunk)] = 1;
-    }
-  }
+  const int64_t n_fluid = build_links(mask, nx, ny, pitch, nch, xper, yper, links.data(), chunk.data());
   HIP_TRY(hipMemcpyAsync(c->links(), links.data(), links.size() * 4, hipMemcpyHostToDevice, c->stream));
   HIP_TRY(hipMemcpyAsync(c->chunk(), chunk.data(), chunk.size(), hipMemcpyHostToDevice, c->stream));
   c->n_fluid = double(n_fluid);

@@ -1,0 +1,628 @@
+// Batched persistent launch over many uneven D2Q9 lattices (C ABI of
+// include/lbm_batch.h).
+//
+// One cooperative grid of resident workgroups advances every lattice for a
+// number of steps.  Per step:
+//   1. workgroup w reduces the partial sums of the previous step for
+//      lattices w, w + G, ... (FP64, fixed tile order) into that lattice's
+//      accumulators and force history, and retires a lattice whose force or
+//      mass is no longer finite;
+//   2. the workgroups stride over the tile table of all lattices (a tile =
+//      256 columns of one row of one lattice) and update each node with the
+//      same node code as the single-lattice kernel (FP32 offsets), logging
+//      the pre-collision populations of the logged columns on logging steps;
+//   3. a grid barrier, whose wait is bounded: a workgroup that waits longer
+//      than the spin limit raises the error flag and leaves, and every
+//      workgroup leaves once the flag is up, so the grid always drains.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "../../include/lbm_batch.h"
+#include "d2q9_dev.hpp"
+#include "lbm_internal.hpp"
+#include "node_dev.hpp"
+
+namespace lbm {
+namespace {
+
+constexpr int kDefaultSpin = 1 << 22;   // polls of ~50 ns: ~0.2 s per barrier
+
+// Fields of one lattice read by bulk_node, with A/B chosen per step.
+struct LatView {
+  const float* A;
+  float* B;
+  const uint32_t* links;
+  const uint8_t* chunk;
+  const double* inlet;
+  int nx, ny, pitch, nchunk;
+  int64_t plane;
+  int xper, yper, n_nn;
+  double omega, s_e, s_eps, s_q, u_in, one_minus_rho_out;
+};
+
+struct BatchLat {
+  float* buf[2];
+  const uint32_t* links;
+  const uint8_t* chunk;
+  int nx, ny, pitch, nchunk;
+  int64_t plane;
+  double omega, s_q, u_in, one_minus_rho_out, n_fluid;
+  int tile0, ntiles;
+  int log_role, log_x, log_row0, pad;
+};
+
+struct BatchCtl {              // device-side control words
+  unsigned count, gen;
+  int err;
+  int pad;
+};
+
+struct BatchArgs {
+  const BatchLat* lats;
+  const int4* tiles;           // (lattice, chunk column, row, 0)
+  int nlat, ntiles;
+  int xper, yper;
+  double s_e, s_eps;
+  float* part[2];              // [ntiles][4] per step parity
+  Acc* acc;                    // [nlat]
+  double* hist;                // [nlat][hist_cap][3]
+  int64_t hist_cap;
+  int* retired;                // [nlat]
+  BatchCtl* ctl;
+  int spin_limit;
+  int64_t step0, nsteps;       // steps taken before this launch, steps to take
+  int64_t log_start, log_every, log_slots;
+  int log_rows;
+  float* x;                    // data set: [slots * log_rows][27]
+  float* xa;                   // ablation inputs [slots * log_rows][27]
+  float* t;                    // targets [slots * log_rows][3] (raw f(log_x) until fixed)
+};
+
+// Logging observer of the pre-collision populations (offsets).
+struct LogHook {
+  float* x;
+  float* xa;
+  float* t;
+  int role, log_x;
+  int64_t row_base;            // sample index of row 0, or -1: not a logging step
+  __device__ void operator()(int x, int y, const float* g) const {
+    if (row_base < 0 || role == 0) return;
+    const int64_t s = row_base + y;
+    const int j = log_x - 1 - x;
+    if (j >= 0 && j < 3) {
+      float* d = (role == 1 ? this->x : xa) + s * 27 + 9 * j;
+#pragma unroll
+      for (int q = 0; q < 9; ++q) d[q] = g[q];
+    } else if (role == 1 && x == log_x) {
+      t[s * 3 + 0] = g[3];
+      t[s * 3 + 1] = g[6];
+      t[s * 3 + 2] = g[7];
+    }
+  }
+};
+
+__device__ void block_sum4_d(double s[4], double out[4]) {
+  __shared__ double red[kWaves][4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) s[k] = wave_sum(s[k]);
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) red[threadIdx.x >> 6][k] = s[k];
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) out[k] = ((red[0][k] + red[1][k]) + red[2][k]) + red[3][k];
+  }
+}
+
+// Fixed-order FP64 sum of lattice l's tile partials of one step, committed to
+// its accumulators (and its retirement flag).
+__device__ void reduce_lattice(const BatchArgs& a, int l, const float* part) {
+  const BatchLat& d = a.lats[l];
+  double s[4] = {0.0, 0.0, 0.0, 0.0}, t[4];
+  for (int k = threadIdx.x; k < d.ntiles; k += kBlock) {
+    const float4 p = reinterpret_cast<const float4*>(part)[d.tile0 + k];
+    s[0] += double(p.x);
+    s[1] += double(p.y);
+    s[2] += double(p.z);
+  }
+  block_sum4_d(s, t);
+  if (threadIdx.x == 0) {
+    Acc* acc = a.acc + l;
+    acc->fx = t[0];
+    acc->fy = t[1];
+    acc->fx_sum += t[0];
+    acc->fy_sum += t[1];
+    acc->mass = d.n_fluid + t[2];
+    const bool bad = !isfinite(t[0]) || !isfinite(t[1]) || !isfinite(t[2]);
+    if (bad) {
+      acc->nonfinite = 1;
+      a.retired[l] = 1;
+    }
+    const int64_t n = acc->n_reduced;
+    if (n < a.hist_cap) {
+      double* h = a.hist + (int64_t(l) * a.hist_cap + n) * 3;
+      h[0] = t[0];
+      h[1] = t[1];
+      h[2] = d.n_fluid + t[2];
+    }
+    acc->n_reduced = n + 1;
+  }
+}
+
+// Grid-wide barrier with a bounded wait.  Returns false (on every thread of
+// the workgroup) if the wait timed out or another workgroup raised the flag.
+// Every thread fences at device scope before arriving and after leaving:
+// the L2 caches of the eight XCDs are not coherent with each other, and the
+// next step reads populations written on other XCDs.
+__device__ bool grid_barrier(const BatchArgs& a) {
+  __shared__ int ok;
+  __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    BatchCtl* c = a.ctl;
+    int good = 1;
+    const unsigned g = __hip_atomic_load(&c->gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+    const unsigned arrived = atomicAdd(&c->count, 1u);
+    if (arrived == gridDim.x - 1) {
+      __hip_atomic_store(&c->count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_fetch_add(&c->gen, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    } else {
+      int spins = 0;
+      while (__hip_atomic_load(&c->gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == g) {
+        if (++spins > a.spin_limit ||
+            __hip_atomic_load(&c->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+          atomicExch(&c->err, 1);
+          good = 0;
+          break;
+        }
+        __builtin_amdgcn_s_sleep(2);
+      }
+    }
+    if (__hip_atomic_load(&c->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) good = 0;
+    ok = good;
+  }
+  __syncthreads();
+  __threadfence();
+  return ok != 0;
+}
+
+template <int MRT>
+__global__ void __launch_bounds__(kBlock) k_batch(const BatchArgs a) {
+  for (int64_t s = 0; s < a.nsteps; ++s) {
+    const int64_t gs = a.step0 + s;         // steps taken before this one
+    const int par = int(gs & 1);
+    // 1. the previous step's sums (pipelined into this step)
+    if (s > 0)
+      for (int l = blockIdx.x; l < a.nlat; l += gridDim.x) reduce_lattice(a, l, a.part[par ^ 1]);
+    // 2. all tiles
+    int64_t slot = -1;
+    if (gs >= a.log_start && (gs - a.log_start) % a.log_every == 0) {
+      slot = (gs - a.log_start) / a.log_every;
+      if (slot >= a.log_slots) slot = -1;
+    }
+    for (int tt = blockIdx.x; tt < a.ntiles; tt += gridDim.x) {
+      const int4 td = a.tiles[tt];
+      const BatchLat& d = a.lats[td.x];
+      float fx = 0.f, fy = 0.f, dm = 0.f;
+      if (!a.retired[td.x]) {
+        LatView v;
+        v.A = d.buf[par];
+        v.B = d.buf[par ^ 1];
+        v.links = d.links;
+        v.chunk = d.chunk;
+        v.inlet = nullptr;
+        v.nx = d.nx;
+        v.ny = d.ny;
+        v.pitch = d.pitch;
+        v.nchunk = d.nchunk;
+        v.plane = d.plane;
+        v.xper = a.xper;
+        v.yper = a.yper;
+        v.n_nn = 0;
+        v.omega = d.omega;
+        v.s_e = a.s_e;
+        v.s_eps = a.s_eps;
+        v.s_q = d.s_q;
+        v.u_in = d.u_in;
+        v.one_minus_rho_out = d.one_minus_rho_out;
+        LogHook hook{a.x, a.xa, a.t, d.log_role, d.log_x,
+                     slot < 0 ? int64_t(-1) : slot * a.log_rows + d.log_row0};
+        const int x = td.y * kChunk + int(threadIdx.x);
+        if (x < d.nx) bulk_node<float, MRT>(v, td.y, x, td.z, fx, fy, dm, hook);
+      }
+      double ps[4] = {double(fx), double(fy), double(dm), 0.0}, pt[4];
+      block_sum4_d(ps, pt);
+      if (threadIdx.x == 0)
+        reinterpret_cast<float4*>(a.part[par])[tt] =
+            make_float4(float(pt[0]), float(pt[1]), float(pt[2]), 0.f);
+    }
+    // 3. all nodes of this step written before any of the next is read
+    if (!grid_barrier(a)) return;
+  }
+  // flush: the last step's sums
+  const int last = int((a.step0 + a.nsteps - 1) & 1);
+  for (int l = blockIdx.x; l < a.nlat; l += gridDim.x) reduce_lattice(a, l, a.part[last]);
+}
+
+// t -= x[column log_x - 1] for the samples of slots [s0, s1).
+__global__ void k_fix_targets(float* t, const float* x, int64_t n0, int64_t n1) {
+  const int64_t i = n0 + int64_t(blockIdx.x) * kBlock + threadIdx.x;
+  if (i >= n1) return;
+  t[i * 3 + 0] -= x[i * 27 + 3];
+  t[i * 3 + 1] -= x[i * 27 + 6];
+  t[i * 3 + 2] -= x[i * 27 + 7];
+}
+
+size_t align256(size_t v) { return (v + 255) / 256 * 256; }
+
+}  // namespace
+}  // namespace lbm
+
+using namespace lbm;
+
+struct lbm_batch {
+  lbm_batch_params p;
+  hipStream_t stream;
+  int nlat, ntiles;
+  std::vector<BatchLat> lat;        // host copy of the descriptors
+  BatchArgs args;
+  int grid;
+  int64_t steps;
+  int64_t fixed_slots;              // slots whose targets are already corrections
+};
+
+namespace {
+
+struct BatchLayout {
+  std::vector<size_t> buf0, buf1, links, chunk;
+  size_t lats, tiles, part0, part1, acc, hist, retired, ctl, x, xa, t, total;
+  int ntiles;
+};
+
+BatchLayout batch_layout(const lbm_batch_params& p, const lbm_batch_lattice* lat, int n) {
+  BatchLayout L{};
+  size_t o = 0;
+  auto take = [&](size_t b) {
+    size_t at = o;
+    o = align256(o + b);
+    return at;
+  };
+  L.ntiles = 0;
+  for (int i = 0; i < n; ++i) {
+    const int pitch = int(align256(size_t(lat[i].nx)));
+    const int nch = pitch / kChunk;
+    const size_t plane = size_t(lat[i].ny) * pitch;
+    L.buf0.push_back(take(9 * plane * 4));
+    L.buf1.push_back(take(9 * plane * 4));
+    L.links.push_back(take(plane * 4));
+    L.chunk.push_back(take(size_t(lat[i].ny) * nch));
+    L.ntiles += nch * lat[i].ny;
+  }
+  L.lats = take(sizeof(BatchLat) * size_t(n));
+  L.tiles = take(sizeof(int4) * size_t(L.ntiles));
+  L.part0 = take(size_t(L.ntiles) * 16);
+  L.part1 = take(size_t(L.ntiles) * 16);
+  L.acc = take(sizeof(Acc) * size_t(n));
+  L.hist = take(size_t(std::max<int64_t>(p.history_cap, 0)) * 24 * size_t(n));
+  L.retired = take(4 * size_t(n));
+  L.ctl = take(sizeof(BatchCtl));
+  const size_t samples = size_t(std::max<int64_t>(p.log_slots, 0)) * size_t(std::max(p.log_rows, 0));
+  L.x = take(samples * 27 * 4);
+  L.xa = take(samples * 27 * 4);
+  L.t = take(samples * 3 * 4);
+  L.total = o;
+  return L;
+}
+
+lbm_status check_batch(const lbm_batch_params* p, const lbm_batch_lattice* lat, int n) {
+  if (!p || !lat) return set_error(LBM_EINVAL, "NULL argument");
+  if (n < 1) return set_error(LBM_EINVAL, "need at least one lattice");
+  if (p->collision != LBM_BGK && p->collision != LBM_MRT) return set_error(LBM_EINVAL, "bad collision");
+  if (p->lateral != LBM_LATERAL_WALLS && p->lateral != LBM_LATERAL_PERIODIC)
+    return set_error(LBM_EINVAL, "bad lateral");
+  if (p->history_cap < 0 || p->log_slots < 0 || p->log_rows < 0 || p->log_start < 0)
+    return set_error(LBM_EINVAL, "negative size");
+  if (p->log_slots > 0 && p->log_every < 1) return set_error(LBM_EINVAL, "log_every must be >= 1");
+  if (p->spin_limit < 0) return set_error(LBM_EINVAL, "spin_limit < 0");
+  for (int i = 0; i < n; ++i) {
+    const lbm_batch_lattice& L = lat[i];
+    if (L.nx < 8 || L.ny < 8) return set_error(LBM_EINVAL, "lattice %d: nx, ny must be >= 8", i);
+    if ((int64_t(L.nx) + 255) * L.ny * 8 >= (int64_t(1) << 32))
+      return set_error(LBM_EINVAL, "lattice %d too large", i);
+    if (!(L.tau > 0.5)) return set_error(LBM_EINVAL, "lattice %d: tau must be > 0.5", i);
+    if (!(std::fabs(L.u_in) < 0.5) || !(L.rho_out > 0))
+      return set_error(LBM_EINVAL, "lattice %d: bad u_in or rho_out", i);
+    if (!L.mask) return set_error(LBM_EINVAL, "lattice %d: mask is NULL", i);
+    if (L.log_role < 0 || L.log_role > 2) return set_error(LBM_EINVAL, "lattice %d: bad log_role", i);
+    if (L.log_role) {
+      const int lo = L.log_role == 1 ? 4 : 3;
+      if (L.log_x < lo || L.log_x > L.nx - 1) return set_error(LBM_EINVAL, "lattice %d: bad log_x", i);
+      if (L.log_row0 < 0 || int64_t(L.log_row0) + L.ny > p->log_rows)
+        return set_error(LBM_EINVAL, "lattice %d: rows exceed log_rows", i);
+    }
+  }
+  return LBM_OK;
+}
+
+#define BTRY(expr)                                                                        \
+  do {                                                                                    \
+    hipError_t e_ = (expr);                                                               \
+    if (e_ != hipSuccess) return set_error(LBM_EHIP, "%s: %s", #expr, hipGetErrorString(e_)); \
+  } while (0)
+
+lbm_status batch_sync(lbm_batch* b) {
+  BTRY(hipStreamSynchronize(b->stream));
+  BatchCtl ctl;
+  BTRY(hipMemcpy(&ctl, b->args.ctl, sizeof ctl, hipMemcpyDeviceToHost));
+  if (ctl.err) return set_error(LBM_EHIP, "batch barrier wait exceeded its bound; the batch state is void");
+  return LBM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t lbm_batch_workspace_bytes(const lbm_batch_params* p, const lbm_batch_lattice* lat, int32_t n) {
+  if (check_batch(p, lat, n) != LBM_OK) return 0;
+  return batch_layout(*p, lat, n).total;
+}
+
+lbm_status lbm_batch_create(const lbm_batch_params* p, const lbm_batch_lattice* lat, int32_t n,
+                            void* ws, size_t bytes, lbm_batch** out) {
+  if (!out) return set_error(LBM_EINVAL, "out is NULL");
+  *out = nullptr;
+  lbm_status st = check_batch(p, lat, n);
+  if (st) return st;
+  if (!ws || reinterpret_cast<uintptr_t>(ws) % 256)
+    return set_error(LBM_EINVAL, "workspace must be non-NULL and 256-byte aligned");
+  const BatchLayout L = batch_layout(*p, lat, n);
+  if (bytes < L.total) return set_error(LBM_ENOSPACE, "workspace has %zu bytes, needs %zu", bytes, L.total);
+  for (int i = 0; i < n; ++i) {
+    for (int y = 0; y < lat[i].ny; ++y)
+      if (lat[i].mask[int64_t(y) * lat[i].nx] || lat[i].mask[int64_t(y) * lat[i].nx + lat[i].nx - 1])
+        return set_error(LBM_EINVAL, "lattice %d: columns 0 and nx-1 must be fluid", i);
+    for (int64_t k = 0; k < int64_t(lat[i].nx) * lat[i].ny; ++k)
+      if (lat[i].mask[k] > 2) return set_error(LBM_EINVAL, "lattice %d: mask value > 2", i);
+  }
+  char* base = static_cast<char*>(ws);
+  hipStream_t stream = static_cast<hipStream_t>(p->stream);
+  const bool yper = p->lateral == LBM_LATERAL_PERIODIC;
+
+  lbm_batch* b = new lbm_batch();
+  b->p = *p;
+  b->stream = stream;
+  b->nlat = n;
+  b->ntiles = L.ntiles;
+  std::vector<int4> tiles;
+  tiles.reserve(L.ntiles);
+  auto cleanup = [&](lbm_status s) {
+    delete b;
+    return s;
+  };
+  for (int i = 0; i < n; ++i) {
+    const lbm_batch_lattice& q = lat[i];
+    BatchLat d{};
+    d.pitch = int(align256(size_t(q.nx)));
+    d.nchunk = d.pitch / kChunk;
+    d.nx = q.nx;
+    d.ny = q.ny;
+    d.plane = int64_t(q.ny) * d.pitch;
+    d.buf[0] = reinterpret_cast<float*>(base + L.buf0[i]);
+    d.buf[1] = reinterpret_cast<float*>(base + L.buf1[i]);
+    d.links = reinterpret_cast<const uint32_t*>(base + L.links[i]);
+    d.chunk = reinterpret_cast<const uint8_t*>(base + L.chunk[i]);
+    d.omega = 1.0 / q.tau;
+    d.s_q = p->s_q > 0 ? p->s_q : 1.0 / (0.5 + (3.0 / 16.0) / (q.tau - 0.5));
+    d.u_in = q.u_in;
+    d.one_minus_rho_out = 1.0 - q.rho_out;
+    d.tile0 = int(tiles.size());
+    for (int y = 0; y < q.ny; ++y)
+      for (int tx = 0; tx < d.nchunk; ++tx) tiles.push_back(make_int4(i, tx, y, 0));
+    d.ntiles = int(tiles.size()) - d.tile0;
+    d.log_role = q.log_role;
+    d.log_x = q.log_x;
+    d.log_row0 = q.log_row0;
+    std::vector<uint32_t> links(size_t(d.plane), 0u);
+    std::vector<uint8_t> chunk(size_t(q.ny) * d.nchunk, 0);
+    d.n_fluid = double(build_links(q.mask, q.nx, q.ny, d.pitch, d.nchunk, false, yper, links.data(),
+                                   chunk.data()));
+    hipError_t e = hipMemcpyAsync(const_cast<uint32_t*>(d.links), links.data(), links.size() * 4,
+                                  hipMemcpyHostToDevice, stream);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(const_cast<uint8_t*>(d.chunk), chunk.data(), chunk.size(),
+                         hipMemcpyHostToDevice, stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);   // host vectors go out of scope
+    if (e != hipSuccess) return cleanup(set_error(LBM_EHIP, "geometry upload: %s", hipGetErrorString(e)));
+    InitLaunch I{};
+    I.precision = LBM_FP32_OFFSET;
+    I.A = d.buf[0];
+    I.B = d.buf[1];
+    I.links = d.links;
+    I.nx = q.nx;
+    I.ny = q.ny;
+    I.pitch = d.pitch;
+    I.plane = d.plane;
+    I.y0 = 0;
+    I.rows = q.ny;
+    I.fields = nullptr;
+    I.u_in = q.u_in;
+    I.noise_amp = p->noise_amp;
+    I.seed = q.seed;
+    e = launch_init(I, stream);
+    if (e != hipSuccess) return cleanup(set_error(LBM_EHIP, "init: %s", hipGetErrorString(e)));
+    b->lat.push_back(d);
+  }
+  hipError_t e = hipMemcpyAsync(base + L.lats, b->lat.data(), sizeof(BatchLat) * size_t(n),
+                                hipMemcpyHostToDevice, stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(base + L.tiles, tiles.data(), sizeof(int4) * tiles.size(),
+                       hipMemcpyHostToDevice, stream);
+  if (e == hipSuccess) e = hipMemsetAsync(base + L.acc, 0, sizeof(Acc) * size_t(n), stream);
+  if (e == hipSuccess) e = hipMemsetAsync(base + L.retired, 0, 4 * size_t(n), stream);
+  if (e == hipSuccess) e = hipMemsetAsync(base + L.ctl, 0, sizeof(BatchCtl), stream);
+  if (e == hipSuccess) e = hipMemsetAsync(base + L.x, 0, L.t - L.x, stream);   // x, xa
+  if (e == hipSuccess) e = hipMemsetAsync(base + L.t, 0, L.total - L.t, stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(stream);
+  if (e != hipSuccess) return cleanup(set_error(LBM_EHIP, "batch set-up: %s", hipGetErrorString(e)));
+
+  BatchArgs& a = b->args;
+  a.lats = reinterpret_cast<const BatchLat*>(base + L.lats);
+  a.tiles = reinterpret_cast<const int4*>(base + L.tiles);
+  a.nlat = n;
+  a.ntiles = L.ntiles;
+  a.xper = 0;
+  a.yper = yper;
+  a.s_e = p->s_e;
+  a.s_eps = p->s_eps;
+  a.part[0] = reinterpret_cast<float*>(base + L.part0);
+  a.part[1] = reinterpret_cast<float*>(base + L.part1);
+  a.acc = reinterpret_cast<Acc*>(base + L.acc);
+  a.hist = reinterpret_cast<double*>(base + L.hist);
+  a.hist_cap = p->history_cap;
+  a.retired = reinterpret_cast<int*>(base + L.retired);
+  a.ctl = reinterpret_cast<BatchCtl*>(base + L.ctl);
+  a.spin_limit = p->spin_limit > 0 ? p->spin_limit : kDefaultSpin;
+  a.log_start = p->log_start;
+  a.log_every = p->log_every > 0 ? p->log_every : 1;
+  a.log_slots = p->log_slots;
+  a.log_rows = p->log_rows;
+  a.x = reinterpret_cast<float*>(base + L.x);
+  a.xa = reinterpret_cast<float*>(base + L.xa);
+  a.t = reinterpret_cast<float*>(base + L.t);
+
+  // co-resident grid: occupancy of the kernel times the number of CUs
+  int dev = 0, cus = 0, per_cu = 0;
+  e = hipGetDevice(&dev);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  if (e == hipSuccess)
+    e = p->collision == LBM_MRT
+            ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batch<1>, kBlock, 0)
+            : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batch<0>, kBlock, 0);
+  if (e != hipSuccess || per_cu < 1 || cus < 1)
+    return cleanup(set_error(LBM_EHIP, "occupancy query failed"));
+  b->grid = std::max(1, std::min(per_cu * cus, L.ntiles));
+  b->steps = 0;
+  b->fixed_slots = 0;
+  *out = b;
+  return LBM_OK;
+}
+
+lbm_status lbm_batch_destroy(lbm_batch* b) {
+  delete b;
+  return LBM_OK;
+}
+
+lbm_status lbm_batch_step(lbm_batch* b, int64_t nsteps) {
+  if (!b) return set_error(LBM_EINVAL, "NULL batch");
+  if (nsteps < 0) return set_error(LBM_EINVAL, "nsteps < 0");
+  if (nsteps == 0) return LBM_OK;
+  BatchArgs a = b->args;
+  a.step0 = b->steps;
+  a.nsteps = nsteps;
+  void* kargs[] = {&a};
+  const void* fn = b->p.collision == LBM_MRT ? reinterpret_cast<const void*>(k_batch<1>)
+                                             : reinterpret_cast<const void*>(k_batch<0>);
+  BTRY(hipLaunchCooperativeKernel(fn, dim3(b->grid), dim3(kBlock), kargs, 0, b->stream));
+  b->steps += nsteps;
+  return LBM_OK;
+}
+
+lbm_status lbm_batch_forces(lbm_batch* b, int32_t l, lbm_force_out* out) {
+  if (!b || !out || l < 0 || l >= b->nlat) return set_error(LBM_EINVAL, "bad argument");
+  lbm_status st = batch_sync(b);
+  if (st) return st;
+  Acc a;
+  BTRY(hipMemcpy(&a, b->args.acc + l, sizeof a, hipMemcpyDeviceToHost));
+  out->fx = a.fx;
+  out->fy = a.fy;
+  out->fx_sum = a.fx_sum;
+  out->fy_sum = a.fy_sum;
+  out->mass = a.mass;
+  out->step = b->steps;
+  out->n_fallback = 0;
+  out->nonfinite = a.nonfinite;
+  out->reserved = 0;
+  if (a.nonfinite) return set_error(LBM_EUNSTABLE, "lattice %d produced a non-finite force or mass", l);
+  return LBM_OK;
+}
+
+lbm_status lbm_batch_force_history(lbm_batch* b, int32_t l, double* fx, double* fy, int64_t cap,
+                                   int64_t* n) {
+  if (!b || !n || l < 0 || l >= b->nlat || (cap > 0 && (!fx || !fy)))
+    return set_error(LBM_EINVAL, "bad argument");
+  lbm_status st = batch_sync(b);
+  if (st) return st;
+  const int64_t m = std::min(std::min(b->steps, b->p.history_cap), cap);
+  *n = std::max<int64_t>(m, 0);
+  if (m <= 0) return LBM_OK;
+  std::vector<double> h(size_t(m) * 3);
+  BTRY(hipMemcpy(h.data(), b->args.hist + int64_t(l) * b->p.history_cap * 3, h.size() * 8,
+                 hipMemcpyDeviceToHost));
+  for (int64_t k = 0; k < m; ++k) {
+    fx[k] = h[3 * k];
+    fy[k] = h[3 * k + 1];
+  }
+  return LBM_OK;
+}
+
+lbm_status lbm_batch_read_populations(lbm_batch* b, int32_t l, double* host) {
+  if (!b || !host || l < 0 || l >= b->nlat) return set_error(LBM_EINVAL, "bad argument");
+  lbm_status st = batch_sync(b);
+  if (st) return st;
+  const BatchLat& d = b->lat[size_t(l)];
+  const int cur = int(b->steps & 1);
+  double* stage = reinterpret_cast<double*>(d.buf[cur ^ 1]);    // spare buffer
+  const size_t spare = size_t(9) * size_t(d.plane) * 4;
+  const int chunk = int(std::max<size_t>(1, std::min<size_t>(size_t(d.ny), spare / (size_t(9) * d.nx * 8))));
+  const size_t nx = size_t(d.nx), plane = nx * size_t(d.ny);
+  for (int y0 = 0; y0 < d.ny; y0 += chunk) {
+    const int rows = std::min(chunk, d.ny - y0);
+    const size_t cnt = size_t(rows) * nx;
+    BTRY(launch_read(LBM_FP32_OFFSET, d.buf[cur], stage, d.nx, d.pitch, d.plane, y0, rows, b->stream));
+    for (int q = 0; q < 9; ++q)
+      BTRY(hipMemcpyAsync(host + q * plane + y0 * nx, stage + q * cnt, cnt * 8, hipMemcpyDeviceToHost,
+                          b->stream));
+    BTRY(hipStreamSynchronize(b->stream));
+  }
+  return LBM_OK;
+}
+
+lbm_status lbm_batch_retired(lbm_batch* b, int32_t* flags) {
+  if (!b || !flags) return set_error(LBM_EINVAL, "NULL argument");
+  lbm_status st = batch_sync(b);
+  if (st) return st;
+  BTRY(hipMemcpy(flags, b->args.retired, 4 * size_t(b->nlat), hipMemcpyDeviceToHost));
+  return LBM_OK;
+}
+
+lbm_status lbm_batch_dataset(lbm_batch* b, const float** x, const float** xa, const float** t,
+                             int64_t* n) {
+  if (!b || !x || !xa || !t || !n) return set_error(LBM_EINVAL, "NULL argument");
+  const lbm_batch_params& p = b->p;
+  int64_t slots = 0;
+  if (p.log_slots > 0 && b->steps > p.log_start)
+    slots = std::min(p.log_slots, (b->steps - 1 - p.log_start) / std::max<int64_t>(p.log_every, 1) + 1);
+  if (slots > b->fixed_slots) {
+    const int64_t n0 = b->fixed_slots * p.log_rows, n1 = slots * p.log_rows;
+    hipLaunchKernelGGL(k_fix_targets, dim3(unsigned((n1 - n0 + kBlock - 1) / kBlock)), dim3(kBlock), 0,
+                       b->stream, b->args.t, b->args.x, n0, n1);
+    BTRY(hipGetLastError());
+    b->fixed_slots = slots;
+  }
+  lbm_status st = batch_sync(b);
+  if (st) return st;
+  *x = b->args.x;
+  *xa = b->args.xa;
+  *t = b->args.t;
+  *n = slots * p.log_rows;
+  return LBM_OK;
+}
+
+}  // extern "C"

@@ -85,6 +85,12 @@ hipError_t launch_step(const StepLaunch& L, hipStream_t s);
 
 // Record an error for lbm_last_error() (thread-local) and return `code`.
 lbm_status set_error(lbm_status code, const char* fmt, ...);
+
+// Per-node link words and per-(row, chunk) flags of a geometry mask (ny*nx,
+// 0 fluid, 1 body, 2 inert solid) for a lattice of row pitch `pitch`;
+// returns the number of fluid nodes.  links and chunk must be zeroed.
+int64_t build_links(const uint8_t* mask, int nx, int ny, int pitch, int nchunk, bool xper,
+                    bool yper, uint32_t* links, uint8_t* chunk);
 hipError_t launch_finalize(const StepLaunch& L, hipStream_t s);
 
 struct InitLaunch {

@@ -63,6 +63,23 @@ class lbm_mlp_host(ctypes.Structure):
                                    "mu_in", "sd_in", "mu_out", "sd_out")]
 
 
+class lbm_batch_lattice(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("tau", ctypes.c_double),
+                ("u_in", ctypes.c_double), ("rho_out", ctypes.c_double),
+                ("mask", ctypes.POINTER(ctypes.c_uint8)), ("seed", ctypes.c_uint64),
+                ("log_role", ctypes.c_int32), ("log_x", ctypes.c_int32),
+                ("log_row0", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class lbm_batch_params(ctypes.Structure):
+    _fields_ = [("collision", ctypes.c_int32), ("lateral", ctypes.c_int32),
+                ("s_e", ctypes.c_double), ("s_eps", ctypes.c_double), ("s_q", ctypes.c_double),
+                ("noise_amp", ctypes.c_double), ("history_cap", ctypes.c_int64),
+                ("log_start", ctypes.c_int64), ("log_every", ctypes.c_int64),
+                ("log_slots", ctypes.c_int64), ("log_rows", ctypes.c_int32),
+                ("spin_limit", ctypes.c_int32), ("stream", ctypes.c_void_p)]
+
+
 PARAM_SHAPES = {"w1": (64, 27), "b1": (64,), "w2": (64, 64), "b2": (64,), "w3": (3, 64), "b3": (3,)}
 N_PARAMS = 6147
 
@@ -101,6 +118,17 @@ def library():
             "lbm_sync": (I32, [VP]),
             "lbm_mlp_forward": (I32, [VP, VP, VP, I64]),
             "lbm_last_error": (ctypes.c_char_p, []),
+            "lbm_batch_workspace_bytes": (ctypes.c_size_t, [P(lbm_batch_params), P(lbm_batch_lattice),
+                                                            ctypes.c_int32]),
+            "lbm_batch_create": (I32, [P(lbm_batch_params), P(lbm_batch_lattice), ctypes.c_int32, VP,
+                                       ctypes.c_size_t, P(VP)]),
+            "lbm_batch_destroy": (I32, [VP]),
+            "lbm_batch_step": (I32, [VP, I64]),
+            "lbm_batch_forces": (I32, [VP, ctypes.c_int32, P(lbm_force_out)]),
+            "lbm_batch_force_history": (I32, [VP, ctypes.c_int32, DP, DP, I64, P(I64)]),
+            "lbm_batch_read_populations": (I32, [VP, ctypes.c_int32, DP]),
+            "lbm_batch_retired": (I32, [VP, P(ctypes.c_int32)]),
+            "lbm_batch_dataset": (I32, [VP, P(VP), P(VP), P(VP), P(I64)]),
             "lbm_train_workspace_bytes": (ctypes.c_size_t, [P(lbm_train_params)]),
             "lbm_train_create": (I32, [P(lbm_train_params), VP, ctypes.c_size_t, P(VP)]),
             "lbm_train_destroy": (I32, [VP]),
@@ -235,6 +263,135 @@ def lbm_mlp_forward(ctx, x_ptr, s_ptr, n):
 
 def lbm_last_error():
     return library().lbm_last_error().decode()
+
+
+# --- batched lattices (include/lbm_batch.h) -----------------------------------------
+
+def _lattice_array(lattices):
+    arr = (lbm_batch_lattice * len(lattices))()
+    masks = []
+    for i, L in enumerate(lattices):
+        m = np.ascontiguousarray(L["mask"], dtype=np.uint8)
+        masks.append(m)
+        ny, nx = m.shape
+        arr[i] = lbm_batch_lattice(nx, ny, L["tau"], L.get("u_in", 0.05), L.get("rho_out", 1.0),
+                                   m.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)), L.get("seed", 0),
+                                   L.get("log_role", 0), L.get("log_x", 0), L.get("log_row0", 0), 0)
+    return arr, masks
+
+
+def lbm_batch_workspace_bytes(params, lattices):
+    arr, masks = _lattice_array(lattices)
+    n = library().lbm_batch_workspace_bytes(ctypes.byref(params), arr, len(lattices))
+    if n == 0:
+        raise LbmError(LBM_EINVAL, "lbm_batch_workspace_bytes", library().lbm_last_error().decode())
+    return n
+
+
+def lbm_batch_create(params, lattices, workspace_ptr, nbytes):
+    arr, masks = _lattice_array(lattices)
+    b = ctypes.c_void_p()
+    _check(library().lbm_batch_create(ctypes.byref(params), arr, len(lattices),
+                                      ctypes.c_void_p(workspace_ptr), nbytes, ctypes.byref(b)),
+           "lbm_batch_create")
+    return b
+
+
+def lbm_batch_destroy(b):
+    return _check(library().lbm_batch_destroy(b), "lbm_batch_destroy")
+
+
+def lbm_batch_step(b, nsteps):
+    return _check(library().lbm_batch_step(b, int(nsteps)), "lbm_batch_step")
+
+
+def lbm_batch_forces(b, lattice, allow_unstable=False):
+    out = lbm_force_out()
+    st = library().lbm_batch_forces(b, lattice, ctypes.byref(out))
+    if not (allow_unstable and st == LBM_EUNSTABLE):
+        _check(st, "lbm_batch_forces")
+    return out
+
+
+def lbm_batch_force_history(b, lattice, cap):
+    fx, fy = np.zeros(cap), np.zeros(cap)
+    n = ctypes.c_int64()
+    _check(library().lbm_batch_force_history(b, lattice, _dptr(fx), _dptr(fy), cap, ctypes.byref(n)),
+           "lbm_batch_force_history")
+    return fx[:n.value], fy[:n.value]
+
+
+def lbm_batch_read_populations(b, lattice, nx, ny):
+    out = np.empty((9, ny, nx))
+    _check(library().lbm_batch_read_populations(b, lattice, _dptr(out)), "lbm_batch_read_populations")
+    return out
+
+
+def lbm_batch_retired(b, n):
+    flags = np.zeros(n, np.int32)
+    _check(library().lbm_batch_retired(b, flags.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))),
+           "lbm_batch_retired")
+    return flags
+
+
+def lbm_batch_dataset(b):
+    x, xa, t = ctypes.c_void_p(), ctypes.c_void_p(), ctypes.c_void_p()
+    n = ctypes.c_int64()
+    _check(library().lbm_batch_dataset(b, ctypes.byref(x), ctypes.byref(xa), ctypes.byref(t),
+                                       ctypes.byref(n)), "lbm_batch_dataset")
+    return x.value, xa.value, t.value, n.value
+
+
+class Batch:
+    """Many lattices advanced together; `lattices` is a list of dicts with
+    mask, tau and optionally u_in, rho_out, seed, log_role, log_x, log_row0."""
+
+    def __init__(self, lattices, *, collision="mrt", lateral="periodic", s_e=1.0, s_eps=1.0, s_q=0.0,
+                 noise_amp=0.0, history_cap=0, log_start=0, log_every=1, log_slots=0, log_rows=0,
+                 spin_limit=0, device="cuda"):
+        import torch
+        self.lattices = lattices
+        self.shapes = [np.shape(L["mask"]) for L in lattices]
+        self.stream = torch.cuda.current_stream(device)
+        self.params = lbm_batch_params(_COLL[collision], _LAT[lateral], s_e, s_eps, s_q, noise_amp,
+                                       history_cap, log_start, log_every, log_slots, log_rows,
+                                       spin_limit, ctypes.c_void_p(self.stream.cuda_stream))
+        nbytes = lbm_batch_workspace_bytes(self.params, lattices)
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=device)
+        self.b = lbm_batch_create(self.params, lattices, self.workspace.data_ptr(), nbytes)
+        self.history_cap = history_cap
+
+    def __del__(self):
+        b = getattr(self, "b", None)
+        if b is not None and _lib is not None:
+            _lib.lbm_batch_destroy(b)
+            self.b = None
+
+    def step(self, n=1):
+        lbm_batch_step(self.b, n)
+
+    def populations(self, i):
+        ny, nx = self.shapes[i]
+        return lbm_batch_read_populations(self.b, i, nx, ny)
+
+    def forces(self, i, allow_unstable=False):
+        return lbm_batch_forces(self.b, i, allow_unstable)
+
+    def force_history(self, i):
+        return lbm_batch_force_history(self.b, i, self.history_cap)
+
+    def retired(self):
+        return lbm_batch_retired(self.b, len(self.lattices))
+
+    def dataset(self):
+        """(x, x_ablation, t) as torch tensors viewing the workspace."""
+        import torch
+        xp, xap, tp, n = lbm_batch_dataset(self.b)
+        base = self.workspace.data_ptr()
+        def view(ptr, cols):
+            off = ptr - base
+            return self.workspace[off:off + n * cols * 4].view(torch.float32).view(n, cols)
+        return view(xp, 27), view(xap, 27), view(tp, 3)
 
 
 # --- training of the outflow network (include/lbm_train.h) -----------------------
