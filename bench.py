@@ -148,6 +148,56 @@ def cpu_baseline(nx, ny, seconds=15.0):
             "sample": f"{n} steps of the same {nx}x{ny} MRT lattice, FP64 NumPy, 1 thread"}
 
 
+def _jsonable(o):
+    if isinstance(o, dict):
+        return {str(k): _jsonable(v) for k, v in o.items()
+                if not hasattr(v, "data_ptr") and k not in ("batch",)}
+    if isinstance(o, (list, tuple)):
+        return [_jsonable(v) for v in o]
+    if isinstance(o, np.ndarray):
+        return o.tolist()
+    if isinstance(o, (np.floating, np.integer)):
+        return o.item()
+    return o
+
+
+def run_studies(which, scale):
+    """Training data -> training -> truncated-domain outflow study, and/or
+    the NACA0012 study; writes results/<name>.json."""
+    import torch
+    from paper_2506_05293_amd import experiments
+    os.makedirs(os.path.join(ROOT, "results"), exist_ok=True)
+    n = lambda k: max(1, int(k * scale))
+    data = experiments.generate_data(steps=n(80_000), log_every=32)
+    idx = experiments.select_rows(data)
+    x, t = data["x"][idx].contiguous(), data["t"][idx].contiguous()
+    gen = {k: data[k] for k in ("wall_s", "nodes", "mlups", "slots", "rows_per_slot")}
+    gen.update(samples=int(x.shape[0]), retired_lattices=int(data["retired"].sum()),
+               pairs=len(data["pairs"]))
+    print(json.dumps({"generate": gen}), flush=True)
+    tr = experiments.train_network(x, t, steps=n(20_000))
+    net = {k: np.asarray(v, np.float64) for k, v in tr["weights"].items()}
+    print(json.dumps({"train": {"loss_curve": tr["loss_curve"][-5:], "wall_s": tr["wall_s"]}}),
+          flush=True)
+    del data, x, t, idx
+    torch.cuda.empty_cache()
+    with open(os.path.join(ROOT, "results", "network.json"), "w") as f:
+        json.dump(_jsonable(tr["weights"]), f)
+    if which in ("nn", "all"):
+        res = experiments.outflow_study(net, steps=n(150_000))
+        out = {"generate": gen, "train": _jsonable(tr), "outflow": _jsonable(res)}
+        with open(os.path.join(ROOT, "results", "outflow_study.json"), "w") as f:
+            json.dump(out, f, indent=1)
+        print(json.dumps({"outflow_rel_err": _jsonable({re: r["rel_err"] for re, r in res.items()})}),
+              flush=True)
+    if which in ("naca", "all"):
+        res = experiments.naca_study(net, steps=n(200_000))
+        with open(os.path.join(ROOT, "results", "naca_study.json"), "w") as f:
+            json.dump(_jsonable(res), f, indent=1)
+        print(json.dumps({"naca_rel_err": _jsonable({a: r["rel_err"] for a, r in res.items()})}),
+              flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -158,6 +208,15 @@ def main():
     ap.add_argument("--precision", default="fp32", choices=list(BYTES_PER_NODE))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-nn", action="store_true")
+    ap.add_argument("--no-accuracy", action="store_true",
+                    help="skip the FP32-vs-FP64 precision study (C_D, C_L, St)")
+    ap.add_argument("--accuracy-steps", type=int, default=50_000)
+    ap.add_argument("--study", choices=["nn", "naca", "all"], default=None,
+                    help="also run the truncated-domain outflow study (training data, "
+                         "training, neural vs Zou-He outflow) and/or the NACA0012 study; "
+                         "results go to results/<study>.json")
+    ap.add_argument("--study-scale", type=float, default=1.0,
+                    help="fraction of the study step counts (for quick checks)")
     ap.add_argument("--calibration-copy", action="store_true")
     ap.add_argument("--write-traffic", nargs=4, metavar="CSV")
     args = ap.parse_args()
@@ -175,7 +234,7 @@ def main():
     nx, ny = args.nx, args.ny
     mask, tau = c2_case(nx, ny)
     lat = lbm.Lattice(mask, tau, precision=args.precision, collision="mrt", lateral="walls",
-                      u_in=0.05, noise_amp=1e-4, seed=2)
+                      u_in=0.05, noise_amp=1e-4, seed=2, s_e=1.0, s_eps=1.0, s_q=1.0)
     ms = time_steps(lat, args.steps, args.warmup, torch)
     out = lat.forces()
     assert out.nonfinite == 0
@@ -196,6 +255,17 @@ def main():
     del lat
     torch.cuda.synchronize()
 
+    accuracy = None
+    if not args.no_accuracy:
+        from paper_2506_05293_amd import experiments
+        acc = experiments.precision_study(args.accuracy_steps, nx, ny)
+        accuracy = {"workload": f"same lattice, {args.accuracy_steps} steps, FP32 offsets vs FP64",
+                    "fp32": {k: acc["fp32"].get(k) for k in ("cd_mean", "cl_rms", "st", "mlups")},
+                    "fp64": {k: acc["fp64"].get(k) for k in ("cd_mean", "cl_rms", "st", "mlups")},
+                    "rel_err": acc["rel_err"]}
+    if args.study:
+        run_studies(args.study, args.study_scale)
+
     line = {
         "metric": "MLUPS + %HBM peak; C_D/C_L/St error, NN vs Zou-He outflow at same MLUPS",
         "value": mlups, "unit": "MLUPS", "n_gpus": 1, "steps": args.steps,
@@ -212,6 +282,7 @@ def main():
                      "bytes_per_node": bpn, "kernel": "k_step (fused pull stream-collide)"},
         "hbm_fraction": gbs / HBM_PEAK_GBS,
         "nn_outflow": nn,
+        "accuracy": accuracy,
         "cpu_baseline": None if args.no_cpu_baseline else cpu_baseline(nx, ny),
     }
     print(json.dumps(line), flush=True)

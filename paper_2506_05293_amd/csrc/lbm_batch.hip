@@ -8,9 +8,10 @@
 //      accumulators and force history, and retires a lattice whose force or
 //      mass is no longer finite;
 //   2. the workgroups stride over the tile table of all lattices (a tile =
-//      256 columns of one row of one lattice) and update each node with the
-//      same node code as the single-lattice kernel (FP32 offsets), logging
-//      the pre-collision populations of the logged columns on logging steps;
+//      256 columns x 4 rows of one lattice, one row per wave, four nodes per
+//      lane with 16-byte accesses) and update each node with the same node
+//      code as the single-lattice kernel (FP32 offsets), logging the
+//      pre-collision populations of the logged columns on logging steps;
 //   3. a grid barrier, whose wait is bounded: a workgroup that waits longer
 //      than the spin limit raises the error flag and leaves, and every
 //      workgroup leaves once the flag is up, so the grid always drains.
@@ -18,6 +19,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <vector>
 
@@ -58,12 +60,12 @@ struct BatchLat {
 struct BatchCtl {              // device-side control words
   unsigned count, gen;
   int err;
-  int pad;
+  unsigned seen;               // arrivals counted when a wait gave up
 };
 
 struct BatchArgs {
   const BatchLat* lats;
-  const int4* tiles;           // (lattice, chunk column, row, 0)
+  const int4* tiles;           // (lattice, chunk column, first row, 0): 256 x 4 nodes
   int nlat, ntiles;
   int xper, yper;
   double s_e, s_eps;
@@ -178,6 +180,9 @@ __device__ bool grid_barrier(const BatchArgs& a) {
       while (__hip_atomic_load(&c->gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == g) {
         if (++spins > a.spin_limit ||
             __hip_atomic_load(&c->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+          if (!__hip_atomic_load(&c->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+            atomicMax(&c->seen, __hip_atomic_load(&c->count, __ATOMIC_RELAXED,
+                                                  __HIP_MEMORY_SCOPE_AGENT));
           atomicExch(&c->err, 1);
           good = 0;
           break;
@@ -234,8 +239,8 @@ __global__ void __launch_bounds__(kBlock) k_batch(const BatchArgs a) {
         v.one_minus_rho_out = d.one_minus_rho_out;
         LogHook hook{a.x, a.xa, a.t, d.log_role, d.log_x,
                      slot < 0 ? int64_t(-1) : slot * a.log_rows + d.log_row0};
-        const int x = td.y * kChunk + int(threadIdx.x);
-        if (x < d.nx) bulk_node<float, MRT>(v, td.y, x, td.z, fx, fy, dm, hook);
+        const int y = td.z + int(threadIdx.x >> 6);
+        if (y < d.ny) bulk_row<float, MRT>(v, td.y, y, int(threadIdx.x & 63), fx, fy, dm, hook);
       }
       double ps[4] = {double(fx), double(fy), double(dm), 0.0}, pt[4];
       block_sum4_d(ps, pt);
@@ -303,7 +308,7 @@ BatchLayout batch_layout(const lbm_batch_params& p, const lbm_batch_lattice* lat
     L.buf1.push_back(take(9 * plane * 4));
     L.links.push_back(take(plane * 4));
     L.chunk.push_back(take(size_t(lat[i].ny) * nch));
-    L.ntiles += nch * lat[i].ny;
+    L.ntiles += nch * ((lat[i].ny + kWaves - 1) / kWaves);
   }
   L.lats = take(sizeof(BatchLat) * size_t(n));
   L.tiles = take(sizeof(int4) * size_t(L.ntiles));
@@ -361,7 +366,10 @@ lbm_status batch_sync(lbm_batch* b) {
   BTRY(hipStreamSynchronize(b->stream));
   BatchCtl ctl;
   BTRY(hipMemcpy(&ctl, b->args.ctl, sizeof ctl, hipMemcpyDeviceToHost));
-  if (ctl.err) return set_error(LBM_EHIP, "batch barrier wait exceeded its bound; the batch state is void");
+  if (ctl.err)
+    return set_error(LBM_EHIP,
+                     "batch barrier wait exceeded its bound (%u of %d workgroups had arrived); "
+                     "the batch state is void", ctl.seen, b->grid);
   return LBM_OK;
 }
 
@@ -423,7 +431,7 @@ lbm_status lbm_batch_create(const lbm_batch_params* p, const lbm_batch_lattice* 
     d.u_in = q.u_in;
     d.one_minus_rho_out = 1.0 - q.rho_out;
     d.tile0 = int(tiles.size());
-    for (int y = 0; y < q.ny; ++y)
+    for (int y = 0; y < q.ny; y += kWaves)
       for (int tx = 0; tx < d.nchunk; ++tx) tiles.push_back(make_int4(i, tx, y, 0));
     d.ntiles = int(tiles.size()) - d.tile0;
     d.log_role = q.log_role;
@@ -507,7 +515,14 @@ lbm_status lbm_batch_create(const lbm_batch_params* p, const lbm_batch_lattice* 
             : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batch<0>, kBlock, 0);
   if (e != hipSuccess || per_cu < 1 || cus < 1)
     return cleanup(set_error(LBM_EHIP, "occupancy query failed"));
-  b->grid = std::max(1, std::min(per_cu * cus, L.ntiles));
+  // The occupancy query has been seen to report one workgroup per CU more
+  // than can be resident together, and a grid barrier needs every
+  // workgroup resident: keep one per CU in reserve.  LBM_BATCH_GRID_FRACTION
+  // scales the grid further (tuning).
+  double frac = 1.0;
+  if (const char* e = getenv("LBM_BATCH_GRID_FRACTION")) frac = std::min(1.0, std::max(0.05, atof(e)));
+  const int resident = std::max(1, per_cu - 1) * cus;
+  b->grid = std::max(1, std::min(int(resident * frac), L.ntiles));
   b->steps = 0;
   b->fixed_slots = 0;
   *out = b;

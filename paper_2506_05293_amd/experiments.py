@@ -1,0 +1,164 @@
+"""Studies of the method on one GPU: precision, training data, training and
+the truncated-domain comparison of the neural and Zou & He outflows.
+
+Each function runs the library's kernels (lbm.py) and returns a dict of
+results; nothing here computes the method itself.
+
+  precision_study   the walled cylinder channel in FP32 offsets and in FP64:
+                    C_D, C_L, St and their relative deviation (Sec. 2.3).
+  generate_data     a batch of cylinder pairs (long twin + truncated lattice)
+                    advanced in one persistent launch, logging network
+                    inputs and targets (Sec. 3.1 training data).
+  train_network     Adam on the logged data (Eq. 17).
+  outflow_study     truncated domains with the neural outflow (Eq. 16) and
+                    with Zou & He, against a long Zou & He reference;
+                    relative errors and cost per answer.
+  naca_study        NACA0012 (Appendix A) truncated 3 chords behind the
+                    trailing edge with both outflows, against 12 chords.
+"""
+import time
+
+import numpy as np
+
+from . import lbm, observables, workloads
+
+
+# MRT relaxation rates of every study: s_nu from tau, all other non-conserved
+# moments relaxed at rate 1.  The Lambda = 3/16 choice of s_q lets the
+# low-viscosity lattices of the data set (tau near 0.52) diverge.
+RATES = dict(s_e=1.0, s_eps=1.0, s_q=1.0)
+
+
+def _sync():
+    import torch
+    torch.cuda.synchronize()
+
+
+def run_case(case, steps, *, precision="fp32", collision="mrt", lateral="periodic",
+             network=None, mass_bound=1e-2, noise_amp=1e-4, seed=2, u_ref=workloads.U_IN,
+             length=None, window=0.4):
+    """Run one lattice for `steps` and summarise its force history."""
+    lat = lbm.Lattice(case["mask"], case["tau"], precision=precision, collision=collision,
+                      lateral=lateral, u_in=workloads.U_IN, noise_amp=noise_amp, seed=seed,
+                      history_cap=steps, **(RATES if collision == "mrt" else {}))
+    if network is not None:
+        lat.set_outflow_nn(network, mass_bound)
+    _sync()
+    t0 = time.perf_counter()
+    lat.step(steps)
+    out = lat.forces(allow_unstable=True)
+    wall = time.perf_counter() - t0
+    fx, fy = lat.force_history()
+    nodes = case["mask"].size
+    res = {"steps": steps, "nodes": int(nodes), "wall_s": wall,
+           "mlups": nodes * steps / wall / 1e6, "nonfinite": int(out.nonfinite),
+           "fallback_per_step": out.n_fallback / max(steps, 1)}
+    if not out.nonfinite:
+        res.update(observables.summarize(fx, fy, u_ref, length or case.get("D", case.get("chord")),
+                                          window))
+    del lat
+    return res
+
+
+def precision_study(steps=50_000, nx=4096, ny=1024):
+    """FP32 offsets vs FP64 on the walled cylinder channel (D = 80, Re = 200,
+    MRT): C_D within 0.5 %, C_L within 0.5 %, St within 1 % is the target."""
+    case = workloads.channel_cylinder(nx, ny, D=80 * nx // 4096)
+    r32 = run_case(case, steps, precision="fp32", lateral="walls")
+    r64 = run_case(case, steps, precision="fp64", lateral="walls")
+    return {"fp32": r32, "fp64": r64, "rel_err": observables.relative_errors(r32, r64)}
+
+
+def generate_data(n_pairs=64, steps=80_000, log_every=32, log_frac=0.4, seed=3):
+    """Training data from a persistent batch of cylinder pairs."""
+    lattices, pairs, rows = workloads.training_pairs(n_pairs, seed)
+    log_start = int(steps * (1 - log_frac))
+    slots = (steps - log_start + log_every - 1) // log_every
+    b = lbm.Batch(lattices, collision="mrt", lateral="periodic", noise_amp=1e-4, **RATES,
+                  log_start=log_start, log_every=log_every, log_slots=slots, log_rows=rows,
+                  history_cap=0)
+    _sync()
+    t0 = time.perf_counter()
+    b.step(steps)
+    x, xa, t = b.dataset()
+    wall = time.perf_counter() - t0
+    retired = b.retired()
+    nodes = sum(L["mask"].size for L in lattices)
+    keep = np.ones(rows, bool)
+    for p in pairs:
+        if retired[p["long"]] or retired[p["short"]]:
+            keep[p["row0"]:p["row0"] + p["ny"]] = False
+    return {"batch": b, "x": x, "x_ablation": xa, "t": t, "rows_per_slot": rows,
+            "slots": slots, "row_mask": keep, "pairs": pairs, "retired": retired,
+            "wall_s": wall, "nodes": int(nodes), "mlups": nodes * steps / wall / 1e6}
+
+
+def select_rows(data):
+    """Indices of logged samples from pairs that stayed finite."""
+    import torch
+    keep = np.flatnonzero(np.tile(data["row_mask"], data["slots"]))
+    return torch.as_tensor(keep, device=data["x"].device)
+
+
+def train_network(x, t, steps=20_000, batch=4096, lr=1e-3, seed=5, init_seed=6):
+    """Adam on (x, t) from Glorot-uniform weights; returns the network and
+    the loss curve."""
+    rng = np.random.default_rng(init_seed)
+
+    def glorot(o, i):
+        a = np.sqrt(6.0 / (o + i))
+        return rng.uniform(-a, a, (o, i)).astype(np.float32)
+    P = {"w1": glorot(64, 27), "b1": np.zeros(64, np.float32), "w2": glorot(64, 64),
+         "b2": np.zeros(64, np.float32), "w3": glorot(3, 64), "b3": np.zeros(3, np.float32)}
+    tr = lbm.Trainer(x, t, batch=batch, lr=lr, seed=seed)
+    tr.set_weights(P)
+    curve = []
+    _sync()
+    t0 = time.perf_counter()
+    chunk = max(1, steps // 40)
+    done = 0
+    while done < steps:
+        n = min(chunk, steps - done)
+        tr.step(n)
+        done += n
+        curve.append((done, tr.loss()))
+    wall = time.perf_counter() - t0
+    return {"weights": tr.weights(), "loss_curve": curve, "wall_s": wall,
+            "flop": 36_000.0 * batch * steps}
+
+
+def outflow_study(network, re_list=(100.0, 200.0, 400.0), steps=150_000, mass_bound=1e-2,
+                  sweep=(8, 12, 16, 24, 32), reference_d=40):
+    """Truncated cylinder lattices (D = 64, 8 D downstream) with the neural
+    and the Zou & He outflow vs the 40 D Zou & He reference; Zou & He length
+    sweep for the cost of an answer of equal accuracy."""
+    out = {}
+    for re in re_list:
+        ref = run_case(workloads.truncated_cylinder(reference_d, re=re), steps)
+        nn = run_case(workloads.truncated_cylinder(8, re=re), steps, network=network,
+                      mass_bound=mass_bound)
+        zh = {d: run_case(workloads.truncated_cylinder(d, re=re), steps) for d in sweep}
+        errs = {"nn_8d": observables.relative_errors(nn, ref) if "st" in nn else None}
+        for d, r in zh.items():
+            errs[f"zh_{d}d"] = observables.relative_errors(r, ref) if "st" in r else None
+        out[re] = {"reference": ref, "nn_8d": nn, "zouhe": zh, "rel_err": errs}
+    return out
+
+
+def naca_study(network, aoas=(0.0, 4.0, 8.0), steps=200_000, precision="fp32", mass_bound=1e-2):
+    """NACA0012, c = 256, Re = 1000, MRT: 3 C behind the trailing edge with
+    both outflows vs 12 C with Zou & He (mean C_D and C_L)."""
+    out = {}
+    for a in aoas:
+        ref = run_case(workloads.naca_case(a, after_te_chords=12.0), steps, precision=precision,
+                       length=256)
+        nn = run_case(workloads.naca_case(a), steps, precision=precision, network=network,
+                      mass_bound=mass_bound, length=256)
+        zh = run_case(workloads.naca_case(a), steps, precision=precision, length=256)
+        rel = {}
+        for name, r in (("nn_3c", nn), ("zh_3c", zh)):
+            rel[name] = ({k: abs(r[k] - ref[k]) / max(abs(ref[k]), 1e-12)
+                          for k in ("cd_mean", "cl_mean")} if "cd_mean" in r and "cd_mean" in ref
+                         else None)
+        out[a] = {"reference": ref, "nn_3c": nn, "zh_3c": zh, "rel_err": rel}
+    return out

@@ -1,7 +1,7 @@
 """GPU tests of the batched persistent launch (include/lbm_batch.h).
 
 A lattice of a batch must evolve bit for bit like the same lattice stepped
-alone (FP32 offsets, scalar tile: the same node code), whatever the other
+alone (FP32 offsets, vector tile: the same node code), whatever the other
 lattices do; its force history agrees to FP32 summation order.  Logged
 samples are checked against the pull of the state read back just before the
 logging step, computed by the oracle's streaming."""
@@ -30,7 +30,7 @@ def _lattices():
 
 @pytest.mark.parametrize("collision,lateral", [("mrt", "periodic"), ("bgk", "walls")])
 def test_batch_equals_single_lattices(collision, lateral, monkeypatch):
-    monkeypatch.setenv("LBM_BULK_PATH", "scalar")
+    monkeypatch.setenv("LBM_BULK_PATH", "vector")
     lats = _lattices()
     _say("batch vs single", collision, lateral)
     b = lbm.Batch(lats, collision=collision, lateral=lateral, noise_amp=1e-3, history_cap=200)
@@ -91,7 +91,7 @@ def test_logging_matches_pull_of_read_state():
 
 
 def test_unstable_lattice_is_retired_alone(monkeypatch):
-    monkeypatch.setenv("LBM_BULK_PATH", "scalar")
+    monkeypatch.setenv("LBM_BULK_PATH", "vector")
     lats = _lattices()[:2]
     bad = dict(mask=geometry.cylinder(200, 60, 40, 30, 20.0), tau=0.5005, u_in=0.3, seed=1)
     _say("batch retirement")

@@ -245,3 +245,22 @@ def test_bf16_gradient_reduces_to_chain_rule(monkeypatch):
     assert abs(loss_e - mlp.mse_loss(o, y)) < 1e-12 * loss_e
     for k in mlp.PARAM_NAMES:
         np.testing.assert_allclose(ge[k], ref[k], rtol=1e-10, atol=1e-14)
+
+
+def test_product_observables_agree_with_oracle():
+    # the library's host-side observables (a different peak refinement) and
+    # the oracle's recover the same synthetic Strouhal number and coefficients
+    from paper_2506_05293_amd import observables as pobs
+    rng = np.random.default_rng(9)
+    f0, D, U = 0.000911, 80.0, 0.05
+    t = np.arange(30000)
+    cl = 0.4 * np.sin(2 * np.pi * f0 * t) + 0.02 * rng.standard_normal(t.size)
+    fx = np.full(t.size, 0.3) * 0.5 * U * U * D
+    fy = cl * 0.5 * U * U * D
+    s = pobs.summarize(fx, fy, U, D, window=1.0)
+    assert abs(s["st"] / (f0 * D / U) - 1) < 1e-3
+    assert abs(s["st"] / observables.strouhal(cl, D, U) - 1) < 1e-3
+    assert abs(s["cd_mean"] - 0.3) < 1e-12
+    assert abs(s["cl_rms"] - 0.4 / np.sqrt(2)) < 5e-3
+    cd, cl2 = observables.force_coefficients(fx, fy, 1.0, U, D)
+    np.testing.assert_allclose(cl2, cl, rtol=1e-12)
