@@ -35,15 +35,20 @@ BYTES_PER_NODE = {"fp64": 144, "fp32": 72, "fp16": 36}   # 9 loads + 9 stores
 HBM_PEAK_GBS = 8000.0
 CSRC = os.path.join(ROOT, "paper_2506_05293_amd", "csrc")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "step_kernel_4096x1024_traffic.txt")
+RESULTS = os.path.join(ROOT, "results")
 CALIB_BYTES = 151 * 1024 * 1024     # bytes read (and written) by the calibration copy
 
 
+STEP_SOURCES = ("d2q9_dev.hpp", "lbm_internal.hpp", "node_dev.hpp", "mlp_dev.hpp",
+                "lbm_kernels.hip", "lbm_api.cpp")
+
+
 def kernel_source_hash():
+    """Hash of the sources the step kernel and its launcher are built from."""
     h = hashlib.sha256()
-    for name in sorted(os.listdir(CSRC)):
-        if name.endswith((".hip", ".hpp", ".cpp")):
-            with open(os.path.join(CSRC, name), "rb") as f:
-                h.update(name.encode() + f.read())
+    for name in STEP_SOURCES:
+        with open(os.path.join(CSRC, name), "rb") as f:
+            h.update(name.encode() + f.read())
     return h.hexdigest()[:16]
 
 
@@ -161,12 +166,16 @@ def _jsonable(o):
     return o
 
 
-def run_studies(which, scale):
-    """Training data -> training -> truncated-domain outflow study, and/or
-    the NACA0012 study; writes results/<name>.json."""
+def _progress(name, res):
+    keys = ("cd_mean", "cl_rms", "st", "mlups", "fallback_per_step", "nonfinite")
+    print(json.dumps({"case": name, **{k: res.get(k) for k in keys}}), flush=True)
+
+
+def train_study(scale):
+    """Training data (one batched launch) and Adam training; writes
+    results/network.json and results/training.json and returns the network."""
     import torch
     from paper_2506_05293_amd import experiments
-    os.makedirs(os.path.join(ROOT, "results"), exist_ok=True)
     n = lambda k: max(1, int(k * scale))
     data = experiments.generate_data(steps=n(80_000), log_every=32)
     idx = experiments.select_rows(data)
@@ -176,23 +185,40 @@ def run_studies(which, scale):
                pairs=len(data["pairs"]))
     print(json.dumps({"generate": gen}), flush=True)
     tr = experiments.train_network(x, t, steps=n(20_000))
-    net = {k: np.asarray(v, np.float64) for k, v in tr["weights"].items()}
     print(json.dumps({"train": {"loss_curve": tr["loss_curve"][-5:], "wall_s": tr["wall_s"]}}),
           flush=True)
     del data, x, t, idx
     torch.cuda.empty_cache()
-    with open(os.path.join(ROOT, "results", "network.json"), "w") as f:
+    with open(os.path.join(RESULTS, "network.json"), "w") as f:
         json.dump(_jsonable(tr["weights"]), f)
+    with open(os.path.join(RESULTS, "training.json"), "w") as f:
+        json.dump({"generate": gen, "train": _jsonable({k: v for k, v in tr.items()
+                                                       if k != "weights"})}, f, indent=1)
+    return {k: np.asarray(v, np.float64) for k, v in tr["weights"].items()}
+
+
+def run_studies(which, scale):
+    """train: training data and training.  nn: truncated-domain outflow study.
+    naca: NACA0012 study.  all: the three in turn.  nn and naca reuse
+    results/network.json when it exists (else they train first)."""
+    from paper_2506_05293_amd import experiments
+    os.makedirs(RESULTS, exist_ok=True)
+    n = lambda k: max(1, int(k * scale))
+    net_file = os.path.join(RESULTS, "network.json")
+    if which in ("train", "all") or not os.path.exists(net_file):
+        net = train_study(scale)
+    else:
+        with open(net_file) as f:
+            net = {k: np.asarray(v, np.float64) for k, v in json.load(f).items()}
     if which in ("nn", "all"):
-        res = experiments.outflow_study(net, steps=n(150_000))
-        out = {"generate": gen, "train": _jsonable(tr), "outflow": _jsonable(res)}
-        with open(os.path.join(ROOT, "results", "outflow_study.json"), "w") as f:
-            json.dump(out, f, indent=1)
+        res = experiments.outflow_study(net, steps=n(150_000), progress=_progress)
+        with open(os.path.join(RESULTS, "outflow_study.json"), "w") as f:
+            json.dump(_jsonable(res), f, indent=1)
         print(json.dumps({"outflow_rel_err": _jsonable({re: r["rel_err"] for re, r in res.items()})}),
               flush=True)
     if which in ("naca", "all"):
-        res = experiments.naca_study(net, steps=n(200_000))
-        with open(os.path.join(ROOT, "results", "naca_study.json"), "w") as f:
+        res = experiments.naca_study(net, steps=n(200_000), progress=_progress)
+        with open(os.path.join(RESULTS, "naca_study.json"), "w") as f:
             json.dump(_jsonable(res), f, indent=1)
         print(json.dumps({"naca_rel_err": _jsonable({a: r["rel_err"] for a, r in res.items()})}),
               flush=True)
@@ -211,7 +237,7 @@ def main():
     ap.add_argument("--no-accuracy", action="store_true",
                     help="skip the FP32-vs-FP64 precision study (C_D, C_L, St)")
     ap.add_argument("--accuracy-steps", type=int, default=50_000)
-    ap.add_argument("--study", choices=["nn", "naca", "all"], default=None,
+    ap.add_argument("--study", choices=["train", "nn", "naca", "all"], default=None,
                     help="also run the truncated-domain outflow study (training data, "
                          "training, neural vs Zou-He outflow) and/or the NACA0012 study; "
                          "results go to results/<study>.json")

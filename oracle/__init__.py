@@ -23,7 +23,10 @@ Modules
                MSE loss (Eq. 17), Adam
   splitmix64   the sequential SplitMix64 generator (Steele, Lea & Flood 2014)
   observables  drag/lift coefficients (Eq. 13) and the Strouhal number
-  masks        independent geometry checks (cylinder, NACA0012 Eq. A.1)
+
+The geometry masks (cylinder, NACA0012 of Eq. A.1) are inputs, built by the
+product's input generators and pinned on their own by closed-form tests
+(area, thickness, symmetry).
 
 Parity status: every function here is pinned by a ``-m "not gpu"`` test in
 ``tests/test_oracle_*.py`` except where its docstring says "parity unpinned".

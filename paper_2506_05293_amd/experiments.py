@@ -127,17 +127,27 @@ def train_network(x, t, steps=20_000, batch=4096, lr=1e-3, seed=5, init_seed=6):
             "flop": 36_000.0 * batch * steps}
 
 
+def _noop(*_):
+    pass
+
+
 def outflow_study(network, re_list=(100.0, 200.0, 400.0), steps=150_000, mass_bound=1e-2,
-                  sweep=(8, 12, 16, 24, 32), reference_d=40):
+                  sweep=(8, 12, 16, 24, 32), reference_d=40, progress=_noop):
     """Truncated cylinder lattices (D = 64, 8 D downstream) with the neural
     and the Zou & He outflow vs the 40 D Zou & He reference; Zou & He length
-    sweep for the cost of an answer of equal accuracy."""
+    sweep for the cost of an answer of equal accuracy.  `progress(name, res)`
+    is called after each case."""
     out = {}
     for re in re_list:
         ref = run_case(workloads.truncated_cylinder(reference_d, re=re), steps)
+        progress(f"Re {re:g} reference {reference_d} D", ref)
         nn = run_case(workloads.truncated_cylinder(8, re=re), steps, network=network,
                       mass_bound=mass_bound)
-        zh = {d: run_case(workloads.truncated_cylinder(d, re=re), steps) for d in sweep}
+        progress(f"Re {re:g} neural 8 D", nn)
+        zh = {}
+        for d in sweep:
+            zh[d] = run_case(workloads.truncated_cylinder(d, re=re), steps)
+            progress(f"Re {re:g} Zou-He {d} D", zh[d])
         errs = {"nn_8d": observables.relative_errors(nn, ref) if "st" in nn else None}
         for d, r in zh.items():
             errs[f"zh_{d}d"] = observables.relative_errors(r, ref) if "st" in r else None
@@ -145,16 +155,20 @@ def outflow_study(network, re_list=(100.0, 200.0, 400.0), steps=150_000, mass_bo
     return out
 
 
-def naca_study(network, aoas=(0.0, 4.0, 8.0), steps=200_000, precision="fp32", mass_bound=1e-2):
+def naca_study(network, aoas=(0.0, 4.0, 8.0), steps=200_000, precision="fp32", mass_bound=1e-2,
+               progress=_noop):
     """NACA0012, c = 256, Re = 1000, MRT: 3 C behind the trailing edge with
     both outflows vs 12 C with Zou & He (mean C_D and C_L)."""
     out = {}
     for a in aoas:
         ref = run_case(workloads.naca_case(a, after_te_chords=12.0), steps, precision=precision,
                        length=256)
+        progress(f"AoA {a:g} reference 12 C", ref)
         nn = run_case(workloads.naca_case(a), steps, precision=precision, network=network,
                       mass_bound=mass_bound, length=256)
+        progress(f"AoA {a:g} neural 3 C", nn)
         zh = run_case(workloads.naca_case(a), steps, precision=precision, length=256)
+        progress(f"AoA {a:g} Zou-He 3 C", zh)
         rel = {}
         for name, r in (("nn_3c", nn), ("zh_3c", zh)):
             rel[name] = ({k: abs(r[k] - ref[k]) / max(abs(ref[k]), 1e-12)

@@ -6,7 +6,8 @@ import numpy as np
 import pytest
 
 from oracle import d2q9
-from oracle.d2q9 import C, OPP
+from oracle.d2q9 import C, OPP, W
+from oracle.mlp import bf16_round
 from oracle.solver import Lattice
 from paper_2506_05293_amd import geometry
 
@@ -250,3 +251,39 @@ def test_nn_outflow_positivity_fallback():
     ref.step(5)
     np.testing.assert_array_equal(lat.f, ref.f)
     assert lat.n_fallback == 5 * ny
+
+
+@pytest.mark.parametrize("k", [0, 4, 8, 9, 13, 20, 26])
+def test_nn_outflow_feature_stencil_order(k):
+    # A network that passes one input feature through both tanh layers to
+    # one output: s_m = tanh(tanh(z_k)) sd_out + mu_out (BF16 roundings as
+    # the fused kernel makes them).  Feature k = 9 j + q is the offset
+    # f_q - w_q at column L-1-j, standardised per feature (Eq. 16 reading).
+    nx, ny = 40, 16
+    mask = geometry.cylinder(nx, ny, 10, 7.5, 5.0)
+    lat = Lattice(mask, 0.6, lateral="periodic", u_in=0.05, noise_amp=1e-3, seed=2)
+    rng = np.random.default_rng(k)
+    P = _zero_mlp()
+    m = k % 3
+    P["w1"][5, k] = 1.0
+    P["w2"][7, 5] = 1.0
+    P["w3"][m, 7] = 1.0
+    P["b3"] = np.array([0.25, -0.5, 0.125])
+    P["mu_in"] = 1e-3 * rng.standard_normal(27)
+    P["sd_in"] = rng.uniform(0.5, 2.0, 27) * 1e-2
+    P["mu_out"] = 1e-4 * rng.standard_normal(3)
+    P["sd_out"] = rng.uniform(1e-4, 1e-3, 3)
+    lat.set_outflow_nn(P, mass_bound=1e9)
+    lat.step(15)
+    fnew = lat.stream(lat.collide())
+    out = lat._outlet_nn(fnew)
+    L = nx - 1
+    q, j = k % 9, k // 9
+    x = (fnew[q, :, L - 1 - j] - W[q]).astype(np.float32)
+    z = (x - np.float32(P["mu_in"][k])) * (np.float32(1.0) / np.float32(P["sd_in"][k]))
+    h = bf16_round(np.tanh(bf16_round(np.tanh(bf16_round(z)))))
+    for r, qq in enumerate((3, 6, 7)):
+        o = P["b3"][r] + (h if r == m else 0.0)
+        np.testing.assert_allclose(out[qq], fnew[qq, :, L - 1] + o * P["sd_out"][r] + P["mu_out"][r],
+                                   rtol=0, atol=1e-15)
+    assert lat.n_fallback == 0
