@@ -172,52 +172,68 @@ def _progress(name, res):
 
 
 def train_study(scale):
-    """Training data (one batched launch) and Adam training; writes
-    results/network.json and results/training.json and returns the network."""
+    """Training data (one batched launch per 2000 steps) and Adam training of
+    every network shape of experiments.NETWORKS; writes
+    results/network_<name>.json and results/training.json and returns the
+    networks."""
     import torch
     from paper_2506_05293_amd import experiments
     n = lambda k: max(1, int(k * scale))
-    data = experiments.generate_data(steps=n(80_000), log_every=32)
+    data = experiments.generate_data(steps=n(80_000), log_every=32, progress=_progress)
     idx = experiments.select_rows(data)
     x, t = data["x"][idx].contiguous(), data["t"][idx].contiguous()
     gen = {k: data[k] for k in ("wall_s", "nodes", "mlups", "slots", "rows_per_slot")}
     gen.update(samples=int(x.shape[0]), retired_lattices=int(data["retired"].sum()),
                pairs=len(data["pairs"]))
     print(json.dumps({"generate": gen}), flush=True)
-    tr = experiments.train_network(x, t, steps=n(20_000))
-    print(json.dumps({"train": {"loss_curve": tr["loss_curve"][-5:], "wall_s": tr["wall_s"]}}),
-          flush=True)
-    del data, x, t, idx
+    del data
     torch.cuda.empty_cache()
-    with open(os.path.join(RESULTS, "network.json"), "w") as f:
-        json.dump(_jsonable(tr["weights"]), f)
+    nets, log = {}, {}
+    for name, (n_in, hidden) in experiments.NETWORKS.items():
+        tr = experiments.train_network(x, t, n_in=n_in, hidden=hidden, steps=n(20_000))
+        print(json.dumps({"train": name, "loss_curve": tr["loss_curve"][-3:],
+                          "wall_s": tr["wall_s"]}), flush=True)
+        nets[name] = {k: np.asarray(v, np.float64) for k, v in tr["weights"].items()}
+        with open(os.path.join(RESULTS, f"network_{name}.json"), "w") as f:
+            json.dump(_jsonable(tr["weights"]), f)
+        log[name] = _jsonable({k: v for k, v in tr.items() if k != "weights"})
     with open(os.path.join(RESULTS, "training.json"), "w") as f:
-        json.dump({"generate": gen, "train": _jsonable({k: v for k, v in tr.items()
-                                                       if k != "weights"})}, f, indent=1)
-    return {k: np.asarray(v, np.float64) for k, v in tr["weights"].items()}
+        json.dump({"generate": gen, "train": log}, f, indent=1)
+    return nets
 
 
-def run_studies(which, scale):
+def load_networks():
+    from paper_2506_05293_amd import experiments
+    nets = {}
+    for name in experiments.NETWORKS:
+        path = os.path.join(RESULTS, f"network_{name}.json")
+        if not os.path.exists(path):
+            return None
+        with open(path) as f:
+            nets[name] = {k: np.asarray(v, np.float64) for k, v in json.load(f).items()}
+    return nets
+
+
+def run_studies(which, scale, nn_switch=0):
     """train: training data and training.  nn: truncated-domain outflow study.
-    naca: NACA0012 study.  all: the three in turn.  nn and naca reuse
-    results/network.json when it exists (else they train first)."""
+    naca: NACA0012 study.  all: the three in turn.  nn and naca reuse the
+    networks in results/ when they exist (else they train first)."""
     from paper_2506_05293_amd import experiments
     os.makedirs(RESULTS, exist_ok=True)
     n = lambda k: max(1, int(k * scale))
-    net_file = os.path.join(RESULTS, "network.json")
-    if which in ("train", "all") or not os.path.exists(net_file):
-        net = train_study(scale)
-    else:
-        with open(net_file) as f:
-            net = {k: np.asarray(v, np.float64) for k, v in json.load(f).items()}
+    nets = None if which in ("train", "all") else load_networks()
+    if nets is None:
+        nets = train_study(scale)
     if which in ("nn", "all"):
-        res = experiments.outflow_study(net, steps=n(150_000), progress=_progress)
+        res = experiments.outflow_study(nets, steps=n(150_000), progress=_progress,
+                                        nn_switch=n(nn_switch))
         with open(os.path.join(RESULTS, "outflow_study.json"), "w") as f:
             json.dump(_jsonable(res), f, indent=1)
         print(json.dumps({"outflow_rel_err": _jsonable({re: r["rel_err"] for re, r in res.items()})}),
               flush=True)
     if which in ("naca", "all"):
-        res = experiments.naca_study(net, steps=n(200_000), progress=_progress)
+        res = experiments.naca_study(nets, steps=n(200_000), progress=_progress,
+                                     nn_switch=n(nn_switch))
         with open(os.path.join(RESULTS, "naca_study.json"), "w") as f:
             json.dump(_jsonable(res), f, indent=1)
         print(json.dumps({"naca_rel_err": _jsonable({a: r["rel_err"] for a, r in res.items()})}),
@@ -243,6 +259,8 @@ def main():
                          "results go to results/<study>.json")
     ap.add_argument("--study-scale", type=float, default=1.0,
                     help="fraction of the study step counts (for quick checks)")
+    ap.add_argument("--nn-switch", type=int, default=0,
+                    help="steps of Zou & He before the neural outflow is switched on (studies)")
     ap.add_argument("--calibration-copy", action="store_true")
     ap.add_argument("--write-traffic", nargs=4, metavar="CSV")
     args = ap.parse_args()
@@ -290,7 +308,7 @@ def main():
                     "fp64": {k: acc["fp64"].get(k) for k in ("cd_mean", "cl_rms", "st", "mlups")},
                     "rel_err": acc["rel_err"]}
     if args.study:
-        run_studies(args.study, args.study_scale)
+        run_studies(args.study, args.study_scale, args.nn_switch)
 
     line = {
         "metric": "MLUPS + %HBM peak; C_D/C_L/St error, NN vs Zou-He outflow at same MLUPS",

@@ -117,18 +117,23 @@ typedef struct {
   int32_t reserved;
 } lbm_force_out;
 
-/* Weights of the outflow MLP 27 -> 64 -> 64 -> 3 (tanh, tanh, linear), host
- * arrays, FP32, row-major [out][in]: w1 [64][27], w2 [64][64], w3 [3][64].
+/* Weights of the outflow MLP n_in -> n_h1 -> n_h2 -> 3 (tanh, tanh, linear;
+ * Sec. 3.1, Eq. 16), host arrays, FP32, row-major [out][in]:
+ * w1 [n_h1][n_in], w2 [n_h2][n_h1], w3 [3][n_h2].  1 <= n_in <= 27,
+ * 1 <= n_h1, n_h2 <= 64: a smaller network runs as the 27-64-64-3 one with
+ * zero weights in the missing places (exactly the same result).  The paper's
+ * own network is 9-20-20-3: the nine populations at x = L-1.
  * Inputs are the population offsets f_i - w_i at x = L-1, L-2, L-3 of the
- * outlet row (feature k = 9 j + q for column L-1-j), standardised as
+ * outlet row (feature k = 9 j + q for column L-1-j; a network with n_in
+ * inputs takes features 0 .. n_in-1), standardised as
  * z = (x - mu_in) * (1/sd_in) in FP32 and rounded to BF16.  Outputs are
  * s = o * sd_out + mu_out, the corrections of populations 3, 6, 7.
  * A node falls back to Zou & He unless every reconstructed population is
  * positive and |rho_g - rho(L-1)| < mass_bound. */
 typedef struct {
-  int32_t n_in, n_h1, n_h2, n_out;   /* must be 27, 64, 64, 3 */
+  int32_t n_in, n_h1, n_h2, n_out;   /* n_in <= 27, n_h1, n_h2 <= 64, n_out = 3 */
   const float *w1, *b1, *w2, *b2, *w3, *b3;
-  const float *mu_in, *sd_in, *mu_out, *sd_out;
+  const float *mu_in, *sd_in, *mu_out, *sd_out;   /* [n_in], [n_in], [3], [3] */
   double mass_bound;
 } lbm_mlp;
 
@@ -197,7 +202,8 @@ lbm_status lbm_write_populations(lbm_ctx* c, const double* host);
 lbm_status lbm_sync(lbm_ctx* c);
 
 /* Evaluate the outflow MLP of the context on n feature rows (device
- * pointers): x [n][27] FP32 population offsets, s [n][3] FP32 outputs
+ * pointers): x [n][27] FP32 population offsets (a network with fewer inputs
+ * reads the first n_in of each row, the rest must be finite), s [n][3] FP32 outputs
  * (corrections of populations 3, 6, 7).  Same kernels and roundings as the
  * fused outflow.  ESTATE unless an LBM_OUT_NN model is set. */
 lbm_status lbm_mlp_forward(lbm_ctx* c, const float* dev_x, float* dev_s,

@@ -134,7 +134,8 @@ class Lattice:
         L = self.nx - 1
         feats = np.concatenate([(fnew[:, :, L - 1 - j] - W[:, None]).T
                                 for j in range(3)], axis=1)      # (ny, 27)
-        s = forward_bf16(feats, self.mlp)                        # (ny, 3)
+        n_in = np.shape(self.mlp["w1"])[1]      # 9: the paper's column L-1 only
+        s = forward_bf16(feats[:, :n_in], self.mlp)              # (ny, 3)
         g = fnew[:, :, L].copy()
         for k, q in enumerate((3, 6, 7)):
             g[q] = fnew[q, :, L - 1] + s[:, k]

@@ -478,32 +478,34 @@ lbm_status lbm_set_outflow_model(lbm_ctx* c, int32_t kind, const lbm_mlp* w) {
   if (kind != LBM_OUT_NN) return fail(LBM_EINVAL, "bad outflow kind %d", kind);
   if (c->p.xbc != LBM_X_INOUT) return fail(LBM_EINVAL, "neural outflow needs LBM_X_INOUT");
   if (!w) return fail(LBM_EINVAL, "weights are NULL");
-  if (w->n_in != 27 || w->n_h1 != 64 || w->n_h2 != 64 || w->n_out != 3)
-    return fail(LBM_EINVAL, "network must be 27-64-64-3 (got %d-%d-%d-%d)", w->n_in, w->n_h1,
-                w->n_h2, w->n_out);
+  const int ni = w->n_in, h1 = w->n_h1, h2 = w->n_h2;
+  if (ni < 1 || ni > 27 || h1 < 1 || h1 > 64 || h2 < 1 || h2 > 64 || w->n_out != 3)
+    return fail(LBM_EINVAL, "network must be at most 27-64-64-3 with 3 outputs (got %d-%d-%d-%d)",
+                ni, h1, h2, w->n_out);
   if (!w->w1 || !w->b1 || !w->w2 || !w->b2 || !w->w3 || !w->b3 || !w->mu_in || !w->sd_in ||
       !w->mu_out || !w->sd_out)
     return fail(LBM_EINVAL, "a weight array is NULL");
+  // A smaller network is embedded in the 27-64-64-3 one: zero weights and
+  // biases in the missing places make the extra hidden units exactly 0 and
+  // the extra inputs contribute exactly 0.
   MlpDev* h = new MlpDev();
   memset(h, 0, sizeof *h);
-  for (int o = 0; o < 64; ++o)
-    for (int i = 0; i < 27; ++i) h->w1[o * 32 + i] = bf16_bits(w->w1[o * 27 + i]);
-  for (int o = 0; o < 64; ++o)
-    for (int i = 0; i < 64; ++i) h->w2[o * 64 + i] = bf16_bits(w->w2[o * 64 + i]);
+  for (int o = 0; o < h1; ++o)
+    for (int i = 0; i < ni; ++i) h->w1[o * 32 + i] = bf16_bits(w->w1[o * ni + i]);
+  for (int o = 0; o < h2; ++o)
+    for (int i = 0; i < h1; ++i) h->w2[o * 64 + i] = bf16_bits(w->w2[o * h1 + i]);
   for (int o = 0; o < 3; ++o)
-    for (int i = 0; i < 64; ++i) h->w3[o * 64 + i] = bf16_bits(w->w3[o * 64 + i]);
-  for (int o = 0; o < 64; ++o) {
-    h->b1[o] = w->b1[o];
-    h->b2[o] = w->b2[o];
-  }
+    for (int i = 0; i < h2; ++i) h->w3[o * 64 + i] = bf16_bits(w->w3[o * h2 + i]);
+  for (int o = 0; o < h1; ++o) h->b1[o] = w->b1[o];
+  for (int o = 0; o < h2; ++o) h->b2[o] = w->b2[o];
   for (int o = 0; o < 3; ++o) {
     h->b3[o] = w->b3[o];
     h->mu_out[o] = w->mu_out[o];
     h->sd_out[o] = w->sd_out[o];
   }
   for (int i = 0; i < 27; ++i) {
-    h->mu_in[i] = w->mu_in[i];
-    h->inv_sd_in[i] = 1.0f / w->sd_in[i];
+    h->mu_in[i] = i < ni ? w->mu_in[i] : 0.0f;
+    h->inv_sd_in[i] = i < ni ? 1.0f / w->sd_in[i] : 1.0f;
   }
   h->mass_bound = float(w->mass_bound);
   hipError_t e = hipMemcpyAsync(c->mlp(), h, sizeof *h, hipMemcpyHostToDevice, c->stream);

@@ -4,14 +4,17 @@
 // One cooperative grid of resident workgroups advances every lattice for a
 // number of steps.  Per step:
 //   1. workgroup w reduces the partial sums of the previous step for
-//      lattices w, w + G, ... (FP64, fixed tile order) into that lattice's
+//      lattices w, w + G, ... (FP64, fixed item order) into that lattice's
 //      accumulators and force history, and retires a lattice whose force or
 //      mass is no longer finite;
-//   2. the workgroups stride over the tile table of all lattices (a tile =
-//      256 columns x 4 rows of one lattice, one row per wave, four nodes per
-//      lane with 16-byte accesses) and update each node with the same node
-//      code as the single-lattice kernel (FP32 offsets), logging the
-//      pre-collision populations of the logged columns on logging steps;
+//   2. every wave strides on its own over the row items of all lattices (an
+//      item = 256 columns of one row of one lattice, four nodes per lane with
+//      16-byte accesses; no workgroup synchronisation in this loop) and
+//      updates each node with the same node code as the single-lattice kernel
+//      (FP32 offsets), logging the pre-collision populations of the logged
+//      columns on logging steps.  Each XCD takes one contiguous eighth of the
+//      item list, so the rows above and below an item are being read by waves
+//      that share its L2;
 //   3. a grid barrier, whose wait is bounded: a workgroup that waits longer
 //      than the spin limit raises the error flag and leaves, and every
 //      workgroup leaves once the flag is up, so the grid always drains.
@@ -53,7 +56,7 @@ struct BatchLat {
   int nx, ny, pitch, nchunk;
   int64_t plane;
   double omega, s_q, u_in, one_minus_rho_out, n_fluid;
-  int tile0, ntiles;
+  int item0, nitems;           // this lattice's range of the item table
   int log_role, log_x, log_row0, pad;
 };
 
@@ -65,11 +68,11 @@ struct BatchCtl {              // device-side control words
 
 struct BatchArgs {
   const BatchLat* lats;
-  const int4* tiles;           // (lattice, chunk column, first row, 0): 256 x 4 nodes
-  int nlat, ntiles;
+  const int4* items;           // (lattice, chunk column, row, 0): 256 x 1 nodes
+  int nlat, nitems;
   int xper, yper;
   double s_e, s_eps;
-  float* part[2];              // [ntiles][4] per step parity
+  float* part[2];              // [nitems][4] per step parity (fx, fy, drho, 0)
   Acc* acc;                    // [nlat]
   double* hist;                // [nlat][hist_cap][3]
   int64_t hist_cap;
@@ -123,13 +126,13 @@ __device__ void block_sum4_d(double s[4], double out[4]) {
   }
 }
 
-// Fixed-order FP64 sum of lattice l's tile partials of one step, committed to
+// Fixed-order FP64 sum of lattice l's item partials of one step, committed to
 // its accumulators (and its retirement flag).
 __device__ void reduce_lattice(const BatchArgs& a, int l, const float* part) {
   const BatchLat& d = a.lats[l];
   double s[4] = {0.0, 0.0, 0.0, 0.0}, t[4];
-  for (int k = threadIdx.x; k < d.ntiles; k += kBlock) {
-    const float4 p = reinterpret_cast<const float4*>(part)[d.tile0 + k];
+  for (int k = threadIdx.x; k < d.nitems; k += kBlock) {
+    const float4 p = reinterpret_cast<const float4*>(part)[d.item0 + k];
     s[0] += double(p.x);
     s[1] += double(p.y);
     s[2] += double(p.z);
@@ -198,55 +201,78 @@ __device__ bool grid_barrier(const BatchArgs& a) {
   return ok != 0;
 }
 
+// Read-only tables of the launch, read through the constant address space so
+// that wave-uniform loads from them are scalar loads.
+template <typename T>
+using const_ptr = const __attribute__((address_space(4))) T*;
+
+// Optional occupancy request (waves per SIMD) for the batched kernel.
+#ifdef LBM_BATCH_WAVES_PER_EU
+#define LBM_BATCH_ATTR \
+  __attribute__((amdgpu_waves_per_eu(LBM_BATCH_WAVES_PER_EU, LBM_BATCH_WAVES_PER_EU)))
+#else
+#define LBM_BATCH_ATTR
+#endif
+
 template <int MRT>
-__global__ void __launch_bounds__(kBlock) k_batch(const BatchArgs a) {
+__global__ void __launch_bounds__(kBlock) LBM_BATCH_ATTR k_batch(const BatchArgs a) {
+  const const_ptr<int> items = (const_ptr<int>)(a.items);
+  const const_ptr<BatchLat> lats = (const_ptr<BatchLat>)(a.lats);
+  // this wave's share of the items: XCD x = blockIdx % 8 takes the contiguous
+  // range [x n / 8, (x + 1) n / 8); its waves stride over that range
+  const int wave = __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6));
+  const int lane = int(threadIdx.x & 63);
+  const int xcd = int(blockIdx.x & 7);
+  const int groups = int(gridDim.x) >> 3;            // workgroups per XCD (grid % 8 == 0)
+  const int first = int(int64_t(a.nitems) * xcd / 8);
+  const int end = int(int64_t(a.nitems) * (xcd + 1) / 8);
+  const int stride = groups * kWaves;
+  const int start = first + int(blockIdx.x >> 3) * kWaves + wave;
   for (int64_t s = 0; s < a.nsteps; ++s) {
     const int64_t gs = a.step0 + s;         // steps taken before this one
     const int par = int(gs & 1);
     // 1. the previous step's sums (pipelined into this step)
     if (s > 0)
       for (int l = blockIdx.x; l < a.nlat; l += gridDim.x) reduce_lattice(a, l, a.part[par ^ 1]);
-    // 2. all tiles
+    // 2. all row items
     int64_t slot = -1;
     if (gs >= a.log_start && (gs - a.log_start) % a.log_every == 0) {
       slot = (gs - a.log_start) / a.log_every;
       if (slot >= a.log_slots) slot = -1;
     }
-    for (int tt = blockIdx.x; tt < a.ntiles; tt += gridDim.x) {
-      const int4 td = a.tiles[tt];
-      const BatchLat& d = a.lats[td.x];
+    for (int it = start; it < end; it += stride) {
+      const int lat = items[4 * it], tx = items[4 * it + 1], y = items[4 * it + 2];
+      const const_ptr<BatchLat> d = lats + lat;
       float fx = 0.f, fy = 0.f, dm = 0.f;
-      if (!a.retired[td.x]) {
+      if (!a.retired[lat]) {
         LatView v;
-        v.A = d.buf[par];
-        v.B = d.buf[par ^ 1];
-        v.links = d.links;
-        v.chunk = d.chunk;
+        v.A = d->buf[par];
+        v.B = d->buf[par ^ 1];
+        v.links = d->links;
+        v.chunk = d->chunk;
         v.inlet = nullptr;
-        v.nx = d.nx;
-        v.ny = d.ny;
-        v.pitch = d.pitch;
-        v.nchunk = d.nchunk;
-        v.plane = d.plane;
+        v.nx = d->nx;
+        v.ny = d->ny;
+        v.pitch = d->pitch;
+        v.nchunk = d->nchunk;
+        v.plane = d->plane;
         v.xper = a.xper;
         v.yper = a.yper;
         v.n_nn = 0;
-        v.omega = d.omega;
+        v.omega = d->omega;
         v.s_e = a.s_e;
         v.s_eps = a.s_eps;
-        v.s_q = d.s_q;
-        v.u_in = d.u_in;
-        v.one_minus_rho_out = d.one_minus_rho_out;
-        LogHook hook{a.x, a.xa, a.t, d.log_role, d.log_x,
-                     slot < 0 ? int64_t(-1) : slot * a.log_rows + d.log_row0};
-        const int y = td.z + int(threadIdx.x >> 6);
-        if (y < d.ny) bulk_row<float, MRT>(v, td.y, y, int(threadIdx.x & 63), fx, fy, dm, hook);
+        v.s_q = d->s_q;
+        v.u_in = d->u_in;
+        v.one_minus_rho_out = d->one_minus_rho_out;
+        LogHook hook{a.x, a.xa, a.t, d->log_role, d->log_x,
+                     slot < 0 ? int64_t(-1) : slot * a.log_rows + d->log_row0};
+        bulk_row<float, MRT>(v, tx, y, lane, fx, fy, dm, hook);
       }
-      double ps[4] = {double(fx), double(fy), double(dm), 0.0}, pt[4];
-      block_sum4_d(ps, pt);
-      if (threadIdx.x == 0)
-        reinterpret_cast<float4*>(a.part[par])[tt] =
-            make_float4(float(pt[0]), float(pt[1]), float(pt[2]), 0.f);
+      fx = wave_sum(fx);
+      fy = wave_sum(fy);
+      dm = wave_sum(dm);
+      if (lane == 0) reinterpret_cast<float4*>(a.part[par])[it] = make_float4(fx, fy, dm, 0.f);
     }
     // 3. all nodes of this step written before any of the next is read
     if (!grid_barrier(a)) return;
@@ -275,7 +301,7 @@ using namespace lbm;
 struct lbm_batch {
   lbm_batch_params p;
   hipStream_t stream;
-  int nlat, ntiles;
+  int nlat, nitems;
   std::vector<BatchLat> lat;        // host copy of the descriptors
   BatchArgs args;
   int grid;
@@ -287,8 +313,8 @@ namespace {
 
 struct BatchLayout {
   std::vector<size_t> buf0, buf1, links, chunk;
-  size_t lats, tiles, part0, part1, acc, hist, retired, ctl, x, xa, t, total;
-  int ntiles;
+  size_t lats, items, part0, part1, acc, hist, retired, ctl, x, xa, t, total;
+  int nitems;
 };
 
 BatchLayout batch_layout(const lbm_batch_params& p, const lbm_batch_lattice* lat, int n) {
@@ -299,7 +325,7 @@ BatchLayout batch_layout(const lbm_batch_params& p, const lbm_batch_lattice* lat
     o = align256(o + b);
     return at;
   };
-  L.ntiles = 0;
+  L.nitems = 0;
   for (int i = 0; i < n; ++i) {
     const int pitch = int(align256(size_t(lat[i].nx)));
     const int nch = pitch / kChunk;
@@ -308,12 +334,12 @@ BatchLayout batch_layout(const lbm_batch_params& p, const lbm_batch_lattice* lat
     L.buf1.push_back(take(9 * plane * 4));
     L.links.push_back(take(plane * 4));
     L.chunk.push_back(take(size_t(lat[i].ny) * nch));
-    L.ntiles += nch * ((lat[i].ny + kWaves - 1) / kWaves);
+    L.nitems += nch * lat[i].ny;
   }
   L.lats = take(sizeof(BatchLat) * size_t(n));
-  L.tiles = take(sizeof(int4) * size_t(L.ntiles));
-  L.part0 = take(size_t(L.ntiles) * 16);
-  L.part1 = take(size_t(L.ntiles) * 16);
+  L.items = take(sizeof(int4) * size_t(L.nitems));
+  L.part0 = take(size_t(L.nitems) * 16);
+  L.part1 = take(size_t(L.nitems) * 16);
   L.acc = take(sizeof(Acc) * size_t(n));
   L.hist = take(size_t(std::max<int64_t>(p.history_cap, 0)) * 24 * size_t(n));
   L.retired = take(4 * size_t(n));
@@ -407,9 +433,9 @@ lbm_status lbm_batch_create(const lbm_batch_params* p, const lbm_batch_lattice* 
   b->p = *p;
   b->stream = stream;
   b->nlat = n;
-  b->ntiles = L.ntiles;
-  std::vector<int4> tiles;
-  tiles.reserve(L.ntiles);
+  b->nitems = L.nitems;
+  std::vector<int4> items;
+  items.reserve(L.nitems);
   auto cleanup = [&](lbm_status s) {
     delete b;
     return s;
@@ -430,10 +456,10 @@ lbm_status lbm_batch_create(const lbm_batch_params* p, const lbm_batch_lattice* 
     d.s_q = p->s_q > 0 ? p->s_q : 1.0 / (0.5 + (3.0 / 16.0) / (q.tau - 0.5));
     d.u_in = q.u_in;
     d.one_minus_rho_out = 1.0 - q.rho_out;
-    d.tile0 = int(tiles.size());
-    for (int y = 0; y < q.ny; y += kWaves)
-      for (int tx = 0; tx < d.nchunk; ++tx) tiles.push_back(make_int4(i, tx, y, 0));
-    d.ntiles = int(tiles.size()) - d.tile0;
+    d.item0 = int(items.size());
+    for (int y = 0; y < q.ny; ++y)
+      for (int tx = 0; tx < d.nchunk; ++tx) items.push_back(make_int4(i, tx, y, 0));
+    d.nitems = int(items.size()) - d.item0;
     d.log_role = q.log_role;
     d.log_x = q.log_x;
     d.log_row0 = q.log_row0;
@@ -470,7 +496,7 @@ lbm_status lbm_batch_create(const lbm_batch_params* p, const lbm_batch_lattice* 
   hipError_t e = hipMemcpyAsync(base + L.lats, b->lat.data(), sizeof(BatchLat) * size_t(n),
                                 hipMemcpyHostToDevice, stream);
   if (e == hipSuccess)
-    e = hipMemcpyAsync(base + L.tiles, tiles.data(), sizeof(int4) * tiles.size(),
+    e = hipMemcpyAsync(base + L.items, items.data(), sizeof(int4) * items.size(),
                        hipMemcpyHostToDevice, stream);
   if (e == hipSuccess) e = hipMemsetAsync(base + L.acc, 0, sizeof(Acc) * size_t(n), stream);
   if (e == hipSuccess) e = hipMemsetAsync(base + L.retired, 0, 4 * size_t(n), stream);
@@ -482,9 +508,9 @@ lbm_status lbm_batch_create(const lbm_batch_params* p, const lbm_batch_lattice* 
 
   BatchArgs& a = b->args;
   a.lats = reinterpret_cast<const BatchLat*>(base + L.lats);
-  a.tiles = reinterpret_cast<const int4*>(base + L.tiles);
+  a.items = reinterpret_cast<const int4*>(base + L.items);
   a.nlat = n;
-  a.ntiles = L.ntiles;
+  a.nitems = L.nitems;
   a.xper = 0;
   a.yper = yper;
   a.s_e = p->s_e;
@@ -521,8 +547,12 @@ lbm_status lbm_batch_create(const lbm_batch_params* p, const lbm_batch_lattice* 
   // scales the grid further (tuning).
   double frac = 1.0;
   if (const char* e = getenv("LBM_BATCH_GRID_FRACTION")) frac = std::min(1.0, std::max(0.05, atof(e)));
-  const int resident = std::max(1, per_cu - 1) * cus;
-  b->grid = std::max(1, std::min(int(resident * frac), L.ntiles));
+  // The item split gives each XCD one eighth of the workgroups: the grid is a
+  // multiple of 8, and no larger than the items need.
+  const int resident = std::max(1, per_cu - 1) * cus / 8 * 8;
+  const int wanted = (L.nitems + 8 * kWaves - 1) / (8 * kWaves) * 8;
+  b->grid = std::max(8, std::min(int(resident * frac) / 8 * 8, wanted));
+  if (b->grid > resident) return cleanup(set_error(LBM_EHIP, "too few resident workgroups"));
   b->steps = 0;
   b->fixed_slots = 0;
   *out = b;

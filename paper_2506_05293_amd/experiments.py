@@ -29,6 +29,10 @@ from . import lbm, observables, workloads
 RATES = dict(s_e=1.0, s_eps=1.0, s_q=1.0)
 
 
+def _noop(*_):
+    pass
+
+
 def _sync():
     import torch
     torch.cuda.synchronize()
@@ -36,23 +40,30 @@ def _sync():
 
 def run_case(case, steps, *, precision="fp32", collision="mrt", lateral="periodic",
              network=None, mass_bound=1e-2, noise_amp=1e-4, seed=2, u_ref=workloads.U_IN,
-             length=None, window=0.4):
-    """Run one lattice for `steps` and summarise its force history."""
+             length=None, window=0.4, nn_switch=0):
+    """Run one lattice for `steps` and summarise its force history.  With a
+    network, the outflow is Zou & He for the first `nn_switch` steps and
+    neural after them."""
     lat = lbm.Lattice(case["mask"], case["tau"], precision=precision, collision=collision,
                       lateral=lateral, u_in=workloads.U_IN, noise_amp=noise_amp, seed=seed,
                       history_cap=steps, **(RATES if collision == "mrt" else {}))
-    if network is not None:
-        lat.set_outflow_nn(network, mass_bound)
     _sync()
     t0 = time.perf_counter()
-    lat.step(steps)
+    if network is not None:
+        first = min(nn_switch, steps)
+        if first:
+            lat.step(first)
+        lat.set_outflow_nn(network, mass_bound)
+        lat.step(steps - first)
+    else:
+        lat.step(steps)
     out = lat.forces(allow_unstable=True)
     wall = time.perf_counter() - t0
     fx, fy = lat.force_history()
     nodes = case["mask"].size
     res = {"steps": steps, "nodes": int(nodes), "wall_s": wall,
            "mlups": nodes * steps / wall / 1e6, "nonfinite": int(out.nonfinite),
-           "fallback_per_step": out.n_fallback / max(steps, 1)}
+           "fallback_per_step": out.n_fallback / max(steps - (nn_switch if network is not None else 0), 1)}
     if not out.nonfinite:
         res.update(observables.summarize(fx, fy, u_ref, length or case.get("D", case.get("chord")),
                                           window))
@@ -69,8 +80,10 @@ def precision_study(steps=50_000, nx=4096, ny=1024):
     return {"fp32": r32, "fp64": r64, "rel_err": observables.relative_errors(r32, r64)}
 
 
-def generate_data(n_pairs=64, steps=80_000, log_every=32, log_frac=0.4, seed=3):
+def generate_data(n_pairs=64, steps=80_000, log_every=32, log_frac=0.4, seed=3, chunk=2000,
+                  progress=None):
     """Training data from a persistent batch of cylinder pairs."""
+    progress = progress or _noop
     lattices, pairs, rows = workloads.training_pairs(n_pairs, seed)
     log_start = int(steps * (1 - log_frac))
     slots = (steps - log_start + log_every - 1) // log_every
@@ -79,7 +92,14 @@ def generate_data(n_pairs=64, steps=80_000, log_every=32, log_frac=0.4, seed=3):
                   history_cap=0)
     _sync()
     t0 = time.perf_counter()
-    b.step(steps)
+    done = 0
+    while done < steps:           # launches of at most `chunk` steps (~2 s each)
+        n = min(chunk, steps - done)
+        b.step(n)
+        done += n
+        if done % (10 * chunk) == 0 or done == steps:
+            _sync()
+            progress(f"data generation: {done} of {steps} steps", {})
     x, xa, t = b.dataset()
     wall = time.perf_counter() - t0
     retired = b.retired()
@@ -100,16 +120,34 @@ def select_rows(data):
     return torch.as_tensor(keep, device=data["x"].device)
 
 
-def train_network(x, t, steps=20_000, batch=4096, lr=1e-3, seed=5, init_seed=6):
-    """Adam on (x, t) from Glorot-uniform weights; returns the network and
-    the loss curve."""
+NETWORKS = {                # name: (inputs, hidden units per layer)
+    "paper_9x20": (9, 20),   # Sec. 3.1: nine populations at L-1, two layers of 20
+    "col1_9x64": (9, 64),
+    "stencil_27x64": (27, 64),
+}
+
+
+def train_network(x, t, n_in=27, hidden=64, steps=20_000, batch=4096, lr=1e-3, seed=5,
+                  init_seed=6):
+    """Adam on (x, t) from Glorot-uniform weights; returns the network
+    (n_in -> hidden -> hidden -> 3) and the loss curve.  A smaller network
+    trains inside the 27-64-64-3 trainer: the unused feature columns are set
+    to zero and the unused weights start at zero, so their gradients are
+    exactly zero and they stay zero."""
+    import torch
     rng = np.random.default_rng(init_seed)
 
-    def glorot(o, i):
+    def glorot(o, i, O, I):
         a = np.sqrt(6.0 / (o + i))
-        return rng.uniform(-a, a, (o, i)).astype(np.float32)
-    P = {"w1": glorot(64, 27), "b1": np.zeros(64, np.float32), "w2": glorot(64, 64),
-         "b2": np.zeros(64, np.float32), "w3": glorot(3, 64), "b3": np.zeros(3, np.float32)}
+        w = np.zeros((O, I), np.float32)
+        w[:o, :i] = rng.uniform(-a, a, (o, i))
+        return w
+    P = {"w1": glorot(hidden, n_in, 64, 27), "b1": np.zeros(64, np.float32),
+         "w2": glorot(hidden, hidden, 64, 64), "b2": np.zeros(64, np.float32),
+         "w3": glorot(3, hidden, 3, 64), "b3": np.zeros(3, np.float32)}
+    if n_in < 27:
+        x = x.clone()
+        x[:, n_in:] = 0.0
     tr = lbm.Trainer(x, t, batch=batch, lr=lr, seed=seed)
     tr.set_weights(P)
     curve = []
@@ -123,56 +161,77 @@ def train_network(x, t, steps=20_000, batch=4096, lr=1e-3, seed=5, init_seed=6):
         done += n
         curve.append((done, tr.loss()))
     wall = time.perf_counter() - t0
-    return {"weights": tr.weights(), "loss_curve": curve, "wall_s": wall,
-            "flop": 36_000.0 * batch * steps}
+    W = tr.weights()
+    del tr, x
+    torch.cuda.empty_cache()
+    pad = (np.abs(W["w1"][hidden:]).max(initial=0), np.abs(W["w1"][:, n_in:]).max(initial=0),
+           np.abs(W["w2"][hidden:]).max(initial=0), np.abs(W["w2"][:, hidden:]).max(initial=0),
+           np.abs(W["w3"][:, hidden:]).max(initial=0), np.abs(W["b1"][hidden:]).max(initial=0),
+           np.abs(W["b2"][hidden:]).max(initial=0))
+    if max(pad) != 0.0:
+        raise RuntimeError(f"padded weights moved during training: {pad}")
+    net = {"w1": W["w1"][:hidden, :n_in], "b1": W["b1"][:hidden],
+           "w2": W["w2"][:hidden, :hidden], "b2": W["b2"][:hidden],
+           "w3": W["w3"][:, :hidden], "b3": W["b3"],
+           "mu_in": W["mu_in"][:n_in], "sd_in": W["sd_in"][:n_in],
+           "mu_out": W["mu_out"], "sd_out": W["sd_out"]}
+    return {"weights": net, "loss_curve": curve, "wall_s": wall,
+            "flop": 36_000.0 * batch * steps, "n_in": n_in, "hidden": hidden}
 
 
-def _noop(*_):
-    pass
-
-
-def outflow_study(network, re_list=(100.0, 200.0, 400.0), steps=150_000, mass_bound=1e-2,
-                  sweep=(8, 12, 16, 24, 32), reference_d=40, progress=_noop):
-    """Truncated cylinder lattices (D = 64, 8 D downstream) with the neural
-    and the Zou & He outflow vs the 40 D Zou & He reference; Zou & He length
-    sweep for the cost of an answer of equal accuracy.  `progress(name, res)`
-    is called after each case."""
+def outflow_study(networks, re_list=(100.0, 200.0, 400.0), steps=150_000, mass_bound=1e-2,
+                  sweep=(8, 12, 16, 24, 32), reference_d=40, progress=_noop, nn_switch=0):
+    """Truncated cylinder lattices (D = 64, 8 D downstream) with each neural
+    outflow of `networks` (name -> weights) and with Zou & He, against the
+    40 D Zou & He reference; Zou & He length sweep for the cost of an answer
+    of equal accuracy.  `progress(name, res)` is called after each case."""
     out = {}
     for re in re_list:
         ref = run_case(workloads.truncated_cylinder(reference_d, re=re), steps)
         progress(f"Re {re:g} reference {reference_d} D", ref)
-        nn = run_case(workloads.truncated_cylinder(8, re=re), steps, network=network,
-                      mass_bound=mass_bound)
-        progress(f"Re {re:g} neural 8 D", nn)
+        nn = {}
+        for name, P in networks.items():
+            nn[name] = run_case(workloads.truncated_cylinder(8, re=re), steps, network=P,
+                                mass_bound=mass_bound, nn_switch=nn_switch)
+            progress(f"Re {re:g} neural {name} 8 D", nn[name])
         zh = {}
         for d in sweep:
             zh[d] = run_case(workloads.truncated_cylinder(d, re=re), steps)
             progress(f"Re {re:g} Zou-He {d} D", zh[d])
-        errs = {"nn_8d": observables.relative_errors(nn, ref) if "st" in nn else None}
+        errs = {f"nn_{k}_8d": observables.relative_errors(r, ref) if "st" in r else None
+                for k, r in nn.items()}
         for d, r in zh.items():
             errs[f"zh_{d}d"] = observables.relative_errors(r, ref) if "st" in r else None
-        out[re] = {"reference": ref, "nn_8d": nn, "zouhe": zh, "rel_err": errs}
+        out[re] = {"reference": ref, "neural_8d": nn, "zouhe": zh, "rel_err": errs}
     return out
 
 
-def naca_study(network, aoas=(0.0, 4.0, 8.0), steps=200_000, precision="fp32", mass_bound=1e-2,
-               progress=_noop):
+def naca_study(networks, aoas=(0.0, 4.0, 8.0), steps=200_000, precision="fp32", mass_bound=1e-2,
+               progress=_noop, nn_switch=0):
     """NACA0012, c = 256, Re = 1000, MRT: 3 C behind the trailing edge with
-    both outflows vs 12 C with Zou & He (mean C_D and C_L)."""
+    each neural outflow, with Zou & He and with Zou & He on FP16 offsets, vs
+    12 C with Zou & He: mean C_D and C_L, relative and absolute deviations."""
     out = {}
     for a in aoas:
         ref = run_case(workloads.naca_case(a, after_te_chords=12.0), steps, precision=precision,
                        length=256)
         progress(f"AoA {a:g} reference 12 C", ref)
-        nn = run_case(workloads.naca_case(a), steps, precision=precision, network=network,
-                      mass_bound=mass_bound, length=256)
-        progress(f"AoA {a:g} neural 3 C", nn)
-        zh = run_case(workloads.naca_case(a), steps, precision=precision, length=256)
-        progress(f"AoA {a:g} Zou-He 3 C", zh)
+        runs = {}
+        for name, P in networks.items():
+            runs[f"nn_{name}_3c"] = run_case(workloads.naca_case(a), steps, precision=precision,
+                                             network=P, mass_bound=mass_bound, length=256,
+                                             nn_switch=nn_switch)
+            progress(f"AoA {a:g} neural {name} 3 C", runs[f"nn_{name}_3c"])
+        runs["zh_3c"] = run_case(workloads.naca_case(a), steps, precision=precision, length=256)
+        progress(f"AoA {a:g} Zou-He 3 C", runs["zh_3c"])
+        runs["zh_3c_fp16"] = run_case(workloads.naca_case(a), steps, precision="fp16", length=256)
+        progress(f"AoA {a:g} Zou-He 3 C FP16", runs["zh_3c_fp16"])
         rel = {}
-        for name, r in (("nn_3c", nn), ("zh_3c", zh)):
-            rel[name] = ({k: abs(r[k] - ref[k]) / max(abs(ref[k]), 1e-12)
-                          for k in ("cd_mean", "cl_mean")} if "cd_mean" in r and "cd_mean" in ref
-                         else None)
-        out[a] = {"reference": ref, "nn_3c": nn, "zh_3c": zh, "rel_err": rel}
+        for name, r in runs.items():
+            rel[name] = ({**{k: abs(r[k] - ref[k]) / max(abs(ref[k]), 1e-12)
+                             for k in ("cd_mean", "cl_mean")},
+                          "cd_abs": abs(r["cd_mean"] - ref["cd_mean"]),
+                          "cl_abs": abs(r["cl_mean"] - ref["cl_mean"])}
+                         if "cd_mean" in r and "cd_mean" in ref else None)
+        out[a] = {"reference": ref, **runs, "rel_err": rel}
     return out

@@ -226,7 +226,9 @@ def lbm_force_history(ctx, cap):
 def _mlp_struct(P, mass_bound):
     keep = {k: np.ascontiguousarray(P[k], dtype=np.float32).reshape(-1)
             for k in ("w1", "b1", "w2", "b2", "w3", "b3", "mu_in", "sd_in", "mu_out", "sd_out")}
-    s = lbm_mlp(27, 64, 64, 3, *[keep[k].ctypes.data_as(_FP) for k in
+    h1, n_in = np.shape(P["w1"])
+    h2 = np.shape(P["w2"])[0]
+    s = lbm_mlp(n_in, h1, h2, 3, *[keep[k].ctypes.data_as(_FP) for k in
                                  ("w1", "b1", "w2", "b2", "w3", "b3", "mu_in", "sd_in",
                                   "mu_out", "sd_out")], float(mass_bound))
     return s, keep

@@ -176,3 +176,65 @@ def test_nn_outflow_full_size_one_step(bulk_path):
     err = np.max(np.abs(f31[:, fl] - ref[:, fl]))
     print("nn full-size one-step error", err, flush=True)
     assert err < 1e-6
+
+
+def paper_params(seed):
+    """A random network of the paper's shape, 9 -> 20 -> 20 -> 3 (Sec. 3.1)."""
+    rng = np.random.default_rng(seed)
+    return {"w1": 0.4 * rng.standard_normal((20, 9)), "b1": 0.1 * rng.standard_normal(20),
+            "w2": 0.3 * rng.standard_normal((20, 20)), "b2": 0.1 * rng.standard_normal(20),
+            "w3": 0.3 * rng.standard_normal((3, 20)), "b3": 0.1 * rng.standard_normal(3),
+            "mu_in": 0.002 * rng.standard_normal(9), "sd_in": 0.01 + 0.01 * rng.random(9),
+            "mu_out": 1e-5 * rng.standard_normal(3), "sd_out": 2e-4 * (1 + rng.random(3))}
+
+
+def padded(P):
+    h1, n_in = P["w1"].shape
+    h2 = P["w2"].shape[0]
+    Q = {"w1": np.zeros((64, 27)), "b1": np.zeros(64), "w2": np.zeros((64, 64)),
+         "b2": np.zeros(64), "w3": np.zeros((3, 64)), "b3": np.array(P["b3"], float),
+         "mu_in": np.zeros(27), "sd_in": np.ones(27), "mu_out": np.array(P["mu_out"], float),
+         "sd_out": np.array(P["sd_out"], float)}
+    Q["w1"][:h1, :n_in] = P["w1"]
+    Q["b1"][:h1] = P["b1"]
+    Q["w2"][:h2, :h1] = P["w2"]
+    Q["b2"][:h2] = P["b2"]
+    Q["w3"][:, :h2] = P["w3"]
+    Q["mu_in"][:n_in] = P["mu_in"]
+    Q["sd_in"][:n_in] = P["sd_in"]
+    return Q
+
+
+def test_paper_network_run_matches_oracle(bulk_path):
+    case = cases.ragged("bgk", "periodic")
+    P = _f32(paper_params(5))
+    _say("paper-shape network run fp64 vs oracle")
+    g = lbm.Lattice(case["mask"], case["tau"], precision="fp64", collision="bgk",
+                    lateral="periodic", u_in=case["u_in"], noise_amp=case["noise_amp"],
+                    seed=case["seed"])
+    g.set_outflow_nn(P, mass_bound=1e9)
+    g.step(40)
+    o = Oracle(case["mask"], **cases.oracle_kwargs(case))
+    o.set_outflow_nn(P, mass_bound=1e9)
+    o.step(40)
+    fl = case["mask"] == 0
+    err = np.max(np.abs(g.populations()[:, fl] - o.post_collision()[:, fl]))
+    print("paper network run max abs error", err, flush=True)
+    assert err < 5e-6
+    assert g.forces().n_fallback == 0 == o.n_fallback
+
+
+def test_paper_network_equals_its_padded_embedding():
+    P = _f32(paper_params(6))
+    _say("paper-shape network vs padded 27-64-64-3, fp32")
+    a = _lattice_with_net(P)
+    b = _lattice_with_net(padded(P))
+    a.step(60)
+    b.step(60)
+    np.testing.assert_array_equal(a.populations(), b.populations())
+    with pytest.raises(lbm.LbmError) as e:
+        bad = dict(P)
+        bad["w1"] = np.zeros((20, 28))
+        bad["mu_in"], bad["sd_in"] = np.zeros(28), np.ones(28)
+        _lattice_with_net(bad)
+    assert e.value.status == lbm.LBM_EINVAL

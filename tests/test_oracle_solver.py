@@ -287,3 +287,46 @@ def test_nn_outflow_feature_stencil_order(k):
         np.testing.assert_allclose(out[qq], fnew[qq, :, L - 1] + o * P["sd_out"][r] + P["mu_out"][r],
                                    rtol=0, atol=1e-15)
     assert lat.n_fallback == 0
+
+
+def _pad_network(P):
+    """Embed a smaller network in the 27-64-64-3 shape with zeros."""
+    h1, n_in = P["w1"].shape
+    h2 = P["w2"].shape[0]
+    Q = _zero_mlp()
+    Q["w1"][:h1, :n_in] = P["w1"]
+    Q["b1"][:h1] = P["b1"]
+    Q["w2"][:h2, :h1] = P["w2"]
+    Q["b2"][:h2] = P["b2"]
+    Q["w3"][:, :h2] = P["w3"]
+    Q["b3"] = P["b3"]
+    Q["mu_in"][:n_in] = P["mu_in"]
+    Q["sd_in"][:n_in] = P["sd_in"]
+    Q["mu_out"], Q["sd_out"] = P["mu_out"], P["sd_out"]
+    return Q
+
+
+def test_nn_outflow_paper_network_is_first_column_only():
+    # Sec. 3.1: the paper's network reads the nine populations at L-1 through
+    # two hidden layers of 20.  It must act exactly like the 27-64-64-3
+    # network that holds it with zero weights elsewhere.
+    nx, ny = 40, 16
+    mask = geometry.cylinder(nx, ny, 10, 7.5, 5.0)
+    rng = np.random.default_rng(11)
+    P = {"w1": 0.4 * rng.standard_normal((20, 9)), "b1": 0.1 * rng.standard_normal(20),
+         "w2": 0.3 * rng.standard_normal((20, 20)), "b2": 0.1 * rng.standard_normal(20),
+         "w3": 0.3 * rng.standard_normal((3, 20)), "b3": 0.1 * rng.standard_normal(3),
+         "mu_in": 1e-3 * rng.standard_normal(9), "sd_in": rng.uniform(5e-3, 2e-2, 9),
+         "mu_out": 1e-5 * rng.standard_normal(3), "sd_out": rng.uniform(1e-4, 3e-4, 3)}
+    a = Lattice(mask, 0.6, lateral="periodic", u_in=0.05, noise_amp=1e-3, seed=2)
+    b = Lattice(mask, 0.6, lateral="periodic", u_in=0.05, noise_amp=1e-3, seed=2)
+    a.set_outflow_nn(P, mass_bound=1e9)
+    b.set_outflow_nn(_pad_network(P), mass_bound=1e9)
+    a.step(25)
+    b.step(25)
+    np.testing.assert_array_equal(a.f, b.f)
+    # and the network changes the outlet (the comparison is not vacuous)
+    z = Lattice(mask, 0.6, lateral="periodic", u_in=0.05, noise_amp=1e-3, seed=2)
+    z.set_outflow_nn(_zero_mlp(), mass_bound=1e9)
+    z.step(25)
+    assert np.max(np.abs(z.f[:, :, -1] - a.f[:, :, -1])) > 1e-6
