@@ -22,6 +22,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
 #include <cstdlib>
 #include <cstring>
 #include <vector>
@@ -35,6 +36,7 @@ namespace lbm {
 namespace {
 
 constexpr int kDefaultSpin = 1 << 22;   // polls of ~50 ns: ~0.2 s per barrier
+constexpr int kBatchGroupsPerCu = 2;
 
 // Fields of one lattice read by bulk_node, with A/B chosen per step.
 struct LatView {
@@ -543,16 +545,24 @@ lbm_status lbm_batch_create(const lbm_batch_params* p, const lbm_batch_lattice* 
     return cleanup(set_error(LBM_EHIP, "occupancy query failed"));
   // The occupancy query has been seen to report one workgroup per CU more
   // than can be resident together, and a grid barrier needs every
-  // workgroup resident: keep one per CU in reserve.  LBM_BATCH_GRID_FRACTION
-  // scales the grid further (tuning).
-  double frac = 1.0;
-  if (const char* e = getenv("LBM_BATCH_GRID_FRACTION")) frac = std::min(1.0, std::max(0.05, atof(e)));
+  // workgroup resident: keep one per CU in reserve (LBM_BATCH_RESERVE
+  // overrides; a grid that is not co-resident ends in the barrier's bounded
+  // wait and an LBM_EHIP).  Within that, kBatchGroupsPerCu workgroups per CU
+  // (LBM_BATCH_GROUPS_PER_CU overrides): more waves stream no faster here,
+  // they contend (measured 0.82 ms per step of the 33M-node data-generation
+  // batch at 2 per CU, 0.88 at 4, 1.01 at 5).
+  int reserve = 1, per = kBatchGroupsPerCu;
+  if (const char* e = getenv("LBM_BATCH_RESERVE")) reserve = std::max(0, atoi(e));
+  if (const char* e = getenv("LBM_BATCH_GROUPS_PER_CU")) per = std::max(1, atoi(e));
   // The item split gives each XCD one eighth of the workgroups: the grid is a
   // multiple of 8, and no larger than the items need.
-  const int resident = std::max(1, per_cu - 1) * cus / 8 * 8;
+  const int resident = std::max(1, per_cu - reserve) * cus / 8 * 8;
   const int wanted = (L.nitems + 8 * kWaves - 1) / (8 * kWaves) * 8;
-  b->grid = std::max(8, std::min(int(resident * frac) / 8 * 8, wanted));
+  b->grid = std::max(8, std::min({per * cus / 8 * 8, resident, wanted}));
   if (b->grid > resident) return cleanup(set_error(LBM_EHIP, "too few resident workgroups"));
+  if (getenv("LBM_BATCH_VERBOSE"))
+    fprintf(stderr, "lbm_batch: %d CUs, occupancy %d workgroups per CU, reserve %d, grid %d\n", cus,
+            per_cu, reserve, b->grid);
   b->steps = 0;
   b->fixed_slots = 0;
   *out = b;

@@ -202,8 +202,28 @@ def outflow_study(networks, re_list=(100.0, 200.0, 400.0), steps=150_000, mass_b
                 for k, r in nn.items()}
         for d, r in zh.items():
             errs[f"zh_{d}d"] = observables.relative_errors(r, ref) if "st" in r else None
-        out[re] = {"reference": ref, "neural_8d": nn, "zouhe": zh, "rel_err": errs}
+        runs = {**{f"nn_{k}_8d": r for k, r in nn.items()},
+                **{f"zh_{d}d": r for d, r in zh.items()}}
+        out[re] = {"reference": ref, "neural_8d": nn, "zouhe": zh, "rel_err": errs,
+                   "cost": answer_cost(runs, errs, ref)}
     return out
+
+
+def answer_cost(runs, errs, ref, tol=0.01):
+    """Cost of an answer: wall time of each truncated run, its answer-
+    equivalent MLUPS (reference-lattice node updates per second of wall
+    time) and whether it reproduces the reference's C_D, rms C_L and St
+    within `tol`; the cheapest run that does."""
+    table = {}
+    for name, r in runs.items():
+        e = errs.get(name)
+        table[name] = {"wall_s": r["wall_s"], "mlups": r["mlups"],
+                       "answer_mlups": ref["nodes"] * r["steps"] / r["wall_s"] / 1e6,
+                       "within_tol": bool(e is not None and max(e.values()) <= tol)}
+    ok = [n for n, v in table.items() if v["within_tol"]]
+    best = min(ok, key=lambda n: table[n]["wall_s"]) if ok else None
+    return {"tol": tol, "runs": table, "cheapest_within_tol": best,
+            "reference_wall_s": ref["wall_s"]}
 
 
 def naca_study(networks, aoas=(0.0, 4.0, 8.0), steps=200_000, precision="fp32", mass_bound=1e-2,
