@@ -36,7 +36,13 @@ namespace lbm {
 namespace {
 
 constexpr int kDefaultSpin = 1 << 22;   // polls of ~50 ns: ~0.2 s per barrier
-constexpr int kBatchGroupsPerCu = 2;
+constexpr int kBatchGroupsPerCu = 4;
+// s_waitcnt operand (gfx9 encoding) that waits for vmcnt = 0 only:
+// vmcnt bits [3:0] and [15:14] zero, expcnt [6:4] and lgkmcnt [11:8] at their maximum
+constexpr int kWaitVmcnt0 = 0x0F70;
+#ifndef LBM_BATCH_SCALAR
+#define LBM_BATCH_SCALAR 0
+#endif
 
 // Fields of one lattice read by bulk_node, with A/B chosen per step.
 struct LatView {
@@ -165,14 +171,21 @@ __device__ void reduce_lattice(const BatchArgs& a, int l, const float* part) {
 
 // Grid-wide barrier with a bounded wait.  Returns false (on every thread of
 // the workgroup) if the wait timed out or another workgroup raised the flag.
-// Every thread fences at device scope before arriving and after leaving:
-// the L2 caches of the eight XCDs are not coherent with each other, and the
-// next step reads populations written on other XCDs.
+// The L2 caches of the eight XCDs are not coherent with each other, and the
+// next step reads populations written on other XCDs.  Every wave first waits
+// until its own stores are complete in its XCD's L2 (s_waitcnt vmcnt(0));
+// after the workgroup barrier one thread makes them visible device-wide (a
+// device-scope release: write-back of the L2's dirty lines) before it
+// arrives, and after the last arrival takes a device-scope acquire
+// (invalidation of this CU's L1 and of the XCD's L2), which covers every wave
+// of the workgroup: they share the CU, and none of them loads in between.
+// A release per wave would repeat the L2 write-back once per wave.
 __device__ bool grid_barrier(const BatchArgs& a) {
   __shared__ int ok;
-  __threadfence();
+  __builtin_amdgcn_s_waitcnt(kWaitVmcnt0);
   __syncthreads();
   if (threadIdx.x == 0) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
     BatchCtl* c = a.ctl;
     int good = 1;
     const unsigned g = __hip_atomic_load(&c->gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
@@ -182,7 +195,9 @@ __device__ bool grid_barrier(const BatchArgs& a) {
       __hip_atomic_fetch_add(&c->gen, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
     } else {
       int spins = 0;
-      while (__hip_atomic_load(&c->gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == g) {
+      // relaxed polls: an acquire per poll would invalidate the L2 under the
+      // waves still streaming; the acquire fence below follows the wait
+      while (__hip_atomic_load(&c->gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == g) {
         if (++spins > a.spin_limit ||
             __hip_atomic_load(&c->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
           if (!__hip_atomic_load(&c->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
@@ -197,9 +212,9 @@ __device__ bool grid_barrier(const BatchArgs& a) {
     }
     if (__hip_atomic_load(&c->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) good = 0;
     ok = good;
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
   }
   __syncthreads();
-  __threadfence();
   return ok != 0;
 }
 
@@ -269,7 +284,12 @@ __global__ void __launch_bounds__(kBlock) LBM_BATCH_ATTR k_batch(const BatchArgs
         v.one_minus_rho_out = d->one_minus_rho_out;
         LogHook hook{a.x, a.xa, a.t, d->log_role, d->log_x,
                      slot < 0 ? int64_t(-1) : slot * a.log_rows + d->log_row0};
+#if LBM_BATCH_SCALAR
+        const int x = tx * kChunk + items[4 * it + 3] * 64 + lane;
+        if (x < v.nx) bulk_node<float, MRT>(v, tx, x, y, fx, fy, dm, hook);
+#else
         bulk_row<float, MRT>(v, tx, y, lane, fx, fy, dm, hook);
+#endif
       }
       fx = wave_sum(fx);
       fy = wave_sum(fy);
@@ -336,7 +356,11 @@ BatchLayout batch_layout(const lbm_batch_params& p, const lbm_batch_lattice* lat
     L.buf1.push_back(take(9 * plane * 4));
     L.links.push_back(take(plane * 4));
     L.chunk.push_back(take(size_t(lat[i].ny) * nch));
+#if LBM_BATCH_SCALAR
+    L.nitems += (lat[i].nx + 63) / 64 * lat[i].ny;
+#else
     L.nitems += nch * lat[i].ny;
+#endif
   }
   L.lats = take(sizeof(BatchLat) * size_t(n));
   L.items = take(sizeof(int4) * size_t(L.nitems));
@@ -460,7 +484,13 @@ lbm_status lbm_batch_create(const lbm_batch_params* p, const lbm_batch_lattice* 
     d.one_minus_rho_out = 1.0 - q.rho_out;
     d.item0 = int(items.size());
     for (int y = 0; y < q.ny; ++y)
-      for (int tx = 0; tx < d.nchunk; ++tx) items.push_back(make_int4(i, tx, y, 0));
+      for (int tx = 0; tx < d.nchunk; ++tx)
+#if LBM_BATCH_SCALAR
+        for (int sub = 0; sub < kChunk / 64; ++sub)
+          if (tx * kChunk + sub * 64 < q.nx) items.push_back(make_int4(i, tx, y, sub));
+#else
+        items.push_back(make_int4(i, tx, y, 0));
+#endif
     d.nitems = int(items.size()) - d.item0;
     d.log_role = q.log_role;
     d.log_x = q.log_x;
@@ -547,10 +577,8 @@ lbm_status lbm_batch_create(const lbm_batch_params* p, const lbm_batch_lattice* 
   // than can be resident together, and a grid barrier needs every
   // workgroup resident: keep one per CU in reserve (LBM_BATCH_RESERVE
   // overrides; a grid that is not co-resident ends in the barrier's bounded
-  // wait and an LBM_EHIP).  Within that, kBatchGroupsPerCu workgroups per CU
-  // (LBM_BATCH_GROUPS_PER_CU overrides): more waves stream no faster here,
-  // they contend (measured 0.82 ms per step of the 33M-node data-generation
-  // batch at 2 per CU, 0.88 at 4, 1.01 at 5).
+  // wait and an LBM_EHIP).  Within that, at most kBatchGroupsPerCu
+  // workgroups per CU (LBM_BATCH_GROUPS_PER_CU overrides).
   int reserve = 1, per = kBatchGroupsPerCu;
   if (const char* e = getenv("LBM_BATCH_RESERVE")) reserve = std::max(0, atoi(e));
   if (const char* e = getenv("LBM_BATCH_GROUPS_PER_CU")) per = std::max(1, atoi(e));

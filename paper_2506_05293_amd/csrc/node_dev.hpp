@@ -237,12 +237,14 @@ __device__ __forceinline__ void bulk_row(const P& L, int tx, int y, int lane,
 
   // 3. per node: fix-ups, boundary columns, force, collision
   bool keep[kV];
-  bool all = true;
+  bool vec = true;        // the lane's nodes are all updated here or padding
+  bool any = false;       // the lane holds at least one node updated here
 #pragma unroll
   for (int i = 0; i < kV; ++i) {
     const int x = x0 + i;
     keep[i] = x < L.nx && !(lk[i] & LINK_SOLID) && !((lk[i] & LINK_OUTLET) && L.n_nn);
-    all = all && keep[i];
+    vec = vec && (keep[i] || x >= L.nx);
+    any = any || keep[i];
     if (!keep[i]) continue;
     if (L.xper && x == L.nx - 1) {            // last column wraps to column 0
 #pragma unroll
@@ -268,15 +270,18 @@ __device__ __forceinline__ void bulk_row(const P& L, int tx, int y, int lane,
     collide<T, MRT>(g[i], L);
   }
 
-  // 4. store: one vector store per plane, or per node where some are skipped
+  // 4. store: one vector store per plane where the lane's nodes are all
+  // updated here or padding (columns nx .. pitch-1 are never read as a valid
+  // node's source: the outlet and wrap-around columns replace those pulls),
+  // else per node; a lane of padding only stores nothing
 #pragma unroll
   for (int q = 0; q < 9; ++q) {
     S* Bq = B + int64_t(q) * L.plane + r0 + uint32_t(x0);
     T e[kV];
 #pragma unroll
     for (int i = 0; i < kV; ++i) e[i] = g[i][q];
-    if (all) {
-      VecIO<S>::st(Bq, e);
+    if (vec) {
+      if (any) VecIO<S>::st(Bq, e);
     } else {
 #pragma unroll
       for (int i = 0; i < kV; ++i)

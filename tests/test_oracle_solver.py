@@ -191,8 +191,9 @@ def _taylor_green_nu(n, tau, steps):
 
 
 def test_taylor_green_viscosity():
-    tau = 0.8
-    nu = (tau - 0.5) / 3
+    # the measured decay rate pins tau(nu) as well as the scheme
+    nu = 0.1
+    tau = d2q9.tau_from_viscosity(nu)
     errs = [abs(_taylor_green_nu(n, tau, int(0.5 * n * n / (8 * np.pi**2 * nu) * 4)) / nu - 1)
             for n in (16, 32, 64)]
     assert errs[2] < 5e-3, errs
