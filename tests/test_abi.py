@@ -70,3 +70,15 @@ def test_create_checks_workspace_without_touching_it():
         lbm.lbm_set_outflow_model(ctx, lbm.LBM_OUT_NN, None)
     assert e.value.status == lbm.LBM_EINVAL
     lbm.lbm_destroy(ctx)
+
+
+def test_largest_lattice_is_accepted_and_one_more_column_is_not():
+    # one population plane (pitch x ny, 8-byte elements) must stay below
+    # 4 GiB: 32-bit byte offsets inside a plane
+    ny = 16384
+    nx_max = (1 << 32) // (8 * ny) - 256          # (nx + 255) * ny * 8 < 2^32
+    ok = lbm.lbm_workspace_bytes(_params(nx=nx_max, ny=ny))
+    assert ok > 2 * 9 * nx_max * ny * 4
+    with pytest.raises(lbm.LbmError) as e:
+        lbm.lbm_workspace_bytes(_params(nx=nx_max + 1, ny=ny))
+    assert e.value.status == lbm.LBM_EINVAL
