@@ -14,15 +14,16 @@ One step t -> t+1, in the order the paper's method implies:
   3. the momentum-exchange force of Eq. 14 over every fluid-to-body link,
      F(t) = Delta P / Delta t (Eq. 15), lattice units (Delta x = Delta t = 1);
   4. boundary columns: Zou & He velocity inlet at x = 0; at x = nx-1 the
-     Zou & He pressure outlet or the neural reconstruction of Eq. 16 with a
-     per-node Zou & He fallback.
+     Zou & He pressure outlet, the neural reconstruction of Eq. 16 with a
+     per-node Zou & He fallback, or the characteristic outflow of Sec. 3.2
+     (oracle/cbc.py) from the state of the three last columns at time t.
 
 Geometry mask values: 0 fluid, 1 body (links to it are force-summed),
 2 inert solid (bounce-back only).  Solid nodes are never updated.
 """
 import numpy as np
 
-from . import d2q9
+from . import cbc, d2q9
 from .d2q9 import C, OPP, W
 from .mlp import forward_bf16
 from .splitmix64 import velocity_noise
@@ -48,6 +49,8 @@ class Lattice:
         self.outflow = "zouhe"
         self.mlp = None
         self.mass_bound = 1e-2
+        self.cbc = None
+        self.cbc_prev = np.zeros((self.ny, 3))
         self.t = 0
         self.fx_hist, self.fy_hist, self.mass_hist = [], [], []
         self.n_fallback = 0
@@ -68,6 +71,16 @@ class Lattice:
     def set_outflow_nn(self, P, mass_bound=1e-2):
         """Use the neural reconstruction (Eq. 16) at the outlet column."""
         self.outflow, self.mlp, self.mass_bound = "nn", P, float(mass_bound)
+
+    def set_outflow_cbc(self, sigma=0.0, kappa2=0.0, mach=0.0, length=None, rho_inf=1.0,
+                        net=None):
+        """Use the characteristic outflow of Sec. 3.2 (Eqs. 18-29), with fixed
+        sigma and kappa_2 or, given ``net``, the tuning network."""
+        self.outflow = "cbc"
+        self.cbc = dict(sigma=float(sigma), kappa2=float(kappa2), mach=float(mach),
+                        length=float(self.nx if length is None else length),
+                        rho_inf=float(rho_inf), net=net)
+        self.cbc_prev = np.zeros((self.ny, 3))
 
     def set_outflow_zouhe(self):
         self.outflow, self.mlp = "zouhe", None
@@ -161,6 +174,11 @@ class Lattice:
             fnew[:, :, 0], _ = inlet_velocity(fnew[:, :, 0], ux, 0.0)
             if self.outflow == "nn":
                 fnew[:, :, -1] = self._outlet_nn(fnew)
+            elif self.outflow == "cbc":
+                rho, ux, uy = d2q9.moments(fstar[:, :, -3:])      # state at time t
+                fnew[:, :, -1], self.cbc_prev = cbc.outlet(
+                    fnew[:, :, -1], rho.T, ux.T, uy.T, self.cbc_prev, self.cbc,
+                    self.lateral == "periodic")
             else:
                 fnew[:, :, -1], _ = outlet_pressure(fnew[:, :, -1], self.rho_out)
         return np.where(self.fluid[None], fnew, fstar), F

@@ -20,24 +20,33 @@ import numpy as np
 from .d2q9 import equilibrium
 
 
+def outlet_reconstruct(fcol, rho, u, v):
+    """Right boundary (x = L): the unknowns 3, 6, 7 from Eqs. 8-10 for a
+    prescribed density and velocity (rho, u, v), each a scalar or per node;
+    the known populations are kept (Eq. 11)."""
+    f = np.array(fcol, dtype=np.float64, copy=True)
+    n = f.shape[1]
+    rho, u, v = (np.broadcast_to(np.asarray(a, dtype=np.float64), (n,)) for a in (rho, u, v))
+    feq = equilibrium(rho, u, v)
+    fneq = f - feq
+    f[6] = feq[6] + fneq[8] + 0.5 * (fneq[4] - fneq[2])   # Eq. 8
+    f[3] = feq[3] + fneq[1]                                # Eq. 9
+    f[7] = feq[7] + fneq[5] - 0.5 * (fneq[4] - fneq[2])   # Eq. 10
+    return f
+
+
 def outlet_pressure(fcol, rho_out):
     """Right boundary (x = L), unknowns 3, 6, 7.
 
     ``fcol`` is (9, n): the populations of the boundary nodes after streaming,
     with the unknown entries ignored.  Returns the completed (9, n) array and
     the normal velocity u from Eq. 7 solved for u at the prescribed rho."""
-    f = np.array(fcol, dtype=np.float64, copy=True)
+    f = np.asarray(fcol, dtype=np.float64)
     rho0 = f[0] + f[2] + f[4]
     rhop = f[1] + f[5] + f[8]
     rho = np.full(f.shape[1], float(rho_out))
     u = (rho0 + 2.0 * rhop) / rho - 1.0          # Eq. 7
-    v = np.zeros_like(u)
-    feq = equilibrium(rho, u, v)
-    fneq = f - feq
-    f[6] = feq[6] + fneq[8] + 0.5 * (fneq[4] - fneq[2])   # Eq. 8
-    f[3] = feq[3] + fneq[1]                                # Eq. 9
-    f[7] = feq[7] + fneq[5] - 0.5 * (fneq[4] - fneq[2])   # Eq. 10
-    return f, u
+    return outlet_reconstruct(f, rho, u, 0.0), u
 
 
 def inlet_velocity(fcol, ux, uy=0.0):
