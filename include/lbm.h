@@ -62,7 +62,7 @@ enum { LBM_FP64 = 0, LBM_FP32_OFFSET = 1, LBM_FP16_OFFSET = 2 };
 enum { LBM_BGK = 0, LBM_MRT = 1 };
 enum { LBM_LATERAL_WALLS = 0, LBM_LATERAL_PERIODIC = 1 };
 enum { LBM_X_INOUT = 0, LBM_X_PERIODIC = 1 };
-enum { LBM_OUT_ZOUHE = 0, LBM_OUT_NN = 1 };
+enum { LBM_OUT_ZOUHE = 0, LBM_OUT_NN = 1, LBM_OUT_CBC = 2 };
 
 /*
  * Lattice description.
@@ -185,8 +185,48 @@ lbm_status lbm_force_history(lbm_ctx* c, double* fx, double* fy, int64_t cap,
                              int64_t* n);
 
 /* Select the outflow at x = nx-1: LBM_OUT_ZOUHE (w ignored, may be NULL) or
- * LBM_OUT_NN with the weights *w, which are copied (rounded to BF16). */
+ * LBM_OUT_NN with the weights *w, which are copied (rounded to BF16).  The
+ * characteristic outflow is selected by lbm_set_outflow_cbc. */
 lbm_status lbm_set_outflow_model(lbm_ctx* c, int32_t kind, const lbm_mlp* w);
+
+/* Tuning network of the characteristic outflow (Sec. 3.2): nine features per
+ * outlet node, (p_x, u_x, v_x, p_y, u_y, v_y, p_t, u_t, v_t), the time
+ * derivatives being those the outflow computed at the previous step (zero
+ * before the first), standardised z = (x - mu_in) / sd_in; two hidden layers
+ * of 20 with LeakyReLU (negative slope leaky_slope); two outputs s_0, s_1;
+ * sigma = sigma_scale * sigmoid(s_0) + sigma_shift and
+ * kappa_2 = kappa_scale * sigmoid(s_1) + kappa_shift.  Host FP32 arrays,
+ * row-major [out][in]: w1 [20][9], w2 [20][20], w3 [2][20]; evaluated in the
+ * arithmetic precision of the lattice. */
+typedef struct {
+  const float *w1, *b1, *w2, *b2, *w3, *b3;
+  const float *mu_in, *sd_in;            /* [9] each, sd_in > 0 */
+  double leaky_slope;
+  double sigma_scale, sigma_shift, kappa_scale, kappa_shift;
+} lbm_cbc_net;
+
+/* Characteristic outflow (Sec. 3.2, Eqs. 18-29).  At every step the outlet
+ * node takes the density and velocity of a forward Euler step of the
+ * isothermal LODI equations (Eqs. 18-20) from the state of columns nx-3 ..
+ * nx-1 (one-sided x-derivatives of second order, central y-derivatives,
+ * one-sided on rows next to walls), with the incoming amplitude
+ * L_1 = kappa_1 (p - p_inf) - kappa_2 T_1 + T_1, kappa_1 = sigma (1 - M^2)
+ * c_s / L (Eqs. 27-28; p = rho / 3, p_inf = rho_inf / 3); the unknown
+ * populations then follow from Eqs. 8-10 for that state, after f_0 is
+ * corrected so that the node carries the density exactly (Eq. 29).  With
+ * net == NULL sigma and kappa_2 are the fixed values below, else the network
+ * sets them per node and step (the network is copied).  Needs LBM_X_INOUT
+ * and fluid in the last three columns.  Selecting it clears the stored time
+ * derivatives. */
+typedef struct {
+  double sigma, kappa2;     /* fixed tuning parameters (ignored with net)     */
+  double mach;              /* M in kappa_1, 0 <= M < 1                        */
+  double length;            /* L in kappa_1 (> 0), e.g. the lattice length     */
+  double rho_inf;           /* far-field density (> 0)                        */
+  const lbm_cbc_net* net;   /* NULL: fixed sigma, kappa_2                     */
+} lbm_cbc;
+
+lbm_status lbm_set_outflow_cbc(lbm_ctx* c, const lbm_cbc* p);
 
 /* Synchronise and copy the stored state -- the post-collision populations
  * f*(t) of the last step, as absolute values f_i (not offsets) -- into host

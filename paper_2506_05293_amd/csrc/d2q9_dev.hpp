@@ -184,6 +184,23 @@ __device__ __forceinline__ void zouhe_outlet(T g[9], T one_minus_rho_out) {
   g[7] = g[5] - h - ru * T(1.0 / 6.0);
 }
 
+// Right boundary with a prescribed state (rho, u, v), offset form (drho =
+// rho - 1): f_0 is corrected so that the node carries the density exactly
+// (Eq. 29, g_0 = f_0 + rho (1 + u) - (rho_0 + 2 rho_+)), the unknowns 3, 6, 7
+// follow from Eqs. 8-10 with the transverse velocity.
+template <typename T>
+__device__ __forceinline__ void outlet_state(T g[9], T drho, T u, T v) {
+  const T d0 = g[0] + g[2] + g[4];
+  const T dp = g[1] + g[5] + g[8];
+  g[0] += (drho + u + drho * u) - (d0 + T(2) * dp);
+  const T rho = T(1) + drho;
+  const T ru = rho * u, rv = rho * v;
+  const T h = T(0.5) * (g[4] - g[2]);
+  g[3] = g[1] - ru * T(2.0 / 3.0);
+  g[6] = g[8] + h - ru * T(1.0 / 6.0) + T(0.5) * rv;
+  g[7] = g[5] - h - ru * T(1.0 / 6.0) - T(0.5) * rv;
+}
+
 // ---- SplitMix64, counter form ------------------------------------------------------
 // Output k (k >= 1) of the stream seeded with s is the finaliser applied to
 // s + k * 0x9e3779b97f4a7c15 (Steele, Lea & Flood 2014).

@@ -110,7 +110,7 @@ struct Layout {
   int path;
   int pitch, nchunk, rows, ntx, nty, nn_max, nslots_max;
   int64_t plane;
-  size_t A, B, links, chunk, inlet, part0, part1, lvl0, lvl1, acc, hist, mlp, total;
+  size_t A, B, links, chunk, inlet, part0, part1, lvl0, lvl1, acc, hist, mlp, cbc, cbc_dt, total;
 };
 
 Layout make_layout(const lbm_params& p) {
@@ -143,6 +143,8 @@ Layout make_layout(const lbm_params& p) {
   L.acc = take(sizeof(Acc));
   L.hist = take(size_t(std::max<int64_t>(p.history_cap, 0)) * 3 * 8);
   L.mlp = take(sizeof(MlpDev));
+  L.cbc = take(sizeof(CbcDev));
+  L.cbc_dt = take(size_t(p.ny) * 4 * 8);
   L.total = o;
   return L;
 }
@@ -203,6 +205,8 @@ struct lbm_ctx {
   Acc* acc() { return reinterpret_cast<Acc*>(ws + lay.acc); }
   double* hist() { return reinterpret_cast<double*>(ws + lay.hist); }
   MlpDev* mlp() { return reinterpret_cast<MlpDev*>(ws + lay.mlp); }
+  CbcDev* cbc() { return reinterpret_cast<CbcDev*>(ws + lay.cbc); }
+  double* cbc_dt() { return reinterpret_cast<double*>(ws + lay.cbc_dt); }
   size_t pop_bytes() const { return size_t(9) * size_t(lay.plane) * elem_size(p.precision); }
 
   StepLaunch launch() {
@@ -225,6 +229,9 @@ struct lbm_ctx {
     L.hist = hist();
     L.hist_cap = p.history_cap;
     L.mlp = mlp();
+    L.cbc = cbc();
+    L.cbc_dt = cbc_dt();
+    L.outlet = outflow == LBM_OUT_CBC ? OUTLET_CBC : OUTLET_NN;
     L.nx = p.nx;
     L.ny = p.ny;
     L.pitch = lay.pitch;
@@ -261,6 +268,7 @@ namespace {
 
 lbm_status reset_counters(lbm_ctx* c) {
   HIP_TRY(hipMemsetAsync(c->acc(), 0, sizeof(Acc), c->stream));
+  HIP_TRY(hipMemsetAsync(c->cbc_dt(), 0, size_t(c->p.ny) * 4 * 8, c->stream));
   c->steps = 0;
   c->pend1 = c->pend2 = false;
   c->pcur = 0;
@@ -517,6 +525,51 @@ lbm_status lbm_set_outflow_model(lbm_ctx* c, int32_t kind, const lbm_mlp* w) {
   return LBM_OK;
 }
 
+lbm_status lbm_set_outflow_cbc(lbm_ctx* c, const lbm_cbc* p) {
+  if (!c || !p) return fail(LBM_EINVAL, "NULL argument");
+  if (c->p.xbc != LBM_X_INOUT) return fail(LBM_EINVAL, "characteristic outflow needs LBM_X_INOUT");
+  if (!std::isfinite(p->sigma) || !std::isfinite(p->kappa2) || !(p->mach >= 0 && p->mach < 1) ||
+      !(p->length > 0) || !std::isfinite(p->length) || !(p->rho_inf > 0) || !std::isfinite(p->rho_inf))
+    return fail(LBM_EINVAL, "bad characteristic outflow parameters (sigma %g, kappa2 %g, mach %g, "
+                "length %g, rho_inf %g)", p->sigma, p->kappa2, p->mach, p->length, p->rho_inf);
+  CbcDev h;
+  memset(&h, 0, sizeof h);
+  h.sigma = p->sigma;
+  h.kappa2 = p->kappa2;
+  h.kappa1_coef = (1.0 - p->mach * p->mach) * std::sqrt(1.0 / 3.0) / p->length;
+  h.rho_inf_m1 = p->rho_inf - 1.0;
+  if (const lbm_cbc_net* n = p->net) {
+    if (!n->w1 || !n->b1 || !n->w2 || !n->b2 || !n->w3 || !n->b3 || !n->mu_in || !n->sd_in)
+      return fail(LBM_EINVAL, "a tuning network array is NULL");
+    for (int i = 0; i < kCbcIn; ++i)
+      if (!(n->sd_in[i] > 0)) return fail(LBM_EINVAL, "sd_in[%d] must be > 0", i);
+    if (!std::isfinite(n->leaky_slope) || !std::isfinite(n->sigma_scale) ||
+        !std::isfinite(n->sigma_shift) || !std::isfinite(n->kappa_scale) ||
+        !std::isfinite(n->kappa_shift))
+      return fail(LBM_EINVAL, "bad tuning network output maps");
+    memcpy(h.w1, n->w1, sizeof h.w1);
+    memcpy(h.b1, n->b1, sizeof h.b1);
+    memcpy(h.w2, n->w2, sizeof h.w2);
+    memcpy(h.b2, n->b2, sizeof h.b2);
+    memcpy(h.w3, n->w3, sizeof h.w3);
+    memcpy(h.b3, n->b3, sizeof h.b3);
+    memcpy(h.mu_in, n->mu_in, sizeof h.mu_in);
+    memcpy(h.sd_in, n->sd_in, sizeof h.sd_in);
+    h.leaky = n->leaky_slope;
+    h.sigma_scale = n->sigma_scale;
+    h.sigma_shift = n->sigma_shift;
+    h.kappa_scale = n->kappa_scale;
+    h.kappa_shift = n->kappa_shift;
+    h.has_net = 1;
+  }
+  HIP_TRY(hipMemcpyAsync(c->cbc(), &h, sizeof h, hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(hipMemsetAsync(c->cbc_dt(), 0, size_t(c->p.ny) * 4 * 8, c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  c->outflow = LBM_OUT_CBC;
+  c->n_nn = c->lay.nn_max;
+  return LBM_OK;
+}
+
 lbm_status lbm_mlp_forward(lbm_ctx* c, const float* x, float* s, int64_t n) {
   if (!c || (n > 0 && (!x || !s))) return fail(LBM_EINVAL, "NULL argument");
   if (c->outflow != LBM_OUT_NN) return fail(LBM_ESTATE, "no network set");
@@ -541,6 +594,11 @@ lbm_status lbm_read_populations(lbm_ctx* c, double* host) {
                              hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(hipStreamSynchronize(c->stream));
   }
+  // the staging overwrote the spare buffer: restore it, since its solid nodes
+  // are never rewritten by a step
+  lbm_status st = mirror_state(c);
+  if (st) return st;
+  HIP_TRY(hipStreamSynchronize(c->stream));
   return LBM_OK;
 }
 

@@ -674,6 +674,10 @@ lbm_status lbm_batch_read_populations(lbm_batch* b, int32_t l, double* host) {
                           b->stream));
     BTRY(hipStreamSynchronize(b->stream));
   }
+  // the staging overwrote the spare buffer: restore it (solid nodes are never
+  // rewritten by a step)
+  BTRY(hipMemcpyAsync(d.buf[cur ^ 1], d.buf[cur], spare, hipMemcpyDeviceToDevice, b->stream));
+  BTRY(hipStreamSynchronize(b->stream));
   return LBM_OK;
 }
 

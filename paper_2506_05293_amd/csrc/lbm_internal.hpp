@@ -48,6 +48,25 @@ struct MlpDev {
   float pad[3];
 };
 
+// Device image of the characteristic outflow (Sec. 3.2): fixed sigma,
+// kappa_2, or the 9-20-20-2 tuning network with its output maps.
+constexpr int kCbcIn = 9, kCbcHidden = 20;
+struct CbcDev {
+  float w1[kCbcHidden * kCbcIn], b1[kCbcHidden];
+  float w2[kCbcHidden * kCbcHidden], b2[kCbcHidden];
+  float w3[2 * kCbcHidden], b3[2];
+  float mu_in[kCbcIn], sd_in[kCbcIn];
+  int has_net;
+  int pad;
+  double leaky, sigma_scale, sigma_shift, kappa_scale, kappa_shift;
+  double sigma, kappa2;
+  double kappa1_coef;       // (1 - M^2) c_s / L: kappa_1 = sigma * kappa1_coef
+  double rho_inf_m1;        // rho_inf - 1
+};
+
+// Outflow of the special outlet blocks of the step kernel.
+enum { OUTLET_NN = 1, OUTLET_CBC = 2 };
+
 // Reduction pipeline: step t writes one partial slot per wave (part_w); the
 // kReducers reducer workgroups of step t+1 sum fixed slices of them into
 // level-2 sums (lvl_w); workgroup 0 of step t+2 sums those into the FP64
@@ -69,11 +88,14 @@ struct StepLaunch {
   double* hist;
   int64_t hist_cap;
   const MlpDev* mlp;
+  const CbcDev* cbc;
+  double* cbc_dt;           // [ny][4]: p_t, u_t, v_t of the last step at the outlet
+  int outlet;               // OUTLET_NN or OUTLET_CBC when n_nn > 0
   int nx, ny, pitch, nchunk;
   int64_t plane;
   int rows;             // rows per bulk block
   int ntx, nty;         // bulk tiles
-  int n_nn;             // neural outlet blocks (0 for Zou & He)
+  int n_nn;             // outlet blocks, neural or characteristic (0: Zou & He)
   int nblocks;          // whole grid: 1 + kReducers + n_nn + ntx*nty
   int nslots;           // partial slots written per step (waves of the
                         // neural and bulk workgroups)

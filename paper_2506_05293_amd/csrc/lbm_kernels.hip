@@ -171,9 +171,9 @@ struct alignas(16) NnSmem {
 };
 
 template <typename S, int MRT>
-__device__ void nn_block(const StepLaunch& L, int nb, typename Store<S>::T* part) {
+__device__ void nn_block(const StepLaunch& L, int nb, NnSmem<typename Store<S>::T>& sm,
+                         typename Store<S>::T* part) {
   using T = typename Store<S>::T;
-  __shared__ NnSmem<T> sm;
   const S* __restrict__ A = static_cast<const S*>(L.A);
   S* __restrict__ B = static_cast<S*>(L.B);
   const MlpDev* __restrict__ w = L.mlp;
@@ -264,10 +264,174 @@ __device__ void nn_block(const StepLaunch& L, int nb, typename Store<S>::T* part
   wave_partials(fx, fy, dm, nfb, part);
 }
 
+
+// ---- characteristic outlet block (Sec. 3.2, Eqs. 18-29) ------------------------
+// 64 outlet rows per workgroup.  The state of the time level is the moments of
+// the stored post-collision populations (collision conserves them); columns
+// nx-3 .. nx-1 of rows y0-2 .. y0+65 are staged and reduced to (drho, u, v),
+// then one thread per row takes the gradients (second-order one-sided in x,
+// central in y, one-sided on wall rows), the tuning network if any, the LODI
+// time derivatives with L_1 of Eq. 27, a forward Euler step, and rebuilds the
+// unknown populations for that state before collision.
+constexpr int kCbRows = kNnRows + 4;
+constexpr int kCbCols = 3;
+static_assert(9 * kCbRows * kCbCols + 3 * kCbCols * kCbRows <= 9 * kStRows * kStCols,
+              "characteristic staging must fit the outlet blocks' LDS");
+
+template <typename T>
+__device__ __forceinline__ T sigmoid_t(T s) {
+  if constexpr (sizeof(T) == 8)
+    return T(1) / (T(1) + exp(-s));
+  else
+    return T(1) / (T(1) + expf(-s));
+}
+
+// The tuning network 9 -> 20 -> 20 -> 2 (LeakyReLU), sigmoid and affine maps.
+template <typename T>
+__device__ void cbc_network(const CbcDev* __restrict__ c, const T f[kCbcIn], T& sigma,
+                            T& kappa2) {
+  T z[kCbcIn];
+#pragma unroll
+  for (int i = 0; i < kCbcIn; ++i) z[i] = (f[i] - T(c->mu_in[i])) / T(c->sd_in[i]);
+  const T a = T(c->leaky);
+  // each first-layer unit is folded into the second-layer sums as soon as it
+  // is known, so only those 20 sums stay live
+  T h2[kCbcHidden];
+#pragma unroll
+  for (int o = 0; o < kCbcHidden; ++o) h2[o] = T(c->b2[o]);
+#pragma unroll 1
+  for (int k = 0; k < kCbcHidden; ++k) {
+    T s = T(c->b1[k]);
+#pragma unroll
+    for (int i = 0; i < kCbcIn; ++i) s += T(c->w1[k * kCbcIn + i]) * z[i];
+    const T h1 = s > T(0) ? s : a * s;
+#pragma unroll
+    for (int o = 0; o < kCbcHidden; ++o) h2[o] += T(c->w2[o * kCbcHidden + k]) * h1;
+  }
+  T s0 = T(c->b3[0]), s1 = T(c->b3[1]);
+#pragma unroll
+  for (int i = 0; i < kCbcHidden; ++i) {
+    const T h = h2[i] > T(0) ? h2[i] : a * h2[i];
+    s0 += T(c->w3[i]) * h;
+    s1 += T(c->w3[kCbcHidden + i]) * h;
+  }
+  sigma = T(c->sigma_scale) * sigmoid_t(s0) + T(c->sigma_shift);
+  kappa2 = T(c->kappa_scale) * sigmoid_t(s1) + T(c->kappa_shift);
+}
+
+template <typename S, int MRT>
+__device__ void cbc_block(const StepLaunch& L, int nb, NnSmem<typename Store<S>::T>& sm,
+                          typename Store<S>::T* part) {
+  using T = typename Store<S>::T;
+  constexpr int R = kCbRows, NC = kCbCols;
+  T* st = sm.u.st;                       // [q][R][NC] populations
+  T* mo = sm.u.st + 9 * R * NC;          // [k][NC][R]: drho, u, v
+  const S* __restrict__ A = static_cast<const S*>(L.A);
+  S* __restrict__ B = static_cast<S*>(L.B);
+  const CbcDev* __restrict__ c = L.cbc;
+  const int y0 = nb * kNnRows;
+  const int xs0 = L.nx - NC;
+
+  // 1. stage A[q][y0-2 .. y0+65][nx-3 .. nx-1]
+  for (int i = threadIdx.x; i < 9 * R * NC; i += kBlock) {
+    const int q = i / (R * NC);
+    const int rem = i - q * (R * NC);
+    const int r = rem / NC;
+    const int cc = rem - r * NC;
+    int y = y0 - 2 + r;
+    if (L.yper)
+      y = (y + 2 * L.ny) % L.ny;
+    else
+      y = min(max(y, 0), L.ny - 1);    // rows past a wall are not used as values
+    st[i] = Store<S>::ld(A + int64_t(q) * L.plane + int64_t(y) * L.pitch + xs0 + cc);
+  }
+  __syncthreads();
+  // 2. the state (drho, u, v) of the staged nodes
+  for (int i = threadIdx.x; i < R * NC; i += kBlock) {
+    const int r = i / NC, cc = i - (i / NC) * NC;
+    T g[9];
+#pragma unroll
+    for (int q = 0; q < 9; ++q) g[q] = st[(q * R + r) * NC + cc];
+    const Macro<T> m = macro(g);
+    mo[(0 * NC + cc) * R + r] = m.drho;
+    mo[(1 * NC + cc) * R + r] = m.jx / m.rho;
+    mo[(2 * NC + cc) * R + r] = m.jy / m.rho;
+  }
+  __syncthreads();
+
+  T fx = T(0), fy = T(0), dm = T(0);
+  const int j = threadIdx.x;
+  const int y = y0 + j;
+  const int x = L.nx - 1;
+  if (j < kNnRows && y < L.ny) {
+    const uint32_t lk = L.links[int64_t(y) * L.pitch + x];
+    if (!(lk & LINK_SOLID)) {
+      const int r = j + 2;
+      T gx[3], gy[3];
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        const T* m2 = mo + (k * NC + 2) * R;
+        gx[k] = T(0.5) * (T(3) * m2[r] - T(4) * mo[(k * NC + 1) * R + r] + mo[(k * NC) * R + r]);
+        if (L.yper || (y > 0 && y < L.ny - 1))
+          gy[k] = T(0.5) * (m2[r + 1] - m2[r - 1]);
+        else if (y == 0)
+          gy[k] = T(0.5) * (T(-3) * m2[r] + T(4) * m2[r + 1] - m2[r + 2]);
+        else
+          gy[k] = T(0.5) * (T(3) * m2[r] - T(4) * m2[r - 1] + m2[r - 2]);
+      }
+      const T cs2 = T(1.0 / 3.0), cs = T(0.57735026918962576451);
+      const T p_x = cs2 * gx[0], u_x = gx[1], v_x = gx[2];
+      const T p_y = cs2 * gy[0], u_y = gy[1], v_y = gy[2];
+      const T drho = mo[(0 * NC + 2) * R + r], u = mo[(1 * NC + 2) * R + r];
+      const T v = mo[(2 * NC + 2) * R + r];
+      const T rho = T(1) + drho, p = cs2 * rho;
+      double* dts = L.cbc_dt + 4 * int64_t(y);
+      T sigma = T(c->sigma), kappa2 = T(c->kappa2);
+      if (c->has_net) {
+        const T f[kCbcIn] = {p_x, u_x, v_x, p_y, u_y, v_y, T(dts[0]), T(dts[1]), T(dts[2])};
+        cbc_network(c, f, sigma, kappa2);
+      }
+      // Eqs. 21-26 (readings: dp/dx in L_1, L_5; du/dy in T_1, T_5)
+      const T L3 = u * v_x;
+      const T L5 = (u + cs) * (p_x + rho * cs * u_x);
+      const T T1 = -(v * p_y + p * v_y - rho * cs * v * u_y);
+      const T T3 = -(v * v_y + p_y / rho);
+      const T T5 = -(v * p_y + p * v_y + rho * cs * v * u_y);
+      // Eqs. 27-28 with T_1,exact = 0
+      const T L1 = sigma * T(c->kappa1_coef) * cs2 * (drho - T(c->rho_inf_m1)) - kappa2 * T1 + T1;
+      // Eqs. 18-20
+      const T rho_t = (-(L5 + L1) + (T5 + T1)) / (T(2) * cs2);
+      const T u_t = (-(L5 - L1) + (T5 - T1)) / (T(2) * rho * cs);
+      const T v_t = -L3 + T3;
+      dts[0] = double(cs2 * rho_t);
+      dts[1] = double(u_t);
+      dts[2] = double(v_t);
+      // post-streaming populations of the outlet node
+      T g[9];
+#pragma unroll
+      for (int q = 0; q < 9; ++q) {
+        const bool bb = (lk >> q) & 1u;
+        const int cc = bb ? 2 : min(2 - cx(q), 2);      // unknowns: replaced below
+        const int rr = bb ? r : r - cy(q);
+        g[q] = st[((bb ? opp(q) : q) * R + rr) * NC + cc];
+      }
+      outlet_state(g, drho + rho_t, u + u_t, v + v_t);   // forward Euler, Eq. 29, Eqs. 8-10
+      add_force(lk, g, fx, fy);
+      dm = macro(g).drho;
+      collide<T, MRT>(g, L);
+      const int64_t row = int64_t(y) * L.pitch + x;
+#pragma unroll
+      for (int q = 0; q < 9; ++q) Store<S>::st(B + int64_t(q) * L.plane + row, g[q]);
+    }
+  }
+  wave_partials(fx, fy, dm, T(0), part);
+}
+
 // ---- the step kernel --------------------------------------------------------------
-// NN selects the variant with neural outlet blocks; the Zou & He variant
-// carries none of their registers or LDS.
-template <typename S, int MRT, bool NN, int PATH>
+// OUT selects the outlet: 0 Zou & He in the bulk node code, OUTLET_NN or
+// OUTLET_CBC in dedicated outlet blocks; each variant carries only its own
+// registers and LDS.
+template <typename S, int MRT, int OUT, int PATH>
 __global__ void __launch_bounds__(kBlock) LBM_STEP_ATTR k_step(const StepLaunch L) {
   using T = typename Store<S>::T;
   constexpr int kFirst = 1 + kReducers;          // first workgroup with slots
@@ -281,9 +445,13 @@ __global__ void __launch_bounds__(kBlock) LBM_STEP_ATTR k_step(const StepLaunch 
     return;
   }
   T* part = static_cast<T*>(L.part_w) + kPartials * kWaves * (v - kFirst);
-  if constexpr (NN) {
+  if constexpr (OUT != 0) {
     if (v < kFirst + L.n_nn) {
-      nn_block<S, MRT>(L, v - kFirst, part);
+      __shared__ NnSmem<T> sm;
+      if constexpr (OUT == OUTLET_CBC)
+        cbc_block<S, MRT>(L, v - kFirst, sm, part);
+      else
+        nn_block<S, MRT>(L, v - kFirst, sm, part);
       return;
     }
   }
@@ -303,20 +471,22 @@ __global__ void __launch_bounds__(kBlock) k_finalize(const StepLaunch L) {
   }
 }
 
-template <typename S, int MRT, bool NN>
+template <typename S, int MRT, int OUT>
 static void launch_path(const StepLaunch& L, hipStream_t s) {
   if (L.path == PATH_VECTOR)
-    hipLaunchKernelGGL((k_step<S, MRT, NN, PATH_VECTOR>), dim3(L.nblocks), dim3(kBlock), 0, s, L);
+    hipLaunchKernelGGL((k_step<S, MRT, OUT, PATH_VECTOR>), dim3(L.nblocks), dim3(kBlock), 0, s, L);
   else
-    hipLaunchKernelGGL((k_step<S, MRT, NN, PATH_SCALAR>), dim3(L.nblocks), dim3(kBlock), 0, s, L);
+    hipLaunchKernelGGL((k_step<S, MRT, OUT, PATH_SCALAR>), dim3(L.nblocks), dim3(kBlock), 0, s, L);
 }
 
 template <typename S, int MRT>
 static hipError_t launch_step_t(const StepLaunch& L, hipStream_t s) {
-  if (L.n_nn)
-    launch_path<S, MRT, true>(L, s);
+  if (!L.n_nn)
+    launch_path<S, MRT, 0>(L, s);
+  else if (L.outlet == OUTLET_CBC)
+    launch_path<S, MRT, OUTLET_CBC>(L, s);
   else
-    launch_path<S, MRT, false>(L, s);
+    launch_path<S, MRT, OUTLET_NN>(L, s);
   return hipGetLastError();
 }
 

@@ -19,7 +19,7 @@ LBM_FP64, LBM_FP32_OFFSET, LBM_FP16_OFFSET = 0, 1, 2
 LBM_BGK, LBM_MRT = 0, 1
 LBM_LATERAL_WALLS, LBM_LATERAL_PERIODIC = 0, 1
 LBM_X_INOUT, LBM_X_PERIODIC = 0, 1
-LBM_OUT_ZOUHE, LBM_OUT_NN = 0, 1
+LBM_OUT_ZOUHE, LBM_OUT_NN, LBM_OUT_CBC = 0, 1, 2
 
 
 class lbm_params(ctypes.Structure):
@@ -50,6 +50,19 @@ class lbm_mlp(ctypes.Structure):
                 ("w1", _FP), ("b1", _FP), ("w2", _FP), ("b2", _FP), ("w3", _FP), ("b3", _FP),
                 ("mu_in", _FP), ("sd_in", _FP), ("mu_out", _FP), ("sd_out", _FP),
                 ("mass_bound", ctypes.c_double)]
+
+
+class lbm_cbc_net(ctypes.Structure):
+    _fields_ = [("w1", _FP), ("b1", _FP), ("w2", _FP), ("b2", _FP), ("w3", _FP), ("b3", _FP),
+                ("mu_in", _FP), ("sd_in", _FP), ("leaky_slope", ctypes.c_double),
+                ("sigma_scale", ctypes.c_double), ("sigma_shift", ctypes.c_double),
+                ("kappa_scale", ctypes.c_double), ("kappa_shift", ctypes.c_double)]
+
+
+class lbm_cbc(ctypes.Structure):
+    _fields_ = [("sigma", ctypes.c_double), ("kappa2", ctypes.c_double),
+                ("mach", ctypes.c_double), ("length", ctypes.c_double),
+                ("rho_inf", ctypes.c_double), ("net", ctypes.POINTER(lbm_cbc_net))]
 
 
 class lbm_train_params(ctypes.Structure):
@@ -113,6 +126,7 @@ def library():
             "lbm_forces": (I32, [VP, P(lbm_force_out)]),
             "lbm_force_history": (I32, [VP, DP, DP, I64, P(I64)]),
             "lbm_set_outflow_model": (I32, [VP, I32, P(lbm_mlp)]),
+            "lbm_set_outflow_cbc": (I32, [VP, P(lbm_cbc)]),
             "lbm_read_populations": (I32, [VP, DP]),
             "lbm_write_populations": (I32, [VP, DP]),
             "lbm_sync": (I32, [VP]),
@@ -241,6 +255,24 @@ def lbm_set_outflow_model(ctx, kind, P=None, mass_bound=1e-2):
     st = library().lbm_set_outflow_model(ctx, kind, ctypes.byref(s))
     del keep
     return _check(st, "lbm_set_outflow_model")
+
+
+def lbm_set_outflow_cbc(ctx, sigma=0.0, kappa2=0.0, mach=0.0, length=1.0, rho_inf=1.0,
+                        net=None):
+    keep = None
+    p = lbm_cbc(sigma, kappa2, mach, length, rho_inf, None)
+    if net is not None:
+        keep = {k: np.ascontiguousarray(net[k], dtype=np.float32).reshape(-1)
+                for k in ("w1", "b1", "w2", "b2", "w3", "b3", "mu_in", "sd_in")}
+        n = lbm_cbc_net(*[keep[k].ctypes.data_as(_FP) for k in
+                          ("w1", "b1", "w2", "b2", "w3", "b3", "mu_in", "sd_in")],
+                        float(net.get("leaky_slope", 0.01)), float(net["sigma_scale"]),
+                        float(net["sigma_shift"]), float(net["kappa_scale"]),
+                        float(net["kappa_shift"]))
+        p.net = ctypes.pointer(n)
+    st = library().lbm_set_outflow_cbc(ctx, ctypes.byref(p))
+    del keep
+    return _check(st, "lbm_set_outflow_cbc")
 
 
 def lbm_read_populations(ctx, nx, ny):
@@ -583,6 +615,12 @@ class Lattice:
 
     def set_outflow_zouhe(self):
         lbm_set_outflow_model(self.ctx, LBM_OUT_ZOUHE)
+
+    def set_outflow_cbc(self, sigma=0.0, kappa2=0.0, mach=0.0, length=None, rho_inf=1.0,
+                        net=None):
+        """Characteristic outflow (lbm_set_outflow_cbc); length defaults to nx."""
+        lbm_set_outflow_cbc(self.ctx, sigma, kappa2, mach,
+                            float(self.nx if length is None else length), rho_inf, net)
 
     def macroscopic(self):
         f = self.populations()

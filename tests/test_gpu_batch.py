@@ -118,3 +118,17 @@ def test_barrier_wait_bound_is_reported():
     with pytest.raises(lbm.LbmError) as e:
         b.forces(0)
     assert e.value.status == lbm.LBM_EHIP
+
+
+def test_batch_solid_nodes_survive_read_out():
+    lats = _lattices()
+    _say("batch solid nodes after read-out")
+    b = lbm.Batch(lats, collision="mrt", lateral="periodic", noise_amp=1e-3)
+    f0 = [b.populations(i) for i in range(len(lats))]
+    for _ in range(3):
+        b.step(1)
+        for i, L in enumerate(lats):
+            f = b.populations(i)
+            solid = L["mask"] != 0
+            np.testing.assert_array_equal(f[:, solid], f0[i][:, solid])
+            assert np.isfinite(f).all()

@@ -218,3 +218,18 @@ def test_full_size_c2_one_step_against_oracle(bulk_path):
     assert err < 5e-8, err
     out = g.forces()
     assert abs(out.fx - F[0]) < 1e-5 * abs(F[0]) + 1e-9 and out.step == 51
+
+
+def test_solid_nodes_survive_read_out(bulk_path):
+    # a read-out stages through the spare population buffer; the next step
+    # must still find the solid nodes' initial equilibrium there
+    case = cases.ragged("mrt", "walls")
+    _say("solid nodes after read-out", bulk_path)
+    g = _gpu(case, "fp32")
+    f0 = g.populations()
+    solid = case["mask"] != 0
+    for _ in range(3):
+        g.step(1)
+        f = g.populations()
+        np.testing.assert_array_equal(f[:, solid], f0[:, solid])
+        assert np.isfinite(f).all()
