@@ -221,6 +221,14 @@ def run_studies(which, scale, nn_switch=0):
     from paper_2506_05293_amd import experiments
     os.makedirs(RESULTS, exist_ok=True)
     n = lambda k: max(1, int(k * scale))
+    if which in ("vortex", "all"):
+        res = experiments.vortex_study(steps=max(10, n(600) // 10 * 10), progress=_progress)
+        with open(os.path.join(RESULTS, "vortex_study.json"), "w") as f:
+            json.dump(_jsonable(res), f, indent=1)
+        print(json.dumps({"vortex": {k: {a: r[a] for a in ("max", "final", "mean", "finite")}
+                                     for k, r in res["runs"].items()}}), flush=True)
+        if which == "vortex":
+            return
     nets = None if which in ("train", "all") else load_networks()
     if nets is None:
         nets = train_study(scale)
@@ -250,10 +258,11 @@ def main():
     ap.add_argument("--precision", default="fp32", choices=list(BYTES_PER_NODE))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-nn", action="store_true")
+    ap.add_argument("--no-cbc", action="store_true")
     ap.add_argument("--no-accuracy", action="store_true",
                     help="skip the FP32-vs-FP64 precision study (C_D, C_L, St)")
     ap.add_argument("--accuracy-steps", type=int, default=50_000)
-    ap.add_argument("--study", choices=["train", "nn", "naca", "all"], default=None,
+    ap.add_argument("--study", choices=["train", "nn", "naca", "vortex", "all"], default=None,
                     help="also run the truncated-domain outflow study (training data, "
                          "training, neural vs Zou-He outflow) and/or the NACA0012 study; "
                          "results go to results/<study>.json")
@@ -297,6 +306,23 @@ def main():
               "ratio_to_zouhe": ms / ms_nn, "weights": "random-init 27-64-64-3",
               "fallback_nodes": int(out_nn.n_fallback)}
     del lat
+    cbc = None
+    if not args.no_cbc:
+        # the characteristic outflow takes periodic laterals: the same lattice
+        # with periodic laterals, Zou & He then characteristic outlet
+        cs = 3 ** -0.5
+        lat = lbm.Lattice(mask, tau, precision=args.precision, collision="mrt",
+                          lateral="periodic", u_in=0.05, noise_amp=1e-4, seed=2,
+                          s_e=1.0, s_eps=1.0, s_q=1.0)
+        ms_zh = time_steps(lat, args.steps, args.warmup, torch)
+        lat.set_outflow_cbc(sigma=0.25, kappa2=0.05 / cs, mach=0.05 / cs)
+        ms_cbc = time_steps(lat, args.steps, args.warmup, torch)
+        assert lat.forces().nonfinite == 0
+        cbc = {"mlups": nodes / (ms_cbc * 1e-3) / 1e6, "ms_per_step": ms_cbc,
+               "ratio_to_zouhe": ms_zh / ms_cbc, "zouhe_mlups": nodes / (ms_zh * 1e-3) / 1e6,
+               "setting": "same lattice with periodic laterals; characteristic outflow, "
+                          "sigma 0.25, kappa_2 = Ma"}
+        del lat
     torch.cuda.synchronize()
 
     accuracy = None
@@ -326,6 +352,7 @@ def main():
                      "bytes_per_node": bpn, "kernel": "k_step (fused pull stream-collide)"},
         "hbm_fraction": gbs / HBM_PEAK_GBS,
         "nn_outflow": nn,
+        "cbc_outflow": cbc,
         "accuracy": accuracy,
         "cpu_baseline": None if args.no_cpu_baseline else cpu_baseline(nx, ny),
     }

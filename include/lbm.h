@@ -208,16 +208,17 @@ typedef struct {
 /* Characteristic outflow (Sec. 3.2, Eqs. 18-29).  At every step the outlet
  * node takes the density and velocity of a forward Euler step of the
  * isothermal LODI equations (Eqs. 18-20) from the state of columns nx-3 ..
- * nx-1 (one-sided x-derivatives of second order, central y-derivatives,
- * one-sided on rows next to walls), with the incoming amplitude
+ * nx-1 (one-sided x-derivatives of second order, central y-derivatives),
+ * with the incoming amplitude
  * L_1 = kappa_1 (p - p_inf) - kappa_2 T_1 + T_1, kappa_1 = sigma (1 - M^2)
  * c_s / L (Eqs. 27-28; p = rho / 3, p_inf = rho_inf / 3); the unknown
  * populations then follow from Eqs. 8-10 for that state, after f_0 is
  * corrected so that the node carries the density exactly (Eq. 29).  With
  * net == NULL sigma and kappa_2 are the fixed values below, else the network
- * sets them per node and step (the network is copied).  Needs LBM_X_INOUT
- * and fluid in the last three columns.  Selecting it clears the stored time
- * derivatives. */
+ * sets them per node and step (the network is copied).  Needs LBM_X_INOUT,
+ * LBM_LATERAL_PERIODIC (the section defines no treatment of the corners
+ * where the outlet meets a wall; EINVAL otherwise) and fluid in the last
+ * three columns.  Selecting it clears the stored time derivatives. */
 typedef struct {
   double sigma, kappa2;     /* fixed tuning parameters (ignored with net)     */
   double mach;              /* M in kappa_1, 0 <= M < 1                        */

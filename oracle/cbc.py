@@ -27,9 +27,11 @@ Readings (the section is terse or garbled in places):
   * M in Eq. 28 is the reference Mach number, L the domain length; p_inf =
     c_s^2 rho_inf;
   * derivatives at the outlet node: second-order one-sided in x,
-    (3 phi_L - 4 phi_{L-1} + phi_{L-2}) / 2; central in y, wrapped for
-    periodic laterals, second-order one-sided on the first and last rows
-    between walls; every field is the state of the current time level (the
+    (3 phi_L - 4 phi_{L-1} + phi_{L-2}) / 2; central in y with periodic
+    laterals, the only lateral condition the section uses (the solver
+    rejects walls: the inviscid update has no consistent treatment of the
+    corner where the outlet meets a no-slip wall, and the wall-row velocity
+    drifts there); every field is the state of the current time level (the
     moments of the stored populations, which collision conserves);
   * Eq. 29 is meant to make the reconstructed node carry the prescribed
     density; the printed form does so only up to a factor (1 + u) on the

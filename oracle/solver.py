@@ -75,7 +75,11 @@ class Lattice:
     def set_outflow_cbc(self, sigma=0.0, kappa2=0.0, mach=0.0, length=None, rho_inf=1.0,
                         net=None):
         """Use the characteristic outflow of Sec. 3.2 (Eqs. 18-29), with fixed
-        sigma and kappa_2 or, given ``net``, the tuning network."""
+        sigma and kappa_2 or, given ``net``, the tuning network.  Periodic
+        laterals only: the section gives no treatment of the corners where
+        the outlet meets a no-slip wall."""
+        if self.lateral != "periodic":
+            raise ValueError("the characteristic outflow needs periodic laterals")
         self.outflow = "cbc"
         self.cbc = dict(sigma=float(sigma), kappa2=float(kappa2), mach=float(mach),
                         length=float(self.nx if length is None else length),

@@ -528,6 +528,9 @@ lbm_status lbm_set_outflow_model(lbm_ctx* c, int32_t kind, const lbm_mlp* w) {
 lbm_status lbm_set_outflow_cbc(lbm_ctx* c, const lbm_cbc* p) {
   if (!c || !p) return fail(LBM_EINVAL, "NULL argument");
   if (c->p.xbc != LBM_X_INOUT) return fail(LBM_EINVAL, "characteristic outflow needs LBM_X_INOUT");
+  if (c->p.lateral != LBM_LATERAL_PERIODIC)
+    return fail(LBM_EINVAL, "characteristic outflow needs periodic laterals (no corner treatment "
+                "where the outlet meets a wall)");
   if (!std::isfinite(p->sigma) || !std::isfinite(p->kappa2) || !(p->mach >= 0 && p->mach < 1) ||
       !(p->length > 0) || !std::isfinite(p->length) || !(p->rho_inf > 0) || !std::isfinite(p->rho_inf))
     return fail(LBM_EINVAL, "bad characteristic outflow parameters (sigma %g, kappa2 %g, mach %g, "

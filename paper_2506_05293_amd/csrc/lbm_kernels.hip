@@ -270,9 +270,10 @@ __device__ void nn_block(const StepLaunch& L, int nb, NnSmem<typename Store<S>::
 // the stored post-collision populations (collision conserves them); columns
 // nx-3 .. nx-1 of rows y0-2 .. y0+65 are staged and reduced to (drho, u, v),
 // then one thread per row takes the gradients (second-order one-sided in x,
-// central in y, one-sided on wall rows), the tuning network if any, the LODI
+// central in y), the tuning network if any, the LODI
 // time derivatives with L_1 of Eq. 27, a forward Euler step, and rebuilds the
-// unknown populations for that state before collision.
+// unknown populations for that state before collision.  Lateral boundaries
+// are periodic (the library rejects walls for this outflow).
 constexpr int kCbRows = kNnRows + 4;
 constexpr int kCbCols = 3;
 static_assert(9 * kCbRows * kCbCols + 3 * kCbCols * kCbRows <= 9 * kStRows * kStCols,
@@ -338,11 +339,7 @@ __device__ void cbc_block(const StepLaunch& L, int nb, NnSmem<typename Store<S>:
     const int rem = i - q * (R * NC);
     const int r = rem / NC;
     const int cc = rem - r * NC;
-    int y = y0 - 2 + r;
-    if (L.yper)
-      y = (y + 2 * L.ny) % L.ny;
-    else
-      y = min(max(y, 0), L.ny - 1);    // rows past a wall are not used as values
+    const int y = (y0 - 2 + r + 2 * L.ny) % L.ny;
     st[i] = Store<S>::ld(A + int64_t(q) * L.plane + int64_t(y) * L.pitch + xs0 + cc);
   }
   __syncthreads();
@@ -372,12 +369,7 @@ __device__ void cbc_block(const StepLaunch& L, int nb, NnSmem<typename Store<S>:
       for (int k = 0; k < 3; ++k) {
         const T* m2 = mo + (k * NC + 2) * R;
         gx[k] = T(0.5) * (T(3) * m2[r] - T(4) * mo[(k * NC + 1) * R + r] + mo[(k * NC) * R + r]);
-        if (L.yper || (y > 0 && y < L.ny - 1))
-          gy[k] = T(0.5) * (m2[r + 1] - m2[r - 1]);
-        else if (y == 0)
-          gy[k] = T(0.5) * (T(-3) * m2[r] + T(4) * m2[r + 1] - m2[r + 2]);
-        else
-          gy[k] = T(0.5) * (T(3) * m2[r] - T(4) * m2[r - 1] + m2[r - 2]);
+        gy[k] = T(0.5) * (m2[r + 1] - m2[r - 1]);         // periodic rows (staged wrapped)
       }
       const T cs2 = T(1.0 / 3.0), cs = T(0.57735026918962576451);
       const T p_x = cs2 * gx[0], u_x = gx[1], v_x = gx[2];

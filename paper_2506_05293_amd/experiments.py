@@ -255,3 +255,46 @@ def naca_study(networks, aoas=(0.0, 4.0, 8.0), steps=200_000, precision="fp32", 
                          if "cd_mean" in r and "cd_mean" in ref else None)
         out[a] = {"reference": ref, **runs, "rel_err": rel}
     return out
+
+
+def vortex_study(steps=600, every=10, nx=200, ny=400, reference_nx=1000, precision="fp32",
+                 settings=None, progress=_noop):
+    """Convected vortex (Sec. 3.2): RMS density error over the truncated
+    lattice against the same flow on a lattice reference_nx long, every
+    `every` steps, for the Zou & He pressure outlet and characteristic
+    outlets with fixed (sigma, kappa_2)."""
+    ref_case = workloads.convected_vortex(nx=reference_nx, ny=ny)
+    ma, u0 = ref_case["ma"], ref_case["u0"]
+    if settings is None:
+        settings = {"cbc_s0_k0": (0.0, 0.0), "cbc_s0_kMa": (0.0, ma), "cbc_s0.25_kMa": (0.25, ma),
+                    "cbc_s1_kMa": (1.0, ma), "cbc_s0.25_k0": (0.25, 0.0)}
+
+    def run(case, outflow):
+        lat = lbm.Lattice(case["mask"], case["tau"], precision=precision, collision="bgk",
+                          lateral="periodic", u_in=u0, noise_amp=0.0)
+        lat.init_fields(case["rho"], case["ux"], case["uy"])
+        if outflow is not None:
+            lat.set_outflow_cbc(sigma=outflow[0], kappa2=outflow[1], mach=ma, length=nx)
+        rhos = []
+        t0 = time.perf_counter()
+        for k in range(steps // every):
+            lat.step(every)
+            f = lat.populations()
+            rhos.append(f[:, :, :nx].sum(axis=0))
+        wall = time.perf_counter() - t0
+        ok = lat.forces(allow_unstable=True).nonfinite == 0
+        del lat
+        return np.array(rhos), ok, wall
+
+    ref, _, _ = run(ref_case, None)
+    progress(f"vortex reference {reference_nx}", {})
+    case = workloads.convected_vortex(nx=nx, ny=ny)
+    out = {"t": list(range(every, steps + 1, every)), "ma": ma, "tau": case["tau"], "runs": {}}
+    for name, par in [("zouhe", None)] + list(settings.items()):
+        rho, ok, wall = run(case, par)
+        err = np.sqrt(np.mean((rho - ref) ** 2, axis=(1, 2)))
+        out["runs"][name] = {"rms_density_error": err.tolist(), "finite": bool(ok),
+                             "max": float(np.max(err)), "final": float(err[-1]),
+                             "mean": float(np.mean(err))}
+        progress(f"vortex {name}", {})
+    return out

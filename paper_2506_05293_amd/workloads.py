@@ -73,3 +73,24 @@ def naca_case(aoa_deg, chord=256, nx=3072, ny=1024, after_te_chords=3.0, re=1000
     nx = int(math.ceil(px + 0.75 * chord + after_te_chords * chord)) + 1
     mask = geometry.naca0012(nx, ny, chord, aoa_deg, (px, ny / 2.0))
     return dict(mask=mask, tau=tau_for(re, chord), chord=chord, re=re, nx=nx, aoa=aoa_deg)
+
+
+def convected_vortex(nx=200, ny=400, ma=0.3, rc=20.0, beta=0.5, x0=150.0, re=750.0,
+                     length=200.0):
+    """Lamb-Oseen vortex in a uniform stream u0 = Ma c_s (Sec. 3.2): centre
+    (x0, ny/2), core radius rc, strength beta; density from the isothermal
+    radial pressure balance, rho = exp(-(beta u0)^2 / (2 c_s^2) e^{-r^2/rc^2});
+    Re = u0 * length / nu.  Returns the mask, tau, the initial fields and u0.
+    The reference lattice is the same with a larger nx."""
+    cs2 = 1.0 / 3.0
+    u0 = ma * math.sqrt(cs2)
+    y, x = np.mgrid[0:ny, 0:nx].astype(np.float64)
+    y0 = ny / 2.0
+    r2 = (x - x0) ** 2 + (y - y0) ** 2
+    e = np.exp(-r2 / (2.0 * rc * rc))
+    ux = u0 - beta * u0 * (y - y0) / rc * e
+    uy = beta * u0 * (x - x0) / rc * e
+    rho = np.exp(-(beta * u0) ** 2 / (2.0 * cs2) * np.exp(-r2 / (rc * rc)))
+    nu = u0 * length / re
+    return dict(mask=np.zeros((ny, nx), np.uint8), tau=3.0 * nu + 0.5, rho=rho, ux=ux, uy=uy,
+                u0=u0, ma=ma, nx=nx, ny=ny)

@@ -82,3 +82,23 @@ def test_largest_lattice_is_accepted_and_one_more_column_is_not():
     with pytest.raises(lbm.LbmError) as e:
         lbm.lbm_workspace_bytes(_params(nx=nx_max + 1, ny=ny))
     assert e.value.status == lbm.LBM_EINVAL
+
+
+def test_characteristic_outflow_needs_periodic_laterals():
+    # validation happens before the workspace is touched
+    p = _params(lateral=lbm.LBM_LATERAL_WALLS)
+    need = lbm.lbm_workspace_bytes(p)
+    ctx = lbm.lbm_create(p, 1 << 20, need)
+    with pytest.raises(lbm.LbmError) as e:
+        lbm.lbm_set_outflow_cbc(ctx, sigma=0.2, kappa2=0.1, mach=0.1, length=200.0)
+    assert e.value.status == lbm.LBM_EINVAL
+    p = _params(lateral=lbm.LBM_LATERAL_PERIODIC)
+    ctx2 = lbm.lbm_create(p, 1 << 20, need)
+    for bad in (dict(mach=1.0), dict(length=0.0), dict(rho_inf=0.0), dict(sigma=float("nan"))):
+        kw = dict(sigma=0.2, kappa2=0.1, mach=0.1, length=200.0, rho_inf=1.0)
+        kw.update(bad)
+        with pytest.raises(lbm.LbmError) as e:
+            lbm.lbm_set_outflow_cbc(ctx2, **kw)
+        assert e.value.status == lbm.LBM_EINVAL
+    lbm.lbm_destroy(ctx)
+    lbm.lbm_destroy(ctx2)

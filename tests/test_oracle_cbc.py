@@ -184,3 +184,9 @@ def test_network_features_are_gradients_and_previous_time_derivatives():
     np.testing.assert_allclose(seen[1][:, :6], np.stack(g, axis=1), rtol=1e-12, atol=1e-18)
     np.testing.assert_array_equal(seen[1][:, 6:], prev)
     np.testing.assert_array_equal(seen[0][:, 6:], 0.0)
+
+
+def test_walls_are_rejected():
+    lat = Lattice(np.zeros((10, 30), np.uint8), 0.6, lateral="walls", u_in=0.05)
+    with pytest.raises(ValueError):
+        lat.set_outflow_cbc(sigma=0.2, kappa2=0.1, mach=0.1, length=30)
