@@ -202,6 +202,10 @@ def train_study(scale):
     return nets
 
 
+def _suffix(mass_bound):
+    return "" if mass_bound == 1e-2 else f"_bound{mass_bound:g}"
+
+
 def load_networks():
     from paper_2506_05293_amd import experiments
     nets = {}
@@ -214,7 +218,7 @@ def load_networks():
     return nets
 
 
-def run_studies(which, scale, nn_switch=0):
+def run_studies(which, scale, nn_switch=0, mass_bound=1e-2):
     """train: training data and training.  nn: truncated-domain outflow study.
     naca: NACA0012 study.  all: the three in turn.  nn and naca reuse the
     networks in results/ when they exist (else they train first)."""
@@ -234,18 +238,20 @@ def run_studies(which, scale, nn_switch=0):
         nets = train_study(scale)
     if which in ("nn", "all"):
         res = experiments.outflow_study(nets, steps=n(150_000), progress=_progress,
-                                        nn_switch=n(nn_switch))
-        with open(os.path.join(RESULTS, "outflow_study.json"), "w") as f:
+                                        nn_switch=n(nn_switch), mass_bound=mass_bound)
+        res = {"mass_bound": mass_bound, **res}
+        with open(os.path.join(RESULTS, f"outflow_study{_suffix(mass_bound)}.json"), "w") as f:
             json.dump(_jsonable(res), f, indent=1)
-        print(json.dumps({"outflow_rel_err": _jsonable({re: r["rel_err"] for re, r in res.items()})}),
-              flush=True)
+        print(json.dumps({"outflow_rel_err": _jsonable({re: r["rel_err"] for re, r in res.items()
+                                                         if re != "mass_bound"})}), flush=True)
     if which in ("naca", "all"):
         res = experiments.naca_study(nets, steps=n(200_000), progress=_progress,
-                                     nn_switch=n(nn_switch))
-        with open(os.path.join(RESULTS, "naca_study.json"), "w") as f:
+                                     nn_switch=n(nn_switch), mass_bound=mass_bound)
+        res = {"mass_bound": mass_bound, **res}
+        with open(os.path.join(RESULTS, f"naca_study{_suffix(mass_bound)}.json"), "w") as f:
             json.dump(_jsonable(res), f, indent=1)
-        print(json.dumps({"naca_rel_err": _jsonable({a: r["rel_err"] for a, r in res.items()})}),
-              flush=True)
+        print(json.dumps({"naca_rel_err": _jsonable({a: r["rel_err"] for a, r in res.items()
+                                                      if a != "mass_bound"})}), flush=True)
 
 
 def main():
@@ -268,6 +274,8 @@ def main():
                          "results go to results/<study>.json")
     ap.add_argument("--study-scale", type=float, default=1.0,
                     help="fraction of the study step counts (for quick checks)")
+    ap.add_argument("--nn-mass-bound", type=float, default=1e-2,
+                    help="fallback density bound of the neural outflow in the studies")
     ap.add_argument("--nn-switch", type=int, default=0,
                     help="steps of Zou & He before the neural outflow is switched on (studies)")
     ap.add_argument("--calibration-copy", action="store_true")
@@ -334,7 +342,7 @@ def main():
                     "fp64": {k: acc["fp64"].get(k) for k in ("cd_mean", "cl_rms", "st", "mlups")},
                     "rel_err": acc["rel_err"]}
     if args.study:
-        run_studies(args.study, args.study_scale, args.nn_switch)
+        run_studies(args.study, args.study_scale, args.nn_switch, args.nn_mass_bound)
 
     line = {
         "metric": "MLUPS + %HBM peak; C_D/C_L/St error, NN vs Zou-He outflow at same MLUPS",

@@ -276,8 +276,16 @@ __device__ void nn_block(const StepLaunch& L, int nb, NnSmem<typename Store<S>::
 // are periodic (the library rejects walls for this outflow).
 constexpr int kCbRows = kNnRows + 4;
 constexpr int kCbCols = 3;
-static_assert(9 * kCbRows * kCbCols + 3 * kCbCols * kCbRows <= 9 * kStRows * kStCols,
-              "characteristic staging must fit the outlet blocks' LDS");
+constexpr int kCbUnits = kCbcHidden / kWaves;   // hidden units per wave and row
+
+template <typename T>
+struct alignas(16) CbcSmem {
+  T st[9 * kCbRows * kCbCols];           // A at columns nx-3 .. nx-1, rows y0-2 .. y0+65
+  T mo[3 * kCbCols * kCbRows];           // [k][column][row]: drho, u, v
+  T feat[kNnRows * kCbcIn];              // network inputs per row
+  T h1[kNnRows * kCbcHidden];            // first hidden layer
+  T ps[kNnRows * kWaves * 2];            // per-wave partial sums of s_0, s_1
+};
 
 template <typename T>
 __device__ __forceinline__ T sigmoid_t(T s) {
@@ -287,60 +295,46 @@ __device__ __forceinline__ T sigmoid_t(T s) {
     return T(1) / (T(1) + expf(-s));
 }
 
-// The tuning network 9 -> 20 -> 20 -> 2 (LeakyReLU), sigmoid and affine maps.
+// Gradients (p_x, u_x, v_x, p_y, u_y, v_y) at the outlet node of staged row r:
+// second-order one-sided in x, central in y (periodic rows are staged wrapped).
 template <typename T>
-__device__ void cbc_network(const CbcDev* __restrict__ c, const T f[kCbcIn], T& sigma,
-                            T& kappa2) {
-  T z[kCbcIn];
+__device__ __forceinline__ void cbc_gradients(const T* mo, int r, T g[6]) {
+  constexpr int R = kCbRows, NC = kCbCols;
+  const T cs2 = T(1.0 / 3.0);
 #pragma unroll
-  for (int i = 0; i < kCbcIn; ++i) z[i] = (f[i] - T(c->mu_in[i])) / T(c->sd_in[i]);
-  const T a = T(c->leaky);
-  // each first-layer unit is folded into the second-layer sums as soon as it
-  // is known, so only those 20 sums stay live
-  T h2[kCbcHidden];
-#pragma unroll
-  for (int o = 0; o < kCbcHidden; ++o) h2[o] = T(c->b2[o]);
-#pragma unroll 1
-  for (int k = 0; k < kCbcHidden; ++k) {
-    T s = T(c->b1[k]);
-#pragma unroll
-    for (int i = 0; i < kCbcIn; ++i) s += T(c->w1[k * kCbcIn + i]) * z[i];
-    const T h1 = s > T(0) ? s : a * s;
-#pragma unroll
-    for (int o = 0; o < kCbcHidden; ++o) h2[o] += T(c->w2[o * kCbcHidden + k]) * h1;
+  for (int k = 0; k < 3; ++k) {
+    const T* m = mo + k * NC * R;
+    const T gx = T(0.5) * (T(3) * m[2 * R + r] - T(4) * m[R + r] + m[r]);
+    const T gy = T(0.5) * (m[2 * R + r + 1] - m[2 * R + r - 1]);
+    g[k] = k == 0 ? cs2 * gx : gx;
+    g[3 + k] = k == 0 ? cs2 * gy : gy;
   }
-  T s0 = T(c->b3[0]), s1 = T(c->b3[1]);
-#pragma unroll
-  for (int i = 0; i < kCbcHidden; ++i) {
-    const T h = h2[i] > T(0) ? h2[i] : a * h2[i];
-    s0 += T(c->w3[i]) * h;
-    s1 += T(c->w3[kCbcHidden + i]) * h;
-  }
-  sigma = T(c->sigma_scale) * sigmoid_t(s0) + T(c->sigma_shift);
-  kappa2 = T(c->kappa_scale) * sigmoid_t(s1) + T(c->kappa_shift);
+}
+
+template <typename T>
+__device__ __forceinline__ T leaky_t(T x, T a) {
+  return x > T(0) ? x : a * x;
 }
 
 template <typename S, int MRT>
-__device__ void cbc_block(const StepLaunch& L, int nb, NnSmem<typename Store<S>::T>& sm,
+__device__ void cbc_block(const StepLaunch& L, int nb, CbcSmem<typename Store<S>::T>& sm,
                           typename Store<S>::T* part) {
   using T = typename Store<S>::T;
   constexpr int R = kCbRows, NC = kCbCols;
-  T* st = sm.u.st;                       // [q][R][NC] populations
-  T* mo = sm.u.st + 9 * R * NC;          // [k][NC][R]: drho, u, v
   const S* __restrict__ A = static_cast<const S*>(L.A);
   S* __restrict__ B = static_cast<S*>(L.B);
   const CbcDev* __restrict__ c = L.cbc;
   const int y0 = nb * kNnRows;
   const int xs0 = L.nx - NC;
 
-  // 1. stage A[q][y0-2 .. y0+65][nx-3 .. nx-1]
+  // 1. stage A[q][y0-2 .. y0+65][nx-3 .. nx-1] (rows wrapped: periodic laterals)
   for (int i = threadIdx.x; i < 9 * R * NC; i += kBlock) {
     const int q = i / (R * NC);
     const int rem = i - q * (R * NC);
     const int r = rem / NC;
     const int cc = rem - r * NC;
     const int y = (y0 - 2 + r + 2 * L.ny) % L.ny;
-    st[i] = Store<S>::ld(A + int64_t(q) * L.plane + int64_t(y) * L.pitch + xs0 + cc);
+    sm.st[i] = Store<S>::ld(A + int64_t(q) * L.plane + int64_t(y) * L.pitch + xs0 + cc);
   }
   __syncthreads();
   // 2. the state (drho, u, v) of the staged nodes
@@ -348,41 +342,80 @@ __device__ void cbc_block(const StepLaunch& L, int nb, NnSmem<typename Store<S>:
     const int r = i / NC, cc = i - (i / NC) * NC;
     T g[9];
 #pragma unroll
-    for (int q = 0; q < 9; ++q) g[q] = st[(q * R + r) * NC + cc];
+    for (int q = 0; q < 9; ++q) g[q] = sm.st[(q * R + r) * NC + cc];
     const Macro<T> m = macro(g);
-    mo[(0 * NC + cc) * R + r] = m.drho;
-    mo[(1 * NC + cc) * R + r] = m.jx / m.rho;
-    mo[(2 * NC + cc) * R + r] = m.jy / m.rho;
+    sm.mo[(0 * NC + cc) * R + r] = m.drho;
+    sm.mo[(1 * NC + cc) * R + r] = m.jx / m.rho;
+    sm.mo[(2 * NC + cc) * R + r] = m.jy / m.rho;
   }
   __syncthreads();
 
-  T fx = T(0), fy = T(0), dm = T(0);
   const int j = threadIdx.x;
   const int y = y0 + j;
+  const bool row = j < kNnRows && y < L.ny;
+  double* dts = L.cbc_dt + 4 * int64_t(row ? y : 0);
+  T sigma = T(c->sigma), kappa2 = T(c->kappa2);
+  // 3. the tuning network, spread over the workgroup (uniform branch)
+  if (c->has_net) {
+    if (j < kNnRows) {
+      T g[6];
+      cbc_gradients(sm.mo, j + 2, g);
+      const T prev[3] = {T(dts[0]), T(dts[1]), T(dts[2])};
+#pragma unroll
+      for (int i = 0; i < kCbcIn; ++i) {
+        const T f = i < 6 ? g[i] : (row ? prev[i - 6] : T(0));
+        sm.feat[j * kCbcIn + i] = (f - T(c->mu_in[i])) / T(c->sd_in[i]);
+      }
+    }
+    __syncthreads();
+    const int rr = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const T a = T(c->leaky);
+#pragma unroll 1
+    for (int u = 0; u < kCbUnits; ++u) {
+      const int o = w * kCbUnits + u;
+      T s = T(c->b1[o]);
+#pragma unroll
+      for (int i = 0; i < kCbcIn; ++i) s += T(c->w1[o * kCbcIn + i]) * sm.feat[rr * kCbcIn + i];
+      sm.h1[rr * kCbcHidden + o] = leaky_t(s, a);
+    }
+    __syncthreads();
+    T p0 = T(0), p1 = T(0);
+#pragma unroll 1
+    for (int u = 0; u < kCbUnits; ++u) {
+      const int o = w * kCbUnits + u;
+      T s = T(c->b2[o]);
+#pragma unroll 4
+      for (int k = 0; k < kCbcHidden; ++k) s += T(c->w2[o * kCbcHidden + k]) * sm.h1[rr * kCbcHidden + k];
+      const T h = leaky_t(s, a);
+      p0 += T(c->w3[o]) * h;
+      p1 += T(c->w3[kCbcHidden + o]) * h;
+    }
+    sm.ps[(rr * kWaves + w) * 2 + 0] = p0;
+    sm.ps[(rr * kWaves + w) * 2 + 1] = p1;
+    __syncthreads();
+    if (j < kNnRows) {
+      const T* q = sm.ps + j * kWaves * 2;
+      const T s0 = T(c->b3[0]) + ((q[0] + q[2]) + (q[4] + q[6]));
+      const T s1 = T(c->b3[1]) + ((q[1] + q[3]) + (q[5] + q[7]));
+      sigma = T(c->sigma_scale) * sigmoid_t(s0) + T(c->sigma_shift);
+      kappa2 = T(c->kappa_scale) * sigmoid_t(s1) + T(c->kappa_shift);
+    }
+  }
+
+  // 4. one thread per row: LODI update, reconstruction, collision
+  T fx = T(0), fy = T(0), dm = T(0);
   const int x = L.nx - 1;
-  if (j < kNnRows && y < L.ny) {
+  if (row) {
     const uint32_t lk = L.links[int64_t(y) * L.pitch + x];
     if (!(lk & LINK_SOLID)) {
       const int r = j + 2;
-      T gx[3], gy[3];
-#pragma unroll
-      for (int k = 0; k < 3; ++k) {
-        const T* m2 = mo + (k * NC + 2) * R;
-        gx[k] = T(0.5) * (T(3) * m2[r] - T(4) * mo[(k * NC + 1) * R + r] + mo[(k * NC) * R + r]);
-        gy[k] = T(0.5) * (m2[r + 1] - m2[r - 1]);         // periodic rows (staged wrapped)
-      }
+      T g6[6];
+      cbc_gradients(sm.mo, r, g6);
+      const T p_x = g6[0], u_x = g6[1], v_x = g6[2], p_y = g6[3], u_y = g6[4], v_y = g6[5];
       const T cs2 = T(1.0 / 3.0), cs = T(0.57735026918962576451);
-      const T p_x = cs2 * gx[0], u_x = gx[1], v_x = gx[2];
-      const T p_y = cs2 * gy[0], u_y = gy[1], v_y = gy[2];
-      const T drho = mo[(0 * NC + 2) * R + r], u = mo[(1 * NC + 2) * R + r];
-      const T v = mo[(2 * NC + 2) * R + r];
+      const T drho = sm.mo[(0 * NC + 2) * R + r], u = sm.mo[(1 * NC + 2) * R + r];
+      const T v = sm.mo[(2 * NC + 2) * R + r];
       const T rho = T(1) + drho, p = cs2 * rho;
-      double* dts = L.cbc_dt + 4 * int64_t(y);
-      T sigma = T(c->sigma), kappa2 = T(c->kappa2);
-      if (c->has_net) {
-        const T f[kCbcIn] = {p_x, u_x, v_x, p_y, u_y, v_y, T(dts[0]), T(dts[1]), T(dts[2])};
-        cbc_network(c, f, sigma, kappa2);
-      }
       // Eqs. 21-26 (readings: dp/dx in L_1, L_5; du/dy in T_1, T_5)
       const T L3 = u * v_x;
       const T L5 = (u + cs) * (p_x + rho * cs * u_x);
@@ -405,15 +438,15 @@ __device__ void cbc_block(const StepLaunch& L, int nb, NnSmem<typename Store<S>:
         const bool bb = (lk >> q) & 1u;
         const int cc = bb ? 2 : min(2 - cx(q), 2);      // unknowns: replaced below
         const int rr = bb ? r : r - cy(q);
-        g[q] = st[((bb ? opp(q) : q) * R + rr) * NC + cc];
+        g[q] = sm.st[((bb ? opp(q) : q) * R + rr) * NC + cc];
       }
       outlet_state(g, drho + rho_t, u + u_t, v + v_t);   // forward Euler, Eq. 29, Eqs. 8-10
       add_force(lk, g, fx, fy);
       dm = macro(g).drho;
       collide<T, MRT>(g, L);
-      const int64_t row = int64_t(y) * L.pitch + x;
+      const int64_t row_off = int64_t(y) * L.pitch + x;
 #pragma unroll
-      for (int q = 0; q < 9; ++q) Store<S>::st(B + int64_t(q) * L.plane + row, g[q]);
+      for (int q = 0; q < 9; ++q) Store<S>::st(B + int64_t(q) * L.plane + row_off, g[q]);
     }
   }
   wave_partials(fx, fy, dm, T(0), part);
@@ -439,11 +472,13 @@ __global__ void __launch_bounds__(kBlock) LBM_STEP_ATTR k_step(const StepLaunch 
   T* part = static_cast<T*>(L.part_w) + kPartials * kWaves * (v - kFirst);
   if constexpr (OUT != 0) {
     if (v < kFirst + L.n_nn) {
-      __shared__ NnSmem<T> sm;
-      if constexpr (OUT == OUTLET_CBC)
+      if constexpr (OUT == OUTLET_CBC) {
+        __shared__ CbcSmem<T> sm;
         cbc_block<S, MRT>(L, v - kFirst, sm, part);
-      else
+      } else {
+        __shared__ NnSmem<T> sm;
         nn_block<S, MRT>(L, v - kFirst, sm, part);
+      }
       return;
     }
   }
