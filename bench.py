@@ -236,6 +236,13 @@ def run_studies(which, scale, nn_switch=0, mass_bound=1e-2):
     nets = None if which in ("train", "all") else load_networks()
     if nets is None:
         nets = train_study(scale)
+    if which in ("scaling", "all"):
+        res = experiments.scaling_study(nets["paper_9x20"], steps=n(150_000), progress=_progress,
+                                        mass_bound=3e-4)
+        with open(os.path.join(RESULTS, "scaling_study.json"), "w") as f:
+            json.dump(_jsonable(res), f, indent=1)
+        print(json.dumps({"scaling_rel_err": _jsonable({re: r["rel_err"] for re, r in res.items()
+                                                         if isinstance(r, dict)})}), flush=True)
     if which in ("nn", "all"):
         res = experiments.outflow_study(nets, steps=n(150_000), progress=_progress,
                                         nn_switch=n(nn_switch), mass_bound=mass_bound)
@@ -268,7 +275,8 @@ def main():
     ap.add_argument("--no-accuracy", action="store_true",
                     help="skip the FP32-vs-FP64 precision study (C_D, C_L, St)")
     ap.add_argument("--accuracy-steps", type=int, default=50_000)
-    ap.add_argument("--study", choices=["train", "nn", "naca", "vortex", "all"], default=None,
+    ap.add_argument("--study", choices=["train", "nn", "naca", "vortex", "scaling", "all"],
+                    default=None,
                     help="also run the truncated-domain outflow study (training data, "
                          "training, neural vs Zou-He outflow) and/or the NACA0012 study; "
                          "results go to results/<study>.json")

@@ -39,13 +39,15 @@ def _sync():
 
 
 def run_case(case, steps, *, precision="fp32", collision="mrt", lateral="periodic",
-             network=None, mass_bound=1e-2, noise_amp=1e-4, seed=2, u_ref=workloads.U_IN,
+             network=None, mass_bound=1e-2, noise_amp=1e-4, seed=2, u_ref=None,
              length=None, window=0.4, nn_switch=0):
     """Run one lattice for `steps` and summarise its force history.  With a
     network, the outflow is Zou & He for the first `nn_switch` steps and
     neural after them."""
+    u_in = case.get("u_in", workloads.U_IN)
+    u_ref = u_in if u_ref is None else u_ref
     lat = lbm.Lattice(case["mask"], case["tau"], precision=precision, collision=collision,
-                      lateral=lateral, u_in=workloads.U_IN, noise_amp=noise_amp, seed=seed,
+                      lateral=lateral, u_in=u_in, noise_amp=noise_amp, seed=seed,
                       history_cap=steps, **(RATES if collision == "mrt" else {}))
     _sync()
     t0 = time.perf_counter()
@@ -297,4 +299,35 @@ def vortex_study(steps=600, every=10, nx=200, ny=400, reference_nx=1000, precisi
                              "max": float(np.max(err)), "final": float(err[-1]),
                              "mean": float(np.mean(err))}
         progress(f"vortex {name}", {})
+    return out
+
+
+def scaling_study(network, re_list=(10.0, 20.0, 50.0, 100.0, 200.0), tau=0.6, steps=150_000,
+                  mass_bound=3e-4, progress=_noop):
+    """Diffusive scaling (tau fixed, u_in = Re nu / D) at Re 10-200: the
+    truncated cylinder (D = 64, 8 D) with Zou & He and with the neural outflow
+    against the 40 D Zou & He reference (mean C_D, rms C_L, St)."""
+    out = {"tau": tau, "mass_bound": mass_bound}
+    for re in re_list:
+        ref = run_case(workloads.truncated_cylinder(40, re=re, tau=tau), steps)
+        progress(f"diffusive Re {re:g} reference 40 D", ref)
+        zh = run_case(workloads.truncated_cylinder(8, re=re, tau=tau), steps)
+        progress(f"diffusive Re {re:g} Zou-He 8 D", zh)
+        nn = run_case(workloads.truncated_cylinder(8, re=re, tau=tau), steps, network=network,
+                      mass_bound=mass_bound)
+        progress(f"diffusive Re {re:g} neural 8 D", nn)
+
+        def errs(r):
+            if "cd_mean" not in r or "cd_mean" not in ref:
+                return None
+            e = {"cd_mean": abs(r["cd_mean"] - ref["cd_mean"]) / abs(ref["cd_mean"])}
+            if ref["cl_rms"] > 1e-2:          # shedding: rms lift and St are defined
+                e.update(cl_rms=abs(r["cl_rms"] - ref["cl_rms"]) / ref["cl_rms"],
+                         st=abs(r["st"] - ref["st"]) / abs(ref["st"]))
+            else:                             # steady: spurious lift, absolute
+                e.update(cl_rms_abs=r["cl_rms"], cl_rms_ref=ref["cl_rms"])
+            return e
+        out[re] = {"u_in": workloads.truncated_cylinder(8, re=re, tau=tau)["u_in"],
+                   "reference": ref, "zouhe_8d": zh, "neural_8d": nn,
+                   "rel_err": {"zh_8d": errs(zh), "nn_8d": errs(nn)}}
     return out

@@ -25,13 +25,17 @@ def channel_cylinder(nx=4096, ny=1024, D=80, re=200.0):
     return dict(mask=mask, tau=tau_for(re, D), D=D, re=re)
 
 
-def truncated_cylinder(downstream_d, D=64, re=200.0, ny=512, x_c=3583):
+def truncated_cylinder(downstream_d, D=64, re=200.0, ny=512, x_c=3583, tau=None):
     """Periodic-lateral cylinder lattice, ny = 8 D, cylinder centre at x_c,
     outlet `downstream_d` diameters behind the centre (4096 x 512 at 8 D,
-    6144 x 512 at 40 D)."""
+    6144 x 512 at 40 D).  Acoustic scaling by default (u_in = U_IN, tau from
+    Re); with `tau` given, diffusive scaling (tau fixed, u_in = Re nu / D)."""
     nx = x_c + int(downstream_d * D) + 1
     mask = geometry.cylinder(nx, ny, x_c, ny // 2, D)
-    return dict(mask=mask, tau=tau_for(re, D), D=D, re=re, nx=nx)
+    if tau is None:
+        return dict(mask=mask, tau=tau_for(re, D), D=D, re=re, nx=nx, u_in=U_IN)
+    u = re * (tau - 0.5) / 3.0 / D
+    return dict(mask=mask, tau=float(tau), D=D, re=re, nx=nx, u_in=u)
 
 
 def training_pairs(n_pairs=64, seed=3, d_range=(20, 40), ld_range=(8.0, 40.0),
