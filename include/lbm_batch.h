@@ -10,9 +10,9 @@
  * the collision operator and the lateral condition; size, geometry, tau,
  * inlet velocity and noise seed are per lattice.
  *
- * One call of lbm_batch_step runs a cooperative (co-resident) grid that
- * strides over the tiles of all lattices and separates time steps with a
- * grid-wide barrier.  The barrier's wait is bounded: if it does not
+ * One call of lbm_batch_step runs a cooperative (co-resident) grid whose
+ * waves stride over the rows of all lattices (256 columns at a time) and
+ * separates time steps with a grid-wide barrier.  The barrier's wait is bounded: if it does not
  * complete within the spin limit the kernel stops and the next
  * synchronising call returns LBM_EHIP.
  *

@@ -3,7 +3,8 @@
 // One launch advances the lattice by one step (Sec. 2.1 Eq. 1 in pull form):
 // every fluid node gathers the post-collision populations of its neighbours
 // from buffer A (half-way bounce-back where the source is a wall or a solid,
-// Eq. 12), completes the inlet / outlet column (Sec. 2.2, Sec. 3.1 Eq. 16),
+// Eq. 12), completes the inlet / outlet column (Sec. 2.2; Sec. 3.1 Eq. 16;
+// Sec. 3.2 Eqs. 18-29),
 // collides (Eq. 2 or MRT) and writes its post-collision populations to B.
 // The same launch produces the momentum-exchange force of the step
 // (Eqs. 14-15) and the mass, as per-workgroup partial sums.
@@ -12,11 +13,12 @@
 //   v = 0                 level-2 reduction (FP64, fixed order) of the step
 //                         before the previous one into the accumulators;
 //   v = 1 .. kReducers    level-1 reduction of the previous step's slots;
-//   next n_nn             neural outlet blocks, 64 outlet rows each;
+//   next n_nn             outlet blocks (neural or characteristic outflow),
+//                         64 outlet rows each;
 //   the rest              bulk tiles, x fastest.
 //
 // Memory layout: population q of node (x, y) at q*plane + y*pitch + x, with
-// pitch a multiple of 64 elements; offsets f - w stored in S.
+// pitch a multiple of 256 elements; offsets f - w stored in S (f for FP64).
 #include "d2q9_dev.hpp"
 #include "lbm_internal.hpp"
 #include "mlp_dev.hpp"
