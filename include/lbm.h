@@ -12,6 +12,8 @@
  *   momentum-exchange force   Sec. 2.3, Eqs. 14-15
  *   neural outflow            Sec. 3.1, Eq. 16 (unknowns 3, 6, 7 at x = nx-1)
  *   MLP training              Sec. 3.1, Eq. 17
+ *   characteristic outflow    Sec. 4, Eqs. 18-29 (fixed or network-tuned
+ *                             sigma, kappa_2; periodic laterals)
  *
  * Conventions shared by every entry point
  *   - D2Q9 numbering q: 0 (0,0) 1 (1,0) 2 (0,1) 3 (-1,0) 4 (0,-1) 5 (1,1)
@@ -189,7 +191,7 @@ lbm_status lbm_force_history(lbm_ctx* c, double* fx, double* fy, int64_t cap,
  * characteristic outflow is selected by lbm_set_outflow_cbc. */
 lbm_status lbm_set_outflow_model(lbm_ctx* c, int32_t kind, const lbm_mlp* w);
 
-/* Tuning network of the characteristic outflow (Sec. 3.2): nine features per
+/* Tuning network of the characteristic outflow (Sec. 4.2): nine features per
  * outlet node, (p_x, u_x, v_x, p_y, u_y, v_y, p_t, u_t, v_t), the time
  * derivatives being those the outflow computed at the previous step (zero
  * before the first), standardised z = (x - mu_in) / sd_in; two hidden layers
@@ -205,7 +207,7 @@ typedef struct {
   double sigma_scale, sigma_shift, kappa_scale, kappa_shift;
 } lbm_cbc_net;
 
-/* Characteristic outflow (Sec. 3.2, Eqs. 18-29).  At every step the outlet
+/* Characteristic outflow (Sec. 4, Eqs. 18-29).  At every step the outlet
  * node takes the density and velocity of a forward Euler step of the
  * isothermal LODI equations (Eqs. 18-20) from the state of columns nx-3 ..
  * nx-1 (one-sided x-derivatives of second order, central y-derivatives),

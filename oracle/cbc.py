@@ -1,7 +1,7 @@
 """Characteristic outflow boundary (CBC) at the right column, FP64 (test
 infrastructure; see ``oracle/__init__``).
 
-Sec. 3.2: at the outlet x = L the density and the velocity of the next step
+Sec. 4: at the outlet x = L the density and the velocity of the next step
 follow from the characteristic (LODI) form of the isothermal equations,
 Eqs. 18-20, with the wave amplitudes of Eqs. 21-23 and the transverse terms
 of Eqs. 24-26; the incoming amplitude L_1 is replaced by Eq. 27 (relaxation

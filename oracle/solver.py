@@ -15,7 +15,7 @@ One step t -> t+1, in the order the paper's method implies:
      F(t) = Delta P / Delta t (Eq. 15), lattice units (Delta x = Delta t = 1);
   4. boundary columns: Zou & He velocity inlet at x = 0; at x = nx-1 the
      Zou & He pressure outlet, the neural reconstruction of Eq. 16 with a
-     per-node Zou & He fallback, or the characteristic outflow of Sec. 3.2
+     per-node Zou & He fallback, or the characteristic outflow of Sec. 4
      (oracle/cbc.py) from the state of the three last columns at time t.
 
 Geometry mask values: 0 fluid, 1 body (links to it are force-summed),
@@ -74,7 +74,7 @@ class Lattice:
 
     def set_outflow_cbc(self, sigma=0.0, kappa2=0.0, mach=0.0, length=None, rho_inf=1.0,
                         net=None):
-        """Use the characteristic outflow of Sec. 3.2 (Eqs. 18-29), with fixed
+        """Use the characteristic outflow of Sec. 4 (Eqs. 18-29), with fixed
         sigma and kappa_2 or, given ``net``, the tuning network.  Periodic
         laterals only: the section gives no treatment of the corners where
         the outlet meets a no-slip wall."""

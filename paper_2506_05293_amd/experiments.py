@@ -261,7 +261,7 @@ def naca_study(networks, aoas=(0.0, 4.0, 8.0), steps=200_000, precision="fp32", 
 
 def vortex_study(steps=600, every=10, nx=200, ny=400, reference_nx=1000, precision="fp32",
                  settings=None, progress=_noop):
-    """Convected vortex (Sec. 3.2): RMS density error over the truncated
+    """Convected vortex (Sec. 4.1): RMS density error over the truncated
     lattice against the same flow on a lattice reference_nx long, every
     `every` steps, for the Zou & He pressure outlet and characteristic
     outlets with fixed (sigma, kappa_2)."""

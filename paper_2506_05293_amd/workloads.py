@@ -81,7 +81,7 @@ def naca_case(aoa_deg, chord=256, nx=3072, ny=1024, after_te_chords=3.0, re=1000
 
 def convected_vortex(nx=200, ny=400, ma=0.3, rc=20.0, beta=0.5, x0=150.0, re=750.0,
                      length=200.0):
-    """Lamb-Oseen vortex in a uniform stream u0 = Ma c_s (Sec. 3.2): centre
+    """Lamb-Oseen vortex in a uniform stream u0 = Ma c_s (Sec. 4.1): centre
     (x0, ny/2), core radius rc, strength beta; density from the isothermal
     radial pressure balance, rho = exp(-(beta u0)^2 / (2 c_s^2) e^{-r^2/rc^2});
     Re = u0 * length / nu.  Returns the mask, tau, the initial fields and u0.

@@ -1,4 +1,4 @@
-"""GPU parity of the characteristic outflow (Sec. 3.2, Eqs. 18-29) fused into
+"""GPU parity of the characteristic outflow (Sec. 4, Eqs. 18-29) fused into
 the step, against the oracle, through the C ABI (lbm_set_outflow_cbc).
 
 FP64: both sides take the same arithmetic in the same order up to

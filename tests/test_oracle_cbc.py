@@ -1,4 +1,4 @@
-"""Pins of the oracle's characteristic outflow (Sec. 3.2, Eqs. 18-29).
+"""Pins of the oracle's characteristic outflow (Sec. 4, Eqs. 18-29).
 
 Each test fixes a part by something other than the code itself: exactness of
 the difference stencils on quadratics, the equilibrium fixed point, the
