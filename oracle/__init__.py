@@ -21,6 +21,11 @@ Modules
                boundary columns, neural outflow (Eq. 16)
   mlp          the outflow MLP: forward with BF16 emulation, FP64 backward,
                MSE loss (Eq. 17), Adam
+  cbc          characteristic outflow (Sec. 4, Eqs. 18-29) and its tuning
+               network (Sec. 4.2)
+  cbc_train    closed-loop training of the tuning network (Sec. 4.2): the
+               step re-expressed in torch FP64, segment loss over Omega_s,
+               gradient by reverse-mode differentiation
   splitmix64   the sequential SplitMix64 generator (Steele, Lea & Flood 2014)
   observables  drag/lift coefficients (Eq. 13) and the Strouhal number
 
