@@ -122,7 +122,7 @@ Layout make_layout(const lbm_params& p) {
   L.ntx = L.nchunk;
   L.nty = (p.ny + L.rows - 1) / L.rows;
   L.nn_max = (p.ny + kNnRows - 1) / kNnRows;
-  L.nslots_max = (L.nn_max + L.ntx * L.nty) * kWaves;
+  L.nslots_max = (L.nn_max + 8 + L.ntx * L.nty) * kWaves;   // + padding to a multiple of 8
   L.plane = int64_t(p.ny) * L.pitch;
   const size_t pop = size_t(9) * size_t(L.plane) * elem_size(p.precision);
   size_t o = 0;
@@ -241,8 +241,9 @@ struct lbm_ctx {
     L.ntx = lay.ntx;
     L.nty = lay.nty;
     L.n_nn = n_nn;
-    L.nblocks = 1 + kReducers + n_nn + lay.ntx * lay.nty;
-    L.nslots = (n_nn + lay.ntx * lay.nty) * kWaves;
+    L.nspecial = (1 + kReducers + n_nn + 7) / 8 * 8;
+    L.nblocks = L.nspecial + lay.ntx * lay.nty;
+    L.nslots = (L.nspecial - 1 - kReducers + lay.ntx * lay.nty) * kWaves;
     L.xper = p.xbc == LBM_X_PERIODIC;
     L.yper = p.lateral == LBM_LATERAL_PERIODIC;
     L.omega = 1.0 / p.tau;

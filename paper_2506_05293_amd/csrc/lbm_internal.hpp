@@ -48,7 +48,7 @@ struct MlpDev {
   float pad[3];
 };
 
-// Device image of the characteristic outflow (Sec. 3.2): fixed sigma,
+// Device image of the characteristic outflow (Sec. 4): fixed sigma,
 // kappa_2, or the 9-20-20-2 tuning network with its output maps.
 constexpr int kCbcIn = 9, kCbcHidden = 20;
 struct CbcDev {
@@ -96,7 +96,8 @@ struct StepLaunch {
   int rows;             // rows per bulk block
   int ntx, nty;         // bulk tiles
   int n_nn;             // outlet blocks, neural or characteristic (0: Zou & He)
-  int nblocks;          // whole grid: 1 + kReducers + n_nn + ntx*nty
+  int nspecial;         // 1 + kReducers + n_nn rounded up to a multiple of 8
+  int nblocks;          // whole grid: nspecial + ntx*nty
   int nslots;           // partial slots written per step (waves of the
                         // neural and bulk workgroups)
   int xper, yper;

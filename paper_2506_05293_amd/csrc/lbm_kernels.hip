@@ -4,17 +4,18 @@
 // every fluid node gathers the post-collision populations of its neighbours
 // from buffer A (half-way bounce-back where the source is a wall or a solid,
 // Eq. 12), completes the inlet / outlet column (Sec. 2.2; Sec. 3.1 Eq. 16;
-// Sec. 3.2 Eqs. 18-29),
+// Sec. 4, Eqs. 18-29),
 // collides (Eq. 2 or MRT) and writes its post-collision populations to B.
 // The same launch produces the momentum-exchange force of the step
 // (Eqs. 14-15) and the mass, as per-workgroup partial sums.
 //
-// Grid layout (virtual block ids after the XCD remap, see xcd_remap):
-//   v = 0                 level-2 reduction (FP64, fixed order) of the step
+// Grid layout (block ids; the bulk tiles are remapped per XCD, see xcd_remap):
+//   0                     level-2 reduction (FP64, fixed order) of the step
 //                         before the previous one into the accumulators;
-//   v = 1 .. kReducers    level-1 reduction of the previous step's slots;
+//   1 .. kReducers        level-1 reduction of the previous step's slots;
 //   next n_nn             outlet blocks (neural or characteristic outflow),
 //                         64 outlet rows each;
+//   up to nspecial        padding to a multiple of 8 (empty slots);
 //   the rest              bulk tiles, x fastest.
 //
 // Memory layout: population q of node (x, y) at q*plane + y*pitch + x, with
@@ -267,7 +268,7 @@ __device__ void nn_block(const StepLaunch& L, int nb, NnSmem<typename Store<S>::
 }
 
 
-// ---- characteristic outlet block (Sec. 3.2, Eqs. 18-29) ------------------------
+// ---- characteristic outlet block (Sec. 4, Eqs. 18-29) ------------------------
 // 64 outlet rows per workgroup.  The state of the time level is the moments of
 // the stored post-collision populations (collision conserves them); columns
 // nx-3 .. nx-1 of rows y0-2 .. y0+65 are staged and reduced to (drho, u, v),
@@ -462,7 +463,11 @@ template <typename S, int MRT, int OUT, int PATH>
 __global__ void __launch_bounds__(kBlock) LBM_STEP_ATTR k_step(const StepLaunch L) {
   using T = typename Store<S>::T;
   constexpr int kFirst = 1 + kReducers;          // first workgroup with slots
-  const int v = xcd_remap(blockIdx.x, L.nblocks);
+  // The reducers and outlet blocks take the first hardware ids, which go to
+  // the eight XCDs in turn; the bulk tiles after them are remapped so that
+  // each XCD works on one contiguous range (nspecial is a multiple of 8).
+  const int b = int(blockIdx.x);
+  const int v = b < L.nspecial ? b : L.nspecial + xcd_remap(b - L.nspecial, L.nblocks - L.nspecial);
   if (v < kFirst) {
     if (v == 0) {
       if (L.reduce2) reduce_level2(L.lvl_r, L);
@@ -484,7 +489,11 @@ __global__ void __launch_bounds__(kBlock) LBM_STEP_ATTR k_step(const StepLaunch 
       return;
     }
   }
-  bulk_block<S, MRT, PATH>(L, v - kFirst - L.n_nn, part);
+  if (v < L.nspecial) {                          // padding: empty slots
+    wave_partials(T(0), T(0), T(0), T(0), part);
+    return;
+  }
+  bulk_block<S, MRT, PATH>(L, v - L.nspecial, part);
 }
 
 // Flush the pipeline after the last step: level 2 of the step before, then
