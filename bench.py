@@ -135,6 +135,58 @@ def time_steps(lat, steps, warmup, torch):
     return e0.elapsed_time(e1) / steps     # ms per step (one step kernel each)
 
 
+# Algorithmic HBM bytes per node and segment step of the CBC trainer (FP32):
+# forward 9 pulled reads + 9 writes, collision adjoint 9 pulled reads + 9
+# adjoint reads + 9 writes, streaming adjoint 9 gathered reads + 9 writes.
+CBC_TRAIN_BYTES_PER_NODE_STEP = 4 * (18 + 27 + 18)
+
+
+def time_cbc_training(torch, steps=20, warmup=3):
+    """Adam steps of the closed-loop CBC trainer on the shape of the
+    paper's training set: 110 start states for each of n_t = 5, 10, 25 on
+    the 200 x 400 convected-vortex lattice (strips of 53 columns), FP32.
+    The start states are the vortex's initial state placed at the outlet
+    (the cost does not depend on the values)."""
+    from paper_2506_05293_amd import lbm, workloads
+    case = workloads.convected_vortex(nx=200, ny=400, x0=185.0)
+    ny, w, n_ts = 400, 53, [5] * 110 + [10] * 110 + [25] * 110
+    lat = lbm.Lattice(case["mask"], case["tau"], precision="fp32", collision="bgk",
+                      lateral="periodic", u_in=case["u0"], noise_amp=0.0)
+    lat.init_fields(case["rho"], case["ux"], case["uy"])
+    strip = lat.populations()[:, :, -w:]
+    del lat
+    a0 = np.ascontiguousarray(np.broadcast_to(strip, (len(n_ts),) + strip.shape))
+    ref = np.zeros((len(n_ts), 3, ny, 25))
+    ref[:, 0] = 1.0
+    ref[:, 1] = case["u0"]
+    rng = np.random.default_rng(0)
+    net = {"w1": rng.standard_normal((20, 9)) * 0.47, "b1": np.zeros(20),
+           "w2": rng.standard_normal((20, 20)) * 0.32, "b2": np.zeros(20),
+           "w3": rng.standard_normal((2, 20)) * 0.02, "b3": np.zeros(2),
+           "mu_in": np.zeros(9), "sd_in": np.full(9, 1e-3), "leaky_slope": 0.01,
+           "sigma_scale": 1.0, "sigma_shift": 0.0, "kappa_scale": 1.0, "kappa_shift": 0.0}
+    tr = lbm.CbcTrainer(a0, ref, np.array(n_ts, np.int32), net, tau=case["tau"],
+                        mach=case["ma"], length=200.0, precision="fp32", eps=1e-16)
+    tr.step(warmup)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    tr.step(steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    node_steps = sum(n_ts) * ny * w
+    gbs = CBC_TRAIN_BYTES_PER_NODE_STEP * node_steps / (ms * 1e-3) / 1e9
+    return {"ms_per_adam_step": ms, "segments": len(n_ts), "segment_steps": sum(n_ts),
+            "node_steps_per_s": node_steps / (ms * 1e-3),
+            "algorithmic_GBps": gbs, "frac_of_hbm_peak": gbs / HBM_PEAK_GBS,
+            "bytes_per_node_step": CBC_TRAIN_BYTES_PER_NODE_STEP,
+            "setting": "110 starts x n_t in {5, 10, 25}, 200x400 vortex lattice, strips of 53 "
+                       "columns, FP32, forward + adjoint + Adam"}
+
+
 def cpu_baseline(nx, ny, seconds=15.0):
     """The FP64 oracle (single thread) on the same lattice for as many whole
     steps as fit in ~`seconds` (at least one)."""
@@ -225,6 +277,17 @@ def run_studies(which, scale, nn_switch=0, mass_bound=1e-2):
     from paper_2506_05293_amd import experiments
     os.makedirs(RESULTS, exist_ok=True)
     n = lambda k: max(1, int(k * scale))
+    if which in ("cbc_train", "all"):
+        res = experiments.cbc_training_study(adam_steps=n(2000), progress=_progress)
+        with open(os.path.join(RESULTS, "cbc_training.json"), "w") as f:
+            json.dump(_jsonable(res), f, indent=1)
+        print(json.dumps({"cbc_training": {
+            "loss_before": res["loss_before"], "loss_after": res["loss_after"],
+            "ms_per_adam_step": res["ms_per_adam_step"],
+            "vortex": {k: {a: r[a] for a in ("max", "final", "mean", "finite")}
+                       for k, r in res["vortex"]["runs"].items()}}}), flush=True)
+        if which == "cbc_train":
+            return
     if which in ("vortex", "all"):
         res = experiments.vortex_study(steps=max(10, n(600) // 10 * 10), progress=_progress)
         with open(os.path.join(RESULTS, "vortex_study.json"), "w") as f:
@@ -275,7 +338,8 @@ def main():
     ap.add_argument("--no-accuracy", action="store_true",
                     help="skip the FP32-vs-FP64 precision study (C_D, C_L, St)")
     ap.add_argument("--accuracy-steps", type=int, default=50_000)
-    ap.add_argument("--study", choices=["train", "nn", "naca", "vortex", "scaling", "all"],
+    ap.add_argument("--study", choices=["train", "nn", "naca", "vortex", "cbc_train", "scaling",
+                                        "all"],
                     default=None,
                     help="also run the truncated-domain outflow study (training data, "
                          "training, neural vs Zou-He outflow) and/or the NACA0012 study; "
@@ -286,6 +350,8 @@ def main():
                     help="fallback density bound of the neural outflow in the studies")
     ap.add_argument("--nn-switch", type=int, default=0,
                     help="steps of Zou & He before the neural outflow is switched on (studies)")
+    ap.add_argument("--no-cbc-train", action="store_true",
+                    help="skip timing the closed-loop trainer of the CBC tuning network")
     ap.add_argument("--calibration-copy", action="store_true")
     ap.add_argument("--write-traffic", nargs=4, metavar="CSV")
     args = ap.parse_args()
@@ -340,6 +406,7 @@ def main():
                           "sigma 0.25, kappa_2 = Ma"}
         del lat
     torch.cuda.synchronize()
+    cbc_training = None if args.no_cbc_train else time_cbc_training(torch)
 
     accuracy = None
     if not args.no_accuracy:
@@ -369,6 +436,7 @@ def main():
         "hbm_fraction": gbs / HBM_PEAK_GBS,
         "nn_outflow": nn,
         "cbc_outflow": cbc,
+        "cbc_training": cbc_training,
         "accuracy": accuracy,
         "cpu_baseline": None if args.no_cpu_baseline else cpu_baseline(nx, ny),
     }

@@ -1,0 +1,931 @@
+// Closed-loop training of the tuning network of the characteristic outflow
+// on gfx950 (C ABI of include/lbm_cbc_train.h).
+//
+// Sec. 4.2: segments of n_t steps start from reference states; the loss at
+// step n_t is the MSE of density and velocity over the n_t columns next to
+// the outlet; the network (9-20-20-2, LeakyReLU, sigmoid output maps) is
+// trained on the exact gradient of that loss through the rollout.  Every
+// segment runs on a strip of W = 2 n_max + 3 columns (nothing further
+// upstream reaches the loss region within n_t steps), in offset form
+// g = f - w, BGK collision, periodic rows, no solids.
+//
+// One optimiser step, every segment at once (a segment whose n_t is
+// shorter than the step index sits out that step):
+//   forward k = 0 .. n_max-1
+//     k_fwd_outlet  one thread per outlet row: gradients of the state at
+//                   the three last columns, network, LODI time derivatives
+//                   (Eqs. 18-28), stored outlet state and time derivatives;
+//     k_fwd_node    one thread per node: pull streaming, outlet state
+//                   (Eq. 29, Eqs. 8-10), BGK; the trajectory is kept;
+//   k_seed          loss over Omega and its derivative w.r.t. the final
+//                   state (the adjoint's initial value);
+//   backward k = n_max-1 .. 0
+//     k_bwd_node    collision adjoint at the recomputed pre-collision state;
+//     k_bwd_outlet  one thread per outlet row: adjoints of the outlet
+//                   reconstruction, of the LODI update and of the network,
+//                   the parameter gradient summed over the workgroup's 64
+//                   rows in LDS into a per-(segment, row block) FP64 slot;
+//     k_bwd_gather  streaming adjoint (a gather: population q of node x
+//                   takes the adjoint of node x + c_q) plus the moment
+//                   terms through which the outlet read the three columns;
+//   k_update        FP64 sum of the slots in a fixed order, Adam.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstddef>
+#include <cstring>
+#include <vector>
+
+#include "../../include/lbm_cbc_train.h"
+#include "d2q9_dev.hpp"
+#include "lbm_internal.hpp"
+
+namespace lbm {
+namespace {
+
+constexpr int kNP = LBM_CBC_NPARAMS;
+constexpr int kIn = 9, kH = 20;
+constexpr int kOW1 = 0, kOB1 = kH * kIn, kOW2 = kOB1 + kH, kOB2 = kOW2 + kH * kH,
+              kOW3 = kOB2 + kH, kOB3 = kOW3 + 2 * kH;
+static_assert(kOB3 + 2 == kNP, "parameter count");
+constexpr int kRows = 64;            // outlet rows per workgroup (one wave)
+constexpr int kNodes = 256;          // nodes per workgroup
+constexpr int kMaxSteps = 64;
+constexpr int kMadj = 12;            // per outlet row: 3 columns x (drho, u, v) + y-part
+
+struct CtState {
+  float w[kNP];                      // FP32 masters
+  double m[kNP], v[kNP];             // Adam moments
+  double mu[kIn], sd[kIn];           // input standardisation
+  double leaky, sig_scale, sig_shift, kap_scale, kap_shift;
+  double kappa1_coef, rho_inf_m1;    // (1 - M^2) c_s / L, rho_inf - 1
+  double loss;
+  double grad[kNP];
+};
+
+template <typename T>
+struct CtArgs {
+  T* traj;              // [seg][n_max+1][9][ny][W]
+  T* outs;              // [seg][n_max][ny][3]    outlet state drho', u', v'
+  T* dts;               // [seg][n_max+1][ny][3]  c_s^2 rho_t, u_t, v_t
+  T* lamA;              // [seg][9][ny][W]        adjoint of the post-collision state
+  T* lamF;              // [seg][9][ny][W]        adjoint of the pulled populations
+  T* lamP;              // [seg][ny][3]           adjoint of the time derivatives
+  T* madj;              // [seg][ny][12]          moment adjoints from the outlet
+  const T* ref;         // [seg][3][ny][n_max]    rho - 1, u, v
+  const int* nts;       // [seg]
+  double* gslot;        // [seg][nrb][kNP]
+  double* lslot;        // [seg][nlb]
+  CtState* st;
+  int ny, W, n_max, nrb, nlb;
+  int64_t plane;        // ny * W
+  T omega;
+  double seg_scale;     // 1 / n_seg
+};
+
+template <typename T>
+__device__ __forceinline__ T* state_at(const CtArgs<T>& a, int s, int k) {
+  return a.traj + (int64_t(s) * (a.n_max + 1) + k) * 9 * a.plane;
+}
+
+__device__ __forceinline__ int wrap(int y, int ny) { return y < 0 ? y + ny : (y >= ny ? y - ny : y); }
+
+template <typename T>
+__device__ __forceinline__ T leaky(T x, T a) {
+  return x > T(0) ? x : a * x;
+}
+
+template <typename T>
+__device__ __forceinline__ T sigmoid(T s) {
+  if constexpr (sizeof(T) == 8)
+    return T(1) / (T(1) + exp(-s));
+  else
+    return T(1) / (T(1) + expf(-s));
+}
+
+template <typename T>
+__device__ __forceinline__ void load_node(const T* A, int64_t plane, int64_t idx, T g[9]) {
+#pragma unroll
+  for (int q = 0; q < 9; ++q) g[q] = A[q * plane + idx];
+}
+
+template <typename T>
+__device__ __forceinline__ void node_state(const T* A, int64_t plane, int64_t idx, T& drho, T& u,
+                                           T& v) {
+  T g[9];
+  load_node(A, plane, idx, g);
+  const Macro<T> m = macro(g);
+  drho = m.drho;
+  u = m.jx / m.rho;
+  v = m.jy / m.rho;
+}
+
+// Pull streaming into node (x, y) of the strip: sources left of the strip
+// are replaced by the edge column itself, the outlet's unknowns are left 0.
+template <typename T>
+__device__ __forceinline__ void pull(const T* A, int64_t plane, int W, int ny, int x, int y,
+                                     T g[9]) {
+#pragma unroll
+  for (int q = 0; q < 9; ++q) {
+    int sx = x - cx(q);
+    const int sy = wrap(y - cy(q), ny);
+    if (sx < 0) sx = x;
+    g[q] = sx <= W - 1 ? A[q * plane + int64_t(sy) * W + sx] : T(0);
+  }
+}
+
+// State and gradients at the outlet node of row r (columns W-3 .. W-1):
+// second-order one-sided in x, central in y (periodic rows).
+template <typename T>
+struct OutIn {
+  T drho, u, v;
+  T g[6];      // p_x, u_x, v_x, p_y, u_y, v_y
+};
+
+template <typename T>
+__device__ OutIn<T> outlet_inputs(const T* A, int64_t plane, int W, int ny, int r) {
+  const T cs2 = T(1.0 / 3.0);
+  T d[3], uu[3], vv[3];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) node_state(A, plane, int64_t(r) * W + W - 3 + c, d[c], uu[c], vv[c]);
+  T dn, un, vn, ds, us, vs;
+  node_state(A, plane, int64_t(wrap(r + 1, ny)) * W + W - 1, dn, un, vn);
+  node_state(A, plane, int64_t(wrap(r - 1, ny)) * W + W - 1, ds, us, vs);
+  OutIn<T> o;
+  o.drho = d[2];
+  o.u = uu[2];
+  o.v = vv[2];
+  o.g[0] = cs2 * (T(0.5) * (T(3) * d[2] - T(4) * d[1] + d[0]));
+  o.g[1] = T(0.5) * (T(3) * uu[2] - T(4) * uu[1] + uu[0]);
+  o.g[2] = T(0.5) * (T(3) * vv[2] - T(4) * vv[1] + vv[0]);
+  o.g[3] = cs2 * (T(0.5) * (dn - ds));
+  o.g[4] = T(0.5) * (un - us);
+  o.g[5] = T(0.5) * (vn - vs);
+  return o;
+}
+
+// The isothermal LODI update (Eqs. 18-26, L_1 of Eqs. 27-28, T_1,exact = 0).
+template <typename T>
+struct Lodi {
+  T rho, p, L1, L3, L5, T1, T3, T5, rho_t, u_t, v_t;
+};
+
+template <typename T>
+__device__ Lodi<T> lodi(const OutIn<T>& in, T sigma, T kappa2, const CtState* st) {
+  const T cs2 = T(1.0 / 3.0), cs = T(0.57735026918962576451);
+  const T px = in.g[0], ux = in.g[1], vx = in.g[2], py = in.g[3], uy = in.g[4], vy = in.g[5];
+  const T u = in.u, v = in.v;
+  Lodi<T> l;
+  l.rho = T(1) + in.drho;
+  l.p = cs2 * l.rho;
+  l.L3 = u * vx;
+  l.L5 = (u + cs) * (px + l.rho * cs * ux);
+  l.T1 = -(v * py + l.p * vy - l.rho * cs * v * uy);
+  l.T3 = -(v * vy + py / l.rho);
+  l.T5 = -(v * py + l.p * vy + l.rho * cs * v * uy);
+  l.L1 = sigma * T(st->kappa1_coef) * cs2 * (in.drho - T(st->rho_inf_m1)) - kappa2 * l.T1 + l.T1;
+  l.rho_t = (-(l.L5 + l.L1) + (l.T5 + l.T1)) / (T(2) * cs2);
+  l.u_t = (-(l.L5 - l.L1) + (l.T5 - l.T1)) / (T(2) * l.rho * cs);
+  l.v_t = -l.L3 + l.T3;
+  return l;
+}
+
+// ---- forward -------------------------------------------------------------------------
+template <typename T>
+__global__ void __launch_bounds__(kRows) k_fwd_outlet(const CtArgs<T> a, int k) {
+  const int s = blockIdx.y;
+  if (k >= a.nts[s]) return;
+  const int r = blockIdx.x * kRows + threadIdx.x;
+  if (r >= a.ny) return;
+  const CtState* st = a.st;
+  const T* A = state_at(a, s, k);
+  const OutIn<T> in = outlet_inputs(A, a.plane, a.W, a.ny, r);
+  const T* P = a.dts + ((int64_t(s) * (a.n_max + 1) + k) * a.ny + r) * 3;
+  T z[kIn];
+#pragma unroll
+  for (int i = 0; i < kIn; ++i) {
+    const T f = i < 6 ? in.g[i] : P[i - 6];
+    z[i] = (f - T(st->mu[i])) / T(st->sd[i]);
+  }
+  const T sl = T(st->leaky);
+  T h1[kH];
+#pragma unroll
+  for (int o = 0; o < kH; ++o) {
+    T acc = T(st->w[kOB1 + o]);
+#pragma unroll
+    for (int i = 0; i < kIn; ++i) acc += T(st->w[kOW1 + o * kIn + i]) * z[i];
+    h1[o] = leaky(acc, sl);
+  }
+  T s0 = T(st->w[kOB3]), s1 = T(st->w[kOB3 + 1]);
+#pragma unroll 1
+  for (int o = 0; o < kH; ++o) {
+    T acc = T(st->w[kOB2 + o]);
+#pragma unroll
+    for (int m = 0; m < kH; ++m) acc += T(st->w[kOW2 + o * kH + m]) * h1[m];
+    const T h = leaky(acc, sl);
+    s0 += T(st->w[kOW3 + o]) * h;
+    s1 += T(st->w[kOW3 + kH + o]) * h;
+  }
+  const T sigma = T(st->sig_scale) * sigmoid(s0) + T(st->sig_shift);
+  const T kappa2 = T(st->kap_scale) * sigmoid(s1) + T(st->kap_shift);
+  const Lodi<T> l = lodi(in, sigma, kappa2, st);
+  T* o = a.outs + ((int64_t(s) * a.n_max + k) * a.ny + r) * 3;
+  o[0] = in.drho + l.rho_t;                 // forward Euler
+  o[1] = in.u + l.u_t;
+  o[2] = in.v + l.v_t;
+  T* Pn = a.dts + ((int64_t(s) * (a.n_max + 1) + k + 1) * a.ny + r) * 3;
+  Pn[0] = T(1.0 / 3.0) * l.rho_t;
+  Pn[1] = l.u_t;
+  Pn[2] = l.v_t;
+}
+
+template <typename T>
+__device__ __forceinline__ void pre_collision(const CtArgs<T>& a, int s, int k, int x, int y,
+                                              T g[9]) {
+  pull(state_at(a, s, k), a.plane, a.W, a.ny, x, y, g);
+  if (x == a.W - 1) {
+    const T* o = a.outs + ((int64_t(s) * a.n_max + k) * a.ny + y) * 3;
+    outlet_state(g, o[0], o[1], o[2]);      // Eq. 29, Eqs. 8-10
+  }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kNodes) k_fwd_node(const CtArgs<T> a, int k) {
+  const int s = blockIdx.y;
+  if (k >= a.nts[s]) return;
+  const int64_t n = int64_t(blockIdx.x) * kNodes + threadIdx.x;
+  if (n >= a.plane) return;
+  const int y = int(n / a.W), x = int(n - int64_t(y) * a.W);
+  T g[9];
+  pre_collision(a, s, k, x, y, g);
+  collide_bgk(g, a.omega);
+  T* B = state_at(a, s, k + 1);
+#pragma unroll
+  for (int q = 0; q < 9; ++q) B[q * a.plane + n] = g[q];
+}
+
+// ---- loss and the adjoint's initial value ------------------------------------------------
+__device__ __forceinline__ double block_sum(double v, double* sh) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o);
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) sh[w] = v;
+  __syncthreads();
+  double t = 0.0;
+  if (threadIdx.x == 0)
+    for (int i = 0; i < int(blockDim.x >> 6); ++i) t += sh[i];
+  return t;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kNodes) k_seed(const CtArgs<T> a) {
+  __shared__ double sh[kNodes / 64];
+  const int s = blockIdx.y;
+  const int nt = a.nts[s];
+  const int64_t n = int64_t(blockIdx.x) * kNodes + threadIdx.x;
+  double contrib = 0.0;
+  if (n < a.plane) {
+    const int y = int(n / a.W), x = int(n - int64_t(y) * a.W);
+    T lam[9];
+#pragma unroll
+    for (int q = 0; q < 9; ++q) lam[q] = T(0);
+    if (x >= a.W - nt) {
+      const T* A = state_at(a, s, nt);
+      T drho, u, v;
+      node_state(A, a.plane, n, drho, u, v);
+      const int e = x - (a.W - a.n_max);                  // reference entry of column x
+      const T* R = a.ref + (int64_t(s) * 3 * a.ny + y) * a.n_max + e;
+      const int64_t cstride = int64_t(a.ny) * a.n_max;
+      const T er = drho - R[0], eu = u - R[cstride], ev = v - R[2 * cstride];
+      const double c = a.seg_scale / (double(nt) * double(a.ny));
+      contrib = c * (double(er) * double(er) + double(eu) * double(eu) + double(ev) * double(ev));
+      const T c2 = T(2.0 * c), inv = T(1) / (T(1) + drho);
+#pragma unroll
+      for (int q = 0; q < 9; ++q)
+        lam[q] = c2 * (er + (eu * (T(cx(q)) - u) + ev * (T(cy(q)) - v)) * inv);
+    }
+    T* L = a.lamA + int64_t(s) * 9 * a.plane;
+#pragma unroll
+    for (int q = 0; q < 9; ++q) L[q * a.plane + n] = lam[q];
+    if (n < int64_t(a.ny) * 3) a.lamP[int64_t(s) * a.ny * 3 + n] = T(0);
+  }
+  const double t = block_sum(contrib, sh);
+  if (threadIdx.x == 0) a.lslot[int64_t(s) * a.nlb + blockIdx.x] = t;
+}
+
+// ---- backward --------------------------------------------------------------------------
+// BGK: A = f - omega (f - f^eq(rho, j)), so with
+//   d f_i^eq / d rho = w_i (1 - 9/2 (c_i.u)^2 + 3/2 u.u),
+//   d f_i^eq / d j   = w_i (3 c_i + 9 (c_i.u) c_i - 3 u),
+// lam_f_j = (1 - omega) lam_j + omega (Lambda_rho + c_j . Lambda_j), Lambda the
+// lam-weighted sums of those derivatives.
+template <typename T>
+__global__ void __launch_bounds__(kNodes) k_bwd_node(const CtArgs<T> a, int k) {
+  const int s = blockIdx.y;
+  if (k >= a.nts[s]) return;
+  const int64_t n = int64_t(blockIdx.x) * kNodes + threadIdx.x;
+  if (n >= a.plane) return;
+  const int y = int(n / a.W), x = int(n - int64_t(y) * a.W);
+  T g[9];
+  pre_collision(a, s, k, x, y, g);
+  const Macro<T> m = macro(g);
+  const T u = m.jx / m.rho, v = m.jy / m.rho;
+  const T usq = T(1.5) * (u * u + v * v);
+  const T* LA = a.lamA + int64_t(s) * 9 * a.plane;
+  T lam[9];
+#pragma unroll
+  for (int q = 0; q < 9; ++q) lam[q] = LA[q * a.plane + n];
+  T Lr = T(0), Ljx = T(0), Ljy = T(0);
+#pragma unroll
+  for (int q = 0; q < 9; ++q) {
+    const T cu = T(cx(q)) * u + T(cy(q)) * v;
+    const T wl = wgt<T>(q) * lam[q];
+    Lr += wl * (T(1) - T(4.5) * cu * cu + usq);
+    Ljx += wl * (T(3 * cx(q)) + T(9) * cu * T(cx(q)) - T(3) * u);
+    Ljy += wl * (T(3 * cy(q)) + T(9) * cu * T(cy(q)) - T(3) * v);
+  }
+  T* LF = a.lamF + int64_t(s) * 9 * a.plane;
+  const T om = a.omega;
+#pragma unroll
+  for (int q = 0; q < 9; ++q)
+    LF[q * a.plane + n] = (T(1) - om) * lam[q] + om * (Lr + T(cx(q)) * Ljx + T(cy(q)) * Ljy);
+}
+
+template <typename T>
+struct alignas(16) BwdSmem {
+  T z[kRows][kIn];
+  T h1[kRows][kH];
+  T h2[kRows][kH];
+  T d1[kRows][kH];    // adjoint of the first pre-activation
+  T d2[kRows][kH];    // adjoint of the second pre-activation
+  T ds[kRows][2];     // adjoint of s_0, s_1
+};
+
+template <typename T>
+__global__ void __launch_bounds__(kRows) k_bwd_outlet(const CtArgs<T> a, int k) {
+  __shared__ BwdSmem<T> sm;
+  const int s = blockIdx.y;
+  if (k >= a.nts[s]) return;                     // uniform over the workgroup
+  const int j = threadIdx.x;
+  const int r = blockIdx.x * kRows + j;
+  const CtState* st = a.st;
+  const T cs2 = T(1.0 / 3.0), cs = T(0.57735026918962576451);
+  if (r < a.ny) {
+    // recompute the forward of this row
+    const T* A = state_at(a, s, k);
+    const OutIn<T> in = outlet_inputs(A, a.plane, a.W, a.ny, r);
+    const T* P = a.dts + ((int64_t(s) * (a.n_max + 1) + k) * a.ny + r) * 3;
+    T z[kIn];
+#pragma unroll
+    for (int i = 0; i < kIn; ++i) {
+      const T f = i < 6 ? in.g[i] : P[i - 6];
+      z[i] = (f - T(st->mu[i])) / T(st->sd[i]);
+      sm.z[j][i] = z[i];
+    }
+    const T sl = T(st->leaky);
+    // activations and LeakyReLU slopes live in LDS (the slopes are scaled
+    // into adjoints below), which keeps the FP64 variant within registers
+#pragma unroll 1
+    for (int o = 0; o < kH; ++o) {
+      T acc = T(st->w[kOB1 + o]);
+#pragma unroll
+      for (int i = 0; i < kIn; ++i) acc += T(st->w[kOW1 + o * kIn + i]) * z[i];
+      sm.h1[j][o] = leaky(acc, sl);
+      sm.d1[j][o] = acc > T(0) ? T(1) : sl;
+    }
+    T s0 = T(st->w[kOB3]), s1 = T(st->w[kOB3 + 1]);
+#pragma unroll 1
+    for (int o = 0; o < kH; ++o) {
+      T acc = T(st->w[kOB2 + o]);
+#pragma unroll 4
+      for (int m = 0; m < kH; ++m) acc += T(st->w[kOW2 + o * kH + m]) * sm.h1[j][m];
+      const T h = leaky(acc, sl);
+      sm.h2[j][o] = h;
+      sm.d2[j][o] = acc > T(0) ? T(1) : sl;     // slope, scaled below
+      s0 += T(st->w[kOW3 + o]) * h;
+      s1 += T(st->w[kOW3 + kH + o]) * h;
+    }
+    const T sg0 = sigmoid(s0), sg1 = sigmoid(s1);
+    const T sigma = T(st->sig_scale) * sg0 + T(st->sig_shift);
+    const T kappa2 = T(st->kap_scale) * sg1 + T(st->kap_shift);
+    const Lodi<T> l = lodi(in, sigma, kappa2, st);
+    const T* o3 = a.outs + ((int64_t(s) * a.n_max + k) * a.ny + r) * 3;
+    const T d1 = o3[0], u1 = o3[1], v1 = o3[2], rho1 = T(1) + d1;
+
+    // outlet reconstruction (offset form: g0 = drho' (1 + u') + u' - (g2 + g4)
+    // - 2 (g1 + g5 + g8), g3 = g1 - 2/3 rho' u', g6 = g8 + (g4 - g2)/2 - rho' u'/6
+    // + rho' v'/2, g7 = g5 - (g4 - g2)/2 - rho' u'/6 - rho' v'/2)
+    T* LF = a.lamF + int64_t(s) * 9 * a.plane;
+    const int64_t on = int64_t(r) * a.W + a.W - 1;
+    T lf[9];
+#pragma unroll
+    for (int q = 0; q < 9; ++q) lf[q] = LF[q * a.plane + on];
+    const T ld1 = lf[0] * (T(1) + u1) - lf[3] * T(2.0 / 3.0) * u1 +
+                  lf[6] * (-u1 / T(6) + T(0.5) * v1) + lf[7] * (-u1 / T(6) - T(0.5) * v1);
+    const T lu1 = rho1 * (lf[0] - T(2.0 / 3.0) * lf[3] - lf[6] / T(6) - lf[7] / T(6));
+    const T lv1 = rho1 * T(0.5) * (lf[6] - lf[7]);
+    LF[0 * a.plane + on] = T(0);
+    LF[1 * a.plane + on] = lf[1] - T(2) * lf[0] + lf[3];
+    LF[2 * a.plane + on] = lf[2] - lf[0] - T(0.5) * lf[6] + T(0.5) * lf[7];
+    LF[3 * a.plane + on] = T(0);
+    LF[4 * a.plane + on] = lf[4] - lf[0] + T(0.5) * lf[6] - T(0.5) * lf[7];
+    LF[5 * a.plane + on] = lf[5] - T(2) * lf[0] + lf[7];
+    LF[6 * a.plane + on] = T(0);
+    LF[7 * a.plane + on] = T(0);
+    LF[8 * a.plane + on] = lf[8] - T(2) * lf[0] + lf[6];
+
+    // forward Euler and the stored time derivatives
+    T* LP = a.lamP + (int64_t(s) * a.ny + r) * 3;
+    const T lrt = ld1 + cs2 * LP[0], lut = lu1 + LP[1], lvt = lv1 + LP[2];
+    T ldr = ld1, lu = lu1, lv = lv1;             // centre state
+    T lg[6] = {T(0), T(0), T(0), T(0), T(0), T(0)};
+
+    // LODI (Eqs. 18-28)
+    const T rho = l.rho, u = in.u, v = in.v;
+    const T px = in.g[0], ux = in.g[1], vx = in.g[2], py = in.g[3], uy = in.g[4], vy = in.g[5];
+    const T ia = T(1) / (T(2) * cs2), ib = T(1) / (T(2) * rho * cs);
+    const T lL5 = -ia * lrt - ib * lut;
+    const T lL1 = -ia * lrt + ib * lut;
+    const T lT5 = ia * lrt + ib * lut;
+    T lT1 = ia * lrt - ib * lut;
+    ldr += -(l.u_t / rho) * lut;
+    const T lL3 = -lvt, lT3 = lvt;
+    const T k1c = T(st->kappa1_coef);
+    const T lsig = lL1 * k1c * cs2 * (in.drho - T(st->rho_inf_m1));
+    ldr += lL1 * sigma * k1c * cs2;
+    const T lkap = -lL1 * l.T1;
+    lT1 += (T(1) - kappa2) * lL1;
+    // L_3 = u v_x
+    lu += lL3 * vx;
+    lg[2] += lL3 * u;
+    // L_5 = (u + c_s)(p_x + rho c_s u_x)
+    lu += lL5 * (px + rho * cs * ux);
+    lg[0] += lL5 * (u + cs);
+    ldr += lL5 * (u + cs) * cs * ux;
+    lg[1] += lL5 * (u + cs) * rho * cs;
+    // T_1 = -(v p_y + p v_y - rho c_s v u_y)
+    lv += lT1 * (-py + rho * cs * uy);
+    lg[3] += -lT1 * v;
+    ldr += lT1 * (-cs2 * vy + cs * v * uy);
+    lg[5] += -lT1 * l.p;
+    lg[4] += lT1 * rho * cs * v;
+    // T_5 = -(v p_y + p v_y + rho c_s v u_y)
+    lv += lT5 * (-py - rho * cs * uy);
+    lg[3] += -lT5 * v;
+    ldr += lT5 * (-cs2 * vy - cs * v * uy);
+    lg[5] += -lT5 * l.p;
+    lg[4] += -lT5 * rho * cs * v;
+    // T_3 = -(v v_y + p_y / rho)
+    lv += -lT3 * vy;
+    lg[5] += -lT3 * v;
+    lg[3] += -lT3 / rho;
+    ldr += lT3 * py / (rho * rho);
+
+    // network: output maps, then the two hidden layers
+    const T ds0 = lsig * T(st->sig_scale) * sg0 * (T(1) - sg0);
+    const T ds1 = lkap * T(st->kap_scale) * sg1 * (T(1) - sg1);
+    sm.ds[j][0] = ds0;
+    sm.ds[j][1] = ds1;
+#pragma unroll
+    for (int o = 0; o < kH; ++o)
+      sm.d2[j][o] *= T(st->w[kOW3 + o]) * ds0 + T(st->w[kOW3 + kH + o]) * ds1;
+    T lz[kIn];
+#pragma unroll
+    for (int i = 0; i < kIn; ++i) lz[i] = T(0);
+#pragma unroll 1
+    for (int m = 0; m < kH; ++m) {
+      T acc = T(0);
+#pragma unroll
+      for (int o = 0; o < kH; ++o) acc += T(st->w[kOW2 + o * kH + m]) * sm.d2[j][o];
+      const T d = acc * sm.d1[j][m];
+      sm.d1[j][m] = d;
+#pragma unroll
+      for (int i = 0; i < kIn; ++i) lz[i] += T(st->w[kOW1 + m * kIn + i]) * d;
+    }
+#pragma unroll
+    for (int i = 0; i < 6; ++i) lg[i] += lz[i] / T(st->sd[i]);
+#pragma unroll
+    for (int i = 0; i < 3; ++i) LP[i] = lz[6 + i] / T(st->sd[6 + i]);
+
+    // gradients -> moments of the three columns
+    T* M = a.madj + (int64_t(s) * a.ny + r) * kMadj;
+    M[0] = T(0.5) * cs2 * lg[0];
+    M[1] = T(0.5) * lg[1];
+    M[2] = T(0.5) * lg[2];
+    M[3] = T(-2) * cs2 * lg[0];
+    M[4] = T(-2) * lg[1];
+    M[5] = T(-2) * lg[2];
+    M[6] = ldr + T(1.5) * cs2 * lg[0];
+    M[7] = lu + T(1.5) * lg[1];
+    M[8] = lv + T(1.5) * lg[2];
+    M[9] = T(0.5) * cs2 * lg[3];
+    M[10] = T(0.5) * lg[4];
+    M[11] = T(0.5) * lg[5];
+  } else {
+#pragma unroll
+    for (int i = 0; i < kIn; ++i) sm.z[j][i] = T(0);
+#pragma unroll
+    for (int o = 0; o < kH; ++o) sm.h1[j][o] = sm.h2[j][o] = sm.d1[j][o] = sm.d2[j][o] = T(0);
+    sm.ds[j][0] = sm.ds[j][1] = T(0);
+  }
+  __syncthreads();
+  // parameter gradient of the workgroup's rows, added to its slot
+  double* G = a.gslot + (int64_t(s) * a.nrb + blockIdx.x) * kNP;
+  for (int p = j; p < kNP; p += kRows) {
+    double acc = 0.0;
+    if (p < kOB1) {
+      const int m = p / kIn, i = p - m * kIn;
+      for (int rr = 0; rr < kRows; ++rr) acc += double(sm.d1[rr][m]) * double(sm.z[rr][i]);
+    } else if (p < kOW2) {
+      const int m = p - kOB1;
+      for (int rr = 0; rr < kRows; ++rr) acc += double(sm.d1[rr][m]);
+    } else if (p < kOB2) {
+      const int o = (p - kOW2) / kH, m = (p - kOW2) - o * kH;
+      for (int rr = 0; rr < kRows; ++rr) acc += double(sm.d2[rr][o]) * double(sm.h1[rr][m]);
+    } else if (p < kOW3) {
+      const int o = p - kOB2;
+      for (int rr = 0; rr < kRows; ++rr) acc += double(sm.d2[rr][o]);
+    } else if (p < kOB3) {
+      const int o = (p - kOW3) / kH, m = (p - kOW3) - o * kH;
+      for (int rr = 0; rr < kRows; ++rr) acc += double(sm.ds[rr][o]) * double(sm.h2[rr][m]);
+    } else {
+      const int o = p - kOB3;
+      for (int rr = 0; rr < kRows; ++rr) acc += double(sm.ds[rr][o]);
+    }
+    G[p] += acc;
+  }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kNodes) k_bwd_gather(const CtArgs<T> a, int k) {
+  const int s = blockIdx.y;
+  if (k >= a.nts[s]) return;
+  const int64_t n = int64_t(blockIdx.x) * kNodes + threadIdx.x;
+  if (n >= a.plane) return;
+  const int y = int(n / a.W), x = int(n - int64_t(y) * a.W);
+  const T* LF = a.lamF + int64_t(s) * 9 * a.plane;
+  T lam[9];
+#pragma unroll
+  for (int q = 0; q < 9; ++q) {
+    const int dx = x + cx(q);
+    const int dy = wrap(y + cy(q), a.ny);
+    T l = T(0);
+    if (dx >= 0 && dx <= a.W - 1) l = LF[q * a.plane + int64_t(dy) * a.W + dx];
+    if (x == 0 && cx(q) == 1) l += LF[q * a.plane + int64_t(dy) * a.W];   // edge copies
+    lam[q] = l;
+  }
+  if (x >= a.W - 3) {
+    const int c = x - (a.W - 3);
+    const T* M = a.madj + (int64_t(s) * a.ny + y) * kMadj;
+    T ld = M[3 * c], lu = M[3 * c + 1], lv = M[3 * c + 2];
+    if (c == 2) {
+      const T* Ms = a.madj + (int64_t(s) * a.ny + wrap(y - 1, a.ny)) * kMadj;   // row y = r + 1
+      const T* Mn = a.madj + (int64_t(s) * a.ny + wrap(y + 1, a.ny)) * kMadj;   // row y = r - 1
+      ld += Ms[9] - Mn[9];
+      lu += Ms[10] - Mn[10];
+      lv += Ms[11] - Mn[11];
+    }
+    T drho, u, v;
+    node_state(state_at(a, s, k), a.plane, n, drho, u, v);
+    const T inv = T(1) / (T(1) + drho);
+#pragma unroll
+    for (int q = 0; q < 9; ++q) lam[q] += ld + (lu * (T(cx(q)) - u) + lv * (T(cy(q)) - v)) * inv;
+  }
+  T* LA = a.lamA + int64_t(s) * 9 * a.plane;
+#pragma unroll
+  for (int q = 0; q < 9; ++q) LA[q * a.plane + n] = lam[q];
+}
+
+__global__ void k_zero(double* p, int64_t n) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0.0;
+}
+
+// FP64 sum of the gradient slots (segment-major, then row block) and of the
+// loss slots; Adam with bias correction when `update`.
+__global__ void __launch_bounds__(kNodes) k_update(CtState* st, const double* gslot, int64_t nslots,
+                                                  const double* lslot, int64_t nl, int update,
+                                                  double lr, double b1, double b2, double eps,
+                                                  double bc1, double bc2) {
+  const int p = blockIdx.x * kNodes + threadIdx.x;
+  if (p == 0) {
+    double t = 0.0;
+    for (int64_t i = 0; i < nl; ++i) t += lslot[i];
+    st->loss = t;
+  }
+  if (p >= kNP) return;
+  double g = 0.0;
+  for (int64_t i = 0; i < nslots; ++i) g += gslot[i * kNP + p];
+  st->grad[p] = g;
+  if (update) {
+    const double m = b1 * st->m[p] + (1.0 - b1) * g;
+    const double v = b2 * st->v[p] + (1.0 - b2) * g * g;
+    st->m[p] = m;
+    st->v[p] = v;
+    st->w[p] = float(double(st->w[p]) - lr * (m / bc1) / (sqrt(v / bc2) + eps));
+  }
+}
+
+// ---- host side ---------------------------------------------------------------------------
+size_t align256(size_t b) { return (b + 255) / 256 * 256; }
+
+struct CtLayout {
+  size_t st, traj, outs, dts, lamA, lamF, lamP, madj, ref, nts, gslot, lslot, total;
+  int W, nrb, nlb;
+  int64_t plane;
+};
+
+size_t elem(int precision) { return precision == LBM_FP64 ? 8 : 4; }
+
+CtLayout ct_layout(const lbm_cbc_train_params& p) {
+  CtLayout L;
+  L.W = 2 * p.n_max + 3;
+  L.plane = int64_t(p.ny) * L.W;
+  L.nrb = (p.ny + kRows - 1) / kRows;
+  L.nlb = int((L.plane + kNodes - 1) / kNodes);
+  const size_t e = elem(p.precision), ns = size_t(p.n_seg), ny = size_t(p.ny);
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    const size_t at = o;
+    o += align256(bytes);
+    return at;
+  };
+  L.st = take(sizeof(CtState));
+  L.traj = take(ns * (p.n_max + 1) * 9 * size_t(L.plane) * e);
+  L.outs = take(ns * p.n_max * ny * 3 * e);
+  L.dts = take(ns * (p.n_max + 1) * ny * 3 * e);
+  L.lamA = take(ns * 9 * size_t(L.plane) * e);
+  L.lamF = take(ns * 9 * size_t(L.plane) * e);
+  L.lamP = take(ns * ny * 3 * e);
+  L.madj = take(ns * ny * kMadj * e);
+  L.ref = take(ns * 3 * ny * p.n_max * e);
+  L.nts = take(ns * sizeof(int));
+  L.gslot = take(ns * L.nrb * kNP * sizeof(double));
+  L.lslot = take(ns * L.nlb * sizeof(double));
+  L.total = o;
+  return L;
+}
+
+lbm_status check_params(const lbm_cbc_train_params* p) {
+  if (!p) return set_error(LBM_EINVAL, "params is NULL");
+  if (p->ny < 3) return set_error(LBM_EINVAL, "ny must be >= 3");
+  if (p->n_max < 1 || p->n_max > kMaxSteps) return set_error(LBM_EINVAL, "n_max must be in 1..%d", kMaxSteps);
+  if (p->n_seg < 1 || p->n_seg > 65535) return set_error(LBM_EINVAL, "n_seg must be in 1..65535");
+  if (p->precision != LBM_FP64 && p->precision != LBM_FP32_OFFSET)
+    return set_error(LBM_EINVAL, "precision must be LBM_FP64 or LBM_FP32_OFFSET");
+  if (!(p->tau > 0.5) || !std::isfinite(p->tau)) return set_error(LBM_EINVAL, "tau must be > 1/2");
+  if (!(p->mach >= 0.0 && p->mach < 1.0)) return set_error(LBM_EINVAL, "mach must be in [0, 1)");
+  if (!(p->length > 0.0) || !std::isfinite(p->length)) return set_error(LBM_EINVAL, "length must be > 0");
+  if (!(p->rho_inf > 0.0) || !std::isfinite(p->rho_inf)) return set_error(LBM_EINVAL, "rho_inf must be > 0");
+  if (!(p->lr > 0.0) || !(p->beta1 >= 0.0 && p->beta1 < 1.0) || !(p->beta2 >= 0.0 && p->beta2 < 1.0) ||
+      !(p->eps > 0.0))
+    return set_error(LBM_EINVAL, "Adam needs lr > 0, 0 <= beta < 1, eps > 0");
+  if (int64_t(p->ny) * (2 * p->n_max + 3) >= (int64_t(1) << 31) / 9)
+    return set_error(LBM_EINVAL, "strip too large");
+  return LBM_OK;
+}
+
+#define CT_TRY(expr)                                                                       \
+  do {                                                                                     \
+    hipError_t e_ = (expr);                                                                \
+    if (e_ != hipSuccess) return set_error(LBM_EHIP, "%s: %s", #expr, hipGetErrorString(e_)); \
+  } while (0)
+
+}  // namespace
+}  // namespace lbm
+
+using namespace lbm;
+
+struct lbm_cbc_trainer {
+  lbm_cbc_train_params p;
+  hipStream_t stream;
+  CtLayout L;
+  char* base;
+  CtState* st;
+  std::vector<int> nts;
+  bool has_data = false, has_net = false;
+  int64_t adam_t = 0;
+
+  template <typename T>
+  CtArgs<T> args() const {
+    CtArgs<T> a;
+    a.traj = reinterpret_cast<T*>(base + L.traj);
+    a.outs = reinterpret_cast<T*>(base + L.outs);
+    a.dts = reinterpret_cast<T*>(base + L.dts);
+    a.lamA = reinterpret_cast<T*>(base + L.lamA);
+    a.lamF = reinterpret_cast<T*>(base + L.lamF);
+    a.lamP = reinterpret_cast<T*>(base + L.lamP);
+    a.madj = reinterpret_cast<T*>(base + L.madj);
+    a.ref = reinterpret_cast<const T*>(base + L.ref);
+    a.nts = reinterpret_cast<const int*>(base + L.nts);
+    a.gslot = reinterpret_cast<double*>(base + L.gslot);
+    a.lslot = reinterpret_cast<double*>(base + L.lslot);
+    a.st = st;
+    a.ny = p.ny;
+    a.W = L.W;
+    a.n_max = p.n_max;
+    a.nrb = L.nrb;
+    a.nlb = L.nlb;
+    a.plane = L.plane;
+    a.omega = T(1.0 / p.tau);
+    a.seg_scale = 1.0 / double(p.n_seg);
+    return a;
+  }
+
+  template <typename T>
+  lbm_status run_t(bool update) {
+    const CtArgs<T> a = args<T>();
+    const dim3 grow(L.nrb, p.n_seg), gnode(L.nlb, p.n_seg);
+    for (int k = 0; k < p.n_max; ++k) {
+      hipLaunchKernelGGL(k_fwd_outlet<T>, grow, dim3(kRows), 0, stream, a, k);
+      hipLaunchKernelGGL(k_fwd_node<T>, gnode, dim3(kNodes), 0, stream, a, k);
+    }
+    const int64_t ng = int64_t(p.n_seg) * L.nrb * kNP;
+    hipLaunchKernelGGL(k_zero, dim3(unsigned((ng + kNodes - 1) / kNodes)), dim3(kNodes), 0, stream,
+                       a.gslot, ng);
+    hipLaunchKernelGGL(k_seed<T>, gnode, dim3(kNodes), 0, stream, a);
+    for (int k = p.n_max - 1; k >= 0; --k) {
+      hipLaunchKernelGGL(k_bwd_node<T>, gnode, dim3(kNodes), 0, stream, a, k);
+      hipLaunchKernelGGL(k_bwd_outlet<T>, grow, dim3(kRows), 0, stream, a, k);
+      hipLaunchKernelGGL(k_bwd_gather<T>, gnode, dim3(kNodes), 0, stream, a, k);
+    }
+    double bc1 = 1.0, bc2 = 1.0;
+    if (update) {
+      bc1 = 1.0 - std::pow(p.beta1, double(adam_t));
+      bc2 = 1.0 - std::pow(p.beta2, double(adam_t));
+    }
+    hipLaunchKernelGGL(k_update, dim3((kNP + kNodes - 1) / kNodes), dim3(kNodes), 0, stream, st,
+                       a.gslot, int64_t(p.n_seg) * L.nrb, a.lslot, int64_t(p.n_seg) * L.nlb,
+                       update ? 1 : 0, p.lr, p.beta1, p.beta2, p.eps, bc1, bc2);
+    CT_TRY(hipGetLastError());
+    return LBM_OK;
+  }
+
+  lbm_status run(bool update) {
+    if (!has_data || !has_net) return set_error(LBM_ESTATE, "segments and network must be set first");
+    return p.precision == LBM_FP64 ? run_t<double>(update) : run_t<float>(update);
+  }
+};
+
+extern "C" {
+
+size_t lbm_cbc_train_workspace_bytes(const lbm_cbc_train_params* p) {
+  if (check_params(p)) return 0;
+  return ct_layout(*p).total;
+}
+
+lbm_status lbm_cbc_train_create(const lbm_cbc_train_params* p, void* ws, size_t bytes,
+                                lbm_cbc_trainer** out) {
+  if (!out) return set_error(LBM_EINVAL, "out is NULL");
+  *out = nullptr;
+  lbm_status s = check_params(p);
+  if (s) return s;
+  if (!ws || reinterpret_cast<uintptr_t>(ws) % 256)
+    return set_error(LBM_EINVAL, "workspace must be non-NULL and 256-byte aligned");
+  const CtLayout L = ct_layout(*p);
+  if (bytes < L.total) return set_error(LBM_ENOSPACE, "workspace has %zu bytes, needs %zu", bytes, L.total);
+  lbm_cbc_trainer* t = new lbm_cbc_trainer();
+  t->p = *p;
+  t->stream = static_cast<hipStream_t>(p->stream);
+  t->L = L;
+  t->base = static_cast<char*>(ws);
+  t->st = reinterpret_cast<CtState*>(t->base + L.st);
+  *out = t;
+  return LBM_OK;
+}
+
+lbm_status lbm_cbc_train_destroy(lbm_cbc_trainer* t) {
+  delete t;
+  return LBM_OK;
+}
+
+lbm_status lbm_cbc_train_set_segments(lbm_cbc_trainer* t, const double* a0, const double* ref,
+                                      const int32_t* n_t) {
+  if (!t || !a0 || !ref || !n_t) return set_error(LBM_EINVAL, "NULL argument");
+  const lbm_cbc_train_params& p = t->p;
+  const CtLayout& L = t->L;
+  for (int s = 0; s < p.n_seg; ++s)
+    if (n_t[s] < 1 || n_t[s] > p.n_max) return set_error(LBM_EINVAL, "n_t[%d] = %d outside 1..%d", s, n_t[s], p.n_max);
+  const size_t seg_vals = size_t(9) * size_t(L.plane);
+  const size_t ref_vals = size_t(3) * size_t(p.ny) * size_t(p.n_max);
+  for (size_t i = 0; i < seg_vals * size_t(p.n_seg); ++i)
+    if (!std::isfinite(a0[i])) return set_error(LBM_EINVAL, "a0 holds a non-finite value");
+  const bool f64 = p.precision == LBM_FP64;
+  const size_t e = elem(p.precision);
+  std::vector<char> h(seg_vals * size_t(p.n_seg) * e);
+  std::vector<char> hr(ref_vals * size_t(p.n_seg) * e);
+  for (size_t i = 0; i < seg_vals * size_t(p.n_seg); ++i) {
+    const int q = int((i / size_t(L.plane)) % 9);
+    const double g = a0[i] - (q == 0 ? 4.0 / 9.0 : (q <= 4 ? 1.0 / 9.0 : 1.0 / 36.0));
+    if (f64) reinterpret_cast<double*>(h.data())[i] = g;
+    else reinterpret_cast<float*>(h.data())[i] = float(g);
+  }
+  for (size_t i = 0; i < ref_vals * size_t(p.n_seg); ++i) {
+    const int c = int((i / (size_t(p.ny) * size_t(p.n_max))) % 3);
+    const double v = c == 0 ? ref[i] - 1.0 : ref[i];      // density as rho - 1
+    if (f64) reinterpret_cast<double*>(hr.data())[i] = v;
+    else reinterpret_cast<float*>(hr.data())[i] = float(v);
+  }
+  CT_TRY(hipMemcpy2DAsync(t->base + L.traj, size_t(p.n_max + 1) * seg_vals * e, h.data(), seg_vals * e,
+                          seg_vals * e, size_t(p.n_seg), hipMemcpyHostToDevice, t->stream));
+  CT_TRY(hipMemcpyAsync(t->base + L.ref, hr.data(), hr.size(), hipMemcpyHostToDevice, t->stream));
+  t->nts.assign(n_t, n_t + p.n_seg);
+  CT_TRY(hipMemcpyAsync(t->base + L.nts, t->nts.data(), t->nts.size() * sizeof(int),
+                        hipMemcpyHostToDevice, t->stream));
+  CT_TRY(hipMemsetAsync(t->base + L.dts, 0, size_t(p.n_seg) * (p.n_max + 1) * p.ny * 3 * e, t->stream));
+  CT_TRY(hipStreamSynchronize(t->stream));
+  t->has_data = true;
+  return LBM_OK;
+}
+
+lbm_status lbm_cbc_train_set_net(lbm_cbc_trainer* t, const lbm_cbc_net* n) {
+  if (!t || !n || !n->w1 || !n->b1 || !n->w2 || !n->b2 || !n->w3 || !n->b3 || !n->mu_in || !n->sd_in)
+    return set_error(LBM_EINVAL, "NULL argument");
+  std::vector<char> buf(sizeof(CtState), 0);
+  CtState* h = reinterpret_cast<CtState*>(buf.data());
+  memcpy(h->w + kOW1, n->w1, kH * kIn * 4);
+  memcpy(h->w + kOB1, n->b1, kH * 4);
+  memcpy(h->w + kOW2, n->w2, kH * kH * 4);
+  memcpy(h->w + kOB2, n->b2, kH * 4);
+  memcpy(h->w + kOW3, n->w3, 2 * kH * 4);
+  memcpy(h->w + kOB3, n->b3, 2 * 4);
+  for (int i = 0; i < kNP; ++i)
+    if (!std::isfinite(h->w[i])) return set_error(LBM_EINVAL, "non-finite weight %d", i);
+  for (int i = 0; i < kIn; ++i) {
+    if (!std::isfinite(n->mu_in[i]) || !(n->sd_in[i] > 0.0f) || !std::isfinite(n->sd_in[i]))
+      return set_error(LBM_EINVAL, "mu_in must be finite and sd_in > 0");
+    h->mu[i] = n->mu_in[i];
+    h->sd[i] = n->sd_in[i];
+  }
+  const double maps[5] = {n->leaky_slope, n->sigma_scale, n->sigma_shift, n->kappa_scale, n->kappa_shift};
+  for (double v : maps)
+    if (!std::isfinite(v)) return set_error(LBM_EINVAL, "non-finite slope or output map");
+  h->leaky = n->leaky_slope;
+  h->sig_scale = n->sigma_scale;
+  h->sig_shift = n->sigma_shift;
+  h->kap_scale = n->kappa_scale;
+  h->kap_shift = n->kappa_shift;
+  const double cs = 0.57735026918962576451;
+  h->kappa1_coef = (1.0 - t->p.mach * t->p.mach) * cs / t->p.length;
+  h->rho_inf_m1 = t->p.rho_inf - 1.0;
+  CT_TRY(hipMemcpyAsync(t->st, h, sizeof(CtState), hipMemcpyHostToDevice, t->stream));
+  CT_TRY(hipStreamSynchronize(t->stream));
+  t->adam_t = 0;
+  t->has_net = true;
+  return LBM_OK;
+}
+
+lbm_status lbm_cbc_train_gradient(lbm_cbc_trainer* t, double* loss, double* grad) {
+  if (!t) return set_error(LBM_EINVAL, "NULL trainer");
+  lbm_status s = t->run(false);
+  if (s) return s;
+  CT_TRY(hipStreamSynchronize(t->stream));
+  if (loss) CT_TRY(hipMemcpy(loss, &t->st->loss, sizeof(double), hipMemcpyDeviceToHost));
+  if (grad) CT_TRY(hipMemcpy(grad, t->st->grad, kNP * sizeof(double), hipMemcpyDeviceToHost));
+  return LBM_OK;
+}
+
+lbm_status lbm_cbc_train_step(lbm_cbc_trainer* t, int64_t nsteps) {
+  if (!t) return set_error(LBM_EINVAL, "NULL trainer");
+  if (nsteps < 0) return set_error(LBM_EINVAL, "nsteps < 0");
+  for (int64_t i = 0; i < nsteps; ++i) {
+    ++t->adam_t;
+    lbm_status s = t->run(true);
+    if (s) return s;
+  }
+  return LBM_OK;
+}
+
+lbm_status lbm_cbc_train_loss(lbm_cbc_trainer* t, double* loss) {
+  if (!t || !loss) return set_error(LBM_EINVAL, "NULL argument");
+  CT_TRY(hipStreamSynchronize(t->stream));
+  CT_TRY(hipMemcpy(loss, &t->st->loss, sizeof(double), hipMemcpyDeviceToHost));
+  return LBM_OK;
+}
+
+lbm_status lbm_cbc_train_get_weights(lbm_cbc_trainer* t, float* theta) {
+  if (!t || !theta) return set_error(LBM_EINVAL, "NULL argument");
+  CT_TRY(hipStreamSynchronize(t->stream));
+  CT_TRY(hipMemcpy(theta, t->st->w, kNP * sizeof(float), hipMemcpyDeviceToHost));
+  return LBM_OK;
+}
+
+lbm_status lbm_cbc_train_final_state(lbm_cbc_trainer* t, int32_t seg, double* host) {
+  if (!t || !host) return set_error(LBM_EINVAL, "NULL argument");
+  if (!t->has_data) return set_error(LBM_ESTATE, "no segments set");
+  if (seg < 0 || seg >= t->p.n_seg) return set_error(LBM_EINVAL, "seg outside 0..n_seg-1");
+  const CtLayout& L = t->L;
+  const size_t vals = size_t(9) * size_t(L.plane), e = elem(t->p.precision);
+  const size_t off = L.traj + (size_t(seg) * (t->p.n_max + 1) + t->nts[seg]) * vals * e;
+  std::vector<char> h(vals * e);
+  CT_TRY(hipStreamSynchronize(t->stream));
+  CT_TRY(hipMemcpy(h.data(), t->base + off, h.size(), hipMemcpyDeviceToHost));
+  for (size_t i = 0; i < vals; ++i) {
+    const int q = int(i / size_t(L.plane));
+    const double w = q == 0 ? 4.0 / 9.0 : (q <= 4 ? 1.0 / 9.0 : 1.0 / 36.0);
+    host[i] = (e == 8 ? reinterpret_cast<double*>(h.data())[i] : double(reinterpret_cast<float*>(h.data())[i])) + w;
+  }
+  return LBM_OK;
+}
+
+}  // extern "C"

@@ -15,6 +15,12 @@ results; nothing here computes the method itself.
                     relative errors and cost per answer.
   naca_study        NACA0012 (Appendix A) truncated 3 chords behind the
                     trailing edge with both outflows, against 12 chords.
+  vortex_study      convected vortex (Sec. 4.1) through Zou & He and
+                    characteristic outlets, against a long lattice.
+  cbc_training_study  closed-loop training of the tuning network of the
+                    characteristic outlet on reference segments (Sec. 4.2),
+                    then the vortex comparison with the trained network.
+  scaling_study     diffusive scaling sweep of the truncated cylinder.
 """
 import time
 
@@ -275,7 +281,9 @@ def vortex_study(steps=600, every=10, nx=200, ny=400, reference_nx=1000, precisi
         lat = lbm.Lattice(case["mask"], case["tau"], precision=precision, collision="bgk",
                           lateral="periodic", u_in=u0, noise_amp=0.0)
         lat.init_fields(case["rho"], case["ux"], case["uy"])
-        if outflow is not None:
+        if isinstance(outflow, dict):               # the tuning network
+            lat.set_outflow_cbc(net=outflow, mach=ma, length=nx)
+        elif outflow is not None:
             lat.set_outflow_cbc(sigma=outflow[0], kappa2=outflow[1], mach=ma, length=nx)
         rhos = []
         t0 = time.perf_counter()
@@ -300,6 +308,136 @@ def vortex_study(steps=600, every=10, nx=200, ny=400, reference_nx=1000, precisi
                              "mean": float(np.mean(err))}
         progress(f"vortex {name}", {})
     return out
+
+
+def _moments(f):
+    """rho, u, v of populations f[9, ...] (read-out of a stored state)."""
+    cx = np.array([0, 1, 0, -1, 0, 1, -1, -1, 1], np.float64)
+    cy = np.array([0, 0, 1, 0, -1, 1, 1, -1, -1], np.float64)
+    rho = f.sum(axis=0)
+    return rho, np.tensordot(cx, f, axes=(0, 0)) / rho, np.tensordot(cy, f, axes=(0, 0)) / rho
+
+
+def _outlet_features(strip, prev):
+    """The nine inputs of the tuning network at the last column of a strip
+    (9, ny, W), with time derivatives against the previous state: used only
+    to set the standardisation of the inputs."""
+    rho, u, v = _moments(strip[:, :, -3:])
+    rp, up, vp = _moments(prev[:, :, -1])
+
+    def dx(a):
+        return 0.5 * (3 * a[:, 2] - 4 * a[:, 1] + a[:, 0])
+
+    def dy(a):
+        return 0.5 * (np.roll(a, -1) - np.roll(a, 1))
+    return np.stack([dx(rho) / 3, dx(u), dx(v), dy(rho[:, 2]) / 3, dy(u[:, 2]), dy(v[:, 2]),
+                     (rho[:, 2] - rp) / 3, u[:, 2] - up, v[:, 2] - vp], axis=1)
+
+
+def cbc_training_study(n_ts=(5, 10, 25), starts=tuple(range(1, 551, 5)), adam_steps=2000,
+                       lr=1e-3, seed=0, nx=200, ny=400, reference_nx=1000, precision="fp32",
+                       sigma_range=(0.0, 1.0), kappa_range=(0.0, 1.0), init=(0.25, 0.3),
+                       eval_steps=600, progress=_noop):
+    """Closed-loop training of the CBC tuning network (Sec. 4.2) on the
+    convected vortex.  The reference runs on a lattice reference_nx long;
+    from its states at the steps `starts` (every 5 steps from 1 to 546: 110
+    fields) segments of each length in n_ts start on the nx-long truncated
+    lattice, and the loss at their end is the MSE of density and velocity
+    over the n_t columns before the outlet.  Inputs are standardised with
+    the mean and standard deviation of the nine features at the outlet
+    column of the reference states; sigma and kappa_2 map the sigmoid
+    outputs to sigma_range and kappa_range; the network starts near
+    (sigma, kappa_2) = init.  Adam on the full set of segments.  Afterwards
+    the vortex comparison of vortex_study with the trained network beside
+    the fixed settings."""
+    ref_case = workloads.convected_vortex(nx=reference_nx, ny=ny)
+    ma, u0, tau = ref_case["ma"], ref_case["u0"], ref_case["tau"]
+    n_max = max(n_ts)
+    w = 2 * n_max + 3
+    last = max(starts) + n_max
+    lat = lbm.Lattice(ref_case["mask"], tau, precision=precision, collision="bgk",
+                      lateral="periodic", u_in=u0, noise_amp=0.0)
+    lat.init_fields(ref_case["rho"], ref_case["ux"], ref_case["uy"])
+    strips = np.empty((last + 1, 9, ny, w))
+    strips[0] = lat.populations()[:, :, nx - w:nx]
+    t0 = time.perf_counter()
+    for t in range(1, last + 1):
+        lat.step(1)
+        strips[t] = lat.populations()[:, :, nx - w:nx]
+    del lat
+    progress(f"cbc training: reference states 0..{last} ({time.perf_counter() - t0:.1f} s)", {})
+
+    a0s, refs, nts = [], [], []
+    for n_t in n_ts:
+        for s0 in starts:
+            a0s.append(strips[s0])
+            r = np.zeros((3, ny, n_max))
+            r[:, :, n_max - n_t:] = np.stack(_moments(strips[s0 + n_t][:, :, w - n_t:]))
+            refs.append(r)
+            nts.append(n_t)
+    feats = np.concatenate([_outlet_features(strips[t], strips[t - 1]) for t in starts])
+    mu, sd = feats.mean(axis=0), np.maximum(feats.std(axis=0), 1e-12)
+
+    rng = np.random.default_rng(seed)
+
+    def logit(p, lo, hi):
+        z = (p - lo) / (hi - lo)
+        return float(np.log(z / (1 - z)))
+    net = {"w1": rng.standard_normal((20, 9)) * np.sqrt(2 / 9),
+           "b1": np.zeros(20),
+           "w2": rng.standard_normal((20, 20)) * np.sqrt(2 / 20),
+           "b2": np.zeros(20),
+           "w3": rng.standard_normal((2, 20)) * 0.1 * np.sqrt(1 / 20),
+           "b3": np.array([logit(init[0], *sigma_range), logit(init[1], *kappa_range)]),
+           "mu_in": mu, "sd_in": sd, "leaky_slope": 0.01,
+           "sigma_scale": sigma_range[1] - sigma_range[0], "sigma_shift": sigma_range[0],
+           "kappa_scale": kappa_range[1] - kappa_range[0], "kappa_shift": kappa_range[0]}
+    net = {k: (np.asarray(v, np.float32).astype(np.float64) if isinstance(v, np.ndarray) else v)
+           for k, v in net.items()}
+    tr = lbm.CbcTrainer(np.stack(a0s), np.stack(refs), np.array(nts, np.int32), net, tau=tau,
+                        mach=ma, length=nx, precision=precision, lr=lr, eps=1e-16)
+    loss0, _ = tr.gradient()
+    history = [(0, loss0)]
+    _sync()
+    t0 = time.perf_counter()
+    chunk = max(1, adam_steps // 20)
+    done = 0
+    while done < adam_steps:
+        k = min(chunk, adam_steps - done)
+        tr.step(k)
+        done += k
+        history.append((done, tr.loss()))
+        progress(f"cbc training: {done} Adam steps, loss {history[-1][1]:.4e}", {})
+    _sync()
+    train_s = time.perf_counter() - t0
+    trained = dict(net, **tr.weights())
+    loss1, _ = tr.gradient()
+    per_nt = {}
+    for n_t in n_ts:
+        idx = [i for i, v in enumerate(nts) if v == n_t]
+        sub = lbm.CbcTrainer(np.stack([a0s[i] for i in idx]), np.stack([refs[i] for i in idx]),
+                             np.full(len(idx), n_t, np.int32), net, tau=tau, mach=ma, length=nx,
+                             precision=precision)
+        before = sub.gradient()[0]
+        sub.set_net(trained)
+        per_nt[n_t] = {"before": before, "after": sub.gradient()[0]}
+        del sub
+    del tr
+    ev = vortex_study(steps=eval_steps, nx=nx, ny=ny, reference_nx=reference_nx,
+                      precision=precision,
+                      settings={"cbc_s0_k0": (0.0, 0.0), "cbc_s0.25_kMa": (0.25, ma),
+                                "cbc_init": tuple(init), "nn_cbc_untrained": net,
+                                "nn_cbc_trained": trained},
+                      progress=progress)
+    return {"segments": len(nts), "n_ts": list(n_ts), "starts": [int(starts[0]), int(starts[-1]),
+                                                               len(starts)],
+            "adam_steps": adam_steps, "lr": lr, "precision": precision, "train_seconds": train_s,
+            "ms_per_adam_step": 1e3 * train_s / max(adam_steps, 1),
+            "loss_before": loss0, "loss_after": loss1, "loss_history": history,
+            "loss_per_n_t": per_nt, "network": {k: (np.asarray(v).tolist()
+                                                    if isinstance(v, np.ndarray) else v)
+                                                for k, v in trained.items()},
+            "vortex": ev}
 
 
 def scaling_study(network, re_list=(10.0, 20.0, 50.0, 100.0, 200.0), tau=0.6, steps=150_000,

@@ -65,6 +65,14 @@ class lbm_cbc(ctypes.Structure):
                 ("rho_inf", ctypes.c_double), ("net", ctypes.POINTER(lbm_cbc_net))]
 
 
+class lbm_cbc_train_params(ctypes.Structure):
+    _fields_ = [("ny", ctypes.c_int32), ("n_max", ctypes.c_int32), ("n_seg", ctypes.c_int32),
+                ("precision", ctypes.c_int32), ("tau", ctypes.c_double), ("mach", ctypes.c_double),
+                ("length", ctypes.c_double), ("rho_inf", ctypes.c_double), ("lr", ctypes.c_double),
+                ("beta1", ctypes.c_double), ("beta2", ctypes.c_double), ("eps", ctypes.c_double),
+                ("stream", ctypes.c_void_p)]
+
+
 class lbm_train_params(ctypes.Structure):
     _fields_ = [("batch", ctypes.c_int32), ("lr", ctypes.c_double), ("beta1", ctypes.c_double),
                 ("beta2", ctypes.c_double), ("eps", ctypes.c_double), ("seed", ctypes.c_uint64),
@@ -95,6 +103,9 @@ class lbm_batch_params(ctypes.Structure):
 
 PARAM_SHAPES = {"w1": (64, 27), "b1": (64,), "w2": (64, 64), "b2": (64,), "w3": (3, 64), "b3": (3,)}
 N_PARAMS = 6147
+CBC_PARAM_SHAPES = {"w1": (20, 9), "b1": (20,), "w2": (20, 20), "b2": (20,), "w3": (2, 20),
+                    "b3": (2,)}
+LBM_CBC_NPARAMS = 662
 
 
 class LbmError(RuntimeError):
@@ -153,6 +164,16 @@ def library():
             "lbm_train_get_weights": (I32, [VP, P(lbm_mlp_host)]),
             "lbm_train_gradient": (I32, [VP, VP, ctypes.c_int32, _FP, DP]),
             "lbm_train_sample_rows": (I32, [VP, I64, P(ctypes.c_int32)]),
+            "lbm_cbc_train_workspace_bytes": (ctypes.c_size_t, [P(lbm_cbc_train_params)]),
+            "lbm_cbc_train_create": (I32, [P(lbm_cbc_train_params), VP, ctypes.c_size_t, P(VP)]),
+            "lbm_cbc_train_destroy": (I32, [VP]),
+            "lbm_cbc_train_set_segments": (I32, [VP, DP, DP, P(ctypes.c_int32)]),
+            "lbm_cbc_train_set_net": (I32, [VP, P(lbm_cbc_net)]),
+            "lbm_cbc_train_gradient": (I32, [VP, DP, DP]),
+            "lbm_cbc_train_step": (I32, [VP, I64]),
+            "lbm_cbc_train_loss": (I32, [VP, DP]),
+            "lbm_cbc_train_get_weights": (I32, [VP, _FP]),
+            "lbm_cbc_train_final_state": (I32, [VP, ctypes.c_int32, DP]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(lib, name)
@@ -257,18 +278,25 @@ def lbm_set_outflow_model(ctx, kind, P=None, mass_bound=1e-2):
     return _check(st, "lbm_set_outflow_model")
 
 
+def _cbc_net_struct(net):
+    """lbm_cbc_net for a dict of weights and maps; returns the struct and the
+    FP32 arrays it points into (keep them alive during the call)."""
+    keep = {k: np.ascontiguousarray(net[k], dtype=np.float32).reshape(-1)
+            for k in ("w1", "b1", "w2", "b2", "w3", "b3", "mu_in", "sd_in")}
+    n = lbm_cbc_net(*[keep[k].ctypes.data_as(_FP) for k in
+                      ("w1", "b1", "w2", "b2", "w3", "b3", "mu_in", "sd_in")],
+                    float(net.get("leaky_slope", 0.01)), float(net["sigma_scale"]),
+                    float(net["sigma_shift"]), float(net["kappa_scale"]),
+                    float(net["kappa_shift"]))
+    return n, keep
+
+
 def lbm_set_outflow_cbc(ctx, sigma=0.0, kappa2=0.0, mach=0.0, length=1.0, rho_inf=1.0,
                         net=None):
     keep = None
     p = lbm_cbc(sigma, kappa2, mach, length, rho_inf, None)
     if net is not None:
-        keep = {k: np.ascontiguousarray(net[k], dtype=np.float32).reshape(-1)
-                for k in ("w1", "b1", "w2", "b2", "w3", "b3", "mu_in", "sd_in")}
-        n = lbm_cbc_net(*[keep[k].ctypes.data_as(_FP) for k in
-                          ("w1", "b1", "w2", "b2", "w3", "b3", "mu_in", "sd_in")],
-                        float(net.get("leaky_slope", 0.01)), float(net["sigma_scale"]),
-                        float(net["sigma_shift"]), float(net["kappa_scale"]),
-                        float(net["kappa_shift"]))
+        n, keep = _cbc_net_struct(net)
         p.net = ctypes.pointer(n)
     st = library().lbm_set_outflow_cbc(ctx, ctypes.byref(p))
     del keep
@@ -549,6 +577,138 @@ class Trainer:
 
     def sample_rows(self, step):
         return lbm_train_sample_rows(self.tr, step, self.batch)
+
+
+# --- closed-loop training of the CBC tuning network (include/lbm_cbc_train.h) -----
+
+def lbm_cbc_train_workspace_bytes(params):
+    n = library().lbm_cbc_train_workspace_bytes(ctypes.byref(params))
+    if n == 0:
+        raise LbmError(LBM_EINVAL, "lbm_cbc_train_workspace_bytes",
+                       library().lbm_last_error().decode())
+    return n
+
+
+def lbm_cbc_train_create(params, workspace_ptr, nbytes):
+    t = ctypes.c_void_p()
+    _check(library().lbm_cbc_train_create(ctypes.byref(params), ctypes.c_void_p(workspace_ptr),
+                                          nbytes, ctypes.byref(t)), "lbm_cbc_train_create")
+    return t
+
+
+def lbm_cbc_train_destroy(t):
+    return _check(library().lbm_cbc_train_destroy(t), "lbm_cbc_train_destroy")
+
+
+def lbm_cbc_train_set_segments(t, a0, ref, n_t):
+    a0 = np.ascontiguousarray(a0, dtype=np.float64)
+    ref = np.ascontiguousarray(ref, dtype=np.float64)
+    n_t = np.ascontiguousarray(n_t, dtype=np.int32)
+    return _check(library().lbm_cbc_train_set_segments(
+        t, _dptr(a0), _dptr(ref), n_t.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))),
+        "lbm_cbc_train_set_segments")
+
+
+def lbm_cbc_train_set_net(t, net):
+    n, keep = _cbc_net_struct(net)
+    st = library().lbm_cbc_train_set_net(t, ctypes.byref(n))
+    del keep
+    return _check(st, "lbm_cbc_train_set_net")
+
+
+def lbm_cbc_train_gradient(t):
+    g = np.zeros(LBM_CBC_NPARAMS)
+    loss = ctypes.c_double()
+    _check(library().lbm_cbc_train_gradient(t, ctypes.byref(loss), _dptr(g)),
+           "lbm_cbc_train_gradient")
+    return loss.value, g
+
+
+def lbm_cbc_train_step(t, nsteps):
+    return _check(library().lbm_cbc_train_step(t, int(nsteps)), "lbm_cbc_train_step")
+
+
+def lbm_cbc_train_loss(t):
+    v = ctypes.c_double()
+    _check(library().lbm_cbc_train_loss(t, ctypes.byref(v)), "lbm_cbc_train_loss")
+    return v.value
+
+
+def lbm_cbc_train_get_weights(t):
+    w = np.zeros(LBM_CBC_NPARAMS, np.float32)
+    _check(library().lbm_cbc_train_get_weights(t, w.ctypes.data_as(_FP)),
+           "lbm_cbc_train_get_weights")
+    return w
+
+
+def lbm_cbc_train_final_state(t, seg, ny, width):
+    out = np.empty((9, ny, width))
+    _check(library().lbm_cbc_train_final_state(t, int(seg), _dptr(out)),
+           "lbm_cbc_train_final_state")
+    return out
+
+
+def cbc_unflatten(v):
+    """Split a flat 662-vector (w1, b1, w2, b2, w3, b3 order) into arrays."""
+    out, o = {}, 0
+    for k, shp in CBC_PARAM_SHAPES.items():
+        n = int(np.prod(shp))
+        out[k] = np.asarray(v[o:o + n]).reshape(shp)
+        o += n
+    return out
+
+
+class CbcTrainer:
+    """Closed-loop trainer of the CBC tuning network on the current device.
+
+    a0 [n_seg][9][ny][2 n_max + 3]: start states of the segments (the last
+    columns of the truncated lattice); ref [n_seg][3][ny][n_max]: reference
+    rho, u, v at step n_t, right-aligned; n_t [n_seg]."""
+
+    def __init__(self, a0, ref, n_t, net, *, tau, mach, length, rho_inf=1.0, precision="fp32",
+                 lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
+        import torch
+        a0 = np.asarray(a0)
+        n_seg, _, ny, width = a0.shape
+        n_max = (width - 3) // 2
+        if width != 2 * n_max + 3 or np.shape(ref) != (n_seg, 3, ny, n_max):
+            raise ValueError("a0 must be [n_seg][9][ny][2 n_max + 3], ref [n_seg][3][ny][n_max]")
+        self.ny, self.width, self.n_max, self.n_seg = ny, width, n_max, n_seg
+        self.stream = torch.cuda.current_stream()
+        self.params = lbm_cbc_train_params(ny, n_max, n_seg, _PREC[precision], tau, mach, length,
+                                           rho_inf, lr, beta1, beta2, eps,
+                                           ctypes.c_void_p(self.stream.cuda_stream))
+        nbytes = lbm_cbc_train_workspace_bytes(self.params)
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+        self.t = lbm_cbc_train_create(self.params, self.workspace.data_ptr(), nbytes)
+        lbm_cbc_train_set_segments(self.t, a0, ref, n_t)
+        lbm_cbc_train_set_net(self.t, net)
+
+    def __del__(self):
+        t = getattr(self, "t", None)
+        if t is not None and _lib is not None:
+            _lib.lbm_cbc_train_destroy(t)
+            self.t = None
+
+    def set_net(self, net):
+        lbm_cbc_train_set_net(self.t, net)
+
+    def gradient(self):
+        """(loss, {w1: .., b3: ..}) of the current weights."""
+        loss, g = lbm_cbc_train_gradient(self.t)
+        return loss, cbc_unflatten(g)
+
+    def step(self, n=1):
+        lbm_cbc_train_step(self.t, n)
+
+    def loss(self):
+        return lbm_cbc_train_loss(self.t)
+
+    def weights(self):
+        return cbc_unflatten(lbm_cbc_train_get_weights(self.t))
+
+    def final_state(self, seg):
+        return lbm_cbc_train_final_state(self.t, seg, self.ny, self.width)
 
 
 # --- convenience: one lattice with a torch-owned workspace --------------------------

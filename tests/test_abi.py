@@ -102,3 +102,45 @@ def test_characteristic_outflow_needs_periodic_laterals():
         assert e.value.status == lbm.LBM_EINVAL
     lbm.lbm_destroy(ctx)
     lbm.lbm_destroy(ctx2)
+
+
+def _ct_params(**kw):
+    p = lbm.lbm_cbc_train_params(70, 9, 3, lbm.LBM_FP64, 0.6, 0.2, 40.0, 1.0, 1e-3, 0.9, 0.999,
+                                 1e-8, None)
+    for k, v in kw.items():
+        setattr(p, k, v)
+    return p
+
+
+def test_cbc_trainer_workspace_accounts_for_the_trajectory():
+    b = lbm.lbm_cbc_train_workspace_bytes(_ct_params())
+    # trajectory of 3 segments: (n_max + 1) states of 9 x 70 x (2 n_max + 3) doubles
+    assert b >= 3 * 10 * 9 * 70 * 21 * 8
+    b2 = lbm.lbm_cbc_train_workspace_bytes(_ct_params(n_seg=6))
+    b32 = lbm.lbm_cbc_train_workspace_bytes(_ct_params(precision=lbm.LBM_FP32_OFFSET))
+    assert b2 > b and b32 < b
+
+
+@pytest.mark.parametrize("field,value", [("ny", 2), ("n_max", 0), ("n_max", 65), ("n_seg", 0),
+                                         ("precision", lbm.LBM_FP16_OFFSET), ("tau", 0.5),
+                                         ("mach", 1.0), ("length", 0.0), ("rho_inf", 0.0),
+                                         ("lr", 0.0), ("beta1", 1.0), ("eps", 0.0)])
+def test_cbc_trainer_rejects_bad_parameters(field, value):
+    with pytest.raises(lbm.LbmError) as e:
+        lbm.lbm_cbc_train_workspace_bytes(_ct_params(**{field: value}))
+    assert e.value.status == lbm.LBM_EINVAL
+
+
+def test_cbc_trainer_needs_segments_and_network_before_a_step():
+    p = _ct_params()
+    need = lbm.lbm_cbc_train_workspace_bytes(p)
+    with pytest.raises(lbm.LbmError) as e:
+        lbm.lbm_cbc_train_create(p, 1 << 20, need - 1)
+    assert e.value.status == lbm.LBM_ENOSPACE
+    t = lbm.lbm_cbc_train_create(p, 1 << 20, need)           # never dereferenced
+    for call in (lambda: lbm.lbm_cbc_train_step(t, 1), lambda: lbm.lbm_cbc_train_gradient(t),
+                 lambda: lbm.lbm_cbc_train_final_state(t, 0, 70, 21)):
+        with pytest.raises(lbm.LbmError) as e:
+            call()
+        assert e.value.status == lbm.LBM_ESTATE
+    lbm.lbm_cbc_train_destroy(t)

@@ -1,0 +1,216 @@
+"""GPU parity of the closed-loop training of the CBC tuning network (Sec. 4.2)
+through the C ABI (lbm_cbc_train_*), against the oracle's torch FP64
+rollout and reverse-mode gradient on the full truncated lattice.
+
+FP64: loss and gradient to 1e-10 relative (the adjoint is written out by
+hand, the oracle's is automatic; both sum rounding errors of order 1e-16
+over a few hundred operations per node and step).  FP32 offsets: the loss
+to 2e-4 and the gradient to 2e-3 relative in the 2-norm (populations carry
+about 1e-8 absolute error, density defects in the loss region are of order
+1e-4, so the squared defects and their derivatives lose about 1e-4
+relative).  The FP32 gradient also depends on how close pre-activations
+come to the LeakyReLU kink: one that lies within FP32 rounding of zero
+takes the other slope, and with features standardised to |z| ~ 100 (sd_in
+ten times too small) that moves the gradient by about 1e-2; with |z| of
+order one, the intended scale, the difference is about 2e-5.  Adam: the
+FP32 masters after two steps match the oracle's Adam,
+run in FP64 and rounded to FP32 after every step, to one unit in the last
+place."""
+import numpy as np
+import pytest
+
+from oracle import cbc_train, d2q9
+from oracle.d2q9 import CS2
+from oracle.mlp import Adam
+from oracle.solver import Lattice
+from paper_2506_05293_amd import lbm
+
+pytestmark = pytest.mark.gpu
+CS = np.sqrt(CS2)
+PARAMS = cbc_train.PARAMS
+
+
+def _say(*a):
+    print("[gpu case]", *a, flush=True)
+
+
+def _net(seed, f32=True):
+    rng = np.random.default_rng(seed)
+    n = {"w1": 0.5 * rng.standard_normal((20, 9)), "b1": 0.3 * rng.standard_normal(20),
+         "w2": 0.3 * rng.standard_normal((20, 20)), "b2": 0.3 * rng.standard_normal(20),
+         "w3": 0.5 * rng.standard_normal((2, 20)), "b3": 0.3 * rng.standard_normal(2),
+         "mu_in": 1e-5 * rng.standard_normal(9), "sd_in": np.full(9, 3e-4)}
+    if f32:      # the trainer holds FP32 masters: give both sides those values
+        n = {k: np.asarray(v, np.float32).astype(np.float64) for k, v in n.items()}
+    n.update(leaky_slope=0.01, sigma_scale=1.0, sigma_shift=0.0, kappa_scale=0.8,
+             kappa_shift=0.1)
+    return n
+
+
+def _vortex_state(nx, ny, u0, tau, xc, seed_steps=4, rc=None, beta=0.4):
+    """A post-collision state with a vortex near the outlet (numpy solver,
+    a few steps with a fixed-parameter characteristic outlet)."""
+    rc = rc or max(2.0, ny / 6)
+    y, x = np.mgrid[0:ny, 0:nx].astype(float)
+    yc = ny / 2 - 0.4
+    r2 = (x - xc) ** 2 + (y - yc) ** 2
+    e = np.exp(-r2 / (2 * rc**2))
+    lat = Lattice(np.zeros((ny, nx), np.uint8), tau, lateral="periodic", u_in=u0)
+    lat.set_outflow_cbc(sigma=0.3, kappa2=0.2, mach=u0 / CS, length=nx)
+    lat.set_equilibrium(np.exp(-(beta * u0) ** 2 / (2 * CS2) * np.exp(-r2 / rc**2)),
+                        u0 - beta * u0 * (y - yc) / rc * e, beta * u0 * (x - xc) / rc * e)
+    lat.step(seed_steps)
+    return lat.post_collision()
+
+
+def _zh_ref(a0, n_t, tau, u0):
+    nx = a0.shape[2]
+    lat = Lattice(np.zeros(a0.shape[1:], np.uint8), tau, lateral="periodic", u_in=u0)
+    a = a0
+    for _ in range(n_t):
+        a, _ = lat.advance_post(a)
+    return np.stack(d2q9.moments(a[:, :, nx - n_t:]))
+
+
+def _case(nx, ny, n_ts, tau=0.6, u0=0.1, seed=0):
+    """Segments on an nx x ny lattice: full states for the oracle, strips and
+    right-aligned references for the trainer."""
+    n_max = max(n_ts)
+    w = 2 * n_max + 3
+    assert w + 1 <= nx
+    segs, a0s, refs = [], [], []
+    for i, n_t in enumerate(n_ts):
+        a0 = _vortex_state(nx, ny, u0, tau, nx - 5.5 - 1.3 * i - 0.2 * seed, seed_steps=3 + i)
+        ref = _zh_ref(a0, n_t, tau, u0)
+        segs.append((a0, ref))
+        a0s.append(a0[:, :, nx - w:])
+        r = np.zeros((3, ny, n_max))
+        r[:, :, n_max - n_t:] = ref
+        refs.append(r)
+    cfg = dict(tau=tau, u_in=u0, mach=u0 / CS, length=float(nx), rho_inf=1.0)
+    return segs, np.stack(a0s), np.stack(refs), np.array(n_ts, np.int32), cfg
+
+
+def _trainer(a0s, refs, nts, net, cfg, precision, **kw):
+    return lbm.CbcTrainer(a0s, refs, nts, net, tau=cfg["tau"], mach=cfg["mach"],
+                          length=cfg["length"], rho_inf=cfg["rho_inf"], precision=precision, **kw)
+
+
+def _flat(g):
+    return np.concatenate([np.asarray(g[k]).reshape(-1) for k in PARAMS])
+
+
+@pytest.mark.parametrize("nx,ny,n_ts", [(40, 70, (1, 4, 9)), (30, 64, (6, 6)), (12, 3, (1, 2)),
+                                        (48, 131, (12, 3))])
+def test_loss_and_gradient_fp64(nx, ny, n_ts):
+    _say("cbc train fp64", nx, ny, n_ts)
+    net = _net(1)
+    segs, a0s, refs, nts, cfg = _case(nx, ny, n_ts)
+    loss_o, g_o = cbc_train.loss_and_grad(segs, net, cfg)
+    tr = _trainer(a0s, refs, nts, net, cfg, "fp64")
+    loss_g, g_g = tr.gradient()
+    print("loss", loss_g, loss_o, flush=True)
+    assert loss_g == pytest.approx(loss_o, rel=1e-10)
+    fo, fg = _flat(g_o), _flat(g_g)
+    err = np.max(np.abs(fg - fo)) / np.max(np.abs(fo))
+    print("max gradient error / max |g|", err, flush=True)
+    assert err < 1e-10
+    big = np.abs(fo) > 1e-3 * np.max(np.abs(fo))
+    np.testing.assert_allclose(fg[big], fo[big], rtol=1e-8)
+    # the final states on the part of the strip that equals the full lattice
+    for s, (a0, ref) in enumerate(segs):
+        n_t = ref.shape[2]
+        full = cbc_train.final_state(a0, net, cfg, n_t)[:, :, nx - a0s.shape[3]:]
+        got = tr.final_state(s)
+        np.testing.assert_allclose(got[:, :, n_t:], full[:, :, n_t:], rtol=0, atol=1e-14)
+
+
+def test_loss_and_gradient_fp32():
+    _say("cbc train fp32")
+    net = _net(2)
+    segs, a0s, refs, nts, cfg = _case(40, 70, (3, 8, 8))
+    loss_o, g_o = cbc_train.loss_and_grad(segs, net, cfg)
+    loss_g, g_g = _trainer(a0s, refs, nts, net, cfg, "fp32").gradient()
+    fo, fg = _flat(g_o), _flat(g_g)
+    rel = np.linalg.norm(fg - fo) / np.linalg.norm(fo)
+    print("fp32 loss", loss_g, loss_o, "gradient rel 2-norm error", rel, flush=True)
+    assert loss_g == pytest.approx(loss_o, rel=2e-4)
+    assert rel < 2e-3
+
+
+def test_adam_steps_match_oracle():
+    _say("cbc train adam")
+    net = _net(3)
+    segs, a0s, refs, nts, cfg = _case(40, 70, (2, 5))
+    # the gradients here are ~1e-8: an eps far below them makes each step
+    # about lr, as Adam intends
+    tr = _trainer(a0s, refs, nts, net, cfg, "fp64", lr=2e-3, eps=1e-12)
+    tr.step(2)
+    got = tr.weights()
+    loss_last = tr.loss()
+    P = {k: np.array(net[k]) for k in PARAMS}
+    opt = Adam(P, lr=2e-3, eps=1e-12)
+    losses = []
+    for _ in range(2):
+        loss, g = cbc_train.loss_and_grad(segs, dict(net, **P), cfg)
+        losses.append(loss)
+        P = opt.step(P, g)
+        P = {k: np.asarray(v, np.float32).astype(np.float64) for k, v in P.items()}
+    assert loss_last == pytest.approx(losses[1], rel=1e-10)
+    for k in PARAMS:
+        ulp = np.spacing(np.abs(P[k]).astype(np.float32)).astype(np.float64)
+        assert np.all(np.abs(got[k] - P[k]) <= ulp + 1e-12), k
+    # the weights moved: about lr per step for every parameter
+    moved = np.abs(_flat(got) - _flat(net))
+    assert np.median(moved) > 1e-3
+
+
+def test_free_stream_gives_zero_loss_and_gradient():
+    _say("cbc train free stream")
+    nx, ny, n_max, u0 = 30, 20, 6, 0.08
+    w = 2 * n_max + 3
+    a = d2q9.equilibrium(np.ones((ny, w)), np.full((ny, w), u0), np.zeros((ny, w)))
+    ref = np.stack([np.ones((ny, n_max)), np.full((ny, n_max), u0), np.zeros((ny, n_max))])
+    tr = lbm.CbcTrainer(a[None], ref[None], np.array([n_max], np.int32), _net(4), tau=0.6,
+                        mach=u0 / CS, length=nx, precision="fp64")
+    loss, g = tr.gradient()
+    assert loss < 1e-28
+    assert np.max(np.abs(_flat(g))) < 1e-18
+
+
+def test_full_size_vortex_segments():
+    # the convected-vortex lattice (200 x 400, periodic rows) with the longest
+    # segment of the training set, n_t = 25, and a shorter one
+    nx, ny, u0, tau = 200, 400, 0.3 * CS, 0.5 + 3 * 0.3 * CS * 200 / 750
+    _say("cbc train full size 200x400 n_t 25,10")
+    y, x = np.mgrid[0:ny, 0:nx].astype(float)
+    segs, a0s, refs = [], [], []
+    n_ts = (25, 10)
+    w = 2 * 25 + 3
+    for xc in (185.0, 196.0):
+        r2 = (x - xc) ** 2 + (y - ny / 2) ** 2
+        e = np.exp(-r2 / (2 * 20.0**2))
+        a0 = d2q9.equilibrium(np.exp(-(0.5 * u0) ** 2 / (2 * CS2) * np.exp(-r2 / 20.0**2)),
+                              u0 - 0.5 * u0 * (y - ny / 2) / 20 * e, 0.5 * u0 * (x - xc) / 20 * e)
+        segs.append(a0)
+    net = _net(5)
+    # standardised features of order one, as the standardisation intends
+    net["sd_in"] = np.full(9, np.float32(1e-3), np.float64)
+    cfg = dict(tau=tau, u_in=u0, mach=u0 / CS, length=float(nx), rho_inf=1.0)
+    full = []
+    for a0, n_t in zip(segs, n_ts):
+        ref = _zh_ref(a0, n_t, tau, u0)
+        full.append((a0, ref))
+        a0s.append(a0[:, :, nx - w:])
+        r = np.zeros((3, ny, 25))
+        r[:, :, 25 - n_t:] = ref
+        refs.append(r)
+    loss_o, g_o = cbc_train.loss_and_grad(full, net, cfg)
+    fo = _flat(g_o)
+    for prec, tol_l, tol_g in (("fp64", 1e-10, 1e-9), ("fp32", 2e-4, 2e-3)):
+        loss_g, g_g = _trainer(np.stack(a0s), np.stack(refs), np.array(n_ts, np.int32), net, cfg,
+                               prec).gradient()
+        rel = np.linalg.norm(_flat(g_g) - fo) / np.linalg.norm(fo)
+        print(prec, "loss", loss_g, loss_o, "gradient rel error", rel, flush=True)
+        assert loss_g == pytest.approx(loss_o, rel=tol_l)
+        assert rel < tol_g
