@@ -136,9 +136,9 @@ def time_steps(lat, steps, warmup, torch):
 
 
 # Algorithmic HBM bytes per node and segment step of the CBC trainer (FP32):
-# forward 9 pulled reads + 9 writes, collision adjoint 9 pulled reads + 9
-# adjoint reads + 9 writes, streaming adjoint 9 gathered reads + 9 writes.
-CBC_TRAIN_BYTES_PER_NODE_STEP = 4 * (18 + 27 + 18)
+# forward 9 pulled reads + 9 writes; backward (streaming and collision
+# adjoints fused) 9 gathered adjoint reads + 9 pulled state reads + 9 writes.
+CBC_TRAIN_BYTES_PER_NODE_STEP = 4 * (18 + 27)
 
 
 def time_cbc_training(torch, steps=20, warmup=3):
@@ -285,7 +285,9 @@ def run_studies(which, scale, nn_switch=0, mass_bound=1e-2):
             "loss_before": res["loss_before"], "loss_after": res["loss_after"],
             "ms_per_adam_step": res["ms_per_adam_step"],
             "vortex": {k: {a: r[a] for a in ("max", "final", "mean", "finite")}
-                       for k, r in res["vortex"]["runs"].items()}}}), flush=True)
+                       for k, r in res["vortex"]["runs"].items()},
+            "held_out": {h: {k: r["mean"] for k, r in v["runs"].items()}
+                         for h, v in res["held_out"].items()}}}), flush=True)
         if which == "cbc_train":
             return
     if which in ("vortex", "all"):

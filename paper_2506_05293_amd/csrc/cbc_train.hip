@@ -7,7 +7,9 @@
 // trained on the exact gradient of that loss through the rollout.  Every
 // segment runs on a strip of W = 2 n_max + 3 columns (nothing further
 // upstream reaches the loss region within n_t steps), in offset form
-// g = f - w, BGK collision, periodic rows, no solids.
+// g = f - w, BGK collision, periodic rows, no solids.  Strips are stored
+// column by column (rows fastest), so that the outlet kernels, which work
+// along the rows of the last columns, read consecutive addresses.
 //
 // One optimiser step, every segment at once (a segment whose n_t is
 // shorter than the step index sits out that step):
@@ -20,15 +22,24 @@
 //   k_seed          loss over Omega and its derivative w.r.t. the final
 //                   state (the adjoint's initial value);
 //   backward k = n_max-1 .. 0
-//     k_bwd_node    collision adjoint at the recomputed pre-collision state;
+//     k_bwd         per node: the adjoint of the post-collision state at
+//                   step k+1 (the seed, or the streaming adjoint of step k+1
+//                   -- a gather: population q of node x takes the adjoint of
+//                   node x + c_q -- plus the moment terms through which the
+//                   outlet read the three last columns), then the collision
+//                   adjoint at the recomputed pre-collision state of step k+1;
+//                   the two are fused because the collision adjoint at x
+//                   needs only that node's adjoint (adjoints of the pulled
+//                   populations alternate between two buffers);
 //     k_bwd_outlet  one thread per outlet row: adjoints of the outlet
 //                   reconstruction, of the LODI update and of the network,
 //                   the parameter gradient summed over the workgroup's 64
 //                   rows in LDS into a per-(segment, row block) FP64 slot;
-//     k_bwd_gather  streaming adjoint (a gather: population q of node x
-//                   takes the adjoint of node x + c_q) plus the moment
-//                   terms through which the outlet read the three columns;
-//   k_update        FP64 sum of the slots in a fixed order, Adam.
+//                   the start state's adjoint is never needed, so the
+//                   streaming adjoint of step 0 is not taken;
+//   k_gsum, k_lsum  first stage of the FP64 sums of the gradient and loss
+//                   slots (fixed order, many workgroups);
+//   k_update        second stage and Adam.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -65,11 +76,12 @@ struct CtState {
 
 template <typename T>
 struct CtArgs {
-  T* traj;              // [seg][n_max+1][9][ny][W]
+  T* traj;              // [seg][n_max+1][9][W][ny] (rows fastest)
   T* outs;              // [seg][n_max][ny][3]    outlet state drho', u', v'
   T* dts;               // [seg][n_max+1][ny][3]  c_s^2 rho_t, u_t, v_t
-  T* lamA;              // [seg][9][ny][W]        adjoint of the post-collision state
-  T* lamF;              // [seg][9][ny][W]        adjoint of the pulled populations
+  T* lamA;              // [seg][9][W][ny]        adjoint of the final state (seed)
+  T* lamF[2];           // [seg][9][W][ny] each   adjoint of the pulled populations,
+                        //                        step k in buffer k & 1
   T* lamP;              // [seg][ny][3]           adjoint of the time derivatives
   T* madj;              // [seg][ny][12]          moment adjoints from the outlet
   const T* ref;         // [seg][3][ny][n_max]    rho - 1, u, v
@@ -78,7 +90,7 @@ struct CtArgs {
   double* lslot;        // [seg][nlb]
   CtState* st;
   int ny, W, n_max, nrb, nlb;
-  int64_t plane;        // ny * W
+  int64_t plane;        // ny * W; node (x, y) of a plane at x * ny + y
   T omega;
   double seg_scale;     // 1 / n_seg
 };
@@ -130,7 +142,7 @@ __device__ __forceinline__ void pull(const T* A, int64_t plane, int W, int ny, i
     int sx = x - cx(q);
     const int sy = wrap(y - cy(q), ny);
     if (sx < 0) sx = x;
-    g[q] = sx <= W - 1 ? A[q * plane + int64_t(sy) * W + sx] : T(0);
+    g[q] = sx <= W - 1 ? A[q * plane + int64_t(sx) * ny + sy] : T(0);
   }
 }
 
@@ -147,10 +159,10 @@ __device__ OutIn<T> outlet_inputs(const T* A, int64_t plane, int W, int ny, int 
   const T cs2 = T(1.0 / 3.0);
   T d[3], uu[3], vv[3];
 #pragma unroll
-  for (int c = 0; c < 3; ++c) node_state(A, plane, int64_t(r) * W + W - 3 + c, d[c], uu[c], vv[c]);
+  for (int c = 0; c < 3; ++c) node_state(A, plane, int64_t(W - 3 + c) * ny + r, d[c], uu[c], vv[c]);
   T dn, un, vn, ds, us, vs;
-  node_state(A, plane, int64_t(wrap(r + 1, ny)) * W + W - 1, dn, un, vn);
-  node_state(A, plane, int64_t(wrap(r - 1, ny)) * W + W - 1, ds, us, vs);
+  node_state(A, plane, int64_t(W - 1) * ny + wrap(r + 1, ny), dn, un, vn);
+  node_state(A, plane, int64_t(W - 1) * ny + wrap(r - 1, ny), ds, us, vs);
   OutIn<T> o;
   o.drho = d[2];
   o.u = uu[2];
@@ -191,40 +203,53 @@ __device__ Lodi<T> lodi(const OutIn<T>& in, T sigma, T kappa2, const CtState* st
 }
 
 // ---- forward -------------------------------------------------------------------------
+// The 662 weights are read by every row: staged once per workgroup in LDS
+// (uniform reads, no scalar-load latency inside the layers).
+__device__ __forceinline__ void stage_weights(const CtState* st, float* sw, int nthreads) {
+  for (int i = threadIdx.x; i < kNP; i += nthreads) sw[i] = st->w[i];
+  __syncthreads();
+}
+
 template <typename T>
 __global__ void __launch_bounds__(kRows) k_fwd_outlet(const CtArgs<T> a, int k) {
+  __shared__ float sw[kNP];
   const int s = blockIdx.y;
-  if (k >= a.nts[s]) return;
-  const int r = blockIdx.x * kRows + threadIdx.x;
-  if (r >= a.ny) return;
+  if (k >= a.nts[s]) return;                     // uniform over the workgroup
   const CtState* st = a.st;
-  const T* A = state_at(a, s, k);
-  const OutIn<T> in = outlet_inputs(A, a.plane, a.W, a.ny, r);
-  const T* P = a.dts + ((int64_t(s) * (a.n_max + 1) + k) * a.ny + r) * 3;
+  // every global load of the row is issued before the weights are staged,
+  // so the two overlap (rows past the end read the last row and store nothing)
+  const int r = blockIdx.x * kRows + threadIdx.x;
+  const bool valid = r < a.ny;
+  const int rl = valid ? r : a.ny - 1;
+  const OutIn<T> in = outlet_inputs(state_at(a, s, k), a.plane, a.W, a.ny, rl);
+  const T* P = a.dts + ((int64_t(s) * (a.n_max + 1) + k) * a.ny + rl) * 3;
+  const T prev[3] = {P[0], P[1], P[2]};
+  stage_weights(st, sw, kRows);
+  if (!valid) return;
   T z[kIn];
 #pragma unroll
   for (int i = 0; i < kIn; ++i) {
-    const T f = i < 6 ? in.g[i] : P[i - 6];
+    const T f = i < 6 ? in.g[i] : prev[i - 6];
     z[i] = (f - T(st->mu[i])) / T(st->sd[i]);
   }
   const T sl = T(st->leaky);
   T h1[kH];
 #pragma unroll
   for (int o = 0; o < kH; ++o) {
-    T acc = T(st->w[kOB1 + o]);
+    T acc = T(sw[kOB1 + o]);
 #pragma unroll
-    for (int i = 0; i < kIn; ++i) acc += T(st->w[kOW1 + o * kIn + i]) * z[i];
+    for (int i = 0; i < kIn; ++i) acc += T(sw[kOW1 + o * kIn + i]) * z[i];
     h1[o] = leaky(acc, sl);
   }
-  T s0 = T(st->w[kOB3]), s1 = T(st->w[kOB3 + 1]);
+  T s0 = T(sw[kOB3]), s1 = T(sw[kOB3 + 1]);
 #pragma unroll 1
   for (int o = 0; o < kH; ++o) {
-    T acc = T(st->w[kOB2 + o]);
+    T acc = T(sw[kOB2 + o]);
 #pragma unroll
-    for (int m = 0; m < kH; ++m) acc += T(st->w[kOW2 + o * kH + m]) * h1[m];
+    for (int m = 0; m < kH; ++m) acc += T(sw[kOW2 + o * kH + m]) * h1[m];
     const T h = leaky(acc, sl);
-    s0 += T(st->w[kOW3 + o]) * h;
-    s1 += T(st->w[kOW3 + kH + o]) * h;
+    s0 += T(sw[kOW3 + o]) * h;
+    s1 += T(sw[kOW3 + kH + o]) * h;
   }
   const T sigma = T(st->sig_scale) * sigmoid(s0) + T(st->sig_shift);
   const T kappa2 = T(st->kap_scale) * sigmoid(s1) + T(st->kap_shift);
@@ -255,7 +280,7 @@ __global__ void __launch_bounds__(kNodes) k_fwd_node(const CtArgs<T> a, int k) {
   if (k >= a.nts[s]) return;
   const int64_t n = int64_t(blockIdx.x) * kNodes + threadIdx.x;
   if (n >= a.plane) return;
-  const int y = int(n / a.W), x = int(n - int64_t(y) * a.W);
+  const int x = int(n / a.ny), y = int(n - int64_t(x) * a.ny);
   T g[9];
   pre_collision(a, s, k, x, y, g);
   collide_bgk(g, a.omega);
@@ -285,7 +310,7 @@ __global__ void __launch_bounds__(kNodes) k_seed(const CtArgs<T> a) {
   const int64_t n = int64_t(blockIdx.x) * kNodes + threadIdx.x;
   double contrib = 0.0;
   if (n < a.plane) {
-    const int y = int(n / a.W), x = int(n - int64_t(y) * a.W);
+    const int x = int(n / a.ny), y = int(n - int64_t(x) * a.ny);
     T lam[9];
 #pragma unroll
     for (int q = 0; q < 9; ++q) lam[q] = T(0);
@@ -319,22 +344,61 @@ __global__ void __launch_bounds__(kNodes) k_seed(const CtArgs<T> a) {
 //   d f_i^eq / d j   = w_i (3 c_i + 9 (c_i.u) c_i - 3 u),
 // lam_f_j = (1 - omega) lam_j + omega (Lambda_rho + c_j . Lambda_j), Lambda the
 // lam-weighted sums of those derivatives.
+// Adjoint of the post-collision state A_kk at node (x, y) from the adjoints
+// LF of the populations pulled at step kk (streaming adjoint) and the moment
+// adjoints the outlet left for the last three columns.
 template <typename T>
-__global__ void __launch_bounds__(kNodes) k_bwd_node(const CtArgs<T> a, int k) {
+__device__ __forceinline__ void state_adjoint(const CtArgs<T>& a, int s, int kk, int x, int y,
+                                              int64_t n, const T* LF, T lam[9]) {
+#pragma unroll
+  for (int q = 0; q < 9; ++q) {
+    const int dx = x + cx(q);
+    const int dy = wrap(y + cy(q), a.ny);
+    T l = T(0);
+    if (dx >= 0 && dx <= a.W - 1) l = LF[q * a.plane + int64_t(dx) * a.ny + dy];
+    if (x == 0 && cx(q) == 1) l += LF[q * a.plane + dy];                  // edge copies
+    lam[q] = l;
+  }
+  if (x >= a.W - 3) {
+    const int c = x - (a.W - 3);
+    const T* M = a.madj + (int64_t(s) * a.ny + y) * kMadj;
+    T ld = M[3 * c], lu = M[3 * c + 1], lv = M[3 * c + 2];
+    if (c == 2) {
+      const T* Ms = a.madj + (int64_t(s) * a.ny + wrap(y - 1, a.ny)) * kMadj;   // row y = r + 1
+      const T* Mn = a.madj + (int64_t(s) * a.ny + wrap(y + 1, a.ny)) * kMadj;   // row y = r - 1
+      ld += Ms[9] - Mn[9];
+      lu += Ms[10] - Mn[10];
+      lv += Ms[11] - Mn[11];
+    }
+    T drho, u, v;
+    node_state(state_at(a, s, kk), a.plane, n, drho, u, v);
+    const T inv = T(1) / (T(1) + drho);
+#pragma unroll
+    for (int q = 0; q < 9; ++q) lam[q] += ld + (lu * (T(cx(q)) - u) + lv * (T(cy(q)) - v)) * inv;
+  }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kNodes) k_bwd(const CtArgs<T> a, int k) {
   const int s = blockIdx.y;
-  if (k >= a.nts[s]) return;
+  const int nt = a.nts[s];
+  if (k >= nt) return;
   const int64_t n = int64_t(blockIdx.x) * kNodes + threadIdx.x;
   if (n >= a.plane) return;
-  const int y = int(n / a.W), x = int(n - int64_t(y) * a.W);
+  const int x = int(n / a.ny), y = int(n - int64_t(x) * a.ny);
+  const int64_t so = int64_t(s) * 9 * a.plane;
+  T lam[9];
+  if (k + 1 == nt) {
+#pragma unroll
+    for (int q = 0; q < 9; ++q) lam[q] = a.lamA[so + q * a.plane + n];
+  } else {
+    state_adjoint(a, s, k + 1, x, y, n, a.lamF[(k + 1) & 1] + so, lam);
+  }
   T g[9];
   pre_collision(a, s, k, x, y, g);
   const Macro<T> m = macro(g);
   const T u = m.jx / m.rho, v = m.jy / m.rho;
   const T usq = T(1.5) * (u * u + v * v);
-  const T* LA = a.lamA + int64_t(s) * 9 * a.plane;
-  T lam[9];
-#pragma unroll
-  for (int q = 0; q < 9; ++q) lam[q] = LA[q * a.plane + n];
   T Lr = T(0), Ljx = T(0), Ljy = T(0);
 #pragma unroll
   for (int q = 0; q < 9; ++q) {
@@ -344,7 +408,7 @@ __global__ void __launch_bounds__(kNodes) k_bwd_node(const CtArgs<T> a, int k) {
     Ljx += wl * (T(3 * cx(q)) + T(9) * cu * T(cx(q)) - T(3) * u);
     Ljy += wl * (T(3 * cy(q)) + T(9) * cu * T(cy(q)) - T(3) * v);
   }
-  T* LF = a.lamF + int64_t(s) * 9 * a.plane;
+  T* LF = a.lamF[k & 1] + so;
   const T om = a.omega;
 #pragma unroll
   for (int q = 0; q < 9; ++q)
@@ -361,24 +425,68 @@ struct alignas(16) BwdSmem {
   T ds[kRows][2];     // adjoint of s_0, s_1
 };
 
+// Sum over the workgroup's rows with four independent accumulators (a fixed
+// order: rows r, r + 4, ... in each, then the four in pairs).
+template <typename F>
+__device__ __forceinline__ double sum_rows(F f) {
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+#pragma unroll 4
+  for (int rr = 0; rr < kRows; rr += 4) {
+    a0 += f(rr);
+    a1 += f(rr + 1);
+    a2 += f(rr + 2);
+    a3 += f(rr + 3);
+  }
+  return (a0 + a1) + (a2 + a3);
+}
+
 template <typename T>
-__global__ void __launch_bounds__(kRows) k_bwd_outlet(const CtArgs<T> a, int k) {
+// Four waves per workgroup: wave 0 takes the 64 outlet rows, all four stage
+// the weights and share the parameter-gradient sums.
+__global__ void __launch_bounds__(kNodes) k_bwd_outlet(const CtArgs<T> a, int k) {
   __shared__ BwdSmem<T> sm;
+  __shared__ float sw[kNP];
   const int s = blockIdx.y;
   if (k >= a.nts[s]) return;                     // uniform over the workgroup
   const int j = threadIdx.x;
+  const bool rowt = j < kRows;
   const int r = blockIdx.x * kRows + j;
   const CtState* st = a.st;
   const T cs2 = T(1.0 / 3.0), cs = T(0.57735026918962576451);
-  if (r < a.ny) {
+  // every global load of the row is issued before the weights are staged
+  // (rows past the end read the last row and contribute nothing)
+  const bool valid = rowt && r < a.ny;
+  const int rl = r < a.ny ? r : a.ny - 1;
+  T* LF = a.lamF[k & 1] + int64_t(s) * 9 * a.plane;
+  T* LP = a.lamP + (int64_t(s) * a.ny + rl) * 3;
+  const int64_t on = int64_t(a.W - 1) * a.ny + rl;
+  OutIn<T> in{};
+  T prev[3] = {T(0), T(0), T(0)}, lp[3] = {T(0), T(0), T(0)}, lf[9];
+  T d1 = T(0), u1 = T(0), v1 = T(0);
+#pragma unroll
+  for (int q = 0; q < 9; ++q) lf[q] = T(0);
+  if (rowt) {
+    in = outlet_inputs(state_at(a, s, k), a.plane, a.W, a.ny, rl);
+    const T* P = a.dts + ((int64_t(s) * (a.n_max + 1) + k) * a.ny + rl) * 3;
+    const T* o3 = a.outs + ((int64_t(s) * a.n_max + k) * a.ny + rl) * 3;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      prev[i] = P[i];
+      lp[i] = LP[i];
+    }
+    d1 = o3[0];
+    u1 = o3[1];
+    v1 = o3[2];
+#pragma unroll
+    for (int q = 0; q < 9; ++q) lf[q] = LF[q * a.plane + on];
+  }
+  stage_weights(st, sw, kNodes);
+  if (valid) {
     // recompute the forward of this row
-    const T* A = state_at(a, s, k);
-    const OutIn<T> in = outlet_inputs(A, a.plane, a.W, a.ny, r);
-    const T* P = a.dts + ((int64_t(s) * (a.n_max + 1) + k) * a.ny + r) * 3;
     T z[kIn];
 #pragma unroll
     for (int i = 0; i < kIn; ++i) {
-      const T f = i < 6 ? in.g[i] : P[i - 6];
+      const T f = i < 6 ? in.g[i] : prev[i - 6];
       z[i] = (f - T(st->mu[i])) / T(st->sd[i]);
       sm.z[j][i] = z[i];
     }
@@ -387,39 +495,33 @@ __global__ void __launch_bounds__(kRows) k_bwd_outlet(const CtArgs<T> a, int k) 
     // into adjoints below), which keeps the FP64 variant within registers
 #pragma unroll 1
     for (int o = 0; o < kH; ++o) {
-      T acc = T(st->w[kOB1 + o]);
+      T acc = T(sw[kOB1 + o]);
 #pragma unroll
-      for (int i = 0; i < kIn; ++i) acc += T(st->w[kOW1 + o * kIn + i]) * z[i];
+      for (int i = 0; i < kIn; ++i) acc += T(sw[kOW1 + o * kIn + i]) * z[i];
       sm.h1[j][o] = leaky(acc, sl);
       sm.d1[j][o] = acc > T(0) ? T(1) : sl;
     }
-    T s0 = T(st->w[kOB3]), s1 = T(st->w[kOB3 + 1]);
+    T s0 = T(sw[kOB3]), s1 = T(sw[kOB3 + 1]);
 #pragma unroll 1
     for (int o = 0; o < kH; ++o) {
-      T acc = T(st->w[kOB2 + o]);
+      T acc = T(sw[kOB2 + o]);
 #pragma unroll 4
-      for (int m = 0; m < kH; ++m) acc += T(st->w[kOW2 + o * kH + m]) * sm.h1[j][m];
+      for (int m = 0; m < kH; ++m) acc += T(sw[kOW2 + o * kH + m]) * sm.h1[j][m];
       const T h = leaky(acc, sl);
       sm.h2[j][o] = h;
       sm.d2[j][o] = acc > T(0) ? T(1) : sl;     // slope, scaled below
-      s0 += T(st->w[kOW3 + o]) * h;
-      s1 += T(st->w[kOW3 + kH + o]) * h;
+      s0 += T(sw[kOW3 + o]) * h;
+      s1 += T(sw[kOW3 + kH + o]) * h;
     }
     const T sg0 = sigmoid(s0), sg1 = sigmoid(s1);
     const T sigma = T(st->sig_scale) * sg0 + T(st->sig_shift);
     const T kappa2 = T(st->kap_scale) * sg1 + T(st->kap_shift);
     const Lodi<T> l = lodi(in, sigma, kappa2, st);
-    const T* o3 = a.outs + ((int64_t(s) * a.n_max + k) * a.ny + r) * 3;
-    const T d1 = o3[0], u1 = o3[1], v1 = o3[2], rho1 = T(1) + d1;
+    const T rho1 = T(1) + d1;
 
     // outlet reconstruction (offset form: g0 = drho' (1 + u') + u' - (g2 + g4)
     // - 2 (g1 + g5 + g8), g3 = g1 - 2/3 rho' u', g6 = g8 + (g4 - g2)/2 - rho' u'/6
     // + rho' v'/2, g7 = g5 - (g4 - g2)/2 - rho' u'/6 - rho' v'/2)
-    T* LF = a.lamF + int64_t(s) * 9 * a.plane;
-    const int64_t on = int64_t(r) * a.W + a.W - 1;
-    T lf[9];
-#pragma unroll
-    for (int q = 0; q < 9; ++q) lf[q] = LF[q * a.plane + on];
     const T ld1 = lf[0] * (T(1) + u1) - lf[3] * T(2.0 / 3.0) * u1 +
                   lf[6] * (-u1 / T(6) + T(0.5) * v1) + lf[7] * (-u1 / T(6) - T(0.5) * v1);
     const T lu1 = rho1 * (lf[0] - T(2.0 / 3.0) * lf[3] - lf[6] / T(6) - lf[7] / T(6));
@@ -435,8 +537,7 @@ __global__ void __launch_bounds__(kRows) k_bwd_outlet(const CtArgs<T> a, int k) 
     LF[8 * a.plane + on] = lf[8] - T(2) * lf[0] + lf[6];
 
     // forward Euler and the stored time derivatives
-    T* LP = a.lamP + (int64_t(s) * a.ny + r) * 3;
-    const T lrt = ld1 + cs2 * LP[0], lut = lu1 + LP[1], lvt = lv1 + LP[2];
+    const T lrt = ld1 + cs2 * lp[0], lut = lu1 + lp[1], lvt = lv1 + lp[2];
     T ldr = ld1, lu = lu1, lv = lv1;             // centre state
     T lg[6] = {T(0), T(0), T(0), T(0), T(0), T(0)};
 
@@ -488,7 +589,7 @@ __global__ void __launch_bounds__(kRows) k_bwd_outlet(const CtArgs<T> a, int k) 
     sm.ds[j][1] = ds1;
 #pragma unroll
     for (int o = 0; o < kH; ++o)
-      sm.d2[j][o] *= T(st->w[kOW3 + o]) * ds0 + T(st->w[kOW3 + kH + o]) * ds1;
+      sm.d2[j][o] *= T(sw[kOW3 + o]) * ds0 + T(sw[kOW3 + kH + o]) * ds1;
     T lz[kIn];
 #pragma unroll
     for (int i = 0; i < kIn; ++i) lz[i] = T(0);
@@ -496,11 +597,11 @@ __global__ void __launch_bounds__(kRows) k_bwd_outlet(const CtArgs<T> a, int k) 
     for (int m = 0; m < kH; ++m) {
       T acc = T(0);
 #pragma unroll
-      for (int o = 0; o < kH; ++o) acc += T(st->w[kOW2 + o * kH + m]) * sm.d2[j][o];
+      for (int o = 0; o < kH; ++o) acc += T(sw[kOW2 + o * kH + m]) * sm.d2[j][o];
       const T d = acc * sm.d1[j][m];
       sm.d1[j][m] = d;
 #pragma unroll
-      for (int i = 0; i < kIn; ++i) lz[i] += T(st->w[kOW1 + m * kIn + i]) * d;
+      for (int i = 0; i < kIn; ++i) lz[i] += T(sw[kOW1 + m * kIn + i]) * d;
     }
 #pragma unroll
     for (int i = 0; i < 6; ++i) lg[i] += lz[i] / T(st->sd[i]);
@@ -521,7 +622,7 @@ __global__ void __launch_bounds__(kRows) k_bwd_outlet(const CtArgs<T> a, int k) 
     M[9] = T(0.5) * cs2 * lg[3];
     M[10] = T(0.5) * lg[4];
     M[11] = T(0.5) * lg[5];
-  } else {
+  } else if (rowt) {
 #pragma unroll
     for (int i = 0; i < kIn; ++i) sm.z[j][i] = T(0);
 #pragma unroll
@@ -529,71 +630,42 @@ __global__ void __launch_bounds__(kRows) k_bwd_outlet(const CtArgs<T> a, int k) 
     sm.ds[j][0] = sm.ds[j][1] = T(0);
   }
   __syncthreads();
-  // parameter gradient of the workgroup's rows, added to its slot
+  // parameter gradient of the workgroup's rows, added to its slot (the
+  // slot values are all requested before the sums, so their latency overlaps)
   double* G = a.gslot + (int64_t(s) * a.nrb + blockIdx.x) * kNP;
-  for (int p = j; p < kNP; p += kRows) {
-    double acc = 0.0;
+  constexpr int kPer = (kNP + kNodes - 1) / kNodes;
+  double old[kPer];
+#pragma unroll
+  for (int u = 0; u < kPer; ++u) {
+    const int p = j + u * kNodes;
+    old[u] = p < kNP ? G[p] : 0.0;
+  }
+#pragma unroll
+  for (int u = 0; u < kPer; ++u) {
+    const int p = j + u * kNodes;
+    if (p >= kNP) break;
+    double acc;
     if (p < kOB1) {
       const int m = p / kIn, i = p - m * kIn;
-      for (int rr = 0; rr < kRows; ++rr) acc += double(sm.d1[rr][m]) * double(sm.z[rr][i]);
+      acc = sum_rows([&](int rr) { return double(sm.d1[rr][m]) * double(sm.z[rr][i]); });
     } else if (p < kOW2) {
       const int m = p - kOB1;
-      for (int rr = 0; rr < kRows; ++rr) acc += double(sm.d1[rr][m]);
+      acc = sum_rows([&](int rr) { return double(sm.d1[rr][m]); });
     } else if (p < kOB2) {
       const int o = (p - kOW2) / kH, m = (p - kOW2) - o * kH;
-      for (int rr = 0; rr < kRows; ++rr) acc += double(sm.d2[rr][o]) * double(sm.h1[rr][m]);
+      acc = sum_rows([&](int rr) { return double(sm.d2[rr][o]) * double(sm.h1[rr][m]); });
     } else if (p < kOW3) {
       const int o = p - kOB2;
-      for (int rr = 0; rr < kRows; ++rr) acc += double(sm.d2[rr][o]);
+      acc = sum_rows([&](int rr) { return double(sm.d2[rr][o]); });
     } else if (p < kOB3) {
       const int o = (p - kOW3) / kH, m = (p - kOW3) - o * kH;
-      for (int rr = 0; rr < kRows; ++rr) acc += double(sm.ds[rr][o]) * double(sm.h2[rr][m]);
+      acc = sum_rows([&](int rr) { return double(sm.ds[rr][o]) * double(sm.h2[rr][m]); });
     } else {
       const int o = p - kOB3;
-      for (int rr = 0; rr < kRows; ++rr) acc += double(sm.ds[rr][o]);
+      acc = sum_rows([&](int rr) { return double(sm.ds[rr][o]); });
     }
-    G[p] += acc;
+    G[p] = old[u] + acc;
   }
-}
-
-template <typename T>
-__global__ void __launch_bounds__(kNodes) k_bwd_gather(const CtArgs<T> a, int k) {
-  const int s = blockIdx.y;
-  if (k >= a.nts[s]) return;
-  const int64_t n = int64_t(blockIdx.x) * kNodes + threadIdx.x;
-  if (n >= a.plane) return;
-  const int y = int(n / a.W), x = int(n - int64_t(y) * a.W);
-  const T* LF = a.lamF + int64_t(s) * 9 * a.plane;
-  T lam[9];
-#pragma unroll
-  for (int q = 0; q < 9; ++q) {
-    const int dx = x + cx(q);
-    const int dy = wrap(y + cy(q), a.ny);
-    T l = T(0);
-    if (dx >= 0 && dx <= a.W - 1) l = LF[q * a.plane + int64_t(dy) * a.W + dx];
-    if (x == 0 && cx(q) == 1) l += LF[q * a.plane + int64_t(dy) * a.W];   // edge copies
-    lam[q] = l;
-  }
-  if (x >= a.W - 3) {
-    const int c = x - (a.W - 3);
-    const T* M = a.madj + (int64_t(s) * a.ny + y) * kMadj;
-    T ld = M[3 * c], lu = M[3 * c + 1], lv = M[3 * c + 2];
-    if (c == 2) {
-      const T* Ms = a.madj + (int64_t(s) * a.ny + wrap(y - 1, a.ny)) * kMadj;   // row y = r + 1
-      const T* Mn = a.madj + (int64_t(s) * a.ny + wrap(y + 1, a.ny)) * kMadj;   // row y = r - 1
-      ld += Ms[9] - Mn[9];
-      lu += Ms[10] - Mn[10];
-      lv += Ms[11] - Mn[11];
-    }
-    T drho, u, v;
-    node_state(state_at(a, s, k), a.plane, n, drho, u, v);
-    const T inv = T(1) / (T(1) + drho);
-#pragma unroll
-    for (int q = 0; q < 9; ++q) lam[q] += ld + (lu * (T(cx(q)) - u) + lv * (T(cy(q)) - v)) * inv;
-  }
-  T* LA = a.lamA + int64_t(s) * 9 * a.plane;
-#pragma unroll
-  for (int q = 0; q < 9; ++q) LA[q * a.plane + n] = lam[q];
 }
 
 __global__ void k_zero(double* p, int64_t n) {
@@ -601,21 +673,58 @@ __global__ void k_zero(double* p, int64_t n) {
   if (i < n) p[i] = 0.0;
 }
 
-// FP64 sum of the gradient slots (segment-major, then row block) and of the
-// loss slots; Adam with bias correction when `update`.
-__global__ void __launch_bounds__(kNodes) k_update(CtState* st, const double* gslot, int64_t nslots,
-                                                  const double* lslot, int64_t nl, int update,
+// Fixed-order FP64 sums in two stages.  k_gsum: workgroup (c, t) adds the
+// gradient slots [c kSlotChunk, (c+1) kSlotChunk) of parameters
+// 64 t .. 64 t + 63, four groups of kSlotChunk/4 consecutive slots combined
+// in order; k_lsum: each workgroup adds kLossChunk consecutive loss slots.
+constexpr int kSlotChunk = 64;
+constexpr int kLossChunk = 4 * kNodes;
+
+__global__ void __launch_bounds__(kNodes) k_gsum(const double* gslot, int64_t nslots,
+                                                double* gpart) {
+  __shared__ double sh[4][64];
+  const int l = threadIdx.x & 63, g = threadIdx.x >> 6;
+  const int p = blockIdx.y * 64 + l;
+  const int64_t i0 = int64_t(blockIdx.x) * kSlotChunk + g * (kSlotChunk / 4);
+  double acc = 0.0;
+  if (p < kNP) {
+#pragma unroll 4
+    for (int j = 0; j < kSlotChunk / 4; ++j) {
+      const int64_t i = i0 + j;
+      if (i < nslots) acc += gslot[i * kNP + p];
+    }
+  }
+  sh[g][l] = acc;
+  __syncthreads();
+  if (g == 0 && p < kNP)
+    gpart[int64_t(blockIdx.x) * kNP + p] = (sh[0][l] + sh[1][l]) + (sh[2][l] + sh[3][l]);
+}
+
+__global__ void __launch_bounds__(kNodes) k_lsum(const double* lslot, int64_t nl, double* lpart) {
+  __shared__ double sh[kNodes / 64];
+  const int64_t i0 = int64_t(blockIdx.x) * kLossChunk + 4 * threadIdx.x;
+  double acc = 0.0;
+#pragma unroll
+  for (int j = 0; j < 4; ++j)
+    if (i0 + j < nl) acc += lslot[i0 + j];
+  const double t = block_sum(acc, sh);
+  if (threadIdx.x == 0) lpart[blockIdx.x] = t;
+}
+
+// Second stage (chunk order) and Adam with bias correction when `update`.
+__global__ void __launch_bounds__(kNodes) k_update(CtState* st, const double* gpart, int ngc,
+                                                  const double* lpart, int nlc, int update,
                                                   double lr, double b1, double b2, double eps,
                                                   double bc1, double bc2) {
   const int p = blockIdx.x * kNodes + threadIdx.x;
   if (p == 0) {
     double t = 0.0;
-    for (int64_t i = 0; i < nl; ++i) t += lslot[i];
+    for (int i = 0; i < nlc; ++i) t += lpart[i];
     st->loss = t;
   }
   if (p >= kNP) return;
   double g = 0.0;
-  for (int64_t i = 0; i < nslots; ++i) g += gslot[i * kNP + p];
+  for (int i = 0; i < ngc; ++i) g += gpart[int64_t(i) * kNP + p];
   st->grad[p] = g;
   if (update) {
     const double m = b1 * st->m[p] + (1.0 - b1) * g;
@@ -630,8 +739,8 @@ __global__ void __launch_bounds__(kNodes) k_update(CtState* st, const double* gs
 size_t align256(size_t b) { return (b + 255) / 256 * 256; }
 
 struct CtLayout {
-  size_t st, traj, outs, dts, lamA, lamF, lamP, madj, ref, nts, gslot, lslot, total;
-  int W, nrb, nlb;
+  size_t st, traj, outs, dts, lamA, lamF, lamP, madj, ref, nts, gslot, lslot, gpart, lpart, total;
+  int W, nrb, nlb, ngc, nlc;      // gradient / loss chunks of the first-stage sums
   int64_t plane;
 };
 
@@ -643,6 +752,8 @@ CtLayout ct_layout(const lbm_cbc_train_params& p) {
   L.plane = int64_t(p.ny) * L.W;
   L.nrb = (p.ny + kRows - 1) / kRows;
   L.nlb = int((L.plane + kNodes - 1) / kNodes);
+  L.ngc = int((int64_t(p.n_seg) * L.nrb + kSlotChunk - 1) / kSlotChunk);
+  L.nlc = int((int64_t(p.n_seg) * L.nlb + kLossChunk - 1) / kLossChunk);
   const size_t e = elem(p.precision), ns = size_t(p.n_seg), ny = size_t(p.ny);
   size_t o = 0;
   auto take = [&](size_t bytes) {
@@ -655,13 +766,15 @@ CtLayout ct_layout(const lbm_cbc_train_params& p) {
   L.outs = take(ns * p.n_max * ny * 3 * e);
   L.dts = take(ns * (p.n_max + 1) * ny * 3 * e);
   L.lamA = take(ns * 9 * size_t(L.plane) * e);
-  L.lamF = take(ns * 9 * size_t(L.plane) * e);
+  L.lamF = take(2 * ns * 9 * size_t(L.plane) * e);
   L.lamP = take(ns * ny * 3 * e);
   L.madj = take(ns * ny * kMadj * e);
   L.ref = take(ns * 3 * ny * p.n_max * e);
   L.nts = take(ns * sizeof(int));
   L.gslot = take(ns * L.nrb * kNP * sizeof(double));
   L.lslot = take(ns * L.nlb * sizeof(double));
+  L.gpart = take(size_t(L.ngc) * kNP * sizeof(double));
+  L.lpart = take(size_t(L.nlc) * sizeof(double));
   L.total = o;
   return L;
 }
@@ -713,7 +826,8 @@ struct lbm_cbc_trainer {
     a.outs = reinterpret_cast<T*>(base + L.outs);
     a.dts = reinterpret_cast<T*>(base + L.dts);
     a.lamA = reinterpret_cast<T*>(base + L.lamA);
-    a.lamF = reinterpret_cast<T*>(base + L.lamF);
+    a.lamF[0] = reinterpret_cast<T*>(base + L.lamF);
+    a.lamF[1] = a.lamF[0] + size_t(p.n_seg) * 9 * size_t(L.plane);
     a.lamP = reinterpret_cast<T*>(base + L.lamP);
     a.madj = reinterpret_cast<T*>(base + L.madj);
     a.ref = reinterpret_cast<const T*>(base + L.ref);
@@ -745,17 +859,22 @@ struct lbm_cbc_trainer {
                        a.gslot, ng);
     hipLaunchKernelGGL(k_seed<T>, gnode, dim3(kNodes), 0, stream, a);
     for (int k = p.n_max - 1; k >= 0; --k) {
-      hipLaunchKernelGGL(k_bwd_node<T>, gnode, dim3(kNodes), 0, stream, a, k);
-      hipLaunchKernelGGL(k_bwd_outlet<T>, grow, dim3(kRows), 0, stream, a, k);
-      hipLaunchKernelGGL(k_bwd_gather<T>, gnode, dim3(kNodes), 0, stream, a, k);
+      hipLaunchKernelGGL(k_bwd<T>, gnode, dim3(kNodes), 0, stream, a, k);
+      hipLaunchKernelGGL(k_bwd_outlet<T>, grow, dim3(kNodes), 0, stream, a, k);
     }
     double bc1 = 1.0, bc2 = 1.0;
     if (update) {
       bc1 = 1.0 - std::pow(p.beta1, double(adam_t));
       bc2 = 1.0 - std::pow(p.beta2, double(adam_t));
     }
+    double* gpart = reinterpret_cast<double*>(base + L.gpart);
+    double* lpart = reinterpret_cast<double*>(base + L.lpart);
+    hipLaunchKernelGGL(k_gsum, dim3(L.ngc, (kNP + 63) / 64), dim3(kNodes), 0, stream, a.gslot,
+                       int64_t(p.n_seg) * L.nrb, gpart);
+    hipLaunchKernelGGL(k_lsum, dim3(L.nlc), dim3(kNodes), 0, stream, a.lslot,
+                       int64_t(p.n_seg) * L.nlb, lpart);
     hipLaunchKernelGGL(k_update, dim3((kNP + kNodes - 1) / kNodes), dim3(kNodes), 0, stream, st,
-                       a.gslot, int64_t(p.n_seg) * L.nrb, a.lslot, int64_t(p.n_seg) * L.nlb,
+                       gpart, L.ngc, lpart, L.nlc,
                        update ? 1 : 0, p.lr, p.beta1, p.beta2, p.eps, bc1, bc2);
     CT_TRY(hipGetLastError());
     return LBM_OK;
@@ -814,11 +933,19 @@ lbm_status lbm_cbc_train_set_segments(lbm_cbc_trainer* t, const double* a0, cons
   const size_t e = elem(p.precision);
   std::vector<char> h(seg_vals * size_t(p.n_seg) * e);
   std::vector<char> hr(ref_vals * size_t(p.n_seg) * e);
-  for (size_t i = 0; i < seg_vals * size_t(p.n_seg); ++i) {
-    const int q = int((i / size_t(L.plane)) % 9);
-    const double g = a0[i] - (q == 0 ? 4.0 / 9.0 : (q <= 4 ? 1.0 / 9.0 : 1.0 / 36.0));
-    if (f64) reinterpret_cast<double*>(h.data())[i] = g;
-    else reinterpret_cast<float*>(h.data())[i] = float(g);
+  // caller layout [seg][9][ny][W] -> device planes [seg][9][W][ny], offsets
+  const size_t W = size_t(L.W), ny = size_t(p.ny);
+  for (size_t sq = 0; sq < size_t(p.n_seg) * 9; ++sq) {
+    const int q = int(sq % 9);
+    const double wq = q == 0 ? 4.0 / 9.0 : (q <= 4 ? 1.0 / 9.0 : 1.0 / 36.0);
+    const double* src = a0 + sq * size_t(L.plane);
+    for (size_t y = 0; y < ny; ++y)
+      for (size_t x = 0; x < W; ++x) {
+        const double g = src[y * W + x] - wq;
+        const size_t d = sq * size_t(L.plane) + x * ny + y;
+        if (f64) reinterpret_cast<double*>(h.data())[d] = g;
+        else reinterpret_cast<float*>(h.data())[d] = float(g);
+      }
   }
   for (size_t i = 0; i < ref_vals * size_t(p.n_seg); ++i) {
     const int c = int((i / (size_t(p.ny) * size_t(p.n_max))) % 3);
@@ -920,10 +1047,16 @@ lbm_status lbm_cbc_train_final_state(lbm_cbc_trainer* t, int32_t seg, double* ho
   std::vector<char> h(vals * e);
   CT_TRY(hipStreamSynchronize(t->stream));
   CT_TRY(hipMemcpy(h.data(), t->base + off, h.size(), hipMemcpyDeviceToHost));
-  for (size_t i = 0; i < vals; ++i) {
-    const int q = int(i / size_t(L.plane));
+  const size_t W = size_t(L.W), ny = size_t(t->p.ny);
+  for (size_t q = 0; q < 9; ++q) {
     const double w = q == 0 ? 4.0 / 9.0 : (q <= 4 ? 1.0 / 9.0 : 1.0 / 36.0);
-    host[i] = (e == 8 ? reinterpret_cast<double*>(h.data())[i] : double(reinterpret_cast<float*>(h.data())[i])) + w;
+    for (size_t y = 0; y < ny; ++y)
+      for (size_t x = 0; x < W; ++x) {
+        const size_t d = q * size_t(L.plane) + x * ny + y;
+        const double g = e == 8 ? reinterpret_cast<double*>(h.data())[d]
+                                : double(reinterpret_cast<float*>(h.data())[d]);
+        host[q * size_t(L.plane) + y * W + x] = g + w;
+      }
   }
   return LBM_OK;
 }

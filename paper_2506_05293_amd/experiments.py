@@ -266,12 +266,14 @@ def naca_study(networks, aoas=(0.0, 4.0, 8.0), steps=200_000, precision="fp32", 
 
 
 def vortex_study(steps=600, every=10, nx=200, ny=400, reference_nx=1000, precision="fp32",
-                 settings=None, progress=_noop):
+                 settings=None, vortex=None, progress=_noop):
     """Convected vortex (Sec. 4.1): RMS density error over the truncated
     lattice against the same flow on a lattice reference_nx long, every
     `every` steps, for the Zou & He pressure outlet and characteristic
-    outlets with fixed (sigma, kappa_2)."""
-    ref_case = workloads.convected_vortex(nx=reference_nx, ny=ny)
+    outlets with fixed (sigma, kappa_2) or a tuning network (a dict).
+    `vortex` overrides parameters of workloads.convected_vortex."""
+    vortex = vortex or {}
+    ref_case = workloads.convected_vortex(nx=reference_nx, ny=ny, **vortex)
     ma, u0 = ref_case["ma"], ref_case["u0"]
     if settings is None:
         settings = {"cbc_s0_k0": (0.0, 0.0), "cbc_s0_kMa": (0.0, ma), "cbc_s0.25_kMa": (0.25, ma),
@@ -298,8 +300,9 @@ def vortex_study(steps=600, every=10, nx=200, ny=400, reference_nx=1000, precisi
 
     ref, _, _ = run(ref_case, None)
     progress(f"vortex reference {reference_nx}", {})
-    case = workloads.convected_vortex(nx=nx, ny=ny)
-    out = {"t": list(range(every, steps + 1, every)), "ma": ma, "tau": case["tau"], "runs": {}}
+    case = workloads.convected_vortex(nx=nx, ny=ny, **vortex)
+    out = {"t": list(range(every, steps + 1, every)), "ma": ma, "tau": case["tau"],
+           "vortex": vortex, "runs": {}}
     for name, par in [("zouhe", None)] + list(settings.items()):
         rho, ok, wall = run(case, par)
         err = np.sqrt(np.mean((rho - ref) ** 2, axis=(1, 2)))
@@ -337,7 +340,7 @@ def _outlet_features(strip, prev):
 def cbc_training_study(n_ts=(5, 10, 25), starts=tuple(range(1, 551, 5)), adam_steps=2000,
                        lr=1e-3, seed=0, nx=200, ny=400, reference_nx=1000, precision="fp32",
                        sigma_range=(0.0, 1.0), kappa_range=(0.0, 1.0), init=(0.25, 0.3),
-                       eval_steps=600, progress=_noop):
+                       eval_steps=600, holdout=None, progress=_noop):
     """Closed-loop training of the CBC tuning network (Sec. 4.2) on the
     convected vortex.  The reference runs on a lattice reference_nx long;
     from its states at the steps `starts` (every 5 steps from 1 to 546: 110
@@ -349,7 +352,11 @@ def cbc_training_study(n_ts=(5, 10, 25), starts=tuple(range(1, 551, 5)), adam_st
     outputs to sigma_range and kappa_range; the network starts near
     (sigma, kappa_2) = init.  Adam on the full set of segments.  Afterwards
     the vortex comparison of vortex_study with the trained network beside
-    the fixed settings."""
+    the fixed settings, and on the held-out vortices of `holdout` (name ->
+    parameters of workloads.convected_vortex)."""
+    if holdout is None:
+        holdout = {"weak_small": dict(beta=0.3, rc=15.0), "ma0.2": dict(ma=0.2),
+                   "strong": dict(beta=0.8, rc=25.0, x0=140.0)}
     ref_case = workloads.convected_vortex(nx=reference_nx, ny=ny)
     ma, u0, tau = ref_case["ma"], ref_case["u0"], ref_case["tau"]
     n_max = max(n_ts)
@@ -429,6 +436,15 @@ def cbc_training_study(n_ts=(5, 10, 25), starts=tuple(range(1, 551, 5)), adam_st
                                 "cbc_init": tuple(init), "nn_cbc_untrained": net,
                                 "nn_cbc_trained": trained},
                       progress=progress)
+    # vortices the network has not seen, each against its own long lattice
+    held_out = {}
+    for name, vx in holdout.items():
+        m = vx.get("ma", 0.3)
+        held_out[name] = vortex_study(steps=eval_steps, nx=nx, ny=ny, reference_nx=reference_nx,
+                                      precision=precision, vortex=vx,
+                                      settings={"cbc_s0.25_kMa": (0.25, m),
+                                                "nn_cbc_trained": trained},
+                                      progress=progress)
     return {"segments": len(nts), "n_ts": list(n_ts), "starts": [int(starts[0]), int(starts[-1]),
                                                                len(starts)],
             "adam_steps": adam_steps, "lr": lr, "precision": precision, "train_seconds": train_s,
@@ -437,7 +453,7 @@ def cbc_training_study(n_ts=(5, 10, 25), starts=tuple(range(1, 551, 5)), adam_st
             "loss_per_n_t": per_nt, "network": {k: (np.asarray(v).tolist()
                                                     if isinstance(v, np.ndarray) else v)
                                                 for k, v in trained.items()},
-            "vortex": ev}
+            "vortex": ev, "held_out": held_out}
 
 
 def scaling_study(network, re_list=(10.0, 20.0, 50.0, 100.0, 200.0), tau=0.6, steps=150_000,
