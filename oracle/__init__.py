@@ -26,6 +26,9 @@ Modules
   cbc_train    closed-loop training of the tuning network (Sec. 4.2): the
                step re-expressed in torch FP64, segment loss over Omega_s,
                gradient by reverse-mode differentiation
+  d3q19        the step carried to three dimensions (D3Q19, BGK, Zou & He
+               faces with transverse corrections, half-way bounce-back,
+               momentum exchange)
   splitmix64   the sequential SplitMix64 generator (Steele, Lea & Flood 2014)
   observables  drag/lift coefficients (Eq. 13) and the Strouhal number
 
