@@ -14,7 +14,7 @@ LIB = os.path.join(HERE, "liblbm.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
-SOURCES = ["lbm_kernels.hip", "lbm_api.cpp", "mlp_train.hip", "lbm_batch.hip", "cbc_train.hip"]
+SOURCES = ["lbm_kernels.hip", "lbm_api.cpp", "mlp_train.hip", "lbm_batch.hip", "cbc_train.hip", "lbm3d.hip"]
 
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-x", "hip",
          # packed FP32 instructions are kept out of the generated code

@@ -73,6 +73,20 @@ class lbm_cbc_train_params(ctypes.Structure):
                 ("stream", ctypes.c_void_p)]
 
 
+class lbm3d_params(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
+                ("precision", ctypes.c_int32), ("lateral_y", ctypes.c_int32),
+                ("lateral_z", ctypes.c_int32), ("xbc", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("tau", ctypes.c_double), ("u_in", ctypes.c_double), ("rho_out", ctypes.c_double),
+                ("history_cap", ctypes.c_int64), ("stream", ctypes.c_void_p)]
+
+
+class lbm3d_force_out(ctypes.Structure):
+    _fields_ = [("fx", ctypes.c_double), ("fy", ctypes.c_double), ("fz", ctypes.c_double),
+                ("dmass", ctypes.c_double), ("step", ctypes.c_int64), ("nonfinite", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
+
+
 class lbm_train_params(ctypes.Structure):
     _fields_ = [("batch", ctypes.c_int32), ("lr", ctypes.c_double), ("beta1", ctypes.c_double),
                 ("beta2", ctypes.c_double), ("eps", ctypes.c_double), ("seed", ctypes.c_uint64),
@@ -164,6 +178,17 @@ def library():
             "lbm_train_get_weights": (I32, [VP, P(lbm_mlp_host)]),
             "lbm_train_gradient": (I32, [VP, VP, ctypes.c_int32, _FP, DP]),
             "lbm_train_sample_rows": (I32, [VP, I64, P(ctypes.c_int32)]),
+            "lbm3d_workspace_bytes": (ctypes.c_size_t, [P(lbm3d_params)]),
+            "lbm3d_create": (I32, [P(lbm3d_params), VP, ctypes.c_size_t, P(VP)]),
+            "lbm3d_destroy": (I32, [VP]),
+            "lbm3d_set_geometry": (I32, [VP, P(ctypes.c_uint8)]),
+            "lbm3d_init_fields": (I32, [VP, DP, DP]),
+            "lbm3d_step": (I32, [VP, I64]),
+            "lbm3d_forces": (I32, [VP, P(lbm3d_force_out)]),
+            "lbm3d_force_history": (I32, [VP, DP, DP, DP, I64, P(I64)]),
+            "lbm3d_read_populations": (I32, [VP, DP]),
+            "lbm3d_write_populations": (I32, [VP, DP]),
+            "lbm3d_sync": (I32, [VP]),
             "lbm_cbc_train_workspace_bytes": (ctypes.c_size_t, [P(lbm_cbc_train_params)]),
             "lbm_cbc_train_create": (I32, [P(lbm_cbc_train_params), VP, ctypes.c_size_t, P(VP)]),
             "lbm_cbc_train_destroy": (I32, [VP]),
@@ -709,6 +734,121 @@ class CbcTrainer:
 
     def final_state(self, seg):
         return lbm_cbc_train_final_state(self.t, seg, self.ny, self.width)
+
+
+# --- the D3Q19 step (include/lbm3d.h) -----------------------------------------------
+
+def lbm3d_workspace_bytes(params):
+    n = library().lbm3d_workspace_bytes(ctypes.byref(params))
+    if n == 0:
+        raise LbmError(LBM_EINVAL, "lbm3d_workspace_bytes", library().lbm_last_error().decode())
+    return n
+
+
+def lbm3d_create(params, workspace_ptr, nbytes):
+    c = ctypes.c_void_p()
+    _check(library().lbm3d_create(ctypes.byref(params), ctypes.c_void_p(workspace_ptr), nbytes,
+                                  ctypes.byref(c)), "lbm3d_create")
+    return c
+
+
+def lbm3d_destroy(c):
+    return _check(library().lbm3d_destroy(c), "lbm3d_destroy")
+
+
+def lbm3d_set_geometry(c, mask):
+    m = np.ascontiguousarray(mask, dtype=np.uint8)
+    return _check(library().lbm3d_set_geometry(c, m.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8))),
+                  "lbm3d_set_geometry")
+
+
+def lbm3d_init_fields(c, rho, u):
+    rho = np.ascontiguousarray(rho, dtype=np.float64)
+    u = np.ascontiguousarray(u, dtype=np.float64)
+    return _check(library().lbm3d_init_fields(c, _dptr(rho), _dptr(u)), "lbm3d_init_fields")
+
+
+def lbm3d_step(c, nsteps):
+    return _check(library().lbm3d_step(c, int(nsteps)), "lbm3d_step")
+
+
+def lbm3d_forces(c, allow_unstable=False):
+    out = lbm3d_force_out()
+    st = library().lbm3d_forces(c, ctypes.byref(out))
+    if not (allow_unstable and st == LBM_EUNSTABLE):
+        _check(st, "lbm3d_forces")
+    return out
+
+
+def lbm3d_force_history(c, cap):
+    fx, fy, fz = np.zeros(cap), np.zeros(cap), np.zeros(cap)
+    n = ctypes.c_int64()
+    _check(library().lbm3d_force_history(c, _dptr(fx), _dptr(fy), _dptr(fz), cap, ctypes.byref(n)),
+           "lbm3d_force_history")
+    return fx[:n.value], fy[:n.value], fz[:n.value]
+
+
+def lbm3d_read_populations(c, nx, ny, nz):
+    out = np.empty((19, nz, ny, nx))
+    _check(library().lbm3d_read_populations(c, _dptr(out)), "lbm3d_read_populations")
+    return out
+
+
+def lbm3d_write_populations(c, f):
+    f = np.ascontiguousarray(f, dtype=np.float64)
+    return _check(library().lbm3d_write_populations(c, _dptr(f)), "lbm3d_write_populations")
+
+
+def lbm3d_sync(c):
+    return _check(library().lbm3d_sync(c), "lbm3d_sync")
+
+
+class Lattice3D:
+    """One D3Q19 lattice on the current device; mask (nz, ny, nx) with 0 fluid
+    and 1 body; lateral 'walls' / 'periodic' or a (y, z) pair."""
+
+    def __init__(self, mask, tau, *, precision="fp32", lateral="walls", xbc="inout", u_in=0.05,
+                 rho_out=1.0, history_cap=0):
+        import torch
+        mask = np.ascontiguousarray(mask, dtype=np.uint8)
+        self.nz, self.ny, self.nx = mask.shape
+        lat_y, lat_z = (lateral, lateral) if isinstance(lateral, str) else lateral
+        self.stream = torch.cuda.current_stream()
+        self.params = lbm3d_params(self.nx, self.ny, self.nz, _PREC[precision], _LAT[lat_y],
+                                   _LAT[lat_z], _XBC[xbc], 0, tau, u_in, rho_out, history_cap,
+                                   ctypes.c_void_p(self.stream.cuda_stream))
+        nbytes = lbm3d_workspace_bytes(self.params)
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+        self.ctx = lbm3d_create(self.params, self.workspace.data_ptr(), nbytes)
+        lbm3d_set_geometry(self.ctx, mask)
+        self.history_cap = history_cap
+
+    def __del__(self):
+        c = getattr(self, "ctx", None)
+        if c is not None and _lib is not None:
+            _lib.lbm3d_destroy(c)
+            self.ctx = None
+
+    def init_fields(self, rho, u):
+        lbm3d_init_fields(self.ctx, rho, u)
+
+    def step(self, n=1):
+        lbm3d_step(self.ctx, n)
+
+    def sync(self):
+        lbm3d_sync(self.ctx)
+
+    def forces(self, allow_unstable=False):
+        return lbm3d_forces(self.ctx, allow_unstable)
+
+    def force_history(self):
+        return lbm3d_force_history(self.ctx, self.history_cap)
+
+    def populations(self):
+        return lbm3d_read_populations(self.ctx, self.nx, self.ny, self.nz)
+
+    def write_populations(self, f):
+        lbm3d_write_populations(self.ctx, f)
 
 
 # --- convenience: one lattice with a torch-owned workspace --------------------------

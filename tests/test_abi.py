@@ -5,6 +5,7 @@ import glob
 import os
 import re
 
+import numpy as np
 import pytest
 
 from paper_2506_05293_amd import lbm
@@ -144,3 +145,42 @@ def test_cbc_trainer_needs_segments_and_network_before_a_step():
             call()
         assert e.value.status == lbm.LBM_ESTATE
     lbm.lbm_cbc_train_destroy(t)
+
+
+def _p3(**kw):
+    p = lbm.lbm3d_params(64, 20, 12, lbm.LBM_FP32_OFFSET, lbm.LBM_LATERAL_WALLS,
+                         lbm.LBM_LATERAL_PERIODIC, lbm.LBM_X_INOUT, 0, 0.6, 0.05, 1.0, 10, None)
+    for k, v in kw.items():
+        setattr(p, k, v)
+    return p
+
+
+def test_d3q19_workspace_holds_two_pitched_buffers():
+    b32 = lbm.lbm3d_workspace_bytes(_p3())
+    b64 = lbm.lbm3d_workspace_bytes(_p3(precision=lbm.LBM_FP64))
+    pop32 = 2 * 19 * 12 * 20 * 64 * 4
+    assert b32 >= pop32 and b64 - b32 == pop32
+
+
+@pytest.mark.parametrize("field,value", [("nx", 3), ("nz", 2), ("precision", lbm.LBM_FP16_OFFSET),
+                                         ("lateral_y", 5), ("xbc", 9), ("tau", 0.5),
+                                         ("u_in", 0.6), ("rho_out", 0.0), ("history_cap", -1)])
+def test_d3q19_rejects_bad_parameters(field, value):
+    with pytest.raises(lbm.LbmError) as e:
+        lbm.lbm3d_workspace_bytes(_p3(**{field: value}))
+    assert e.value.status == lbm.LBM_EINVAL
+
+
+def test_d3q19_needs_a_geometry_before_stepping():
+    p = _p3()
+    need = lbm.lbm3d_workspace_bytes(p)
+    c = lbm.lbm3d_create(p, 1 << 20, need)               # never dereferenced
+    with pytest.raises(lbm.LbmError) as e:
+        lbm.lbm3d_step(c, 1)
+    assert e.value.status == lbm.LBM_ESTATE
+    mask = np.zeros((12, 20, 64), np.uint8)
+    mask[:, :, 0] = 1
+    with pytest.raises(lbm.LbmError) as e:
+        lbm.lbm3d_set_geometry(c, mask)                  # a solid inlet plane
+    assert e.value.status == lbm.LBM_EINVAL
+    lbm.lbm3d_destroy(c)
