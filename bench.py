@@ -187,6 +187,46 @@ def time_cbc_training(torch, steps=20, warmup=3):
                        "columns, FP32, forward + adjoint + Adam"}
 
 
+# Algorithmic HBM bytes per node and step of the D3Q19 step (FP32 offsets):
+# 19 pulled reads + 19 writes.
+D3Q19_BYTES_PER_NODE = 4 * 38
+
+
+def time_d3q19(torch, steps=500, warmup=50, nx=256, ny=128, nz=128):
+    """The D3Q19 step on a walled channel nx x ny x nz with a sphere of
+    diameter ny/4 at x = nx/4, FP32 offsets, Re = 100 (u_in 0.05)."""
+    from paper_2506_05293_amd import lbm
+    d = ny / 4
+    Z, Y, X = np.mgrid[0:nz, 0:ny, 0:nx]
+    mask = (((X - nx / 4) ** 2 + (Y - (ny - 1) / 2) ** 2 + (Z - (nz - 1) / 2) ** 2)
+            <= (d / 2) ** 2).astype(np.uint8)
+    tau = 0.5 + 3 * 0.05 * d / 100
+    lat = lbm.Lattice3D(mask, tau, precision="fp32", lateral="walls", u_in=0.05,
+                        history_cap=steps + warmup)
+    lat.step(warmup)
+    lat.sync()
+    stream = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    lat.step(steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    fo = lat.forces()
+    assert fo.nonfinite == 0
+    nodes = nx * ny * nz
+    gbs = D3Q19_BYTES_PER_NODE * nodes / (ms * 1e-3) / 1e9
+    return {"mlups": nodes / (ms * 1e-3) / 1e6, "ms_per_step": ms,
+            "roofline": {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": gbs / HBM_PEAK_GBS, "bytes_per_node": D3Q19_BYTES_PER_NODE,
+                         "kernel": "k3_step (force sums reduced every 16 steps by k3_reduce)"},
+            "drag_fx_last": fo.fx,
+            "setting": f"D3Q19 BGK {nx}x{ny}x{nz} walled channel, sphere D={d:g} at x={nx // 4}, "
+                       "FP32 offsets, Zou-He faces, Re=100"}
+
+
 def cpu_baseline(nx, ny, seconds=15.0):
     """The FP64 oracle (single thread) on the same lattice for as many whole
     steps as fit in ~`seconds` (at least one)."""
@@ -354,6 +394,7 @@ def main():
                     help="steps of Zou & He before the neural outflow is switched on (studies)")
     ap.add_argument("--no-cbc-train", action="store_true",
                     help="skip timing the closed-loop trainer of the CBC tuning network")
+    ap.add_argument("--no-3d", action="store_true", help="skip the D3Q19 step")
     ap.add_argument("--calibration-copy", action="store_true")
     ap.add_argument("--write-traffic", nargs=4, metavar="CSV")
     args = ap.parse_args()
@@ -409,6 +450,7 @@ def main():
         del lat
     torch.cuda.synchronize()
     cbc_training = None if args.no_cbc_train else time_cbc_training(torch)
+    d3q19 = None if args.no_3d else time_d3q19(torch)
 
     accuracy = None
     if not args.no_accuracy:
@@ -439,6 +481,7 @@ def main():
         "nn_outflow": nn,
         "cbc_outflow": cbc,
         "cbc_training": cbc_training,
+        "d3q19": d3q19,
         "accuracy": accuracy,
         "cpu_baseline": None if args.no_cpu_baseline else cpu_baseline(nx, ny),
     }

@@ -10,8 +10,10 @@
 // node's link word -- bounces back half-way and adds the momentum exchange
 // to the force), the Zou & He face at x = 0 or x = nx-1, BGK collision in
 // offset form g = f - w, non-temporal stores.  Each workgroup leaves one FP64
-// partial of (F_x, F_y, F_z, sum rho - 1); k3_reduce adds them in a fixed
-// order and appends the force to the history.
+// partial of (F_x, F_y, F_z, sum rho - 1) in a ring of kRing step slots;
+// k3_reduce adds them in a fixed order, one workgroup per step, for up to
+// kRing steps per launch (and before any read of the forces), and appends
+// the forces to the history.
 //
 // HBM traffic per node and step (FP32): 19 loads + 19 stores + the link
 // word = 156 B (152 B algorithmic).
@@ -182,7 +184,7 @@ __global__ void __launch_bounds__(kB3) k3_step(const Step3 L) {
         if (xout) {
           g[q] = T(0);                                        // unknown of a face
         } else if (bb) {
-          g[q] = A[opp3(q) * L.plane + idx];
+          g[q] = __builtin_nontemporal_load(A + opp3(q) * L.plane + idx);
           if ((lk >> q) & 1u) {                               // a body link
             const T m = T(-2) * (g[q] + w3<T>(q));
             fx += m * T(c3(q, 0));
@@ -190,7 +192,7 @@ __global__ void __launch_bounds__(kB3) k3_step(const Step3 L) {
             fz += m * T(c3(q, 2));
           }
         } else {
-          g[q] = A[q * L.plane + (int64_t(sz) * L.ny + sy) * L.pitch + sx];
+          g[q] = __builtin_nontemporal_load(A + q * L.plane + (int64_t(sz) * L.ny + sy) * L.pitch + sx);
         }
       }
       if (!L.xper) {
@@ -215,30 +217,40 @@ __global__ void __launch_bounds__(kB3) k3_step(const Step3 L) {
   }
 }
 
-// Fixed-order sum of the workgroup partials: thread t adds a contiguous
-// range, then a tree; appends the force to the history and records a
-// non-finite sum.
-__global__ void __launch_bounds__(kB3) k3_reduce(const double* part, int nblocks, double* last,
-                                                 double* hist, int64_t t, int64_t cap) {
-  __shared__ double sh[kB3][4];
-  const int per = (nblocks + kB3 - 1) / kB3;
-  const int b0 = threadIdx.x * per, b1 = min(nblocks, b0 + per);
+// Fixed-order sum of the workgroup partials of steps t0 .. t0 + gridDim.x - 1
+// (workgroup j takes step t0 + j, ring slot (t0 + j) % kRing): thread t adds
+// partials t, t + 1024, ... (coalesced reads), then a tree; appends the force
+// to the history, the last step also to `last`, and records a non-finite sum.
+constexpr int kRed3 = 1024;
+constexpr int kRing = 16;
+
+__global__ void __launch_bounds__(kRed3) k3_reduce(const double* ring, int nblocks, double* last,
+                                                   double* hist, int64_t t0, int64_t cap) {
+  __shared__ double sh[4][kRed3];
+  const int64_t t = t0 + blockIdx.x;
+  const double* part = ring + (t % kRing) * int64_t(nblocks) * 4;
   double s[4] = {0.0, 0.0, 0.0, 0.0};
-  for (int b = b0; b < b1; ++b)
-    for (int c = 0; c < 4; ++c) s[c] += part[int64_t(b) * 4 + c];
-  for (int c = 0; c < 4; ++c) sh[threadIdx.x][c] = s[c];
+  for (int b = threadIdx.x; b < nblocks; b += kRed3) {
+    const double4 v = reinterpret_cast<const double4*>(part)[b];
+    s[0] += v.x;
+    s[1] += v.y;
+    s[2] += v.z;
+    s[3] += v.w;
+  }
+  for (int c = 0; c < 4; ++c) sh[c][threadIdx.x] = s[c];
   __syncthreads();
-  for (int o = kB3 / 2; o >= 1; o >>= 1) {
+  for (int o = kRed3 / 2; o >= 1; o >>= 1) {
     if (int(threadIdx.x) < o)
-      for (int c = 0; c < 4; ++c) sh[threadIdx.x][c] += sh[threadIdx.x + o][c];
+      for (int c = 0; c < 4; ++c) sh[c][threadIdx.x] += sh[c][threadIdx.x + o];
     __syncthreads();
   }
   if (threadIdx.x == 0) {
-    for (int c = 0; c < 4; ++c) last[c] = sh[0][c];
-    if (!isfinite(sh[0][0]) || !isfinite(sh[0][1]) || !isfinite(sh[0][2]) || !isfinite(sh[0][3]))
+    if (blockIdx.x == gridDim.x - 1)
+      for (int c = 0; c < 4; ++c) last[c] = sh[c][0];
+    if (!isfinite(sh[0][0]) || !isfinite(sh[1][0]) || !isfinite(sh[2][0]) || !isfinite(sh[3][0]))
       last[4] = 1.0;
     if (t < cap)
-      for (int c = 0; c < 3; ++c) hist[t * 3 + c] = sh[0][c];
+      for (int c = 0; c < 3; ++c) hist[t * 3 + c] = sh[c][0];
   }
 }
 
@@ -267,7 +279,7 @@ Layout3 layout3(const lbm3d_params& p) {
   L.A = take(size_t(19) * L.plane * esz(p.precision));
   L.B = take(size_t(19) * L.plane * esz(p.precision));
   L.links = take(size_t(L.plane) * 4);
-  L.part = take(size_t(L.nblocks) * 4 * 8);
+  L.part = take(size_t(kRing) * L.nblocks * 4 * 8);
   L.last = take(8 * 8);
   L.hist = take(size_t(p.history_cap) * 3 * 8);
   L.total = o;
@@ -310,6 +322,21 @@ struct lbm3d_ctx {
   bool has_geometry = false;
   int cur = 0;              // which buffer holds the state: 0 = A, 1 = B
   int64_t t = 0;
+  int64_t pending = 0;      // steps whose partials are not yet reduced
+
+  // reduce the partials of the pending steps (one workgroup per step)
+  lbm_status flush() {
+    if (pending) {
+      hipLaunchKernelGGL(k3_reduce, dim3(unsigned(pending)), dim3(kRed3), 0, stream,
+                         reinterpret_cast<const double*>(base + L.part), L.nblocks,
+                         reinterpret_cast<double*>(base + L.last),
+                         reinterpret_cast<double*>(base + L.hist), t - pending,
+                         int64_t(p.history_cap));
+      pending = 0;
+      L3_TRY(hipGetLastError());
+    }
+    return LBM_OK;
+  }
   std::vector<uint8_t> mask;
 
   size_t bufoff(int which) const { return which == 0 ? L.A : L.B; }
@@ -431,6 +458,7 @@ lbm_status lbm3d_set_geometry(lbm3d_ctx* c, const uint8_t* host_mask) {
   L3_TRY(hipMemsetAsync(c->base + c->L.last, 0, 8 * 8, c->stream));
   c->has_geometry = true;
   c->t = 0;
+  c->pending = 0;
   return c->upload(c->equilibrium_state(nullptr, nullptr));
 }
 
@@ -462,19 +490,21 @@ lbm_status lbm3d_step(lbm3d_ctx* c, int64_t nsteps) {
   s.omega = 1.0 / p.tau;
   s.u_in = p.u_in;
   s.one_minus_rho_out = 1.0 - p.rho_out;
-  double* last = reinterpret_cast<double*>(c->base + L.last);
-  double* hist = reinterpret_cast<double*>(c->base + L.hist);
+  double* ring = reinterpret_cast<double*>(c->base + L.part);
   for (int64_t i = 0; i < nsteps; ++i) {
     s.A = c->base + c->bufoff(c->cur);
     s.B = c->base + c->bufoff(1 - c->cur);
+    s.part = ring + (c->t % kRing) * int64_t(L.nblocks) * 4;
     if (p.precision == LBM_FP64)
       hipLaunchKernelGGL(k3_step<double>, dim3(L.nblocks), dim3(kB3), 0, c->stream, s);
     else
       hipLaunchKernelGGL(k3_step<float>, dim3(L.nblocks), dim3(kB3), 0, c->stream, s);
-    hipLaunchKernelGGL(k3_reduce, dim3(1), dim3(kB3), 0, c->stream, s.part, L.nblocks, last, hist,
-                       c->t, int64_t(p.history_cap));
     c->cur = 1 - c->cur;
     ++c->t;
+    if (++c->pending == kRing) {
+      lbm_status st = c->flush();
+      if (st) return st;
+    }
   }
   L3_TRY(hipGetLastError());
   return LBM_OK;
@@ -483,6 +513,8 @@ lbm_status lbm3d_step(lbm3d_ctx* c, int64_t nsteps) {
 lbm_status lbm3d_forces(lbm3d_ctx* c, lbm3d_force_out* out) {
   if (!c || !out) return set_error(LBM_EINVAL, "NULL argument");
   double h[8];
+  lbm_status st = c->flush();
+  if (st) return st;
   L3_TRY(hipStreamSynchronize(c->stream));
   L3_TRY(hipMemcpy(h, c->base + c->L.last, sizeof(h), hipMemcpyDeviceToHost));
   out->fx = h[0];
@@ -500,6 +532,8 @@ lbm_status lbm3d_force_history(lbm3d_ctx* c, double* fx, double* fy, double* fz,
   if (!c || !fx || !fy || !fz || !n || cap < 0) return set_error(LBM_EINVAL, "bad argument");
   const int64_t m = std::min(std::min(cap, c->t), int64_t(c->p.history_cap));
   std::vector<double> h(size_t(m) * 3);
+  lbm_status st = c->flush();
+  if (st) return st;
   L3_TRY(hipStreamSynchronize(c->stream));
   if (m) L3_TRY(hipMemcpy(h.data(), c->base + c->L.hist, h.size() * 8, hipMemcpyDeviceToHost));
   for (int64_t i = 0; i < m; ++i) {
@@ -545,6 +579,8 @@ lbm_status lbm3d_write_populations(lbm3d_ctx* c, const double* host) {
 
 lbm_status lbm3d_sync(lbm3d_ctx* c) {
   if (!c) return set_error(LBM_EINVAL, "NULL context");
+  lbm_status st = c->flush();
+  if (st) return st;
   L3_TRY(hipStreamSynchronize(c->stream));
   return LBM_OK;
 }
