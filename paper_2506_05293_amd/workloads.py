@@ -98,3 +98,25 @@ def convected_vortex(nx=200, ny=400, ma=0.3, rc=20.0, beta=0.5, x0=150.0, re=750
     nu = u0 * length / re
     return dict(mask=np.zeros((ny, nx), np.uint8), tau=3.0 * nu + 0.5, rho=rho, ux=ux, uy=uy,
                 u0=u0, ma=ma, nx=nx, ny=ny)
+
+
+def smooth_fields(shape, u_in, amp=0.02, modes=4, seed=0):
+    """Seeded smooth initial fields on a lattice of `shape` ((ny, nx) or
+    (nz, ny, nx)): rho = 1 + a sum of `modes` sine modes of amplitude
+    amp / modes, and u = (u_in, 0[, 0]) plus such sums in every component;
+    wavenumbers 1..4 along each axis and phases are drawn from
+    default_rng(seed).  Returns rho and u (components first)."""
+    rng = np.random.default_rng(seed)
+    grids = np.meshgrid(*[np.arange(n, dtype=np.float64) for n in shape], indexing="ij")
+
+    def field():
+        f = np.zeros(shape)
+        for _ in range(modes):
+            arg = sum(2.0 * math.pi * rng.integers(1, 5) * g / n + rng.uniform(0, 2 * math.pi)
+                      for g, n in zip(grids, shape))
+            f += amp / modes * np.sin(arg)
+        return f
+    rho = 1.0 + field()
+    u = np.stack([field() for _ in shape][::-1])       # x component first
+    u[0] += u_in
+    return rho, u

@@ -3,8 +3,10 @@
 A lattice of a batch must evolve bit for bit like the same lattice stepped
 alone (FP32 offsets, vector tile: the same node code), whatever the other
 lattices do; its force history agrees to FP32 summation order.  Logged
-samples are checked against the pull of the state read back just before the
-logging step, computed by the oracle's streaming."""
+samples are the pulled populations of the logging step: bit for bit the
+permutation of the state read back just before it (a copy, checked by
+index), and within FP32 rounding the oracle's own run from the same seeded
+start."""
 import numpy as np
 import pytest
 
@@ -65,17 +67,27 @@ def test_logging_matches_pull_of_read_state():
     b = lbm.Batch(lats, collision="mrt", lateral="periodic", noise_amp=1e-3,
                   log_start=5, log_every=3, log_slots=2, log_rows=ny)
 
-    def pull():
-        out = []
-        for i, L in enumerate(lats):
-            o = Oracle(L["mask"], L["tau"], collision="mrt", lateral="periodic")
-            out.append(o.stream(b.populations(i)) - W[:, None, None])    # offsets
-        return out
-    expect = []
+    cx = [0, 1, 0, -1, 0, 1, -1, -1, 1]
+    cy = [0, 0, 1, 0, -1, 1, 1, -1, -1]
+
+    def pull(f):
+        # the logged columns are interior and free of solids, the rows
+        # periodic: population q of node (x, y) is f_q(x - c_x, y - c_y)
+        return np.stack([np.roll(np.roll(f[q], cy[q], axis=0), cx[q], axis=1)
+                         for q in range(9)]) - W[:, None, None]                   # offsets
+    oracles = [Oracle(L["mask"], L["tau"], collision="mrt", lateral="periodic", u_in=0.05,
+                      noise_amp=1e-3, seed=L["seed"]) for L in lats]
+    expect, indep = [], []
     b.step(5)                     # the next step (5 taken before it) logs slot 0
-    expect.append(pull())
+    expect.append([pull(b.populations(i)) for i in range(2)])
+    for o in oracles:
+        o.step(5)
+    indep.append([pull(o.post_collision()) for o in oracles])
     b.step(3)                     # ... and the step after 8 logs slot 1
-    expect.append(pull())
+    expect.append([pull(b.populations(i)) for i in range(2)])
+    for o in oracles:
+        o.step(3)
+    indep.append([pull(o.post_collision()) for o in oracles])
     b.step(21)                    # two slots only: nothing more is logged
     x, xa, t = (v.cpu().numpy() for v in b.dataset())
     assert x.shape == (2 * ny, 27) and t.shape == (2 * ny, 3)
@@ -88,6 +100,13 @@ def test_logging_matches_pull_of_read_state():
         want = (pl[[3, 6, 7], :, x_cut].T.astype(np.float32) -
                 pl[[3, 6, 7], :, x_cut - 1].T.astype(np.float32))
         np.testing.assert_array_equal(t[rows], want)
+        # the same samples from the oracle's own runs (FP64 against FP32 offsets)
+        ol, os_ = indep[k]
+        for j in range(3):
+            col = x_cut - 1 - j
+            np.testing.assert_allclose(x[rows, 9 * j:9 * j + 9], ol[:, :, col].T, rtol=0, atol=2e-7)
+            np.testing.assert_allclose(xa[rows, 9 * j:9 * j + 9], os_[:, :, col].T, rtol=0,
+                                       atol=2e-7)
 
 
 def test_unstable_lattice_is_retired_alone(monkeypatch):

@@ -11,7 +11,7 @@ import pytest
 
 from oracle.d2q9 import CS2, moments
 from oracle.solver import Lattice as Oracle
-from paper_2506_05293_amd import geometry, lbm
+from paper_2506_05293_amd import geometry, lbm, workloads
 
 pytestmark = pytest.mark.gpu
 CS = np.sqrt(CS2)
@@ -146,26 +146,26 @@ def test_cbc_plane_pulse_leaves_without_reflection():
     assert out["cbc"] < 0.05 and out["zouhe"] > 0.5
 
 
-def test_cbc_full_size_one_step(bulk_path):
+def test_cbc_full_size_steps(bulk_path):
     # the 4096 x 1024 cylinder lattice with periodic laterals, FP32,
-    # characteristic outlet: one step from a developed state against the
-    # oracle on rows sampled over the outlet blocks and the tail
+    # characteristic outlet: both sides start from the same seeded smooth
+    # fields and take three steps; every fluid node is compared
     nx, ny = 4096, 1024
     mask = geometry.cylinder(nx, ny, 800, ny // 2, 80)
     tau = 3 * 0.05 * 80 / 200 + 0.5
     _say("cbc full size 4096x1024 fp32")
+    rho, u = workloads.smooth_fields(mask.shape, 0.05, amp=0.02, seed=14)
     g = lbm.Lattice(mask, tau, precision="fp32", collision="mrt", lateral="periodic",
-                    u_in=0.05, noise_amp=1e-3, seed=5)
+                    u_in=0.05, noise_amp=0.0)
+    g.init_fields(rho, u[0], u[1])
     g.set_outflow_cbc(sigma=0.25, kappa2=0.05 / CS, mach=0.05 / CS)
-    g.step(20)
-    f20 = g.populations()
-    g.step(1)
-    f21 = g.populations()
+    g.step(3)
     o = Oracle(mask, tau, collision="mrt", lateral="periodic", u_in=0.05)
+    o.set_equilibrium(rho, u[0], u[1])
     o.set_outflow_cbc(sigma=0.25, kappa2=0.05 / CS, mach=0.05 / CS, length=nx)
-    # the time derivatives of step 20 only feed a network; none here
-    ref, _ = o.advance_post(f20)
-    rows = np.r_[0:3, 60:70, 500:515, ny - 3:ny]
-    d = np.abs(f21[:, rows, -4:] - ref[:, rows, -4:])
-    assert np.max(d) < 2e-6
-    assert np.max(np.abs(f21[:, rows, :] - ref[:, rows, :])) < 2e-6
+    o.step(3)
+    fl = mask == 0
+    ref = o.post_collision()
+    err = np.max(np.abs(g.populations()[:, fl] - ref[:, fl]))
+    print("cbc full-size three-step error", err, flush=True)
+    assert err < 2e-6
