@@ -151,3 +151,28 @@ def test_batch_solid_nodes_survive_read_out():
             solid = L["mask"] != 0
             np.testing.assert_array_equal(f[:, solid], f0[i][:, solid])
             assert np.isfinite(f).all()
+
+
+def test_full_training_batch_against_oracle():
+    # the data-generation batch itself: 64 cylinder pairs (128 lattices,
+    # 33.4M nodes) in one persistent launch, FP32, MRT with the study rates;
+    # three steps, then the first pair and the largest lattice against the
+    # oracle's own runs from the same seeded start
+    from paper_2506_05293_amd import workloads
+    lats, _, _ = workloads.training_pairs(64, 3)
+    lats = [dict(L, log_role=0) for L in lats]             # no logging here
+    _say("batch full size", len(lats), "lattices")
+    rates = dict(s_e=1.0, s_eps=1.0, s_q=1.0)
+    b = lbm.Batch(lats, collision="mrt", lateral="periodic", noise_amp=1e-4, **rates)
+    b.step(3)
+    big = int(np.argmax([L["mask"].size for L in lats]))
+    for i in (0, 1, big):
+        L = lats[i]
+        o = Oracle(L["mask"], L["tau"], collision="mrt", lateral="periodic", u_in=L["u_in"],
+                   noise_amp=1e-4, seed=L["seed"], **rates)
+        o.step(3)
+        fl = L["mask"] == 0
+        err = np.max(np.abs(b.populations(i)[:, fl] - o.post_collision()[:, fl]))
+        print("lattice", i, L["mask"].shape, "three-step error", err, flush=True)
+        assert err < 5e-8
+    assert not np.any(b.retired())
