@@ -264,3 +264,24 @@ def test_product_observables_agree_with_oracle():
     assert abs(s["cl_rms"] - 0.4 / np.sqrt(2)) < 5e-3
     cd, cl2 = observables.force_coefficients(fx, fy, 1.0, U, D)
     np.testing.assert_allclose(cl2, cl, rtol=1e-12)
+
+
+def test_naca_coefficients_are_the_printed_ones():
+    # the mask generator uses the coefficients of Eq. A.1 as printed, and the
+    # printed law has the properties of a closed-trailing-edge NACA0012:
+    # zero thickness at x = 1 (to the 9 printed digits) and a maximum
+    # thickness of nominally 12 % of the chord near 30 % chord (the printed
+    # closed-edge form gives 11.897 %)
+    import json
+    import os
+    with open(os.path.join(os.path.dirname(__file__), "golden", "naca0012_eq_a1.json")) as fh:
+        g = json.load(fh)
+    printed = tuple(g[k] for k in ("a0", "a1", "a2", "a3", "a4", "a5"))
+    assert geometry.NACA0012_COEF == printed
+    a0, a1, a2, a3, a4, a5 = printed
+    s = np.linspace(0.0, 1.0, 1000001)
+    y = a0 * (a1 * np.sqrt(s) + a2 * s + a3 * s**2 + a4 * s**3 + a5 * s**4)
+    assert abs(y[-1]) < 1e-9
+    k = np.argmax(y)
+    assert abs(2 * y[k] - 0.12) < 1.5e-3
+    assert 0.28 < s[k] < 0.32
