@@ -227,6 +227,35 @@ def time_d3q19(torch, steps=500, warmup=50, nx=256, ny=128, nz=128):
                        "FP32 offsets, Zou-He faces, Re=100"}
 
 
+def time_batch(torch, steps=1000, warmup=200, n_pairs=64, launch="per_step"):
+    """The training-data batch: n_pairs cylinder pairs (128 lattices, 33.4M
+    nodes at 64 pairs), MRT with the study rates, FP32, one launch per step."""
+    from paper_2506_05293_amd import lbm, workloads
+    lattices, _, rows = workloads.training_pairs(n_pairs, 3)
+    nodes = sum(L["mask"].size for L in lattices)
+    b = lbm.Batch(lattices, collision="mrt", lateral="periodic", noise_amp=1e-4, history_cap=0,
+                  log_rows=rows, s_e=1.0, s_eps=1.0, s_q=1.0, launch=launch)
+    b.step(warmup)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    b.step(steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    assert not np.any(b.retired())
+    gbs = 72 * nodes / (ms * 1e-3) / 1e9
+    return {"mlups": nodes / (ms * 1e-3) / 1e6, "ms_per_step": ms, "nodes": int(nodes),
+            "lattices": len(lattices),
+            "roofline": {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": gbs / HBM_PEAK_GBS, "bytes_per_node": 72,
+                         "kernel": "k_batch_step (one launch per step)"},
+            "setting": f"{n_pairs} cylinder pairs (D 20-40, Re 40-400), MRT s=1, FP32 offsets, "
+                       f"launch {launch}"}
+
+
 def cpu_baseline(nx, ny, seconds=15.0):
     """The FP64 oracle (single thread) on the same lattice for as many whole
     steps as fit in ~`seconds` (at least one)."""
@@ -395,6 +424,7 @@ def main():
     ap.add_argument("--no-cbc-train", action="store_true",
                     help="skip timing the closed-loop trainer of the CBC tuning network")
     ap.add_argument("--no-3d", action="store_true", help="skip the D3Q19 step")
+    ap.add_argument("--no-batch", action="store_true", help="skip the training-data batch")
     ap.add_argument("--calibration-copy", action="store_true")
     ap.add_argument("--write-traffic", nargs=4, metavar="CSV")
     args = ap.parse_args()
@@ -451,6 +481,7 @@ def main():
     torch.cuda.synchronize()
     cbc_training = None if args.no_cbc_train else time_cbc_training(torch)
     d3q19 = None if args.no_3d else time_d3q19(torch)
+    batch = None if args.no_batch else time_batch(torch)
 
     accuracy = None
     if not args.no_accuracy:
@@ -482,6 +513,7 @@ def main():
         "cbc_outflow": cbc,
         "cbc_training": cbc_training,
         "d3q19": d3q19,
+        "batch": batch,
         "accuracy": accuracy,
         "cpu_baseline": None if args.no_cpu_baseline else cpu_baseline(nx, ny),
     }

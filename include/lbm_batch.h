@@ -10,11 +10,13 @@
  * the collision operator and the lateral condition; size, geometry, tau,
  * inlet velocity and noise seed are per lattice.
  *
- * One call of lbm_batch_step runs a cooperative (co-resident) grid whose
- * waves stride over the rows of all lattices (256 columns at a time) and
- * separates time steps with a grid-wide barrier.  The barrier's wait is bounded: if it does not
- * complete within the spin limit the kernel stops and the next
- * synchronising call returns LBM_EHIP.
+ * In the persistent mode one call of lbm_batch_step runs a cooperative
+ * (co-resident) grid whose waves stride over the rows of all lattices (256
+ * columns at a time) and separates time steps with a grid-wide barrier.
+ * The barrier's wait is bounded: if it does not complete within the spin
+ * limit the kernel stops and the next synchronising call returns LBM_EHIP.
+ * In the per-step mode every step is a launch of its own (see
+ * LBM_BATCH_PER_STEP below).
  *
  * Logging (Sec. 3.1: interior populations as network inputs, the next
  * column as ground truth).  A lattice with log_role 1 ("source") writes, at
@@ -64,8 +66,18 @@ typedef struct {
   int64_t log_start, log_every, log_slots;
   int32_t log_rows;             /* sample rows per logging slot                  */
   int32_t spin_limit;           /* barrier wait bound in polls; 0: default      */
+  int32_t launch;               /* LBM_BATCH_PER_STEP (0) or LBM_BATCH_PERSISTENT */
+  int32_t reserved;             /* 0                                             */
   void* stream;                 /* hipStream_t, borrowed                        */
 } lbm_batch_params;
+
+/* Launch modes.  PER_STEP (the default): one launch per step (the kernel
+ * boundary separates the steps; every wave takes one row item and each
+ * launch first sums the previous step's partials), then one launch that
+ * sums the last step's.  PERSISTENT: one cooperative launch per
+ * lbm_batch_step call, steps separated by the grid barrier.  Both run the
+ * same node code: the results are identical bit for bit. */
+enum { LBM_BATCH_PER_STEP = 0, LBM_BATCH_PERSISTENT = 1 };
 
 size_t lbm_batch_workspace_bytes(const lbm_batch_params* p, const lbm_batch_lattice* lat,
                                  int32_t n);
@@ -76,7 +88,8 @@ lbm_status lbm_batch_create(const lbm_batch_params* p, const lbm_batch_lattice* 
                             void* dev_workspace, size_t bytes, lbm_batch** out);
 lbm_status lbm_batch_destroy(lbm_batch* b);
 
-/* Advance every live lattice by nsteps (one cooperative launch). */
+/* Advance every live lattice by nsteps (one cooperative launch, or one
+ * launch per step, as params.launch selects). */
 lbm_status lbm_batch_step(lbm_batch* b, int64_t nsteps);
 
 /* Per-lattice read-outs (synchronising), as lbm_forces, lbm_force_history

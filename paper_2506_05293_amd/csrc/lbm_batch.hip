@@ -231,10 +231,61 @@ using const_ptr = const __attribute__((address_space(4))) T*;
 #define LBM_BATCH_ATTR
 #endif
 
+// One row item (256 columns of one lattice row) of step gs by one wave:
+// the node update, then the wave's partial (fx, fy, sum rho - 1).
 template <int MRT>
-__global__ void __launch_bounds__(kBlock) LBM_BATCH_ATTR k_batch(const BatchArgs a) {
+__device__ __forceinline__ void batch_item(const BatchArgs& a, int it, int par, int64_t slot,
+                                           int lane) {
   const const_ptr<int> items = (const_ptr<int>)(a.items);
   const const_ptr<BatchLat> lats = (const_ptr<BatchLat>)(a.lats);
+  const int lat = items[4 * it], tx = items[4 * it + 1], y = items[4 * it + 2];
+  const const_ptr<BatchLat> d = lats + lat;
+  float fx = 0.f, fy = 0.f, dm = 0.f;
+  if (!a.retired[lat]) {
+    LatView v;
+    v.A = d->buf[par];
+    v.B = d->buf[par ^ 1];
+    v.links = d->links;
+    v.chunk = d->chunk;
+    v.inlet = nullptr;
+    v.nx = d->nx;
+    v.ny = d->ny;
+    v.pitch = d->pitch;
+    v.nchunk = d->nchunk;
+    v.plane = d->plane;
+    v.xper = a.xper;
+    v.yper = a.yper;
+    v.n_nn = 0;
+    v.omega = d->omega;
+    v.s_e = a.s_e;
+    v.s_eps = a.s_eps;
+    v.s_q = d->s_q;
+    v.u_in = d->u_in;
+    v.one_minus_rho_out = d->one_minus_rho_out;
+    LogHook hook{a.x, a.xa, a.t, d->log_role, d->log_x,
+                 slot < 0 ? int64_t(-1) : slot * a.log_rows + d->log_row0};
+#if LBM_BATCH_SCALAR
+    const int x = tx * kChunk + items[4 * it + 3] * 64 + lane;
+    if (x < v.nx) bulk_node<float, MRT>(v, tx, x, y, fx, fy, dm, hook);
+#else
+    bulk_row<float, MRT>(v, tx, y, lane, fx, fy, dm, hook);
+#endif
+  }
+  fx = wave_sum(fx);
+  fy = wave_sum(fy);
+  dm = wave_sum(dm);
+  if (lane == 0) reinterpret_cast<float4*>(a.part[par])[it] = make_float4(fx, fy, dm, 0.f);
+}
+
+// The logging slot of the step taken after gs steps, or -1.
+__device__ __forceinline__ int64_t log_slot(const BatchArgs& a, int64_t gs) {
+  if (gs < a.log_start || (gs - a.log_start) % a.log_every != 0) return -1;
+  const int64_t slot = (gs - a.log_start) / a.log_every;
+  return slot < a.log_slots ? slot : -1;
+}
+
+template <int MRT>
+__global__ void __launch_bounds__(kBlock) LBM_BATCH_ATTR k_batch(const BatchArgs a) {
   // this wave's share of the items: XCD x = blockIdx % 8 takes the contiguous
   // range [x n / 8, (x + 1) n / 8); its waves stride over that range
   const int wave = __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6));
@@ -252,56 +303,38 @@ __global__ void __launch_bounds__(kBlock) LBM_BATCH_ATTR k_batch(const BatchArgs
     if (s > 0)
       for (int l = blockIdx.x; l < a.nlat; l += gridDim.x) reduce_lattice(a, l, a.part[par ^ 1]);
     // 2. all row items
-    int64_t slot = -1;
-    if (gs >= a.log_start && (gs - a.log_start) % a.log_every == 0) {
-      slot = (gs - a.log_start) / a.log_every;
-      if (slot >= a.log_slots) slot = -1;
-    }
-    for (int it = start; it < end; it += stride) {
-      const int lat = items[4 * it], tx = items[4 * it + 1], y = items[4 * it + 2];
-      const const_ptr<BatchLat> d = lats + lat;
-      float fx = 0.f, fy = 0.f, dm = 0.f;
-      if (!a.retired[lat]) {
-        LatView v;
-        v.A = d->buf[par];
-        v.B = d->buf[par ^ 1];
-        v.links = d->links;
-        v.chunk = d->chunk;
-        v.inlet = nullptr;
-        v.nx = d->nx;
-        v.ny = d->ny;
-        v.pitch = d->pitch;
-        v.nchunk = d->nchunk;
-        v.plane = d->plane;
-        v.xper = a.xper;
-        v.yper = a.yper;
-        v.n_nn = 0;
-        v.omega = d->omega;
-        v.s_e = a.s_e;
-        v.s_eps = a.s_eps;
-        v.s_q = d->s_q;
-        v.u_in = d->u_in;
-        v.one_minus_rho_out = d->one_minus_rho_out;
-        LogHook hook{a.x, a.xa, a.t, d->log_role, d->log_x,
-                     slot < 0 ? int64_t(-1) : slot * a.log_rows + d->log_row0};
-#if LBM_BATCH_SCALAR
-        const int x = tx * kChunk + items[4 * it + 3] * 64 + lane;
-        if (x < v.nx) bulk_node<float, MRT>(v, tx, x, y, fx, fy, dm, hook);
-#else
-        bulk_row<float, MRT>(v, tx, y, lane, fx, fy, dm, hook);
-#endif
-      }
-      fx = wave_sum(fx);
-      fy = wave_sum(fy);
-      dm = wave_sum(dm);
-      if (lane == 0) reinterpret_cast<float4*>(a.part[par])[it] = make_float4(fx, fy, dm, 0.f);
-    }
+    const int64_t slot = log_slot(a, gs);
+    for (int it = start; it < end; it += stride) batch_item<MRT>(a, it, par, slot, lane);
     // 3. all nodes of this step written before any of the next is read
     if (!grid_barrier(a)) return;
   }
   // flush: the last step's sums
   const int last = int((a.step0 + a.nsteps - 1) & 1);
   for (int l = blockIdx.x; l < a.nlat; l += gridDim.x) reduce_lattice(a, l, a.part[last]);
+}
+
+// One step per launch (the kernel boundary orders the steps): wave w of
+// workgroup b takes item first(b % 8) + (b / 8) * 4 + w of its XCD's range;
+// the workgroups first reduce the previous step's partials when that step
+// was taken by the previous launch of the same call.
+template <int MRT>
+__global__ void __launch_bounds__(kBlock) k_batch_step(const BatchArgs a, int reduce_prev) {
+  const int wave = __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6));
+  const int lane = int(threadIdx.x & 63);
+  const int xcd = int(blockIdx.x & 7);
+  const int first = int(int64_t(a.nitems) * xcd / 8);
+  const int end = int(int64_t(a.nitems) * (xcd + 1) / 8);
+  const int64_t gs = a.step0;
+  const int par = int(gs & 1);
+  if (reduce_prev)
+    for (int l = blockIdx.x; l < a.nlat; l += gridDim.x) reduce_lattice(a, l, a.part[par ^ 1]);
+  const int it = first + int(blockIdx.x >> 3) * kWaves + wave;
+  if (it < end) batch_item<MRT>(a, it, par, log_slot(a, gs), lane);
+}
+
+// The sums of the last step of a call (parity par).
+__global__ void __launch_bounds__(kBlock) k_batch_flush(const BatchArgs a, int par) {
+  for (int l = blockIdx.x; l < a.nlat; l += gridDim.x) reduce_lattice(a, l, a.part[par]);
 }
 
 // t -= x[column log_x - 1] for the samples of slots [s0, s1).
@@ -326,7 +359,8 @@ struct lbm_batch {
   int nlat, nitems;
   std::vector<BatchLat> lat;        // host copy of the descriptors
   BatchArgs args;
-  int grid;
+  int grid;                         // persistent grid
+  int grid_step;                    // per-step grid: one wave per item
   int64_t steps;
   int64_t fixed_slots;              // slots whose targets are already corrections
 };
@@ -388,6 +422,8 @@ lbm_status check_batch(const lbm_batch_params* p, const lbm_batch_lattice* lat, 
     return set_error(LBM_EINVAL, "negative size");
   if (p->log_slots > 0 && p->log_every < 1) return set_error(LBM_EINVAL, "log_every must be >= 1");
   if (p->spin_limit < 0) return set_error(LBM_EINVAL, "spin_limit < 0");
+  if (p->launch != LBM_BATCH_PERSISTENT && p->launch != LBM_BATCH_PER_STEP)
+    return set_error(LBM_EINVAL, "bad launch mode");
   for (int i = 0; i < n; ++i) {
     const lbm_batch_lattice& L = lat[i];
     if (L.nx < 8 || L.ny < 8) return set_error(LBM_EINVAL, "lattice %d: nx, ny must be >= 8", i);
@@ -587,7 +623,10 @@ lbm_status lbm_batch_create(const lbm_batch_params* p, const lbm_batch_lattice* 
   const int resident = std::max(1, per_cu - reserve) * cus / 8 * 8;
   const int wanted = (L.nitems + 8 * kWaves - 1) / (8 * kWaves) * 8;
   b->grid = std::max(8, std::min({per * cus / 8 * 8, resident, wanted}));
-  if (b->grid > resident) return cleanup(set_error(LBM_EHIP, "too few resident workgroups"));
+  if (p->launch == LBM_BATCH_PERSISTENT && b->grid > resident)
+    return cleanup(set_error(LBM_EHIP, "too few resident workgroups"));
+  const int per_xcd = (L.nitems + 7) / 8;
+  b->grid_step = 8 * std::max(1, (per_xcd + kWaves - 1) / kWaves);
   if (getenv("LBM_BATCH_VERBOSE"))
     fprintf(stderr, "lbm_batch: %d CUs, occupancy %d workgroups per CU, reserve %d, grid %d\n", cus,
             per_cu, reserve, b->grid);
@@ -609,6 +648,22 @@ lbm_status lbm_batch_step(lbm_batch* b, int64_t nsteps) {
   BatchArgs a = b->args;
   a.step0 = b->steps;
   a.nsteps = nsteps;
+  if (b->p.launch == LBM_BATCH_PER_STEP) {
+    a.nsteps = 1;
+    for (int64_t i = 0; i < nsteps; ++i) {
+      a.step0 = b->steps + i;
+      if (b->p.collision == LBM_MRT)
+        hipLaunchKernelGGL(k_batch_step<1>, dim3(b->grid_step), dim3(kBlock), 0, b->stream, a, int(i > 0));
+      else
+        hipLaunchKernelGGL(k_batch_step<0>, dim3(b->grid_step), dim3(kBlock), 0, b->stream, a, int(i > 0));
+    }
+    const int flush_grid = std::max(1, std::min(b->nlat, 1024));
+    hipLaunchKernelGGL(k_batch_flush, dim3(flush_grid), dim3(kBlock), 0, b->stream, a,
+                       int((b->steps + nsteps - 1) & 1));
+    BTRY(hipGetLastError());
+    b->steps += nsteps;
+    return LBM_OK;
+  }
   void* kargs[] = {&a};
   const void* fn = b->p.collision == LBM_MRT ? reinterpret_cast<const void*>(k_batch<1>)
                                              : reinterpret_cast<const void*>(k_batch<0>);

@@ -20,6 +20,7 @@ LBM_BGK, LBM_MRT = 0, 1
 LBM_LATERAL_WALLS, LBM_LATERAL_PERIODIC = 0, 1
 LBM_X_INOUT, LBM_X_PERIODIC = 0, 1
 LBM_OUT_ZOUHE, LBM_OUT_NN, LBM_OUT_CBC = 0, 1, 2
+LBM_BATCH_PER_STEP, LBM_BATCH_PERSISTENT = 0, 1
 
 
 class lbm_params(ctypes.Structure):
@@ -112,7 +113,8 @@ class lbm_batch_params(ctypes.Structure):
                 ("noise_amp", ctypes.c_double), ("history_cap", ctypes.c_int64),
                 ("log_start", ctypes.c_int64), ("log_every", ctypes.c_int64),
                 ("log_slots", ctypes.c_int64), ("log_rows", ctypes.c_int32),
-                ("spin_limit", ctypes.c_int32), ("stream", ctypes.c_void_p)]
+                ("spin_limit", ctypes.c_int32), ("launch", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("stream", ctypes.c_void_p)]
 
 
 PARAM_SHAPES = {"w1": (64, 27), "b1": (64,), "w2": (64, 64), "b2": (64,), "w3": (3, 64), "b3": (3,)}
@@ -435,14 +437,15 @@ class Batch:
 
     def __init__(self, lattices, *, collision="mrt", lateral="periodic", s_e=1.0, s_eps=1.0, s_q=0.0,
                  noise_amp=0.0, history_cap=0, log_start=0, log_every=1, log_slots=0, log_rows=0,
-                 spin_limit=0, device="cuda"):
+                 spin_limit=0, launch="per_step", device="cuda"):
         import torch
         self.lattices = lattices
         self.shapes = [np.shape(L["mask"]) for L in lattices]
         self.stream = torch.cuda.current_stream(device)
         self.params = lbm_batch_params(_COLL[collision], _LAT[lateral], s_e, s_eps, s_q, noise_amp,
                                        history_cap, log_start, log_every, log_slots, log_rows,
-                                       spin_limit, ctypes.c_void_p(self.stream.cuda_stream))
+                                       spin_limit, _LAUNCH[launch], 0,
+                                       ctypes.c_void_p(self.stream.cuda_stream))
         nbytes = lbm_batch_workspace_bytes(self.params, lattices)
         self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=device)
         self.b = lbm_batch_create(self.params, lattices, self.workspace.data_ptr(), nbytes)
@@ -857,6 +860,7 @@ _PREC = {"fp64": LBM_FP64, "fp32": LBM_FP32_OFFSET, "fp16": LBM_FP16_OFFSET}
 _COLL = {"bgk": LBM_BGK, "mrt": LBM_MRT}
 _LAT = {"walls": LBM_LATERAL_WALLS, "periodic": LBM_LATERAL_PERIODIC}
 _XBC = {"inout": LBM_X_INOUT, "periodic": LBM_X_PERIODIC}
+_LAUNCH = {"persistent": LBM_BATCH_PERSISTENT, "per_step": LBM_BATCH_PER_STEP}
 
 
 class Lattice:

@@ -30,12 +30,17 @@ def _lattices():
     ]
 
 
+LAUNCHES = ["persistent", "per_step"]
+
+
+@pytest.mark.parametrize("launch", LAUNCHES)
 @pytest.mark.parametrize("collision,lateral", [("mrt", "periodic"), ("bgk", "walls")])
-def test_batch_equals_single_lattices(collision, lateral, monkeypatch):
+def test_batch_equals_single_lattices(collision, lateral, launch, monkeypatch):
     monkeypatch.setenv("LBM_BULK_PATH", "vector")
     lats = _lattices()
-    _say("batch vs single", collision, lateral)
-    b = lbm.Batch(lats, collision=collision, lateral=lateral, noise_amp=1e-3, history_cap=200)
+    _say("batch vs single", collision, lateral, launch)
+    b = lbm.Batch(lats, collision=collision, lateral=lateral, noise_amp=1e-3, history_cap=200,
+                  launch=launch)
     b.step(70)
     b.step(130)
     for i, L in enumerate(lats):
@@ -53,7 +58,8 @@ def test_batch_equals_single_lattices(collision, lateral, monkeypatch):
     assert not b.retired().any()
 
 
-def test_logging_matches_pull_of_read_state():
+@pytest.mark.parametrize("launch", LAUNCHES)
+def test_logging_matches_pull_of_read_state(launch):
     # a source lattice (logged at an interior cut column) and its truncated
     # twin (logged at its outlet), rows aligned
     D = 16
@@ -63,9 +69,9 @@ def test_logging_matches_pull_of_read_state():
     short_mask = geometry.cylinder(x_cut + 1, ny, 4 * D, ny // 2, D)
     lats = [dict(mask=long_mask, tau=0.56, seed=3, log_role=1, log_x=x_cut, log_row0=0),
             dict(mask=short_mask, tau=0.56, seed=3, log_role=2, log_x=x_cut, log_row0=0)]
-    _say("batch logging")
+    _say("batch logging", launch)
     b = lbm.Batch(lats, collision="mrt", lateral="periodic", noise_amp=1e-3,
-                  log_start=5, log_every=3, log_slots=2, log_rows=ny)
+                  log_start=5, log_every=3, log_slots=2, log_rows=ny, launch=launch)
 
     cx = [0, 1, 0, -1, 0, 1, -1, -1, 1]
     cy = [0, 0, 1, 0, -1, 1, 1, -1, -1]
@@ -109,12 +115,14 @@ def test_logging_matches_pull_of_read_state():
                                        atol=2e-7)
 
 
-def test_unstable_lattice_is_retired_alone(monkeypatch):
+@pytest.mark.parametrize("launch", LAUNCHES)
+def test_unstable_lattice_is_retired_alone(launch, monkeypatch):
     monkeypatch.setenv("LBM_BULK_PATH", "vector")
     lats = _lattices()[:2]
     bad = dict(mask=geometry.cylinder(200, 60, 40, 30, 20.0), tau=0.5005, u_in=0.3, seed=1)
-    _say("batch retirement")
-    b = lbm.Batch(lats + [bad], collision="bgk", lateral="walls", noise_amp=1e-2, history_cap=400)
+    _say("batch retirement", launch)
+    b = lbm.Batch(lats + [bad], collision="bgk", lateral="walls", noise_amp=1e-2, history_cap=400,
+                  launch=launch)
     b.step(400)
     flags = b.retired()
     assert list(flags) == [0, 0, 1]
@@ -132,7 +140,8 @@ def test_barrier_wait_bound_is_reported():
     # a one-poll wait bound makes the grid barrier give up; every workgroup
     # leaves and the next synchronising call reports the failure
     _say("batch barrier bound")
-    b = lbm.Batch(_lattices(), collision="mrt", lateral="periodic", spin_limit=1)
+    b = lbm.Batch(_lattices(), collision="mrt", lateral="periodic", spin_limit=1,
+                  launch="persistent")
     b.step(50)
     with pytest.raises(lbm.LbmError) as e:
         b.forces(0)
@@ -153,7 +162,8 @@ def test_batch_solid_nodes_survive_read_out():
             assert np.isfinite(f).all()
 
 
-def test_full_training_batch_against_oracle():
+@pytest.mark.parametrize("launch", LAUNCHES)
+def test_full_training_batch_against_oracle(launch):
     # the data-generation batch itself: 64 cylinder pairs (128 lattices,
     # 33.4M nodes) in one persistent launch, FP32, MRT with the study rates;
     # three steps, then the first pair and the largest lattice against the
@@ -161,9 +171,9 @@ def test_full_training_batch_against_oracle():
     from paper_2506_05293_amd import workloads
     lats, _, _ = workloads.training_pairs(64, 3)
     lats = [dict(L, log_role=0) for L in lats]             # no logging here
-    _say("batch full size", len(lats), "lattices")
+    _say("batch full size", len(lats), "lattices", launch)
     rates = dict(s_e=1.0, s_eps=1.0, s_q=1.0)
-    b = lbm.Batch(lats, collision="mrt", lateral="periodic", noise_amp=1e-4, **rates)
+    b = lbm.Batch(lats, collision="mrt", lateral="periodic", noise_amp=1e-4, launch=launch, **rates)
     b.step(3)
     big = int(np.argmax([L["mask"].size for L in lats]))
     for i in (0, 1, big):
