@@ -1,6 +1,7 @@
 /*
- * lbm_batch.h -- many uneven D2Q9 lattices advanced by one persistent launch
- * (C ABI).  Used to generate the training data of the outflow network.
+ * lbm_batch.h -- many uneven D2Q9 lattices advanced together, one launch per
+ * step or one persistent launch (C ABI).  Used to generate the training data
+ * of the outflow network.
  *
  * Every lattice takes exactly the single-lattice step of lbm.h (Sec. 2.1
  * Eqs. 1-4, Zou & He columns of Sec. 2.2, half-way bounce-back of Sec. 2.3,
@@ -11,7 +12,7 @@
  * inlet velocity and noise seed are per lattice.
  *
  * In the persistent mode one call of lbm_batch_step runs a cooperative
- * (co-resident) grid whose waves stride over the rows of all lattices (256
+ * (co-resident) grid whose waves stride over the rows of all lattices (64
  * columns at a time) and separates time steps with a grid-wide barrier.
  * The barrier's wait is bounded: if it does not complete within the spin
  * limit the kernel stops and the next synchronising call returns LBM_EHIP.

@@ -1,23 +1,26 @@
-// Batched persistent launch over many uneven D2Q9 lattices (C ABI of
+// Batched launch over many uneven D2Q9 lattices (C ABI of
 // include/lbm_batch.h).
 //
-// One cooperative grid of resident workgroups advances every lattice for a
-// number of steps.  Per step:
-//   1. workgroup w reduces the partial sums of the previous step for
-//      lattices w, w + G, ... (FP64, fixed item order) into that lattice's
-//      accumulators and force history, and retires a lattice whose force or
-//      mass is no longer finite;
-//   2. every wave strides on its own over the row items of all lattices (an
-//      item = 256 columns of one row of one lattice, four nodes per lane with
-//      16-byte accesses; no workgroup synchronisation in this loop) and
-//      updates each node with the same node code as the single-lattice kernel
-//      (FP32 offsets), logging the pre-collision populations of the logged
-//      columns on logging steps.  Each XCD takes one contiguous eighth of the
-//      item list, so the rows above and below an item are being read by waves
-//      that share its L2;
-//   3. a grid barrier, whose wait is bounded: a workgroup that waits longer
-//      than the spin limit raises the error flag and leaves, and every
-//      workgroup leaves once the flag is up, so the grid always drains.
+// Work is split into row items: 64 columns of one row of one lattice, one
+// node per lane (LBM_BATCH_SCALAR, the default), or 256 columns with four
+// nodes per lane and 16-byte accesses (LBM_BATCH_SCALAR=0).  Every item is
+// updated with the node code of the single-lattice kernel (FP32 offsets),
+// logging the pre-collision populations of the logged columns on logging
+// steps.  Each XCD takes one contiguous eighth of the item list, so the rows
+// above and below an item are being read by waves that share its L2.
+//
+// One launch per step (k_batch_step, the default mode): every wave takes one
+// item; the workgroups first reduce the partial sums of the previous step
+// for lattices w, w + G, ... (FP64, fixed item order) into that lattice's
+// accumulators and force history and retire a lattice whose force or mass
+// is no longer finite; k_batch_flush reduces the last step of a call.
+//
+// Persistent mode (k_batch): one cooperative grid of resident workgroups
+// advances every lattice for a number of steps; per step the same reduction,
+// then every wave strides on its own over its XCD's items, then a grid
+// barrier, whose wait is bounded: a workgroup that waits longer than the
+// spin limit raises the error flag and leaves, and every workgroup leaves
+// once the flag is up, so the grid always drains.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -41,7 +44,7 @@ constexpr int kBatchGroupsPerCu = 4;
 // vmcnt bits [3:0] and [15:14] zero, expcnt [6:4] and lgkmcnt [11:8] at their maximum
 constexpr int kWaitVmcnt0 = 0x0F70;
 #ifndef LBM_BATCH_SCALAR
-#define LBM_BATCH_SCALAR 0
+#define LBM_BATCH_SCALAR 1
 #endif
 
 // Fields of one lattice read by bulk_node, with A/B chosen per step.
@@ -76,7 +79,8 @@ struct BatchCtl {              // device-side control words
 
 struct BatchArgs {
   const BatchLat* lats;
-  const int4* items;           // (lattice, chunk column, row, 0): 256 x 1 nodes
+  const int4* items;           // (lattice, chunk column, row, sub): 64 x 1 nodes
+                               // (256 x 1 with the four-nodes-per-lane code)
   int nlat, nitems;
   int xper, yper;
   double s_e, s_eps;
@@ -231,7 +235,7 @@ using const_ptr = const __attribute__((address_space(4))) T*;
 #define LBM_BATCH_ATTR
 #endif
 
-// One row item (256 columns of one lattice row) of step gs by one wave:
+// One row item (64 or 256 columns of one lattice row) of step gs by one wave:
 // the node update, then the wave's partial (fx, fy, sum rho - 1).
 template <int MRT>
 __device__ __forceinline__ void batch_item(const BatchArgs& a, int it, int par, int64_t slot,
