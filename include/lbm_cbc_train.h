@@ -82,6 +82,14 @@ lbm_status lbm_cbc_train_destroy(lbm_cbc_trainer* t);
 lbm_status lbm_cbc_train_set_segments(lbm_cbc_trainer* t, const double* a0, const double* ref,
                                       const int32_t* n_t);
 
+/* Per-segment relaxation time and Mach number (host arrays of n_seg doubles,
+ * copied; NULL keeps the trainer's tau or mach for every segment), so that
+ * one training set can span several flows; tau > 1/2, 0 <= mach < 1.
+ * lbm_cbc_train_set_segments resets both to the trainer's values.
+ * Synchronises. */
+lbm_status lbm_cbc_train_set_segment_params(lbm_cbc_trainer* t, const double* tau,
+                                            const double* mach);
+
 /* The network: weights become the FP32 masters, standardisation and output
  * maps are kept fixed (as in lbm_cbc_net); resets Adam. */
 lbm_status lbm_cbc_train_set_net(lbm_cbc_trainer* t, const lbm_cbc_net* net);

@@ -187,13 +187,20 @@ def _theta(net, requires_grad):
             for k in PARAMS}
 
 
+def _seg(segment, cfg):
+    """(a0, ref, cfg) of a segment given as (a0, ref) or (a0, ref, own cfg)."""
+    return (segment[0], segment[1], segment[2] if len(segment) > 2 else cfg)
+
+
 def loss_and_grad(segments, net, cfg):
-    """Mean loss over segments [(a0, ref), ...] (n_t of each = ref.shape[2])
-    and its gradient with respect to w1, b1, w2, b2, w3, b3 (numpy dict)."""
+    """Mean loss over segments [(a0, ref), ...] (n_t of each = ref.shape[2];
+    a segment may carry its own cfg as a third element) and its gradient
+    with respect to w1, b1, w2, b2, w3, b3 (numpy dict)."""
     theta = _theta(net, True)
     total = 0.0
-    for a0, ref in segments:
-        states = rollout(a0, theta, net, cfg, ref.shape[2])
+    for seg in segments:
+        a0, ref, c = _seg(seg, cfg)
+        states = rollout(a0, theta, net, c, ref.shape[2])
         total = total + segment_loss(states[-1], ref)
     loss = total / len(segments)
     loss.backward()
@@ -203,8 +210,10 @@ def loss_and_grad(segments, net, cfg):
 def loss_only(segments, net, cfg):
     theta = _theta(net, False)
     with torch.no_grad():
-        total = sum(float(segment_loss(rollout(a0, theta, net, cfg, ref.shape[2])[-1], ref))
-                    for a0, ref in segments)
+        total = 0.0
+        for seg in segments:
+            a0, ref, c = _seg(seg, cfg)
+            total += float(segment_loss(rollout(a0, theta, net, c, ref.shape[2])[-1], ref))
     return total / len(segments)
 
 

@@ -69,7 +69,7 @@ struct CtState {
   double m[kNP], v[kNP];             // Adam moments
   double mu[kIn], sd[kIn];           // input standardisation
   double leaky, sig_scale, sig_shift, kap_scale, kap_shift;
-  double kappa1_coef, rho_inf_m1;    // (1 - M^2) c_s / L, rho_inf - 1
+  double rho_inf_m1;                 // rho_inf - 1
   double loss;
   double grad[kNP];
 };
@@ -91,7 +91,8 @@ struct CtArgs {
   CtState* st;
   int ny, W, n_max, nrb, nlb;
   int64_t plane;        // ny * W; node (x, y) of a plane at x * ny + y
-  T omega;
+  const double* seg_omega;   // [seg] 1 / tau
+  const double* seg_k1c;     // [seg] (1 - M^2) c_s / L  (kappa_1 = sigma k1c)
   double seg_scale;     // 1 / n_seg
 };
 
@@ -183,7 +184,7 @@ struct Lodi {
 };
 
 template <typename T>
-__device__ Lodi<T> lodi(const OutIn<T>& in, T sigma, T kappa2, const CtState* st) {
+__device__ Lodi<T> lodi(const OutIn<T>& in, T sigma, T kappa2, T k1c, const CtState* st) {
   const T cs2 = T(1.0 / 3.0), cs = T(0.57735026918962576451);
   const T px = in.g[0], ux = in.g[1], vx = in.g[2], py = in.g[3], uy = in.g[4], vy = in.g[5];
   const T u = in.u, v = in.v;
@@ -195,7 +196,7 @@ __device__ Lodi<T> lodi(const OutIn<T>& in, T sigma, T kappa2, const CtState* st
   l.T1 = -(v * py + l.p * vy - l.rho * cs * v * uy);
   l.T3 = -(v * vy + py / l.rho);
   l.T5 = -(v * py + l.p * vy + l.rho * cs * v * uy);
-  l.L1 = sigma * T(st->kappa1_coef) * cs2 * (in.drho - T(st->rho_inf_m1)) - kappa2 * l.T1 + l.T1;
+  l.L1 = sigma * k1c * cs2 * (in.drho - T(st->rho_inf_m1)) - kappa2 * l.T1 + l.T1;
   l.rho_t = (-(l.L5 + l.L1) + (l.T5 + l.T1)) / (T(2) * cs2);
   l.u_t = (-(l.L5 - l.L1) + (l.T5 - l.T1)) / (T(2) * l.rho * cs);
   l.v_t = -l.L3 + l.T3;
@@ -253,7 +254,7 @@ __global__ void __launch_bounds__(kRows) k_fwd_outlet(const CtArgs<T> a, int k) 
   }
   const T sigma = T(st->sig_scale) * sigmoid(s0) + T(st->sig_shift);
   const T kappa2 = T(st->kap_scale) * sigmoid(s1) + T(st->kap_shift);
-  const Lodi<T> l = lodi(in, sigma, kappa2, st);
+  const Lodi<T> l = lodi(in, sigma, kappa2, T(a.seg_k1c[s]), st);
   T* o = a.outs + ((int64_t(s) * a.n_max + k) * a.ny + r) * 3;
   o[0] = in.drho + l.rho_t;                 // forward Euler
   o[1] = in.u + l.u_t;
@@ -283,7 +284,7 @@ __global__ void __launch_bounds__(kNodes) k_fwd_node(const CtArgs<T> a, int k) {
   const int x = int(n / a.ny), y = int(n - int64_t(x) * a.ny);
   T g[9];
   pre_collision(a, s, k, x, y, g);
-  collide_bgk(g, a.omega);
+  collide_bgk(g, T(a.seg_omega[s]));
   T* B = state_at(a, s, k + 1);
 #pragma unroll
   for (int q = 0; q < 9; ++q) B[q * a.plane + n] = g[q];
@@ -409,7 +410,7 @@ __global__ void __launch_bounds__(kNodes) k_bwd(const CtArgs<T> a, int k) {
     Ljy += wl * (T(3 * cy(q)) + T(9) * cu * T(cy(q)) - T(3) * v);
   }
   T* LF = a.lamF[k & 1] + so;
-  const T om = a.omega;
+  const T om = T(a.seg_omega[s]);
 #pragma unroll
   for (int q = 0; q < 9; ++q)
     LF[q * a.plane + n] = (T(1) - om) * lam[q] + om * (Lr + T(cx(q)) * Ljx + T(cy(q)) * Ljy);
@@ -516,7 +517,7 @@ __global__ void __launch_bounds__(kNodes) k_bwd_outlet(const CtArgs<T> a, int k)
     const T sg0 = sigmoid(s0), sg1 = sigmoid(s1);
     const T sigma = T(st->sig_scale) * sg0 + T(st->sig_shift);
     const T kappa2 = T(st->kap_scale) * sg1 + T(st->kap_shift);
-    const Lodi<T> l = lodi(in, sigma, kappa2, st);
+    const Lodi<T> l = lodi(in, sigma, kappa2, T(a.seg_k1c[s]), st);
     const T rho1 = T(1) + d1;
 
     // outlet reconstruction (offset form: g0 = drho' (1 + u') + u' - (g2 + g4)
@@ -551,7 +552,7 @@ __global__ void __launch_bounds__(kNodes) k_bwd_outlet(const CtArgs<T> a, int k)
     T lT1 = ia * lrt - ib * lut;
     ldr += -(l.u_t / rho) * lut;
     const T lL3 = -lvt, lT3 = lvt;
-    const T k1c = T(st->kappa1_coef);
+    const T k1c = T(a.seg_k1c[s]);
     const T lsig = lL1 * k1c * cs2 * (in.drho - T(st->rho_inf_m1));
     ldr += lL1 * sigma * k1c * cs2;
     const T lkap = -lL1 * l.T1;
@@ -739,7 +740,8 @@ __global__ void __launch_bounds__(kNodes) k_update(CtState* st, const double* gp
 size_t align256(size_t b) { return (b + 255) / 256 * 256; }
 
 struct CtLayout {
-  size_t st, traj, outs, dts, lamA, lamF, lamP, madj, ref, nts, gslot, lslot, gpart, lpart, total;
+  size_t st, traj, outs, dts, lamA, lamF, lamP, madj, ref, nts, seg_omega, seg_k1c, gslot, lslot,
+      gpart, lpart, total;
   int W, nrb, nlb, ngc, nlc;      // gradient / loss chunks of the first-stage sums
   int64_t plane;
 };
@@ -775,6 +777,8 @@ CtLayout ct_layout(const lbm_cbc_train_params& p) {
   L.lslot = take(ns * L.nlb * sizeof(double));
   L.gpart = take(size_t(L.ngc) * kNP * sizeof(double));
   L.lpart = take(size_t(L.nlc) * sizeof(double));
+  L.seg_omega = take(ns * sizeof(double));
+  L.seg_k1c = take(ns * sizeof(double));
   L.total = o;
   return L;
 }
@@ -841,7 +845,8 @@ struct lbm_cbc_trainer {
     a.nrb = L.nrb;
     a.nlb = L.nlb;
     a.plane = L.plane;
-    a.omega = T(1.0 / p.tau);
+    a.seg_omega = reinterpret_cast<const double*>(base + L.seg_omega);
+    a.seg_k1c = reinterpret_cast<const double*>(base + L.seg_k1c);
     a.seg_scale = 1.0 / double(p.n_seg);
     return a;
   }
@@ -885,6 +890,27 @@ struct lbm_cbc_trainer {
     return p.precision == LBM_FP64 ? run_t<double>(update) : run_t<float>(update);
   }
 };
+
+// Per-segment relaxation and kappa_1 coefficient (host arrays of n_seg, or
+// NULL for the trainer's own tau / mach), copied to the device.
+lbm_status set_seg_params(lbm_cbc_trainer* t, const double* tau, const double* mach) {
+  const lbm_cbc_train_params& p = t->p;
+  const double cs = 0.57735026918962576451;
+  std::vector<double> om(size_t(p.n_seg)), k1(size_t(p.n_seg));
+  for (int s = 0; s < p.n_seg; ++s) {
+    const double ta = tau ? tau[s] : p.tau, ma = mach ? mach[s] : p.mach;
+    if (!(ta > 0.5) || !std::isfinite(ta)) return set_error(LBM_EINVAL, "tau[%d] must be > 1/2", s);
+    if (!(ma >= 0.0 && ma < 1.0)) return set_error(LBM_EINVAL, "mach[%d] must be in [0, 1)", s);
+    om[size_t(s)] = 1.0 / ta;
+    k1[size_t(s)] = (1.0 - ma * ma) * cs / p.length;
+  }
+  CT_TRY(hipMemcpyAsync(t->base + t->L.seg_omega, om.data(), om.size() * 8, hipMemcpyHostToDevice,
+                        t->stream));
+  CT_TRY(hipMemcpyAsync(t->base + t->L.seg_k1c, k1.data(), k1.size() * 8, hipMemcpyHostToDevice,
+                        t->stream));
+  CT_TRY(hipStreamSynchronize(t->stream));
+  return LBM_OK;
+}
 
 extern "C" {
 
@@ -957,12 +983,23 @@ lbm_status lbm_cbc_train_set_segments(lbm_cbc_trainer* t, const double* a0, cons
                           seg_vals * e, size_t(p.n_seg), hipMemcpyHostToDevice, t->stream));
   CT_TRY(hipMemcpyAsync(t->base + L.ref, hr.data(), hr.size(), hipMemcpyHostToDevice, t->stream));
   t->nts.assign(n_t, n_t + p.n_seg);
+  {
+    lbm_status st = set_seg_params(t, nullptr, nullptr);
+    if (st) return st;
+  }
   CT_TRY(hipMemcpyAsync(t->base + L.nts, t->nts.data(), t->nts.size() * sizeof(int),
                         hipMemcpyHostToDevice, t->stream));
   CT_TRY(hipMemsetAsync(t->base + L.dts, 0, size_t(p.n_seg) * (p.n_max + 1) * p.ny * 3 * e, t->stream));
   CT_TRY(hipStreamSynchronize(t->stream));
   t->has_data = true;
   return LBM_OK;
+}
+
+lbm_status lbm_cbc_train_set_segment_params(lbm_cbc_trainer* t, const double* tau,
+                                            const double* mach) {
+  if (!t) return set_error(LBM_EINVAL, "NULL trainer");
+  if (!t->has_data) return set_error(LBM_ESTATE, "set the segments first");
+  return set_seg_params(t, tau, mach);
 }
 
 lbm_status lbm_cbc_train_set_net(lbm_cbc_trainer* t, const lbm_cbc_net* n) {
@@ -992,8 +1029,6 @@ lbm_status lbm_cbc_train_set_net(lbm_cbc_trainer* t, const lbm_cbc_net* n) {
   h->sig_shift = n->sigma_shift;
   h->kap_scale = n->kappa_scale;
   h->kap_shift = n->kappa_shift;
-  const double cs = 0.57735026918962576451;
-  h->kappa1_coef = (1.0 - t->p.mach * t->p.mach) * cs / t->p.length;
   h->rho_inf_m1 = t->p.rho_inf - 1.0;
   CT_TRY(hipMemcpyAsync(t->st, h, sizeof(CtState), hipMemcpyHostToDevice, t->stream));
   CT_TRY(hipStreamSynchronize(t->stream));

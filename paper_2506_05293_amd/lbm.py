@@ -196,6 +196,7 @@ def library():
             "lbm_cbc_train_destroy": (I32, [VP]),
             "lbm_cbc_train_set_segments": (I32, [VP, DP, DP, P(ctypes.c_int32)]),
             "lbm_cbc_train_set_net": (I32, [VP, P(lbm_cbc_net)]),
+            "lbm_cbc_train_set_segment_params": (I32, [VP, DP, DP]),
             "lbm_cbc_train_gradient": (I32, [VP, DP, DP]),
             "lbm_cbc_train_step": (I32, [VP, I64]),
             "lbm_cbc_train_loss": (I32, [VP, DP]),
@@ -637,6 +638,13 @@ def lbm_cbc_train_set_segments(t, a0, ref, n_t):
         "lbm_cbc_train_set_segments")
 
 
+def lbm_cbc_train_set_segment_params(t, tau=None, mach=None):
+    keep = [None if a is None else np.ascontiguousarray(a, dtype=np.float64) for a in (tau, mach)]
+    ptrs = [None if a is None else _dptr(a) for a in keep]
+    return _check(library().lbm_cbc_train_set_segment_params(t, *ptrs),
+                  "lbm_cbc_train_set_segment_params")
+
+
 def lbm_cbc_train_set_net(t, net):
     n, keep = _cbc_net_struct(net)
     st = library().lbm_cbc_train_set_net(t, ctypes.byref(n))
@@ -720,6 +728,10 @@ class CbcTrainer:
 
     def set_net(self, net):
         lbm_cbc_train_set_net(self.t, net)
+
+    def set_segment_params(self, tau=None, mach=None):
+        """Per-segment relaxation time and Mach number (arrays of n_seg)."""
+        lbm_cbc_train_set_segment_params(self.t, tau, mach)
 
     def gradient(self):
         """(loss, {w1: .., b3: ..}) of the current weights."""

@@ -165,6 +165,35 @@ def test_adam_steps_match_oracle():
     assert np.median(moved) > 1e-3
 
 
+def test_per_segment_relaxation_and_mach():
+    # one training set over two flows: segments of a Ma 0.17, tau 0.6 run and
+    # of a Ma 0.10, tau 0.72 run, each rolled out with its own tau and kappa_1
+    _say("cbc train per-segment tau and mach")
+    net = _net(6)
+    segs_a, a0_a, ref_a, nt_a, cfg_a = _case(40, 70, (3, 8), tau=0.6, u0=0.1)
+    segs_b, a0_b, ref_b, nt_b, cfg_b = _case(40, 70, (8, 5), tau=0.72, u0=0.06, seed=1)
+    segs = [s + (cfg_a,) for s in segs_a] + [s + (cfg_b,) for s in segs_b]
+    loss_o, g_o = cbc_train.loss_and_grad(segs, net, cfg_a)
+    tr = _trainer(np.concatenate([a0_a, a0_b]), np.concatenate([ref_a, ref_b]),
+                  np.concatenate([nt_a, nt_b]), net, cfg_a, "fp64")
+    tr.set_segment_params([cfg_a["tau"]] * 2 + [cfg_b["tau"]] * 2,
+                          [cfg_a["mach"]] * 2 + [cfg_b["mach"]] * 2)
+    loss_g, g_g = tr.gradient()
+    fo, fg = _flat(g_o), _flat(g_g)
+    err = np.max(np.abs(fg - fo)) / np.max(np.abs(fo))
+    print("loss", loss_g, loss_o, "max gradient error / max |g|", err, flush=True)
+    assert loss_g == pytest.approx(loss_o, rel=1e-10)
+    assert err < 1e-10
+    # NULL arrays fall back to the trainer's own tau and Mach number
+    tr.set_segment_params(None, None)
+    loss_u, _ = tr.gradient()
+    loss_uo = cbc_train.loss_only([s[:2] for s in segs], net, cfg_a)
+    assert loss_u == pytest.approx(loss_uo, rel=1e-10)
+    assert abs(loss_u - loss_g) > 1e-6 * loss_g
+    with pytest.raises(lbm.LbmError):
+        tr.set_segment_params([0.6, 0.5, 0.7, 0.7], None)
+
+
 def test_free_stream_gives_zero_loss_and_gradient():
     _say("cbc train free stream")
     nx, ny, n_max, u0 = 30, 20, 6, 0.08
