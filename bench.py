@@ -346,19 +346,29 @@ def run_studies(which, scale, nn_switch=0, mass_bound=1e-2):
     from paper_2506_05293_amd import experiments
     os.makedirs(RESULTS, exist_ok=True)
     n = lambda k: max(1, int(k * scale))
-    if which in ("cbc_train", "all"):
-        res = experiments.cbc_training_study(adam_steps=n(2000), progress=_progress)
-        with open(os.path.join(RESULTS, "cbc_training.json"), "w") as f:
+    cbc_runs = {"cbc_train": ("cbc_training.json", {}),
+                # two Mach numbers in one training set, Ma 0.2 between them held out
+                "cbc_train_mach": ("cbc_training_mach.json", dict(
+                    flows=[{}, {"ma": 0.1}],
+                    holdout={"ma0.2": dict(ma=0.2), "ma0.15": dict(ma=0.15),
+                             "ma0.25": dict(ma=0.25),
+                             "strong_ma0.2": dict(ma=0.2, beta=0.8, rc=25.0, x0=140.0)}))}
+    for name, (out, kw) in cbc_runs.items():
+        if which not in (name, "all"):
+            continue
+        res = experiments.cbc_training_study(adam_steps=n(2000), progress=_progress, **kw)
+        with open(os.path.join(RESULTS, out), "w") as f:
             json.dump(_jsonable(res), f, indent=1)
-        print(json.dumps({"cbc_training": {
+        print(json.dumps({name: {
             "loss_before": res["loss_before"], "loss_after": res["loss_after"],
-            "ms_per_adam_step": res["ms_per_adam_step"],
+            "ms_per_adam_step": res["ms_per_adam_step"], "loss_per_flow": res["loss_per_flow"],
             "vortex": {k: {a: r[a] for a in ("max", "final", "mean", "finite")}
                        for k, r in res["vortex"]["runs"].items()},
-            "held_out": {h: {k: r["mean"] for k, r in v["runs"].items()}
-                         for h, v in res["held_out"].items()}}}), flush=True)
-        if which == "cbc_train":
-            return
+            **{part: {h: {k: r["mean"] for k, r in v["runs"].items()}
+                      for h, v in res[part].items()} for part in ("trained_flows", "held_out")}}}),
+              flush=True)
+    if which in ("cbc_train", "cbc_train_mach"):
+        return
     if which in ("vortex", "all"):
         res = experiments.vortex_study(steps=max(10, n(600) // 10 * 10), progress=_progress)
         with open(os.path.join(RESULTS, "vortex_study.json"), "w") as f:
@@ -409,8 +419,8 @@ def main():
     ap.add_argument("--no-accuracy", action="store_true",
                     help="skip the FP32-vs-FP64 precision study (C_D, C_L, St)")
     ap.add_argument("--accuracy-steps", type=int, default=50_000)
-    ap.add_argument("--study", choices=["train", "nn", "naca", "vortex", "cbc_train", "scaling",
-                                        "all"],
+    ap.add_argument("--study", choices=["train", "nn", "naca", "vortex", "cbc_train",
+                                        "cbc_train_mach", "scaling", "all"],
                     default=None,
                     help="also run the truncated-domain outflow study (training data, "
                          "training, neural vs Zou-He outflow) and/or the NACA0012 study; "

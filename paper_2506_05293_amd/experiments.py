@@ -337,53 +337,69 @@ def _outlet_features(strip, prev):
                      (rho[:, 2] - rp) / 3, u[:, 2] - up, v[:, 2] - vp], axis=1)
 
 
-def cbc_training_study(n_ts=(5, 10, 25), starts=tuple(range(1, 551, 5)), adam_steps=2000,
-                       lr=1e-3, seed=0, nx=200, ny=400, reference_nx=1000, precision="fp32",
-                       sigma_range=(0.0, 1.0), kappa_range=(0.0, 1.0), init=(0.25, 0.3),
-                       eval_steps=600, holdout=None, progress=_noop):
-    """Closed-loop training of the CBC tuning network (Sec. 4.2) on the
-    convected vortex.  The reference runs on a lattice reference_nx long;
-    from its states at the steps `starts` (every 5 steps from 1 to 546: 110
-    fields) segments of each length in n_ts start on the nx-long truncated
-    lattice, and the loss at their end is the MSE of density and velocity
-    over the n_t columns before the outlet.  Inputs are standardised with
-    the mean and standard deviation of the nine features at the outlet
-    column of the reference states; sigma and kappa_2 map the sigmoid
-    outputs to sigma_range and kappa_range; the network starts near
-    (sigma, kappa_2) = init.  Adam on the full set of segments.  Afterwards
-    the vortex comparison of vortex_study with the trained network beside
-    the fixed settings, and on the held-out vortices of `holdout` (name ->
-    parameters of workloads.convected_vortex)."""
-    if holdout is None:
-        holdout = {"weak_small": dict(beta=0.3, rc=15.0), "ma0.2": dict(ma=0.2),
-                   "strong": dict(beta=0.8, rc=25.0, x0=140.0)}
-    ref_case = workloads.convected_vortex(nx=reference_nx, ny=ny)
-    ma, u0, tau = ref_case["ma"], ref_case["u0"], ref_case["tau"]
-    n_max = max(n_ts)
-    w = 2 * n_max + 3
-    last = max(starts) + n_max
-    lat = lbm.Lattice(ref_case["mask"], tau, precision=precision, collision="bgk",
-                      lateral="periodic", u_in=u0, noise_amp=0.0)
-    lat.init_fields(ref_case["rho"], ref_case["ux"], ref_case["uy"])
+def _vortex_strips(vx, nx, ny, reference_nx, w, last, precision):
+    """Post-collision states 0..last of the convected vortex `vx` (parameters
+    of workloads.convected_vortex) on its reference_nx-long lattice, cut to
+    the w columns before x = nx; and the flow's Mach number and tau."""
+    case = workloads.convected_vortex(nx=reference_nx, ny=ny, **vx)
+    lat = lbm.Lattice(case["mask"], case["tau"], precision=precision, collision="bgk",
+                      lateral="periodic", u_in=case["u0"], noise_amp=0.0)
+    lat.init_fields(case["rho"], case["ux"], case["uy"])
     strips = np.empty((last + 1, 9, ny, w))
     strips[0] = lat.populations()[:, :, nx - w:nx]
-    t0 = time.perf_counter()
     for t in range(1, last + 1):
         lat.step(1)
         strips[t] = lat.populations()[:, :, nx - w:nx]
-    del lat
-    progress(f"cbc training: reference states 0..{last} ({time.perf_counter() - t0:.1f} s)", {})
+    return strips, case["ma"], case["tau"]
 
-    a0s, refs, nts = [], [], []
-    for n_t in n_ts:
-        for s0 in starts:
-            a0s.append(strips[s0])
-            r = np.zeros((3, ny, n_max))
-            r[:, :, n_max - n_t:] = np.stack(_moments(strips[s0 + n_t][:, :, w - n_t:]))
-            refs.append(r)
-            nts.append(n_t)
-    feats = np.concatenate([_outlet_features(strips[t], strips[t - 1]) for t in starts])
+
+def cbc_training_study(n_ts=(5, 10, 25), starts=tuple(range(1, 551, 5)), adam_steps=2000,
+                       lr=1e-3, seed=0, nx=200, ny=400, reference_nx=1000, precision="fp32",
+                       sigma_range=(0.0, 1.0), kappa_range=(0.0, 1.0), init=(0.25, 0.3),
+                       eval_steps=600, flows=None, holdout=None, progress=_noop):
+    """Closed-loop training of the CBC tuning network (Sec. 4.2) on the
+    convected vortex.  Each flow of `flows` (parameters of
+    workloads.convected_vortex; default the Ma 0.3 vortex alone) runs on a
+    lattice reference_nx long; from its states at the steps `starts` (every
+    5 steps from 1 to 546: 110 fields) segments of each length in n_ts start
+    on the nx-long truncated lattice, with the flow's own tau and Mach
+    number, and the loss at their end is the MSE of density and velocity
+    over the n_t columns before the outlet.  Inputs are standardised with
+    the mean and standard deviation of the nine features at the outlet
+    column of all reference states; sigma and kappa_2 map the sigmoid
+    outputs to sigma_range and kappa_range; the network starts near
+    (sigma, kappa_2) = init.  Adam on the full set of segments.  Afterwards
+    the vortex comparison of vortex_study with the trained network beside
+    the fixed settings on the first flow, the trained network and the
+    fixed CBC on the other flows, and both on the held-out vortices of
+    `holdout` (name -> parameters of workloads.convected_vortex)."""
+    flows = [dict(f) for f in (flows or [{}])]
+    if holdout is None:
+        holdout = {"weak_small": dict(beta=0.3, rc=15.0), "ma0.2": dict(ma=0.2),
+                   "strong": dict(beta=0.8, rc=25.0, x0=140.0)}
+    n_max = max(n_ts)
+    w = 2 * n_max + 3
+    last = max(starts) + n_max
+    a0s, refs, nts, taus, machs, feats = [], [], [], [], [], []
+    for vx in flows:
+        t0 = time.perf_counter()
+        strips, ma, tau = _vortex_strips(vx, nx, ny, reference_nx, w, last, precision)
+        progress(f"cbc training: reference states 0..{last} of {vx or 'the Ma 0.3 vortex'} "
+                 f"({time.perf_counter() - t0:.1f} s)", {})
+        for n_t in n_ts:
+            for s0 in starts:
+                a0s.append(strips[s0])
+                r = np.zeros((3, ny, n_max))
+                r[:, :, n_max - n_t:] = np.stack(_moments(strips[s0 + n_t][:, :, w - n_t:]))
+                refs.append(r)
+                nts.append(n_t)
+                taus.append(tau)
+                machs.append(ma)
+        feats.extend(_outlet_features(strips[t], strips[t - 1]) for t in starts)
+        del strips
+    feats = np.concatenate(feats)
     mu, sd = feats.mean(axis=0), np.maximum(feats.std(axis=0), 1e-12)
+    ma0 = machs[0]
 
     rng = np.random.default_rng(seed)
 
@@ -401,8 +417,14 @@ def cbc_training_study(n_ts=(5, 10, 25), starts=tuple(range(1, 551, 5)), adam_st
            "kappa_scale": kappa_range[1] - kappa_range[0], "kappa_shift": kappa_range[0]}
     net = {k: (np.asarray(v, np.float32).astype(np.float64) if isinstance(v, np.ndarray) else v)
            for k, v in net.items()}
-    tr = lbm.CbcTrainer(np.stack(a0s), np.stack(refs), np.array(nts, np.int32), net, tau=tau,
-                        mach=ma, length=nx, precision=precision, lr=lr, eps=1e-16)
+
+    def trainer(idx, **kw):
+        t = lbm.CbcTrainer(np.stack([a0s[i] for i in idx]), np.stack([refs[i] for i in idx]),
+                           np.array([nts[i] for i in idx], np.int32), net, tau=taus[idx[0]],
+                           mach=machs[idx[0]], length=nx, precision=precision, **kw)
+        t.set_segment_params([taus[i] for i in idx], [machs[i] for i in idx])
+        return t
+    tr = trainer(list(range(len(nts))), lr=lr, eps=1e-16)
     loss0, _ = tr.gradient()
     history = [(0, loss0)]
     _sync()
@@ -419,41 +441,46 @@ def cbc_training_study(n_ts=(5, 10, 25), starts=tuple(range(1, 551, 5)), adam_st
     train_s = time.perf_counter() - t0
     trained = dict(net, **tr.weights())
     loss1, _ = tr.gradient()
-    per_nt = {}
+    del tr
+    per_nt, per_flow = {}, {}
     for n_t in n_ts:
-        idx = [i for i, v in enumerate(nts) if v == n_t]
-        sub = lbm.CbcTrainer(np.stack([a0s[i] for i in idx]), np.stack([refs[i] for i in idx]),
-                             np.full(len(idx), n_t, np.int32), net, tau=tau, mach=ma, length=nx,
-                             precision=precision)
+        sub = trainer([i for i, v in enumerate(nts) if v == n_t])
         before = sub.gradient()[0]
         sub.set_net(trained)
         per_nt[n_t] = {"before": before, "after": sub.gradient()[0]}
         del sub
-    del tr
+    per_seg = len(n_ts) * len(starts)
+    for f in range(len(flows)):
+        sub = trainer(list(range(f * per_seg, (f + 1) * per_seg)))
+        before = sub.gradient()[0]
+        sub.set_net(trained)
+        per_flow[f"ma{machs[f * per_seg]:g}"] = {"before": before, "after": sub.gradient()[0]}
+        del sub
     ev = vortex_study(steps=eval_steps, nx=nx, ny=ny, reference_nx=reference_nx,
-                      precision=precision,
-                      settings={"cbc_s0_k0": (0.0, 0.0), "cbc_s0.25_kMa": (0.25, ma),
+                      precision=precision, vortex=flows[0] or None,
+                      settings={"cbc_s0_k0": (0.0, 0.0), "cbc_s0.25_kMa": (0.25, ma0),
                                 "cbc_init": tuple(init), "nn_cbc_untrained": net,
                                 "nn_cbc_trained": trained},
                       progress=progress)
-    # vortices the network has not seen, each against its own long lattice
-    held_out = {}
-    for name, vx in holdout.items():
+
+    def compare(vx):
         m = vx.get("ma", 0.3)
-        held_out[name] = vortex_study(steps=eval_steps, nx=nx, ny=ny, reference_nx=reference_nx,
-                                      precision=precision, vortex=vx,
-                                      settings={"cbc_s0.25_kMa": (0.25, m),
-                                                "nn_cbc_trained": trained},
-                                      progress=progress)
-    return {"segments": len(nts), "n_ts": list(n_ts), "starts": [int(starts[0]), int(starts[-1]),
-                                                               len(starts)],
+        return vortex_study(steps=eval_steps, nx=nx, ny=ny, reference_nx=reference_nx,
+                            precision=precision, vortex=vx,
+                            settings={"cbc_s0.25_kMa": (0.25, m), "nn_cbc_trained": trained},
+                            progress=progress)
+    # the other training flows, and vortices the network has not seen
+    trained_flows = {f"ma{machs[f * per_seg]:g}": compare(flows[f]) for f in range(1, len(flows))}
+    held_out = {name: compare(vx) for name, vx in holdout.items()}
+    return {"flows": flows, "segments": len(nts), "n_ts": list(n_ts),
+            "starts": [int(starts[0]), int(starts[-1]), len(starts)],
             "adam_steps": adam_steps, "lr": lr, "precision": precision, "train_seconds": train_s,
             "ms_per_adam_step": 1e3 * train_s / max(adam_steps, 1),
             "loss_before": loss0, "loss_after": loss1, "loss_history": history,
-            "loss_per_n_t": per_nt, "network": {k: (np.asarray(v).tolist()
-                                                    if isinstance(v, np.ndarray) else v)
-                                                for k, v in trained.items()},
-            "vortex": ev, "held_out": held_out}
+            "loss_per_n_t": per_nt, "loss_per_flow": per_flow,
+            "network": {k: (np.asarray(v).tolist() if isinstance(v, np.ndarray) else v)
+                        for k, v in trained.items()},
+            "vortex": ev, "trained_flows": trained_flows, "held_out": held_out}
 
 
 def scaling_study(network, re_list=(10.0, 20.0, 50.0, 100.0, 200.0), tau=0.6, steps=150_000,
