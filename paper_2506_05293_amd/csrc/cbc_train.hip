@@ -16,22 +16,26 @@
 //   forward k = 0 .. n_max-1
 //     k_fwd_outlet  one thread per outlet row: gradients of the state at
 //                   the three last columns, network, LODI time derivatives
-//                   (Eqs. 18-28), stored outlet state and time derivatives;
-//     k_fwd_node    one thread per node: pull streaming, outlet state
-//                   (Eq. 29, Eqs. 8-10), BGK; the trajectory is kept;
+//                   (Eqs. 18-28), stored outlet state and time derivatives,
+//                   and the outlet node's update (pull, outlet state by
+//                   Eq. 29 and Eqs. 8-10, BGK);
+//     k_fwd_node    one thread per node left of the outlet column: pull
+//                   streaming, BGK; the trajectory is kept;
 //   k_seed          loss over Omega and its derivative w.r.t. the final
 //                   state (the adjoint's initial value);
 //   backward k = n_max-1 .. 0
-//     k_bwd         per node: the adjoint of the post-collision state at
-//                   step k+1 (the seed, or the streaming adjoint of step k+1
-//                   -- a gather: population q of node x takes the adjoint of
-//                   node x + c_q -- plus the moment terms through which the
-//                   outlet read the three last columns), then the collision
-//                   adjoint at the recomputed pre-collision state of step k+1;
-//                   the two are fused because the collision adjoint at x
-//                   needs only that node's adjoint (adjoints of the pulled
-//                   populations alternate between two buffers);
-//     k_bwd_outlet  one thread per outlet row: adjoints of the outlet
+//     k_bwd         per node left of the last three columns: the adjoint
+//                   of the post-collision state at step k+1 (the seed, or
+//                   the streaming adjoint of step k+1 -- a gather:
+//                   population q of node x takes the adjoint of node x + c_q),
+//                   then the collision adjoint at the recomputed
+//                   pre-collision state of step k+1; the two are fused
+//                   because the collision adjoint at x needs only that
+//                   node's adjoint (adjoints of the pulled populations
+//                   alternate between two buffers);
+//     k_bwd_outlet  the same node adjoints for the last three columns, plus
+//                   the moment terms through which the outlet read them;
+//                   then one thread per outlet row: adjoints of the outlet
 //                   reconstruction, of the LODI update and of the network,
 //                   the parameter gradient summed over the workgroup's 64
 //                   rows in LDS into a per-(segment, row block) FP64 slot;
@@ -40,6 +44,10 @@
 //   k_gsum, k_lsum  first stage of the FP64 sums of the gradient and loss
 //                   slots (fixed order, many workgroups);
 //   k_update        second stage and Adam.
+// The outlet kernels are latency-bound (a few rows, a long chain per row)
+// and the node kernels bandwidth-bound, and within a step neither reads
+// what the other writes: the outlet kernels run on a second stream beside
+// the node kernels, joined by events after every step.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -61,6 +69,15 @@ constexpr int kOW1 = 0, kOB1 = kH * kIn, kOW2 = kOB1 + kH, kOB2 = kOW2 + kH * kH
 static_assert(kOB3 + 2 == kNP, "parameter count");
 constexpr int kRows = 64;            // outlet rows per workgroup (one wave)
 constexpr int kNodes = 256;          // nodes per workgroup
+// The backward outlet workgroup is one wave: it takes the node adjoints of
+// the last three columns of its 64 rows, then the rows, then the
+// parameter-gradient sums.  It runs beside the bulk kernel, so the fewer CU
+// slots it holds through its long row chain the better (four waves, one per
+// column and all sharing the sums, measured 1 % slower per optimiser step).
+constexpr int kBwdThreads = kRows;
+// The step-to-step events only order the two streams of one device: no
+// system-scope fence (measured 3 % faster per optimiser step).
+constexpr unsigned kEventFlags = hipEventDisableTiming | hipEventDisableSystemFence;
 constexpr int kMaxSteps = 64;
 constexpr int kMadj = 12;            // per outlet row: 3 columns x (drho, u, v) + y-part
 
@@ -83,13 +100,15 @@ struct CtArgs {
   T* lamF[2];           // [seg][9][W][ny] each   adjoint of the pulled populations,
                         //                        step k in buffer k & 1
   T* lamP;              // [seg][ny][3]           adjoint of the time derivatives
-  T* madj;              // [seg][ny][12]          moment adjoints from the outlet
+  T* madj[2];           // [seg][ny][12] each     moment adjoints from the outlet,
+                        //                        step k in buffer k & 1
   const T* ref;         // [seg][3][ny][n_max]    rho - 1, u, v
   const int* nts;       // [seg]
   double* gslot;        // [seg][nrb][kNP]
   double* lslot;        // [seg][nlb]
   CtState* st;
   int ny, W, n_max, nrb, nlb;
+  int nlb_fwd, nlb_bwd;  // node blocks of the bulk kernels (columns 0..W-2, 0..W-4)
   int64_t plane;        // ny * W; node (x, y) of a plane at x * ny + y
   const double* seg_omega;   // [seg] 1 / tau
   const double* seg_k1c;     // [seg] (1 - M^2) c_s / L  (kappa_1 = sigma k1c)
@@ -263,6 +282,16 @@ __global__ void __launch_bounds__(kRows) k_fwd_outlet(const CtArgs<T> a, int k) 
   Pn[0] = T(1.0 / 3.0) * l.rho_t;
   Pn[1] = l.u_t;
   Pn[2] = l.v_t;
+  // the outlet node itself: pull, completed by the new outlet state
+  // (Eq. 29, Eqs. 8-10), BGK
+  T g[9];
+  const int64_t n = int64_t(a.W - 1) * a.ny + r;
+  pull(state_at(a, s, k), a.plane, a.W, a.ny, a.W - 1, r, g);
+  outlet_state(g, in.drho + l.rho_t, in.u + l.u_t, in.v + l.v_t);
+  collide_bgk(g, T(a.seg_omega[s]));
+  T* B = state_at(a, s, k + 1);
+#pragma unroll
+  for (int q = 0; q < 9; ++q) B[q * a.plane + n] = g[q];
 }
 
 template <typename T>
@@ -275,12 +304,13 @@ __device__ __forceinline__ void pre_collision(const CtArgs<T>& a, int s, int k, 
   }
 }
 
+// Every node left of the outlet column (the outlet kernel updates that one).
 template <typename T>
 __global__ void __launch_bounds__(kNodes) k_fwd_node(const CtArgs<T> a, int k) {
   const int s = blockIdx.y;
   if (k >= a.nts[s]) return;
   const int64_t n = int64_t(blockIdx.x) * kNodes + threadIdx.x;
-  if (n >= a.plane) return;
+  if (n >= a.plane - a.ny) return;
   const int x = int(n / a.ny), y = int(n - int64_t(x) * a.ny);
   T g[9];
   pre_collision(a, s, k, x, y, g);
@@ -362,11 +392,12 @@ __device__ __forceinline__ void state_adjoint(const CtArgs<T>& a, int s, int kk,
   }
   if (x >= a.W - 3) {
     const int c = x - (a.W - 3);
-    const T* M = a.madj + (int64_t(s) * a.ny + y) * kMadj;
+    const T* MA = a.madj[kk & 1] + int64_t(s) * a.ny * kMadj;
+    const T* M = MA + int64_t(y) * kMadj;
     T ld = M[3 * c], lu = M[3 * c + 1], lv = M[3 * c + 2];
     if (c == 2) {
-      const T* Ms = a.madj + (int64_t(s) * a.ny + wrap(y - 1, a.ny)) * kMadj;   // row y = r + 1
-      const T* Mn = a.madj + (int64_t(s) * a.ny + wrap(y + 1, a.ny)) * kMadj;   // row y = r - 1
+      const T* Ms = MA + int64_t(wrap(y - 1, a.ny)) * kMadj;   // row y = r + 1
+      const T* Mn = MA + int64_t(wrap(y + 1, a.ny)) * kMadj;   // row y = r - 1
       ld += Ms[9] - Mn[9];
       lu += Ms[10] - Mn[10];
       lv += Ms[11] - Mn[11];
@@ -379,14 +410,12 @@ __device__ __forceinline__ void state_adjoint(const CtArgs<T>& a, int s, int kk,
   }
 }
 
+// Adjoint of the pulled populations of node (x, y) at step k (lf): the
+// adjoint of the post-collision state at step k+1 (the seed at the last
+// step), then the collision adjoint at the recomputed pre-collision state.
 template <typename T>
-__global__ void __launch_bounds__(kNodes) k_bwd(const CtArgs<T> a, int k) {
-  const int s = blockIdx.y;
-  const int nt = a.nts[s];
-  if (k >= nt) return;
-  const int64_t n = int64_t(blockIdx.x) * kNodes + threadIdx.x;
-  if (n >= a.plane) return;
-  const int x = int(n / a.ny), y = int(n - int64_t(x) * a.ny);
+__device__ __forceinline__ void node_adjoint(const CtArgs<T>& a, int s, int nt, int k, int x, int y,
+                                             int64_t n, T lf[9]) {
   const int64_t so = int64_t(s) * 9 * a.plane;
   T lam[9];
   if (k + 1 == nt) {
@@ -409,21 +438,41 @@ __global__ void __launch_bounds__(kNodes) k_bwd(const CtArgs<T> a, int k) {
     Ljx += wl * (T(3 * cx(q)) + T(9) * cu * T(cx(q)) - T(3) * u);
     Ljy += wl * (T(3 * cy(q)) + T(9) * cu * T(cy(q)) - T(3) * v);
   }
-  T* LF = a.lamF[k & 1] + so;
   const T om = T(a.seg_omega[s]);
 #pragma unroll
   for (int q = 0; q < 9; ++q)
-    LF[q * a.plane + n] = (T(1) - om) * lam[q] + om * (Lr + T(cx(q)) * Ljx + T(cy(q)) * Ljy);
+    lf[q] = (T(1) - om) * lam[q] + om * (Lr + T(cx(q)) * Ljx + T(cy(q)) * Ljy);
 }
 
+// Every node left of the last three columns (whose adjoints need the
+// outlet's moment adjoints: the outlet kernel takes those).
+template <typename T>
+__global__ void __launch_bounds__(kNodes) k_bwd(const CtArgs<T> a, int k) {
+  const int s = blockIdx.y;
+  const int nt = a.nts[s];
+  if (k >= nt) return;
+  const int64_t n = int64_t(blockIdx.x) * kNodes + threadIdx.x;
+  if (n >= a.plane - 3 * int64_t(a.ny)) return;
+  const int x = int(n / a.ny), y = int(n - int64_t(x) * a.ny);
+  T lf[9];
+  node_adjoint(a, s, nt, k, x, y, n, lf);
+  T* LF = a.lamF[k & 1] + int64_t(s) * 9 * a.plane;
+#pragma unroll
+  for (int q = 0; q < 9; ++q) LF[q * a.plane + n] = lf[q];
+}
+
+// Per-row arrays, read row by row in the gradient sums and one row per lane
+// in the row work: rows of an odd number of words keep the lanes of the
+// latter on distinct banks.
+constexpr int kHp = kH + 1;
 template <typename T>
 struct alignas(16) BwdSmem {
   T z[kRows][kIn];
-  T h1[kRows][kH];
-  T h2[kRows][kH];
-  T d1[kRows][kH];    // adjoint of the first pre-activation
-  T d2[kRows][kH];    // adjoint of the second pre-activation
-  T ds[kRows][2];     // adjoint of s_0, s_1
+  T h1[kRows][kHp];
+  T h2[kRows][kHp];
+  T d1[kRows][kHp];   // adjoint of the first pre-activation
+  T d2[kRows][kHp];   // adjoint of the second pre-activation
+  T ds[kRows][3];     // adjoint of s_0, s_1
 };
 
 // Sum over the workgroup's rows with four independent accumulators (a fixed
@@ -442,16 +491,20 @@ __device__ __forceinline__ double sum_rows(F f) {
 }
 
 template <typename T>
-// Four waves per workgroup: wave 0 takes the 64 outlet rows, all four stage
-// the weights and share the parameter-gradient sums.
-__global__ void __launch_bounds__(kNodes) k_bwd_outlet(const CtArgs<T> a, int k) {
+// The node adjoints of the outlet column and of the two columns before it
+// for the workgroup's 64 rows (with several waves, one column each), then
+// the outlet rows on the first wave; every thread stages the weights and
+// shares the parameter-gradient sums.
+__global__ void __launch_bounds__(kBwdThreads) k_bwd_outlet(const CtArgs<T> a, int k) {
   __shared__ BwdSmem<T> sm;
   __shared__ float sw[kNP];
   const int s = blockIdx.y;
-  if (k >= a.nts[s]) return;                     // uniform over the workgroup
+  const int nt = a.nts[s];
+  if (k >= nt) return;                           // uniform over the workgroup
   const int j = threadIdx.x;
-  const bool rowt = j < kRows;
-  const int r = blockIdx.x * kRows + j;
+  const int wv = j / kRows;
+  const bool rowt = wv == 0;
+  const int r = blockIdx.x * kRows + (j & (kRows - 1));
   const CtState* st = a.st;
   const T cs2 = T(1.0 / 3.0), cs = T(0.57735026918962576451);
   // every global load of the row is issued before the weights are staged
@@ -466,6 +519,21 @@ __global__ void __launch_bounds__(kNodes) k_bwd_outlet(const CtArgs<T> a, int k)
   T d1 = T(0), u1 = T(0), v1 = T(0);
 #pragma unroll
   for (int q = 0; q < 9; ++q) lf[q] = T(0);
+  // the outlet column's adjoint stays in wave 0's registers for the outlet
+#pragma unroll
+  for (int c = wv; c < 3; c += kBwdThreads / kRows) {
+    if (r < a.ny) {
+      const int x = a.W - 1 - c;
+      const int64_t n = int64_t(x) * a.ny + r;
+      T l9[9];
+      node_adjoint(a, s, nt, k, x, r, n, l9);
+#pragma unroll
+      for (int q = 0; q < 9; ++q) {
+        if (c == 0) lf[q] = l9[q];
+        else LF[q * a.plane + n] = l9[q];
+      }
+    }
+  }
   if (rowt) {
     in = outlet_inputs(state_at(a, s, k), a.plane, a.W, a.ny, rl);
     const T* P = a.dts + ((int64_t(s) * (a.n_max + 1) + k) * a.ny + rl) * 3;
@@ -478,10 +546,8 @@ __global__ void __launch_bounds__(kNodes) k_bwd_outlet(const CtArgs<T> a, int k)
     d1 = o3[0];
     u1 = o3[1];
     v1 = o3[2];
-#pragma unroll
-    for (int q = 0; q < 9; ++q) lf[q] = LF[q * a.plane + on];
   }
-  stage_weights(st, sw, kNodes);
+  stage_weights(st, sw, kBwdThreads);
   if (valid) {
     // recompute the forward of this row
     T z[kIn];
@@ -610,7 +676,7 @@ __global__ void __launch_bounds__(kNodes) k_bwd_outlet(const CtArgs<T> a, int k)
     for (int i = 0; i < 3; ++i) LP[i] = lz[6 + i] / T(st->sd[6 + i]);
 
     // gradients -> moments of the three columns
-    T* M = a.madj + (int64_t(s) * a.ny + r) * kMadj;
+    T* M = a.madj[k & 1] + (int64_t(s) * a.ny + r) * kMadj;
     M[0] = T(0.5) * cs2 * lg[0];
     M[1] = T(0.5) * lg[1];
     M[2] = T(0.5) * lg[2];
@@ -634,16 +700,16 @@ __global__ void __launch_bounds__(kNodes) k_bwd_outlet(const CtArgs<T> a, int k)
   // parameter gradient of the workgroup's rows, added to its slot (the
   // slot values are all requested before the sums, so their latency overlaps)
   double* G = a.gslot + (int64_t(s) * a.nrb + blockIdx.x) * kNP;
-  constexpr int kPer = (kNP + kNodes - 1) / kNodes;
+  constexpr int kPer = (kNP + kBwdThreads - 1) / kBwdThreads;
   double old[kPer];
 #pragma unroll
   for (int u = 0; u < kPer; ++u) {
-    const int p = j + u * kNodes;
+    const int p = j + u * kBwdThreads;
     old[u] = p < kNP ? G[p] : 0.0;
   }
 #pragma unroll
   for (int u = 0; u < kPer; ++u) {
-    const int p = j + u * kNodes;
+    const int p = j + u * kBwdThreads;
     if (p >= kNP) break;
     double acc;
     if (p < kOB1) {
@@ -770,7 +836,7 @@ CtLayout ct_layout(const lbm_cbc_train_params& p) {
   L.lamA = take(ns * 9 * size_t(L.plane) * e);
   L.lamF = take(2 * ns * 9 * size_t(L.plane) * e);
   L.lamP = take(ns * ny * 3 * e);
-  L.madj = take(ns * ny * kMadj * e);
+  L.madj = take(2 * ns * ny * kMadj * e);
   L.ref = take(ns * 3 * ny * p.n_max * e);
   L.nts = take(ns * sizeof(int));
   L.gslot = take(ns * L.nrb * kNP * sizeof(double));
@@ -816,6 +882,8 @@ using namespace lbm;
 struct lbm_cbc_trainer {
   lbm_cbc_train_params p;
   hipStream_t stream;
+  hipStream_t side = nullptr;                  // the outlet kernels' stream
+  hipEvent_t ev_node = nullptr, ev_side = nullptr;
   CtLayout L;
   char* base;
   CtState* st;
@@ -833,7 +901,8 @@ struct lbm_cbc_trainer {
     a.lamF[0] = reinterpret_cast<T*>(base + L.lamF);
     a.lamF[1] = a.lamF[0] + size_t(p.n_seg) * 9 * size_t(L.plane);
     a.lamP = reinterpret_cast<T*>(base + L.lamP);
-    a.madj = reinterpret_cast<T*>(base + L.madj);
+    a.madj[0] = reinterpret_cast<T*>(base + L.madj);
+    a.madj[1] = a.madj[0] + size_t(p.n_seg) * size_t(p.ny) * kMadj;
     a.ref = reinterpret_cast<const T*>(base + L.ref);
     a.nts = reinterpret_cast<const int*>(base + L.nts);
     a.gslot = reinterpret_cast<double*>(base + L.gslot);
@@ -844,6 +913,8 @@ struct lbm_cbc_trainer {
     a.n_max = p.n_max;
     a.nrb = L.nrb;
     a.nlb = L.nlb;
+    a.nlb_fwd = int((L.plane - p.ny + kNodes - 1) / kNodes);
+    a.nlb_bwd = int((L.plane - 3 * int64_t(p.ny) + kNodes - 1) / kNodes);
     a.plane = L.plane;
     a.seg_omega = reinterpret_cast<const double*>(base + L.seg_omega);
     a.seg_k1c = reinterpret_cast<const double*>(base + L.seg_k1c);
@@ -851,22 +922,41 @@ struct lbm_cbc_trainer {
     return a;
   }
 
+  // One step on both streams: each first waits for the other's previous
+  // step (a wait takes the event's latest record at the time of the call).
+  hipError_t join_step() {
+    const hipError_t e = hipStreamWaitEvent(stream, ev_side, 0);
+    return e != hipSuccess ? e : hipStreamWaitEvent(side, ev_node, 0);
+  }
+
   template <typename T>
   lbm_status run_t(bool update) {
     const CtArgs<T> a = args<T>();
     const dim3 grow(L.nrb, p.n_seg), gnode(L.nlb, p.n_seg);
+    const dim3 gfwd(a.nlb_fwd, p.n_seg), gbwd(a.nlb_bwd, p.n_seg);
+    CT_TRY(hipEventRecord(ev_node, stream));
+    CT_TRY(hipEventRecord(ev_side, side));
     for (int k = 0; k < p.n_max; ++k) {
-      hipLaunchKernelGGL(k_fwd_outlet<T>, grow, dim3(kRows), 0, stream, a, k);
-      hipLaunchKernelGGL(k_fwd_node<T>, gnode, dim3(kNodes), 0, stream, a, k);
+      CT_TRY(join_step());
+      hipLaunchKernelGGL(k_fwd_outlet<T>, grow, dim3(kRows), 0, side, a, k);
+      CT_TRY(hipEventRecord(ev_side, side));
+      hipLaunchKernelGGL(k_fwd_node<T>, gfwd, dim3(kNodes), 0, stream, a, k);
+      CT_TRY(hipEventRecord(ev_node, stream));
     }
+    CT_TRY(hipStreamWaitEvent(stream, ev_side, 0));
     const int64_t ng = int64_t(p.n_seg) * L.nrb * kNP;
     hipLaunchKernelGGL(k_zero, dim3(unsigned((ng + kNodes - 1) / kNodes)), dim3(kNodes), 0, stream,
                        a.gslot, ng);
     hipLaunchKernelGGL(k_seed<T>, gnode, dim3(kNodes), 0, stream, a);
+    CT_TRY(hipEventRecord(ev_node, stream));
     for (int k = p.n_max - 1; k >= 0; --k) {
-      hipLaunchKernelGGL(k_bwd<T>, gnode, dim3(kNodes), 0, stream, a, k);
-      hipLaunchKernelGGL(k_bwd_outlet<T>, grow, dim3(kNodes), 0, stream, a, k);
+      CT_TRY(join_step());
+      hipLaunchKernelGGL(k_bwd_outlet<T>, grow, dim3(kBwdThreads), 0, side, a, k);
+      CT_TRY(hipEventRecord(ev_side, side));
+      hipLaunchKernelGGL(k_bwd<T>, gbwd, dim3(kNodes), 0, stream, a, k);
+      CT_TRY(hipEventRecord(ev_node, stream));
     }
+    CT_TRY(hipStreamWaitEvent(stream, ev_side, 0));
     double bc1 = 1.0, bc2 = 1.0;
     if (update) {
       bc1 = 1.0 - std::pow(p.beta1, double(adam_t));
@@ -887,6 +977,11 @@ struct lbm_cbc_trainer {
 
   lbm_status run(bool update) {
     if (!has_data || !has_net) return set_error(LBM_ESTATE, "segments and network must be set first");
+    // the second stream and the events: made on the first run, on the
+    // device current then
+    if (!ev_node) CT_TRY(hipEventCreateWithFlags(&ev_node, kEventFlags));
+    if (!ev_side) CT_TRY(hipEventCreateWithFlags(&ev_side, kEventFlags));
+    if (!side) CT_TRY(hipStreamCreateWithFlags(&side, hipStreamNonBlocking));
     return p.precision == LBM_FP64 ? run_t<double>(update) : run_t<float>(update);
   }
 };
@@ -940,6 +1035,13 @@ lbm_status lbm_cbc_train_create(const lbm_cbc_train_params* p, void* ws, size_t 
 }
 
 lbm_status lbm_cbc_train_destroy(lbm_cbc_trainer* t) {
+  if (!t) return LBM_OK;
+  if (t->side) {
+    (void)hipStreamSynchronize(t->side);
+    (void)hipStreamDestroy(t->side);
+  }
+  if (t->ev_node) (void)hipEventDestroy(t->ev_node);
+  if (t->ev_side) (void)hipEventDestroy(t->ev_side);
   delete t;
   return LBM_OK;
 }
