@@ -47,12 +47,17 @@ static_assert(opp3(7) == 8 && opp3(8) == 7 && c3(7, 0) == -c3(8, 0) && c3(17, 2)
               "opposites");
 
 constexpr uint32_t kSolid3 = 1u << 24;    // link word: the node itself is solid
-constexpr int kB3 = 256;                  // nodes per workgroup (along x)
+constexpr int kB3 = 256;                  // nodes per row of a workgroup (along x)
+// (y, z) rows per workgroup: two or four rows (larger contiguous pieces of
+// each population plane per workgroup) measured 1.7 % and 4.4 % slower
+constexpr int kR3 = 1;
+constexpr int kT3 = kB3 * kR3;             // threads per workgroup
 
 struct Step3 {
   const void* A;
   void* B;
   const uint32_t* links;
+  const uint8_t* rowf;   // [nz][ny]: 1 where the row holds a solid node or a body link
   double* part;          // [nblocks][4]
   int nx, ny, nz, pitch, ntx, nblocks;
   int64_t plane;         // nz * ny * pitch
@@ -152,16 +157,19 @@ __device__ __forceinline__ T bgk3(T g[19], T omega) {
 }
 
 template <typename T>
-__global__ void __launch_bounds__(kB3) k3_step(const Step3 L) {
-  __shared__ double sh[kB3 / 64][4];
+__global__ void __launch_bounds__(kT3) k3_step(const Step3 L) {
+  __shared__ double sh[kT3 / 64][4];
   const int v = xcd_range(int(blockIdx.x), L.nblocks);
-  const int tx = v % L.ntx, row = v / L.ntx;
+  const int tx = v % L.ntx;
+  const int row = (v / L.ntx) * kR3 + int(threadIdx.x) / kB3;
   const int y = row % L.ny, z = row / L.ny;
-  const int x = tx * kB3 + int(threadIdx.x);
+  const int x = tx * kB3 + int(threadIdx.x) % kB3;
   T fx = T(0), fy = T(0), fz = T(0), dm = T(0);
-  if (x < L.nx) {
+  if (x < L.nx && z < L.nz) {
     const int64_t idx = (int64_t(z) * L.ny + y) * L.pitch + x;
-    const uint32_t lk = L.links[idx];
+    // rows far from the body hold no link word worth reading (4 of the
+    // 156 bytes per node)
+    const uint32_t lk = L.rowf[row] ? L.links[idx] : 0u;
     if (!(lk & kSolid3)) {
       const T* __restrict__ A = static_cast<const T*>(L.A);
       T g[19];
@@ -213,7 +221,10 @@ __global__ void __launch_bounds__(kB3) k3_step(const Step3 L) {
   __syncthreads();
   if (threadIdx.x < 4) {
     const int c = threadIdx.x;
-    L.part[int64_t(v) * 4 + c] = (sh[0][c] + sh[1][c]) + (sh[2][c] + sh[3][c]);
+    double t = 0.0;
+#pragma unroll
+    for (int i = 0; i < kT3 / 64; i += 4) t += (sh[i][c] + sh[i + 1][c]) + (sh[i + 2][c] + sh[i + 3][c]);
+    L.part[int64_t(v) * 4 + c] = t;
   }
 }
 
@@ -259,7 +270,7 @@ size_t al256(size_t b) { return (b + 255) / 256 * 256; }
 struct Layout3 {
   int pitch, ntx, nblocks;
   int64_t plane;
-  size_t A, B, links, part, last, hist, total;
+  size_t A, B, links, rowf, part, last, hist, total;
 };
 
 size_t esz(int precision) { return precision == LBM_FP64 ? 8 : 4; }
@@ -268,7 +279,7 @@ Layout3 layout3(const lbm3d_params& p) {
   Layout3 L;
   L.pitch = (p.nx + 63) / 64 * 64;
   L.ntx = (p.nx + kB3 - 1) / kB3;
-  L.nblocks = L.ntx * p.ny * p.nz;
+  L.nblocks = L.ntx * ((p.ny * p.nz + kR3 - 1) / kR3);
   L.plane = int64_t(p.nz) * p.ny * L.pitch;
   size_t o = 0;
   auto take = [&](size_t b) {
@@ -279,6 +290,7 @@ Layout3 layout3(const lbm3d_params& p) {
   L.A = take(size_t(19) * L.plane * esz(p.precision));
   L.B = take(size_t(19) * L.plane * esz(p.precision));
   L.links = take(size_t(L.plane) * 4);
+  L.rowf = take(size_t(p.nz) * p.ny);
   L.part = take(size_t(kRing) * L.nblocks * 4 * 8);
   L.last = take(8 * 8);
   L.hist = take(size_t(p.history_cap) * 3 * 8);
@@ -430,6 +442,7 @@ lbm_status lbm3d_set_geometry(lbm3d_ctx* c, const uint8_t* host_mask) {
   const bool xper = p.xbc == LBM_X_PERIODIC, yper = p.lateral_y == LBM_LATERAL_PERIODIC,
              zper = p.lateral_z == LBM_LATERAL_PERIODIC;
   std::vector<uint32_t> links(size_t(c->L.plane), 0);
+  std::vector<uint8_t> rowf(size_t(nz) * ny, 0);
   for (int z = 0; z < nz; ++z)
     for (int y = 0; y < ny; ++y)
       for (int x = 0; x < nx; ++x) {
@@ -452,8 +465,11 @@ lbm_status lbm3d_set_geometry(lbm3d_ctx* c, const uint8_t* host_mask) {
           if (host_mask[(size_t(sz) * ny + sy) * nx + sx]) lk |= 1u << q;
         }
         links[(size_t(z) * ny + y) * c->L.pitch + x] = lk;
+        if (lk) rowf[size_t(z) * ny + y] = 1;
       }
   L3_TRY(hipMemcpyAsync(c->base + c->L.links, links.data(), links.size() * 4, hipMemcpyHostToDevice,
+                        c->stream));
+  L3_TRY(hipMemcpyAsync(c->base + c->L.rowf, rowf.data(), rowf.size(), hipMemcpyHostToDevice,
                         c->stream));
   L3_TRY(hipMemsetAsync(c->base + c->L.last, 0, 8 * 8, c->stream));
   c->has_geometry = true;
@@ -476,6 +492,7 @@ lbm_status lbm3d_step(lbm3d_ctx* c, int64_t nsteps) {
   const Layout3& L = c->L;
   Step3 s;
   s.links = reinterpret_cast<const uint32_t*>(c->base + L.links);
+  s.rowf = reinterpret_cast<const uint8_t*>(c->base + L.rowf);
   s.part = reinterpret_cast<double*>(c->base + L.part);
   s.nx = p.nx;
   s.ny = p.ny;
@@ -496,9 +513,9 @@ lbm_status lbm3d_step(lbm3d_ctx* c, int64_t nsteps) {
     s.B = c->base + c->bufoff(1 - c->cur);
     s.part = ring + (c->t % kRing) * int64_t(L.nblocks) * 4;
     if (p.precision == LBM_FP64)
-      hipLaunchKernelGGL(k3_step<double>, dim3(L.nblocks), dim3(kB3), 0, c->stream, s);
+      hipLaunchKernelGGL(k3_step<double>, dim3(L.nblocks), dim3(kT3), 0, c->stream, s);
     else
-      hipLaunchKernelGGL(k3_step<float>, dim3(L.nblocks), dim3(kB3), 0, c->stream, s);
+      hipLaunchKernelGGL(k3_step<float>, dim3(L.nblocks), dim3(kT3), 0, c->stream, s);
     c->cur = 1 - c->cur;
     ++c->t;
     if (++c->pending == kRing) {
