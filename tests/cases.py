@@ -39,3 +39,23 @@ def c2(nx=4096, ny=1024):
 def oracle_kwargs(case):
     keys = ("tau", "collision", "lateral", "u_in", "noise_amp", "seed")
     return {k: case[k] for k in keys}
+
+
+def random_params(seed, w_scale=1.0, out_sd=1e-3):
+    """A seeded 27-64-64-3 outflow network (Glorot-uniform weights scaled by
+    w_scale, output standardisation of scale out_sd)."""
+    rng = np.random.default_rng(seed)
+
+    def glorot(o, i):
+        a = np.sqrt(6.0 / (o + i)) * w_scale
+        return rng.uniform(-a, a, (o, i))
+    return {"w1": glorot(64, 27), "b1": 0.1 * rng.standard_normal(64),
+            "w2": glorot(64, 64), "b2": 0.1 * rng.standard_normal(64),
+            "w3": glorot(3, 64), "b3": 0.1 * rng.standard_normal(3),
+            "mu_in": 0.002 * rng.standard_normal(27), "sd_in": 0.01 + 0.01 * rng.random(27),
+            "mu_out": 1e-4 * rng.standard_normal(3), "sd_out": out_sd * (1 + rng.random(3))}
+
+
+def f32_values(P):
+    """The network's values rounded to FP32 (the form the step holds)."""
+    return {k: np.asarray(v, np.float32).astype(np.float64) for k, v in P.items()}
