@@ -29,8 +29,9 @@
  *
  * Arithmetic in the precision chosen (populations stored as offsets f - w
  * in FP64 or FP32), network weights held as FP32 masters (the form the
- * step reads), gradients summed in FP64 in a fixed order: runs are
- * reproducible.  Memory: the whole trajectory of every segment is kept,
+ * step reads), gradients summed over each block of 64 outlet rows in the
+ * precision chosen and over the blocks in FP64, all in a fixed order: runs
+ * are reproducible.  Memory: the whole trajectory of every segment is kept,
  * about (n_max + 5) * 9 * ny * W * n_seg values of the precision.
  *
  * Conventions as in lbm.h: asynchronous on the given stream unless a
