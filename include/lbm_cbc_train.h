@@ -36,7 +36,7 @@
  *
  * Conventions as in lbm.h: asynchronous on the given stream unless a
  * comment says it synchronises, caller-owned workspace, status codes and
- * lbm_last_error().  The outlet kernels of a step run on a second stream
+ * lbm_last_error().  The backward outlet kernels run on a second stream
  * that the trainer creates on its first gradient or step (on the device
  * current then) and joins back into the given stream before the call's
  * work ends there; lbm_cbc_train_destroy waits for it and releases it.

@@ -14,13 +14,13 @@
 // One optimiser step, every segment at once (a segment whose n_t is
 // shorter than the step index sits out that step):
 //   forward k = 0 .. n_max-1
-//     k_fwd_outlet  one thread per outlet row: gradients of the state at
-//                   the three last columns, network, LODI time derivatives
-//                   (Eqs. 18-28), stored outlet state and time derivatives,
-//                   and the outlet node's update (pull, outlet state by
-//                   Eq. 29 and Eqs. 8-10, BGK);
-//     k_fwd_node    one thread per node left of the outlet column: pull
-//                   streaming, BGK; the trajectory is kept;
+//     k_fwd         outlet workgroups, one thread per outlet row: gradients
+//                   of the state at the three last columns, network, LODI
+//                   time derivatives (Eqs. 18-28), stored outlet state and
+//                   time derivatives, and the outlet node's update (pull,
+//                   outlet state by Eq. 29 and Eqs. 8-10, BGK); node
+//                   workgroups, one thread per node left of the outlet
+//                   column: pull streaming, BGK; the trajectory is kept;
 //   k_seed          loss over Omega and its derivative w.r.t. the final
 //                   state (the adjoint's initial value);
 //   backward k = n_max-1 .. 0
@@ -45,10 +45,12 @@
 //   k_gsum, k_lsum  first stage of the FP64 sums of the gradient and loss
 //                   slots (fixed order, many workgroups);
 //   k_update        second stage and Adam.
-// The outlet kernels are latency-bound (a few rows, a long chain per row)
-// and the node kernels bandwidth-bound, and within a step neither reads
-// what the other writes: the outlet kernels run on a second stream beside
-// the node kernels, joined by events after every step.
+// The outlet work is latency-bound (a few rows, a long chain per row) and
+// the node work bandwidth-bound, and within a step neither reads what the
+// other writes.  Forward, both are workgroups of one launch (the outlet
+// ones are few, hold little, and start first); backward, the outlet kernel
+// holds a large LDS block through its chain and runs on a second stream
+// beside the node kernel, the two joined by events after every step.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -110,6 +112,7 @@ struct CtArgs {
   CtState* st;
   int ny, W, n_max, nrb, nlb;
   int nlb_fwd, nlb_bwd;  // node blocks of the bulk kernels (columns 0..W-2, 0..W-4)
+  int nrb_fwd, n_seg;    // outlet blocks of the forward kernel (256 rows each), segments
   int64_t plane;        // ny * W; node (x, y) of a plane at x * ny + y
   const double* seg_omega;   // [seg] 1 / tau
   const double* seg_k1c;     // [seg] (1 - M^2) c_s / L  (kappa_1 = sigma k1c)
@@ -231,21 +234,19 @@ __device__ __forceinline__ void stage_weights(const CtState* st, float* sw, int 
   __syncthreads();
 }
 
+// The outlet row r of segment s at step k: every global load of the row is
+// issued before the weights are staged, so the two overlap (rows past the
+// end read the last row and store nothing).  Called by every thread of the
+// workgroup (the staging synchronises it).
 template <typename T>
-__global__ void __launch_bounds__(kRows) k_fwd_outlet(const CtArgs<T> a, int k) {
-  __shared__ float sw[kNP];
-  const int s = blockIdx.y;
-  if (k >= a.nts[s]) return;                     // uniform over the workgroup
+__device__ __forceinline__ void fwd_outlet_row(const CtArgs<T>& a, float* sw, int s, int k, int r) {
   const CtState* st = a.st;
-  // every global load of the row is issued before the weights are staged,
-  // so the two overlap (rows past the end read the last row and store nothing)
-  const int r = blockIdx.x * kRows + threadIdx.x;
   const bool valid = r < a.ny;
   const int rl = valid ? r : a.ny - 1;
   const OutIn<T> in = outlet_inputs(state_at(a, s, k), a.plane, a.W, a.ny, rl);
   const T* P = a.dts + ((int64_t(s) * (a.n_max + 1) + k) * a.ny + rl) * 3;
   const T prev[3] = {P[0], P[1], P[2]};
-  stage_weights(st, sw, kRows);
+  stage_weights(st, sw, kNodes);
   if (!valid) return;
   T z[kIn];
 #pragma unroll
@@ -305,12 +306,24 @@ __device__ __forceinline__ void pre_collision(const CtArgs<T>& a, int s, int k, 
   }
 }
 
-// Every node left of the outlet column (the outlet kernel updates that one).
+// One forward step: the first n_seg * nrb_fwd workgroups take the outlet
+// rows (256 per workgroup; their network chain is long but they are few and
+// start first), the rest every node left of the outlet column.
 template <typename T>
-__global__ void __launch_bounds__(kNodes) k_fwd_node(const CtArgs<T> a, int k) {
-  const int s = blockIdx.y;
+__global__ void __launch_bounds__(kNodes) k_fwd(const CtArgs<T> a, int k) {
+  __shared__ float sw[kNP];
+  int b = int(blockIdx.x);
+  const int nout = a.n_seg * a.nrb_fwd;
+  if (b < nout) {
+    const int s = b / a.nrb_fwd;
+    if (k >= a.nts[s]) return;                   // uniform over the workgroup
+    fwd_outlet_row(a, sw, s, k, (b - s * a.nrb_fwd) * kNodes + int(threadIdx.x));
+    return;
+  }
+  b -= nout;
+  const int s = b / a.nlb_fwd;
   if (k >= a.nts[s]) return;
-  const int64_t n = int64_t(blockIdx.x) * kNodes + threadIdx.x;
+  const int64_t n = int64_t(b - s * a.nlb_fwd) * kNodes + threadIdx.x;
   if (n >= a.plane - a.ny) return;
   const int x = int(n / a.ny), y = int(n - int64_t(x) * a.ny);
   T g[9];
@@ -918,6 +931,8 @@ struct lbm_cbc_trainer {
     a.nlb = L.nlb;
     a.nlb_fwd = int((L.plane - p.ny + kNodes - 1) / kNodes);
     a.nlb_bwd = int((L.plane - 3 * int64_t(p.ny) + kNodes - 1) / kNodes);
+    a.nrb_fwd = (p.ny + kNodes - 1) / kNodes;
+    a.n_seg = p.n_seg;
     a.plane = L.plane;
     a.seg_omega = reinterpret_cast<const double*>(base + L.seg_omega);
     a.seg_k1c = reinterpret_cast<const double*>(base + L.seg_k1c);
@@ -936,22 +951,16 @@ struct lbm_cbc_trainer {
   lbm_status run_t(bool update) {
     const CtArgs<T> a = args<T>();
     const dim3 grow(L.nrb, p.n_seg), gnode(L.nlb, p.n_seg);
-    const dim3 gfwd(a.nlb_fwd, p.n_seg), gbwd(a.nlb_bwd, p.n_seg);
-    CT_TRY(hipEventRecord(ev_node, stream));
-    CT_TRY(hipEventRecord(ev_side, side));
-    for (int k = 0; k < p.n_max; ++k) {
-      CT_TRY(join_step());
-      hipLaunchKernelGGL(k_fwd_outlet<T>, grow, dim3(kRows), 0, side, a, k);
-      CT_TRY(hipEventRecord(ev_side, side));
-      hipLaunchKernelGGL(k_fwd_node<T>, gfwd, dim3(kNodes), 0, stream, a, k);
-      CT_TRY(hipEventRecord(ev_node, stream));
-    }
-    CT_TRY(hipStreamWaitEvent(stream, ev_side, 0));
+    const dim3 gbwd(a.nlb_bwd, p.n_seg);
+    const unsigned gf = unsigned(p.n_seg) * unsigned(a.nrb_fwd + a.nlb_fwd);
+    for (int k = 0; k < p.n_max; ++k)
+      hipLaunchKernelGGL(k_fwd<T>, dim3(gf), dim3(kNodes), 0, stream, a, k);
     const int64_t ng = int64_t(p.n_seg) * L.nrb * kNP;
     hipLaunchKernelGGL(k_zero, dim3(unsigned((ng + kNodes - 1) / kNodes)), dim3(kNodes), 0, stream,
                        a.gslot, ng);
     hipLaunchKernelGGL(k_seed<T>, gnode, dim3(kNodes), 0, stream, a);
     CT_TRY(hipEventRecord(ev_node, stream));
+    CT_TRY(hipEventRecord(ev_side, side));
     for (int k = p.n_max - 1; k >= 0; --k) {
       CT_TRY(join_step());
       hipLaunchKernelGGL(k_bwd_outlet<T>, grow, dim3(kBwdThreads), 0, side, a, k);
