@@ -194,6 +194,29 @@ def test_per_segment_relaxation_and_mach():
         tr.set_segment_params([0.6, 0.5, 0.7, 0.7], None)
 
 
+def test_runs_are_bitwise_reproducible():
+    # the backward outlet kernel runs on a second stream joined to the
+    # node kernel's after every step; sums are in a fixed order, so repeated
+    # gradients and a second trainer taking the same Adam steps agree bit
+    # for bit (a missing wait between the streams would show up here)
+    _say("cbc train reproducibility, fp32 and fp64")
+    net = _net(7)
+    segs, a0s, refs, nts, cfg = _case(48, 131, (12, 3, 7))
+    for prec in ("fp32", "fp64"):
+        tr = _trainer(a0s, refs, nts, net, cfg, prec, lr=1e-3, eps=1e-12)
+        first = tr.gradient()
+        for _ in range(3):
+            again = tr.gradient()
+            assert again[0] == first[0]
+            assert np.array_equal(_flat(again[1]), _flat(first[1]))
+        tr.step(4)
+        other = _trainer(a0s, refs, nts, net, cfg, prec, lr=1e-3, eps=1e-12)
+        other.step(4)
+        assert tr.loss() == other.loss()
+        assert np.array_equal(_flat(tr.weights()), _flat(other.weights()))
+        assert np.array_equal(tr.final_state(2), other.final_state(2))
+
+
 def test_free_stream_gives_zero_loss_and_gradient():
     _say("cbc train free stream")
     nx, ny, n_max, u0 = 30, 20, 6, 0.08
