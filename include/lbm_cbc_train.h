@@ -32,7 +32,7 @@
  * step reads), gradients summed over each block of 64 outlet rows in the
  * precision chosen and over the blocks in FP64, all in a fixed order: runs
  * are reproducible.  Memory: the whole trajectory of every segment is kept,
- * about (n_max + 5) * 9 * ny * W * n_seg values of the precision.
+ * about (n_max + 3) * 9 * ny * W * n_seg values of the precision.
  *
  * Conventions as in lbm.h: asynchronous on the given stream unless a
  * comment says it synchronises, caller-owned workspace, status codes and

@@ -21,8 +21,9 @@
 //                   outlet state by Eq. 29 and Eqs. 8-10, BGK); node
 //                   workgroups, one thread per node left of the outlet
 //                   column: pull streaming, BGK; the trajectory is kept;
-//   k_seed          loss over Omega and its derivative w.r.t. the final
-//                   state (the adjoint's initial value);
+//   k_seed          loss over Omega (its derivative with respect to the
+//                   final state, the adjoint's initial value, is recomputed
+//                   where the backward pass takes it);
 //   backward k = n_max-1 .. 0
 //     k_bwd         per node left of the last three columns: the adjoint
 //                   of the post-collision state at step k+1 (the seed, or
@@ -99,7 +100,6 @@ struct CtArgs {
   T* traj;              // [seg][n_max+1][9][W][ny] (rows fastest)
   T* outs;              // [seg][n_max][ny][3]    outlet state drho', u', v'
   T* dts;               // [seg][n_max+1][ny][3]  c_s^2 rho_t, u_t, v_t
-  T* lamA;              // [seg][9][W][ny]        adjoint of the final state (seed)
   T* lamF[2];           // [seg][9][W][ny] each   adjoint of the pulled populations,
                         //                        step k in buffer k & 1
   T* lamP;              // [seg][ny][3]           adjoint of the time derivatives
@@ -347,6 +347,33 @@ __device__ __forceinline__ double block_sum(double v, double* sh) {
   return t;
 }
 
+// The loss term of node (x, y) of segment s (0 outside Omega, the last n_t
+// columns) and its derivative with respect to the node's final state, the
+// adjoint's initial value: with e = rho - rho_ref, u - u_ref, v - v_ref and
+// c = 1 / (n_seg n_t ny), loss = c (e_rho^2 + |e_u|^2) and
+// lam_q = 2 c (e_rho + (e_u . (c_q - u)) / rho).
+template <typename T>
+__device__ __forceinline__ double seed_adjoint(const CtArgs<T>& a, int s, int nt, int x, int y,
+                                               int64_t n, T lam[9]) {
+#pragma unroll
+  for (int q = 0; q < 9; ++q) lam[q] = T(0);
+  if (x < a.W - nt) return 0.0;
+  T drho, u, v;
+  node_state(state_at(a, s, nt), a.plane, n, drho, u, v);
+  const int e = x - (a.W - a.n_max);                      // reference entry of column x
+  const T* R = a.ref + (int64_t(s) * 3 * a.ny + y) * a.n_max + e;
+  const int64_t cstride = int64_t(a.ny) * a.n_max;
+  const T er = drho - R[0], eu = u - R[cstride], ev = v - R[2 * cstride];
+  const double c = a.seg_scale / (double(nt) * double(a.ny));
+  const T c2 = T(2.0 * c), inv = T(1) / (T(1) + drho);
+#pragma unroll
+  for (int q = 0; q < 9; ++q) lam[q] = c2 * (er + (eu * (T(cx(q)) - u) + ev * (T(cy(q)) - v)) * inv);
+  return c * (double(er) * double(er) + double(eu) * double(eu) + double(ev) * double(ev));
+}
+
+// The loss over Omega of every segment (per-workgroup FP64 slots) and the
+// zero adjoint of the time derivatives; the adjoint's initial value is
+// recomputed where the backward pass starts.
 template <typename T>
 __global__ void __launch_bounds__(kNodes) k_seed(const CtArgs<T> a) {
   __shared__ double sh[kNodes / 64];
@@ -357,26 +384,7 @@ __global__ void __launch_bounds__(kNodes) k_seed(const CtArgs<T> a) {
   if (n < a.plane) {
     const int x = int(n / a.ny), y = int(n - int64_t(x) * a.ny);
     T lam[9];
-#pragma unroll
-    for (int q = 0; q < 9; ++q) lam[q] = T(0);
-    if (x >= a.W - nt) {
-      const T* A = state_at(a, s, nt);
-      T drho, u, v;
-      node_state(A, a.plane, n, drho, u, v);
-      const int e = x - (a.W - a.n_max);                  // reference entry of column x
-      const T* R = a.ref + (int64_t(s) * 3 * a.ny + y) * a.n_max + e;
-      const int64_t cstride = int64_t(a.ny) * a.n_max;
-      const T er = drho - R[0], eu = u - R[cstride], ev = v - R[2 * cstride];
-      const double c = a.seg_scale / (double(nt) * double(a.ny));
-      contrib = c * (double(er) * double(er) + double(eu) * double(eu) + double(ev) * double(ev));
-      const T c2 = T(2.0 * c), inv = T(1) / (T(1) + drho);
-#pragma unroll
-      for (int q = 0; q < 9; ++q)
-        lam[q] = c2 * (er + (eu * (T(cx(q)) - u) + ev * (T(cy(q)) - v)) * inv);
-    }
-    T* L = a.lamA + int64_t(s) * 9 * a.plane;
-#pragma unroll
-    for (int q = 0; q < 9; ++q) L[q * a.plane + n] = lam[q];
+    contrib = seed_adjoint(a, s, nt, x, y, n, lam);
     if (n < int64_t(a.ny) * 3) a.lamP[int64_t(s) * a.ny * 3 + n] = T(0);
   }
   const double t = block_sum(contrib, sh);
@@ -433,8 +441,7 @@ __device__ __forceinline__ void node_adjoint(const CtArgs<T>& a, int s, int nt, 
   const int64_t so = int64_t(s) * 9 * a.plane;
   T lam[9];
   if (k + 1 == nt) {
-#pragma unroll
-    for (int q = 0; q < 9; ++q) lam[q] = a.lamA[so + q * a.plane + n];
+    (void)seed_adjoint(a, s, nt, x, y, n, lam);
   } else {
     state_adjoint(a, s, k + 1, x, y, n, a.lamF[(k + 1) & 1] + so, lam);
   }
@@ -822,7 +829,7 @@ __global__ void __launch_bounds__(kNodes) k_update(CtState* st, const double* gp
 size_t align256(size_t b) { return (b + 255) / 256 * 256; }
 
 struct CtLayout {
-  size_t st, traj, outs, dts, lamA, lamF, lamP, madj, ref, nts, seg_omega, seg_k1c, gslot, lslot,
+  size_t st, traj, outs, dts, lamF, lamP, madj, ref, nts, seg_omega, seg_k1c, gslot, lslot,
       gpart, lpart, total;
   int W, nrb, nlb, ngc, nlc;      // gradient / loss chunks of the first-stage sums
   int64_t plane;
@@ -849,7 +856,6 @@ CtLayout ct_layout(const lbm_cbc_train_params& p) {
   L.traj = take(ns * (p.n_max + 1) * 9 * size_t(L.plane) * e);
   L.outs = take(ns * p.n_max * ny * 3 * e);
   L.dts = take(ns * (p.n_max + 1) * ny * 3 * e);
-  L.lamA = take(ns * 9 * size_t(L.plane) * e);
   L.lamF = take(2 * ns * 9 * size_t(L.plane) * e);
   L.lamP = take(ns * ny * 3 * e);
   L.madj = take(2 * ns * ny * kMadj * e);
@@ -913,7 +919,6 @@ struct lbm_cbc_trainer {
     a.traj = reinterpret_cast<T*>(base + L.traj);
     a.outs = reinterpret_cast<T*>(base + L.outs);
     a.dts = reinterpret_cast<T*>(base + L.dts);
-    a.lamA = reinterpret_cast<T*>(base + L.lamA);
     a.lamF[0] = reinterpret_cast<T*>(base + L.lamF);
     a.lamF[1] = a.lamF[0] + size_t(p.n_seg) * 9 * size_t(L.plane);
     a.lamP = reinterpret_cast<T*>(base + L.lamP);
