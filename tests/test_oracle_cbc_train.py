@@ -116,6 +116,38 @@ def test_gradient_matches_finite_differences():
     assert abs(g["b3"][0]) > 0 and abs(g["b3"][1]) > 0
 
 
+def test_segments_with_their_own_relaxation_and_mach():
+    # a segment may carry its own configuration (tau, inflow, Mach number):
+    # the mixed set's loss is the numpy solver's with each segment on a
+    # lattice of its own parameters, and its gradient the mean of the
+    # segments' own gradients
+    net = _net(4)
+    u1 = 0.06
+    cfg1 = dict(CFG, tau=0.72, u_in=u1, mach=u1 / CS)
+    a, b = _state(0), _state(1, 8)
+    ref_a, ref_b = _ref(a, 4), _ref(b, 3)
+    loss, g = cbc_train.loss_and_grad([(a, ref_a), (b, ref_b, cfg1)], net, CFG)
+
+    def np_seg(a0, ref, tau, u_in, mach):
+        lat = Lattice(np.zeros((NY, NX), np.uint8), tau, lateral="periodic", u_in=u_in)
+        lat.set_outflow_cbc(net=net, mach=mach, length=NX)
+        st = a0
+        for _ in range(ref.shape[2]):
+            st, _ = lat.advance_post(st)
+        rho, u, v = d2q9.moments(st[:, :, -ref.shape[2]:])
+        return np.mean((rho - ref[0]) ** 2) + np.mean((u - ref[1]) ** 2 + (v - ref[2]) ** 2)
+    want = 0.5 * (np_seg(a, ref_a, TAU, U0, CFG["mach"]) + np_seg(b, ref_b, 0.72, u1, u1 / CS))
+    assert loss == pytest.approx(want, rel=1e-12)
+    la, ga = cbc_train.loss_and_grad([(a, ref_a)], net, CFG)
+    lb, gb = cbc_train.loss_and_grad([(b, ref_b)], net, cfg1)
+    assert loss == pytest.approx(0.5 * (la + lb), rel=1e-14)
+    for k in cbc_train.PARAMS:
+        np.testing.assert_allclose(g[k], 0.5 * (ga[k] + gb[k]), rtol=1e-12,
+                                   atol=1e-12 * np.max(np.abs(g[k])))
+    # the segment's own parameters matter
+    assert abs(cbc_train.loss_only([(b, ref_b)], net, CFG) - lb) > 1e-3 * lb
+
+
 def test_free_stream_has_zero_loss_and_gradient():
     a0 = d2q9.equilibrium(np.ones((NY, NX)), np.full((NY, NX), U0), np.zeros((NY, NX)))
     ref = np.stack([np.ones((NY, 5)), np.full((NY, 5), U0), np.zeros((NY, 5))])
