@@ -98,6 +98,7 @@ struct StepLaunch {
   int n_nn;             // outlet blocks, neural or characteristic (0: Zou & He)
   int nspecial;         // 1 + kReducers + n_nn rounded up to a multiple of 8
   int nblocks;          // whole grid: nspecial + ntx*nty
+  int xcd_chunk;        // bulk tiles per chunk dealt to the XCDs in turn (0: one band each)
   int nslots;           // partial slots written per step (waves of the
                         // neural and bulk workgroups)
   int xper, yper;

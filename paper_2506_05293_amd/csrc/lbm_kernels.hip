@@ -28,9 +28,11 @@
 namespace lbm {
 
 // Workgroups are dispatched to the eight XCDs round-robin by blockIdx; give
-// each XCD a contiguous range of tiles so that the cache lines two x-adjacent
+// each XCD contiguous runs of tiles so that the cache lines two x-adjacent
 // tiles share (the pull reads one element past each tile edge) meet in the
-// same L2.
+// same L2.  Either one band of n/8 tiles per XCD, or chunks of S tiles dealt
+// to the XCDs in turn (XCD x takes chunks x, x + 8, ...; the tail after the
+// last full round in bands).  Which one is the host's choice (xcd_chunk).
 #ifndef LBM_XCD_REMAP
 #define LBM_XCD_REMAP 1
 #endif
@@ -38,6 +40,12 @@ __device__ __forceinline__ int xcd_remap(int bid, int n) {
   if constexpr (!LBM_XCD_REMAP) return bid;
   const int q = n >> 3, r = n & 7, x = bid & 7;
   return x * q + min(x, r) + (bid >> 3);
+}
+__device__ __forceinline__ int xcd_remap_chunks(int bid, int n, int S) {
+  const int full = n / (8 * S) * (8 * S);
+  if (bid >= full) return full + xcd_remap(bid - full, n - full);
+  const int x = bid & 7, k = bid >> 3;
+  return ((k / S) * 8 + x) * S + k % S;
 }
 
 // Optional occupancy request for the step kernel (waves per SIMD).
@@ -467,7 +475,11 @@ __global__ void __launch_bounds__(kBlock) LBM_STEP_ATTR k_step(const StepLaunch 
   // the eight XCDs in turn; the bulk tiles after them are remapped so that
   // each XCD works on one contiguous range (nspecial is a multiple of 8).
   const int b = int(blockIdx.x);
-  const int v = b < L.nspecial ? b : L.nspecial + xcd_remap(b - L.nspecial, L.nblocks - L.nspecial);
+  const int nb = L.nblocks - L.nspecial;
+  const int v = b < L.nspecial ? b
+                : L.nspecial + (L.xcd_chunk > 0 && LBM_XCD_REMAP
+                                    ? xcd_remap_chunks(b - L.nspecial, nb, L.xcd_chunk)
+                                    : xcd_remap(b - L.nspecial, nb));
   if (v < kFirst) {
     if (v == 0) {
       if (L.reduce2) reduce_level2(L.lvl_r, L);

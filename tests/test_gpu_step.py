@@ -221,6 +221,28 @@ def test_full_size_c2_steps_against_oracle(bulk_path):
     np.testing.assert_allclose(fy, o.fy_hist, rtol=1e-5, atol=1e-7)
 
 
+def test_full_size_steps_with_the_xcd_chunk_mapping(bulk_path):
+    # a 4096 x 896 channel (the C2 cylinder, 896 rows): its per-XCD bands
+    # would be 1.75 MiB of a plane, so the bulk tiles go to the XCDs in
+    # chunks of 32 rows (the tail in bands); three steps against the oracle
+    case = cases.c2(4096, 896)
+    _say("4096x896 full size fp32 mrt, chunked XCD mapping", bulk_path)
+    rho, u = workloads.smooth_fields(case["mask"].shape, case["u_in"], amp=0.02, seed=14)
+    g = _gpu(case, "fp32", history_cap=3)
+    g.init_fields(rho, u[0], u[1])
+    g.step(3)
+    o = Oracle(case["mask"], **cases.oracle_kwargs(case))
+    o.set_equilibrium(rho, u[0], u[1])
+    o.step(3)
+    fl = case["mask"] == 0
+    err = np.max(np.abs(g.populations()[:, fl] - o.post_collision()[:, fl]))
+    print("4096x896 three-step max abs error", err, flush=True)
+    assert err < 5e-8, err
+    fx, fy = g.force_history()
+    np.testing.assert_allclose(fx, o.fx_hist, rtol=1e-5, atol=1e-9)
+    np.testing.assert_allclose(fy, o.fy_hist, rtol=1e-5, atol=1e-7)
+
+
 def test_solid_nodes_survive_read_out(bulk_path):
     # a read-out stages through the spare population buffer; the next step
     # must still find the solid nodes' initial equilibrium there
