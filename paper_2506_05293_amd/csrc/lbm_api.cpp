@@ -153,8 +153,8 @@ Layout make_layout(const lbm_params& p) {
   L.inlet = take(size_t(p.ny) * 8);
   L.part0 = take(size_t(L.nslots_max) * kPartials * 8);   // one slot per wave
   L.part1 = take(size_t(L.nslots_max) * kPartials * 8);
-  L.lvl0 = take(size_t(kReducers) * 4 * 8);
-  L.lvl1 = take(size_t(kReducers) * 4 * 8);
+  L.lvl0 = take(size_t(2 * kReducers) * 4 * 8);   // two steps' sums for two-step launches
+  L.lvl1 = take(size_t(2 * kReducers) * 4 * 8);
   L.acc = take(sizeof(Acc));
   L.hist = take(size_t(std::max<int64_t>(p.history_cap, 0)) * 3 * 8);
   L.mlp = take(sizeof(MlpDev));
@@ -259,6 +259,7 @@ struct lbm_ctx {
     L.nspecial = (1 + kReducers + n_nn + 7) / 8 * 8;
     L.nblocks = L.nspecial + lay.ntx * lay.nty;
     L.xcd_chunk = xcd_chunk_tiles(lay, p.precision);
+    L.pair_nslots = pair_waves(p.nx, p.ny);
     L.nslots = (L.nspecial - 1 - kReducers + lay.ntx * lay.nty) * kWaves;
     L.xper = p.xbc == LBM_X_PERIODIC;
     L.yper = p.lateral == LBM_LATERAL_PERIODIC;
@@ -439,17 +440,37 @@ lbm_status lbm_step(lbm_ctx* c, int64_t nsteps) {
   if (!c->geometry) return fail(LBM_ESTATE, "lbm_step before lbm_set_geometry");
   if (nsteps < 0) return fail(LBM_EINVAL, "nsteps < 0");
   if (nsteps == 0) return LBM_OK;
-  for (int64_t s = 0; s < nsteps; ++s) {
-    const StepLaunch L = c->launch();
-    HIP_TRY(launch_step(L, c->stream));
-    c->pend2 = c->pend1;
-    c->pend1 = true;
-    c->pcur ^= 1;
-    c->cur ^= 1;
+  int64_t s = 0;
+  // LBM_STEP_PAIRS=1, with the Zou & He outflow: pairs of steps in one launch
+  // each (the same node arithmetic; at 4096 x 1024 about 1 % faster than one
+  // launch per step, so one launch per step stays the default)
+  const char* e = getenv("LBM_STEP_PAIRS");
+  if (c->n_nn == 0 && nsteps >= 2 && e && !strcmp(e, "1")) {
+    for (; s + 1 < nsteps; s += 2) {
+      const StepLaunch L = c->launch();
+      HIP_TRY(launch_pair(L, c->stream));
+      c->pend2 = c->pend1;
+      c->pend1 = true;
+      c->pcur ^= 1;
+      c->cur ^= 1;
+    }
+    StepLaunch F = c->launch();
+    HIP_TRY(launch_finalize_pair(F, c->stream));
+    c->pend1 = c->pend2 = false;
   }
-  StepLaunch F = c->launch();
-  HIP_TRY(launch_finalize(F, c->stream));
-  c->pend1 = c->pend2 = false;
+  if (s < nsteps) {
+    for (; s < nsteps; ++s) {
+      const StepLaunch L = c->launch();
+      HIP_TRY(launch_step(L, c->stream));
+      c->pend2 = c->pend1;
+      c->pend1 = true;
+      c->pcur ^= 1;
+      c->cur ^= 1;
+    }
+    StepLaunch F = c->launch();
+    HIP_TRY(launch_finalize(F, c->stream));
+    c->pend1 = c->pend2 = false;
+  }
   c->steps += nsteps;
   return LBM_OK;
 }

@@ -99,6 +99,7 @@ struct StepLaunch {
   int nspecial;         // 1 + kReducers + n_nn rounded up to a multiple of 8
   int nblocks;          // whole grid: nspecial + ntx*nty
   int xcd_chunk;        // bulk tiles per chunk dealt to the XCDs in turn (0: one band each)
+  int pair_nslots;      // two-step launches: waves (slots per step)
   int nslots;           // partial slots written per step (waves of the
                         // neural and bulk workgroups)
   int xper, yper;
@@ -116,6 +117,10 @@ lbm_status set_error(lbm_status code, const char* fmt, ...);
 int64_t build_links(const uint8_t* mask, int nx, int ny, int pitch, int nchunk, bool xper,
                     bool yper, uint32_t* links, uint8_t* chunk);
 hipError_t launch_finalize(const StepLaunch& L, hipStream_t s);
+// Two steps per launch (Zou & He outflow only) and the flush after the last pair.
+int pair_waves(int nx, int ny);
+hipError_t launch_pair(const StepLaunch& L, hipStream_t s);
+hipError_t launch_finalize_pair(const StepLaunch& L, hipStream_t s);
 
 struct InitLaunch {
   int precision;

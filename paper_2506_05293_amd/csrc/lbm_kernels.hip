@@ -560,6 +560,250 @@ hipError_t launch_finalize(const StepLaunch& L, hipStream_t s) {
   return hipGetLastError();
 }
 
+// ---- two steps per launch (Zou & He outflow) --------------------------------------
+// Every wave owns a strip of kPairCols columns and kPairRows rows and takes
+// both steps t+1 and t+2 of it in registers: lane l holds column x0 - 2 + l
+// and walks down rows y0 - 2 .. y0 + kPairRows + 1, keeping the last three
+// rows as read (step t) and the last three rows after the first collision
+// (step t+1); each node pulls from the rows above and below in its window
+// and from the neighbouring columns by lane shuffles, so a pair of steps
+// reads and writes each population once (plus the strip's two-column and
+// two-row halo, recomputed by the neighbouring strips).  Lanes 2..61 write
+// step t+2.  The node code is the single-step one (bounce-back by the link
+// word, Zou & He columns, force and mass of every fluid node, collision), so
+// the populations are those of two single steps.  Per step and wave one
+// partial slot (FP64 whatever the storage); the next launch's reducers take
+// both steps (level 1), the one after commits them in order (level 2), as
+// for single steps.
+constexpr int kPairCols = 60;          // output columns per wave
+constexpr int kPairRows = 24;          // output rows per wave (20, 32 and 48 measured slower)
+
+template <typename T>
+__device__ __forceinline__ void pair_pull(const T lo[9], const T mid[9], const T hi[9], int lane,
+                                          T g[9]) {
+#pragma unroll
+  for (int q = 0; q < 9; ++q) {
+    const T v = cy(q) == 1 ? lo[q] : (cy(q) == -1 ? hi[q] : mid[q]);
+    g[q] = cx(q) == 0 ? v : __shfl(v, (lane - cx(q)) & 63);
+  }
+}
+
+// One node update from its pulled populations g and its own row values
+// `own` (the bounce-back sources); returns false for a solid node.
+template <typename T, int MRT>
+__device__ __forceinline__ bool pair_node(const StepLaunch& L, uint32_t lk, int y, const T own[9],
+                                          T g[9], bool count, T& fx, T& fy, T& dm) {
+  if (lk & LINK_SOLID) return false;
+  // bounce-back as selects: a branch per direction here made the compiler
+  // keep g in scratch memory (77 instead of 53 us per step at 4096 x 1024)
+#pragma unroll
+  for (int q = 1; q < 9; ++q) g[q] = ((lk >> q) & 1u) ? own[opp(q)] : g[q];
+  if (lk & LINK_INLET)
+    zouhe_inlet(g, L.inlet ? T(L.inlet[y]) : T(L.u_in));
+  else if (lk & LINK_OUTLET)
+    zouhe_outlet(g, T(L.one_minus_rho_out));
+  if (count) {
+    add_force(lk, g, fx, fy);
+    dm += macro(g).drho;
+  }
+  collide<T, MRT>(g, L);
+  return true;
+}
+
+template <typename S, int MRT>
+__device__ __forceinline__ void pair_strip(const StepLaunch& L, int wave, double* part) {
+  using T = typename Store<S>::T;
+  const int lane = threadIdx.x & 63;
+  const int nstrip = (L.nx + kPairCols - 1) / kPairCols;
+  const int strip = wave % nstrip, seg = wave / nstrip;
+  const int x0 = strip * kPairCols, y0 = seg * kPairRows;
+  const int xl = x0 - 2 + lane;                       // this lane's column
+  int xs = xl;                                        // ... where it is read
+  if (L.xper) xs = xs < 0 ? xs + L.nx : (xs >= L.nx ? xs - L.nx : xs);
+  else xs = xs < 0 ? 0 : (xs >= L.nx ? L.nx - 1 : xs);
+  // a lattice node (periodic x: every lane, wrapped); the output columns are
+  // the strip's own, unwrapped
+  const bool col_in = L.xper || (xl >= 0 && xl < L.nx);
+  const bool out_col = lane >= 2 && lane < 2 + kPairCols && xl < L.nx;
+  const int ye = min(y0 + kPairRows, L.ny);           // end of the output rows
+  const S* __restrict__ A = static_cast<const S*>(L.A);
+  S* __restrict__ B = static_cast<S*>(L.B);
+  T R0[9], R1[9], R2[9], S0[9], S1[9], S2[9], P[9];
+  uint32_t K0 = 0, K1 = 0, K2 = 0, KP = 0;
+  // force and mass in FP64 from the node on: a wave covers ~2000 nodes, and
+  // the drag is a sum with heavy cancellation
+  double fxa = 0.0, fya = 0.0, dma = 0.0, fxb = 0.0, fyb = 0.0, dmb = 0.0;
+  const int nrow = ye - y0 + 4;
+  // row yr into P, KP, issued one iteration ahead of its use so that the
+  // loads overlap the collisions
+  auto fetch = [&](int yr) {
+    int ys = yr;
+    if (L.yper) ys = ys < 0 ? ys + L.ny : (ys >= L.ny ? ys - L.ny : ys);
+    else ys = ys < 0 ? 0 : (ys >= L.ny ? L.ny - 1 : ys);
+    const int64_t off = int64_t(ys) * L.pitch + xs;
+#pragma unroll
+    for (int q = 0; q < 9; ++q) P[q] = Store<S>::ld_nt(A + int64_t(q) * L.plane + off);
+    KP = 0;
+    const bool row_in = L.yper || (yr >= 0 && yr < L.ny);
+    if (row_in && col_in && L.chunk[ys * L.nchunk + xs / kChunk]) KP = L.links[off];
+  };
+  fetch(y0 - 2);
+  for (int j = 0; j < nrow; ++j) {
+    const int yr = y0 - 2 + j;                        // row taken at this iteration
+#pragma unroll
+    for (int q = 0; q < 9; ++q) R2[q] = P[q];
+    K2 = KP;
+    if (j + 1 < nrow) fetch(yr + 1);
+    if (j >= 2) {
+      // step t+1 at row yr - 1
+      const int y1 = yr - 1;
+      const bool in1 = L.yper || (y1 >= 0 && y1 < L.ny);
+      T g[9];
+      pair_pull(R0, R1, R2, lane, g);
+      const bool cnt1 = out_col && y1 >= y0 && y1 < ye;
+      T fx1 = T(0), fy1 = T(0), dm1 = T(0);
+      if (!(in1 && col_in && pair_node<T, MRT>(L, K1, y1 < 0 ? y1 + L.ny : (y1 >= L.ny ? y1 - L.ny : y1),
+                                                  R1, g, cnt1, fx1, fy1, dm1))) {
+#pragma unroll
+        for (int q = 0; q < 9; ++q) g[q] = R1[q];    // solid or outside: unchanged
+      }
+      fxa += double(fx1);
+      fya += double(fy1);
+      dma += double(dm1);
+#pragma unroll
+      for (int q = 0; q < 9; ++q) S2[q] = g[q];
+      if (j >= 4) {
+        // step t+2 at row yr - 2
+        const int y2 = yr - 2;
+        pair_pull(S0, S1, S2, lane, g);
+        const bool cnt2 = out_col && y2 >= y0 && y2 < ye;
+        T fx2 = T(0), fy2 = T(0), dm2 = T(0);
+        if (cnt2 && pair_node<T, MRT>(L, K0, y2, S1, g, true, fx2, fy2, dm2)) {
+          const int64_t o2 = int64_t(y2) * L.pitch + xs;
+#pragma unroll
+          for (int q = 0; q < 9; ++q) Store<S>::st(B + int64_t(q) * L.plane + o2, g[q]);
+        }
+        fxb += double(fx2);
+        fyb += double(fy2);
+        dmb += double(dm2);
+      }
+#pragma unroll
+      for (int q = 0; q < 9; ++q) {
+        S0[q] = S1[q];
+        S1[q] = S2[q];
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < 9; ++q) {
+      R0[q] = R1[q];
+      R1[q] = R2[q];
+    }
+    K0 = K1;
+    K1 = K2;
+  }
+  // one slot per wave and step: [0, n) the first step, [n, 2n) the second
+  const int n = L.pair_nslots;
+  fxa = wave_sum(fxa); fya = wave_sum(fya); dma = wave_sum(dma);
+  fxb = wave_sum(fxb); fyb = wave_sum(fyb); dmb = wave_sum(dmb);
+  if (lane == 0) {
+    double* a = part + int64_t(kPartials) * wave;
+    double* b = part + int64_t(kPartials) * (n + wave);
+    a[0] = fxa; a[1] = fya; a[2] = dma; a[3] = 0.0;
+    b[0] = fxb; b[1] = fyb; b[2] = dmb; b[3] = 0.0;
+  }
+}
+
+// Level 2 of a pair: both steps' kReducers sums, committed in step order.
+__device__ void pair_level2(const double* __restrict__ lvl, const StepLaunch& L) {
+  for (int h = 0; h < 2; ++h) {
+    double s[4] = {0.0, 0.0, 0.0, 0.0}, t[4];
+    if (threadIdx.x < kReducers) {
+#pragma unroll
+      for (int k = 0; k < 4; ++k) s[k] = lvl[(h * kReducers + threadIdx.x) * 4 + k];
+    }
+    block_sum4(s, t);
+    if (threadIdx.x == 0) commit_step(t, L);
+    __syncthreads();
+  }
+}
+
+// Level 1 of a pair: reducer r (of 2 kReducers) sums its slice of one step's slots.
+template <typename T>
+__device__ void pair_level1(const T* __restrict__ part, int r, const StepLaunch& L) {
+  const int h = r / kReducers, rr = r - h * kReducers, n = L.pair_nslots;
+  const int per = (n + kReducers - 1) / kReducers;
+  const int b0 = min(rr * per, n), b1 = min(b0 + per, n);
+  double t[4];
+  sum_slots(part + int64_t(kPartials) * h * n, b0, b1, t);
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) L.lvl_w[(h * kReducers + rr) * 4 + k] = t[k];
+  }
+}
+
+constexpr int kPairSpecial = (1 + 2 * kReducers + 7) / 8 * 8;
+
+template <typename S, int MRT>
+__global__ void __launch_bounds__(kBlock) k_step2(const StepLaunch L) {
+  const int v = int(blockIdx.x);
+  if (v < kPairSpecial) {
+    if (v == 0) {
+      if (L.reduce2) pair_level2(L.lvl_r, L);
+    } else if (v <= 2 * kReducers && L.reduce1) {
+      pair_level1(static_cast<const double*>(L.part_r), v - 1, L);
+    }
+    return;
+  }
+  const int wave = (v - kPairSpecial) * kWaves + int(threadIdx.x >> 6);
+  if (wave >= L.pair_nslots) return;                  // whole wave
+  pair_strip<S, MRT>(L, wave, static_cast<double*>(L.part_w));
+}
+
+// Flush after the last pair: level 2 of the pair before, then both steps of
+// the last pair's slots in one workgroup.
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_finalize2(const StepLaunch L) {
+  if (L.reduce2) pair_level2(L.lvl_r, L);
+  __syncthreads();
+  if (L.reduce1) {
+    for (int h = 0; h < 2; ++h) {
+      double t[4];
+      sum_slots(static_cast<const T*>(L.part_r) + int64_t(kPartials) * h * L.pair_nslots, 0,
+                L.pair_nslots, t);
+      if (threadIdx.x == 0) commit_step(t, L);
+      __syncthreads();
+    }
+  }
+}
+
+template <typename S, int MRT>
+static hipError_t launch_pair_t(const StepLaunch& L, hipStream_t s) {
+  const int blocks = kPairSpecial + (L.pair_nslots + kWaves - 1) / kWaves;
+  hipLaunchKernelGGL((k_step2<S, MRT>), dim3(blocks), dim3(kBlock), 0, s, L);
+  return hipGetLastError();
+}
+
+int pair_waves(int nx, int ny) {
+  return ((nx + kPairCols - 1) / kPairCols) * ((ny + kPairRows - 1) / kPairRows);
+}
+
+hipError_t launch_pair(const StepLaunch& L, hipStream_t s) {
+  switch (L.precision * 2 + L.collision) {
+    case LBM_FP64 * 2 + LBM_BGK: return launch_pair_t<double, 0>(L, s);
+    case LBM_FP64 * 2 + LBM_MRT: return launch_pair_t<double, 1>(L, s);
+    case LBM_FP32_OFFSET * 2 + LBM_BGK: return launch_pair_t<float, 0>(L, s);
+    case LBM_FP32_OFFSET * 2 + LBM_MRT: return launch_pair_t<float, 1>(L, s);
+    case LBM_FP16_OFFSET * 2 + LBM_BGK: return launch_pair_t<__half, 0>(L, s);
+    case LBM_FP16_OFFSET * 2 + LBM_MRT: return launch_pair_t<__half, 1>(L, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_finalize_pair(const StepLaunch& L, hipStream_t s) {
+  hipLaunchKernelGGL((k_finalize2<double>), dim3(1), dim3(kBlock), 0, s, L);   // FP64 slots
+  return hipGetLastError();
+}
+
 // ---- initialisation (Eq. 3 at rest density, noisy inlet velocity) -------------------
 template <typename S>
 __global__ void __launch_bounds__(kBlock) k_init(const InitLaunch L) {
