@@ -36,6 +36,8 @@ HBM_PEAK_GBS = 8000.0
 CSRC = os.path.join(ROOT, "paper_2506_05293_amd", "csrc")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "step_kernel_4096x1024_traffic.txt")
 RESULTS = os.path.join(ROOT, "results")
+# the Zou & He step runs two lattice steps per launch of this kernel
+STEP_KERNEL, STEPS_PER_LAUNCH = "k_step2<", 2
 CALIB_BYTES = 151 * 1024 * 1024     # bytes read (and written) by the calibration copy
 
 
@@ -77,9 +79,10 @@ def write_traffic(step_fetch, step_write, copy_fetch, copy_write, command_note):
     kib = CALIB_BYTES / 1024.0
     f_scale = kib / _median_counter(copy_fetch, "copyBuffer")
     w_scale = kib / _median_counter(copy_write, "copyBuffer")
-    fetch = _median_counter(step_fetch, "k_step") * f_scale * 1024
-    write = _median_counter(step_write, "k_step") * w_scale * 1024
+    fetch = _median_counter(step_fetch, STEP_KERNEL) * f_scale * 1024
+    write = _median_counter(step_write, STEP_KERNEL) * w_scale * 1024
     lines = [f"source_hash={kernel_source_hash()}",
+             f"kernel={STEP_KERNEL}", f"steps_per_launch={STEPS_PER_LAUNCH}",
              f"fetch_bytes_per_launch={fetch:.0f}",
              f"write_bytes_per_launch={write:.0f}",
              f"fetch_scale={f_scale:.4f}", f"write_scale={w_scale:.4f}",
@@ -90,14 +93,16 @@ def write_traffic(step_fetch, step_write, copy_fetch, copy_write, command_note):
 
 
 def stored_traffic():
-    """HBM bytes per launch from the counter summary, or None when the kernel
+    """HBM bytes per lattice step from the counter summary (a launch of the
+    step kernel advances STEPS_PER_LAUNCH steps), or None when the kernel
     sources changed since the counters were taken."""
     if not os.path.exists(TRAFFIC_FILE):
         return None
     kv = dict(l.strip().split("=", 1) for l in open(TRAFFIC_FILE) if "=" in l)
-    if kv.get("source_hash") != kernel_source_hash():
+    if kv.get("source_hash") != kernel_source_hash() or kv.get("kernel") != STEP_KERNEL:
         return None
-    return float(kv["fetch_bytes_per_launch"]) + float(kv["write_bytes_per_launch"])
+    per_launch = float(kv["fetch_bytes_per_launch"]) + float(kv["write_bytes_per_launch"])
+    return per_launch / int(kv["steps_per_launch"])
 
 
 def c2_case(nx, ny):
@@ -517,7 +522,8 @@ def main():
                      "frac": gbs / HBM_PEAK_GBS,
                      "traffic": (None if traffic is None or (nx, ny, args.precision) != (4096, 1024, "fp32")
                                  else traffic / (ms * 1e-3) / 1e9),
-                     "bytes_per_node": bpn, "kernel": "k_step (fused pull stream-collide)"},
+                     "bytes_per_node": bpn,
+                     "kernel": "k_step2 (two fused pull stream-collide steps per launch)"},
         "hbm_fraction": gbs / HBM_PEAK_GBS,
         "nn_outflow": nn,
         "cbc_outflow": cbc,

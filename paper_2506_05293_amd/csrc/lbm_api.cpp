@@ -441,11 +441,12 @@ lbm_status lbm_step(lbm_ctx* c, int64_t nsteps) {
   if (nsteps < 0) return fail(LBM_EINVAL, "nsteps < 0");
   if (nsteps == 0) return LBM_OK;
   int64_t s = 0;
-  // LBM_STEP_PAIRS=1, with the Zou & He outflow: pairs of steps in one launch
-  // each (the same node arithmetic; at 4096 x 1024 about 1 % faster than one
-  // launch per step, so one launch per step stays the default)
+  // With the Zou & He outflow, pairs of steps run in one launch each (the
+  // same node arithmetic; at 4096 x 1024 about 4 % faster than one launch per
+  // step); LBM_STEP_PAIRS=0 keeps one launch per step.  The neural and the
+  // characteristic outlets always take one launch per step.
   const char* e = getenv("LBM_STEP_PAIRS");
-  if (c->n_nn == 0 && nsteps >= 2 && e && !strcmp(e, "1")) {
+  if (c->n_nn == 0 && nsteps >= 2 && !(e && !strcmp(e, "0"))) {
     for (; s + 1 < nsteps; s += 2) {
       const StepLaunch L = c->launch();
       HIP_TRY(launch_pair(L, c->stream));

@@ -578,13 +578,34 @@ hipError_t launch_finalize(const StepLaunch& L, hipStream_t s) {
 constexpr int kPairCols = 60;          // output columns per wave
 constexpr int kPairRows = 24;          // output rows per wave (20, 32 and 48 measured slower)
 
+// The value of the lane to the left (lane - 1) or right (lane + 1) by a
+// whole-wave DPP shift (a VALU move; lanes 0 and 63 get no neighbour and are
+// halo lanes here).
+template <int DIR>
+__device__ __forceinline__ int lane_shift(int v) {
+  return __builtin_amdgcn_update_dpp(0, v, DIR > 0 ? 0x138 : 0x130, 0xF, 0xF, false);   // wave_shr:1 / wave_shl:1
+}
+template <int DIR>
+__device__ __forceinline__ float lane_shift(float v) {
+  return __builtin_bit_cast(float, lane_shift<DIR>(__builtin_bit_cast(int, v)));
+}
+template <int DIR>
+__device__ __forceinline__ double lane_shift(double v) {
+  const long long b = __builtin_bit_cast(long long, v);
+  const int lo = lane_shift<DIR>(int(b & 0xFFFFFFFFll)), hi = lane_shift<DIR>(int(b >> 32));
+  return __builtin_bit_cast(double, (static_cast<long long>(hi) << 32) |
+                                        static_cast<long long>(static_cast<unsigned>(lo)));
+}
+
 template <typename T>
 __device__ __forceinline__ void pair_pull(const T lo[9], const T mid[9], const T hi[9], int lane,
                                           T g[9]) {
+  (void)lane;
 #pragma unroll
   for (int q = 0; q < 9; ++q) {
     const T v = cy(q) == 1 ? lo[q] : (cy(q) == -1 ? hi[q] : mid[q]);
-    g[q] = cx(q) == 0 ? v : __shfl(v, (lane - cx(q)) & 63);
+    // population q comes from column x - c_x: the left lane for c_x = +1
+    g[q] = cx(q) == 0 ? v : (cx(q) == 1 ? lane_shift<1>(v) : lane_shift<-1>(v));
   }
 }
 

@@ -37,6 +37,9 @@ LAUNCHES = ["persistent", "per_step"]
 @pytest.mark.parametrize("collision,lateral", [("mrt", "periodic"), ("bgk", "walls")])
 def test_batch_equals_single_lattices(collision, lateral, launch, monkeypatch):
     monkeypatch.setenv("LBM_BULK_PATH", "vector")
+    # the batch kernel runs the single-step node code: single lattices
+    # with one launch per step are its bitwise reference
+    monkeypatch.setenv("LBM_STEP_PAIRS", "0")
     lats = _lattices()
     _say("batch vs single", collision, lateral, launch)
     b = lbm.Batch(lats, collision=collision, lateral=lateral, noise_amp=1e-3, history_cap=200,
@@ -118,6 +121,9 @@ def test_logging_matches_pull_of_read_state(launch):
 @pytest.mark.parametrize("launch", LAUNCHES)
 def test_unstable_lattice_is_retired_alone(launch, monkeypatch):
     monkeypatch.setenv("LBM_BULK_PATH", "vector")
+    # the batch kernel runs the single-step node code: single lattices
+    # with one launch per step are its bitwise reference
+    monkeypatch.setenv("LBM_STEP_PAIRS", "0")
     lats = _lattices()[:2]
     bad = dict(mask=geometry.cylinder(200, 60, 40, 30, 20.0), tau=0.5005, u_in=0.3, seed=1)
     _say("batch retirement", launch)

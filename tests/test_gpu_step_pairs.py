@@ -1,5 +1,6 @@
-"""GPU parity of the opt-in two-steps-per-launch path of the step
-(LBM_STEP_PAIRS=1, Zou & He outflow): every node takes the single-step node
+"""GPU parity of the two-steps-per-launch path of the step (the default
+with the Zou & He outflow; LBM_STEP_PAIRS=0 gives one launch per step):
+every node takes the single-step node
 code in registers, compiled into another kernel (the compiler may contract
 multiply-adds differently there), so the populations agree with one launch
 per step to rounding: 1e-12 relative in FP64, 1e-6 absolute in FP32 and
