@@ -464,8 +464,15 @@ def main():
     nodes = nx * ny
     traffic = stored_traffic()
     mlups = nodes / (ms * 1e-3) / 1e6
-    bpn = BYTES_PER_NODE[args.precision]
+    # algorithmic HBM bytes per node and lattice step: a launch reads and
+    # writes the populations once, so the two-steps-per-launch kernel moves
+    # half of the single-step kernel's bytes per step
+    pairs = os.environ.get("LBM_STEP_PAIRS") != "0"
+    spl = STEPS_PER_LAUNCH if pairs else 1
+    bpn = BYTES_PER_NODE[args.precision] / spl
     gbs = bpn * nodes / (ms * 1e-3) / 1e9
+    if not pairs:
+        traffic = None
 
     nn = None
     if not args.no_nn:
@@ -522,8 +529,11 @@ def main():
                      "frac": gbs / HBM_PEAK_GBS,
                      "traffic": (None if traffic is None or (nx, ny, args.precision) != (4096, 1024, "fp32")
                                  else traffic / (ms * 1e-3) / 1e9),
-                     "bytes_per_node": bpn,
-                     "kernel": "k_step2 (two fused pull stream-collide steps per launch)"},
+                     "bytes_per_node_step": bpn, "steps_per_launch": spl,
+                     "single_step_equivalent_GBps": BYTES_PER_NODE[args.precision] * nodes
+                                                    / (ms * 1e-3) / 1e9,
+                     "kernel": ("k_step2 (two fused pull stream-collide steps per launch)" if pairs
+                                else "k_step (fused pull stream-collide)")},
         "hbm_fraction": gbs / HBM_PEAK_GBS,
         "nn_outflow": nn,
         "cbc_outflow": cbc,
