@@ -174,7 +174,11 @@ lbm_status lbm_set_inlet_profile(lbm_ctx* c, const double* host_ux);
 /* Advance nsteps time steps (asynchronous).  One step: pull streaming of
  * the post-collision populations with half-way bounce-back on walls and
  * solids, the inlet and outlet columns, collision, and the force and mass
- * of the step.  ESTATE before lbm_set_geometry. */
+ * of the step (Sec. 2, Eqs. 1-4, 5-11, 12, 14-15).  With the Zou & He outflow
+ * two steps run in each launch (the same node arithmetic, so the
+ * populations agree with one launch per step to rounding; an odd count
+ * ends with one single step); the environment variable LBM_STEP_PAIRS=0
+ * selects one launch per step.  ESTATE before lbm_set_geometry. */
 lbm_status lbm_step(lbm_ctx* c, int64_t nsteps);
 
 /* Synchronise the stream and read the accumulators.  Returns EUNSTABLE
