@@ -147,7 +147,21 @@ class Lattice:
             dP += f_in * C[i] - f_out * C[OPP[i]]
         return dP          # / Delta t = 1
 
-    def _outlet_nn(self, fnew):
+    def nn_outlet(self, fnew):
+        """Eq. 16 at the outlet column with the Zou & He fallback, from the
+        pre-collision populations ``fnew`` of the next step (the outlet
+        unknowns may be NaN).  Returns a dict: ``nn`` and ``zh`` the outlet
+        column (9, ny) reconstructed both ways, ``ok`` the per-row decision
+        (True: the reconstruction is kept), ``jump`` the FP32 density jump
+        |rho_g - rho(L-1)| the decision compared with the bound, ``positive``
+        the FP32 positivity test.
+
+        The decision is a floating-point test that selects between two
+        results, so it is taken in the kernel's precision: positivity of the
+        reconstructed absolute populations rounded to FP32, and the density
+        jump as the difference of the two densities' offsets rho - 1 (summed
+        in FP64 from f - w, each rounded to FP32), subtracted and compared in
+        FP32."""
         L = self.nx - 1
         feats = np.concatenate([(fnew[:, :, L - 1 - j] - W[:, None]).T
                                 for j in range(3)], axis=1)      # (ny, 27)
@@ -157,15 +171,37 @@ class Lattice:
         for k, q in enumerate((3, 6, 7)):
             g[q] = fnew[q, :, L - 1] + s[:, k]
         zh, _ = outlet_pressure(fnew[:, :, L], self.rho_out)
-        # Fallback test, in FP32 like the fused kernel: positivity of the
-        # reconstructed populations and the density jump to column L-1.
         g32 = g.astype(np.float32)
-        rho_g = g.sum(0).astype(np.float32)
-        rho_prev = fnew[:, :, L - 1].sum(0).astype(np.float32)
-        ok = np.all(g32[[3, 6, 7]] > 0, axis=0) & \
-            (np.abs(rho_g - rho_prev) < np.float32(self.mass_bound))
-        self.n_fallback += int((~ok).sum())
-        return np.where(ok[None], g, zh)
+        positive = np.all(g32[[3, 6, 7]] > 0, axis=0)
+        drho_g = (g - W[:, None]).sum(0).astype(np.float32)
+        drho_prev = (fnew[:, :, L - 1] - W[:, None]).sum(0).astype(np.float32)
+        jump = np.abs(drho_g - drho_prev)                         # FP32
+        ok = positive & (jump < np.float32(self.mass_bound))
+        return {"nn": g, "zh": zh, "ok": ok, "jump": jump, "positive": positive}
+
+    def _outlet_nn(self, fnew):
+        r = self.nn_outlet(fnew)
+        self.n_fallback += int((~r["ok"]).sum())
+        return np.where(r["ok"][None], r["nn"], r["zh"])
+
+    def nn_outlet_candidates(self, fstar):
+        """For a post-collision state fstar(t): the post-collision outlet
+        column of step t+1 with the reconstruction kept at every row
+        (``post_nn``) and with the Zou & He fallback at every row
+        (``post_zh``), and the per-row decision the step takes (``ok``,
+        ``jump``, ``positive`` as in nn_outlet).  Does not touch the state."""
+        fnew = self.stream(np.asarray(fstar, dtype=np.float64))
+        if self.xbc == "inout":
+            ux = self.u_in if self.inlet_profile is None else self.inlet_profile
+            fnew[:, :, 0], _ = inlet_velocity(fnew[:, :, 0], ux, 0.0)
+        r = self.nn_outlet(fnew)
+        out = {k: r[k] for k in ("ok", "jump", "positive")}
+        for name in ("nn", "zh"):
+            f = fnew.copy()
+            f[:, :, -1] = r[name]
+            f = np.where(self.fluid[None], f, fstar)
+            out["post_" + name] = self.collide(f)[:, :, -1]
+        return out
 
     def _advance(self, fstar):
         """Streaming, force and boundary columns from the post-collision

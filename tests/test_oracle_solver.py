@@ -254,6 +254,26 @@ def test_nn_outflow_positivity_fallback():
     assert lat.n_fallback == 5 * ny
 
 
+@pytest.mark.parametrize("bound,keep", [(1.06e-4, True), (1.04e-4, False)])
+def test_nn_outflow_density_jump_of_a_constant_correction(bound, keep):
+    # Uniform flow f^eq(1, u) with periodic laterals and no body: the known
+    # populations pulled into the outlet column equal those at L-1, so the
+    # reconstruction g_i = f_i(L-1) + s_i (Eq. 16) moves the density by
+    # exactly s_3 + s_6 + s_7 (R17: the node falls back once that jump
+    # reaches the bound).  A zero network with mu_out = s gives constant s.
+    nx, ny = 24, 8
+    lat = Lattice(np.zeros((ny, nx), np.uint8), 0.6, lateral="periodic", u_in=0.05)
+    P = _zero_mlp()
+    P["mu_out"] = np.array([1e-4, -2.5e-5, 3e-5])
+    lat.set_outflow_nn(P, mass_bound=bound)
+    r = lat.nn_outlet(lat.stream(lat.collide()))
+    np.testing.assert_allclose(r["jump"], 1.05e-4, rtol=1e-6)
+    assert np.all(r["positive"]) and np.all(r["ok"] == keep)
+    np.testing.assert_allclose(r["nn"][3], lat.f[3, :, -2] + 1e-4, rtol=0, atol=1e-16)
+    lat.step(1)
+    assert lat.n_fallback == (0 if keep else ny)
+
+
 @pytest.mark.parametrize("k", [0, 4, 8, 9, 13, 20, 26])
 def test_nn_outflow_feature_stencil_order(k):
     # A network that passes one input feature through both tanh layers to
