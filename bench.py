@@ -105,6 +105,27 @@ def stored_traffic():
     return per_launch / int(kv["steps_per_launch"])
 
 
+def step_roofline(nodes, ms_per_step, spl, precision, traffic_per_step):
+    """The roofline object of the step: algorithmic bytes per launch (72 B
+    per node and step at FP32 times the node-steps of one launch) over the
+    launch's mean duration; the counter traffic (bytes per step) beside it."""
+    bpn = BYTES_PER_NODE[precision]
+    launch_ms = ms_per_step * spl
+    gbs = bpn * nodes * spl / (launch_ms * 1e-3) / 1e9
+    tr = None if traffic_per_step is None else traffic_per_step / (ms_per_step * 1e-3) / 1e9
+    return {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": gbs / HBM_PEAK_GBS, "traffic": tr,
+            "traffic_frac": None if tr is None else tr / HBM_PEAK_GBS,
+            "bytes_per_node_step": bpn, "steps_per_launch": spl,
+            "algorithmic_bytes_per_launch": bpn * nodes * spl, "launch_ms": launch_ms,
+            # a launch of two steps needs to move the populations only once:
+            # its own minimum is bpn / spl per node-step
+            "launch_minimum_bytes_per_node_step": bpn / spl,
+            "launch_minimum_frac": gbs / spl / HBM_PEAK_GBS,
+            "kernel": ("k_step2 (two fused pull stream-collide steps per launch)" if spl == 2
+                       else "k_step (fused pull stream-collide)")}
+
+
 def c2_case(nx, ny):
     from paper_2506_05293_amd import geometry
     D = 80.0 * nx / 4096
@@ -261,9 +282,20 @@ def time_batch(torch, steps=1000, warmup=200, n_pairs=64, launch="per_step"):
                        f"launch {launch}"}
 
 
-def cpu_baseline(nx, ny, seconds=15.0):
-    """The FP64 oracle (single thread) on the same lattice for as many whole
-    steps as fit in ~`seconds` (at least one)."""
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _oracle_worker(args):
+    """One process: the FP64 oracle on its own copy of the lattice for
+    ~`seconds` (single thread); returns (node updates, seconds)."""
+    nx, ny, seconds = args
     from threadpoolctl import threadpool_limits
     from oracle.solver import Lattice as Oracle
     mask, tau = c2_case(nx, ny)
@@ -274,9 +306,31 @@ def cpu_baseline(nx, ny, seconds=15.0):
         while n == 0 or time.perf_counter() - t0 < seconds:
             o.step(1)
             n += 1
-        dt = time.perf_counter() - t0
-    return {"value": nx * ny * n / dt / 1e6, "unit": "MLUPS", "cores": 1, "kind": "oracle",
-            "sample": f"{n} steps of the same {nx}x{ny} MRT lattice, FP64 NumPy, 1 thread"}
+        return nx * ny * n, time.perf_counter() - t0
+
+
+def cpu_baseline(nx, ny, seconds=15.0, all_cores=True):
+    """The FP64 oracle (single thread) on the same lattice for as many whole
+    steps as fit in ~`seconds` (at least one); then, optionally, one oracle
+    process per core of this process's CPU set (at most 16), each on its own
+    copy of a quarter-height lattice, for the aggregate figure."""
+    nodes, dt = _oracle_worker((nx, ny, seconds))
+    out = {"value": nodes / dt / 1e6, "unit": "MLUPS", "cores": 1, "kind": "oracle",
+           "cpu": cpu_model(),
+           "sample": f"{nodes // (nx * ny)} steps of the same {nx}x{ny} MRT lattice, FP64 NumPy, "
+                     "1 thread"}
+    if all_cores:
+        import multiprocessing as mp
+        procs = max(1, min(16, len(os.sched_getaffinity(0))))
+        sub = max(64, ny // 4)
+        ctx = mp.get_context("spawn")
+        with ctx.Pool(procs) as pool:
+            res = pool.map(_oracle_worker, [(nx, sub, 10.0)] * procs)
+        out["all_cores"] = {"value": sum(n / t for n, t in res) / 1e6, "unit": "MLUPS",
+                            "cores": procs,
+                            "sample": f"{procs} processes, each the oracle on its own {nx}x{sub} "
+                                      "copy of the lattice for ~10 s, 1 thread each"}
+    return out
 
 
 def _jsonable(o):
@@ -423,7 +477,15 @@ def main():
     ap.add_argument("--no-cbc", action="store_true")
     ap.add_argument("--no-accuracy", action="store_true",
                     help="skip the FP32-vs-FP64 precision study (C_D, C_L, St)")
-    ap.add_argument("--accuracy-steps", type=int, default=50_000)
+    ap.add_argument("--accuracy-steps", type=int, default=300_000,
+                    help="steps of the FP32-vs-FP64 runs (the statistics window, the last "
+                         "40 %%, must cover saturated shedding)")
+    ap.add_argument("--launch", default="pairs", choices=["pairs", "single"],
+                    help="kernel schedule of the timed lattice (lbm_params.launch)")
+    ap.add_argument("--no-big", action="store_true",
+                    help="skip the 16384x4096 lattice (4.8 GB working set)")
+    ap.add_argument("--big-steps", type=int, default=400)
+    ap.add_argument("--no-cpu-all-cores", action="store_true")
     ap.add_argument("--study", choices=["train", "nn", "naca", "vortex", "cbc_train",
                                         "cbc_train_mach", "scaling", "all"],
                     default=None,
@@ -456,41 +518,43 @@ def main():
     from paper_2506_05293_amd import lbm
     nx, ny = args.nx, args.ny
     mask, tau = c2_case(nx, ny)
-    lat = lbm.Lattice(mask, tau, precision=args.precision, collision="mrt", lateral="walls",
-                      u_in=0.05, noise_amp=1e-4, seed=2, s_e=1.0, s_eps=1.0, s_q=1.0)
+    kw = dict(precision=args.precision, collision="mrt", lateral="walls", u_in=0.05,
+              noise_amp=1e-4, seed=2, s_e=1.0, s_eps=1.0, s_q=1.0)
+    lat = lbm.Lattice(mask, tau, launch=args.launch, **kw)
     ms = time_steps(lat, args.steps, args.warmup, torch)
     out = lat.forces()
     assert out.nonfinite == 0
     nodes = nx * ny
-    traffic = stored_traffic()
     mlups = nodes / (ms * 1e-3) / 1e6
-    # algorithmic HBM bytes per node and lattice step: a launch reads and
-    # writes the populations once, so the two-steps-per-launch kernel moves
-    # half of the single-step kernel's bytes per step
-    pairs = os.environ.get("LBM_STEP_PAIRS") != "0"
-    spl = STEPS_PER_LAUNCH if pairs else 1
-    bpn = BYTES_PER_NODE[args.precision] / spl
-    gbs = bpn * nodes / (ms * 1e-3) / 1e9
-    if not pairs:
-        traffic = None
+    spl = STEPS_PER_LAUNCH if args.launch == "pairs" else 1
+    roofline = step_roofline(nodes, ms, spl, args.precision,
+                             stored_traffic() if (nx, ny, args.precision, spl) ==
+                             (4096, 1024, "fp32", STEPS_PER_LAUNCH) else None)
 
     nn = None
     if not args.no_nn:
         lat.set_outflow_nn(random_mlp(), mass_bound=1e-2)
         ms_nn = time_steps(lat, args.steps, args.warmup, torch)
         out_nn = lat.forces()
+        del lat
+        single = lbm.Lattice(mask, tau, launch="single", **kw)
+        ms_single = time_steps(single, args.steps, args.warmup, torch)
+        del single
         nn = {"mlups": nodes / (ms_nn * 1e-3) / 1e6, "ms_per_step": ms_nn,
-              "ratio_to_zouhe": ms / ms_nn, "weights": "random-init 27-64-64-3",
-              "fallback_nodes": int(out_nn.n_fallback)}
-    del lat
+              "ratio_to_zouhe": ms / ms_nn, "ratio_to_zouhe_single": ms_single / ms_nn,
+              "zouhe_single_mlups": nodes / (ms_single * 1e-3) / 1e6,
+              "weights": "random-init 27-64-64-3", "fallback_nodes": int(out_nn.n_fallback),
+              "note": "ratio_to_zouhe: against the Zou & He lattice on the timed schedule; "
+                      "ratio_to_zouhe_single: against Zou & He at one launch per step"}
+    else:
+        del lat
     cbc = None
     if not args.no_cbc:
         # the characteristic outflow takes periodic laterals: the same lattice
         # with periodic laterals, Zou & He then characteristic outlet
         cs = 3 ** -0.5
-        lat = lbm.Lattice(mask, tau, precision=args.precision, collision="mrt",
-                          lateral="periodic", u_in=0.05, noise_amp=1e-4, seed=2,
-                          s_e=1.0, s_eps=1.0, s_q=1.0)
+        kwp = dict(kw, lateral="periodic")
+        lat = lbm.Lattice(mask, tau, launch=args.launch, **kwp)
         ms_zh = time_steps(lat, args.steps, args.warmup, torch)
         lat.set_outflow_cbc(sigma=0.25, kappa2=0.05 / cs, mach=0.05 / cs)
         ms_cbc = time_steps(lat, args.steps, args.warmup, torch)
@@ -500,6 +564,21 @@ def main():
                "setting": "same lattice with periodic laterals; characteristic outflow, "
                           "sigma 0.25, kappa_2 = Ma"}
         del lat
+    big = None
+    if not args.no_big:
+        bx, by = 16384, 4096
+        bmask, btau = c2_case(bx, by)
+        lat = lbm.Lattice(bmask, btau, launch=args.launch, **kw)
+        ms_big = time_steps(lat, args.big_steps, 20, torch)
+        assert lat.forces().nonfinite == 0
+        del lat
+        torch.cuda.empty_cache()
+        big = {"workload": f"same physics at {bx}x{by} (D = {80 * bx // 4096}), "
+                           f"{BYTES_PER_NODE[args.precision] * bx * by / 1e9:.1f} GB per step of "
+                           "population traffic, far above the 256 MB cache",
+               "mlups": bx * by / (ms_big * 1e-3) / 1e6, "ms_per_step": ms_big,
+               "steps": args.big_steps,
+               "roofline": step_roofline(bx * by, ms_big, spl, args.precision, None)}
     torch.cuda.synchronize()
     cbc_training = None if args.no_cbc_train else time_cbc_training(torch)
     d3q19 = None if args.no_3d else time_d3q19(torch)
@@ -509,10 +588,19 @@ def main():
     if not args.no_accuracy:
         from paper_2506_05293_amd import experiments
         acc = experiments.precision_study(args.accuracy_steps, nx, ny)
-        accuracy = {"workload": f"same lattice, {args.accuracy_steps} steps, FP32 offsets vs FP64",
-                    "fp32": {k: acc["fp32"].get(k) for k in ("cd_mean", "cl_rms", "st", "mlups")},
-                    "fp64": {k: acc["fp64"].get(k) for k in ("cd_mean", "cl_rms", "st", "mlups")},
-                    "rel_err": acc["rel_err"]}
+        keys = ("cd_mean", "cl_rms", "st", "mlups", "cl_rms_halves")
+        h = acc["fp64"]["cl_rms_halves"]
+        accuracy = {"workload": f"same lattice, {args.accuracy_steps} steps, FP32 offsets vs FP64, "
+                                "statistics over the last 40 %",
+                    "fp32": {k: acc["fp32"].get(k) for k in keys},
+                    "fp64": {k: acc["fp64"].get(k) for k in keys},
+                    "rel_err": acc["rel_err"],
+                    "gates": {"cd_mean": 5e-3, "cl_rms": 5e-3, "st": 1e-2},
+                    "pass": all(acc["rel_err"][k] <= g for k, g in
+                                (("cd_mean", 5e-3), ("cl_rms", 5e-3), ("st", 1e-2))),
+                    # saturated shedding: the rms of C_L - mean agrees between
+                    # the two halves of the window
+                    "cl_rms_half_change": abs(h[1] - h[0]) / h[1]}
     if args.study:
         run_studies(args.study, args.study_scale, args.nn_switch, args.nn_mass_bound)
 
@@ -525,23 +613,16 @@ def main():
         "config": {"workload": f"D2Q9 MRT channel {nx}x{ny}, cylinder D={80 * nx // 4096} at x=10D, "
                                f"{args.precision} offset storage, Zou-He inlet/outlet, walls, Re=200",
                    "nx": nx, "ny": ny, "precision": args.precision, "collision": "mrt"},
-        "roofline": {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": gbs / HBM_PEAK_GBS,
-                     "traffic": (None if traffic is None or (nx, ny, args.precision) != (4096, 1024, "fp32")
-                                 else traffic / (ms * 1e-3) / 1e9),
-                     "bytes_per_node_step": bpn, "steps_per_launch": spl,
-                     "single_step_equivalent_GBps": BYTES_PER_NODE[args.precision] * nodes
-                                                    / (ms * 1e-3) / 1e9,
-                     "kernel": ("k_step2 (two fused pull stream-collide steps per launch)" if pairs
-                                else "k_step (fused pull stream-collide)")},
-        "hbm_fraction": gbs / HBM_PEAK_GBS,
+        "roofline": roofline,
+        "c2_big": big,
         "nn_outflow": nn,
         "cbc_outflow": cbc,
         "cbc_training": cbc_training,
         "d3q19": d3q19,
         "batch": batch,
         "accuracy": accuracy,
-        "cpu_baseline": None if args.no_cpu_baseline else cpu_baseline(nx, ny),
+        "cpu_baseline": None if args.no_cpu_baseline else cpu_baseline(
+            nx, ny, all_cores=not args.no_cpu_all_cores),
     }
     print(json.dumps(line), flush=True)
 

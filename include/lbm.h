@@ -65,6 +65,10 @@ enum { LBM_BGK = 0, LBM_MRT = 1 };
 enum { LBM_LATERAL_WALLS = 0, LBM_LATERAL_PERIODIC = 1 };
 enum { LBM_X_INOUT = 0, LBM_X_PERIODIC = 1 };
 enum { LBM_OUT_ZOUHE = 0, LBM_OUT_NN = 1, LBM_OUT_CBC = 2 };
+/* Kernel schedule of lbm_step (results agree to rounding, see lbm_step). */
+enum { LBM_LAUNCH_PAIRS = 0, LBM_LAUNCH_SINGLE = 1 };
+/* Bulk tile of the one-step kernel: chosen by lattice size, or forced. */
+enum { LBM_PATH_AUTO = 0, LBM_PATH_SCALAR = 1, LBM_PATH_VECTOR = 2 };
 
 /*
  * Lattice description.
@@ -82,6 +86,12 @@ enum { LBM_OUT_ZOUHE = 0, LBM_OUT_NN = 1, LBM_OUT_CBC = 2 };
  *   xbc          LBM_X_INOUT: Zou & He velocity inlet at x = 0 and outflow at
  *                x = nx-1 (Zou & He pressure or neural); LBM_X_PERIODIC:
  *                periodic in x (no inlet, no outlet).
+ *   launch       LBM_LAUNCH_PAIRS (0, the default): two time steps per kernel
+ *                launch wherever the outflow has a two-step form (see
+ *                lbm_step); LBM_LAUNCH_SINGLE: one launch per time step.
+ *   bulk_path    tile of the one-step kernel: LBM_PATH_AUTO (0: one node per
+ *                thread below 12M nodes, four per lane above), or forced
+ *                LBM_PATH_SCALAR / LBM_PATH_VECTOR.  Same results.
  *   tau          relaxation time, > 0.5.
  *   s_e, s_eps   MRT rates of the energy moments (ignored by BGK).
  *   s_q          MRT rate of the energy-flux moments; <= 0 selects
@@ -97,6 +107,7 @@ enum { LBM_OUT_ZOUHE = 0, LBM_OUT_NN = 1, LBM_OUT_CBC = 2 };
 typedef struct {
   int32_t nx, ny;
   int32_t precision, collision, lateral, xbc;
+  int32_t launch, bulk_path;
   double tau, s_e, s_eps, s_q;
   double u_in, rho_out;
   double noise_amp;
@@ -174,11 +185,12 @@ lbm_status lbm_set_inlet_profile(lbm_ctx* c, const double* host_ux);
 /* Advance nsteps time steps (asynchronous).  One step: pull streaming of
  * the post-collision populations with half-way bounce-back on walls and
  * solids, the inlet and outlet columns, collision, and the force and mass
- * of the step (Sec. 2, Eqs. 1-4, 5-11, 12, 14-15).  With the Zou & He outflow
- * two steps run in each launch (the same node arithmetic, so the
- * populations agree with one launch per step to rounding; an odd count
- * ends with one single step); the environment variable LBM_STEP_PAIRS=0
- * selects one launch per step.  ESTATE before lbm_set_geometry. */
+ * of the step (Sec. 2, Eqs. 1-4, 5-11, 12, 14-15).  With params.launch =
+ * LBM_LAUNCH_PAIRS and the Zou & He outflow two steps run in each launch
+ * (the same node arithmetic, every intermediate state rounded to the storage
+ * precision as a store would round it, so the populations agree with one
+ * launch per step to the rounding of the sums; an odd count ends with one
+ * single step).  ESTATE before lbm_set_geometry. */
 lbm_status lbm_step(lbm_ctx* c, int64_t nsteps);
 
 /* Synchronise the stream and read the accumulators.  Returns EUNSTABLE
@@ -234,6 +246,14 @@ typedef struct {
 } lbm_cbc;
 
 lbm_status lbm_set_outflow_cbc(lbm_ctx* c, const lbm_cbc* p);
+
+/* Synchronise and write the moments of the stored state (Eq. 4), FP64, to
+ * host arrays of ny*nx doubles, row-major: rho = sum_i f_i, ux = sum_i c_ix
+ * f_i / rho, uy = sum_i c_iy f_i / rho, summed in FP64 from the stored values
+ * (collision conserves them, so they are also the moments before the
+ * collision of the last step).  Solid nodes give rho = 1, u = 0 (their
+ * stored equilibrium).  ESTATE before lbm_set_geometry. */
+lbm_status lbm_read_macroscopic(lbm_ctx* c, double* rho, double* ux, double* uy);
 
 /* Synchronise and copy the stored state -- the post-collision populations
  * f*(t) of the last step, as absolute values f_i (not offsets) -- into host

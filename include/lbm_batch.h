@@ -68,7 +68,9 @@ typedef struct {
   int32_t log_rows;             /* sample rows per logging slot                  */
   int32_t spin_limit;           /* barrier wait bound in polls; 0: default      */
   int32_t launch;               /* LBM_BATCH_PER_STEP (0) or LBM_BATCH_PERSISTENT */
-  int32_t reserved;             /* 0                                             */
+  int32_t groups_per_cu;        /* persistent grid: workgroups per CU (0: 4);
+                                   EINVAL if more than the kernel's resources
+                                   let one CU hold at once                      */
   void* stream;                 /* hipStream_t, borrowed                        */
 } lbm_batch_params;
 

@@ -44,7 +44,8 @@ enum : uint32_t {
 // ---- storage conversion -----------------------------------------------------
 // ld: plain load; ld_nt: load with the non-temporal hint; st: store with the
 // non-temporal hint (each population is written once per step); st_cached:
-// plain store (set-up kernels).
+// plain store (set-up kernels); stored: the value a store and a reload give
+// (a kernel that keeps a state in registers between steps rounds it so).
 template <typename S> struct Store;
 template <> struct Store<double> {
   using T = double;
@@ -52,6 +53,7 @@ template <> struct Store<double> {
   __device__ static T ld_nt(const double* p) { return __builtin_nontemporal_load(p); }
   __device__ static void st(double* p, T v) { __builtin_nontemporal_store(v, p); }
   __device__ static void st_cached(double* p, T v) { *p = v; }
+  __device__ static T stored(T v) { return v; }
 };
 template <> struct Store<float> {
   using T = float;
@@ -59,6 +61,7 @@ template <> struct Store<float> {
   __device__ static T ld_nt(const float* p) { return __builtin_nontemporal_load(p); }
   __device__ static void st(float* p, T v) { __builtin_nontemporal_store(v, p); }
   __device__ static void st_cached(float* p, T v) { *p = v; }
+  __device__ static T stored(T v) { return v; }
 };
 template <> struct Store<__half> {
   using T = float;
@@ -72,6 +75,7 @@ template <> struct Store<__half> {
                                 reinterpret_cast<unsigned short*>(p));
   }
   __device__ static void st_cached(__half* p, T v) { *p = __float2half_rn(v); }
+  __device__ static T stored(T v) { return __half2float(__float2half_rn(v)); }
 };
 
 // ---- moments -----------------------------------------------------------------

@@ -96,13 +96,12 @@ size_t elem_size(int precision) {
 
 // Bulk path: the vector tile pays off once the grid holds many waves per
 // resident slot (large lattices); small lattices use the scalar tile.
-// LBM_BULK_PATH=scalar|vector overrides the choice.
+// params.bulk_path may force either.
 constexpr int64_t kVectorPathMinNodes = int64_t(12) << 20;
 
 int choose_path(const lbm_params& p) {
-  const char* e = getenv("LBM_BULK_PATH");
-  if (e && !strcmp(e, "scalar")) return PATH_SCALAR;
-  if (e && !strcmp(e, "vector")) return PATH_VECTOR;
+  if (p.bulk_path == LBM_PATH_SCALAR) return PATH_SCALAR;
+  if (p.bulk_path == LBM_PATH_VECTOR) return PATH_VECTOR;
   return int64_t(p.nx) * p.ny >= kVectorPathMinNodes ? PATH_VECTOR : PATH_SCALAR;
 }
 
@@ -177,6 +176,10 @@ lbm_status check_params(const lbm_params* p) {
   if (p->lateral != LBM_LATERAL_WALLS && p->lateral != LBM_LATERAL_PERIODIC)
     return fail(LBM_EINVAL, "bad lateral %d", p->lateral);
   if (p->xbc != LBM_X_INOUT && p->xbc != LBM_X_PERIODIC) return fail(LBM_EINVAL, "bad xbc %d", p->xbc);
+  if (p->launch != LBM_LAUNCH_PAIRS && p->launch != LBM_LAUNCH_SINGLE)
+    return fail(LBM_EINVAL, "bad launch %d", p->launch);
+  if (p->bulk_path < LBM_PATH_AUTO || p->bulk_path > LBM_PATH_VECTOR)
+    return fail(LBM_EINVAL, "bad bulk_path %d", p->bulk_path);
   if (!(p->tau > 0.5) || !std::isfinite(p->tau)) return fail(LBM_EINVAL, "tau must be > 0.5 (got %g)", p->tau);
   if (!std::isfinite(p->u_in) || std::fabs(p->u_in) >= 0.5)
     return fail(LBM_EINVAL, "|u_in| must be < 0.5 (got %g)", p->u_in);
@@ -441,12 +444,10 @@ lbm_status lbm_step(lbm_ctx* c, int64_t nsteps) {
   if (nsteps < 0) return fail(LBM_EINVAL, "nsteps < 0");
   if (nsteps == 0) return LBM_OK;
   int64_t s = 0;
-  // With the Zou & He outflow, pairs of steps run in one launch each (the
-  // same node arithmetic; at 4096 x 1024 about 4 % faster than one launch per
-  // step); LBM_STEP_PAIRS=0 keeps one launch per step.  The neural and the
-  // characteristic outlets always take one launch per step.
-  const char* e = getenv("LBM_STEP_PAIRS");
-  if (c->n_nn == 0 && nsteps >= 2 && !(e && !strcmp(e, "0"))) {
+  // With the Zou & He outflow and params.launch = LBM_LAUNCH_PAIRS, pairs of
+  // steps run in one launch each (the same node arithmetic); the neural and
+  // the characteristic outlets take one launch per step.
+  if (c->n_nn == 0 && nsteps >= 2 && c->p.launch == LBM_LAUNCH_PAIRS) {
     for (; s + 1 < nsteps; s += 2) {
       const StepLaunch L = c->launch();
       HIP_TRY(launch_pair(L, c->stream));
@@ -638,6 +639,31 @@ lbm_status lbm_read_populations(lbm_ctx* c, double* host) {
   }
   // the staging overwrote the spare buffer: restore it, since its solid nodes
   // are never rewritten by a step
+  lbm_status st = mirror_state(c);
+  if (st) return st;
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  return LBM_OK;
+}
+
+lbm_status lbm_read_macroscopic(lbm_ctx* c, double* rho, double* ux, double* uy) {
+  if (!c || !rho || !ux || !uy) return fail(LBM_EINVAL, "NULL argument");
+  if (!c->geometry) return fail(LBM_ESTATE, "lbm_set_geometry first");
+  double* stage = static_cast<double*>(c->buf[c->cur ^ 1]);
+  const int chunk = c->stage_rows(3);
+  const size_t nx = size_t(c->p.nx);
+  double* out[3] = {rho, ux, uy};
+  for (int y0 = 0; y0 < c->p.ny; y0 += chunk) {
+    const int rows = std::min(chunk, c->p.ny - y0);
+    const size_t n = size_t(rows) * nx;
+    HIP_TRY(launch_macro(c->p.precision, c->buf[c->cur], stage, c->p.nx, c->lay.pitch, c->lay.plane,
+                         y0, rows, c->stream));
+    for (int k = 0; k < 3; ++k)
+      HIP_TRY(hipMemcpyAsync(out[k] + y0 * nx, stage + k * n, n * 8, hipMemcpyDeviceToHost,
+                             c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+  }
+  // the staging overwrote the spare buffer, whose solid nodes a step never
+  // rewrites: restore it
   lbm_status st = mirror_state(c);
   if (st) return st;
   HIP_TRY(hipStreamSynchronize(c->stream));

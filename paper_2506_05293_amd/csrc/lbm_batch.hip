@@ -433,6 +433,7 @@ lbm_status check_batch(const lbm_batch_params* p, const lbm_batch_lattice* lat, 
     return set_error(LBM_EINVAL, "negative size");
   if (p->log_slots > 0 && p->log_every < 1) return set_error(LBM_EINVAL, "log_every must be >= 1");
   if (p->spin_limit < 0) return set_error(LBM_EINVAL, "spin_limit < 0");
+  if (p->groups_per_cu < 0) return set_error(LBM_EINVAL, "groups_per_cu < 0");
   if (p->launch != LBM_BATCH_PERSISTENT && p->launch != LBM_BATCH_PER_STEP)
     return set_error(LBM_EINVAL, "bad launch mode");
   for (int i = 0; i < n; ++i) {
@@ -610,38 +611,46 @@ lbm_status lbm_batch_create(const lbm_batch_params* p, const lbm_batch_lattice* 
   a.xa = reinterpret_cast<float*>(base + L.xa);
   a.t = reinterpret_cast<float*>(base + L.t);
 
-  // co-resident grid: occupancy of the kernel times the number of CUs
+  // Co-resident grid of the persistent mode.  A workgroup of 256 threads
+  // puts one wave on each of a CU's four SIMDs, so a CU holds k workgroups
+  // at once when k waves of the kernel fit one SIMD: k times its VGPRs
+  // (allocated in granules of 8 from the 512 of the unified register file)
+  // within 512, k <= 8 waves, k times its LDS within the CU's 160 KiB, and
+  // k times its SGPRs within the SIMD's 800 (a wave allocates at most 112,
+  // so any k <= 7 fits).  The smaller of that bound and the occupancy query
+  // is taken; the grid uses groups_per_cu (default kBatchGroupsPerCu) of
+  // them per CU.
   int dev = 0, cus = 0, per_cu = 0;
+  hipFuncAttributes fa{};
+  const void* kfn = p->collision == LBM_MRT ? reinterpret_cast<const void*>(k_batch<1>)
+                                            : reinterpret_cast<const void*>(k_batch<0>);
   e = hipGetDevice(&dev);
   if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
   if (e == hipSuccess)
     e = p->collision == LBM_MRT
             ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batch<1>, kBlock, 0)
             : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batch<0>, kBlock, 0);
+  if (e == hipSuccess) e = hipFuncGetAttributes(&fa, kfn);
   if (e != hipSuccess || per_cu < 1 || cus < 1)
     return cleanup(set_error(LBM_EHIP, "occupancy query failed"));
-  // The occupancy query has been seen to report one workgroup per CU more
-  // than can be resident together, and a grid barrier needs every
-  // workgroup resident: keep one per CU in reserve (LBM_BATCH_RESERVE
-  // overrides; a grid that is not co-resident ends in the barrier's bounded
-  // wait and an LBM_EHIP).  Within that, at most kBatchGroupsPerCu
-  // workgroups per CU (LBM_BATCH_GROUPS_PER_CU overrides).
-  int reserve = 1, per = kBatchGroupsPerCu;
-  if (const char* e = getenv("LBM_BATCH_RESERVE")) reserve = std::max(0, atoi(e));
-  if (const char* e = getenv("LBM_BATCH_GROUPS_PER_CU")) per = std::max(1, atoi(e));
+  const int vgpr = std::max(8, (fa.numRegs + 7) / 8 * 8);
+  const int lds = std::max<int>(1, int(fa.sharedSizeBytes));
+  const int fit = std::min({512 / vgpr, 8, 7, (160 * 1024) / lds, per_cu});
+  const int per = p->groups_per_cu > 0 ? p->groups_per_cu : kBatchGroupsPerCu;
+  if (p->launch == LBM_BATCH_PERSISTENT && per > fit)
+    return cleanup(set_error(LBM_EINVAL, "groups_per_cu %d exceeds the %d workgroups per CU the "
+                             "persistent kernel can hold at once (%d VGPRs, %d B of LDS)",
+                             per, fit, fa.numRegs, lds));
   // The item split gives each XCD one eighth of the workgroups: the grid is a
   // multiple of 8, and no larger than the items need.
-  const int resident = std::max(1, per_cu - reserve) * cus / 8 * 8;
   const int wanted = (L.nitems + 8 * kWaves - 1) / (8 * kWaves) * 8;
-  b->grid = std::max(8, std::min({per * cus / 8 * 8, resident, wanted}));
-  if (p->launch == LBM_BATCH_PERSISTENT && b->grid > resident)
-    return cleanup(set_error(LBM_EHIP, "too few resident workgroups"));
+  b->grid = std::max(8, std::min(std::min(per, fit) * cus / 8 * 8, wanted));
   // items of the XCD with the most (whole rounds of chunks)
   const int per_xcd = (L.nitems + 8 * kItemChunk - 1) / (8 * kItemChunk) * kItemChunk;
   b->grid_step = 8 * std::max(1, (per_xcd + kWaves - 1) / kWaves);
   if (getenv("LBM_BATCH_VERBOSE"))
-    fprintf(stderr, "lbm_batch: %d CUs, occupancy %d workgroups per CU, reserve %d, grid %d\n", cus,
-            per_cu, reserve, b->grid);
+    fprintf(stderr, "lbm_batch: %d CUs, occupancy query %d, resource bound %d workgroups per CU "
+            "(%d VGPRs, %d B LDS), grid %d\n", cus, per_cu, fit, fa.numRegs, lds, b->grid);
   b->steps = 0;
   b->fixed_slots = 0;
   *out = b;

@@ -142,6 +142,10 @@ hipError_t launch_read(int precision, const void* A, double* out, int nx, int pi
                        int64_t plane, int y0, int rows, hipStream_t s);
 hipError_t launch_write(int precision, void* A, void* B, const double* in, int nx,
                         int pitch, int64_t plane, int y0, int rows, hipStream_t s);
+// Moments (rho, ux, uy; Eq. 4) of rows [y0, y0+rows) of A into a dense FP64
+// staging array [3][rows][nx].
+hipError_t launch_macro(int precision, const void* A, double* out, int nx, int pitch,
+                        int64_t plane, int y0, int rows, hipStream_t s);
 
 // Standalone MLP evaluation on n feature rows (same device code as the fused
 // outflow).

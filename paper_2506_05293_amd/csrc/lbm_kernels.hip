@@ -691,8 +691,10 @@ __device__ __forceinline__ void pair_strip(const StepLaunch& L, int wave, double
       fxa += double(fx1);
       fya += double(fy1);
       dma += double(dm1);
+      // the state of step t+1 as a store and reload would give it (FP16
+      // storage rounds here, as one launch per step does)
 #pragma unroll
-      for (int q = 0; q < 9; ++q) S2[q] = g[q];
+      for (int q = 0; q < 9; ++q) S2[q] = Store<S>::stored(g[q]);
       if (j >= 4) {
         // step t+2 at row yr - 2
         const int y2 = yr - 2;
@@ -901,6 +903,46 @@ __global__ void __launch_bounds__(kBlock) k_write(S* A, S* B, const double* in, 
     Store<S>::st_cached(A + q * plane + node, v);
     Store<S>::st_cached(B + q * plane + node, v);
   }
+}
+
+// Moments of the stored state in FP64 (Eq. 4): rho = 1 + sum of the offsets,
+// j = sum_i c_i g_i (the weights carry no momentum), u = j / rho.
+template <typename S>
+__global__ void __launch_bounds__(kBlock) k_macro(const S* A, double* out, int nx, int pitch,
+                                                  int64_t plane, int y0, int rows) {
+  const int64_t n = int64_t(rows) * nx;
+  const int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+  if (i >= n) return;
+  const int r = int(i / nx), x = int(i - int64_t(r) * nx);
+  const int64_t node = int64_t(y0 + r) * pitch + x;
+  double g[9];
+#pragma unroll
+  for (int q = 0; q < 9; ++q) g[q] = double(Store<S>::ld(A + q * plane + node));
+  const Macro<double> m = macro(g);
+  out[i] = m.rho;
+  out[n + i] = m.jx / m.rho;
+  out[2 * n + i] = m.jy / m.rho;
+}
+
+hipError_t launch_macro(int precision, const void* A, double* out, int nx, int pitch,
+                        int64_t plane, int y0, int rows, hipStream_t s) {
+  const dim3 grid(unsigned((int64_t(rows) * nx + kBlock - 1) / kBlock));
+  switch (precision) {
+    case LBM_FP64:
+      hipLaunchKernelGGL(k_macro<double>, grid, dim3(kBlock), 0, s,
+                         static_cast<const double*>(A), out, nx, pitch, plane, y0, rows);
+      break;
+    case LBM_FP32_OFFSET:
+      hipLaunchKernelGGL(k_macro<float>, grid, dim3(kBlock), 0, s,
+                         static_cast<const float*>(A), out, nx, pitch, plane, y0, rows);
+      break;
+    case LBM_FP16_OFFSET:
+      hipLaunchKernelGGL(k_macro<__half>, grid, dim3(kBlock), 0, s,
+                         static_cast<const __half*>(A), out, nx, pitch, plane, y0, rows);
+      break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
 }
 
 hipError_t launch_read(int precision, const void* A, double* out, int nx, int pitch,

@@ -20,6 +20,8 @@ LBM_BGK, LBM_MRT = 0, 1
 LBM_LATERAL_WALLS, LBM_LATERAL_PERIODIC = 0, 1
 LBM_X_INOUT, LBM_X_PERIODIC = 0, 1
 LBM_OUT_ZOUHE, LBM_OUT_NN, LBM_OUT_CBC = 0, 1, 2
+LBM_LAUNCH_PAIRS, LBM_LAUNCH_SINGLE = 0, 1
+LBM_PATH_AUTO, LBM_PATH_SCALAR, LBM_PATH_VECTOR = 0, 1, 2
 LBM_BATCH_PER_STEP, LBM_BATCH_PERSISTENT = 0, 1
 
 
@@ -27,6 +29,7 @@ class lbm_params(ctypes.Structure):
     _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32),
                 ("precision", ctypes.c_int32), ("collision", ctypes.c_int32),
                 ("lateral", ctypes.c_int32), ("xbc", ctypes.c_int32),
+                ("launch", ctypes.c_int32), ("bulk_path", ctypes.c_int32),
                 ("tau", ctypes.c_double), ("s_e", ctypes.c_double),
                 ("s_eps", ctypes.c_double), ("s_q", ctypes.c_double),
                 ("u_in", ctypes.c_double), ("rho_out", ctypes.c_double),
@@ -114,7 +117,7 @@ class lbm_batch_params(ctypes.Structure):
                 ("log_start", ctypes.c_int64), ("log_every", ctypes.c_int64),
                 ("log_slots", ctypes.c_int64), ("log_rows", ctypes.c_int32),
                 ("spin_limit", ctypes.c_int32), ("launch", ctypes.c_int32),
-                ("reserved", ctypes.c_int32), ("stream", ctypes.c_void_p)]
+                ("groups_per_cu", ctypes.c_int32), ("stream", ctypes.c_void_p)]
 
 
 PARAM_SHAPES = {"w1": (64, 27), "b1": (64,), "w2": (64, 64), "b2": (64,), "w3": (3, 64), "b3": (3,)}
@@ -155,6 +158,7 @@ def library():
             "lbm_set_outflow_model": (I32, [VP, I32, P(lbm_mlp)]),
             "lbm_set_outflow_cbc": (I32, [VP, P(lbm_cbc)]),
             "lbm_read_populations": (I32, [VP, DP]),
+            "lbm_read_macroscopic": (I32, [VP, DP, DP, DP]),
             "lbm_write_populations": (I32, [VP, DP]),
             "lbm_sync": (I32, [VP]),
             "lbm_mlp_forward": (I32, [VP, VP, VP, I64]),
@@ -337,6 +341,13 @@ def lbm_read_populations(ctx, nx, ny):
     return out
 
 
+def lbm_read_macroscopic(ctx, nx, ny):
+    rho, ux, uy = (np.empty((ny, nx)) for _ in range(3))
+    _check(library().lbm_read_macroscopic(ctx, _dptr(rho), _dptr(ux), _dptr(uy)),
+           "lbm_read_macroscopic")
+    return rho, ux, uy
+
+
 def lbm_write_populations(ctx, f):
     a = np.ascontiguousarray(f, dtype=np.float64)
     return _check(library().lbm_write_populations(ctx, _dptr(a)), "lbm_write_populations")
@@ -438,14 +449,14 @@ class Batch:
 
     def __init__(self, lattices, *, collision="mrt", lateral="periodic", s_e=1.0, s_eps=1.0, s_q=0.0,
                  noise_amp=0.0, history_cap=0, log_start=0, log_every=1, log_slots=0, log_rows=0,
-                 spin_limit=0, launch="per_step", device="cuda"):
+                 spin_limit=0, launch="per_step", groups_per_cu=0, device="cuda"):
         import torch
         self.lattices = lattices
         self.shapes = [np.shape(L["mask"]) for L in lattices]
         self.stream = torch.cuda.current_stream(device)
         self.params = lbm_batch_params(_COLL[collision], _LAT[lateral], s_e, s_eps, s_q, noise_amp,
                                        history_cap, log_start, log_every, log_slots, log_rows,
-                                       spin_limit, _LAUNCH[launch], 0,
+                                       spin_limit, _LAUNCH[launch], groups_per_cu,
                                        ctypes.c_void_p(self.stream.cuda_stream))
         nbytes = lbm_batch_workspace_bytes(self.params, lattices)
         self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=device)
@@ -875,19 +886,30 @@ _XBC = {"inout": LBM_X_INOUT, "periodic": LBM_X_PERIODIC}
 _LAUNCH = {"persistent": LBM_BATCH_PERSISTENT, "per_step": LBM_BATCH_PER_STEP}
 
 
+_STEP_LAUNCH = {"pairs": LBM_LAUNCH_PAIRS, "single": LBM_LAUNCH_SINGLE}
+_PATH = {"auto": LBM_PATH_AUTO, "scalar": LBM_PATH_SCALAR, "vector": LBM_PATH_VECTOR}
+# Kernel schedule of Lattice objects created without explicit launch /
+# bulk_path arguments (passed to the library in lbm_params).
+LATTICE_DEFAULTS = {"launch": "pairs", "bulk_path": "auto"}
+
+
 class Lattice:
     """A lattice on the current CUDA (HIP) device.  The workspace is a torch
     uint8 tensor and the stream is torch's current stream."""
 
     def __init__(self, mask, tau, *, precision="fp32", collision="bgk", lateral="walls",
                  xbc="inout", u_in=0.05, rho_out=1.0, s_e=1.0, s_eps=1.0, s_q=0.0,
-                 noise_amp=0.0, seed=0, history_cap=0, device="cuda"):
+                 noise_amp=0.0, seed=0, history_cap=0, launch=None, bulk_path=None,
+                 device="cuda"):
         import torch
         mask = np.ascontiguousarray(mask, dtype=np.uint8)
         self.ny, self.nx = mask.shape
         self.stream = torch.cuda.current_stream(device)
+        launch = LATTICE_DEFAULTS["launch"] if launch is None else launch
+        bulk_path = LATTICE_DEFAULTS["bulk_path"] if bulk_path is None else bulk_path
         self.params = lbm_params(self.nx, self.ny, _PREC[precision], _COLL[collision],
-                                 _LAT[lateral], _XBC[xbc], tau, s_e, s_eps, s_q, u_in,
+                                 _LAT[lateral], _XBC[xbc], _STEP_LAUNCH[launch], _PATH[bulk_path],
+                                 tau, s_e, s_eps, s_q, u_in,
                                  rho_out, noise_amp, seed, history_cap,
                                  ctypes.c_void_p(self.stream.cuda_stream))
         nbytes = lbm_workspace_bytes(self.params)
@@ -939,11 +961,7 @@ class Lattice:
                             float(self.nx if length is None else length), rho_inf, net)
 
     def macroscopic(self):
-        f = self.populations()
-        rho = f.sum(0)
-        cxv = np.array([0, 1, 0, -1, 0, 1, -1, -1, 1], float)[:, None, None]
-        cyv = np.array([0, 0, 1, 0, -1, 1, 1, -1, -1], float)[:, None, None]
-        return rho, (cxv * f).sum(0) / rho, (cyv * f).sum(0) / rho
+        return lbm_read_macroscopic(self.ctx, self.nx, self.ny)
 
     def sync(self):
         lbm_sync(self.ctx)

@@ -34,10 +34,15 @@ def summarize(fx, fy, u_ref, length, window=0.4):
     n0 = int(len(cd) * (1.0 - window))
     cd, cl = cd[n0:], cl[n0:]
     f = peak_frequency(cl)
+    h = len(cl) // 2
+    halves = [float(np.sqrt(np.mean((c - c.mean()) ** 2))) for c in (cl[:h], cl[h:])]
     return {"cd_mean": float(cd.mean()), "cl_mean": float(cl.mean()),
             "cl_rms": float(np.sqrt(np.mean((cl - cl.mean()) ** 2))),
             "cl_amp": float(0.5 * (cl.max() - cl.min())), "st": float(f * length / u_ref),
-            "samples": int(len(cd))}
+            "samples": int(len(cd)),
+            # rms of C_L - mean in the first and second half of the window:
+            # equal within a few per cent once the shedding has saturated
+            "cl_rms_halves": halves}
 
 
 def relative_errors(test, ref):

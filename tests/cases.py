@@ -59,3 +59,4 @@ def random_params(seed, w_scale=1.0, out_sd=1e-3):
 def f32_values(P):
     """The network's values rounded to FP32 (the form the step holds)."""
     return {k: np.asarray(v, np.float32).astype(np.float64) for k, v in P.items()}
+

@@ -13,8 +13,13 @@ def pytest_configure(config):
     config.addinivalue_line("markers", "slow: long CPU test")
 
 
-@pytest.fixture(params=["scalar", "vector"])
-def bulk_path(request, monkeypatch):
-    """Run a GPU test once per bulk tile shape of the step kernel."""
-    monkeypatch.setenv("LBM_BULK_PATH", request.param)
+@pytest.fixture(params=["pairs", "single-scalar", "single-vector"])
+def schedule(request, monkeypatch):
+    """Run a GPU test once per kernel schedule of lbm_step, chosen through
+    lbm_params: two steps per launch (where the outflow has that form), and
+    one step per launch with each bulk tile shape."""
+    from paper_2506_05293_amd import lbm
+    launch, _, path = request.param.partition("-")
+    monkeypatch.setitem(lbm.LATTICE_DEFAULTS, "launch", launch)
+    monkeypatch.setitem(lbm.LATTICE_DEFAULTS, "bulk_path", path or "auto")
     return request.param

@@ -31,7 +31,8 @@ def test_every_declared_symbol_is_exported():
 
 def _params(**kw):
     p = lbm.lbm_params(200, 80, lbm.LBM_FP32_OFFSET, lbm.LBM_MRT, lbm.LBM_LATERAL_WALLS,
-                       lbm.LBM_X_INOUT, 0.56, 1.0, 1.0, 0.0, 0.05, 1.0, 1e-4, 1, 100, None)
+                       lbm.LBM_X_INOUT, lbm.LBM_LAUNCH_PAIRS, lbm.LBM_PATH_AUTO,
+                       0.56, 1.0, 1.0, 0.0, 0.05, 1.0, 1e-4, 1, 100, None)
     for k, v in kw.items():
         setattr(p, k, v)
     return p
@@ -47,7 +48,9 @@ def test_workspace_size_scales_with_precision():
 
 @pytest.mark.parametrize("field,value", [("tau", 0.5), ("tau", float("nan")), ("nx", 4),
                                          ("precision", 7), ("collision", 3), ("u_in", 0.6),
-                                         ("rho_out", 0.0), ("history_cap", -1)])
+                                         ("rho_out", 0.0), ("history_cap", -1),
+                                         ("launch", 2), ("launch", -1), ("bulk_path", 3),
+                                         ("bulk_path", -1)])
 def test_bad_parameters_are_rejected(field, value):
     with pytest.raises(lbm.LbmError) as e:
         lbm.lbm_workspace_bytes(_params(**{field: value}))
@@ -70,6 +73,9 @@ def test_create_checks_workspace_without_touching_it():
     with pytest.raises(lbm.LbmError) as e:
         lbm.lbm_set_outflow_model(ctx, lbm.LBM_OUT_NN, None)
     assert e.value.status == lbm.LBM_EINVAL
+    with pytest.raises(lbm.LbmError) as e:
+        lbm.lbm_read_macroscopic(ctx, 200, 80)
+    assert e.value.status == lbm.LBM_ESTATE
     lbm.lbm_destroy(ctx)
 
 

@@ -36,10 +36,10 @@ LAUNCHES = ["persistent", "per_step"]
 @pytest.mark.parametrize("launch", LAUNCHES)
 @pytest.mark.parametrize("collision,lateral", [("mrt", "periodic"), ("bgk", "walls")])
 def test_batch_equals_single_lattices(collision, lateral, launch, monkeypatch):
-    monkeypatch.setenv("LBM_BULK_PATH", "vector")
     # the batch kernel runs the single-step node code: single lattices
     # with one launch per step are its bitwise reference
-    monkeypatch.setenv("LBM_STEP_PAIRS", "0")
+    monkeypatch.setitem(lbm.LATTICE_DEFAULTS, "schedule", "vector")
+    monkeypatch.setitem(lbm.LATTICE_DEFAULTS, "launch", "single")
     lats = _lattices()
     _say("batch vs single", collision, lateral, launch)
     b = lbm.Batch(lats, collision=collision, lateral=lateral, noise_amp=1e-3, history_cap=200,
@@ -120,10 +120,10 @@ def test_logging_matches_pull_of_read_state(launch):
 
 @pytest.mark.parametrize("launch", LAUNCHES)
 def test_unstable_lattice_is_retired_alone(launch, monkeypatch):
-    monkeypatch.setenv("LBM_BULK_PATH", "vector")
     # the batch kernel runs the single-step node code: single lattices
     # with one launch per step are its bitwise reference
-    monkeypatch.setenv("LBM_STEP_PAIRS", "0")
+    monkeypatch.setitem(lbm.LATTICE_DEFAULTS, "schedule", "vector")
+    monkeypatch.setitem(lbm.LATTICE_DEFAULTS, "launch", "single")
     lats = _lattices()[:2]
     bad = dict(mask=geometry.cylinder(200, 60, 40, 30, 20.0), tau=0.5005, u_in=0.3, seed=1)
     _say("batch retirement", launch)
@@ -152,6 +152,21 @@ def test_barrier_wait_bound_is_reported():
     with pytest.raises(lbm.LbmError) as e:
         b.forces(0)
     assert e.value.status == lbm.LBM_EHIP
+
+
+def test_persistent_grid_beyond_residency_is_rejected():
+    # the persistent grid must be co-resident: asking for more workgroups per
+    # CU than the kernel's registers and LDS let a CU hold is an argument
+    # error at creation, not a barrier that never completes
+    _say("batch groups_per_cu beyond residency")
+    with pytest.raises(lbm.LbmError) as e:
+        lbm.Batch(_lattices(), collision="mrt", lateral="periodic", launch="persistent",
+                  groups_per_cu=64)
+    assert e.value.status == lbm.LBM_EINVAL
+    b = lbm.Batch(_lattices(), collision="mrt", lateral="periodic", launch="persistent",
+                  groups_per_cu=2)
+    b.step(4)
+    assert b.forces(0).step == 4
 
 
 def test_batch_solid_nodes_survive_read_out():

@@ -60,7 +60,7 @@ FIXED = dict(sigma=0.4, kappa2=0.3, mach=0.1 / CS, length=61.0, rho_inf=1.0)
 
 
 @pytest.mark.parametrize("collision,body", [("bgk", False), ("mrt", False), ("mrt", True)])
-def test_cbc_fp64_parity(collision, body, bulk_path):
+def test_cbc_fp64_parity(collision, body, schedule):
     lateral = "periodic"
     _say("cbc fp64", collision, "body" if body else "")
     mask = geometry.cylinder(61, 43, 14.3, 20.6, 9.0) if body else None
@@ -81,7 +81,7 @@ def test_cbc_fp64_parity(collision, body, bulk_path):
     assert abs(fo.mass - o.mass_hist[-1]) < 1e-10 * o.mass_hist[-1]
 
 
-def test_cbc_network_fp64_parity(bulk_path):
+def test_cbc_network_fp64_parity(schedule):
     _say("cbc network fp64")
     cbc = dict(FIXED, net=random_net(3))
     g, o = _pair(61, 43, "periodic", "bgk", "fp64", cbc)
@@ -102,7 +102,7 @@ def test_cbc_network_fp64_parity(bulk_path):
 
 
 @pytest.mark.parametrize("collision", ["bgk", "mrt"])
-def test_cbc_fp32_offsets(collision, bulk_path):
+def test_cbc_fp32_offsets(collision, schedule):
     _say("cbc fp32", collision)
     g, o = _pair(61, 43, "periodic", collision, "fp32", FIXED)
     g.step(300)
@@ -146,7 +146,7 @@ def test_cbc_plane_pulse_leaves_without_reflection():
     assert out["cbc"] < 0.05 and out["zouhe"] > 0.5
 
 
-def test_cbc_full_size_steps(bulk_path):
+def test_cbc_full_size_steps(schedule):
     # the 4096 x 1024 cylinder lattice with periodic laterals, FP32,
     # characteristic outlet: both sides start from the same seeded smooth
     # fields and take three steps; every fluid node is compared

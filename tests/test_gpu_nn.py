@@ -13,6 +13,7 @@ import pytest
 import torch
 
 import cases
+import nn_bounds
 from oracle import mlp as omlp
 from oracle.solver import Lattice as Oracle
 from paper_2506_05293_amd import geometry, lbm, workloads
@@ -28,19 +29,7 @@ random_params = cases.random_params
 _f32 = cases.f32_values
 
 
-def output_bound(x, P):
-    """Per-output error bound for the BF16 network (see module docstring)."""
-    b = omlp.bf16_round
-    z = b(omlp.standardise_f32(x, P["mu_in"], P["sd_in"]))
-    W1, W2, W3 = b(P["w1"]), b(P["w2"]), b(P["w3"])
-    a1 = z @ W1.T + P["b1"]
-    h1 = np.tanh(a1)
-    e1 = 2.0**-8 * np.abs(h1) + 1e-5 * (np.abs(z) @ np.abs(W1).T + np.abs(P["b1"]))
-    a2 = b(h1) @ W2.T + P["b2"]
-    h2 = np.tanh(a2)
-    e2 = e1 @ np.abs(W2).T + 2.0**-8 * np.abs(h2) + 1e-5 * (np.abs(h1) @ np.abs(W2).T)
-    e3 = e2 @ np.abs(W3).T + 1e-5 * (np.abs(h2) @ np.abs(W3).T + np.abs(P["b3"]))
-    return e3 * P["sd_out"], 1e-5 * (np.abs(b(h2)) @ np.abs(W3).T + np.abs(P["b3"])) * P["sd_out"]
+output_bound = nn_bounds.output_bound
 
 
 def _lattice_with_net(P, mass_bound=1e9, **kw):
@@ -92,10 +81,10 @@ def test_zero_network_is_copy_outflow_fp64():
 
 
 @pytest.mark.parametrize("how", ["mass_bound_zero", "nan_weights"])
-def test_forced_fallback_equals_zouhe_bitwise(how, bulk_path, monkeypatch):
+def test_forced_fallback_equals_zouhe_bitwise(how, schedule, monkeypatch):
     # the neural kernel's fallback runs the single-step node code: compare
     # with one launch per step on the Zou & He side too
-    monkeypatch.setenv("LBM_STEP_PAIRS", "0")
+    monkeypatch.setitem(lbm.LATTICE_DEFAULTS, "launch", "single")
     case = cases.ragged("mrt", "periodic")
     P = _f32(random_params(2))
     bound = 0.0
@@ -118,7 +107,7 @@ def test_forced_fallback_equals_zouhe_bitwise(how, bulk_path, monkeypatch):
     assert b.forces().n_fallback == 120 * ny
 
 
-def test_nn_outflow_run_matches_oracle(bulk_path):
+def test_nn_outflow_run_matches_oracle(schedule):
     case = cases.ragged("bgk", "periodic")
     P = _f32(random_params(3, w_scale=0.5, out_sd=2e-4))
     _say("nn outflow run fp64 vs oracle")
@@ -144,7 +133,7 @@ def test_nn_outflow_run_matches_oracle(bulk_path):
     assert np.max(np.abs(z.post_collision()[:, :, -1] - ref[:, :, -1])) > 1e-5
 
 
-def test_nn_outflow_full_size_steps(bulk_path):
+def test_nn_outflow_full_size_steps(schedule):
     # truncated cylinder lattice 4096 x 512 (D = 64, periodic laterals, MRT,
     # FP32) with the neural outflow: both sides start from the same seeded
     # smooth fields and take three steps
@@ -171,7 +160,7 @@ def test_nn_outflow_full_size_steps(bulk_path):
 
 
 @pytest.mark.parametrize("precision,tol", [("fp32", 5e-6), ("fp16", 2e-4)])
-def test_naca_full_size_with_neural_outflow(precision, tol, bulk_path):
+def test_naca_full_size_with_neural_outflow(precision, tol, schedule):
     # the NACA0012 lattice of the airfoil study (chord 256, AoA 4 deg, 3 chords
     # behind the trailing edge: 3072 x 1024, MRT, Re 1000) with a network of the
     # paper's shape at the outlet, FP32 and FP16 offsets: three steps from the
@@ -226,7 +215,7 @@ def padded(P):
     return Q
 
 
-def test_paper_network_run_matches_oracle(bulk_path):
+def test_paper_network_run_matches_oracle(schedule):
     case = cases.ragged("bgk", "periodic")
     P = _f32(paper_params(5))
     _say("paper-shape network run fp64 vs oracle")

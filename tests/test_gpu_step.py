@@ -69,7 +69,7 @@ def test_c1_literal_fp64_parity(steps):
 
 
 @pytest.mark.parametrize("re,collision", [(75.0, "bgk"), (100.0, "mrt")])
-def test_c1_fp64_parity_2000_steps(re, collision, bulk_path):
+def test_c1_fp64_parity_2000_steps(re, collision, schedule):
     _say("c1 fp64", collision, "Re", re, 2000)
     _c1_parity(cases.c1(re, collision), 2000)
 
@@ -89,7 +89,7 @@ def test_c1_literal_divergence_is_flagged():
 
 @pytest.mark.parametrize("collision,lateral", [("mrt", "periodic"), ("bgk", "walls"),
                                                ("mrt", "walls"), ("bgk", "periodic")])
-def test_ragged_fp64_parity(collision, lateral, bulk_path):
+def test_ragged_fp64_parity(collision, lateral, schedule):
     case = cases.ragged(collision, lateral)
     _say("ragged fp64", collision, lateral)
     g = _gpu(case, history_cap=300)
@@ -104,7 +104,7 @@ def test_ragged_fp64_parity(collision, lateral, bulk_path):
     assert np.max(np.abs(fy - o.fy_hist)) < 1e-12 * scale
 
 
-def test_fully_periodic_taylor_green_parity(bulk_path):
+def test_fully_periodic_taylor_green_parity(schedule):
     n = 96
     k = 2 * np.pi / n
     Y, X = np.mgrid[0:n, 0:n].astype(float)
@@ -138,7 +138,7 @@ def test_inlet_profile_parity():
 
 @pytest.mark.parametrize("precision,drho_tol,du_tol", [("fp32", 1e-5, 1e-4), ("fp16", 2e-2, 2e-2)])
 @pytest.mark.parametrize("re,collision", [(75.0, "bgk"), (100.0, "mrt")])
-def test_c1_offset_storage(precision, drho_tol, du_tol, re, collision, bulk_path):
+def test_c1_offset_storage(precision, drho_tol, du_tol, re, collision, schedule):
     case = cases.c1(re, collision)
     _say("c1", precision, collision, re, 2000)
     g = _gpu(case, precision, history_cap=2000)
@@ -156,7 +156,7 @@ def test_c1_offset_storage(precision, drho_tol, du_tol, re, collision, bulk_path
     assert np.all(np.isfinite(fx)) and np.all(np.isfinite(fy))
 
 
-def test_checkpoint_roundtrip_is_bitwise(bulk_path):
+def test_checkpoint_roundtrip_is_bitwise(schedule):
     case = cases.ragged("mrt", "walls")
     _say("checkpoint fp32")
     a = _gpu(case, "fp32")
@@ -169,7 +169,30 @@ def test_checkpoint_roundtrip_is_bitwise(bulk_path):
     np.testing.assert_array_equal(a.populations(), b.populations())
 
 
-def test_runs_are_deterministic(bulk_path):
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "fp16"])
+def test_macroscopic_read_out(precision):
+    # lbm_read_macroscopic (Eq. 4 in the library, FP64 sums of the stored
+    # state) against the moments of the populations read out by
+    # lbm_read_populations, and rho = 1, u = 0 on solid nodes
+    case = cases.ragged("mrt", "walls")
+    _say("macroscopic read-out", precision)
+    g = _gpu(case, precision)
+    g.step(37)
+    f = g.populations()
+    rho, ux, uy = g.macroscopic()
+    cxv = np.array([0, 1, 0, -1, 0, 1, -1, -1, 1], float)[:, None, None]
+    cyv = np.array([0, 0, 1, 0, -1, 1, 1, -1, -1], float)[:, None, None]
+    r = f.sum(0)
+    np.testing.assert_allclose(rho, r, rtol=0, atol=1e-14)
+    np.testing.assert_allclose(ux, (cxv * f).sum(0) / r, rtol=0, atol=1e-14)
+    np.testing.assert_allclose(uy, (cyv * f).sum(0) / r, rtol=0, atol=1e-14)
+    solid = case["mask"] != 0
+    assert np.all(rho[solid] == 1.0) and np.all(ux[solid] == 0.0) and np.all(uy[solid] == 0.0)
+    # the read-out leaves the state as it was
+    np.testing.assert_array_equal(g.populations(), f)
+
+
+def test_runs_are_deterministic(schedule):
     case = cases.ragged("mrt", "periodic")
     _say("determinism fp32")
     a = _gpu(case, "fp32", history_cap=150)
@@ -199,12 +222,12 @@ def test_zero_steps_and_state_errors():
         lbm.lbm_step(g.ctx, -1)
 
 
-def test_full_size_c2_steps_against_oracle(bulk_path):
+def test_full_size_c2_steps_against_oracle(schedule):
     # the bench lattice (4096 x 1024, MRT, FP32 offsets) in the bench's launch
     # configuration: both sides start from the same seeded smooth fields and
     # take three steps; every fluid node and the force are compared
     case = cases.c2()
-    _say("c2 full size fp32 mrt", bulk_path)
+    _say("c2 full size fp32 mrt", schedule)
     rho, u = workloads.smooth_fields(case["mask"].shape, case["u_in"], amp=0.02, seed=11)
     g = _gpu(case, "fp32", history_cap=3)
     g.init_fields(rho, u[0], u[1])
@@ -221,12 +244,12 @@ def test_full_size_c2_steps_against_oracle(bulk_path):
     np.testing.assert_allclose(fy, o.fy_hist, rtol=1e-5, atol=1e-7)
 
 
-def test_full_size_steps_with_the_xcd_chunk_mapping(bulk_path):
+def test_full_size_steps_with_the_xcd_chunk_mapping(schedule):
     # a 4096 x 896 channel (the C2 cylinder, 896 rows): its per-XCD bands
     # would be 1.75 MiB of a plane, so the bulk tiles go to the XCDs in
     # chunks of 32 rows (the tail in bands); three steps against the oracle
     case = cases.c2(4096, 896)
-    _say("4096x896 full size fp32 mrt, chunked XCD mapping", bulk_path)
+    _say("4096x896 full size fp32 mrt, chunked XCD mapping", schedule)
     rho, u = workloads.smooth_fields(case["mask"].shape, case["u_in"], amp=0.02, seed=14)
     g = _gpu(case, "fp32", history_cap=3)
     g.init_fields(rho, u[0], u[1])
@@ -243,11 +266,11 @@ def test_full_size_steps_with_the_xcd_chunk_mapping(bulk_path):
     np.testing.assert_allclose(fy, o.fy_hist, rtol=1e-5, atol=1e-7)
 
 
-def test_solid_nodes_survive_read_out(bulk_path):
+def test_solid_nodes_survive_read_out(schedule):
     # a read-out stages through the spare population buffer; the next step
     # must still find the solid nodes' initial equilibrium there
     case = cases.ragged("mrt", "walls")
-    _say("solid nodes after read-out", bulk_path)
+    _say("solid nodes after read-out", schedule)
     g = _gpu(case, "fp32")
     f0 = g.populations()
     solid = case["mask"] != 0

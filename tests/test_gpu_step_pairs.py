@@ -1,16 +1,15 @@
 """GPU parity of the two-steps-per-launch path of the step (the default
-with the Zou & He outflow; LBM_STEP_PAIRS=0 gives one launch per step):
-every node takes the single-step node
-code in registers, compiled into another kernel (the compiler may contract
-multiply-adds differently there), so the populations agree with one launch
-per step to rounding: 1e-12 relative in FP64, 1e-6 absolute in FP32 and
-1e-3 in FP16 offsets after 81 steps; the force and mass partials are summed
-in another grouping, so the force history agrees to 1e-12 of its scale in
-FP64, 1e-5 in FP32 (the single-step path's own bound against the oracle)
-and 1e-3 in FP16 (populations that round to FP16 differently move the
-force by ~1e-4); and against the oracle as the single-step path does.
-Measured: FP64 2.4e-15 (BGK cylinder) and 0 (MRT ragged), FP32 0, FP16
-9e-5 in the populations."""
+with the Zou & He outflow, params.launch = LBM_LAUNCH_PAIRS; LBM_LAUNCH_SINGLE
+gives one launch per step): every node takes the single-step node code in
+registers, compiled into another kernel (the compiler may contract
+multiply-adds differently there), and the state between the two steps is
+rounded to the storage precision as a store and reload would round it, so
+the populations agree with one launch per step to rounding: 1e-12 relative
+in FP64, 1e-6 absolute in FP32 and in FP16 offsets after 81 steps; the force
+and mass partials are summed in another grouping, so the force history
+agrees to 1e-12 of its scale in FP64 and 1e-5 in FP32 and FP16 (the
+single-step path's own bound against the oracle); and against the oracle as
+the single-step path does."""
 import numpy as np
 import pytest
 
@@ -25,16 +24,15 @@ def _say(*a):
     print("[gpu case]", *a, flush=True)
 
 
-def _gpu(case, precision, history_cap):
+def _gpu(case, precision, history_cap, launch="pairs"):
     return lbm.Lattice(case["mask"], case["tau"], precision=precision,
                        collision=case["collision"], lateral=case["lateral"],
                        u_in=case["u_in"], noise_amp=case["noise_amp"], seed=case["seed"],
-                       history_cap=history_cap)
+                       history_cap=history_cap, launch=launch)
 
 
-def _run(case, precision, steps, pairs, monkeypatch, chunks=(None,)):
-    monkeypatch.setenv("LBM_STEP_PAIRS", "1" if pairs else "0")
-    g = _gpu(case, precision, steps)
+def _run(case, precision, steps, pairs, chunks=(None,)):
+    g = _gpu(case, precision, steps, "pairs" if pairs else "single")
     for n in chunks:
         g.step(n if n is not None else steps)
     return g.populations(), g.force_history()
@@ -42,34 +40,34 @@ def _run(case, precision, steps, pairs, monkeypatch, chunks=(None,)):
 
 @pytest.mark.parametrize("name,precision", [("c1_bgk", "fp64"), ("ragged_mrt_periodic", "fp64"),
                                             ("ragged_mrt_walls", "fp32"), ("c1_mrt", "fp16")])
-def test_pairs_equal_single_steps(name, precision, monkeypatch):
+def test_pairs_equal_single_steps(name, precision):
     case = {"c1_bgk": cases.c1(75.0), "ragged_mrt_periodic": cases.ragged("mrt", "periodic"),
             "ragged_mrt_walls": cases.ragged("mrt", "walls"), "c1_mrt": cases.c1(100.0, "mrt")}[name]
     _say("pairs vs single steps", name, precision)
     # odd counts and read-outs in between: pairs, a single step, pairs again
     chunks = (40, 7, 34)
-    f1, (fx1, fy1) = _run(case, precision, 81, True, monkeypatch, chunks)
-    f0, (fx0, fy0) = _run(case, precision, 81, False, monkeypatch, chunks)
+    f1, (fx1, fy1) = _run(case, precision, 81, True, chunks)
+    f0, (fx0, fy0) = _run(case, precision, 81, False, chunks)
     if precision == "fp64":
         fl = case["mask"] == 0
         err = np.max(np.abs(f1[:, fl] - f0[:, fl]) / np.abs(f0[:, fl]))
         bound = 1e-12
     else:
         err = np.max(np.abs(f1 - f0))
-        bound = 1e-6 if precision == "fp32" else 1e-3
+        bound = 1e-6
     print("pairs vs single steps: max difference", err, flush=True)
     assert err < bound
     assert len(fx1) == 81
-    tol = {"fp64": 1e-12, "fp32": 1e-5, "fp16": 1e-3}[precision]
+    tol = {"fp64": 1e-12, "fp32": 1e-5, "fp16": 1e-5}[precision]
     scale = max(np.max(np.abs(fx0)), 1e-9)
     assert np.max(np.abs(fx1 - fx0)) <= tol * scale
     assert np.max(np.abs(fy1 - fy0)) <= tol * max(np.max(np.abs(fy0)), 1e-9) + tol * scale
 
 
-def test_pairs_fp64_against_oracle(monkeypatch):
+def test_pairs_fp64_against_oracle():
     case = cases.c1(75.0)
     _say("pairs c1 fp64 vs oracle, 300 steps")
-    f, (fx, fy) = _run(case, "fp64", 300, True, monkeypatch)
+    f, (fx, fy) = _run(case, "fp64", 300, True)
     o = Oracle(case["mask"], **cases.oracle_kwargs(case))
     o.step(300)
     fl = case["mask"] == 0
@@ -81,12 +79,11 @@ def test_pairs_fp64_against_oracle(monkeypatch):
     np.testing.assert_allclose(fy, o.fy_hist, rtol=1e-10, atol=1e-12)
 
 
-def test_pairs_full_size_c2(monkeypatch):
+def test_pairs_full_size_c2():
     # the bench lattice, FP32 offsets, MRT: four steps (two launches) from
     # the same smooth fields as the oracle
     case = cases.c2()
     _say("pairs c2 full size fp32")
-    monkeypatch.setenv("LBM_STEP_PAIRS", "1")
     rho, u = workloads.smooth_fields(case["mask"].shape, case["u_in"], amp=0.02, seed=17)
     g = _gpu(case, "fp32", 4)
     g.init_fields(rho, u[0], u[1])
