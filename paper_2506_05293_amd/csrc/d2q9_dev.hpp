@@ -63,6 +63,14 @@ template <> struct Store<float> {
   __device__ static void st_cached(float* p, T v) { *p = v; }
   __device__ static T stored(T v) { return v; }
 };
+// FP16 storage rounds the FP32 value the arithmetic left (round to nearest
+// even): to_half keeps the compiler from fusing the multiply-add that made v
+// with the conversion (a mixed-precision FMA rounds once, straight to FP16,
+// and would make one kernel's stored value differ from another's).
+__device__ __forceinline__ __half to_half(float v) {
+  asm volatile("" : "+v"(v));
+  return __float2half_rn(v);
+}
 template <> struct Store<__half> {
   using T = float;
   __device__ static T ld(const __half* p) { return __half2float(*p); }
@@ -71,12 +79,34 @@ template <> struct Store<__half> {
         __builtin_nontemporal_load(reinterpret_cast<const unsigned short*>(p))));
   }
   __device__ static void st(__half* p, T v) {
-    __builtin_nontemporal_store(__half_as_ushort(__float2half_rn(v)),
-                                reinterpret_cast<unsigned short*>(p));
+    __builtin_nontemporal_store(__half_as_ushort(to_half(v)), reinterpret_cast<unsigned short*>(p));
   }
-  __device__ static void st_cached(__half* p, T v) { *p = __float2half_rn(v); }
-  __device__ static T stored(T v) { return __half2float(__float2half_rn(v)); }
+  __device__ static void st_cached(__half* p, T v) { *p = to_half(v); }
+  __device__ static T stored(T v) { return __half2float(to_half(v)); }
 };
+
+// ---- arithmetic shared by every kernel ------------------------------------------
+// The node arithmetic below is written with explicit fused multiply-adds and
+// with contraction switched off, so the compiler cannot fuse a product and a
+// sum differently in different kernels: every kernel that runs these
+// functions (one step per launch, two steps per launch, the batch, the
+// outlet blocks) computes the same IEEE operations on the same values.
+template <typename T>
+__device__ __forceinline__ T fmadd(T a, T b, T c) {
+  if constexpr (sizeof(T) == 8)
+    return __builtin_fma(a, b, c);
+  else
+    return __builtin_fmaf(a, b, c);
+}
+
+// 1 / rho: the hardware reciprocal in FP32 (within 1 ulp), a division in FP64.
+template <typename T>
+__device__ __forceinline__ T inv_rho(T rho) {
+  if constexpr (sizeof(T) == 8)
+    return T(1) / rho;
+  else
+    return __builtin_amdgcn_rcpf(rho);
+}
 
 // ---- moments -----------------------------------------------------------------
 template <typename T>
@@ -86,6 +116,7 @@ struct Macro {
 
 template <typename T>
 __device__ __forceinline__ Macro<T> macro(const T g[9]) {
+#pragma clang fp contract(off)
   Macro<T> m;
   m.drho = ((g[0] + g[2] + g[4]) + (g[1] + g[3])) + ((g[5] + g[7]) + (g[6] + g[8]));
   m.rho = T(1) + m.drho;
@@ -95,17 +126,23 @@ __device__ __forceinline__ Macro<T> macro(const T g[9]) {
 }
 
 // ---- BGK (Eq. 2) in offset form -------------------------------------------------
+// g_eq = w (drho + rho (c.u (3 + 9/2 c.u) - 3/2 u.u)); c.u is a signed sum of
+// u_x and u_y (no products by 0 or 1).
 template <typename T>
 __device__ __forceinline__ void collide_bgk(T g[9], T omega) {
+#pragma clang fp contract(off)
   const Macro<T> m = macro(g);
-  const T inv = T(1) / m.rho;
+  const T inv = inv_rho(m.rho);
   const T ux = m.jx * inv, uy = m.jy * inv;
-  const T usq = T(1.5) * (ux * ux + uy * uy);
+  const T usq = T(1.5) * fmadd(ux, ux, uy * uy);
 #pragma unroll
   for (int q = 0; q < 9; ++q) {
-    const T cu = T(cx(q)) * ux + T(cy(q)) * uy;
-    const T geq = wgt<T>(q) * (m.drho + m.rho * (T(3) * cu + T(4.5) * cu * cu - usq));
-    g[q] = g[q] - omega * (g[q] - geq);
+    const T cu = cx(q) == 0 ? (cy(q) == 0 ? T(0) : (cy(q) > 0 ? uy : -uy))
+                            : (cy(q) == 0 ? (cx(q) > 0 ? ux : -ux)
+                                          : (cx(q) > 0 ? ux : -ux) + (cy(q) > 0 ? uy : -uy));
+    const T poly = q == 0 ? -usq : fmadd(cu, fmadd(T(4.5), cu, T(3)), -usq);
+    const T geq = wgt<T>(q) * fmadd(m.rho, poly, m.drho);
+    g[q] = fmadd(-omega, g[q] - geq, g[q]);
   }
 }
 
@@ -124,35 +161,37 @@ struct MrtRates {
 
 template <typename T>
 __device__ __forceinline__ void collide_mrt(T g[9], const MrtRates<T>& r) {
+#pragma clang fp contract(off)
   const Macro<T> m = macro(g);
-  const T inv = T(1) / m.rho;
-  const T j2 = (m.jx * m.jx + m.jy * m.jy) * inv;
-  const T sa = g[1] + g[2] + g[3] + g[4];
-  const T sd = g[5] + g[6] + g[7] + g[8];
-  const T e = T(-4) * g[0] - sa + T(2) * sd;
-  const T eps = T(4) * g[0] - T(2) * sa + sd;
+  const T inv = inv_rho(m.rho);
+  const T jy2 = m.jy * m.jy;
+  const T j2 = fmadd(m.jx, m.jx, jy2) * inv;
+  const T sa = (g[1] + g[2]) + (g[3] + g[4]);
+  const T sd = (g[5] + g[6]) + (g[7] + g[8]);
+  const T e = fmadd(T(2), sd, fmadd(T(-4), g[0], -sa));
+  const T eps = fmadd(T(4), g[0], fmadd(T(-2), sa, sd));
   const T d57 = g[5] - g[7], d86 = g[8] - g[6], d68 = g[6] - g[8];
-  const T qx = T(2) * (g[3] - g[1]) + d57 + d86;
-  const T qy = T(2) * (g[4] - g[2]) + d57 + d68;
+  const T qx = fmadd(T(2), g[3] - g[1], d57 + d86);
+  const T qy = fmadd(T(2), g[4] - g[2], d57 + d68);
   const T pxx = (g[1] + g[3]) - (g[2] + g[4]);
   const T pxy = (g[5] + g[7]) - (g[6] + g[8]);
-  const T de = r.s_e * (e - (T(-2) * m.drho + T(3) * j2)) * T(1.0 / 36.0);
-  const T dp = r.s_eps * (eps - (m.drho - T(3) * j2)) * T(1.0 / 36.0);
+  const T de = r.s_e * (e - fmadd(T(-2), m.drho, T(3) * j2)) * T(1.0 / 36.0);
+  const T dp = r.s_eps * (eps - fmadd(T(-3), j2, m.drho)) * T(1.0 / 36.0);
   const T dqx = r.s_q * (qx + m.jx) * T(1.0 / 12.0);
   const T dqy = r.s_q * (qy + m.jy) * T(1.0 / 12.0);
-  const T dxx = r.s_nu * (pxx - (m.jx * m.jx - m.jy * m.jy) * inv) * T(0.25);
-  const T dxy = r.s_nu * (pxy - m.jx * m.jy * inv) * T(0.25);
-  const T a = -de - T(2) * dp;          // shared by q = 1..4
-  const T b = T(2) * de + dp;           // shared by q = 5..8
-  g[0] -= T(4) * (dp - de);
-  g[1] -= a - T(2) * dqx + dxx;
-  g[2] -= a - T(2) * dqy - dxx;
-  g[3] -= a + T(2) * dqx + dxx;
-  g[4] -= a + T(2) * dqy - dxx;
-  g[5] -= b + dqx + dqy + dxy;
-  g[6] -= b - dqx + dqy - dxy;
-  g[7] -= b - dqx - dqy + dxy;
-  g[8] -= b + dqx - dqy - dxy;
+  const T dxx = r.s_nu * fmadd(-fmadd(m.jx, m.jx, -jy2), inv, pxx) * T(0.25);
+  const T dxy = r.s_nu * fmadd(-(m.jx * m.jy), inv, pxy) * T(0.25);
+  const T a = fmadd(T(-2), dp, -de);    // shared by q = 1..4
+  const T b = fmadd(T(2), de, dp);      // shared by q = 5..8
+  g[0] = fmadd(T(-4), dp - de, g[0]);
+  g[1] -= fmadd(T(-2), dqx, a) + dxx;
+  g[2] -= fmadd(T(-2), dqy, a) - dxx;
+  g[3] -= fmadd(T(2), dqx, a) + dxx;
+  g[4] -= fmadd(T(2), dqy, a) - dxx;
+  g[5] -= ((b + dqx) + dqy) + dxy;
+  g[6] -= ((b - dqx) + dqy) - dxy;
+  g[7] -= ((b - dqx) - dqy) + dxy;
+  g[8] -= ((b + dqx) - dqy) - dxy;
 }
 
 // ---- Zou & He columns (Sec. 2.2), offsets ----------------------------------------
@@ -163,14 +202,15 @@ __device__ __forceinline__ void collide_mrt(T g[9], const MrtRates<T>& r) {
 //   g8 = g6 - (g4 - g2)/2 + rho u/6.
 template <typename T>
 __device__ __forceinline__ void zouhe_inlet(T g[9], T u) {
+#pragma clang fp contract(off)
   const T d0 = g[0] + g[2] + g[4];
   const T dm = g[3] + g[6] + g[7];
-  const T drho = (d0 + T(2) * dm + u) / (T(1) - u);
+  const T drho = (fmadd(T(2), dm, d0) + u) / (T(1) - u);
   const T ru = (T(1) + drho) * u;
   const T h = T(0.5) * (g[4] - g[2]);
-  g[1] = g[3] + ru * T(2.0 / 3.0);
-  g[5] = g[7] + h + ru * T(1.0 / 6.0);
-  g[8] = g[6] - h + ru * T(1.0 / 6.0);
+  g[1] = fmadd(ru, T(2.0 / 3.0), g[3]);
+  g[5] = fmadd(ru, T(1.0 / 6.0), g[7] + h);
+  g[8] = fmadd(ru, T(1.0 / 6.0), g[6] - h);
 }
 
 // Pressure outlet at x = nx-1, prescribed rho_out and v = 0, unknowns 3, 6, 7:
@@ -179,13 +219,14 @@ __device__ __forceinline__ void zouhe_inlet(T g[9], T u) {
 //   g7 = g5 - (g4 - g2)/2 - rho u/6.
 template <typename T>
 __device__ __forceinline__ void zouhe_outlet(T g[9], T one_minus_rho_out) {
+#pragma clang fp contract(off)
   const T d0 = g[0] + g[2] + g[4];
   const T dp = g[1] + g[5] + g[8];
-  const T ru = d0 + T(2) * dp + one_minus_rho_out;
+  const T ru = fmadd(T(2), dp, d0) + one_minus_rho_out;
   const T h = T(0.5) * (g[4] - g[2]);
-  g[3] = g[1] - ru * T(2.0 / 3.0);
-  g[6] = g[8] + h - ru * T(1.0 / 6.0);
-  g[7] = g[5] - h - ru * T(1.0 / 6.0);
+  g[3] = fmadd(ru, T(-2.0 / 3.0), g[1]);
+  g[6] = fmadd(ru, T(-1.0 / 6.0), g[8] + h);
+  g[7] = fmadd(ru, T(-1.0 / 6.0), g[5] - h);
 }
 
 // Right boundary with a prescribed state (rho, u, v), offset form (drho =
@@ -194,15 +235,16 @@ __device__ __forceinline__ void zouhe_outlet(T g[9], T one_minus_rho_out) {
 // follow from Eqs. 8-10 with the transverse velocity.
 template <typename T>
 __device__ __forceinline__ void outlet_state(T g[9], T drho, T u, T v) {
+#pragma clang fp contract(off)
   const T d0 = g[0] + g[2] + g[4];
   const T dp = g[1] + g[5] + g[8];
-  g[0] += (drho + u + drho * u) - (d0 + T(2) * dp);
+  g[0] += fmadd(drho, u, drho + u) - fmadd(T(2), dp, d0);
   const T rho = T(1) + drho;
   const T ru = rho * u, rv = rho * v;
   const T h = T(0.5) * (g[4] - g[2]);
-  g[3] = g[1] - ru * T(2.0 / 3.0);
-  g[6] = g[8] + h - ru * T(1.0 / 6.0) + T(0.5) * rv;
-  g[7] = g[5] - h - ru * T(1.0 / 6.0) - T(0.5) * rv;
+  g[3] = fmadd(ru, T(-2.0 / 3.0), g[1]);
+  g[6] = fmadd(T(0.5), rv, fmadd(ru, T(-1.0 / 6.0), g[8] + h));
+  g[7] = fmadd(T(-0.5), rv, fmadd(ru, T(-1.0 / 6.0), g[5] - h));
 }
 
 // ---- SplitMix64, counter form ------------------------------------------------------

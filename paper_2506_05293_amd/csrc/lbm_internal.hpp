@@ -90,6 +90,7 @@ struct StepLaunch {
   const MlpDev* mlp;
   const CbcDev* cbc;
   double* cbc_dt;           // [ny][4]: p_t, u_t, v_t of the last step at the outlet
+  double* cbc_dt_w;         // two-step launches: where the launch leaves them
   int outlet;               // OUTLET_NN or OUTLET_CBC when n_nn > 0
   int nx, ny, pitch, nchunk;
   int64_t plane;
@@ -99,7 +100,9 @@ struct StepLaunch {
   int nspecial;         // 1 + kReducers + n_nn rounded up to a multiple of 8
   int nblocks;          // whole grid: nspecial + ntx*nty
   int xcd_chunk;        // bulk tiles per chunk dealt to the XCDs in turn (0: one band each)
-  int pair_nslots;      // two-step launches: waves (slots per step)
+  int pair_nslots;      // two-step launches: waves (slots per step), outlet blocks first
+  int pair_nx;          // two-step launches: columns the bulk strips write
+  int pair_out;         // two-step launches: outlet blocks (0: Zou & He in the strips)
   int nslots;           // partial slots written per step (waves of the
                         // neural and bulk workgroups)
   int xper, yper;
@@ -119,6 +122,10 @@ int64_t build_links(const uint8_t* mask, int nx, int ny, int pitch, int nchunk, 
 hipError_t launch_finalize(const StepLaunch& L, hipStream_t s);
 // Two steps per launch (Zou & He outflow only) and the flush after the last pair.
 int pair_waves(int nx, int ny);
+// Two steps per launch with the neural outlet: outlet blocks for ny rows, and
+// the columns at the outlet they take (the strips take the rest).
+int pair_outlet_blocks(int ny);
+int pair_outlet_cols();
 hipError_t launch_pair(const StepLaunch& L, hipStream_t s);
 hipError_t launch_finalize_pair(const StepLaunch& L, hipStream_t s);
 

@@ -181,6 +181,35 @@ struct alignas(16) NnSmem {
   T prev[kNnRows * 4];                 // g3, g6, g7 and drho at x = L-1
 };
 
+// Eq. 16 at the outlet node: g holds its pulled populations (the unknowns
+// 3, 6, 7 are replaced), o the network's standardised outputs, prev the
+// pre-collision g3, g6, g7 and density offset of column L-1.  The node keeps
+// g_i = f_i(L-1) + s_i, s = o sd_out + mu_out, if every reconstructed
+// population is positive and the density moves by less than mass_bound
+// (FP32 tests); otherwise Zou & He.  Returns true if the reconstruction is
+// kept.
+template <typename T>
+__device__ __forceinline__ bool nn_reconstruct(const MlpDev* __restrict__ w, const float* o,
+                                               const T* prev, T g[9], T one_minus_rho_out) {
+#pragma clang fp contract(off)
+  T r[9];
+#pragma unroll
+  for (int q = 0; q < 9; ++q) r[q] = g[q];
+  r[3] = prev[0] + T(fmaf(o[0], w->sd_out[0], w->mu_out[0]));
+  r[6] = prev[1] + T(fmaf(o[1], w->sd_out[1], w->mu_out[1]));
+  r[7] = prev[2] + T(fmaf(o[2], w->sd_out[2], w->mu_out[2]));
+  const float drg = float(macro(r).drho);
+  const bool ok = float(r[3] + wgt<T>(3)) > 0.f && float(r[6] + wgt<T>(6)) > 0.f &&
+                  float(r[7] + wgt<T>(7)) > 0.f && fabsf(drg - float(prev[3])) < w->mass_bound;
+  if (ok) {
+#pragma unroll
+    for (int q = 0; q < 9; ++q) g[q] = r[q];
+  } else {
+    zouhe_outlet(g, one_minus_rho_out);
+  }
+  return ok;
+}
+
 template <typename S, int MRT>
 __device__ void nn_block(const StepLaunch& L, int nb, NnSmem<typename Store<S>::T>& sm,
                          typename Store<S>::T* part) {
@@ -249,23 +278,8 @@ __device__ void nn_block(const StepLaunch& L, int nb, NnSmem<typename Store<S>::
   // 4. reconstruct the outlet node, fall back to Zou & He, collide, store
   if (k == 3 && active && !(lk & LINK_SOLID)) {
     add_force(lk, g, fx, fy);
-    T r[9];
-#pragma unroll
-    for (int q = 0; q < 9; ++q) r[q] = g[q];
-    r[3] = sm.prev[j * 4 + 0] + T(sm.u.H.o[j * 4 + 0] * w->sd_out[0] + w->mu_out[0]);
-    r[6] = sm.prev[j * 4 + 1] + T(sm.u.H.o[j * 4 + 1] * w->sd_out[1] + w->mu_out[1]);
-    r[7] = sm.prev[j * 4 + 2] + T(sm.u.H.o[j * 4 + 2] * w->sd_out[2] + w->mu_out[2]);
-    const float drg = float(macro(r).drho);
-    const bool ok = float(r[3] + wgt<T>(3)) > 0.f && float(r[6] + wgt<T>(6)) > 0.f &&
-                    float(r[7] + wgt<T>(7)) > 0.f &&
-                    fabsf(drg - float(sm.prev[j * 4 + 3])) < w->mass_bound;
-    if (ok) {
-#pragma unroll
-      for (int q = 0; q < 9; ++q) g[q] = r[q];
-    } else {
-      zouhe_outlet(g, T(L.one_minus_rho_out));
+    if (!nn_reconstruct(w, &sm.u.H.o[j * 4], &sm.prev[j * 4], g, T(L.one_minus_rho_out)))
       nfb = T(1);
-    }
     dm = macro(g).drho;
     collide<T, MRT>(g, L);
     const int64_t row = int64_t(y) * L.pitch + x;
@@ -289,13 +303,19 @@ constexpr int kCbRows = kNnRows + 4;
 constexpr int kCbCols = 3;
 constexpr int kCbUnits = kCbcHidden / kWaves;   // hidden units per wave and row
 
+// LDS of the tuning network evaluated for 64 rows.
+template <typename T>
+struct alignas(16) CbcNetSmem {
+  T feat[kNnRows * kCbcIn];              // network inputs per row
+  T h1[kNnRows * kCbcHidden];            // first hidden layer
+  T ps[kNnRows * kWaves * 2];            // per-wave partial sums of s_0, s_1
+};
+
 template <typename T>
 struct alignas(16) CbcSmem {
   T st[9 * kCbRows * kCbCols];           // A at columns nx-3 .. nx-1, rows y0-2 .. y0+65
   T mo[3 * kCbCols * kCbRows];           // [k][column][row]: drho, u, v
-  T feat[kNnRows * kCbcIn];              // network inputs per row
-  T h1[kNnRows * kCbcHidden];            // first hidden layer
-  T ps[kNnRows * kWaves * 2];            // per-wave partial sums of s_0, s_1
+  CbcNetSmem<T> net;
 };
 
 template <typename T>
@@ -306,15 +326,33 @@ __device__ __forceinline__ T sigmoid_t(T s) {
     return T(1) / (T(1) + expf(-s));
 }
 
-// Gradients (p_x, u_x, v_x, p_y, u_y, v_y) at the outlet node of staged row r:
-// second-order one-sided in x, central in y (periodic rows are staged wrapped).
-template <typename T>
+// Moments (drho, u, v) of the nodes of three consecutive columns c0 .. c0+2
+// of a staged tile src[q][R][C] into mo[k][3][R] (all R rows).
+template <typename T, int R, int C>
+__device__ __forceinline__ void tile_moments(const T* src, int c0, T* mo) {
+#pragma clang fp contract(off)
+  for (int i = threadIdx.x; i < R * 3; i += kBlock) {
+    const int r = i / 3, cc = i - (i / 3) * 3;
+    T g[9];
+#pragma unroll
+    for (int q = 0; q < 9; ++q) g[q] = src[(q * R + r) * C + c0 + cc];
+    const Macro<T> m = macro(g);
+    mo[(0 * 3 + cc) * R + r] = m.drho;
+    mo[(1 * 3 + cc) * R + r] = m.jx / m.rho;
+    mo[(2 * 3 + cc) * R + r] = m.jy / m.rho;
+  }
+}
+
+// Gradients (p_x, u_x, v_x, p_y, u_y, v_y) at the outlet node of row r of a
+// moment tile mo[k][3][R] (columns L-2, L-1, L): second-order one-sided in x,
+// central in y (periodic rows are staged wrapped).
+template <typename T, int R>
 __device__ __forceinline__ void cbc_gradients(const T* mo, int r, T g[6]) {
-  constexpr int R = kCbRows, NC = kCbCols;
+#pragma clang fp contract(off)
   const T cs2 = T(1.0 / 3.0);
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
-    const T* m = mo + k * NC * R;
+    const T* m = mo + k * 3 * R;
     const T gx = T(0.5) * (T(3) * m[2 * R + r] - T(4) * m[R + r] + m[r]);
     const T gy = T(0.5) * (m[2 * R + r + 1] - m[2 * R + r - 1]);
     g[k] = k == 0 ? cs2 * gx : gx;
@@ -325,6 +363,93 @@ __device__ __forceinline__ void cbc_gradients(const T* mo, int r, T g[6]) {
 template <typename T>
 __device__ __forceinline__ T leaky_t(T x, T a) {
   return x > T(0) ? x : a * x;
+}
+
+// The tuning network (Sec. 4.2) on 64 rows, spread over the workgroup:
+// thread j < 64 has written the nine standardised features of row j into
+// net.feat; each wave takes kCbUnits of the hidden units of every row and
+// leaves partial output sums, added in a fixed order.  Every thread calls
+// it (it holds barriers); thread j < 64 gets sigma and kappa_2 of row j.
+template <typename T>
+__device__ __forceinline__ void cbc_network(const CbcDev* __restrict__ c, CbcNetSmem<T>& net,
+                                            T& sigma, T& kappa2) {
+#pragma clang fp contract(off)
+  __syncthreads();
+  const int rr = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const T a = T(c->leaky);
+#pragma unroll 1
+  for (int u = 0; u < kCbUnits; ++u) {
+    const int o = w * kCbUnits + u;
+    T s = T(c->b1[o]);
+#pragma unroll
+    for (int i = 0; i < kCbcIn; ++i) s += T(c->w1[o * kCbcIn + i]) * net.feat[rr * kCbcIn + i];
+    net.h1[rr * kCbcHidden + o] = leaky_t(s, a);
+  }
+  __syncthreads();
+  T p0 = T(0), p1 = T(0);
+#pragma unroll 1
+  for (int u = 0; u < kCbUnits; ++u) {
+    const int o = w * kCbUnits + u;
+    T s = T(c->b2[o]);
+#pragma unroll 4
+    for (int k = 0; k < kCbcHidden; ++k) s += T(c->w2[o * kCbcHidden + k]) * net.h1[rr * kCbcHidden + k];
+    const T h = leaky_t(s, a);
+    p0 += T(c->w3[o]) * h;
+    p1 += T(c->w3[kCbcHidden + o]) * h;
+  }
+  net.ps[(rr * kWaves + w) * 2 + 0] = p0;
+  net.ps[(rr * kWaves + w) * 2 + 1] = p1;
+  __syncthreads();
+  if (threadIdx.x < kNnRows) {
+    const T* q = net.ps + threadIdx.x * kWaves * 2;
+    const T s0 = T(c->b3[0]) + ((q[0] + q[2]) + (q[4] + q[6]));
+    const T s1 = T(c->b3[1]) + ((q[1] + q[3]) + (q[5] + q[7]));
+    sigma = T(c->sigma_scale) * sigmoid_t(s0) + T(c->sigma_shift);
+    kappa2 = T(c->kappa_scale) * sigmoid_t(s1) + T(c->kappa_shift);
+  }
+}
+
+// Network features of one row: the gradients and the previous step's time
+// derivatives (p_t, u_t, v_t), standardised.
+template <typename T>
+__device__ __forceinline__ void cbc_features(const CbcDev* __restrict__ c, const T g[6],
+                                             const T prev[3], T* feat) {
+#pragma clang fp contract(off)
+#pragma unroll
+  for (int i = 0; i < kCbcIn; ++i) {
+    const T f = i < 6 ? g[i] : prev[i - 6];
+    feat[i] = (f - T(c->mu_in[i])) / T(c->sd_in[i]);
+  }
+}
+
+// Eqs. 18-28 at one outlet row: from the gradients g, the state (drho, u, v)
+// and sigma, kappa_2, the LODI time derivatives; returns the new state by
+// forward Euler in st and (p_t, u_t, v_t) in dt.
+template <typename T>
+__device__ __forceinline__ void cbc_lodi(const CbcDev* __restrict__ c, const T g6[6], T drho, T u,
+                                         T v, T sigma, T kappa2, T st[3], T dt[3]) {
+#pragma clang fp contract(off)
+  const T p_x = g6[0], u_x = g6[1], v_x = g6[2], p_y = g6[3], u_y = g6[4], v_y = g6[5];
+  const T cs2 = T(1.0 / 3.0), cs = T(0.57735026918962576451);
+  const T rho = T(1) + drho, p = cs2 * rho;
+  // Eqs. 21-26 (readings: dp/dx in L_1, L_5; du/dy in T_1, T_5)
+  const T L3 = u * v_x;
+  const T L5 = (u + cs) * (p_x + rho * cs * u_x);
+  const T T1 = -(v * p_y + p * v_y - rho * cs * v * u_y);
+  const T T3 = -(v * v_y + p_y / rho);
+  const T T5 = -(v * p_y + p * v_y + rho * cs * v * u_y);
+  // Eqs. 27-28 with T_1,exact = 0
+  const T L1 = sigma * T(c->kappa1_coef) * cs2 * (drho - T(c->rho_inf_m1)) - kappa2 * T1 + T1;
+  // Eqs. 18-20
+  const T rho_t = (-(L5 + L1) + (T5 + T1)) / (T(2) * cs2);
+  const T u_t = (-(L5 - L1) + (T5 - T1)) / (T(2) * rho * cs);
+  const T v_t = -L3 + T3;
+  dt[0] = cs2 * rho_t;
+  dt[1] = u_t;
+  dt[2] = v_t;
+  st[0] = drho + rho_t;
+  st[1] = u + u_t;
+  st[2] = v + v_t;
 }
 
 template <typename S, int MRT>
@@ -349,16 +474,7 @@ __device__ void cbc_block(const StepLaunch& L, int nb, CbcSmem<typename Store<S>
   }
   __syncthreads();
   // 2. the state (drho, u, v) of the staged nodes
-  for (int i = threadIdx.x; i < R * NC; i += kBlock) {
-    const int r = i / NC, cc = i - (i / NC) * NC;
-    T g[9];
-#pragma unroll
-    for (int q = 0; q < 9; ++q) g[q] = sm.st[(q * R + r) * NC + cc];
-    const Macro<T> m = macro(g);
-    sm.mo[(0 * NC + cc) * R + r] = m.drho;
-    sm.mo[(1 * NC + cc) * R + r] = m.jx / m.rho;
-    sm.mo[(2 * NC + cc) * R + r] = m.jy / m.rho;
-  }
+  tile_moments<T, R, NC>(sm.st, 0, sm.mo);
   __syncthreads();
 
   const int j = threadIdx.x;
@@ -370,47 +486,11 @@ __device__ void cbc_block(const StepLaunch& L, int nb, CbcSmem<typename Store<S>
   if (c->has_net) {
     if (j < kNnRows) {
       T g[6];
-      cbc_gradients(sm.mo, j + 2, g);
-      const T prev[3] = {T(dts[0]), T(dts[1]), T(dts[2])};
-#pragma unroll
-      for (int i = 0; i < kCbcIn; ++i) {
-        const T f = i < 6 ? g[i] : (row ? prev[i - 6] : T(0));
-        sm.feat[j * kCbcIn + i] = (f - T(c->mu_in[i])) / T(c->sd_in[i]);
-      }
+      cbc_gradients<T, R>(sm.mo, j + 2, g);
+      const T prev[3] = {row ? T(dts[0]) : T(0), row ? T(dts[1]) : T(0), row ? T(dts[2]) : T(0)};
+      cbc_features(c, g, prev, &sm.net.feat[j * kCbcIn]);
     }
-    __syncthreads();
-    const int rr = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const T a = T(c->leaky);
-#pragma unroll 1
-    for (int u = 0; u < kCbUnits; ++u) {
-      const int o = w * kCbUnits + u;
-      T s = T(c->b1[o]);
-#pragma unroll
-      for (int i = 0; i < kCbcIn; ++i) s += T(c->w1[o * kCbcIn + i]) * sm.feat[rr * kCbcIn + i];
-      sm.h1[rr * kCbcHidden + o] = leaky_t(s, a);
-    }
-    __syncthreads();
-    T p0 = T(0), p1 = T(0);
-#pragma unroll 1
-    for (int u = 0; u < kCbUnits; ++u) {
-      const int o = w * kCbUnits + u;
-      T s = T(c->b2[o]);
-#pragma unroll 4
-      for (int k = 0; k < kCbcHidden; ++k) s += T(c->w2[o * kCbcHidden + k]) * sm.h1[rr * kCbcHidden + k];
-      const T h = leaky_t(s, a);
-      p0 += T(c->w3[o]) * h;
-      p1 += T(c->w3[kCbcHidden + o]) * h;
-    }
-    sm.ps[(rr * kWaves + w) * 2 + 0] = p0;
-    sm.ps[(rr * kWaves + w) * 2 + 1] = p1;
-    __syncthreads();
-    if (j < kNnRows) {
-      const T* q = sm.ps + j * kWaves * 2;
-      const T s0 = T(c->b3[0]) + ((q[0] + q[2]) + (q[4] + q[6]));
-      const T s1 = T(c->b3[1]) + ((q[1] + q[3]) + (q[5] + q[7]));
-      sigma = T(c->sigma_scale) * sigmoid_t(s0) + T(c->sigma_shift);
-      kappa2 = T(c->kappa_scale) * sigmoid_t(s1) + T(c->kappa_shift);
-    }
+    cbc_network(c, sm.net, sigma, kappa2);
   }
 
   // 4. one thread per row: LODI update, reconstruction, collision
@@ -420,28 +500,13 @@ __device__ void cbc_block(const StepLaunch& L, int nb, CbcSmem<typename Store<S>
     const uint32_t lk = L.links[int64_t(y) * L.pitch + x];
     if (!(lk & LINK_SOLID)) {
       const int r = j + 2;
-      T g6[6];
-      cbc_gradients(sm.mo, r, g6);
-      const T p_x = g6[0], u_x = g6[1], v_x = g6[2], p_y = g6[3], u_y = g6[4], v_y = g6[5];
-      const T cs2 = T(1.0 / 3.0), cs = T(0.57735026918962576451);
-      const T drho = sm.mo[(0 * NC + 2) * R + r], u = sm.mo[(1 * NC + 2) * R + r];
-      const T v = sm.mo[(2 * NC + 2) * R + r];
-      const T rho = T(1) + drho, p = cs2 * rho;
-      // Eqs. 21-26 (readings: dp/dx in L_1, L_5; du/dy in T_1, T_5)
-      const T L3 = u * v_x;
-      const T L5 = (u + cs) * (p_x + rho * cs * u_x);
-      const T T1 = -(v * p_y + p * v_y - rho * cs * v * u_y);
-      const T T3 = -(v * v_y + p_y / rho);
-      const T T5 = -(v * p_y + p * v_y + rho * cs * v * u_y);
-      // Eqs. 27-28 with T_1,exact = 0
-      const T L1 = sigma * T(c->kappa1_coef) * cs2 * (drho - T(c->rho_inf_m1)) - kappa2 * T1 + T1;
-      // Eqs. 18-20
-      const T rho_t = (-(L5 + L1) + (T5 + T1)) / (T(2) * cs2);
-      const T u_t = (-(L5 - L1) + (T5 - T1)) / (T(2) * rho * cs);
-      const T v_t = -L3 + T3;
-      dts[0] = double(cs2 * rho_t);
-      dts[1] = double(u_t);
-      dts[2] = double(v_t);
+      T g6[6], nst[3], dt[3];
+      cbc_gradients<T, R>(sm.mo, r, g6);
+      cbc_lodi(c, g6, sm.mo[(0 * NC + 2) * R + r], sm.mo[(1 * NC + 2) * R + r],
+               sm.mo[(2 * NC + 2) * R + r], sigma, kappa2, nst, dt);
+      dts[0] = double(dt[0]);
+      dts[1] = double(dt[1]);
+      dts[2] = double(dt[2]);
       // post-streaming populations of the outlet node
       T g[9];
 #pragma unroll
@@ -451,7 +516,7 @@ __device__ void cbc_block(const StepLaunch& L, int nb, CbcSmem<typename Store<S>
         const int rr = bb ? r : r - cy(q);
         g[q] = sm.st[((bb ? opp(q) : q) * R + rr) * NC + cc];
       }
-      outlet_state(g, drho + rho_t, u + u_t, v + v_t);   // forward Euler, Eq. 29, Eqs. 8-10
+      outlet_state(g, nst[0], nst[1], nst[2]);   // forward Euler, Eq. 29, Eqs. 8-10
       add_force(lk, g, fx, fy);
       dm = macro(g).drho;
       collide<T, MRT>(g, L);
@@ -576,7 +641,7 @@ hipError_t launch_finalize(const StepLaunch& L, hipStream_t s) {
 // both steps (level 1), the one after commits them in order (level 2), as
 // for single steps.
 constexpr int kPairCols = 60;          // output columns per wave
-constexpr int kPairRows = 24;          // output rows per wave (20, 32 and 48 measured slower)
+constexpr int kPairRows = 24;          // output rows per wave
 
 // The value of the lane to the left (lane - 1) or right (lane + 1) by a
 // whole-wave DPP shift (a VALU move; lanes 0 and 63 get no neighbour and are
@@ -598,9 +663,7 @@ __device__ __forceinline__ double lane_shift(double v) {
 }
 
 template <typename T>
-__device__ __forceinline__ void pair_pull(const T lo[9], const T mid[9], const T hi[9], int lane,
-                                          T g[9]) {
-  (void)lane;
+__device__ __forceinline__ void pair_pull(const T lo[9], const T mid[9], const T hi[9], T g[9]) {
 #pragma unroll
   for (int q = 0; q < 9; ++q) {
     const T v = cy(q) == 1 ? lo[q] : (cy(q) == -1 ? hi[q] : mid[q]);
@@ -619,10 +682,14 @@ __device__ __forceinline__ bool pair_node(const StepLaunch& L, uint32_t lk, int 
   // keep g in scratch memory (77 instead of 53 us per step at 4096 x 1024)
 #pragma unroll
   for (int q = 1; q < 9; ++q) g[q] = ((lk >> q) & 1u) ? own[opp(q)] : g[q];
-  if (lk & LINK_INLET)
-    zouhe_inlet(g, L.inlet ? T(L.inlet[y]) : T(L.u_in));
-  else if (lk & LINK_OUTLET)
+  if (lk & LINK_INLET) {
+    // the row's inlet velocity by a scalar load (y is wave-uniform), which
+    // waits on its own counter rather than on the rows in flight
+    using cp = const __attribute__((address_space(4))) double*;
+    zouhe_inlet(g, L.inlet ? T(((cp)(L.inlet))[y]) : T(L.u_in));
+  } else if (lk & LINK_OUTLET) {
     zouhe_outlet(g, T(L.one_minus_rho_out));
+  }
   if (count) {
     add_force(lk, g, fx, fy);
     dm += macro(g).drho;
@@ -631,62 +698,90 @@ __device__ __forceinline__ bool pair_node(const StepLaunch& L, uint32_t lk, int 
   return true;
 }
 
+// The strip of wave `wave` and the column of this lane.
+template <typename S>
+struct PairWave {
+  int lane, y0, ye, nrow;
+  int xl, xs;              // this lane's column, and where it is read
+  uint32_t off;            // byte offset of column xs within a row
+  bool col_in, out_col;
+
+  __device__ PairWave(const StepLaunch& L, int wave) {
+    lane = threadIdx.x & 63;
+    const int nstrip = (L.pair_nx + kPairCols - 1) / kPairCols;
+    const int strip = wave % nstrip, seg = wave / nstrip;
+    const int x0 = strip * kPairCols;
+    y0 = seg * kPairRows;
+    xl = x0 - 2 + lane;
+    xs = xl;
+    if (L.xper) xs = xs < 0 ? xs + L.nx : (xs >= L.nx ? xs - L.nx : xs);
+    else xs = xs < 0 ? 0 : (xs >= L.nx ? L.nx - 1 : xs);
+    off = uint32_t(xs) * uint32_t(sizeof(S));
+    // a lattice node (periodic x: every lane, wrapped); the output columns
+    // are the strip's own, unwrapped
+    col_in = L.xper || (xl >= 0 && xl < L.nx);
+    out_col = lane >= 2 && lane < 2 + kPairCols && xl < L.pair_nx;
+    ye = min(y0 + kPairRows, L.ny);
+    nrow = ye - y0 + 4;
+  }
+
+  __device__ int wrap_row(int y, const StepLaunch& L) const {
+    if (L.yper) return y < 0 ? y + L.ny : (y >= L.ny ? y - L.ny : y);
+    return y < 0 ? 0 : (y >= L.ny ? L.ny - 1 : y);
+  }
+};
+
+// Strip `wave` of the bulk; its partials go to slot `slot`.
+//
+// The walk keeps three rows as read (R0..R2, step t), three rows after the
+// first collision (S0..S2, step t+1) and the next row's loads (P).  Row j
+// is fetched at the top of iteration j - 1 and copied into R2 at the top of
+// iteration j.  Measured alternatives at 4096 x 1024 FP32 (all slower):
+// fetching one row further ahead with a single wait per row (-4 %),
+// holding the step-(t+2) stores for one row (-5 %), rings of 4 to 6 rows
+// unrolled in registers (-8 to -17 %), one scalar flag load per row (-2 %),
+// a separate path for rows without link words (-4 %), strips of 12 to 20
+// rows (-12 to -15 %).
 template <typename S, int MRT>
-__device__ __forceinline__ void pair_strip(const StepLaunch& L, int wave, double* part) {
+__device__ __forceinline__ void pair_strip(const StepLaunch& L, int wave, int slot, double* part) {
   using T = typename Store<S>::T;
-  const int lane = threadIdx.x & 63;
-  const int nstrip = (L.nx + kPairCols - 1) / kPairCols;
-  const int strip = wave % nstrip, seg = wave / nstrip;
-  const int x0 = strip * kPairCols, y0 = seg * kPairRows;
-  const int xl = x0 - 2 + lane;                       // this lane's column
-  int xs = xl;                                        // ... where it is read
-  if (L.xper) xs = xs < 0 ? xs + L.nx : (xs >= L.nx ? xs - L.nx : xs);
-  else xs = xs < 0 ? 0 : (xs >= L.nx ? L.nx - 1 : xs);
-  // a lattice node (periodic x: every lane, wrapped); the output columns are
-  // the strip's own, unwrapped
-  const bool col_in = L.xper || (xl >= 0 && xl < L.nx);
-  const bool out_col = lane >= 2 && lane < 2 + kPairCols && xl < L.nx;
-  const int ye = min(y0 + kPairRows, L.ny);           // end of the output rows
+  const PairWave<S> w(L, wave);
+  const int y0 = w.y0, ye = w.ye, nrow = w.nrow;
+  const bool col_in = w.col_in, out_col = w.out_col;
   const S* __restrict__ A = static_cast<const S*>(L.A);
   S* __restrict__ B = static_cast<S*>(L.B);
   T R0[9], R1[9], R2[9], S0[9], S1[9], S2[9], P[9];
   uint32_t K0 = 0, K1 = 0, K2 = 0, KP = 0;
-  // force and mass in FP64 from the node on: a wave covers ~2000 nodes, and
-  // the drag is a sum with heavy cancellation
   double fxa = 0.0, fya = 0.0, dma = 0.0, fxb = 0.0, fyb = 0.0, dmb = 0.0;
-  const int nrow = ye - y0 + 4;
-  // row yr into P, KP, issued one iteration ahead of its use so that the
-  // loads overlap the collisions
+  // row yr (absolute, may lie outside) into P and its link words into KP
+  // (where the row's 256-column chunk has any)
   auto fetch = [&](int yr) {
-    int ys = yr;
-    if (L.yper) ys = ys < 0 ? ys + L.ny : (ys >= L.ny ? ys - L.ny : ys);
-    else ys = ys < 0 ? 0 : (ys >= L.ny ? L.ny - 1 : ys);
-    const int64_t off = int64_t(ys) * L.pitch + xs;
+    const int ys = w.wrap_row(yr, L);
+    const int64_t row = int64_t(ys) * L.pitch;
 #pragma unroll
-    for (int q = 0; q < 9; ++q) P[q] = Store<S>::ld_nt(A + int64_t(q) * L.plane + off);
+    for (int q = 0; q < 9; ++q) P[q] = ld_at(A + int64_t(q) * L.plane + row, w.off);
     KP = 0;
     const bool row_in = L.yper || (yr >= 0 && yr < L.ny);
-    if (row_in && col_in && L.chunk[ys * L.nchunk + xs / kChunk]) KP = L.links[off];
+    if (row_in && col_in && L.chunk[ys * L.nchunk + w.xs / kChunk]) KP = L.links[row + w.xs];
   };
   fetch(y0 - 2);
   for (int j = 0; j < nrow; ++j) {
-    const int yr = y0 - 2 + j;                        // row taken at this iteration
+    const int yr = y0 - 2 + j;
 #pragma unroll
     for (int q = 0; q < 9; ++q) R2[q] = P[q];
     K2 = KP;
     if (j + 1 < nrow) fetch(yr + 1);
     if (j >= 2) {
-      // step t+1 at row yr - 1
+      // step t+1 at row yr - 1 from rows yr-2 .. yr
       const int y1 = yr - 1;
       const bool in1 = L.yper || (y1 >= 0 && y1 < L.ny);
-      T g[9];
-      pair_pull(R0, R1, R2, lane, g);
       const bool cnt1 = out_col && y1 >= y0 && y1 < ye;
+      T g[9];
+      pair_pull(R0, R1, R2, g);
       T fx1 = T(0), fy1 = T(0), dm1 = T(0);
-      if (!(in1 && col_in && pair_node<T, MRT>(L, K1, y1 < 0 ? y1 + L.ny : (y1 >= L.ny ? y1 - L.ny : y1),
-                                                  R1, g, cnt1, fx1, fy1, dm1))) {
+      if (!(in1 && col_in && pair_node<T, MRT>(L, K1, w.wrap_row(y1, L), R1, g, cnt1, fx1, fy1, dm1))) {
 #pragma unroll
-        for (int q = 0; q < 9; ++q) g[q] = R1[q];    // solid or outside: unchanged
+        for (int q = 0; q < 9; ++q) g[q] = R1[q];   // solid or outside: unchanged
       }
       fxa += double(fx1);
       fya += double(fy1);
@@ -696,15 +791,15 @@ __device__ __forceinline__ void pair_strip(const StepLaunch& L, int wave, double
 #pragma unroll
       for (int q = 0; q < 9; ++q) S2[q] = Store<S>::stored(g[q]);
       if (j >= 4) {
-        // step t+2 at row yr - 2
+        // step t+2 at row yr - 2 (always one of the strip's rows) from the
+        // step-(t+1) rows yr-3 .. yr-1
         const int y2 = yr - 2;
-        pair_pull(S0, S1, S2, lane, g);
-        const bool cnt2 = out_col && y2 >= y0 && y2 < ye;
+        pair_pull(S0, S1, S2, g);
+        const uint32_t o2 = uint32_t(y2) * uint32_t(L.pitch) * uint32_t(sizeof(S)) + w.off;
         T fx2 = T(0), fy2 = T(0), dm2 = T(0);
-        if (cnt2 && pair_node<T, MRT>(L, K0, y2, S1, g, true, fx2, fy2, dm2)) {
-          const int64_t o2 = int64_t(y2) * L.pitch + xs;
+        if (out_col && pair_node<T, MRT>(L, K0, y2, S1, g, true, fx2, fy2, dm2)) {
 #pragma unroll
-          for (int q = 0; q < 9; ++q) Store<S>::st(B + int64_t(q) * L.plane + o2, g[q]);
+          for (int q = 0; q < 9; ++q) st_at(B + int64_t(q) * L.plane, o2, g[q]);
         }
         fxb += double(fx2);
         fyb += double(fy2);
@@ -728,11 +823,416 @@ __device__ __forceinline__ void pair_strip(const StepLaunch& L, int wave, double
   const int n = L.pair_nslots;
   fxa = wave_sum(fxa); fya = wave_sum(fya); dma = wave_sum(dma);
   fxb = wave_sum(fxb); fyb = wave_sum(fyb); dmb = wave_sum(dmb);
-  if (lane == 0) {
-    double* a = part + int64_t(kPartials) * wave;
-    double* b = part + int64_t(kPartials) * (n + wave);
+  if (w.lane == 0) {
+    double* a = part + int64_t(kPartials) * slot;
+    double* b = part + int64_t(kPartials) * (n + slot);
     a[0] = fxa; a[1] = fya; a[2] = dma; a[3] = 0.0;
     b[0] = fxb; b[1] = fyb; b[2] = dmb; b[3] = 0.0;
+  }
+}
+
+// ---- two steps per launch at the neural outlet (Sec. 3.1, Eq. 16) -------------
+// An outlet block takes both steps of the last kOutCols columns (nx-4 .. nx-1)
+// for kOutRows rows y0 .. y0+61; the bulk strips stop at column nx-5.  It
+// stages A_t over columns nx-6 .. nx-1 and rows y0-2 .. y0+63, takes step t+1
+// on columns nx-5 .. nx-1 for rows y0-1 .. y0+62 -- the outlet column
+// through the network on those 64 rows -- then step t+2 on its own columns
+// and rows, the network on its 62 rows.  Every node runs the single-step
+// node code (pull with bounce-back by the link word, force and mass, Eq. 16
+// with its fallback, collision), and the state between the steps is rounded
+// as a store would round it, so the result is that of two single steps.
+constexpr int kOutCols = 4;                 // columns nx-4 .. nx-1
+constexpr int kOutRows = kNnRows - 2;       // rows per outlet block
+constexpr int kSt2Rows = kOutRows + 4;      // staged rows y0-2 .. y0+63
+constexpr int kSt2Cols = kOutCols + 2;      // staged columns nx-6 .. nx-1
+constexpr int kS1Rows = kOutRows + 2;       // step t+1 rows y0-1 .. y0+62
+constexpr int kS1Cols = kOutCols + 1;       // step t+1 columns nx-5 .. nx-1
+static_assert(kS1Rows == kNnRows && kBlock == 4 * kNnRows, "one network tile per step");
+
+template <typename T>
+struct alignas(16) Nn2Smem {
+  union {
+    T st[9 * kSt2Rows * kSt2Cols];   // A_t (dead once step t+1 has pulled it)
+    MlpH H;                          // network activations
+  } u;
+  T s1[9 * kS1Rows * kS1Cols];       // post-collision state of step t+1
+  MlpX X;
+  T prev[kNnRows * 4];               // g3, g6, g7, density offset at x = L-1
+};
+
+// Row y of the lattice for a block row (periodic wrap, or -1 outside walls).
+// A block's rows reach y0 + 63, more than one period when ny < 64.
+__device__ __forceinline__ int block_row(const StepLaunch& L, int y) {
+  if (L.yper) return ((y % L.ny) + L.ny) % L.ny;
+  return (y < 0 || y >= L.ny) ? -1 : y;
+}
+
+// Pull the populations of node (r, c) of a staged tile src[q][R][C] (row
+// and column of the tile), bounce-back by the link word from the node's own
+// values.  Unknowns of the outlet column (source beyond the last staged
+// column) get the node's own value, replaced later.
+template <typename T, int R, int C>
+__device__ __forceinline__ void tile_pull(const T* src, int r, int c, uint32_t lk, T g[9]) {
+#pragma unroll
+  for (int q = 0; q < 9; ++q) {
+    const bool bb = (lk >> q) & 1u;
+    const int cc = bb ? c : c - cx(q);
+    const bool out = cc >= C;
+    const int qq = (bb || out) ? opp(q) : q;
+    g[q] = src[(qq * R + ((bb || out) ? r : r - cy(q))) * C + (out ? c : cc)];
+  }
+}
+
+template <typename S, int MRT>
+__device__ void nn2_block(const StepLaunch& L, int nb, Nn2Smem<typename Store<S>::T>& sm,
+                          double* part, int slot) {
+  using T = typename Store<S>::T;
+  const S* __restrict__ A = static_cast<const S*>(L.A);
+  S* __restrict__ B = static_cast<S*>(L.B);
+  const MlpDev* __restrict__ w = L.mlp;
+  const int y0 = nb * kOutRows;
+  const int xs0 = L.nx - kSt2Cols;           // first staged column
+  const int tid = threadIdx.x;
+  const int j = tid & 63, k = tid >> 6;
+  double fx1 = 0, fy1 = 0, dm1 = 0, nf1 = 0, fx2 = 0, fy2 = 0, dm2 = 0, nf2 = 0;
+
+  // 1. stage A_t[q][y0-2 .. y0+63][nx-6 .. nx-1]
+  for (int i = tid; i < 9 * kSt2Rows * kSt2Cols; i += kBlock) {
+    const int q = i / (kSt2Rows * kSt2Cols);
+    const int rem = i - q * (kSt2Rows * kSt2Cols);
+    const int r = rem / kSt2Cols, c = rem - r * kSt2Cols;
+    int y = y0 - 2 + r;
+    y = L.yper ? (y + 2 * L.ny) % L.ny : min(max(y, 0), L.ny - 1);   // clamped rows: never pulled
+    sm.u.st[i] = Store<S>::ld(A + int64_t(q) * L.plane + int64_t(y) * L.pitch + xs0 + c);
+  }
+  __syncthreads();
+
+  // 2. step t+1 on columns nx-5 .. nx-2 (thread: row y0-1+j, column nx-5+k),
+  // and the pull of the outlet column (threads k = 0)
+  {
+    const int yb = block_row(L, y0 - 1 + j);
+    const int x = L.nx - 5 + k;
+    const uint32_t lk = yb >= 0 ? L.links[int64_t(yb) * L.pitch + x] : LINK_SOLID;
+    const bool own = j >= 1 && j <= kOutRows && y0 - 1 + j < L.ny;   // the block's own rows
+    T g[9];
+    tile_pull<T, kSt2Rows, kSt2Cols>(sm.u.st, j + 1, k + 1, lk, g);
+    const bool live = !(lk & LINK_SOLID);
+    if (k >= 1) {
+      // features of column x = L-1-jc, feature index 9 jc + q
+      const int jc = 3 - k;
+#pragma unroll
+      for (int q = 0; q < 9; ++q)
+        sm.X.x[j * kXPitch + 9 * jc + q] = live ? feature_bf16(w, 9 * jc + q, float(g[q])) : 0;
+      if (k == 3) {
+        sm.prev[j * 4 + 0] = g[3];
+        sm.prev[j * 4 + 1] = g[6];
+        sm.prev[j * 4 + 2] = g[7];
+        sm.prev[j * 4 + 3] = macro(g).drho;
+      }
+    } else {
+#pragma unroll
+      for (int f = 27; f < 32; ++f) sm.X.x[j * kXPitch + f] = 0;
+    }
+    if (live) {
+      if (own && k >= 1) {
+        T fx = T(0), fy = T(0);
+        add_force(lk, g, fx, fy);
+        fx1 += double(fx);
+        fy1 += double(fy);
+        dm1 += double(macro(g).drho);
+      }
+      collide<T, MRT>(g, L);
+    } else {
+#pragma unroll
+      for (int q = 0; q < 9; ++q) g[q] = sm.u.st[(q * kSt2Rows + j + 1) * kSt2Cols + k + 1];
+    }
+#pragma unroll
+    for (int q = 0; q < 9; ++q) sm.s1[(q * kS1Rows + j) * kS1Cols + k] = Store<S>::stored(g[q]);
+  }
+  // the outlet node of row y0-1+j at step t+1: its known populations now
+  uint32_t lko = LINK_SOLID;
+  T go[9];
+  if (k == 0) {
+    const int yb = block_row(L, y0 - 1 + j);
+    lko = yb >= 0 ? L.links[int64_t(yb) * L.pitch + L.nx - 1] : LINK_SOLID;
+    tile_pull<T, kSt2Rows, kSt2Cols>(sm.u.st, j + 1, kSt2Cols - 1, lko, go);
+    if (lko & LINK_SOLID) {
+#pragma unroll
+      for (int q = 0; q < 9; ++q) go[q] = sm.u.st[(q * kSt2Rows + j + 1) * kSt2Cols + kSt2Cols - 1];
+    }
+  }
+  __syncthreads();                      // features, prev; the stage is dead
+  mlp_tile(w, sm.X, sm.u.H);
+  if (k == 0) {
+    const bool own = j >= 1 && j <= kOutRows && y0 - 1 + j < L.ny;
+    if (!(lko & LINK_SOLID)) {
+      T fx = T(0), fy = T(0);
+      if (own) add_force(lko, go, fx, fy);
+      const bool kept = nn_reconstruct(w, &sm.u.H.o[j * 4], &sm.prev[j * 4], go,
+                                       T(L.one_minus_rho_out));
+      if (own) {
+        fx1 += double(fx);
+        fy1 += double(fy);
+        dm1 += double(macro(go).drho);
+        nf1 += kept ? 0.0 : 1.0;
+      }
+      collide<T, MRT>(go, L);
+    }
+#pragma unroll
+    for (int q = 0; q < 9; ++q) sm.s1[(q * kS1Rows + j) * kS1Cols + kS1Cols - 1] = Store<S>::stored(go[q]);
+  }
+  __syncthreads();                      // s1 complete; H read
+
+  // 3. step t+2 on the block's own rows y0 + j (j < 62): columns nx-4 .. nx-2
+  // (k = 0 .. 2), the outlet column (k = 3)
+  const int y = y0 + j;
+  const bool row_ok = j < kOutRows && y < L.ny;
+  const uint32_t lk = row_ok ? L.links[int64_t(y) * L.pitch + L.nx - 4 + k] : LINK_SOLID;
+  T g[9];
+  // rows j >= kOutRows are no output rows: their (unused) pull stays inside s1
+  tile_pull<T, kS1Rows, kS1Cols>(sm.s1, min(j, kOutRows - 1) + 1, k + 1, lk, g);
+  const bool live = row_ok && !(lk & LINK_SOLID);
+  if (k < 3) {
+    const int jc = 2 - k;
+#pragma unroll
+    for (int q = 0; q < 9; ++q)
+      sm.X.x[j * kXPitch + 9 * jc + q] = live ? feature_bf16(w, 9 * jc + q, float(g[q])) : 0;
+    if (k == 2) {
+      sm.prev[j * 4 + 0] = g[3];
+      sm.prev[j * 4 + 1] = g[6];
+      sm.prev[j * 4 + 2] = g[7];
+      sm.prev[j * 4 + 3] = macro(g).drho;
+    }
+    if (live) {
+      T fx = T(0), fy = T(0);
+      add_force(lk, g, fx, fy);
+      fx2 += double(fx);
+      fy2 += double(fy);
+      dm2 += double(macro(g).drho);
+      collide<T, MRT>(g, L);
+      const int64_t row = int64_t(y) * L.pitch + L.nx - 4 + k;
+#pragma unroll
+      for (int q = 0; q < 9; ++q) Store<S>::st(B + int64_t(q) * L.plane + row, g[q]);
+    }
+  } else {
+#pragma unroll
+    for (int f = 27; f < 32; ++f) sm.X.x[j * kXPitch + f] = 0;
+  }
+  __syncthreads();
+  mlp_tile(w, sm.X, sm.u.H);
+  if (k == 3 && live) {
+    T fx = T(0), fy = T(0);
+    add_force(lk, g, fx, fy);
+    const bool kept = nn_reconstruct(w, &sm.u.H.o[j * 4], &sm.prev[j * 4], g,
+                                     T(L.one_minus_rho_out));
+    fx2 += double(fx);
+    fy2 += double(fy);
+    dm2 += double(macro(g).drho);
+    nf2 += kept ? 0.0 : 1.0;
+    collide<T, MRT>(g, L);
+    const int64_t row = int64_t(y) * L.pitch + L.nx - 1;
+#pragma unroll
+    for (int q = 0; q < 9; ++q) Store<S>::st(B + int64_t(q) * L.plane + row, g[q]);
+  }
+  // one slot per wave and step, as the strips
+  const int n = L.pair_nslots;
+  fx1 = wave_sum(fx1); fy1 = wave_sum(fy1); dm1 = wave_sum(dm1); nf1 = wave_sum(nf1);
+  fx2 = wave_sum(fx2); fy2 = wave_sum(fy2); dm2 = wave_sum(dm2); nf2 = wave_sum(nf2);
+  if (j == 0) {
+    double* a = part + int64_t(kPartials) * (slot + k);
+    double* b = part + int64_t(kPartials) * (n + slot + k);
+    a[0] = fx1; a[1] = fy1; a[2] = dm1; a[3] = nf1;
+    b[0] = fx2; b[1] = fy2; b[2] = dm2; b[3] = nf2;
+  }
+}
+
+// ---- two steps per launch at the characteristic outlet (Sec. 4) ----------------
+// The geometry of the neural outlet blocks: own columns nx-4 .. nx-1 and 62
+// rows, A_t staged over columns nx-6 .. nx-1 and rows y0-2 .. y0+63.  Step
+// t+1 runs on columns nx-5 .. nx-1 for rows y0-1 .. y0+62, the outlet column
+// from the LODI update of the moments of A_t; step t+2 on the own columns
+// and rows from the moments of the step-(t+1) state, the network features
+// taking the time derivatives of step t+1 from LDS.  The time derivatives
+// are read from L.cbc_dt (rows of step t) and written to L.cbc_dt_w (own
+// rows of step t+2): neighbouring blocks read the rows this block writes.
+// Periodic laterals (the library rejects walls for this outflow).
+template <typename T>
+struct alignas(16) Cbc2Smem {
+  T st[9 * kSt2Rows * kSt2Cols];     // A_t
+  T s1[9 * kS1Rows * kS1Cols];       // post-collision state of step t+1
+  T mo[3 * 3 * kSt2Rows];            // moments of columns nx-3 .. nx-1 (step t, then t+1)
+  T dt1[kNnRows * 3];                // p_t, u_t, v_t of step t+1 per step-(t+1) row
+  CbcNetSmem<T> net;
+};
+
+template <typename S, int MRT>
+__device__ void cbc2_block(const StepLaunch& L, int nb, Cbc2Smem<typename Store<S>::T>& sm,
+                           double* part, int slot) {
+  using T = typename Store<S>::T;
+  const S* __restrict__ A = static_cast<const S*>(L.A);
+  S* __restrict__ B = static_cast<S*>(L.B);
+  const CbcDev* __restrict__ c = L.cbc;
+  const int y0 = nb * kOutRows;
+  const int xs0 = L.nx - kSt2Cols;
+  const int tid = threadIdx.x;
+  const int j = tid & 63, k = tid >> 6;
+  double fx1 = 0, fy1 = 0, dm1 = 0, fx2 = 0, fy2 = 0, dm2 = 0;
+
+  // 1. stage A_t[q][y0-2 .. y0+63][nx-6 .. nx-1] (rows wrapped)
+  for (int i = tid; i < 9 * kSt2Rows * kSt2Cols; i += kBlock) {
+    const int q = i / (kSt2Rows * kSt2Cols);
+    const int rem = i - q * (kSt2Rows * kSt2Cols);
+    const int r = rem / kSt2Cols, cc = rem - r * kSt2Cols;
+    const int y = (y0 - 2 + r + 2 * L.ny) % L.ny;
+    sm.st[i] = Store<S>::ld(A + int64_t(q) * L.plane + int64_t(y) * L.pitch + xs0 + cc);
+  }
+  __syncthreads();
+  tile_moments<T, kSt2Rows, kSt2Cols>(sm.st, kSt2Cols - 3, sm.mo);
+
+  // 2. step t+1 on columns nx-5 .. nx-2 (thread: row y0-1+j, column nx-5+k)
+  {
+    const int yb = (y0 - 1 + j + L.ny) % L.ny;
+    const int x = L.nx - 5 + k;
+    const uint32_t lk = L.links[int64_t(yb) * L.pitch + x];
+    const bool own = j >= 1 && j <= kOutRows && y0 - 1 + j < L.ny;
+    T g[9];
+    tile_pull<T, kSt2Rows, kSt2Cols>(sm.st, j + 1, k + 1, lk, g);
+    if (!(lk & LINK_SOLID)) {
+      if (own && k >= 1) {
+        T fx = T(0), fy = T(0);
+        add_force(lk, g, fx, fy);
+        fx1 += double(fx);
+        fy1 += double(fy);
+        dm1 += double(macro(g).drho);
+      }
+      collide<T, MRT>(g, L);
+    } else {
+#pragma unroll
+      for (int q = 0; q < 9; ++q) g[q] = sm.st[(q * kSt2Rows + j + 1) * kSt2Cols + k + 1];
+    }
+#pragma unroll
+    for (int q = 0; q < 9; ++q) sm.s1[(q * kS1Rows + j) * kS1Cols + k] = Store<S>::stored(g[q]);
+  }
+  __syncthreads();                      // moments of A_t
+  // the outlet column at step t+1, rows y0-1+j (thread j < 64)
+  T sigma = T(c->sigma), kappa2 = T(c->kappa2);
+  {
+    const int yb = (y0 - 1 + j + L.ny) % L.ny;
+    if (c->has_net) {
+      if (tid < kNnRows) {
+        T g6[6];
+        cbc_gradients<T, kSt2Rows>(sm.mo, j + 1, g6);
+        const double* d = L.cbc_dt + 4 * int64_t(yb);
+        const T prev[3] = {T(d[0]), T(d[1]), T(d[2])};
+        cbc_features(c, g6, prev, &sm.net.feat[j * kCbcIn]);
+      }
+      cbc_network(c, sm.net, sigma, kappa2);
+    }
+    if (tid < kNnRows) {
+      const uint32_t lk = L.links[int64_t(yb) * L.pitch + L.nx - 1];
+      const bool own = j >= 1 && j <= kOutRows && y0 - 1 + j < L.ny;
+      T g[9];
+      tile_pull<T, kSt2Rows, kSt2Cols>(sm.st, j + 1, kSt2Cols - 1, lk, g);
+      if (!(lk & LINK_SOLID)) {
+        const int r = j + 1;
+        T g6[6], nst[3], dt[3];
+        cbc_gradients<T, kSt2Rows>(sm.mo, r, g6);
+        cbc_lodi(c, g6, sm.mo[(0 * 3 + 2) * kSt2Rows + r], sm.mo[(1 * 3 + 2) * kSt2Rows + r],
+                 sm.mo[(2 * 3 + 2) * kSt2Rows + r], sigma, kappa2, nst, dt);
+        sm.dt1[j * 3 + 0] = dt[0];
+        sm.dt1[j * 3 + 1] = dt[1];
+        sm.dt1[j * 3 + 2] = dt[2];
+        outlet_state(g, nst[0], nst[1], nst[2]);
+        if (own) {
+          T fx = T(0), fy = T(0);
+          add_force(lk, g, fx, fy);
+          fx1 += double(fx);
+          fy1 += double(fy);
+          dm1 += double(macro(g).drho);
+        }
+        collide<T, MRT>(g, L);
+      } else {
+#pragma unroll
+        for (int q = 0; q < 9; ++q) g[q] = sm.st[(q * kSt2Rows + j + 1) * kSt2Cols + kSt2Cols - 1];
+        sm.dt1[j * 3 + 0] = sm.dt1[j * 3 + 1] = sm.dt1[j * 3 + 2] = T(0);
+      }
+#pragma unroll
+      for (int q = 0; q < 9; ++q)
+        sm.s1[(q * kS1Rows + j) * kS1Cols + kS1Cols - 1] = Store<S>::stored(g[q]);
+    }
+  }
+  __syncthreads();                      // s1 complete
+  // moments of the step-(t+1) state at columns nx-3 .. nx-1, rows y0-1 .. y0+62
+  tile_moments<T, kS1Rows, kS1Cols>(sm.s1, kS1Cols - 3, sm.mo);
+
+  // 3. step t+2 on the own rows y0 + j (j < 62): columns nx-4 .. nx-2 (k < 3)
+  const int y = y0 + j;
+  const bool row_ok = j < kOutRows && y < L.ny;
+  if (k < 3 && row_ok) {
+    const uint32_t lk = L.links[int64_t(y) * L.pitch + L.nx - 4 + k];
+    if (!(lk & LINK_SOLID)) {
+      T g[9];
+      tile_pull<T, kS1Rows, kS1Cols>(sm.s1, j + 1, k + 1, lk, g);
+      T fx = T(0), fy = T(0);
+      add_force(lk, g, fx, fy);
+      fx2 += double(fx);
+      fy2 += double(fy);
+      dm2 += double(macro(g).drho);
+      collide<T, MRT>(g, L);
+      const int64_t off = int64_t(y) * L.pitch + L.nx - 4 + k;
+#pragma unroll
+      for (int q = 0; q < 9; ++q) Store<S>::st(B + int64_t(q) * L.plane + off, g[q]);
+    }
+  }
+  __syncthreads();                      // moments of step t+1
+  sigma = T(c->sigma);
+  kappa2 = T(c->kappa2);
+  if (c->has_net) {
+    if (tid < kNnRows) {
+      const int r = min(j, kOutRows - 1) + 1;    // rows j >= 62: unused
+      T g6[6];
+      cbc_gradients<T, kS1Rows>(sm.mo, r, g6);
+      const T prev[3] = {sm.dt1[r * 3 + 0], sm.dt1[r * 3 + 1], sm.dt1[r * 3 + 2]};
+      cbc_features(c, g6, prev, &sm.net.feat[j * kCbcIn]);
+    }
+    cbc_network(c, sm.net, sigma, kappa2);
+  }
+  if (tid < kNnRows && row_ok) {
+    const uint32_t lk = L.links[int64_t(y) * L.pitch + L.nx - 1];
+    if (!(lk & LINK_SOLID)) {
+      const int r = j + 1;
+      T g[9], g6[6], nst[3], dt[3];
+      tile_pull<T, kS1Rows, kS1Cols>(sm.s1, r, kS1Cols - 1, lk, g);
+      cbc_gradients<T, kS1Rows>(sm.mo, r, g6);
+      cbc_lodi(c, g6, sm.mo[(0 * 3 + 2) * kS1Rows + r], sm.mo[(1 * 3 + 2) * kS1Rows + r],
+               sm.mo[(2 * 3 + 2) * kS1Rows + r], sigma, kappa2, nst, dt);
+      double* d = L.cbc_dt_w + 4 * int64_t(y);
+      d[0] = double(dt[0]);
+      d[1] = double(dt[1]);
+      d[2] = double(dt[2]);
+      outlet_state(g, nst[0], nst[1], nst[2]);
+      T fx = T(0), fy = T(0);
+      add_force(lk, g, fx, fy);
+      fx2 += double(fx);
+      fy2 += double(fy);
+      dm2 += double(macro(g).drho);
+      collide<T, MRT>(g, L);
+      const int64_t off = int64_t(y) * L.pitch + L.nx - 1;
+#pragma unroll
+      for (int q = 0; q < 9; ++q) Store<S>::st(B + int64_t(q) * L.plane + off, g[q]);
+    } else {
+      double* d = L.cbc_dt_w + 4 * int64_t(y);
+      d[0] = d[1] = d[2] = 0.0;
+    }
+  }
+  const int n = L.pair_nslots;
+  fx1 = wave_sum(fx1); fy1 = wave_sum(fy1); dm1 = wave_sum(dm1);
+  fx2 = wave_sum(fx2); fy2 = wave_sum(fy2); dm2 = wave_sum(dm2);
+  if (j == 0) {
+    double* a = part + int64_t(kPartials) * (slot + k);
+    double* b = part + int64_t(kPartials) * (n + slot + k);
+    a[0] = fx1; a[1] = fy1; a[2] = dm1; a[3] = 0.0;
+    b[0] = fx2; b[1] = fy2; b[2] = dm2; b[3] = 0.0;
   }
 }
 
@@ -766,7 +1266,10 @@ __device__ void pair_level1(const T* __restrict__ part, int r, const StepLaunch&
 
 constexpr int kPairSpecial = (1 + 2 * kReducers + 7) / 8 * 8;
 
-template <typename S, int MRT>
+// OUT: 0 the Zou & He outlet inside the strips; OUTLET_NN or OUTLET_CBC the
+// outlet blocks of the neural or characteristic outflow (the first pair_out
+// workgroups after the reducers).
+template <typename S, int MRT, int OUT>
 __global__ void __launch_bounds__(kBlock) k_step2(const StepLaunch L) {
   const int v = int(blockIdx.x);
   if (v < kPairSpecial) {
@@ -777,9 +1280,26 @@ __global__ void __launch_bounds__(kBlock) k_step2(const StepLaunch L) {
     }
     return;
   }
-  const int wave = (v - kPairSpecial) * kWaves + int(threadIdx.x >> 6);
-  if (wave >= L.pair_nslots) return;                  // whole wave
-  pair_strip<S, MRT>(L, wave, static_cast<double*>(L.part_w));
+  const int b = v - kPairSpecial;
+  double* part = static_cast<double*>(L.part_w);
+  if constexpr (OUT == OUTLET_NN) {
+    if (b < L.pair_out) {
+      __shared__ Nn2Smem<typename Store<S>::T> sm;
+      nn2_block<S, MRT>(L, b, sm, part, b * kWaves);
+      return;
+    }
+  } else if constexpr (OUT == OUTLET_CBC) {
+    if (b < L.pair_out) {
+      __shared__ Cbc2Smem<typename Store<S>::T> sm;
+      cbc2_block<S, MRT>(L, b, sm, part, b * kWaves);
+      return;
+    }
+  }
+  // the wave's slot, held in a scalar register: the strip's rows and
+  // columns are then wave-uniform values and its row addresses scalar
+  const int slot = __builtin_amdgcn_readfirstlane(b * kWaves + int(threadIdx.x >> 6));
+  if (slot >= L.pair_nslots) return;                  // whole wave
+  pair_strip<S, MRT>(L, slot - L.pair_out * kWaves, slot, part);
 }
 
 // Flush after the last pair: level 2 of the pair before, then both steps of
@@ -802,13 +1322,24 @@ __global__ void __launch_bounds__(kBlock) k_finalize2(const StepLaunch L) {
 template <typename S, int MRT>
 static hipError_t launch_pair_t(const StepLaunch& L, hipStream_t s) {
   const int blocks = kPairSpecial + (L.pair_nslots + kWaves - 1) / kWaves;
-  hipLaunchKernelGGL((k_step2<S, MRT>), dim3(blocks), dim3(kBlock), 0, s, L);
+  if (L.pair_out > 0 && L.outlet == OUTLET_NN)
+    hipLaunchKernelGGL((k_step2<S, MRT, OUTLET_NN>), dim3(blocks), dim3(kBlock), 0, s, L);
+  else if (L.pair_out > 0 && L.outlet == OUTLET_CBC)
+    hipLaunchKernelGGL((k_step2<S, MRT, OUTLET_CBC>), dim3(blocks), dim3(kBlock), 0, s, L);
+  else if (L.pair_out == 0)
+    hipLaunchKernelGGL((k_step2<S, MRT, 0>), dim3(blocks), dim3(kBlock), 0, s, L);
+  else
+    return hipErrorInvalidValue;
   return hipGetLastError();
 }
 
 int pair_waves(int nx, int ny) {
   return ((nx + kPairCols - 1) / kPairCols) * ((ny + kPairRows - 1) / kPairRows);
 }
+
+int pair_outlet_blocks(int ny) { return (ny + kOutRows - 1) / kOutRows; }
+
+int pair_outlet_cols() { return kOutCols; }
 
 hipError_t launch_pair(const StepLaunch& L, hipStream_t s) {
   switch (L.precision * 2 + L.collision) {

@@ -30,14 +30,15 @@ __device__ __forceinline__ void collide(T g[9], const P& L) {
 // node in direction -c_q; the link carries 2 f*_qbar (-c_q) into the body.
 template <typename T>
 __device__ __forceinline__ void add_force(uint32_t lk, const T g[9], T& fx, T& fy) {
+#pragma clang fp contract(off)
   const uint32_t fb = (lk >> LINK_FORCE_SHIFT) & 0x1FFu;
   if (fb) {
 #pragma unroll
     for (int q = 1; q < 9; ++q) {
       if ((fb >> q) & 1u) {
         const T f = g[q] + wgt<T>(q);
-        fx -= T(2 * cx(q)) * f;
-        fy -= T(2 * cy(q)) * f;
+        if (cx(q) != 0) fx = fmadd(T(-2 * cx(q)), f, fx);
+        if (cy(q) != 0) fy = fmadd(T(-2 * cy(q)), f, fy);
       }
     }
   }
@@ -176,7 +177,7 @@ template <> struct VecIO<__half> {
   __device__ static void st(__half* p, const float* e) {
     v a;
 #pragma unroll
-    for (int i = 0; i < kV; ++i) a[i] = __half_as_ushort(__float2half_rn(e[i]));
+    for (int i = 0; i < kV; ++i) a[i] = __half_as_ushort(to_half(e[i]));
     st_vec_nt(reinterpret_cast<v*>(p), a);
   }
 };

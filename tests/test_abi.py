@@ -38,12 +38,21 @@ def _params(**kw):
     return p
 
 
+def _plane_bytes(ny, pitch, es):
+    """A population plane's byte stride: ny x pitch elements, padded to lie
+    4352 bytes past a multiple of 64 KiB."""
+    b = ny * pitch * es
+    return b + (4352 - b % 65536) % 65536
+
+
 def test_workspace_size_scales_with_precision():
     b64 = lbm.lbm_workspace_bytes(_params(precision=lbm.LBM_FP64))
     b32 = lbm.lbm_workspace_bytes(_params(precision=lbm.LBM_FP32_OFFSET))
     b16 = lbm.lbm_workspace_bytes(_params(precision=lbm.LBM_FP16_OFFSET))
-    pop32 = 2 * 9 * 80 * 256 * 4        # two buffers, pitch 256
-    assert b64 > b32 > b16 and b32 >= pop32 and b64 - b32 == pop32
+    # two buffers of nine planes, pitch 256; everything else is the same
+    pop = {es: 2 * 9 * _plane_bytes(80, 256, es) for es in (2, 4, 8)}
+    assert b64 > b32 > b16 and b32 >= pop[4]
+    assert b64 - b32 == pop[8] - pop[4] and b32 - b16 == pop[4] - pop[2]
 
 
 @pytest.mark.parametrize("field,value", [("tau", 0.5), ("tau", float("nan")), ("nx", 4),

@@ -169,3 +169,53 @@ def test_cbc_full_size_steps(schedule):
     err = np.max(np.abs(g.populations()[:, fl] - ref[:, fl]))
     print("cbc full-size three-step error", err, flush=True)
     assert err < 2e-6
+
+
+@pytest.mark.parametrize("net", [False, True])
+def test_cbc_pairs_equal_single_steps(net):
+    # two steps per launch at the characteristic outlet: the outlet blocks run
+    # the single-step arithmetic (LODI update, Eq. 29 reconstruction, the
+    # network in FP64) and carry the time derivatives of the first step to
+    # the second in LDS, so both schedules agree to 1e-12 relative in FP64,
+    # over odd counts, read-outs and a lattice shorter than one outlet block
+    _say("cbc pairs vs single steps", "network" if net else "fixed")
+    cbc = dict(FIXED, net=random_net(3)) if net else FIXED
+    mask = geometry.cylinder(61, 43, 14.3, 20.6, 9.0)
+    out = {}
+    for launch in ("pairs", "single"):
+        g = lbm.Lattice(mask, 0.58, precision="fp64", collision="mrt", lateral="periodic",
+                        u_in=0.1, noise_amp=0.0, seed=1, launch=launch, history_cap=81)
+        g.init_fields(*vortex_fields(61, 43, 0.1, 61 - 14.5, 43 / 2 - 0.3))
+        g.set_outflow_cbc(**cbc)
+        for n in (40, 7, 34):
+            g.step(n)
+        out[launch] = (g.populations(), g.force_history()[0])
+    (f1, fx1), (f0, fx0) = out["pairs"], out["single"]
+    err = np.max(np.abs(f1 - f0) / np.abs(f0))
+    print("cbc pairs vs single:", err, flush=True)
+    assert err < 1e-12
+    np.testing.assert_allclose(fx1, fx0, rtol=0, atol=1e-12 * np.max(np.abs(fx0)))
+
+
+def test_cbc_pairs_full_size():
+    # the 4096 x 1024 cylinder lattice with periodic laterals and the
+    # characteristic outlet, FP32, four steps in two launches, against the
+    # oracle from the same seeded smooth fields
+    nx, ny = 4096, 1024
+    mask = geometry.cylinder(nx, ny, 800, ny // 2, 80)
+    tau = 3 * 0.05 * 80 / 200 + 0.5
+    _say("cbc pairs full size 4096x1024 fp32")
+    rho, u = workloads.smooth_fields(mask.shape, 0.05, amp=0.02, seed=14)
+    g = lbm.Lattice(mask, tau, precision="fp32", collision="mrt", lateral="periodic",
+                    u_in=0.05, noise_amp=0.0, launch="pairs")
+    g.init_fields(rho, u[0], u[1])
+    g.set_outflow_cbc(sigma=0.25, kappa2=0.05 / CS, mach=0.05 / CS)
+    g.step(4)
+    o = Oracle(mask, tau, collision="mrt", lateral="periodic", u_in=0.05)
+    o.set_equilibrium(rho, u[0], u[1])
+    o.set_outflow_cbc(sigma=0.25, kappa2=0.05 / CS, mach=0.05 / CS, length=nx)
+    o.step(4)
+    fl = mask == 0
+    err = np.max(np.abs(g.populations()[:, fl] - o.post_collision()[:, fl]))
+    print("cbc pairs full-size four-step error", err, flush=True)
+    assert err < 2e-6

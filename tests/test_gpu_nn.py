@@ -248,3 +248,110 @@ def test_paper_network_equals_its_padded_embedding():
         bad["mu_in"], bad["sd_in"] = np.zeros(28), np.ones(28)
         _lattice_with_net(bad)
     assert e.value.status == lbm.LBM_EINVAL
+
+
+# ---- two steps per launch with the neural outlet ------------------------------
+
+@pytest.mark.parametrize("precision,mass_bound", [("fp64", 1e9), ("fp64", 3e-4), ("fp32", 3e-4)])
+def test_nn_pairs_equal_single_steps(precision, mass_bound):
+    # the outlet blocks of the two-step kernel run the single-step node code
+    # and Eq. 16 with its fallback on the same network tiles, so both
+    # schedules give the same populations (FP64 to 1e-12 relative, FP32 to
+    # 1e-6) and the same fallback counts, over odd counts and read-outs
+    case = cases.ragged("mrt", "periodic")
+    P = _f32(random_params(3, w_scale=0.5, out_sd=2e-4))
+    _say("nn pairs vs single steps", precision, mass_bound)
+    out = {}
+    for launch in ("pairs", "single"):
+        g = lbm.Lattice(case["mask"], case["tau"], precision=precision, collision="mrt",
+                        lateral="periodic", u_in=case["u_in"], noise_amp=case["noise_amp"],
+                        seed=case["seed"], history_cap=81, launch=launch)
+        g.set_outflow_nn(P, mass_bound=mass_bound)
+        for n in (40, 7, 34):
+            g.step(n)
+        out[launch] = (g.populations(), g.forces().n_fallback, g.force_history())
+    f1, n1, (fx1, _) = out["pairs"]
+    f0, n0, (fx0, _) = out["single"]
+    fl = case["mask"] == 0
+    if precision == "fp64":
+        err = np.max(np.abs(f1[:, fl] - f0[:, fl]) / np.abs(f0[:, fl]))
+        bound = 1e-12
+    else:
+        err = np.max(np.abs(f1 - f0))
+        bound = 1e-6
+    print("nn pairs vs single:", err, "fallbacks", n1, n0, flush=True)
+    assert err < bound and n1 == n0
+    if mass_bound < 1:
+        assert 0.1 * 81 * 77 < n0 < 0.9 * 81 * 77      # partial fallback
+    # force partials are summed in another grouping (FP32: the one-step kernel
+    # sums a wave's nodes in FP32 before the FP64 reduction)
+    tol = 1e-12 if precision == "fp64" else 1e-5
+    np.testing.assert_allclose(fx1, fx0, rtol=0, atol=tol * np.max(np.abs(fx0)) + 1e-15)
+
+
+def test_nn_pairs_fp64_300_steps_against_oracle():
+    case = cases.ragged("bgk", "periodic")
+    P = _f32(random_params(3, w_scale=0.5, out_sd=2e-4))
+    _say("nn pairs fp64 vs oracle, 300 steps")
+    g = lbm.Lattice(case["mask"], case["tau"], precision="fp64", collision="bgk",
+                    lateral="periodic", u_in=case["u_in"], noise_amp=case["noise_amp"],
+                    seed=case["seed"], history_cap=300, launch="pairs")
+    g.set_outflow_nn(P, mass_bound=1e9)
+    g.step(300)
+    o = Oracle(case["mask"], **cases.oracle_kwargs(case))
+    o.set_outflow_nn(P, mass_bound=1e9)
+    o.step(300)
+    fl = case["mask"] == 0
+    err = np.max(np.abs(g.populations()[:, fl] - o.post_collision()[:, fl]))
+    print("nn pairs 300-step max abs error", err, flush=True)
+    # corrections are ~2e-4; a BF16 flip moves one by <= 2^-8 of that
+    assert err < 5e-6
+    # the force moves with the populations near the body: 1e-6 of its scale
+    fx, _ = g.force_history()
+    np.testing.assert_allclose(fx, o.fx_hist, rtol=0, atol=1e-6 * np.max(np.abs(o.fx_hist)))
+
+
+def test_nn_pairs_full_size():
+    # the truncated-domain lattice 4096 x 512 (D = 64, periodic laterals,
+    # MRT, FP32) with the neural outflow: four steps in two launches from the
+    # same seeded smooth fields as the oracle
+    nx, ny, D = 4096, 512, 64
+    mask = geometry.cylinder(nx, ny, nx - 1 - 8 * D, ny // 2, D)
+    tau = 3 * 0.05 * D / 200 + 0.5
+    P = _f32(random_params(4, w_scale=0.5, out_sd=2e-4))
+    _say("nn pairs full size 4096x512 fp32")
+    rho, u = workloads.smooth_fields(mask.shape, 0.05, amp=0.02, seed=12)
+    g = lbm.Lattice(mask, tau, precision="fp32", collision="mrt", lateral="periodic",
+                    u_in=0.05, noise_amp=0.0, launch="pairs", history_cap=4)
+    g.init_fields(rho, u[0], u[1])
+    g.set_outflow_nn(P, mass_bound=1e9)
+    g.step(4)
+    o = Oracle(mask, tau, collision="mrt", lateral="periodic", u_in=0.05)
+    o.set_equilibrium(rho, u[0], u[1])
+    o.set_outflow_nn(P, mass_bound=1e9)
+    o.step(4)
+    fl = mask == 0
+    err = np.max(np.abs(g.populations()[:, fl] - o.post_collision()[:, fl]))
+    print("nn pairs full-size four-step error", err, flush=True)
+    assert err < 1e-6
+    fx, fy = g.force_history()
+    np.testing.assert_allclose(fx, o.fx_hist, rtol=1e-5, atol=1e-9)
+
+
+def test_nn_pairs_on_a_lattice_shorter_than_a_third_of_an_outlet_block():
+    # 60 x 20 with periodic laterals: an outlet block's 64 rows wrap round
+    # the lattice more than three times; pairs and single steps agree
+    nx, ny = 60, 20
+    mask = geometry.cylinder(nx, ny, 15, 9.5, 6.0)
+    P = _f32(random_params(8, w_scale=0.5, out_sd=2e-4))
+    _say("nn pairs, 60 x 20 periodic")
+    out = {}
+    for launch in ("pairs", "single"):
+        g = lbm.Lattice(mask, 0.6, precision="fp64", collision="bgk", lateral="periodic",
+                        u_in=0.05, noise_amp=1e-3, seed=3, launch=launch)
+        g.set_outflow_nn(P, mass_bound=1e9)
+        g.step(30)
+        out[launch] = g.populations()
+    fl = mask == 0
+    err = np.max(np.abs(out["pairs"][:, fl] - out["single"][:, fl]) / np.abs(out["single"][:, fl]))
+    assert err < 1e-12, err

@@ -5,15 +5,17 @@ registers, compiled into another kernel (the compiler may contract
 multiply-adds differently there), and the state between the two steps is
 rounded to the storage precision as a store and reload would round it, so
 the populations agree with one launch per step to rounding: 1e-12 relative
-in FP64, 1e-6 absolute in FP32 and in FP16 offsets after 81 steps; the force
-and mass partials are summed in another grouping, so the force history
-agrees to 1e-12 of its scale in FP64 and 1e-5 in FP32 and FP16 (the
-single-step path's own bound against the oracle); and against the oracle as
-the single-step path does."""
+in FP64, 1e-6 absolute in FP32, and in FP16 offsets within two FP16 units
+in the last place at no more than 1e-3 of the values after 81 steps; the
+force and mass partials are summed in another grouping, so the force
+history agrees to 1e-12 of its scale in FP64, 1e-5 in FP32 (the
+single-step path's own bound against the oracle) and 2e-3 in FP16; and
+against the oracle as the single-step path does."""
 import numpy as np
 import pytest
 
 import cases
+from oracle.d2q9 import W
 from oracle.solver import Lattice as Oracle
 from paper_2506_05293_amd import lbm, workloads
 
@@ -52,14 +54,29 @@ def test_pairs_equal_single_steps(name, precision):
         fl = case["mask"] == 0
         err = np.max(np.abs(f1[:, fl] - f0[:, fl]) / np.abs(f0[:, fl]))
         bound = 1e-12
-    else:
+    elif precision == "fp32":
         err = np.max(np.abs(f1 - f0))
         bound = 1e-6
-    print("pairs vs single steps: max difference", err, flush=True)
-    assert err < bound
+    else:
+        # FP16 offsets: both schedules round every step's state to FP16; the
+        # two kernels' FP32 arithmetic may contract a multiply-add
+        # differently, which moves a value across an FP16 rounding boundary
+        # now and then: at most two FP16 units in the last place of the
+        # offset, at no more than 1e-3 of the values (skipping the rounding
+        # between the two steps of a launch moved nearly every value)
+        d = np.abs(f1 - f0)
+        g = np.maximum(np.abs(f1 - W[:, None, None]), np.abs(f0 - W[:, None, None]))
+        ulp = 2.0 ** (np.floor(np.log2(np.maximum(g, 2.0**-14))) - 10)
+        frac = np.mean(d > 0)
+        print("fp16 pairs vs single steps: values that differ", frac, "max ulps",
+              np.max(d / ulp), flush=True)
+        assert frac <= 1e-3
+        err, bound = np.max(d / ulp), 2.0 + 1e-9
     assert len(fx1) == 81
-    tol = {"fp64": 1e-12, "fp32": 1e-5, "fp16": 1e-5}[precision]
+    # force: FP16 flips at a body link move F by ~2 x 2^-15 of a force of ~0.04
+    tol = {"fp64": 1e-12, "fp32": 1e-5, "fp16": 2e-3}[precision]
     scale = max(np.max(np.abs(fx0)), 1e-9)
+    print("force history: max difference / scale", np.max(np.abs(fx1 - fx0)) / scale, flush=True)
     assert np.max(np.abs(fx1 - fx0)) <= tol * scale
     assert np.max(np.abs(fy1 - fy0)) <= tol * max(np.max(np.abs(fy0)), 1e-9) + tol * scale
 
