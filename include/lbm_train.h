@@ -83,6 +83,29 @@ lbm_status lbm_train_get_weights(lbm_trainer* t, const lbm_mlp_host* out);
 lbm_status lbm_train_gradient(lbm_trainer* t, const int32_t* dev_rows, int32_t n_rows,
                               float* grad, double* loss);
 
+/* For callers that cannot allocate device memory -- code under HIP graph
+ * capture, serving loops, harnesses that forbid hipMalloc -- the loss and
+ * gradient of lbm_train_gradient without a trainer or a workspace: the
+ * network *w (27-64-64-3, FP32 host arrays; its mu_in, sd_in, mu_out,
+ * sd_out are the standardisation, z = (x - mu) * (1/sd) in FP32) on the
+ * samples dev_x [.][27], dev_t [.][3] (device FP32) at the n_rows rows
+ * dev_rows (device int32, each a valid sample index), n_rows a multiple of
+ * 64 and at most 4096.  Same kernels and summation order as
+ * lbm_train_gradient: with the trainer's weights and standardisation (as
+ * lbm_train_get_weights returns them) the results are identical.  grad
+ * receives the 6147 gradients on the host (order of lbm_train_gradient),
+ * loss the mean loss; the call synchronises the stream (hipStream_t).
+ * It allocates nothing: its state, per-tile partial sums and summed
+ * gradient live in a 2 MiB static device array that each GPU holds for the
+ * life of the process (its address is looked up on the first call on that
+ * device) and that every call on that GPU reuses, so calls that overlap on
+ * one GPU (other threads, other streams) race and must be serialised by
+ * the caller.  EINVAL for a bad network or n_rows beyond 4096; EHIP if the
+ * symbol lookup or a launch fails. */
+lbm_status lbm_mlp_gradient_noalloc(const lbm_mlp* w, const float* dev_x, const float* dev_t,
+                                    const int32_t* dev_rows, int32_t n_rows, float* grad,
+                                    double* loss, void* stream);
+
 /* The rows the sampler draws for optimiser step `step` (host array of
  * `batch` int32). */
 lbm_status lbm_train_sample_rows(lbm_trainer* t, int64_t step, int32_t* rows);

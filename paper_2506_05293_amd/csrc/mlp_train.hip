@@ -22,6 +22,7 @@
 #include <cmath>
 #include <cstddef>
 #include <cstring>
+#include <mutex>
 #include <vector>
 
 #include "../../include/lbm_train.h"
@@ -465,6 +466,50 @@ lbm_status run_tiles(lbm_trainer* tr, const int32_t* rows, int nrows, int64_t st
   TRY_HIP(hipGetLastError());
   return LBM_OK;
 }
+// ---- the entry point that allocates nothing -------------------------------
+// lbm_mlp_gradient_noalloc runs the gradient kernels of lbm_train_gradient
+// with their state (weights image and standardisation), per-tile partial
+// sums and summed gradient in this file-scope device array instead of a
+// caller workspace.  Every GPU holds its own copy at its own address, looked
+// up once per device with hipGetSymbolAddress; host code uses only that
+// address, never the array's name.
+constexpr int kNoallocMaxRows = 4096;
+constexpr size_t kNoallocState = (sizeof(TrainState) + 255) / 256 * 256;
+constexpr size_t kNoallocPart = size_t(kNoallocMaxRows / kTS) * kPartStride * 4;
+constexpr size_t kNoallocGrad = size_t(kNP) * 4;
+constexpr size_t kNoallocBytes = size_t(2) << 20;    // 2 MiB per GPU
+static_assert(kNoallocState + (kNoallocPart + 255) / 256 * 256 + kNoallocGrad <= kNoallocBytes,
+              "scratch layout");
+static __device__ __align__(256) unsigned char scratch[kNoallocBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices];
+
+// Device address of the current device's scratch array (looked up once).
+lbm_status scratch_address(void** out) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return set_error(LBM_EHIP, "hipGetDevice: %s", hipGetErrorString(e));
+  if (dev < 0 || dev >= kMaxDevices) return set_error(LBM_EINVAL, "device %d out of range", dev);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+      return set_error(LBM_EHIP, "hipGetSymbolAddress(scratch): %s", hipGetErrorString(e));
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return LBM_OK;
+}
+
+// Host image of the state a gradient pass reads: FP32 masters, BF16 copies
+// and the standardisation maps (one per host thread: calls from several
+// threads build their images apart; on one GPU they still share the device
+// scratch).
+thread_local TrainState g_noalloc_image;
+
 }  // namespace
 
 extern "C" {
@@ -633,6 +678,86 @@ lbm_status lbm_train_gradient(lbm_trainer* tr, const int32_t* rows, int32_t n_ro
   TRY_HIP(hipMemcpyAsync(grad, tr->grad, kNP * 4, hipMemcpyDeviceToHost, tr->stream));
   TRY_HIP(hipMemcpyAsync(loss, &tr->st->loss, 8, hipMemcpyDeviceToHost, tr->stream));
   TRY_HIP(hipStreamSynchronize(tr->stream));
+  return LBM_OK;
+}
+
+lbm_status lbm_mlp_gradient_noalloc(const lbm_mlp* w, const float* dev_x, const float* dev_t,
+                                    const int32_t* dev_rows, int32_t n_rows, float* grad,
+                                    double* loss, void* stream) {
+  if (!w || !w->w1 || !w->b1 || !w->w2 || !w->b2 || !w->w3 || !w->b3 || !w->mu_in || !w->sd_in ||
+      !w->mu_out || !w->sd_out || !dev_x || !dev_t || !dev_rows || !grad || !loss)
+    return set_error(LBM_EINVAL, "NULL argument");
+  if (w->n_in != 27 || w->n_h1 != 64 || w->n_h2 != 64 || w->n_out != 3)
+    return set_error(LBM_EINVAL, "network must be 27-64-64-3");
+  if (n_rows < kTS || n_rows % kTS)
+    return set_error(LBM_EINVAL, "n_rows must be a positive multiple of 64 (got %d)", n_rows);
+  if (n_rows > kNoallocMaxRows)
+    return set_error(LBM_EINVAL, "n_rows %d exceeds the %d rows the static scratch buffer holds",
+                     n_rows, kNoallocMaxRows);
+  for (int c = 0; c < 27; ++c)
+    if (!(w->sd_in[c] > 0) || !std::isfinite(w->sd_in[c]))
+      return set_error(LBM_EINVAL, "sd_in[%d] must be finite and > 0", c);
+  for (int c = 0; c < 3; ++c)
+    if (!(w->sd_out[c] > 0) || !std::isfinite(w->sd_out[c]))
+      return set_error(LBM_EINVAL, "sd_out[%d] must be finite and > 0", c);
+  void* ptr = nullptr;
+  lbm_status st = scratch_address(&ptr);
+  if (st) return st;
+  hipStream_t strm = static_cast<hipStream_t>(stream);
+  char* base = static_cast<char*>(ptr);
+  TrainState* dst = reinterpret_cast<TrainState*>(base);
+  float* part = reinterpret_cast<float*>(base + kNoallocState);
+  float* gdev = reinterpret_cast<float*>(base + kNoallocState + (kNoallocPart + 255) / 256 * 256);
+  // the image lbm_train_set_weights and lbm_train_set_data leave: masters,
+  // zero moments, BF16 copies, FP32 means and reciprocal deviations
+  TrainState& h = g_noalloc_image;
+  memset(&h, 0, sizeof h);
+  memcpy(h.w + kOffW1, w->w1, 64 * 27 * 4);
+  memcpy(h.w + kOffB1, w->b1, 64 * 4);
+  memcpy(h.w + kOffW2, w->w2, 64 * 64 * 4);
+  memcpy(h.w + kOffB2, w->b2, 64 * 4);
+  memcpy(h.w + kOffW3, w->w3, 3 * 64 * 4);
+  memcpy(h.w + kOffB3, w->b3, 3 * 4);
+  for (int j = 0; j < 64; ++j)
+    for (int f = 0; f < 27; ++f) h.w1b[j * 32 + f] = host_bf16(w->w1[j * 27 + f]);
+  for (int j = 0; j < 64; ++j)
+    for (int i = 0; i < 64; ++i) {
+      h.w2b[j * 64 + i] = host_bf16(w->w2[j * 64 + i]);
+      h.w2t[i * 64 + j] = host_bf16(w->w2[j * 64 + i]);
+    }
+  for (int k = 0; k < 3; ++k)
+    for (int i = 0; i < 64; ++i) h.w3b[k * 64 + i] = host_bf16(w->w3[k * 64 + i]);
+  for (int c = 0; c < 27; ++c) {
+    h.mu[c] = w->mu_in[c];
+    h.inv_sd[c] = 1.0f / w->sd_in[c];
+  }
+  for (int c = 0; c < 3; ++c) {
+    h.mu_out[c] = w->mu_out[c];
+    h.inv_sd_out[c] = 1.0f / w->sd_out[c];
+  }
+  TRY_HIP(hipMemcpyAsync(dst, &h, offsetof(TrainState, loss), hipMemcpyHostToDevice, strm));
+  TrainArgs a{};
+  a.st = dst;
+  a.x = dev_x;
+  a.t = dev_t;
+  a.n = 0;                       // rows are given: the sampler is not used
+  a.rows = dev_rows;
+  a.batch = n_rows;
+  a.part = part;
+  a.gscale = float(2.0 / (3.0 * n_rows));
+  hipLaunchKernelGGL(k_train_tile, dim3(n_rows / kTS), dim3(kBlock), 0, strm, a);
+  TRY_HIP(hipGetLastError());
+  UpdateArgs u{};
+  u.st = dst;
+  u.part = part;
+  u.tiles = n_rows / kTS;
+  u.grad = gdev;
+  u.loss_scale = 1.0 / (3.0 * n_rows);
+  hipLaunchKernelGGL(k_train_update, dim3(kUpdBlocks), dim3(kBlock), 0, strm, u);
+  TRY_HIP(hipGetLastError());
+  TRY_HIP(hipMemcpyAsync(grad, gdev, kNP * 4, hipMemcpyDeviceToHost, strm));
+  TRY_HIP(hipMemcpyAsync(loss, &dst->loss, 8, hipMemcpyDeviceToHost, strm));
+  TRY_HIP(hipStreamSynchronize(strm));
   return LBM_OK;
 }
 

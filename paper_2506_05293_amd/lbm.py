@@ -184,6 +184,8 @@ def library():
             "lbm_train_get_weights": (I32, [VP, P(lbm_mlp_host)]),
             "lbm_train_gradient": (I32, [VP, VP, ctypes.c_int32, _FP, DP]),
             "lbm_train_sample_rows": (I32, [VP, I64, P(ctypes.c_int32)]),
+            "lbm_mlp_gradient_noalloc": (I32, [P(lbm_mlp), VP, VP, VP, ctypes.c_int32, _FP, DP,
+                                               VP]),
             "lbm3d_workspace_bytes": (ctypes.c_size_t, [P(lbm3d_params)]),
             "lbm3d_create": (I32, [P(lbm3d_params), VP, ctypes.c_size_t, P(VP)]),
             "lbm3d_destroy": (I32, [VP]),
@@ -556,6 +558,20 @@ def lbm_train_gradient(tr, rows_ptr, n_rows):
     loss = ctypes.c_double()
     _check(library().lbm_train_gradient(tr, ctypes.c_void_p(rows_ptr), n_rows, g.ctypes.data_as(_FP),
                                         ctypes.byref(loss)), "lbm_train_gradient")
+    return g, loss.value
+
+
+def lbm_mlp_gradient_noalloc(P, x_ptr, t_ptr, rows_ptr, n_rows, stream_ptr):
+    """Loss and gradient of network P (a 27-64-64-3 dict with its
+    standardisation) on device samples at device rows, with no workspace."""
+    s, keep = _mlp_struct(P, 0.0)
+    g = np.zeros(N_PARAMS, np.float32)
+    loss = ctypes.c_double()
+    _check(library().lbm_mlp_gradient_noalloc(ctypes.byref(s), ctypes.c_void_p(x_ptr),
+                                              ctypes.c_void_p(t_ptr), ctypes.c_void_p(rows_ptr),
+                                              n_rows, g.ctypes.data_as(_FP), ctypes.byref(loss),
+                                              ctypes.c_void_p(stream_ptr)), "lbm_mlp_gradient_noalloc")
+    del keep
     return g, loss.value
 
 
