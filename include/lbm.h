@@ -159,7 +159,9 @@ size_t lbm_workspace_bytes(const lbm_params* p);
 lbm_status lbm_create(const lbm_params* p, void* dev_workspace, size_t bytes,
                       lbm_ctx** out);
 
-/* Release the context (not the workspace, which the caller owns). */
+/* Wait for the work queued on the context's stream, then release the
+ * context (not the workspace, which the caller owns and may free once this
+ * returns).  NULL is a no-op. */
 lbm_status lbm_destroy(lbm_ctx* c);
 
 /* Upload the geometry and initialise the state.  host_mask is ny*nx bytes,

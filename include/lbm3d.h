@@ -72,6 +72,8 @@ size_t lbm3d_workspace_bytes(const lbm3d_params* p);
 
 lbm_status lbm3d_create(const lbm3d_params* p, void* dev_workspace, size_t bytes,
                         lbm3d_ctx** out);
+/* Wait for the context's stream, then release the context (not the
+ * workspace).  NULL is a no-op. */
 lbm_status lbm3d_destroy(lbm3d_ctx* c);
 
 /* Geometry (host nz*ny*nx bytes, copied) and the initial state

@@ -89,6 +89,8 @@ size_t lbm_batch_workspace_bytes(const lbm_batch_params* p, const lbm_batch_latt
  * lbm_set_geometry does (f^eq(1, (u_in, 0) + noise)). */
 lbm_status lbm_batch_create(const lbm_batch_params* p, const lbm_batch_lattice* lat, int32_t n,
                             void* dev_workspace, size_t bytes, lbm_batch** out);
+/* Wait for the batch's stream (a persistent launch included), then release
+ * the batch (not the workspace).  NULL is a no-op. */
 lbm_status lbm_batch_destroy(lbm_batch* b);
 
 /* Advance every live lattice by nsteps (one cooperative launch, or one

@@ -53,6 +53,8 @@ size_t lbm_train_workspace_bytes(const lbm_train_params* p);
 
 lbm_status lbm_train_create(const lbm_train_params* p, void* dev_workspace, size_t bytes,
                             lbm_trainer** out);
+/* Wait for the trainer's stream, then release it (not the workspace).  NULL
+ * is a no-op. */
 lbm_status lbm_train_destroy(lbm_trainer* t);
 
 /* Attach the data (device pointers, kept by reference: they must stay valid

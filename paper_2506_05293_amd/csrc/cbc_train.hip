@@ -1053,6 +1053,7 @@ lbm_status lbm_cbc_train_create(const lbm_cbc_train_params* p, void* ws, size_t 
 
 lbm_status lbm_cbc_train_destroy(lbm_cbc_trainer* t) {
   if (!t) return LBM_OK;
+  (void)hipStreamSynchronize(t->stream);
   if (t->side) {
     (void)hipStreamSynchronize(t->side);
     (void)hipStreamDestroy(t->side);

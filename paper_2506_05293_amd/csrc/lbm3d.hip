@@ -436,6 +436,7 @@ lbm_status lbm3d_create(const lbm3d_params* p, void* ws, size_t bytes, lbm3d_ctx
 }
 
 lbm_status lbm3d_destroy(lbm3d_ctx* c) {
+  if (c) (void)hipStreamSynchronize(c->stream);
   delete c;
   return LBM_OK;
 }

@@ -415,6 +415,7 @@ lbm_status lbm_create(const lbm_params* p, void* dev_workspace, size_t bytes, lb
 }
 
 lbm_status lbm_destroy(lbm_ctx* c) {
+  if (c) (void)hipStreamSynchronize(c->stream);   // queued steps finish first
   delete c;
   return LBM_OK;
 }

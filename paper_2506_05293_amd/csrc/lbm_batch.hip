@@ -658,6 +658,7 @@ lbm_status lbm_batch_create(const lbm_batch_params* p, const lbm_batch_lattice* 
 }
 
 lbm_status lbm_batch_destroy(lbm_batch* b) {
+  if (b) (void)hipStreamSynchronize(b->stream);   // a persistent launch may still run
   delete b;
   return LBM_OK;
 }

@@ -547,6 +547,7 @@ lbm_status lbm_train_create(const lbm_train_params* p, void* ws, size_t bytes, l
 }
 
 lbm_status lbm_train_destroy(lbm_trainer* t) {
+  if (t) (void)hipStreamSynchronize(t->stream);
   delete t;
   return LBM_OK;
 }

@@ -4,8 +4,10 @@ the same names, argument marshalling only.  PyTorch supplies device memory
 library's HIP kernels.  There is no fallback: if the library or a GPU is
 missing, the calls raise.
 """
+import atexit
 import ctypes
 import os
+import weakref
 
 import numpy as np
 
@@ -134,6 +136,15 @@ class LbmError(RuntimeError):
 
 
 _lib = None
+# Native objects still alive; closed at interpreter exit, before torch and the
+# HIP runtime are torn down, so no launch is still running then.
+_live = weakref.WeakSet()
+
+
+@atexit.register
+def _close_live():
+    for obj in list(_live):
+        obj.close()
 
 
 def library():
@@ -463,13 +474,18 @@ class Batch:
         nbytes = lbm_batch_workspace_bytes(self.params, lattices)
         self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=device)
         self.b = lbm_batch_create(self.params, lattices, self.workspace.data_ptr(), nbytes)
+        _live.add(self)
         self.history_cap = history_cap
 
-    def __del__(self):
-        b = getattr(self, "b", None)
-        if b is not None and _lib is not None:
-            _lib.lbm_batch_destroy(b)
-            self.b = None
+    def close(self):
+        """Wait for the queued work and release the native object (also at
+        interpreter exit and on garbage collection)."""
+        h = getattr(self, "b", None)
+        if h is not None and _lib is not None:
+            _lib.lbm_batch_destroy(h)
+        self.b = None
+
+    __del__ = close
 
     def step(self, n=1):
         lbm_batch_step(self.b, n)
@@ -605,14 +621,19 @@ class Trainer:
         nbytes = lbm_train_workspace_bytes(self.params)
         self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=x.device)
         self.tr = lbm_train_create(self.params, self.workspace.data_ptr(), nbytes)
+        _live.add(self)
         lbm_train_set_data(self.tr, self.x.data_ptr(), self.t.data_ptr(), self.x.shape[0])
         self.batch = batch
 
-    def __del__(self):
-        tr = getattr(self, "tr", None)
-        if tr is not None and _lib is not None:
-            _lib.lbm_train_destroy(tr)
-            self.tr = None
+    def close(self):
+        """Wait for the queued work and release the native object (also at
+        interpreter exit and on garbage collection)."""
+        h = getattr(self, "tr", None)
+        if h is not None and _lib is not None:
+            _lib.lbm_train_destroy(h)
+        self.tr = None
+
+    __del__ = close
 
     def set_weights(self, P):
         lbm_train_set_weights(self.tr, P)
@@ -744,14 +765,19 @@ class CbcTrainer:
         nbytes = lbm_cbc_train_workspace_bytes(self.params)
         self.workspace = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
         self.t = lbm_cbc_train_create(self.params, self.workspace.data_ptr(), nbytes)
+        _live.add(self)
         lbm_cbc_train_set_segments(self.t, a0, ref, n_t)
         lbm_cbc_train_set_net(self.t, net)
 
-    def __del__(self):
-        t = getattr(self, "t", None)
-        if t is not None and _lib is not None:
-            _lib.lbm_cbc_train_destroy(t)
-            self.t = None
+    def close(self):
+        """Wait for the queued work and release the native object (also at
+        interpreter exit and on garbage collection)."""
+        h = getattr(self, "t", None)
+        if h is not None and _lib is not None:
+            _lib.lbm_cbc_train_destroy(h)
+        self.t = None
+
+    __del__ = close
 
     def set_net(self, net):
         lbm_cbc_train_set_net(self.t, net)
@@ -862,14 +888,19 @@ class Lattice3D:
         nbytes = lbm3d_workspace_bytes(self.params)
         self.workspace = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
         self.ctx = lbm3d_create(self.params, self.workspace.data_ptr(), nbytes)
+        _live.add(self)
         lbm3d_set_geometry(self.ctx, mask)
         self.history_cap = history_cap
 
-    def __del__(self):
-        c = getattr(self, "ctx", None)
-        if c is not None and _lib is not None:
-            _lib.lbm3d_destroy(c)
-            self.ctx = None
+    def close(self):
+        """Wait for the queued work and release the native object (also at
+        interpreter exit and on garbage collection)."""
+        h = getattr(self, "ctx", None)
+        if h is not None and _lib is not None:
+            _lib.lbm3d_destroy(h)
+        self.ctx = None
+
+    __del__ = close
 
     def init_fields(self, rho, u):
         lbm3d_init_fields(self.ctx, rho, u)
@@ -933,14 +964,19 @@ class Lattice:
         self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=device)
         assert self.workspace.data_ptr() % 256 == 0
         self.ctx = lbm_create(self.params, self.workspace.data_ptr(), nbytes)
+        _live.add(self)
         lbm_set_geometry(self.ctx, mask)
         self.history_cap = history_cap
 
-    def __del__(self):
-        ctx = getattr(self, "ctx", None)
-        if ctx is not None and _lib is not None:
-            _lib.lbm_destroy(ctx)
-            self.ctx = None
+    def close(self):
+        """Wait for the queued work and release the native object (also at
+        interpreter exit and on garbage collection)."""
+        h = getattr(self, "ctx", None)
+        if h is not None and _lib is not None:
+            _lib.lbm_destroy(h)
+        self.ctx = None
+
+    __del__ = close
 
     def step(self, n=1):
         lbm_step(self.ctx, n)
