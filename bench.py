@@ -11,11 +11,12 @@ with the neural outflow active (MLP 27-64-64-3 fused into the step).
 Prints one JSON line.  Usage: python bench.py [--steps K] [--warmup W]
 
 Counter figures for roofline.traffic are taken with rocprofv3 (see
-profiles/step_kernel_4096x1024_traffic.txt for the commands): the HBM
+profiles/step_kernel_<nx>x<ny>_traffic.txt for the commands): the HBM
 counters FETCH_SIZE and WRITE_SIZE of the step kernel, each scaled by what
 the same counter reads for a plain copy of known size (``--calibration-copy``).
-``--write-traffic`` turns those CSV files into that summary, stamped with a
-hash of the kernel sources; traffic is reported only while the hash matches.
+``--write-traffic`` turns those CSV files into that summary (for the lattice
+size given by --nx/--ny), stamped with a hash of the kernel sources; traffic
+is reported only while the hash matches.
 """
 import argparse
 import csv
@@ -34,7 +35,6 @@ sys.path.insert(0, ROOT)
 BYTES_PER_NODE = {"fp64": 144, "fp32": 72, "fp16": 36}   # 9 loads + 9 stores
 HBM_PEAK_GBS = 8000.0
 CSRC = os.path.join(ROOT, "paper_2506_05293_amd", "csrc")
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "step_kernel_4096x1024_traffic.txt")
 RESULTS = os.path.join(ROOT, "results")
 # the Zou & He step runs two lattice steps per launch of this kernel
 STEP_KERNEL, STEPS_PER_LAUNCH = "k_step2<", 2
@@ -73,7 +73,11 @@ def _median_counter(path, name_part):
     return statistics.median(vals)
 
 
-def write_traffic(step_fetch, step_write, copy_fetch, copy_write, command_note):
+def traffic_file(nx, ny):
+    return os.path.join(ROOT, "profiles", f"step_kernel_{nx}x{ny}_traffic.txt")
+
+
+def write_traffic(nx, ny, step_fetch, step_write, copy_fetch, copy_write, command_note):
     """Scale the step kernel's FETCH_SIZE / WRITE_SIZE (KiB per dispatch) by
     the copy's reading of CALIB_BYTES and store bytes per launch."""
     kib = CALIB_BYTES / 1024.0
@@ -87,18 +91,20 @@ def write_traffic(step_fetch, step_write, copy_fetch, copy_write, command_note):
              f"write_bytes_per_launch={write:.0f}",
              f"fetch_scale={f_scale:.4f}", f"write_scale={w_scale:.4f}",
              f"commands={command_note}"]
-    with open(TRAFFIC_FILE, "w") as f:
+    with open(traffic_file(nx, ny), "w") as f:
         f.write("\n".join(lines) + "\n")
     print("\n".join(lines))
 
 
-def stored_traffic():
-    """HBM bytes per lattice step from the counter summary (a launch of the
-    step kernel advances STEPS_PER_LAUNCH steps), or None when the kernel
-    sources changed since the counters were taken."""
-    if not os.path.exists(TRAFFIC_FILE):
+def stored_traffic(nx, ny):
+    """HBM bytes per lattice step of the FP32 nx x ny lattice from its
+    counter summary (a launch of the step kernel advances STEPS_PER_LAUNCH
+    steps), or None when there is none or the kernel sources changed since
+    the counters were taken."""
+    path = traffic_file(nx, ny)
+    if not os.path.exists(path):
         return None
-    kv = dict(l.strip().split("=", 1) for l in open(TRAFFIC_FILE) if "=" in l)
+    kv = dict(l.strip().split("=", 1) for l in open(path) if "=" in l)
     if kv.get("source_hash") != kernel_source_hash() or kv.get("kernel") != STEP_KERNEL:
         return None
     per_launch = float(kv["fetch_bytes_per_launch"]) + float(kv["write_bytes_per_launch"])
@@ -508,7 +514,8 @@ def main():
     if args.calibration_copy:
         return calibration_copy()
     if args.write_traffic:
-        return write_traffic(*args.write_traffic, command_note=os.environ.get("TRAFFIC_NOTE", ""))
+        return write_traffic(args.nx, args.ny, *args.write_traffic,
+                             command_note=os.environ.get("TRAFFIC_NOTE", ""))
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               "(the lattice would shard in x-slabs with a per-step halo exchange)", file=sys.stderr)
@@ -527,9 +534,9 @@ def main():
     nodes = nx * ny
     mlups = nodes / (ms * 1e-3) / 1e6
     spl = STEPS_PER_LAUNCH if args.launch == "pairs" else 1
+    counted = args.precision == "fp32" and spl == STEPS_PER_LAUNCH
     roofline = step_roofline(nodes, ms, spl, args.precision,
-                             stored_traffic() if (nx, ny, args.precision, spl) ==
-                             (4096, 1024, "fp32", STEPS_PER_LAUNCH) else None)
+                             stored_traffic(nx, ny) if counted else None)
 
     nn = None
     if not args.no_nn:
@@ -578,7 +585,8 @@ def main():
                            "population traffic, far above the 256 MB cache",
                "mlups": bx * by / (ms_big * 1e-3) / 1e6, "ms_per_step": ms_big,
                "steps": args.big_steps,
-               "roofline": step_roofline(bx * by, ms_big, spl, args.precision, None)}
+               "roofline": step_roofline(bx * by, ms_big, spl, args.precision,
+                                         stored_traffic(bx, by) if counted else None)}
     torch.cuda.synchronize()
     cbc_training = None if args.no_cbc_train else time_cbc_training(torch)
     d3q19 = None if args.no_3d else time_d3q19(torch)
