@@ -291,6 +291,7 @@ struct lbm_ctx {
     L.pair_out = n_nn ? pair_outlet_blocks(p.ny) : 0;
     L.pair_nx = L.pair_out ? p.nx - pair_outlet_cols() : p.nx;
     L.pair_nslots = pair_waves(L.pair_nx, p.ny) + L.pair_out * kWaves;
+    L.pair_chunk = pair_chunk(L.pair_nx);
     L.nslots = (L.nspecial - 1 - kReducers + lay.ntx * lay.nty) * kWaves;
     L.xper = p.xbc == LBM_X_PERIODIC;
     L.yper = p.lateral == LBM_LATERAL_PERIODIC;

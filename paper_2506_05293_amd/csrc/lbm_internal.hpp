@@ -103,6 +103,7 @@ struct StepLaunch {
   int pair_nslots;      // two-step launches: waves (slots per step), outlet blocks first
   int pair_nx;          // two-step launches: columns the bulk strips write
   int pair_out;         // two-step launches: outlet blocks (0: Zou & He in the strips)
+  int pair_chunk;       // two-step launches: strip workgroups per chunk dealt to an XCD (0: eighths)
   int nslots;           // partial slots written per step (waves of the
                         // neural and bulk workgroups)
   int xper, yper;
@@ -125,6 +126,8 @@ int pair_waves(int nx, int ny);
 // Two steps per launch with the neural outlet: outlet blocks for ny rows, and
 // the columns at the outlet they take (the strips take the rest).
 int pair_outlet_blocks(int ny);
+// Strip workgroups per chunk dealt to the XCDs in turn (0: one eighth each).
+int pair_chunk(int pair_nx);
 int pair_outlet_cols();
 hipError_t launch_pair(const StepLaunch& L, hipStream_t s);
 hipError_t launch_finalize_pair(const StepLaunch& L, hipStream_t s);

@@ -740,8 +740,9 @@ struct PairWave {
 // fetching one row further ahead with a single wait per row (-4 %),
 // holding the step-(t+2) stores for one row (-5 %), rings of 4 to 6 rows
 // unrolled in registers (-8 to -17 %), one scalar flag load per row (-2 %),
-// a separate path for rows without link words (-4 %), strips of 12 to 20
-// rows (-12 to -15 %).  Loads and stores take the default cache policy: the
+// a separate path for rows without link words (-4 %; +6 % at 16384 x 4096),
+// FP32 sums of the strip's force terms (+1 %), strips of 12 to 20 rows
+// (-12 to -15 %).  Loads and stores take the default cache policy: the
 // strips' halo rows and their partly shared 128-byte lines are then found
 // in the caches (non-temporal loads and stores: 88 against 100 thousand
 // MLUPS at 4096 x 1024 and 78 against 107 at 16384 x 4096; non-temporal
@@ -1305,9 +1306,14 @@ __global__ void __launch_bounds__(kBlock) k_step2(const StepLaunch L) {
       return;
     }
   }
+  // strip workgroups dealt to the XCDs: chunks of pair_chunk workgroups in
+  // turn, or one contiguous eighth per XCD (pair_chunk 0)
+  int sb = b - L.pair_out;
+  const int nsb = int(gridDim.x) - kPairSpecial - L.pair_out;
+  sb = L.pair_chunk > 0 ? xcd_remap_chunks(sb, nsb, L.pair_chunk) : xcd_remap(sb, nsb);
   // the wave's slot, held in a scalar register: the strip's rows and
   // columns are then wave-uniform values and its row addresses scalar
-  const int slot = __builtin_amdgcn_readfirstlane(b * kWaves + int(threadIdx.x >> 6));
+  const int slot = __builtin_amdgcn_readfirstlane((L.pair_out + sb) * kWaves + int(threadIdx.x >> 6));
   if (slot >= L.pair_nslots) return;                  // whole wave
   pair_strip<S, MRT>(L, slot - L.pair_out * kWaves, slot, part);
 }
@@ -1348,6 +1354,18 @@ int pair_waves(int nx, int ny) {
 }
 
 int pair_outlet_blocks(int ny) { return (ny + kOutRows - 1) / kOutRows; }
+
+// Strip workgroups are dealt to the XCDs in chunks of one band (the
+// workgroups of one row of strips), XCD x taking chunks x, x + 8, ...: the
+// lines that x-adjacent strips share then meet in one L2.  Against dispatch
+// order (MLUPS, FP32): 4096 x 1024 99.0k -> 102.4k, 4096 x 2048 84.8k ->
+// 89.3k, 8192 x 2048 97.7k -> 104.5k, 16384 x 4096 107.6k -> 110.8k; FP16 and
+// FP64 at 4096 x 1024 +1 %.  Chunks of two or four bands and one contiguous
+// eighth per XCD were within 2 % of it (eighths 1 % ahead at 16384 x 4096
+// and 3 % in FP64, 1-2 % behind elsewhere).
+int pair_chunk(int pair_nx) {
+  return ((pair_nx + kPairCols - 1) / kPairCols + kWaves - 1) / kWaves;
+}
 
 int pair_outlet_cols() { return kOutCols; }
 
