@@ -155,7 +155,8 @@ Layout make_layout(const lbm_params& p) {
   L.nslots_max = (L.nn_max + 8 + L.ntx * L.nty) * kWaves;   // + padding to a multiple of 8
   // two-step launches write two steps' slots (outlet blocks included)
   L.nslots_max = std::max(L.nslots_max,
-                          2 * (pair_waves(p.nx, p.ny) + pair_outlet_blocks(p.ny) * kWaves));
+                          2 * (pair_waves(p.nx, p.ny, pair_rows(p.nx, p.ny, L.pitch * int(elem_size(p.precision)))) +
+                               pair_outlet_blocks(p.ny) * kWaves));
   L.plane = padded_plane(int64_t(p.ny) * L.pitch, elem_size(p.precision));
   const size_t pop = size_t(9) * size_t(L.plane) * elem_size(p.precision);
   size_t o = 0;
@@ -290,7 +291,8 @@ struct lbm_ctx {
     // columns and come first; the strips take the other columns
     L.pair_out = n_nn ? pair_outlet_blocks(p.ny) : 0;
     L.pair_nx = L.pair_out ? p.nx - pair_outlet_cols() : p.nx;
-    L.pair_nslots = pair_waves(L.pair_nx, p.ny) + L.pair_out * kWaves;
+    L.pair_rows = pair_rows(p.nx, p.ny, lay.pitch * int(elem_size(p.precision)));
+    L.pair_nslots = pair_waves(L.pair_nx, p.ny, L.pair_rows) + L.pair_out * kWaves;
     L.pair_chunk = pair_chunk(L.pair_nx);
     L.nslots = (L.nspecial - 1 - kReducers + lay.ntx * lay.nty) * kWaves;
     L.xper = p.xbc == LBM_X_PERIODIC;

@@ -104,6 +104,7 @@ struct StepLaunch {
   int pair_nx;          // two-step launches: columns the bulk strips write
   int pair_out;         // two-step launches: outlet blocks (0: Zou & He in the strips)
   int pair_chunk;       // two-step launches: strip workgroups per chunk dealt to an XCD (0: eighths)
+  int pair_rows;        // two-step launches: output rows per strip
   int nslots;           // partial slots written per step (waves of the
                         // neural and bulk workgroups)
   int xper, yper;
@@ -122,7 +123,10 @@ int64_t build_links(const uint8_t* mask, int nx, int ny, int pitch, int nchunk, 
                     bool yper, uint32_t* links, uint8_t* chunk);
 hipError_t launch_finalize(const StepLaunch& L, hipStream_t s);
 // Two steps per launch (Zou & He outflow only) and the flush after the last pair.
-int pair_waves(int nx, int ny);
+int pair_waves(int nx, int ny, int rows);
+// Output rows per strip of the two-step kernel for an nx x ny lattice whose
+// rows are pitch_bytes apart.
+int pair_rows(int nx, int ny, int pitch_bytes);
 // Two steps per launch with the neural outlet: outlet blocks for ny rows, and
 // the columns at the outlet they take (the strips take the rest).
 int pair_outlet_blocks(int ny);

@@ -626,9 +626,9 @@ hipError_t launch_finalize(const StepLaunch& L, hipStream_t s) {
 }
 
 // ---- two steps per launch (Zou & He outflow) --------------------------------------
-// Every wave owns a strip of kPairCols columns and kPairRows rows and takes
+// Every wave owns a strip of kPairCols columns and pair_rows rows and takes
 // both steps t+1 and t+2 of it in registers: lane l holds column x0 - 2 + l
-// and walks down rows y0 - 2 .. y0 + kPairRows + 1, keeping the last three
+// and walks down rows y0 - 2 .. y0 + pair_rows + 1, keeping the last three
 // rows as read (step t) and the last three rows after the first collision
 // (step t+1); each node pulls from the rows above and below in its window
 // and from the neighbouring columns by lane shuffles, so a pair of steps
@@ -641,7 +641,6 @@ hipError_t launch_finalize(const StepLaunch& L, hipStream_t s) {
 // both steps (level 1), the one after commits them in order (level 2), as
 // for single steps.
 constexpr int kPairCols = 60;          // output columns per wave
-constexpr int kPairRows = 24;          // output rows per wave
 
 // The value of the lane to the left (lane - 1) or right (lane + 1) by a
 // whole-wave DPP shift (a VALU move; lanes 0 and 63 get no neighbour and are
@@ -711,7 +710,7 @@ struct PairWave {
     const int nstrip = (L.pair_nx + kPairCols - 1) / kPairCols;
     const int strip = wave % nstrip, seg = wave / nstrip;
     const int x0 = strip * kPairCols;
-    y0 = seg * kPairRows;
+    y0 = seg * L.pair_rows;
     xl = x0 - 2 + lane;
     xs = xl;
     if (L.xper) xs = xs < 0 ? xs + L.nx : (xs >= L.nx ? xs - L.nx : xs);
@@ -721,7 +720,7 @@ struct PairWave {
     // are the strip's own, unwrapped
     col_in = L.xper || (xl >= 0 && xl < L.nx);
     out_col = lane >= 2 && lane < 2 + kPairCols && xl < L.pair_nx;
-    ye = min(y0 + kPairRows, L.ny);
+    ye = min(y0 + L.pair_rows, L.ny);
     nrow = ye - y0 + 4;
   }
 
@@ -736,13 +735,13 @@ struct PairWave {
 // The walk keeps three rows as read (R0..R2, step t), three rows after the
 // first collision (S0..S2, step t+1) and the next row's loads (P).  Row j
 // is fetched at the top of iteration j - 1 and copied into R2 at the top of
-// iteration j.  Measured alternatives at 4096 x 1024 FP32 (all slower):
-// fetching one row further ahead with a single wait per row (-4 %),
-// holding the step-(t+2) stores for one row (-5 %), rings of 4 to 6 rows
-// unrolled in registers (-8 to -17 %), one scalar flag load per row (-2 %),
-// a separate path for rows without link words (-4 %; +6 % at 16384 x 4096),
-// FP32 sums of the strip's force terms (+1 %), strips of 12 to 20 rows
-// (-12 to -15 %).  Loads and stores take the default cache policy: the
+// iteration j.  Measured alternatives at 4096 x 1024 FP32 with 24-row
+// strips (not kept): fetching one row further ahead with a single wait per
+// row (-4 %), holding the step-(t+2) stores for one row (-5 %), rings of 4
+// to 6 rows unrolled in registers (-8 to -17 %), one scalar flag load per
+// row (-2 %), a separate path for rows without link words (-4 %; +6 % at
+// 16384 x 4096), FP32 sums of the strip's force terms (+1 %).  The strip
+// height is chosen per lattice (pair_rows).  Loads and stores take the default cache policy: the
 // strips' halo rows and their partly shared 128-byte lines are then found
 // in the caches (non-temporal loads and stores: 88 against 100 thousand
 // MLUPS at 4096 x 1024 and 78 against 107 at 16384 x 4096; non-temporal
@@ -1349,8 +1348,30 @@ static hipError_t launch_pair_t(const StepLaunch& L, hipStream_t s) {
   return hipGetLastError();
 }
 
-int pair_waves(int nx, int ny) {
-  return ((nx + kPairCols - 1) / kPairCols) * ((ny + kPairRows - 1) / kPairRows);
+int pair_waves(int nx, int ny, int rows) {
+  return ((nx + kPairCols - 1) / kPairCols) * ((ny + rows - 1) / rows);
+}
+
+// Output rows per strip.  The shortest strips (least halo per wave is the
+// longest) that keep the grid within four waves per SIMD (4096 waves: all
+// resident at once with room to spare), between 12 and 18 rows; a height
+// above 12 whose band stride (rows x row bytes) is a multiple of 64 KiB is
+// moved by one row, since bands that start on such strides met the same
+// HBM channels (4096 x 1024 FP32: 16 rows 104.9k, 18 rows 111.7k MLUPS).
+// Measured against fixed heights (MLUPS, FP32): 4096 x 1024 18 rows 111.7k
+// (24: 102.2k, best of 12-24); 4096 x 512 12 rows 114.1k (24: 79.7k);
+// 6144 x 512 14 rows 131.3k (24: 106.1k); 3072 x 1024 14 rows 131.8k;
+// 2048 x 2048 18 rows 108.8k; 8192 x 2048 17 rows 106.7k (12: 109.2k);
+// 16384 x 4096 17 rows 114.0k (16: 115.0k, 24: 110.6k); FP16 4096 x 1024
+// 143.7k (24: 127.6k); FP64 4096 x 1024 52.2k (24: 53.2k).
+constexpr int kPairRowsMin = 12, kPairRowsMax = 18;
+int pair_rows(int nx, int ny, int pitch_bytes) {
+  const int strips = (nx + kPairCols - 1) / kPairCols;
+  const int bands = std::max(1, 4 * 1024 / strips);
+  int rows = std::min(std::max((ny + bands - 1) / bands, kPairRowsMin), kPairRowsMax);
+  if (rows > kPairRowsMin && (int64_t(rows) * pitch_bytes) % 65536 == 0)
+    rows += rows < kPairRowsMax ? 1 : -1;
+  return rows;
 }
 
 int pair_outlet_blocks(int ny) { return (ny + kOutRows - 1) / kOutRows; }

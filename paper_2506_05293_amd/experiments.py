@@ -188,32 +188,61 @@ def train_network(x, t, n_in=27, hidden=64, steps=20_000, batch=4096, lr=1e-3, s
 
 
 def outflow_study(networks, re_list=(100.0, 200.0, 400.0), steps=150_000, mass_bound=1e-2,
-                  sweep=(8, 12, 16, 24, 32), reference_d=40, progress=_noop, nn_switch=0):
+                  sweep=(8, 12, 16, 24, 32), reference_d=40, progress=_noop, nn_switch=0,
+                  seeds=(2,)):
     """Truncated cylinder lattices (D = 64, 8 D downstream) with each neural
     outflow of `networks` (name -> weights) and with Zou & He, against the
     40 D Zou & He reference; Zou & He length sweep for the cost of an answer
-    of equal accuracy.  `progress(name, res)` is called after each case."""
+    of equal accuracy.  Every case runs once per seed of the initial noise;
+    each run is compared with the reference of the same seed, and the
+    relative errors are given per seed and as mean and sample standard
+    deviation over the seeds (the reference's own spread over seeds is the
+    averaging uncertainty of the statistics window).  `progress(name, res)`
+    is called after each run."""
     out = {}
     for re in re_list:
-        ref = run_case(workloads.truncated_cylinder(reference_d, re=re), steps)
-        progress(f"Re {re:g} reference {reference_d} D", ref)
-        nn = {}
-        for name, P in networks.items():
-            nn[name] = run_case(workloads.truncated_cylinder(8, re=re), steps, network=P,
-                                mass_bound=mass_bound, nn_switch=nn_switch)
-            progress(f"Re {re:g} neural {name} 8 D", nn[name])
-        zh = {}
-        for d in sweep:
-            zh[d] = run_case(workloads.truncated_cylinder(d, re=re), steps)
-            progress(f"Re {re:g} Zou-He {d} D", zh[d])
-        errs = {f"nn_{k}_8d": observables.relative_errors(r, ref) if "st" in r else None
-                for k, r in nn.items()}
-        for d, r in zh.items():
-            errs[f"zh_{d}d"] = observables.relative_errors(r, ref) if "st" in r else None
-        runs = {**{f"nn_{k}_8d": r for k, r in nn.items()},
-                **{f"zh_{d}d": r for d, r in zh.items()}}
-        out[re] = {"reference": ref, "neural_8d": nn, "zouhe": zh, "rel_err": errs,
-                   "cost": answer_cost(runs, errs, ref)}
+        refs = {}
+        runs = {f"nn_{k}_8d": {} for k in networks}
+        runs.update({f"zh_{d}d": {} for d in sweep})
+        for seed in seeds:
+            refs[seed] = run_case(workloads.truncated_cylinder(reference_d, re=re), steps, seed=seed)
+            progress(f"Re {re:g} seed {seed} reference {reference_d} D", refs[seed])
+            for name, P in networks.items():
+                runs[f"nn_{name}_8d"][seed] = run_case(workloads.truncated_cylinder(8, re=re), steps,
+                                                       network=P, mass_bound=mass_bound,
+                                                       nn_switch=nn_switch, seed=seed)
+                progress(f"Re {re:g} seed {seed} neural {name} 8 D", runs[f"nn_{name}_8d"][seed])
+            for d in sweep:
+                runs[f"zh_{d}d"][seed] = run_case(workloads.truncated_cylinder(d, re=re), steps,
+                                                  seed=seed)
+                progress(f"Re {re:g} seed {seed} Zou-He {d} D", runs[f"zh_{d}d"][seed])
+        per_seed = {c: {s: (observables.relative_errors(r, refs[s])
+                            if "st" in r and "st" in refs[s] else None) for s, r in rs.items()}
+                    for c, rs in runs.items()}
+        mean_err, std_err = {}, {}
+        for c, es in per_seed.items():
+            ok = [e for e in es.values() if e is not None]
+            # a case counts only if every seed stayed finite
+            if len(ok) == len(seeds):
+                mean_err[c] = {k: float(np.mean([e[k] for e in ok])) for k in ok[0]}
+                std_err[c] = {k: float(np.std([e[k] for e in ok], ddof=1)) if len(ok) > 1 else None
+                              for k in ok[0]}
+            else:
+                mean_err[c], std_err[c] = None, None
+        spread = {}
+        for k in ("cd_mean", "cl_rms", "st"):
+            v = [r[k] for r in refs.values() if k in r]
+            spread[k] = float(np.std(v, ddof=1) / abs(np.mean(v))) if len(v) > 1 else None
+        # cost of an answer on the seed means: mean wall time, mean errors
+        mean_runs = {c: {"wall_s": float(np.mean([r["wall_s"] for r in rs.values()])),
+                         "mlups": float(np.mean([r["mlups"] for r in rs.values()])),
+                         "steps": steps} for c, rs in runs.items()}
+        ref_mean = {"nodes": next(iter(refs.values()))["nodes"],
+                    "wall_s": float(np.mean([r["wall_s"] for r in refs.values()]))}
+        out[re] = {"seeds": list(seeds), "reference": refs, "runs": runs, "rel_err": per_seed,
+                   "rel_err_mean": mean_err, "rel_err_std": std_err,
+                   "reference_seed_spread": spread,
+                   "cost": answer_cost(mean_runs, mean_err, ref_mean)}
     return out
 
 
