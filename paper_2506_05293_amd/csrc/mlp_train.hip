@@ -8,8 +8,9 @@
 //                   rows, forward pass (MFMA 16x16x32 BF16, FP32 tanh), loss,
 //                   backward pass (MFMA for every product contracted over
 //                   units or over samples), per-tile FP32 gradient sums;
-//   k_train_update  one thread per parameter: FP64 sum of the tile gradients
-//                   in tile order, Adam on the FP32 master weight, refresh of
+//   k_train_update  32 parameters per workgroup: FP64 sum of the tile gradients
+//                   in a fixed order (eight tile groups, each in tile order),
+//                   Adam on the FP32 master weight, refresh of
 //                   the BF16 copies the next forward pass reads.
 //
 // LDS holds every activation twice, row-major [sample][unit] (A operand of
@@ -42,7 +43,7 @@ constexpr int kP = 72;                  // LDS pitch (BF16) of 64-wide rows
 constexpr int kPartStride = kNP + 1;    // gradient sums + loss sum per tile
 constexpr int kStatCols = 30;           // 27 inputs + 3 targets
 constexpr int kStatBlocks = 256;
-constexpr int kUpdBlocks = (kNP + kBlock - 1) / kBlock;
+constexpr int kUpdBlocks = (kNP + 1 + 31) / 32;   // 32 parameters (and the loss) per workgroup
 
 struct TrainState {
   float w[kNP], m[kNP], v[kNP];   // FP32 masters and Adam moments
@@ -297,28 +298,49 @@ struct UpdateArgs {
   double loss_scale;  // 1 / (3 batch)
 };
 
+// 32 parameters per workgroup (index kNP is the loss), eight groups of tiles
+// per parameter: thread (i, k) sums tiles k, k + 8, ... of parameter i in
+// FP64 with its loads issued together, and the eight sums are added in
+// group order (a fixed order; one thread per parameter walking all tiles in
+// turn took 20.3 us per step, a chain of dependent loads).
+constexpr int kUpdParams = 32, kUpdGroups = kBlock / kUpdParams;
 __global__ void __launch_bounds__(kBlock) k_train_update(const UpdateArgs a) {
-  const int p = blockIdx.x * kBlock + threadIdx.x;
-  if (p < kNP) {
-    double g = 0.0;
-    for (int t = 0; t < a.tiles; ++t) g += double(a.part[int64_t(t) * kPartStride + p]);
-    const float gf = float(g);
-    if (a.grad) {
-      a.grad[p] = gf;
-    } else {
-      TrainState* st = a.st;
-      const float m = a.beta1 * st->m[p] + (1.f - a.beta1) * gf;
-      const float v = a.beta2 * st->v[p] + (1.f - a.beta2) * gf * gf;
-      st->m[p] = m;
-      st->v[p] = v;
-      st->w[p] -= a.lr * (m * a.c1) / (sqrtf(v * a.c2) + a.eps);
-      refresh_bf16(st, p);
+  __shared__ double red[kUpdGroups][kUpdParams];
+  const int i = threadIdx.x % kUpdParams, k = threadIdx.x / kUpdParams;
+  const int p = blockIdx.x * kUpdParams + i;
+  double s = 0.0;
+  if (p <= kNP) {
+    for (int t0 = k; t0 < a.tiles; t0 += 8 * kUpdGroups) {
+      float v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int t = t0 + u * kUpdGroups;
+        v[u] = t < a.tiles ? a.part[int64_t(t) * kPartStride + p] : 0.f;
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) s += double(v[u]);
     }
   }
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
-    double l = 0.0;
-    for (int t = 0; t < a.tiles; ++t) l += double(a.part[int64_t(t) * kPartStride + kNP]);
-    a.st->loss = l * a.loss_scale;
+  red[k][i] = s;
+  __syncthreads();
+  if (k != 0 || p > kNP) return;
+  double g = 0.0;
+  for (int j = 0; j < kUpdGroups; ++j) g += red[j][i];
+  if (p == kNP) {
+    a.st->loss = g * a.loss_scale;
+    return;
+  }
+  const float gf = float(g);
+  if (a.grad) {
+    a.grad[p] = gf;
+  } else {
+    TrainState* st = a.st;
+    const float m = a.beta1 * st->m[p] + (1.f - a.beta1) * gf;
+    const float v = a.beta2 * st->v[p] + (1.f - a.beta2) * gf * gf;
+    st->m[p] = m;
+    st->v[p] = v;
+    st->w[p] -= a.lr * (m * a.c1) / (sqrtf(v * a.c2) + a.eps);
+    refresh_bf16(st, p);
   }
 }
 
