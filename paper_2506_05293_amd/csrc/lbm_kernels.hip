@@ -1365,9 +1365,10 @@ int pair_waves(int nx, int ny, int rows) {
 // 16384 x 4096 17 rows 114.0k (16: 115.0k, 24: 110.6k); FP16 4096 x 1024
 // 143.7k (24: 127.6k); FP64 4096 x 1024 52.2k (24: 53.2k).
 constexpr int kPairRowsMin = 12, kPairRowsMax = 18;
+constexpr int kSimds = 256 * 4;      // the MI355X's 256 CUs of four SIMDs each
 int pair_rows(int nx, int ny, int pitch_bytes) {
   const int strips = (nx + kPairCols - 1) / kPairCols;
-  const int bands = std::max(1, 4 * 1024 / strips);
+  const int bands = std::max(1, 4 * kSimds / strips);
   int rows = std::min(std::max((ny + bands - 1) / bands, kPairRowsMin), kPairRowsMax);
   if (rows > kPairRowsMin && (int64_t(rows) * pitch_bytes) % 65536 == 0)
     rows += rows < kPairRowsMax ? 1 : -1;

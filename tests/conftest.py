@@ -16,8 +16,8 @@ def pytest_configure(config):
 @pytest.fixture(params=["pairs", "single-scalar", "single-vector"])
 def schedule(request, monkeypatch):
     """Run a GPU test once per kernel schedule of lbm_step, chosen through
-    lbm_params: two steps per launch (where the outflow has that form), and
-    one step per launch with each bulk tile shape."""
+    lbm_params: two steps per launch, and one step per launch with each bulk
+    tile shape."""
     from paper_2506_05293_amd import lbm
     launch, _, path = request.param.partition("-")
     monkeypatch.setitem(lbm.LATTICE_DEFAULTS, "launch", launch)
