@@ -55,6 +55,30 @@ extern "C" {
  * b3 [2], row-major [out][in]. */
 #define LBM_CBC_NPARAMS 662
 
+/* The same trainer drives the outflow reconstruction of Eq. 16 (Sec. 3.1)
+ * instead when its network is set with lbm_cbc_train_set_nn: at every
+ * outlet row the unknowns are g_i = f_i(L-1) + s_i, i = 3, 6, 7, where
+ * f(L-1) are the streamed populations of column L-1 and s = o sd_out +
+ * mu_out, o the 9-20-20-3 network (tanh hidden layers, linear output) of
+ * the standardised pre-collision offsets f - w of column L-1, z = (f - w -
+ * mu_in) / sd_in; the outlet node then collides like every other (no
+ * fallback inside a segment: the fallback is a selection, not a function
+ * the training differentiates).  Parameters in the order of the gradient
+ * and weight arrays: w1 [20][9], b1 [20], w2 [20][20], b2 [20], w3 [3][20],
+ * b3 [3], row-major [out][in]. */
+#define LBM_NN9_NPARAMS 683
+
+typedef struct {
+  const float* w1;      /* [20][9]  */
+  const float* b1;      /* [20]     */
+  const float* w2;      /* [20][20] */
+  const float* b2;      /* [20]     */
+  const float* w3;      /* [3][20]  */
+  const float* b3;      /* [3]      */
+  float mu_in[9], sd_in[9];     /* input standardisation, sd > 0  */
+  float mu_out[3], sd_out[3];   /* output map, sd_out > 0         */
+} lbm_nn9_net;
+
 typedef struct lbm_cbc_trainer lbm_cbc_trainer;
 
 typedef struct {
@@ -95,12 +119,21 @@ lbm_status lbm_cbc_train_set_segment_params(lbm_cbc_trainer* t, const double* ta
                                             const double* mach);
 
 /* The network: weights become the FP32 masters, standardisation and output
- * maps are kept fixed (as in lbm_cbc_net); resets Adam. */
+ * maps are kept fixed (as in lbm_cbc_net); resets Adam.  The segments then
+ * run the characteristic outlet. */
 lbm_status lbm_cbc_train_set_net(lbm_cbc_trainer* t, const lbm_cbc_net* net);
 
+/* The Eq. 16 network (host arrays, copied; synchronises): weights become
+ * the FP32 masters, the standardisation and output map stay fixed; resets
+ * Adam.  The segments then run the Eq. 16 outlet (mach, length and rho_inf
+ * of the parameters are not used).  Gradients and weights then have
+ * LBM_NN9_NPARAMS entries.  EINVAL for a NULL or non-finite argument or an
+ * sd that is not positive. */
+lbm_status lbm_cbc_train_set_nn(lbm_cbc_trainer* t, const lbm_nn9_net* net);
+
 /* Loss and gradient of the current weights over every segment, without an
- * update (synchronises).  grad: host array of LBM_CBC_NPARAMS doubles, or
- * NULL. */
+ * update (synchronises).  grad: host array of LBM_CBC_NPARAMS doubles
+ * (LBM_NN9_NPARAMS with the Eq. 16 network), or NULL. */
 lbm_status lbm_cbc_train_gradient(lbm_cbc_trainer* t, double* loss, double* grad);
 
 /* nsteps optimiser steps, each on the full set of segments (asynchronous). */
@@ -109,7 +142,8 @@ lbm_status lbm_cbc_train_step(lbm_cbc_trainer* t, int64_t nsteps);
 /* Synchronise; the loss of the weights before the last step's update. */
 lbm_status lbm_cbc_train_loss(lbm_cbc_trainer* t, double* loss);
 
-/* Synchronise and copy the FP32 master weights (LBM_CBC_NPARAMS floats). */
+/* Synchronise and copy the FP32 master weights (LBM_CBC_NPARAMS floats;
+ * LBM_NN9_NPARAMS with the Eq. 16 network). */
 lbm_status lbm_cbc_train_get_weights(lbm_cbc_trainer* t, float* theta);
 
 /* Synchronise and copy segment seg's state at its step n_t of the last

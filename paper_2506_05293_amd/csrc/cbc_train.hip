@@ -66,11 +66,14 @@
 namespace lbm {
 namespace {
 
-constexpr int kNP = LBM_CBC_NPARAMS;
+constexpr int kNP = LBM_CBC_NPARAMS;        // the tuning network (2 outputs)
+constexpr int kNPNn = LBM_NN9_NPARAMS;      // the Eq. 16 network (3 outputs)
+constexpr int kNPMax = kNPNn;               // stride of the gradient slots
 constexpr int kIn = 9, kH = 20;
 constexpr int kOW1 = 0, kOB1 = kH * kIn, kOW2 = kOB1 + kH, kOB2 = kOW2 + kH * kH,
-              kOW3 = kOB2 + kH, kOB3 = kOW3 + 2 * kH;
+              kOW3 = kOB2 + kH, kOB3 = kOW3 + 2 * kH, kOB3n = kOW3 + 3 * kH;
 static_assert(kOB3 + 2 == kNP, "parameter count");
+static_assert(kOB3n + 3 == kNPNn, "parameter count");
 constexpr int kRows = 64;            // outlet rows per workgroup (one wave)
 constexpr int kNodes = 256;          // nodes per workgroup
 // The backward outlet workgroup is one wave: it takes the node adjoints of
@@ -84,21 +87,27 @@ constexpr int kBwdThreads = kRows;
 constexpr unsigned kEventFlags = hipEventDisableTiming | hipEventDisableSystemFence;
 constexpr int kMaxSteps = 64;
 constexpr int kMadj = 12;            // per outlet row: 3 columns x (drho, u, v) + y-part
+                                     // (Eq. 16 outlet: the 9 population adjoints it left)
+// The outlet of a segment: the characteristic outflow with its tuning
+// network, or the reconstruction of Eq. 16 with its network.
+constexpr int kOutCbc = 0, kOutNn = 1;
 
 struct CtState {
-  float w[kNP];                      // FP32 masters
-  double m[kNP], v[kNP];             // Adam moments
+  float w[kNPMax];                   // FP32 masters
+  double m[kNPMax], v[kNPMax];       // Adam moments
   double mu[kIn], sd[kIn];           // input standardisation
   double leaky, sig_scale, sig_shift, kap_scale, kap_shift;
+  double mu_out[3], sd_out[3];       // Eq. 16: s = o sd_out + mu_out
   double rho_inf_m1;                 // rho_inf - 1
   double loss;
-  double grad[kNP];
+  double grad[kNPMax];
 };
 
 template <typename T>
 struct CtArgs {
   T* traj;              // [seg][n_max+1][9][W][ny] (rows fastest)
   T* outs;              // [seg][n_max][ny][3]    outlet state drho', u', v'
+                        //                        (Eq. 16: the reconstructed g3, g6, g7)
   T* dts;               // [seg][n_max+1][ny][3]  c_s^2 rho_t, u_t, v_t
   T* lamF[2];           // [seg][9][W][ny] each   adjoint of the pulled populations,
                         //                        step k in buffer k & 1
@@ -107,7 +116,7 @@ struct CtArgs {
                         //                        step k in buffer k & 1
   const T* ref;         // [seg][3][ny][n_max]    rho - 1, u, v
   const int* nts;       // [seg]
-  double* gslot;        // [seg][nrb][kNP]
+  double* gslot;        // [seg][nrb][kNPMax]
   double* lslot;        // [seg][nlb]
   CtState* st;
   int ny, W, n_max, nrb, nlb;
@@ -129,6 +138,14 @@ __device__ __forceinline__ int wrap(int y, int ny) { return y < 0 ? y + ny : (y 
 template <typename T>
 __device__ __forceinline__ T leaky(T x, T a) {
   return x > T(0) ? x : a * x;
+}
+
+template <typename T>
+__device__ __forceinline__ T tanh_t(T x) {
+  if constexpr (sizeof(T) == 8)
+    return tanh(x);
+  else
+    return tanhf(x);
 }
 
 template <typename T>
@@ -227,10 +244,11 @@ __device__ Lodi<T> lodi(const OutIn<T>& in, T sigma, T kappa2, T k1c, const CtSt
 }
 
 // ---- forward -------------------------------------------------------------------------
-// The 662 weights are read by every row: staged once per workgroup in LDS
-// (uniform reads, no scalar-load latency inside the layers).
-__device__ __forceinline__ void stage_weights(const CtState* st, float* sw, int nthreads) {
-  for (int i = threadIdx.x; i < kNP; i += nthreads) sw[i] = st->w[i];
+// The weights (662 or 683) are read by every row: staged once per
+// workgroup in LDS (uniform reads, no scalar-load latency inside the layers).
+__device__ __forceinline__ void stage_weights(const CtState* st, float* sw, int nthreads,
+                                              int np = kNP) {
+  for (int i = threadIdx.x; i < np; i += nthreads) sw[i] = st->w[i];
   __syncthreads();
 }
 
@@ -296,28 +314,90 @@ __device__ __forceinline__ void fwd_outlet_row(const CtArgs<T>& a, float* sw, in
   for (int q = 0; q < 9; ++q) B[q * a.plane + n] = g[q];
 }
 
+// The outlet row r with the reconstruction of Eq. 16: the pulled offsets
+// of column L-1 = W-2 are the network's features (standardised), the
+// unknowns are g_i = f_i(L-1) + s_i for i = 3, 6, 7 with s = o sd_out +
+// mu_out, o the 9-20-20-3 network (tanh hidden layers, linear output).
 template <typename T>
+__device__ __forceinline__ void fwd_outlet_row_nn(const CtArgs<T>& a, float* sw, int s, int k,
+                                                  int r) {
+  const CtState* st = a.st;
+  const bool valid = r < a.ny;
+  const int rl = valid ? r : a.ny - 1;
+  const T* A = state_at(a, s, k);
+  T fe[9], g[9];
+  pull(A, a.plane, a.W, a.ny, a.W - 2, rl, fe);
+  pull(A, a.plane, a.W, a.ny, a.W - 1, rl, g);
+  stage_weights(st, sw, kNodes, kNPNn);
+  if (!valid) return;
+  T z[kIn];
+#pragma unroll
+  for (int i = 0; i < kIn; ++i) z[i] = (fe[i] - T(st->mu[i])) / T(st->sd[i]);
+  T h1[kH];
+#pragma unroll
+  for (int o = 0; o < kH; ++o) {
+    T acc = T(sw[kOB1 + o]);
+#pragma unroll
+    for (int i = 0; i < kIn; ++i) acc += T(sw[kOW1 + o * kIn + i]) * z[i];
+    h1[o] = tanh_t(acc);
+  }
+  T o0 = T(sw[kOB3n]), o1 = T(sw[kOB3n + 1]), o2 = T(sw[kOB3n + 2]);
+#pragma unroll 1
+  for (int o = 0; o < kH; ++o) {
+    T acc = T(sw[kOB2 + o]);
+#pragma unroll
+    for (int m = 0; m < kH; ++m) acc += T(sw[kOW2 + o * kH + m]) * h1[m];
+    const T h = tanh_t(acc);
+    o0 += T(sw[kOW3 + o]) * h;
+    o1 += T(sw[kOW3 + kH + o]) * h;
+    o2 += T(sw[kOW3 + 2 * kH + o]) * h;
+  }
+  g[3] = fe[3] + (o0 * T(st->sd_out[0]) + T(st->mu_out[0]));
+  g[6] = fe[6] + (o1 * T(st->sd_out[1]) + T(st->mu_out[1]));
+  g[7] = fe[7] + (o2 * T(st->sd_out[2]) + T(st->mu_out[2]));
+  T* O = a.outs + ((int64_t(s) * a.n_max + k) * a.ny + r) * 3;
+  O[0] = g[3];
+  O[1] = g[6];
+  O[2] = g[7];
+  collide_bgk(g, T(a.seg_omega[s]));
+  T* B = state_at(a, s, k + 1);
+  const int64_t n = int64_t(a.W - 1) * a.ny + r;
+#pragma unroll
+  for (int q = 0; q < 9; ++q) B[q * a.plane + n] = g[q];
+}
+
+template <typename T, int OK>
 __device__ __forceinline__ void pre_collision(const CtArgs<T>& a, int s, int k, int x, int y,
                                               T g[9]) {
   pull(state_at(a, s, k), a.plane, a.W, a.ny, x, y, g);
   if (x == a.W - 1) {
     const T* o = a.outs + ((int64_t(s) * a.n_max + k) * a.ny + y) * 3;
-    outlet_state(g, o[0], o[1], o[2]);      // Eq. 29, Eqs. 8-10
+    if constexpr (OK == kOutNn) {
+      g[3] = o[0];                          // Eq. 16
+      g[6] = o[1];
+      g[7] = o[2];
+    } else {
+      outlet_state(g, o[0], o[1], o[2]);    // Eq. 29, Eqs. 8-10
+    }
   }
 }
 
 // One forward step: the first n_seg * nrb_fwd workgroups take the outlet
 // rows (256 per workgroup; their network chain is long but they are few and
 // start first), the rest every node left of the outlet column.
-template <typename T>
+template <typename T, int OK>
 __global__ void __launch_bounds__(kNodes) k_fwd(const CtArgs<T> a, int k) {
-  __shared__ float sw[kNP];
+  __shared__ float sw[kNPMax];
   int b = int(blockIdx.x);
   const int nout = a.n_seg * a.nrb_fwd;
   if (b < nout) {
     const int s = b / a.nrb_fwd;
     if (k >= a.nts[s]) return;                   // uniform over the workgroup
-    fwd_outlet_row(a, sw, s, k, (b - s * a.nrb_fwd) * kNodes + int(threadIdx.x));
+    const int r = (b - s * a.nrb_fwd) * kNodes + int(threadIdx.x);
+    if constexpr (OK == kOutNn)
+      fwd_outlet_row_nn(a, sw, s, k, r);
+    else
+      fwd_outlet_row(a, sw, s, k, r);
     return;
   }
   b -= nout;
@@ -327,7 +407,7 @@ __global__ void __launch_bounds__(kNodes) k_fwd(const CtArgs<T> a, int k) {
   if (n >= a.plane - a.ny) return;
   const int x = int(n / a.ny), y = int(n - int64_t(x) * a.ny);
   T g[9];
-  pre_collision(a, s, k, x, y, g);
+  pre_collision<T, OK>(a, s, k, x, y, g);
   collide_bgk(g, T(a.seg_omega[s]));
   T* B = state_at(a, s, k + 1);
 #pragma unroll
@@ -400,7 +480,7 @@ __global__ void __launch_bounds__(kNodes) k_seed(const CtArgs<T> a) {
 // Adjoint of the post-collision state A_kk at node (x, y) from the adjoints
 // LF of the populations pulled at step kk (streaming adjoint) and the moment
 // adjoints the outlet left for the last three columns.
-template <typename T>
+template <typename T, int OK>
 __device__ __forceinline__ void state_adjoint(const CtArgs<T>& a, int s, int kk, int x, int y,
                                               int64_t n, const T* LF, T lam[9]) {
 #pragma unroll
@@ -412,7 +492,16 @@ __device__ __forceinline__ void state_adjoint(const CtArgs<T>& a, int s, int kk,
     if (x == 0 && cx(q) == 1) l += LF[q * a.plane + dy];                  // edge copies
     lam[q] = l;
   }
-  if (x >= a.W - 3) {
+  if (OK == kOutNn && x >= a.W - 3) {
+    // Eq. 16 read population q of this node as feature q of the outlet row
+    // r = y + c_y(q) (a pull into column W-2) -- and, for q = 3, 6, 7, as
+    // f_q(L-1) of that row's reconstruction: the row left both adjoints in
+    // its slot q
+    const T* MA = a.madj[kk & 1] + int64_t(s) * a.ny * kMadj;
+#pragma unroll
+    for (int q = 0; q < 9; ++q)
+      if (x == a.W - 2 - cx(q)) lam[q] += MA[int64_t(wrap(y + cy(q), a.ny)) * kMadj + q];
+  } else if (x >= a.W - 3) {
     const int c = x - (a.W - 3);
     const T* MA = a.madj[kk & 1] + int64_t(s) * a.ny * kMadj;
     const T* M = MA + int64_t(y) * kMadj;
@@ -435,7 +524,7 @@ __device__ __forceinline__ void state_adjoint(const CtArgs<T>& a, int s, int kk,
 // Adjoint of the pulled populations of node (x, y) at step k (lf): the
 // adjoint of the post-collision state at step k+1 (the seed at the last
 // step), then the collision adjoint at the recomputed pre-collision state.
-template <typename T>
+template <typename T, int OK>
 __device__ __forceinline__ void node_adjoint(const CtArgs<T>& a, int s, int nt, int k, int x, int y,
                                              int64_t n, T lf[9]) {
   const int64_t so = int64_t(s) * 9 * a.plane;
@@ -443,10 +532,10 @@ __device__ __forceinline__ void node_adjoint(const CtArgs<T>& a, int s, int nt, 
   if (k + 1 == nt) {
     (void)seed_adjoint(a, s, nt, x, y, n, lam);
   } else {
-    state_adjoint(a, s, k + 1, x, y, n, a.lamF[(k + 1) & 1] + so, lam);
+    state_adjoint<T, OK>(a, s, k + 1, x, y, n, a.lamF[(k + 1) & 1] + so, lam);
   }
   T g[9];
-  pre_collision(a, s, k, x, y, g);
+  pre_collision<T, OK>(a, s, k, x, y, g);
   const Macro<T> m = macro(g);
   const T u = m.jx / m.rho, v = m.jy / m.rho;
   const T usq = T(1.5) * (u * u + v * v);
@@ -467,7 +556,7 @@ __device__ __forceinline__ void node_adjoint(const CtArgs<T>& a, int s, int nt, 
 
 // Every node left of the last three columns (whose adjoints need the
 // outlet's moment adjoints: the outlet kernel takes those).
-template <typename T>
+template <typename T, int OK>
 __global__ void __launch_bounds__(kNodes) k_bwd(const CtArgs<T> a, int k) {
   const int s = blockIdx.y;
   const int nt = a.nts[s];
@@ -476,7 +565,7 @@ __global__ void __launch_bounds__(kNodes) k_bwd(const CtArgs<T> a, int k) {
   if (n >= a.plane - 3 * int64_t(a.ny)) return;
   const int x = int(n / a.ny), y = int(n - int64_t(x) * a.ny);
   T lf[9];
-  node_adjoint(a, s, nt, k, x, y, n, lf);
+  node_adjoint<T, OK>(a, s, nt, k, x, y, n, lf);
   T* LF = a.lamF[k & 1] + int64_t(s) * 9 * a.plane;
 #pragma unroll
   for (int q = 0; q < 9; ++q) LF[q * a.plane + n] = lf[q];
@@ -547,7 +636,7 @@ __global__ void __launch_bounds__(kBwdThreads) k_bwd_outlet(const CtArgs<T> a, i
       const int x = a.W - 1 - c;
       const int64_t n = int64_t(x) * a.ny + r;
       T l9[9];
-      node_adjoint(a, s, nt, k, x, r, n, l9);
+      node_adjoint<T, kOutCbc>(a, s, nt, k, x, r, n, l9);
 #pragma unroll
       for (int q = 0; q < 9; ++q) {
         if (c == 0) lf[q] = l9[q];
@@ -722,7 +811,7 @@ __global__ void __launch_bounds__(kBwdThreads) k_bwd_outlet(const CtArgs<T> a, i
   // precision (FP64 in the FP64 variant: 0.1 ms per optimiser step less in
   // FP32) and added to its FP64 slot (the slot values are all requested
   // before the sums, so their latency overlaps)
-  double* G = a.gslot + (int64_t(s) * a.nrb + blockIdx.x) * kNP;
+  double* G = a.gslot + (int64_t(s) * a.nrb + blockIdx.x) * kNPMax;
   constexpr int kPer = (kNP + kBwdThreads - 1) / kBwdThreads;
   double old[kPer];
 #pragma unroll
@@ -758,6 +847,148 @@ __global__ void __launch_bounds__(kBwdThreads) k_bwd_outlet(const CtArgs<T> a, i
   }
 }
 
+// The Eq. 16 outlet of the workgroup's 64 rows: the node adjoints of the
+// last three columns (the outlet column's stays in registers), then per row
+// the network recomputed and its backward pass: the outlet node's adjoint
+// lam_g of g3, g6, g7 is the adjoint of f_q(L-1) (left in the row's slot q
+// with the features' adjoints) and, times sd_out, of the network's output;
+// then the parameter-gradient sums of the rows.
+template <typename T>
+__global__ void __launch_bounds__(kBwdThreads) k_bwd_outlet_nn(const CtArgs<T> a, int k) {
+  __shared__ BwdSmem<T> sm;
+  __shared__ float sw[kNPNn];
+  const int s = blockIdx.y;
+  const int nt = a.nts[s];
+  if (k >= nt) return;                           // uniform over the workgroup
+  const int j = threadIdx.x;
+  const int r = blockIdx.x * kRows + j;
+  const CtState* st = a.st;
+  const bool valid = r < a.ny;
+  const int rl = valid ? r : a.ny - 1;
+  T* LF = a.lamF[k & 1] + int64_t(s) * 9 * a.plane;
+  T lf[9];
+#pragma unroll
+  for (int q = 0; q < 9; ++q) lf[q] = T(0);
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    if (valid) {
+      const int x = a.W - 1 - c;
+      const int64_t n = int64_t(x) * a.ny + r;
+      T l9[9];
+      node_adjoint<T, kOutNn>(a, s, nt, k, x, r, n, l9);
+#pragma unroll
+      for (int q = 0; q < 9; ++q) {
+        if (c == 0) lf[q] = l9[q];
+        else LF[q * a.plane + n] = l9[q];
+      }
+    }
+  }
+  T fe[9];
+  pull(state_at(a, s, k), a.plane, a.W, a.ny, a.W - 2, rl, fe);
+  stage_weights(st, sw, kBwdThreads, kNPNn);
+  if (valid) {
+    const int64_t on = int64_t(a.W - 1) * a.ny + r;
+    // the outlet node's known populations feed the streaming adjoint; its
+    // unknowns have no source inside the strip
+#pragma unroll
+    for (int q = 0; q < 9; ++q) LF[q * a.plane + on] = (q == 3 || q == 6 || q == 7) ? T(0) : lf[q];
+    T z[kIn];
+#pragma unroll
+    for (int i = 0; i < kIn; ++i) {
+      z[i] = (fe[i] - T(st->mu[i])) / T(st->sd[i]);
+      sm.z[j][i] = z[i];
+    }
+    // activations and tanh derivatives in LDS (the derivatives are scaled
+    // into the pre-activation adjoints below)
+#pragma unroll 1
+    for (int o = 0; o < kH; ++o) {
+      T acc = T(sw[kOB1 + o]);
+#pragma unroll
+      for (int i = 0; i < kIn; ++i) acc += T(sw[kOW1 + o * kIn + i]) * z[i];
+      const T h = tanh_t(acc);
+      sm.h1[j][o] = h;
+      sm.d1[j][o] = T(1) - h * h;
+    }
+#pragma unroll 1
+    for (int o = 0; o < kH; ++o) {
+      T acc = T(sw[kOB2 + o]);
+#pragma unroll 4
+      for (int m = 0; m < kH; ++m) acc += T(sw[kOW2 + o * kH + m]) * sm.h1[j][m];
+      const T h = tanh_t(acc);
+      sm.h2[j][o] = h;
+      sm.d2[j][o] = T(1) - h * h;
+    }
+    // s_i = o_i sd_out_i + mu_out_i, g_{3,6,7} = f_{3,6,7}(L-1) + s
+    const T lo0 = lf[3] * T(st->sd_out[0]), lo1 = lf[6] * T(st->sd_out[1]),
+            lo2 = lf[7] * T(st->sd_out[2]);
+    sm.ds[j][0] = lo0;
+    sm.ds[j][1] = lo1;
+    sm.ds[j][2] = lo2;
+#pragma unroll
+    for (int o = 0; o < kH; ++o)
+      sm.d2[j][o] *= T(sw[kOW3 + o]) * lo0 + T(sw[kOW3 + kH + o]) * lo1 +
+                     T(sw[kOW3 + 2 * kH + o]) * lo2;
+    T lz[kIn];
+#pragma unroll
+    for (int i = 0; i < kIn; ++i) lz[i] = T(0);
+#pragma unroll 1
+    for (int m = 0; m < kH; ++m) {
+      T acc = T(0);
+#pragma unroll
+      for (int o = 0; o < kH; ++o) acc += T(sw[kOW2 + o * kH + m]) * sm.d2[j][o];
+      const T d = acc * sm.d1[j][m];
+      sm.d1[j][m] = d;
+#pragma unroll
+      for (int i = 0; i < kIn; ++i) lz[i] += T(sw[kOW1 + m * kIn + i]) * d;
+    }
+    T* P = a.madj[k & 1] + (int64_t(s) * a.ny + r) * kMadj;
+#pragma unroll
+    for (int q = 0; q < 9; ++q)
+      P[q] = lz[q] / T(st->sd[q]) + (q == 3 || q == 6 || q == 7 ? lf[q] : T(0));
+  } else {
+#pragma unroll
+    for (int i = 0; i < kIn; ++i) sm.z[j][i] = T(0);
+#pragma unroll
+    for (int o = 0; o < kH; ++o) sm.h1[j][o] = sm.h2[j][o] = sm.d1[j][o] = sm.d2[j][o] = T(0);
+    sm.ds[j][0] = sm.ds[j][1] = sm.ds[j][2] = T(0);
+  }
+  __syncthreads();
+  double* G = a.gslot + (int64_t(s) * a.nrb + blockIdx.x) * kNPMax;
+  constexpr int kPer = (kNPNn + kBwdThreads - 1) / kBwdThreads;
+  double old[kPer];
+#pragma unroll
+  for (int u = 0; u < kPer; ++u) {
+    const int p = j + u * kBwdThreads;
+    old[u] = p < kNPNn ? G[p] : 0.0;
+  }
+#pragma unroll
+  for (int u = 0; u < kPer; ++u) {
+    const int p = j + u * kBwdThreads;
+    if (p >= kNPNn) break;
+    T acc;
+    if (p < kOB1) {
+      const int m = p / kIn, i = p - m * kIn;
+      acc = sum_rows([&](int rr) { return sm.d1[rr][m] * sm.z[rr][i]; });
+    } else if (p < kOW2) {
+      const int m = p - kOB1;
+      acc = sum_rows([&](int rr) { return sm.d1[rr][m]; });
+    } else if (p < kOB2) {
+      const int o = (p - kOW2) / kH, m = (p - kOW2) - o * kH;
+      acc = sum_rows([&](int rr) { return sm.d2[rr][o] * sm.h1[rr][m]; });
+    } else if (p < kOW3) {
+      const int o = p - kOB2;
+      acc = sum_rows([&](int rr) { return sm.d2[rr][o]; });
+    } else if (p < kOB3n) {
+      const int o = (p - kOW3) / kH, m = (p - kOW3) - o * kH;
+      acc = sum_rows([&](int rr) { return sm.ds[rr][o] * sm.h2[rr][m]; });
+    } else {
+      const int o = p - kOB3n;
+      acc = sum_rows([&](int rr) { return sm.ds[rr][o]; });
+    }
+    G[p] = old[u] + acc;
+  }
+}
+
 __global__ void k_zero(double* p, int64_t n) {
   const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i < n) p[i] = 0.0;
@@ -771,23 +1002,23 @@ constexpr int kSlotChunk = 64;
 constexpr int kLossChunk = 4 * kNodes;
 
 __global__ void __launch_bounds__(kNodes) k_gsum(const double* gslot, int64_t nslots,
-                                                double* gpart) {
+                                                double* gpart, int np) {
   __shared__ double sh[4][64];
   const int l = threadIdx.x & 63, g = threadIdx.x >> 6;
   const int p = blockIdx.y * 64 + l;
   const int64_t i0 = int64_t(blockIdx.x) * kSlotChunk + g * (kSlotChunk / 4);
   double acc = 0.0;
-  if (p < kNP) {
+  if (p < np) {
 #pragma unroll 4
     for (int j = 0; j < kSlotChunk / 4; ++j) {
       const int64_t i = i0 + j;
-      if (i < nslots) acc += gslot[i * kNP + p];
+      if (i < nslots) acc += gslot[i * kNPMax + p];
     }
   }
   sh[g][l] = acc;
   __syncthreads();
-  if (g == 0 && p < kNP)
-    gpart[int64_t(blockIdx.x) * kNP + p] = (sh[0][l] + sh[1][l]) + (sh[2][l] + sh[3][l]);
+  if (g == 0 && p < np)
+    gpart[int64_t(blockIdx.x) * kNPMax + p] = (sh[0][l] + sh[1][l]) + (sh[2][l] + sh[3][l]);
 }
 
 __global__ void __launch_bounds__(kNodes) k_lsum(const double* lslot, int64_t nl, double* lpart) {
@@ -805,16 +1036,16 @@ __global__ void __launch_bounds__(kNodes) k_lsum(const double* lslot, int64_t nl
 __global__ void __launch_bounds__(kNodes) k_update(CtState* st, const double* gpart, int ngc,
                                                   const double* lpart, int nlc, int update,
                                                   double lr, double b1, double b2, double eps,
-                                                  double bc1, double bc2) {
+                                                  double bc1, double bc2, int np) {
   const int p = blockIdx.x * kNodes + threadIdx.x;
   if (p == 0) {
     double t = 0.0;
     for (int i = 0; i < nlc; ++i) t += lpart[i];
     st->loss = t;
   }
-  if (p >= kNP) return;
+  if (p >= np) return;
   double g = 0.0;
-  for (int i = 0; i < ngc; ++i) g += gpart[int64_t(i) * kNP + p];
+  for (int i = 0; i < ngc; ++i) g += gpart[int64_t(i) * kNPMax + p];
   st->grad[p] = g;
   if (update) {
     const double m = b1 * st->m[p] + (1.0 - b1) * g;
@@ -861,9 +1092,9 @@ CtLayout ct_layout(const lbm_cbc_train_params& p) {
   L.madj = take(2 * ns * ny * kMadj * e);
   L.ref = take(ns * 3 * ny * p.n_max * e);
   L.nts = take(ns * sizeof(int));
-  L.gslot = take(ns * L.nrb * kNP * sizeof(double));
+  L.gslot = take(ns * L.nrb * kNPMax * sizeof(double));
   L.lslot = take(ns * L.nlb * sizeof(double));
-  L.gpart = take(size_t(L.ngc) * kNP * sizeof(double));
+  L.gpart = take(size_t(L.ngc) * kNPMax * sizeof(double));
   L.lpart = take(size_t(L.nlc) * sizeof(double));
   L.seg_omega = take(ns * sizeof(double));
   L.seg_k1c = take(ns * sizeof(double));
@@ -911,7 +1142,10 @@ struct lbm_cbc_trainer {
   CtState* st;
   std::vector<int> nts;
   bool has_data = false, has_net = false;
+  int kind = kOutCbc;                          // the outlet the network set drives
   int64_t adam_t = 0;
+
+  int np() const { return kind == kOutNn ? kNPNn : kNP; }
 
   template <typename T>
   CtArgs<T> args() const {
@@ -952,15 +1186,15 @@ struct lbm_cbc_trainer {
     return e != hipSuccess ? e : hipStreamWaitEvent(side, ev_node, 0);
   }
 
-  template <typename T>
+  template <typename T, int OK>
   lbm_status run_t(bool update) {
     const CtArgs<T> a = args<T>();
     const dim3 grow(L.nrb, p.n_seg), gnode(L.nlb, p.n_seg);
     const dim3 gbwd(a.nlb_bwd, p.n_seg);
     const unsigned gf = unsigned(p.n_seg) * unsigned(a.nrb_fwd + a.nlb_fwd);
     for (int k = 0; k < p.n_max; ++k)
-      hipLaunchKernelGGL(k_fwd<T>, dim3(gf), dim3(kNodes), 0, stream, a, k);
-    const int64_t ng = int64_t(p.n_seg) * L.nrb * kNP;
+      hipLaunchKernelGGL((k_fwd<T, OK>), dim3(gf), dim3(kNodes), 0, stream, a, k);
+    const int64_t ng = int64_t(p.n_seg) * L.nrb * kNPMax;
     hipLaunchKernelGGL(k_zero, dim3(unsigned((ng + kNodes - 1) / kNodes)), dim3(kNodes), 0, stream,
                        a.gslot, ng);
     hipLaunchKernelGGL(k_seed<T>, gnode, dim3(kNodes), 0, stream, a);
@@ -968,9 +1202,12 @@ struct lbm_cbc_trainer {
     CT_TRY(hipEventRecord(ev_side, side));
     for (int k = p.n_max - 1; k >= 0; --k) {
       CT_TRY(join_step());
-      hipLaunchKernelGGL(k_bwd_outlet<T>, grow, dim3(kBwdThreads), 0, side, a, k);
+      if constexpr (OK == kOutNn)
+        hipLaunchKernelGGL(k_bwd_outlet_nn<T>, grow, dim3(kBwdThreads), 0, side, a, k);
+      else
+        hipLaunchKernelGGL(k_bwd_outlet<T>, grow, dim3(kBwdThreads), 0, side, a, k);
       CT_TRY(hipEventRecord(ev_side, side));
-      hipLaunchKernelGGL(k_bwd<T>, gbwd, dim3(kNodes), 0, stream, a, k);
+      hipLaunchKernelGGL((k_bwd<T, OK>), gbwd, dim3(kNodes), 0, stream, a, k);
       CT_TRY(hipEventRecord(ev_node, stream));
     }
     CT_TRY(hipStreamWaitEvent(stream, ev_side, 0));
@@ -981,13 +1218,13 @@ struct lbm_cbc_trainer {
     }
     double* gpart = reinterpret_cast<double*>(base + L.gpart);
     double* lpart = reinterpret_cast<double*>(base + L.lpart);
-    hipLaunchKernelGGL(k_gsum, dim3(L.ngc, (kNP + 63) / 64), dim3(kNodes), 0, stream, a.gslot,
-                       int64_t(p.n_seg) * L.nrb, gpart);
+    hipLaunchKernelGGL(k_gsum, dim3(L.ngc, (np() + 63) / 64), dim3(kNodes), 0, stream, a.gslot,
+                       int64_t(p.n_seg) * L.nrb, gpart, np());
     hipLaunchKernelGGL(k_lsum, dim3(L.nlc), dim3(kNodes), 0, stream, a.lslot,
                        int64_t(p.n_seg) * L.nlb, lpart);
-    hipLaunchKernelGGL(k_update, dim3((kNP + kNodes - 1) / kNodes), dim3(kNodes), 0, stream, st,
+    hipLaunchKernelGGL(k_update, dim3((np() + kNodes - 1) / kNodes), dim3(kNodes), 0, stream, st,
                        gpart, L.ngc, lpart, L.nlc,
-                       update ? 1 : 0, p.lr, p.beta1, p.beta2, p.eps, bc1, bc2);
+                       update ? 1 : 0, p.lr, p.beta1, p.beta2, p.eps, bc1, bc2, np());
     CT_TRY(hipGetLastError());
     return LBM_OK;
   }
@@ -999,7 +1236,9 @@ struct lbm_cbc_trainer {
     if (!ev_node) CT_TRY(hipEventCreateWithFlags(&ev_node, kEventFlags));
     if (!ev_side) CT_TRY(hipEventCreateWithFlags(&ev_side, kEventFlags));
     if (!side) CT_TRY(hipStreamCreateWithFlags(&side, hipStreamNonBlocking));
-    return p.precision == LBM_FP64 ? run_t<double>(update) : run_t<float>(update);
+    if (kind == kOutNn)
+      return p.precision == LBM_FP64 ? run_t<double, kOutNn>(update) : run_t<float, kOutNn>(update);
+    return p.precision == LBM_FP64 ? run_t<double, kOutCbc>(update) : run_t<float, kOutCbc>(update);
   }
 };
 
@@ -1153,6 +1392,39 @@ lbm_status lbm_cbc_train_set_net(lbm_cbc_trainer* t, const lbm_cbc_net* n) {
   CT_TRY(hipMemcpyAsync(t->st, h, sizeof(CtState), hipMemcpyHostToDevice, t->stream));
   CT_TRY(hipStreamSynchronize(t->stream));
   t->adam_t = 0;
+  t->kind = kOutCbc;
+  t->has_net = true;
+  return LBM_OK;
+}
+
+lbm_status lbm_cbc_train_set_nn(lbm_cbc_trainer* t, const lbm_nn9_net* n) {
+  if (!t || !n) return set_error(LBM_EINVAL, "NULL argument");
+  std::vector<char> buf(sizeof(CtState), 0);
+  CtState* h = reinterpret_cast<CtState*>(buf.data());
+  memcpy(h->w + kOW1, n->w1, kH * kIn * 4);
+  memcpy(h->w + kOB1, n->b1, kH * 4);
+  memcpy(h->w + kOW2, n->w2, kH * kH * 4);
+  memcpy(h->w + kOB2, n->b2, kH * 4);
+  memcpy(h->w + kOW3, n->w3, 3 * kH * 4);
+  memcpy(h->w + kOB3n, n->b3, 3 * 4);
+  for (int i = 0; i < kNPNn; ++i)
+    if (!std::isfinite(h->w[i])) return set_error(LBM_EINVAL, "non-finite weight %d", i);
+  for (int i = 0; i < kIn; ++i) {
+    if (!std::isfinite(n->mu_in[i]) || !(n->sd_in[i] > 0.0f) || !std::isfinite(n->sd_in[i]))
+      return set_error(LBM_EINVAL, "mu_in must be finite and sd_in > 0");
+    h->mu[i] = n->mu_in[i];
+    h->sd[i] = n->sd_in[i];
+  }
+  for (int i = 0; i < 3; ++i) {
+    if (!std::isfinite(n->mu_out[i]) || !(n->sd_out[i] > 0.0f) || !std::isfinite(n->sd_out[i]))
+      return set_error(LBM_EINVAL, "mu_out must be finite and sd_out > 0");
+    h->mu_out[i] = n->mu_out[i];
+    h->sd_out[i] = n->sd_out[i];
+  }
+  CT_TRY(hipMemcpyAsync(t->st, h, sizeof(CtState), hipMemcpyHostToDevice, t->stream));
+  CT_TRY(hipStreamSynchronize(t->stream));
+  t->adam_t = 0;
+  t->kind = kOutNn;
   t->has_net = true;
   return LBM_OK;
 }
@@ -1163,7 +1435,7 @@ lbm_status lbm_cbc_train_gradient(lbm_cbc_trainer* t, double* loss, double* grad
   if (s) return s;
   CT_TRY(hipStreamSynchronize(t->stream));
   if (loss) CT_TRY(hipMemcpy(loss, &t->st->loss, sizeof(double), hipMemcpyDeviceToHost));
-  if (grad) CT_TRY(hipMemcpy(grad, t->st->grad, kNP * sizeof(double), hipMemcpyDeviceToHost));
+  if (grad) CT_TRY(hipMemcpy(grad, t->st->grad, t->np() * sizeof(double), hipMemcpyDeviceToHost));
   return LBM_OK;
 }
 
@@ -1188,7 +1460,7 @@ lbm_status lbm_cbc_train_loss(lbm_cbc_trainer* t, double* loss) {
 lbm_status lbm_cbc_train_get_weights(lbm_cbc_trainer* t, float* theta) {
   if (!t || !theta) return set_error(LBM_EINVAL, "NULL argument");
   CT_TRY(hipStreamSynchronize(t->stream));
-  CT_TRY(hipMemcpy(theta, t->st->w, kNP * sizeof(float), hipMemcpyDeviceToHost));
+  CT_TRY(hipMemcpy(theta, t->st->w, t->np() * sizeof(float), hipMemcpyDeviceToHost));
   return LBM_OK;
 }
 

@@ -71,6 +71,12 @@ class lbm_cbc(ctypes.Structure):
                 ("rho_inf", ctypes.c_double), ("net", ctypes.POINTER(lbm_cbc_net))]
 
 
+class lbm_nn9_net(ctypes.Structure):
+    _fields_ = [(k, ctypes.POINTER(ctypes.c_float)) for k in ("w1", "b1", "w2", "b2", "w3", "b3")] + \
+               [("mu_in", ctypes.c_float * 9), ("sd_in", ctypes.c_float * 9),
+                ("mu_out", ctypes.c_float * 3), ("sd_out", ctypes.c_float * 3)]
+
+
 class lbm_cbc_train_params(ctypes.Structure):
     _fields_ = [("ny", ctypes.c_int32), ("n_max", ctypes.c_int32), ("n_seg", ctypes.c_int32),
                 ("precision", ctypes.c_int32), ("tau", ctypes.c_double), ("mach", ctypes.c_double),
@@ -127,6 +133,9 @@ N_PARAMS = 6147
 CBC_PARAM_SHAPES = {"w1": (20, 9), "b1": (20,), "w2": (20, 20), "b2": (20,), "w3": (2, 20),
                     "b3": (2,)}
 LBM_CBC_NPARAMS = 662
+LBM_NN9_NPARAMS = 683
+NN9_PARAM_SHAPES = {"w1": (20, 9), "b1": (20,), "w2": (20, 20), "b2": (20,), "w3": (3, 20),
+                    "b3": (3,)}
 
 
 class LbmError(RuntimeError):
@@ -213,6 +222,7 @@ def library():
             "lbm_cbc_train_destroy": (I32, [VP]),
             "lbm_cbc_train_set_segments": (I32, [VP, DP, DP, P(ctypes.c_int32)]),
             "lbm_cbc_train_set_net": (I32, [VP, P(lbm_cbc_net)]),
+            "lbm_cbc_train_set_nn": (I32, [VP, P(lbm_nn9_net)]),
             "lbm_cbc_train_set_segment_params": (I32, [VP, DP, DP]),
             "lbm_cbc_train_gradient": (I32, [VP, DP, DP]),
             "lbm_cbc_train_step": (I32, [VP, I64]),
@@ -700,8 +710,22 @@ def lbm_cbc_train_set_net(t, net):
     return _check(st, "lbm_cbc_train_set_net")
 
 
-def lbm_cbc_train_gradient(t):
-    g = np.zeros(LBM_CBC_NPARAMS)
+def lbm_cbc_train_set_nn(t, net):
+    """The Eq. 16 network (dict w1 .. b3, mu_in, sd_in, mu_out, sd_out)."""
+    keep = {k: np.ascontiguousarray(net[k], dtype=np.float32).reshape(-1)
+            for k in ("w1", "b1", "w2", "b2", "w3", "b3")}
+    n = lbm_nn9_net(*[keep[k].ctypes.data_as(_FP) for k in ("w1", "b1", "w2", "b2", "w3", "b3")],
+                    (ctypes.c_float * 9)(*np.asarray(net["mu_in"], np.float32)),
+                    (ctypes.c_float * 9)(*np.asarray(net["sd_in"], np.float32)),
+                    (ctypes.c_float * 3)(*np.asarray(net["mu_out"], np.float32)),
+                    (ctypes.c_float * 3)(*np.asarray(net["sd_out"], np.float32)))
+    st = library().lbm_cbc_train_set_nn(t, ctypes.byref(n))
+    del keep
+    return _check(st, "lbm_cbc_train_set_nn")
+
+
+def lbm_cbc_train_gradient(t, nparams=LBM_CBC_NPARAMS):
+    g = np.zeros(nparams)
     loss = ctypes.c_double()
     _check(library().lbm_cbc_train_gradient(t, ctypes.byref(loss), _dptr(g)),
            "lbm_cbc_train_gradient")
@@ -718,8 +742,8 @@ def lbm_cbc_train_loss(t):
     return v.value
 
 
-def lbm_cbc_train_get_weights(t):
-    w = np.zeros(LBM_CBC_NPARAMS, np.float32)
+def lbm_cbc_train_get_weights(t, nparams=LBM_CBC_NPARAMS):
+    w = np.zeros(nparams, np.float32)
     _check(library().lbm_cbc_train_get_weights(t, w.ctypes.data_as(_FP)),
            "lbm_cbc_train_get_weights")
     return w
@@ -732,10 +756,11 @@ def lbm_cbc_train_final_state(t, seg, ny, width):
     return out
 
 
-def cbc_unflatten(v):
-    """Split a flat 662-vector (w1, b1, w2, b2, w3, b3 order) into arrays."""
+def cbc_unflatten(v, shapes=None):
+    """Split a flat parameter vector (w1, b1, w2, b2, w3, b3 order: 662 for
+    the tuning network, 683 with NN9_PARAM_SHAPES) into arrays."""
     out, o = {}, 0
-    for k, shp in CBC_PARAM_SHAPES.items():
+    for k, shp in (shapes or CBC_PARAM_SHAPES).items():
         n = int(np.prod(shp))
         out[k] = np.asarray(v[o:o + n]).reshape(shp)
         o += n
@@ -743,14 +768,15 @@ def cbc_unflatten(v):
 
 
 class CbcTrainer:
-    """Closed-loop trainer of the CBC tuning network on the current device.
+    """Closed-loop trainer on the current device: of the CBC tuning network
+    (outlet "cbc") or of the Eq. 16 reconstruction network (outlet "nn").
 
     a0 [n_seg][9][ny][2 n_max + 3]: start states of the segments (the last
     columns of the truncated lattice); ref [n_seg][3][ny][n_max]: reference
     rho, u, v at step n_t, right-aligned; n_t [n_seg]."""
 
-    def __init__(self, a0, ref, n_t, net, *, tau, mach, length, rho_inf=1.0, precision="fp32",
-                 lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
+    def __init__(self, a0, ref, n_t, net, *, tau, mach=0.0, length=1.0, rho_inf=1.0,
+                 precision="fp32", lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, outlet="cbc"):
         import torch
         a0 = np.asarray(a0)
         n_seg, _, ny, width = a0.shape
@@ -767,7 +793,8 @@ class CbcTrainer:
         self.t = lbm_cbc_train_create(self.params, self.workspace.data_ptr(), nbytes)
         _live.add(self)
         lbm_cbc_train_set_segments(self.t, a0, ref, n_t)
-        lbm_cbc_train_set_net(self.t, net)
+        self.outlet = outlet
+        self.set_net(net)
 
     def close(self):
         """Wait for the queued work and release the native object (also at
@@ -780,7 +807,14 @@ class CbcTrainer:
     __del__ = close
 
     def set_net(self, net):
-        lbm_cbc_train_set_net(self.t, net)
+        if self.outlet == "nn":
+            lbm_cbc_train_set_nn(self.t, net)
+        else:
+            lbm_cbc_train_set_net(self.t, net)
+
+    def _shapes(self):
+        return (NN9_PARAM_SHAPES, LBM_NN9_NPARAMS) if self.outlet == "nn" else \
+            (CBC_PARAM_SHAPES, LBM_CBC_NPARAMS)
 
     def set_segment_params(self, tau=None, mach=None):
         """Per-segment relaxation time and Mach number (arrays of n_seg)."""
@@ -788,8 +822,9 @@ class CbcTrainer:
 
     def gradient(self):
         """(loss, {w1: .., b3: ..}) of the current weights."""
-        loss, g = lbm_cbc_train_gradient(self.t)
-        return loss, cbc_unflatten(g)
+        shapes, n = self._shapes()
+        loss, g = lbm_cbc_train_gradient(self.t, n)
+        return loss, cbc_unflatten(g, shapes)
 
     def step(self, n=1):
         lbm_cbc_train_step(self.t, n)
@@ -798,7 +833,8 @@ class CbcTrainer:
         return lbm_cbc_train_loss(self.t)
 
     def weights(self):
-        return cbc_unflatten(lbm_cbc_train_get_weights(self.t))
+        shapes, n = self._shapes()
+        return cbc_unflatten(lbm_cbc_train_get_weights(self.t, n), shapes)
 
     def final_state(self, seg):
         return lbm_cbc_train_final_state(self.t, seg, self.ny, self.width)
