@@ -445,6 +445,32 @@ def run_studies(which, scale, nn_switch=0, mass_bound=1e-2, study_seeds=(2,)):
     nets = None if which in ("train", "all") else load_networks()
     if nets is None:
         nets = train_study(scale)
+    if which in ("nn_train", "all"):
+        res = experiments.nn_rollout_training_study(
+            nets["paper_9x20"], adam_steps=n(5000), eval_steps=n(150_000),
+            eval_seeds=study_seeds, progress=_progress)
+        with open(os.path.join(RESULTS, "nn_rollout_training.json"), "w") as f:
+            json.dump(_jsonable(res), f, indent=1)
+        print(json.dumps({"nn_train": _jsonable({
+            k: res[k] for k in ("loss_before", "loss_after", "val_loss_before", "val_loss_after",
+                                "zou_he_loss", "zou_he_val_loss", "ms_per_adam_step")}),
+            "nn_train_rel_err_mean": _jsonable({re: r["rel_err_mean"]
+                                                for re, r in res["evaluation"].items()})}),
+            flush=True)
+        if which == "nn_train":
+            return
+    if which in ("nn_drift", "all"):
+        with open(os.path.join(RESULTS, "nn_rollout_training.json")) as f:
+            trained = {k: np.asarray(v, np.float64) for k, v in json.load(f)["network"].items()}
+        res = experiments.drift_trace({
+            "rollout_m0.01": (trained, 1e-2, 0), "rollout_m0.01_after_zou_he": (trained, 1e-2, 60_000),
+            "rollout_m0.001": (trained, 1e-3, 0), "logged_m0.01": (nets["paper_9x20"], 1e-2, 0),
+            "zou_he": (None, 0.0, 0)}, steps=n(150_000), every=max(1, n(10_000)),
+            progress=_progress)
+        with open(os.path.join(RESULTS, "nn_drift.json"), "w") as f:
+            json.dump(_jsonable(res), f, indent=1)
+        if which == "nn_drift":
+            return
     if which in ("scaling", "all"):
         res = experiments.scaling_study(nets["paper_9x20"], steps=n(150_000), progress=_progress,
                                         mass_bound=3e-4)
@@ -495,7 +521,8 @@ def main():
     ap.add_argument("--big-steps", type=int, default=400)
     ap.add_argument("--no-cpu-all-cores", action="store_true")
     ap.add_argument("--study", choices=["train", "nn", "naca", "vortex", "cbc_train",
-                                        "cbc_train_mach", "scaling", "all"],
+                                        "cbc_train_mach", "nn_train", "nn_drift", "scaling",
+                                        "all"],
                     default=None,
                     help="also run the truncated-domain outflow study (training data, "
                          "training, neural vs Zou-He outflow) and/or the NACA0012 study; "

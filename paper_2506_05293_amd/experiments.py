@@ -20,6 +20,10 @@ results; nothing here computes the method itself.
   cbc_training_study  closed-loop training of the tuning network of the
                     characteristic outlet on reference segments (Sec. 4.2),
                     then the vortex comparison with the trained network.
+  nn_rollout_training_study  closed-loop training of the Eq. 16 network on
+                    segments of the long cylinder run (the Sec. 4.2
+                    procedure), then the truncated-domain comparison.
+  drift_trace       mass balance of a neural outflow over a long run.
   scaling_study     diffusive scaling sweep of the truncated cylinder.
 """
 import time
@@ -189,7 +193,7 @@ def train_network(x, t, n_in=27, hidden=64, steps=20_000, batch=4096, lr=1e-3, s
 
 def outflow_study(networks, re_list=(100.0, 200.0, 400.0), steps=150_000, mass_bound=1e-2,
                   sweep=(8, 12, 16, 24, 32), reference_d=40, progress=_noop, nn_switch=0,
-                  seeds=(2,)):
+                  seeds=(2,), collision="mrt"):
     """Truncated cylinder lattices (D = 64, 8 D downstream) with each neural
     outflow of `networks` (name -> weights) and with Zou & He, against the
     40 D Zou & He reference; Zou & He length sweep for the cost of an answer
@@ -197,24 +201,28 @@ def outflow_study(networks, re_list=(100.0, 200.0, 400.0), steps=150_000, mass_b
     each run is compared with the reference of the same seed, and the
     relative errors are given per seed and as mean and sample standard
     deviation over the seeds (the reference's own spread over seeds is the
-    averaging uncertainty of the statistics window).  `progress(name, res)`
-    is called after each run."""
+    averaging uncertainty of the statistics window).  Every lattice uses
+    `collision`; `mass_bound` is one fallback bound for every network or a
+    dict name -> bound.  `progress(name, res)` is called after each run."""
+    bounds = mass_bound if isinstance(mass_bound, dict) else {k: mass_bound for k in networks}
     out = {}
     for re in re_list:
         refs = {}
         runs = {f"nn_{k}_8d": {} for k in networks}
         runs.update({f"zh_{d}d": {} for d in sweep})
         for seed in seeds:
-            refs[seed] = run_case(workloads.truncated_cylinder(reference_d, re=re), steps, seed=seed)
+            refs[seed] = run_case(workloads.truncated_cylinder(reference_d, re=re), steps, seed=seed,
+                                  collision=collision)
             progress(f"Re {re:g} seed {seed} reference {reference_d} D", refs[seed])
             for name, P in networks.items():
                 runs[f"nn_{name}_8d"][seed] = run_case(workloads.truncated_cylinder(8, re=re), steps,
-                                                       network=P, mass_bound=mass_bound,
-                                                       nn_switch=nn_switch, seed=seed)
+                                                       network=P, mass_bound=bounds[name],
+                                                       nn_switch=nn_switch, seed=seed,
+                                                       collision=collision)
                 progress(f"Re {re:g} seed {seed} neural {name} 8 D", runs[f"nn_{name}_8d"][seed])
             for d in sweep:
                 runs[f"zh_{d}d"][seed] = run_case(workloads.truncated_cylinder(d, re=re), steps,
-                                                  seed=seed)
+                                                  seed=seed, collision=collision)
                 progress(f"Re {re:g} seed {seed} Zou-He {d} D", runs[f"zh_{d}d"][seed])
         per_seed = {c: {s: (observables.relative_errors(r, refs[s])
                             if "st" in r and "st" in refs[s] else None) for s, r in rs.items()}
@@ -510,6 +518,228 @@ def cbc_training_study(n_ts=(5, 10, 25), starts=tuple(range(1, 551, 5)), adam_st
             "network": {k: (np.asarray(v).tolist() if isinstance(v, np.ndarray) else v)
                         for k, v in trained.items()},
             "vortex": ev, "trained_flows": trained_flows, "held_out": held_out}
+
+
+def _cylinder_segments(re, seed, n_ts, starts, reference_d=40, cut_d=8, precision="fp32",
+                       progress=_noop):
+    """Segments of the truncated cylinder cut from its long BGK reference run
+    (Zou & He outlet reference_d diameters behind the centre, initial noise
+    of `seed`).  The truncated lattice ends cut_d diameters behind the
+    centre, at column L - 1 = nx_cut - 1.  At each step of `starts`: the
+    post-collision state of the 2 n_max + 3 columns before nx_cut; for each
+    n_t of n_ts the reference rho, u, v at step start + n_t over the n_t
+    columns before nx_cut, right-aligned in n_max columns.  Also the
+    relaxation time and the inlet velocity of the flow."""
+    ref_case = workloads.truncated_cylinder(reference_d, re=re)
+    nx_cut = workloads.truncated_cylinder(cut_d, re=re)["nx"]
+    n_max = max(n_ts)
+    w = 2 * n_max + 3
+    lat = lbm.Lattice(ref_case["mask"], ref_case["tau"], precision=precision, collision="bgk",
+                      lateral="periodic", u_in=ref_case["u_in"], noise_amp=1e-4, seed=seed)
+    ny = ref_case["mask"].shape[0]
+    a0s, refs, nts = [], [], []
+    t = 0
+    t0 = time.perf_counter()
+    for s0 in starts:
+        if s0 < t:
+            raise ValueError("starts must be increasing and at least n_max apart")
+        lat.step(s0 - t)
+        t = s0
+        a0 = lat.populations()[:, :, nx_cut - w:nx_cut].copy()
+        if not np.all(np.isfinite(a0)):
+            raise RuntimeError(f"reference run at Re {re:g} is not finite at step {s0}")
+        for n_t in sorted(n_ts):
+            lat.step(s0 + n_t - t)
+            t = s0 + n_t
+            r = np.zeros((3, ny, n_max))
+            for c, a in enumerate(lat.macroscopic()):
+                r[c, :, n_max - n_t:] = a[:, nx_cut - n_t:nx_cut]
+            a0s.append(a0)
+            refs.append(r)
+            nts.append(n_t)
+    progress(f"nn training: {len(starts)} reference states at Re {re:g} "
+             f"({time.perf_counter() - t0:.1f} s)", {})
+    del lat
+    return a0s, refs, nts, ref_case["tau"], ref_case["u_in"]
+
+
+def _zouhe_segment_loss(a0s, refs, nts, taus, u_in, precision="fp32"):
+    """Mean over segments of the training loss that the Zou & He outlet
+    gets on the same segments: each start state advanced n_t steps on a
+    lattice of its own columns (BGK, periodic rows, velocity inlet, Zou &
+    He pressure outlet), then the MSE of rho and of (u, v) against the
+    reference over the n_t columns before the outlet."""
+    ny, w = a0s[0].shape[1:]
+    lats, total = {}, 0.0
+    for a0, ref, n_t, tau in zip(a0s, refs, nts, taus):
+        if tau not in lats:
+            lats[tau] = lbm.Lattice(np.zeros((ny, w), np.uint8), tau, precision=precision,
+                                    collision="bgk", lateral="periodic", u_in=u_in,
+                                    noise_amp=0.0)
+        lat = lats[tau]
+        lat.write_populations(a0)
+        lat.step(n_t)
+        rho, u, v = (a[:, w - n_t:] for a in lat.macroscopic())
+        r = ref[:, :, ref.shape[2] - n_t:]
+        total += np.mean((rho - r[0]) ** 2) + np.mean((u - r[1]) ** 2 + (v - r[2]) ** 2)
+    del lats
+    return total / len(a0s)
+
+
+def nn_rollout_training_study(network, train_re=(100.0, 200.0), n_ts=(5, 10, 25),
+                              starts=tuple(range(90_000, 109_200, 100)),
+                              val_starts=tuple(range(130_000, 134_800, 100)),
+                              adam_steps=5000, lr=2e-4, train_seed=1, precision="fp32",
+                              eval_re=(100.0, 150.0, 200.0), eval_steps=150_000,
+                              eval_seeds=(2, 3, 4), sweep=(8, 12, 16, 24),
+                              mass_bounds=(1e-2, 1e-3, 3e-4), progress=_noop):
+    """Closed-loop training of the Eq. 16 reconstruction network (the
+    procedure of Sec. 4.2 applied to the network of Sec. 3.1), then the
+    truncated-domain comparison.  The truncated cylinder (D = 64, outlet 8 D
+    behind the centre) takes its segments from the 40 D BGK reference run at
+    each Reynolds number of train_re (noise seed train_seed): start states
+    at the steps `starts` (during developed shedding), n_t of n_ts, with the
+    flow's own relaxation time.  `network` (a 9-20-20-3 network fitted to
+    logged samples, Eq. 17) is the starting point and keeps its input and
+    output standardisation; Adam on the full set of segments.  The loss is
+    also given on segments from the later window `val_starts` that training
+    never sees, and for the Zou & He outlet on both sets.  Afterwards
+    outflow_study under BGK at eval_re (each with seeds eval_seeds, none of
+    them the training seed): the trained and the starting network at 8 D,
+    each with every fallback density bound of mass_bounds, against the 40 D
+    reference, and the Zou & He length sweep.  (BGK at
+    Re 400, tau = 0.524, diverges on this lattice: the study stays at
+    Re <= 200, where the evaluation's Re 150 is not a training flow.)"""
+    a0s, refs, nts, taus = [], [], [], []
+    va0s, vrefs, vnts, vtaus = [], [], [], []
+    u_in = None
+    for re in train_re:
+        a, r, n, tau, u_in = _cylinder_segments(re, train_seed, n_ts,
+                                                tuple(starts) + tuple(val_starts),
+                                                precision=precision, progress=progress)
+        k = len(starts) * len(n_ts)
+        a0s += a[:k]
+        refs += r[:k]
+        nts += n[:k]
+        taus += [tau] * k
+        va0s += a[k:]
+        vrefs += r[k:]
+        vnts += n[k:]
+        vtaus += [tau] * (len(n) - k)
+        del a, r
+    net0 = {k: np.asarray(network[k], np.float32).astype(np.float64)
+            for k in ("w1", "b1", "w2", "b2", "w3", "b3", "mu_in", "sd_in", "mu_out", "sd_out")}
+
+    def trainer(a, r, n, tt, **kw):
+        t = lbm.CbcTrainer(np.stack(a), np.stack(r), np.array(n, np.int32), net0, tau=tt[0],
+                           precision=precision, outlet="nn", **kw)
+        t.set_segment_params(tt)
+        return t
+
+    zh_train = _zouhe_segment_loss(a0s, refs, nts, taus, u_in, precision)
+    zh_val = _zouhe_segment_loss(va0s, vrefs, vnts, vtaus, u_in, precision)
+    progress(f"nn training: Zou & He loss {zh_train:.4e} (training), {zh_val:.4e} (held out)", {})
+    tr = trainer(a0s, refs, nts, taus, lr=lr, eps=1e-16)
+    loss0, _ = tr.gradient()
+    history = [(0, loss0)]
+    _sync()
+    t0 = time.perf_counter()
+    chunk = max(1, adam_steps // 20)
+    done = 0
+    while done < adam_steps:
+        k = min(chunk, adam_steps - done)
+        tr.step(k)
+        done += k
+        history.append((done, tr.loss()))
+        progress(f"nn training: {done} Adam steps, loss {history[-1][1]:.4e}", {})
+    _sync()
+    train_s = time.perf_counter() - t0
+    trained = dict(net0, **tr.weights())
+    loss1, _ = tr.gradient()
+    del tr
+    val = trainer(va0s, vrefs, vnts, vtaus)
+    val_before = val.gradient()[0]
+    val.set_net(trained)
+    val_after = val.gradient()[0]
+    del val
+    per_nt = {}
+    for n_t in n_ts:
+        idx = [i for i, v in enumerate(nts) if v == n_t]
+        sub = trainer([a0s[i] for i in idx], [refs[i] for i in idx], [n_t] * len(idx),
+                      [taus[i] for i in idx])
+        before = sub.gradient()[0]
+        sub.set_net(trained)
+        per_nt[n_t] = {"before": before, "after": sub.gradient()[0],
+                       "zou_he": _zouhe_segment_loss([a0s[i] for i in idx],
+                                                     [refs[i] for i in idx], [n_t] * len(idx),
+                                                     [taus[i] for i in idx], u_in, precision)}
+        del sub
+    n_seg, n_val = len(nts), len(vnts)
+    del a0s, refs, va0s, vrefs
+    progress(f"nn training: loss {loss0:.4e} -> {loss1:.4e}, held out {val_before:.4e} -> "
+             f"{val_after:.4e} ({train_s:.1f} s)", {})
+    nets, bounds = {}, {}
+    for b in mass_bounds:
+        for name, P in (("logged", net0), ("rollout", trained)):
+            nets[f"{name}_m{b:g}"] = P
+            bounds[f"{name}_m{b:g}"] = b
+    ev = outflow_study(nets, re_list=eval_re, steps=eval_steps, mass_bound=bounds, sweep=sweep,
+                       progress=progress, seeds=eval_seeds, collision="bgk")
+    return {"train_re": list(train_re), "train_seed": train_seed, "n_ts": list(n_ts),
+            "starts": [int(starts[0]), int(starts[-1]), len(starts)],
+            "val_starts": [int(val_starts[0]), int(val_starts[-1]), len(val_starts)],
+            "segments": n_seg, "val_segments": n_val, "adam_steps": adam_steps, "lr": lr,
+            "precision": precision, "train_seconds": train_s,
+            "ms_per_adam_step": 1e3 * train_s / max(adam_steps, 1),
+            "loss_before": loss0, "loss_after": loss1, "loss_history": history,
+            "val_loss_before": val_before, "val_loss_after": val_after,
+            "zou_he_loss": zh_train, "zou_he_val_loss": zh_val, "loss_per_n_t": per_nt,
+            "mass_bounds": list(mass_bounds),
+            "network": {k: np.asarray(v).tolist() for k, v in trained.items()},
+            "evaluation": ev}
+
+
+def drift_trace(networks, re=200.0, cut_d=8, steps=150_000, every=10_000, seed=2,
+                collision="bgk", progress=_noop):
+    """Mass balance of the truncated cylinder with a neural outflow over a
+    long run: for each entry name -> (weights, mass bound, switch step) of
+    `networks` (Zou & He before the switch step), every `every` steps the
+    mean of rho - 1 over the fluid, the mean outlet velocity u_x and density
+    and the outlet rows per step that fell back to Zou & He since the last
+    record; the trace stops at the first non-finite record."""
+    case = workloads.truncated_cylinder(cut_d, re=re)
+    fluid = case["mask"] == 0
+    out = {}
+    for name, (P, bound, switch) in networks.items():
+        lat = lbm.Lattice(case["mask"], case["tau"], precision="fp32", collision=collision,
+                          lateral="periodic", u_in=case["u_in"], noise_amp=1e-4, seed=seed,
+                          history_cap=steps, **(RATES if collision == "mrt" else {}))
+        t, fb0, rows = 0, 0, []
+        if switch:
+            lat.step(switch)
+            t = switch
+            fb0 = lat.forces(allow_unstable=True).n_fallback
+        if P is not None:
+            lat.set_outflow_nn(P, bound)
+        while t < steps:
+            k = min(every, steps - t)
+            lat.step(k)
+            t += k
+            f = lat.forces(allow_unstable=True)
+            rho, ux, _ = lat.macroscopic()
+            rows.append({"step": t, "mean_rho_minus_1": float(np.mean(rho[fluid]) - 1.0),
+                         "outlet_ux": float(np.mean(ux[:, -1])),
+                         "outlet_rho_minus_1": float(np.mean(rho[:, -1]) - 1.0),
+                         "fallback_per_step": (f.n_fallback - fb0) / k,
+                         "nonfinite": int(f.nonfinite)})
+            fb0 = f.n_fallback
+            if f.nonfinite:
+                break
+        del lat
+        out[name] = {"mass_bound": bound, "switch": switch, "u_in": case["u_in"],
+                     "trace": rows}
+        progress(f"drift {name}: {len(rows)} records, last {rows[-1]}", {})
+    return out
 
 
 def scaling_study(network, re_list=(10.0, 20.0, 50.0, 100.0, 200.0), tau=0.6, steps=150_000,
