@@ -66,7 +66,8 @@ enum { LBM_LATERAL_WALLS = 0, LBM_LATERAL_PERIODIC = 1 };
 enum { LBM_X_INOUT = 0, LBM_X_PERIODIC = 1 };
 enum { LBM_OUT_ZOUHE = 0, LBM_OUT_NN = 1, LBM_OUT_CBC = 2 };
 /* Kernel schedule of lbm_step (results agree to rounding, see lbm_step). */
-enum { LBM_LAUNCH_PAIRS = 0, LBM_LAUNCH_SINGLE = 1 };
+enum { LBM_LAUNCH_PAIRS = 0, LBM_LAUNCH_SINGLE = 1, LBM_LAUNCH_PAIRS_PLAIN = 2,
+       LBM_LAUNCH_PAIRS_HELD = 3 };
 /* Bulk tile of the one-step kernel: chosen by lattice size, or forced. */
 enum { LBM_PATH_AUTO = 0, LBM_PATH_SCALAR = 1, LBM_PATH_VECTOR = 2 };
 
@@ -89,6 +90,12 @@ enum { LBM_PATH_AUTO = 0, LBM_PATH_SCALAR = 1, LBM_PATH_VECTOR = 2 };
  *   launch       LBM_LAUNCH_PAIRS (0, the default): two time steps per kernel
  *                launch wherever the outflow has a two-step form (see
  *                lbm_step); LBM_LAUNCH_SINGLE: one launch per time step.
+ *                Two-step launches walk their strips in one of two orders,
+ *                chosen by lattice size (the stores of a row held back by
+ *                one row above 200 MB per population buffer, FP32 and FP64
+ *                only); LBM_LAUNCH_PAIRS_PLAIN and LBM_LAUNCH_PAIRS_HELD
+ *                force one (HELD: not with LBM_FP16_OFFSET).  Every
+ *                two-step order gives the same results bit for bit.
  *   bulk_path    tile of the one-step kernel: LBM_PATH_AUTO (0: one node per
  *                thread below 12M nodes, four per lane above), or forced
  *                LBM_PATH_SCALAR / LBM_PATH_VECTOR.  Same results.

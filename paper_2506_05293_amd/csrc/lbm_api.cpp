@@ -197,8 +197,10 @@ lbm_status check_params(const lbm_params* p) {
   if (p->lateral != LBM_LATERAL_WALLS && p->lateral != LBM_LATERAL_PERIODIC)
     return fail(LBM_EINVAL, "bad lateral %d", p->lateral);
   if (p->xbc != LBM_X_INOUT && p->xbc != LBM_X_PERIODIC) return fail(LBM_EINVAL, "bad xbc %d", p->xbc);
-  if (p->launch != LBM_LAUNCH_PAIRS && p->launch != LBM_LAUNCH_SINGLE)
+  if (p->launch < LBM_LAUNCH_PAIRS || p->launch > LBM_LAUNCH_PAIRS_HELD)
     return fail(LBM_EINVAL, "bad launch %d", p->launch);
+  if (p->launch == LBM_LAUNCH_PAIRS_HELD && p->precision == LBM_FP16_OFFSET)
+    return fail(LBM_EINVAL, "LBM_LAUNCH_PAIRS_HELD needs LBM_FP64 or LBM_FP32_OFFSET");
   if (p->bulk_path < LBM_PATH_AUTO || p->bulk_path > LBM_PATH_VECTOR)
     return fail(LBM_EINVAL, "bad bulk_path %d", p->bulk_path);
   if (!(p->tau > 0.5) || !std::isfinite(p->tau)) return fail(LBM_EINVAL, "tau must be > 0.5 (got %g)", p->tau);
@@ -292,6 +294,9 @@ struct lbm_ctx {
     L.pair_out = n_nn ? pair_outlet_blocks(p.ny) : 0;
     L.pair_nx = L.pair_out ? p.nx - pair_outlet_cols() : p.nx;
     L.pair_rows = pair_rows(p.nx, p.ny, lay.pitch * int(elem_size(p.precision)));
+    L.pair_hold = p.launch == LBM_LAUNCH_PAIRS_HELD    ? 1
+                  : p.launch == LBM_LAUNCH_PAIRS_PLAIN ? 0
+                                                       : pair_hold(p.precision, 9 * lay.plane * int64_t(elem_size(p.precision)));
     L.pair_nslots = pair_waves(L.pair_nx, p.ny, L.pair_rows) + L.pair_out * kWaves;
     L.pair_chunk = pair_chunk(L.pair_nx);
     L.nslots = (L.nspecial - 1 - kReducers + lay.ntx * lay.nty) * kWaves;
@@ -477,9 +482,9 @@ lbm_status lbm_step(lbm_ctx* c, int64_t nsteps) {
   if (nsteps < 0) return fail(LBM_EINVAL, "nsteps < 0");
   if (nsteps == 0) return LBM_OK;
   int64_t s = 0;
-  // With params.launch = LBM_LAUNCH_PAIRS, pairs of steps run in one launch
-  // each (the same node arithmetic) whatever the outflow.
-  if (nsteps >= 2 && c->p.launch == LBM_LAUNCH_PAIRS) {
+  // With params.launch other than LBM_LAUNCH_SINGLE, pairs of steps run in
+  // one launch each (the same node arithmetic) whatever the outflow.
+  if (nsteps >= 2 && c->p.launch != LBM_LAUNCH_SINGLE) {
     for (; s + 1 < nsteps; s += 2) {
       const StepLaunch L = c->launch();
       HIP_TRY(launch_pair(L, c->stream));

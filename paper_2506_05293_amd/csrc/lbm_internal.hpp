@@ -105,6 +105,7 @@ struct StepLaunch {
   int pair_out;         // two-step launches: outlet blocks (0: Zou & He in the strips)
   int pair_chunk;       // two-step launches: strip workgroups per chunk dealt to an XCD (0: eighths)
   int pair_rows;        // two-step launches: output rows per strip
+  int pair_hold;        // two-step launches: step-(t+2) stores held one row (pair_hold)
   int nslots;           // partial slots written per step (waves of the
                         // neural and bulk workgroups)
   int xper, yper;
@@ -127,6 +128,9 @@ int pair_waves(int nx, int ny, int rows);
 // Output rows per strip of the two-step kernel for an nx x ny lattice whose
 // rows are pitch_bytes apart.
 int pair_rows(int nx, int ny, int pitch_bytes);
+// Whether the two-step strips hold their stores back by one row, for a
+// lattice whose population buffer holds buffer_bytes.
+int pair_hold(int precision, int64_t buffer_bytes);
 // Two steps per launch with the neural outlet: outlet blocks for ny rows, and
 // the columns at the outlet they take (the strips take the rest).
 int pair_outlet_blocks(int ny);

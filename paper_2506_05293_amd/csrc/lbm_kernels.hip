@@ -20,6 +20,8 @@
 //
 // Memory layout: population q of node (x, y) at q*plane + y*pitch + x, with
 // pitch a multiple of 256 elements; offsets f - w stored in S (f for FP64).
+#include <type_traits>
+
 #include "d2q9_dev.hpp"
 #include "lbm_internal.hpp"
 #include "mlp_dev.hpp"
@@ -641,6 +643,7 @@ hipError_t launch_finalize(const StepLaunch& L, hipStream_t s) {
 // both steps (level 1), the one after commits them in order (level 2), as
 // for single steps.
 constexpr int kPairCols = 60;          // output columns per wave
+constexpr int kPairRowsMin = 12, kPairRowsMax = 18;   // strip heights (pair_rows)
 
 // The value of the lane to the left (lane - 1) or right (lane + 1) by a
 // whole-wave DPP shift (a VALU move; lanes 0 and 63 get no neighbour and are
@@ -735,9 +738,15 @@ struct PairWave {
 // The walk keeps three rows as read (R0..R2, step t), three rows after the
 // first collision (S0..S2, step t+1) and the next row's loads (P).  Row j
 // is fetched at the top of iteration j - 1 and copied into R2 at the top of
-// iteration j.  Measured alternatives at 4096 x 1024 FP32 with 24-row
-// strips (not kept): fetching one row further ahead with a single wait per
-// row (-4 %), holding the step-(t+2) stores for one row (-5 %), rings of 4
+// iteration j.  In the plain walk (HOLD = 0) the fetch reads the row's
+// link-chunk flag and branches on it, and loads and stores share one
+// completion counter, so that wait also waits for the row's own loads and
+// for the stores before them: a wave's loads overlap other waves' work
+// only.  The held walk (HOLD = 1) reads the flags of the whole strip first
+// and issues a row's stores one row late, with the next row's loads; its
+// one wait per row then comes after the row's work (pair_hold chooses).
+// Measured alternatives at 4096 x 1024 FP32 with 24-row strips, in the
+// plain walk (not kept): fetching one row further ahead (-4 %), rings of 4
 // to 6 rows unrolled in registers (-8 to -17 %), one scalar flag load per
 // row (-2 %), a separate path for rows without link words (-4 %; +6 % at
 // 16384 x 4096), FP32 sums of the strip's force terms (+1 %).  The strip
@@ -747,7 +756,7 @@ struct PairWave {
 // MLUPS at 4096 x 1024 and 78 against 107 at 16384 x 4096; non-temporal
 // stores alone were 3 % faster at 4096 x 1024 FP32 only and 5-16 % slower
 // at FP16 and FP64 and at 4096 x 2048, 8192 x 2048 and 16384 x 4096).
-template <typename S, int MRT>
+template <typename S, int MRT, int HOLD>
 __device__ __forceinline__ void pair_strip(const StepLaunch& L, int wave, int slot, double* part) {
   using T = typename Store<S>::T;
   const PairWave<S> w(L, wave);
@@ -758,6 +767,24 @@ __device__ __forceinline__ void pair_strip(const StepLaunch& L, int wave, int sl
   T R0[9], R1[9], R2[9], S0[9], S1[9], S2[9], P[9];
   uint32_t K0 = 0, K1 = 0, K2 = 0, KP = 0;
   double fxa = 0.0, fya = 0.0, dma = 0.0, fxb = 0.0, fyb = 0.0, dmb = 0.0;
+  // HOLD: bit j of lmask says that row y0 - 2 + j is a lattice row whose
+  // 256-column chunk at this lane's column holds link words.  All flags are
+  // loaded here at once, so that no load of the row walk waits on another
+  // and the loads of a row are waited for only after the row's work.
+  static_assert(kPairRowsMax + 4 <= 32, "one flag bit per strip row");
+  uint32_t lmask = 0;
+  if constexpr (HOLD) {
+    uint8_t fl[kPairRowsMax + 4];
+#pragma unroll
+    for (int j = 0; j < kPairRowsMax + 4; ++j) {
+      const int yr = y0 - 2 + j;
+      const bool row_in = L.yper || (yr >= 0 && yr < L.ny);
+      fl[j] = (j < nrow && row_in && col_in) ? L.chunk[w.wrap_row(yr, L) * L.nchunk + w.xs / kChunk]
+                                              : uint8_t(0);
+    }
+#pragma unroll
+    for (int j = 0; j < kPairRowsMax + 4; ++j) lmask |= uint32_t(fl[j] != 0) << j;
+  }
   // row yr (absolute, may lie outside) into P and its link words into KP
   // (where the row's 256-column chunk has any)
   auto fetch = [&](int yr) {
@@ -769,8 +796,26 @@ __device__ __forceinline__ void pair_strip(const StepLaunch& L, int wave, int sl
           reinterpret_cast<const char*>(A + int64_t(q) * L.plane + row) + w.off));
     }
     KP = 0;
-    const bool row_in = L.yper || (yr >= 0 && yr < L.ny);
-    if (row_in && col_in && L.chunk[ys * L.nchunk + w.xs / kChunk]) KP = L.links[row + w.xs];
+    if constexpr (HOLD) {
+      if ((lmask >> (yr - (y0 - 2))) & 1u) KP = L.links[row + w.xs];
+    } else {
+      const bool row_in = L.yper || (yr >= 0 && yr < L.ny);
+      if (row_in && col_in && L.chunk[ys * L.nchunk + w.xs / kChunk]) KP = L.links[row + w.xs];
+    }
+  };
+  // HOLD: the step-(t+2) values of a row (H, at byte offset oh) are stored
+  // with the next row's loads, so that both have that row's work to finish
+  T H[9];
+  uint32_t oh = 0;
+  bool held = false;
+  auto flush = [&]() {
+    if (held) {
+#pragma unroll
+      for (int q = 0; q < 9; ++q)
+        Store<S>::st_cached(reinterpret_cast<S*>(reinterpret_cast<char*>(B + int64_t(q) * L.plane) + oh),
+                            H[q]);
+    }
+    held = false;
   };
   fetch(y0 - 2);
   for (int j = 0; j < nrow; ++j) {
@@ -779,6 +824,7 @@ __device__ __forceinline__ void pair_strip(const StepLaunch& L, int wave, int sl
     for (int q = 0; q < 9; ++q) R2[q] = P[q];
     K2 = KP;
     if (j + 1 < nrow) fetch(yr + 1);
+    if constexpr (HOLD) flush();
     if (j >= 2) {
       // step t+1 at row yr - 1 from rows yr-2 .. yr
       const int y1 = yr - 1;
@@ -806,10 +852,17 @@ __device__ __forceinline__ void pair_strip(const StepLaunch& L, int wave, int sl
         const uint32_t o2 = uint32_t(y2) * uint32_t(L.pitch) * uint32_t(sizeof(S)) + w.off;
         T fx2 = T(0), fy2 = T(0), dm2 = T(0);
         if (out_col && pair_node<T, MRT>(L, K0, y2, S1, g, true, fx2, fy2, dm2)) {
+          if constexpr (HOLD) {
 #pragma unroll
-          for (int q = 0; q < 9; ++q)
-            Store<S>::st_cached(reinterpret_cast<S*>(reinterpret_cast<char*>(B + int64_t(q) * L.plane) + o2),
-                                g[q]);
+            for (int q = 0; q < 9; ++q) H[q] = g[q];
+            oh = o2;
+            held = true;
+          } else {
+#pragma unroll
+            for (int q = 0; q < 9; ++q)
+              Store<S>::st_cached(
+                  reinterpret_cast<S*>(reinterpret_cast<char*>(B + int64_t(q) * L.plane) + o2), g[q]);
+          }
         }
         fxb += double(fx2);
         fyb += double(fy2);
@@ -829,6 +882,7 @@ __device__ __forceinline__ void pair_strip(const StepLaunch& L, int wave, int sl
     K0 = K1;
     K1 = K2;
   }
+  if constexpr (HOLD) flush();
   // one slot per wave and step: [0, n) the first step, [n, 2n) the second
   const int n = L.pair_nslots;
   fxa = wave_sum(fxa); fya = wave_sum(fya); dma = wave_sum(dma);
@@ -1279,7 +1333,7 @@ constexpr int kPairSpecial = (1 + 2 * kReducers + 7) / 8 * 8;
 // OUT: 0 the Zou & He outlet inside the strips; OUTLET_NN or OUTLET_CBC the
 // outlet blocks of the neural or characteristic outflow (the first pair_out
 // workgroups after the reducers).
-template <typename S, int MRT, int OUT>
+template <typename S, int MRT, int OUT, int HOLD>
 __global__ void __launch_bounds__(kBlock) k_step2(const StepLaunch L) {
   const int v = int(blockIdx.x);
   if (v < kPairSpecial) {
@@ -1314,7 +1368,7 @@ __global__ void __launch_bounds__(kBlock) k_step2(const StepLaunch L) {
   // columns are then wave-uniform values and its row addresses scalar
   const int slot = __builtin_amdgcn_readfirstlane((L.pair_out + sb) * kWaves + int(threadIdx.x >> 6));
   if (slot >= L.pair_nslots) return;                  // whole wave
-  pair_strip<S, MRT>(L, slot - L.pair_out * kWaves, slot, part);
+  pair_strip<S, MRT, HOLD>(L, slot - L.pair_out * kWaves, slot, part);
 }
 
 // Flush after the last pair: level 2 of the pair before, then both steps of
@@ -1334,18 +1388,42 @@ __global__ void __launch_bounds__(kBlock) k_finalize2(const StepLaunch L) {
   }
 }
 
-template <typename S, int MRT>
-static hipError_t launch_pair_t(const StepLaunch& L, hipStream_t s) {
+template <typename S, int MRT, int HOLD>
+static hipError_t launch_pair_h(const StepLaunch& L, hipStream_t s) {
   const int blocks = kPairSpecial + (L.pair_nslots + kWaves - 1) / kWaves;
   if (L.pair_out > 0 && L.outlet == OUTLET_NN)
-    hipLaunchKernelGGL((k_step2<S, MRT, OUTLET_NN>), dim3(blocks), dim3(kBlock), 0, s, L);
+    hipLaunchKernelGGL((k_step2<S, MRT, OUTLET_NN, HOLD>), dim3(blocks), dim3(kBlock), 0, s, L);
   else if (L.pair_out > 0 && L.outlet == OUTLET_CBC)
-    hipLaunchKernelGGL((k_step2<S, MRT, OUTLET_CBC>), dim3(blocks), dim3(kBlock), 0, s, L);
+    hipLaunchKernelGGL((k_step2<S, MRT, OUTLET_CBC, HOLD>), dim3(blocks), dim3(kBlock), 0, s, L);
   else if (L.pair_out == 0)
-    hipLaunchKernelGGL((k_step2<S, MRT, 0>), dim3(blocks), dim3(kBlock), 0, s, L);
+    hipLaunchKernelGGL((k_step2<S, MRT, 0, HOLD>), dim3(blocks), dim3(kBlock), 0, s, L);
   else
     return hipErrorInvalidValue;
   return hipGetLastError();
+}
+
+template <typename S, int MRT>
+static hipError_t launch_pair_t(const StepLaunch& L, hipStream_t s) {
+  if constexpr (!std::is_same_v<S, __half>) {
+    if (L.pair_hold) return launch_pair_h<S, MRT, 1>(L, s);
+  }
+  return L.pair_hold ? hipErrorInvalidValue : launch_pair_h<S, MRT, 0>(L, s);
+}
+
+// Whether the strips hold their step-(t+2) stores back by one row (with
+// the link flags of the whole strip read first).  The plain walk waits for
+// the next row's loads (and the stores before them) as soon as it has
+// issued them; the held walk waits for them only after the row's work.
+// That pays where the populations come from HBM, and loses where much of
+// both buffers stays in the 256 MB last-level cache.  Measured (MRT, MLUPS,
+// plain / held): FP32 4096 x 1024 (151 MB per buffer) 111.5k / 102.0k,
+// 6144 x 512 131.6k / 119.4k, 3072 x 1024 131.6k / 119.8k, 4096 x 1536
+// (226 MB) 88.9k / 102.0k, 4096 x 2048 99.6k / 105.5k, 8192 x 2048
+// 106.6k / 109.6k, 8192 x 4096 110.3k / 115.0k, 16384 x 4096 114.0k /
+// 120.9k; FP64 16384 x 4096 60.3k / 66.0k, 4096 x 1024 (302 MB) 52.2k /
+// 51.9k; FP16 16384 x 4096 186.0k / 146.1k (never held).
+int pair_hold(int precision, int64_t buffer_bytes) {
+  return precision != LBM_FP16_OFFSET && buffer_bytes > int64_t(200) * 1000 * 1000;
 }
 
 int pair_waves(int nx, int ny, int rows) {
@@ -1364,7 +1442,6 @@ int pair_waves(int nx, int ny, int rows) {
 // 2048 x 2048 18 rows 108.8k; 8192 x 2048 17 rows 106.7k (12: 109.2k);
 // 16384 x 4096 17 rows 114.0k (16: 115.0k, 24: 110.6k); FP16 4096 x 1024
 // 143.7k (24: 127.6k); FP64 4096 x 1024 52.2k (24: 53.2k).
-constexpr int kPairRowsMin = 12, kPairRowsMax = 18;
 constexpr int kSimds = 256 * 4;      // the MI355X's 256 CUs of four SIMDs each
 int pair_rows(int nx, int ny, int pitch_bytes) {
   const int strips = (nx + kPairCols - 1) / kPairCols;

@@ -58,11 +58,25 @@ def test_workspace_size_scales_with_precision():
 @pytest.mark.parametrize("field,value", [("tau", 0.5), ("tau", float("nan")), ("nx", 4),
                                          ("precision", 7), ("collision", 3), ("u_in", 0.6),
                                          ("rho_out", 0.0), ("history_cap", -1),
-                                         ("launch", 2), ("launch", -1), ("bulk_path", 3),
+                                         ("launch", 4), ("launch", -1), ("bulk_path", 3),
                                          ("bulk_path", -1)])
 def test_bad_parameters_are_rejected(field, value):
     with pytest.raises(lbm.LbmError) as e:
         lbm.lbm_workspace_bytes(_params(**{field: value}))
+    assert e.value.status == lbm.LBM_EINVAL
+
+
+def test_two_step_walks_can_be_forced():
+    # both walks of the two-step kernel take the same workspace; the walk
+    # that holds its stores back has no FP16 form
+    base = lbm.lbm_workspace_bytes(_params())
+    for launch in (lbm.LBM_LAUNCH_PAIRS_PLAIN, lbm.LBM_LAUNCH_PAIRS_HELD):
+        assert lbm.lbm_workspace_bytes(_params(launch=launch)) == base
+    assert lbm.lbm_workspace_bytes(_params(launch=lbm.LBM_LAUNCH_PAIRS_HELD,
+                                           precision=lbm.LBM_FP64)) > 0
+    with pytest.raises(lbm.LbmError) as e:
+        lbm.lbm_workspace_bytes(_params(launch=lbm.LBM_LAUNCH_PAIRS_HELD,
+                                        precision=lbm.LBM_FP16_OFFSET))
     assert e.value.status == lbm.LBM_EINVAL
 
 

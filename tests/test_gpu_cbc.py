@@ -182,7 +182,7 @@ def test_cbc_pairs_equal_single_steps(net):
     cbc = dict(FIXED, net=random_net(3)) if net else FIXED
     mask = geometry.cylinder(61, 43, 14.3, 20.6, 9.0)
     out = {}
-    for launch in ("pairs", "single"):
+    for launch in ("pairs", "pairs_held", "single"):
         g = lbm.Lattice(mask, 0.58, precision="fp64", collision="mrt", lateral="periodic",
                         u_in=0.1, noise_amp=0.0, seed=1, launch=launch, history_cap=81)
         g.init_fields(*vortex_fields(61, 43, 0.1, 61 - 14.5, 43 / 2 - 0.3))
@@ -193,6 +193,9 @@ def test_cbc_pairs_equal_single_steps(net):
     (f1, fx1), (f0, fx0) = out["pairs"], out["single"]
     print("cbc pairs vs single: populations that differ", np.count_nonzero(f1 != f0), flush=True)
     np.testing.assert_array_equal(f1, f0)
+    # the strips' other walk (stores held back one row): the same bits
+    np.testing.assert_array_equal(out["pairs_held"][0], f1)
+    np.testing.assert_array_equal(out["pairs_held"][1], fx1)
     np.testing.assert_allclose(fx1, fx0, rtol=0, atol=1e-12 * np.max(np.abs(fx0)))
 
 

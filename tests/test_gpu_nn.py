@@ -262,7 +262,7 @@ def test_nn_pairs_equal_single_steps(precision, mass_bound):
     P = _f32(random_params(3, w_scale=0.5, out_sd=2e-4))
     _say("nn pairs vs single steps", precision, mass_bound)
     out = {}
-    for launch in ("pairs", "single"):
+    for launch in ("pairs", "pairs_held", "single"):
         g = lbm.Lattice(case["mask"], case["tau"], precision=precision, collision="mrt",
                         lateral="periodic", u_in=case["u_in"], noise_amp=case["noise_amp"],
                         seed=case["seed"], history_cap=81, launch=launch)
@@ -276,6 +276,11 @@ def test_nn_pairs_equal_single_steps(precision, mass_bound):
           "fallbacks", n1, n0, flush=True)
     np.testing.assert_array_equal(f1, f0)
     assert n1 == n0
+    # the strips' other walk (stores held back one row): the same bits
+    fh, nh, (fxh, _) = out["pairs_held"]
+    np.testing.assert_array_equal(fh, f1)
+    assert nh == n1
+    np.testing.assert_array_equal(fxh, fx1)
     if mass_bound < 1:
         assert 0.1 * 81 * 77 < n0 < 0.9 * 81 * 77      # partial fallback
     # force partials are summed in another grouping (FP32: the one-step kernel

@@ -1,16 +1,16 @@
-"""GPU parity of the two-steps-per-launch path of the step (the default
-with the Zou & He outflow, params.launch = LBM_LAUNCH_PAIRS; LBM_LAUNCH_SINGLE
-gives one launch per step): every node takes the single-step node code in
-registers, compiled into another kernel (the compiler may contract
-multiply-adds differently there), and the state between the two steps is
+"""GPU parity of the two-steps-per-launch path of the step (the default,
+params.launch = LBM_LAUNCH_PAIRS; LBM_LAUNCH_SINGLE gives one launch per
+step).  Every node takes the single-step node code in registers with the
+same explicit fused multiply-adds, and the state between the two steps is
 rounded to the storage precision as a store and reload would round it, so
-the populations agree with one launch per step to rounding: 1e-12 relative
-in FP64, 1e-6 absolute in FP32, and in FP16 offsets within two FP16 units
-in the last place at no more than 1e-3 of the values after 81 steps; the
-force and mass partials are summed in another grouping, so the force
-history agrees to 1e-12 of its scale in FP64, 1e-5 in FP32 (the
-single-step path's own bound against the oracle) and 2e-3 in FP16; and
-against the oracle as the single-step path does."""
+the populations equal those of one launch per step bit for bit in FP64,
+FP32 and FP16 over odd step counts and read-outs.  The force and mass
+partials are summed in another grouping: the force history agrees to 1e-12
+of its scale in FP64 and 1e-5 in FP32 and FP16 (the one-step kernel adds a
+wave's node terms in FP32 first).  The two walks of the strips (the stores
+of a row held back one row, or not; LBM_LAUNCH_PAIRS_HELD and
+LBM_LAUNCH_PAIRS_PLAIN force one) give the same populations and the same
+force history bit for bit.  Against the oracle as the single-step path."""
 import numpy as np
 import pytest
 
@@ -65,6 +65,46 @@ def test_pairs_equal_single_steps(name, precision):
     print("force history: max difference / scale", np.max(np.abs(fx1 - fx0)) / scale, flush=True)
     np.testing.assert_allclose(fx1, fx0, rtol=0, atol=tol * scale)
     np.testing.assert_allclose(fy1, fy0, rtol=0, atol=tol * scale)
+
+
+@pytest.mark.parametrize("name,precision", [("c1_bgk", "fp64"), ("ragged_mrt_periodic", "fp32"),
+                                            ("ragged_mrt_walls", "fp64"), ("c1_mrt", "fp32")])
+def test_held_walk_equals_plain_walk(name, precision):
+    # the two walks of the two-step kernel differ only in when a row's
+    # stores are issued and how the link flags are read: the same
+    # populations and the same force partials, bit for bit
+    case = {"c1_bgk": cases.c1(75.0), "ragged_mrt_periodic": cases.ragged("mrt", "periodic"),
+            "ragged_mrt_walls": cases.ragged("mrt", "walls"), "c1_mrt": cases.c1(100.0, "mrt")}[name]
+    _say("held vs plain walk", name, precision)
+    out = {}
+    for launch in ("pairs_held", "pairs_plain"):
+        g = _gpu(case, precision, 81, launch)
+        for n in (40, 7, 34):
+            g.step(n)
+        out[launch] = (g.populations(), g.force_history())
+    (f1, (fx1, fy1)), (f0, (fx0, fy0)) = out["pairs_held"], out["pairs_plain"]
+    print("held vs plain: populations that differ", np.count_nonzero(f1 != f0), flush=True)
+    np.testing.assert_array_equal(f1, f0)
+    np.testing.assert_array_equal(fx1, fx0)
+    np.testing.assert_array_equal(fy1, fy0)
+
+
+def test_held_walk_full_size_by_default():
+    # 4096 x 1536 FP32 holds 226 MB per population buffer, past the size
+    # from which the default two-step launch holds its stores: four steps
+    # equal four single-step launches bit for bit
+    case = cases.c2(4096, 1536)
+    _say("held walk by default, 4096 x 1536 fp32")
+    rho, u = workloads.smooth_fields(case["mask"].shape, case["u_in"], amp=0.02, seed=17)
+    out = {}
+    for launch in ("pairs", "single"):
+        g = _gpu(case, "fp32", 4, launch)
+        g.init_fields(rho, u[0], u[1])
+        g.step(4)
+        out[launch] = g.populations()
+        del g
+    print("populations that differ", np.count_nonzero(out["pairs"] != out["single"]), flush=True)
+    np.testing.assert_array_equal(out["pairs"], out["single"])
 
 
 def test_pairs_fp64_against_oracle():
