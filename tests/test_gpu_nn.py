@@ -161,6 +161,8 @@ def test_nn_outflow_full_size_steps(schedule):
 
 @pytest.mark.parametrize("precision,tol", [("fp32", 5e-6), ("fp16", 2e-4)])
 def test_naca_full_size_with_neural_outflow(precision, tol, schedule):
+    if schedule == "pairs_held" and precision == "fp16":
+        pytest.skip("the held walk has no FP16 form (LBM_LAUNCH_PAIRS_HELD rejects FP16)")
     # the NACA0012 lattice of the airfoil study (chord 256, AoA 4 deg, 3 chords
     # behind the trailing edge: 3072 x 1024, MRT, Re 1000) with a network of the
     # paper's shape at the outlet, FP32 and FP16 offsets: three steps from the

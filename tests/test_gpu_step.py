@@ -139,6 +139,8 @@ def test_inlet_profile_parity():
 @pytest.mark.parametrize("precision,drho_tol,du_tol", [("fp32", 1e-5, 1e-4), ("fp16", 2e-2, 2e-2)])
 @pytest.mark.parametrize("re,collision", [(75.0, "bgk"), (100.0, "mrt")])
 def test_c1_offset_storage(precision, drho_tol, du_tol, re, collision, schedule):
+    if schedule == "pairs_held" and precision == "fp16":
+        pytest.skip("the held walk has no FP16 form (LBM_LAUNCH_PAIRS_HELD rejects FP16)")
     case = cases.c1(re, collision)
     _say("c1", precision, collision, re, 2000)
     g = _gpu(case, precision, history_cap=2000)
