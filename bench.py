@@ -37,7 +37,7 @@ HBM_PEAK_GBS = 8000.0
 CSRC = os.path.join(ROOT, "paper_2506_05293_amd", "csrc")
 RESULTS = os.path.join(ROOT, "results")
 # the Zou & He step runs two lattice steps per launch of this kernel
-STEP_KERNEL, STEPS_PER_LAUNCH = "k_step2<", 2
+STEP_KERNEL, STEPS_PER_LAUNCH = "k_step3<", 3
 CALIB_BYTES = 151 * 1024 * 1024     # bytes read (and written) by the calibration copy
 
 
@@ -124,12 +124,13 @@ def step_roofline(nodes, ms_per_step, spl, precision, traffic_per_step):
             "traffic_frac": None if tr is None else tr / HBM_PEAK_GBS,
             "bytes_per_node_step": bpn, "steps_per_launch": spl,
             "algorithmic_bytes_per_launch": bpn * nodes * spl, "launch_ms": launch_ms,
-            # a launch of two steps needs to move the populations only once:
+            # a launch of spl steps needs to move the populations only once:
             # its own minimum is bpn / spl per node-step
             "launch_minimum_bytes_per_node_step": bpn / spl,
             "launch_minimum_frac": gbs / spl / HBM_PEAK_GBS,
-            "kernel": ("k_step2 (two fused pull stream-collide steps per launch)" if spl == 2
-                       else "k_step (fused pull stream-collide)")}
+            "kernel": {3: "k_step3 (three fused pull stream-collide steps per launch)",
+                       2: "k_step2 (two fused pull stream-collide steps per launch)"}.get(
+                           spl, "k_step (fused pull stream-collide)")}
 
 
 def c2_case(nx, ny):
@@ -501,7 +502,7 @@ def run_studies(which, scale, nn_switch=0, mass_bound=1e-2, study_seeds=(2,)):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--steps", type=int, default=2001)
     ap.add_argument("--warmup", type=int, default=200)
     ap.add_argument("--nx", type=int, default=4096)
     ap.add_argument("--ny", type=int, default=1024)
@@ -514,11 +515,11 @@ def main():
     ap.add_argument("--accuracy-steps", type=int, default=300_000,
                     help="steps of the FP32-vs-FP64 runs (the statistics window, the last "
                          "40 %%, must cover saturated shedding)")
-    ap.add_argument("--launch", default="pairs", choices=["pairs", "single"],
+    ap.add_argument("--launch", default="auto", choices=["auto", "triples", "pairs", "single"],
                     help="kernel schedule of the timed lattice (lbm_params.launch)")
     ap.add_argument("--no-big", action="store_true",
                     help="skip the 16384x4096 lattice (4.8 GB working set)")
-    ap.add_argument("--big-steps", type=int, default=400)
+    ap.add_argument("--big-steps", type=int, default=402)
     ap.add_argument("--no-cpu-all-cores", action="store_true")
     ap.add_argument("--study", choices=["train", "nn", "naca", "vortex", "cbc_train",
                                         "cbc_train_mach", "nn_train", "nn_drift", "scaling",
@@ -564,7 +565,9 @@ def main():
     assert out.nonfinite == 0
     nodes = nx * ny
     mlups = nodes / (ms * 1e-3) / 1e6
-    spl = STEPS_PER_LAUNCH if args.launch == "pairs" else 1
+    # steps per launch of the Zou & He lattice: three by default at FP32 and
+    # FP16 (lbm_params.launch), two at FP64 or with --launch pairs
+    spl = {"single": 1, "pairs": 2}.get(args.launch, 2 if args.precision == "fp64" else 3)
     counted = args.precision == "fp32" and spl == STEPS_PER_LAUNCH
     roofline = step_roofline(nodes, ms, spl, args.precision,
                              stored_traffic(nx, ny) if counted else None)
@@ -578,12 +581,19 @@ def main():
         single = lbm.Lattice(mask, tau, launch="single", **kw)
         ms_single = time_steps(single, args.steps, args.warmup, torch)
         del single
+        two = lbm.Lattice(mask, tau, launch="pairs", **kw)
+        ms_two = time_steps(two, args.steps, args.warmup, torch)
+        del two
         nn = {"mlups": nodes / (ms_nn * 1e-3) / 1e6, "ms_per_step": ms_nn,
-              "ratio_to_zouhe": ms / ms_nn, "ratio_to_zouhe_single": ms_single / ms_nn,
+              "ratio_to_zouhe": ms / ms_nn, "ratio_to_zouhe_pairs": ms_two / ms_nn,
+              "ratio_to_zouhe_single": ms_single / ms_nn,
+              "zouhe_pairs_mlups": nodes / (ms_two * 1e-3) / 1e6,
               "zouhe_single_mlups": nodes / (ms_single * 1e-3) / 1e6,
               "weights": "random-init 27-64-64-3", "fallback_nodes": int(out_nn.n_fallback),
-              "note": "ratio_to_zouhe: against the Zou & He lattice on the timed schedule; "
-                      "ratio_to_zouhe_single: against Zou & He at one launch per step"}
+              "note": "the neural outflow runs two steps per launch (it has no three-step "
+                      "form); ratio_to_zouhe: against the Zou & He lattice on the timed "
+                      "schedule; ratio_to_zouhe_pairs: against Zou & He at two steps per "
+                      "launch, the same schedule; ratio_to_zouhe_single: one launch per step"}
     else:
         del lat
     cbc = None
@@ -597,11 +607,17 @@ def main():
         lat.set_outflow_cbc(sigma=0.25, kappa2=0.05 / cs, mach=0.05 / cs)
         ms_cbc = time_steps(lat, args.steps, args.warmup, torch)
         assert lat.forces().nonfinite == 0
-        cbc = {"mlups": nodes / (ms_cbc * 1e-3) / 1e6, "ms_per_step": ms_cbc,
-               "ratio_to_zouhe": ms_zh / ms_cbc, "zouhe_mlups": nodes / (ms_zh * 1e-3) / 1e6,
-               "setting": "same lattice with periodic laterals; characteristic outflow, "
-                          "sigma 0.25, kappa_2 = Ma"}
         del lat
+        two = lbm.Lattice(mask, tau, launch="pairs", **kwp)
+        ms_zh2 = time_steps(two, args.steps, args.warmup, torch)
+        del two
+        cbc = {"mlups": nodes / (ms_cbc * 1e-3) / 1e6, "ms_per_step": ms_cbc,
+               "ratio_to_zouhe": ms_zh / ms_cbc, "ratio_to_zouhe_pairs": ms_zh2 / ms_cbc,
+               "zouhe_mlups": nodes / (ms_zh * 1e-3) / 1e6,
+               "zouhe_pairs_mlups": nodes / (ms_zh2 * 1e-3) / 1e6,
+               "setting": "same lattice with periodic laterals; characteristic outflow, "
+                          "sigma 0.25, kappa_2 = Ma; two steps per launch (no three-step "
+                          "form), ratio_to_zouhe_pairs against Zou & He on that schedule"}
     big = None
     if not args.no_big:
         bx, by = 16384, 4096

@@ -65,9 +65,10 @@ enum { LBM_BGK = 0, LBM_MRT = 1 };
 enum { LBM_LATERAL_WALLS = 0, LBM_LATERAL_PERIODIC = 1 };
 enum { LBM_X_INOUT = 0, LBM_X_PERIODIC = 1 };
 enum { LBM_OUT_ZOUHE = 0, LBM_OUT_NN = 1, LBM_OUT_CBC = 2 };
-/* Kernel schedule of lbm_step (results agree to rounding, see lbm_step). */
-enum { LBM_LAUNCH_PAIRS = 0, LBM_LAUNCH_SINGLE = 1, LBM_LAUNCH_PAIRS_PLAIN = 2,
-       LBM_LAUNCH_PAIRS_HELD = 3 };
+/* Kernel schedule of lbm_step (the populations agree bit for bit, see
+ * lbm_step). */
+enum { LBM_LAUNCH_AUTO = 0, LBM_LAUNCH_SINGLE = 1, LBM_LAUNCH_PAIRS_PLAIN = 2,
+       LBM_LAUNCH_PAIRS_HELD = 3, LBM_LAUNCH_TRIPLES = 4, LBM_LAUNCH_PAIRS = 5 };
 /* Bulk tile of the one-step kernel: chosen by lattice size, or forced. */
 enum { LBM_PATH_AUTO = 0, LBM_PATH_SCALAR = 1, LBM_PATH_VECTOR = 2 };
 
@@ -87,15 +88,20 @@ enum { LBM_PATH_AUTO = 0, LBM_PATH_SCALAR = 1, LBM_PATH_VECTOR = 2 };
  *   xbc          LBM_X_INOUT: Zou & He velocity inlet at x = 0 and outflow at
  *                x = nx-1 (Zou & He pressure or neural); LBM_X_PERIODIC:
  *                periodic in x (no inlet, no outlet).
- *   launch       LBM_LAUNCH_PAIRS (0, the default): two time steps per kernel
- *                launch wherever the outflow has a two-step form (see
- *                lbm_step); LBM_LAUNCH_SINGLE: one launch per time step.
- *                Two-step launches walk their strips in one of two orders,
- *                chosen by lattice size (the stores of a row held back by
- *                one row above 200 MB per population buffer, FP32 and FP64
- *                only); LBM_LAUNCH_PAIRS_PLAIN and LBM_LAUNCH_PAIRS_HELD
- *                force one (HELD: not with LBM_FP16_OFFSET).  Every
- *                two-step order gives the same results bit for bit.
+ *   launch       LBM_LAUNCH_AUTO (0, the default): three time steps per
+ *                kernel launch with the Zou & He outflow at FP32 and FP16
+ *                offsets, two per launch otherwise (every outflow has a
+ *                two-step form), the rest of a count in two-step and single
+ *                launches.  LBM_LAUNCH_TRIPLES: the same, and rejected with
+ *                LBM_FP64.  LBM_LAUNCH_PAIRS: two steps per launch only.
+ *                LBM_LAUNCH_SINGLE: one launch per time step.  Two-step
+ *                launches walk their strips in one of two orders, chosen by
+ *                lattice size (the stores of a row held back by one row
+ *                above 200 MB per population buffer, FP32 and FP64 only);
+ *                LBM_LAUNCH_PAIRS_PLAIN and LBM_LAUNCH_PAIRS_HELD take
+ *                two-step launches with one of them (HELD: not with
+ *                LBM_FP16_OFFSET).  Every schedule gives the same
+ *                populations bit for bit.
  *   bulk_path    tile of the one-step kernel: LBM_PATH_AUTO (0: one node per
  *                thread below 12M nodes, four per lane above), or forced
  *                LBM_PATH_SCALAR / LBM_PATH_VECTOR.  Same results.
@@ -194,12 +200,13 @@ lbm_status lbm_set_inlet_profile(lbm_ctx* c, const double* host_ux);
 /* Advance nsteps time steps (asynchronous).  One step: pull streaming of
  * the post-collision populations with half-way bounce-back on walls and
  * solids, the inlet and outlet columns, collision, and the force and mass
- * of the step (Sec. 2, Eqs. 1-4, 5-11, 12, 14-15).  With params.launch =
- * LBM_LAUNCH_PAIRS and the Zou & He outflow two steps run in each launch
- * (the same node arithmetic, every intermediate state rounded to the storage
- * precision as a store would round it, so the populations agree with one
- * launch per step to the rounding of the sums; an odd count ends with one
- * single step).  ESTATE before lbm_set_geometry. */
+ * of the step (Sec. 2, Eqs. 1-4, 5-11, 12, 14-15).  Unless params.launch =
+ * LBM_LAUNCH_SINGLE, two or three steps run in each launch (params.launch)
+ * with the same node arithmetic and every intermediate state rounded to the
+ * storage precision as a store would round it, so the populations equal
+ * those of one launch per step bit for bit and the force and mass sums
+ * agree to their rounding; a count that does not divide ends with a
+ * two-step or single launch.  ESTATE before lbm_set_geometry. */
 lbm_status lbm_step(lbm_ctx* c, int64_t nsteps);
 
 /* Synchronise the stream and read the accumulators.  Returns EUNSTABLE

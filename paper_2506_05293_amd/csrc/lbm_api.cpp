@@ -153,10 +153,14 @@ Layout make_layout(const lbm_params& p) {
   L.nty = (p.ny + L.rows - 1) / L.rows;
   L.nn_max = (p.ny + kNnRows - 1) / kNnRows;
   L.nslots_max = (L.nn_max + 8 + L.ntx * L.nty) * kWaves;   // + padding to a multiple of 8
-  // two-step launches write two steps' slots (outlet blocks included)
+  // two-step launches write two steps' slots (outlet blocks included),
+  // three-step launches three steps' slots
+  const int row_bytes = L.pitch * int(elem_size(p.precision));
   L.nslots_max = std::max(L.nslots_max,
-                          2 * (pair_waves(p.nx, p.ny, pair_rows(p.nx, p.ny, L.pitch * int(elem_size(p.precision)))) +
+                          2 * (pair_waves(p.nx, p.ny, pair_rows(p.nx, p.ny, row_bytes)) +
                                pair_outlet_blocks(p.ny) * kWaves));
+  if (tri_supported(p.precision))
+    L.nslots_max = std::max(L.nslots_max, 3 * tri_waves(p.nx, p.ny, tri_rows(p.nx, p.ny, row_bytes)));
   L.plane = padded_plane(int64_t(p.ny) * L.pitch, elem_size(p.precision));
   const size_t pop = size_t(9) * size_t(L.plane) * elem_size(p.precision);
   size_t o = 0;
@@ -172,8 +176,8 @@ Layout make_layout(const lbm_params& p) {
   L.inlet = take(size_t(p.ny) * 8);
   L.part0 = take(size_t(L.nslots_max) * kPartials * 8);   // one slot per wave
   L.part1 = take(size_t(L.nslots_max) * kPartials * 8);
-  L.lvl0 = take(size_t(2 * kReducers) * 4 * 8);   // two steps' sums for two-step launches
-  L.lvl1 = take(size_t(2 * kReducers) * 4 * 8);
+  L.lvl0 = take(size_t(3 * kReducers) * 4 * 8);   // the sums of up to three steps per launch
+  L.lvl1 = take(size_t(3 * kReducers) * 4 * 8);
   L.acc = take(sizeof(Acc));
   L.hist = take(size_t(std::max<int64_t>(p.history_cap, 0)) * 3 * 8);
   L.mlp = take(sizeof(MlpDev));
@@ -197,8 +201,10 @@ lbm_status check_params(const lbm_params* p) {
   if (p->lateral != LBM_LATERAL_WALLS && p->lateral != LBM_LATERAL_PERIODIC)
     return fail(LBM_EINVAL, "bad lateral %d", p->lateral);
   if (p->xbc != LBM_X_INOUT && p->xbc != LBM_X_PERIODIC) return fail(LBM_EINVAL, "bad xbc %d", p->xbc);
-  if (p->launch < LBM_LAUNCH_PAIRS || p->launch > LBM_LAUNCH_PAIRS_HELD)
+  if (p->launch < LBM_LAUNCH_AUTO || p->launch > LBM_LAUNCH_PAIRS)
     return fail(LBM_EINVAL, "bad launch %d", p->launch);
+  if (p->launch == LBM_LAUNCH_TRIPLES && !tri_supported(p->precision))
+    return fail(LBM_EINVAL, "LBM_LAUNCH_TRIPLES needs LBM_FP32_OFFSET or LBM_FP16_OFFSET");
   if (p->launch == LBM_LAUNCH_PAIRS_HELD && p->precision == LBM_FP16_OFFSET)
     return fail(LBM_EINVAL, "LBM_LAUNCH_PAIRS_HELD needs LBM_FP64 or LBM_FP32_OFFSET");
   if (p->bulk_path < LBM_PATH_AUTO || p->bulk_path > LBM_PATH_VECTOR)
@@ -299,6 +305,9 @@ struct lbm_ctx {
                                                        : pair_hold(p.precision, 9 * lay.plane * int64_t(elem_size(p.precision)));
     L.pair_nslots = pair_waves(L.pair_nx, p.ny, L.pair_rows) + L.pair_out * kWaves;
     L.pair_chunk = pair_chunk(L.pair_nx);
+    L.tri_rows = tri_rows(p.nx, p.ny, lay.pitch * int(elem_size(p.precision)));
+    L.tri_nslots = tri_waves(p.nx, p.ny, L.tri_rows);
+    L.tri_chunk = tri_chunk(p.nx);
     L.nslots = (L.nspecial - 1 - kReducers + lay.ntx * lay.nty) * kWaves;
     L.xper = p.xbc == LBM_X_PERIODIC;
     L.yper = p.lateral == LBM_LATERAL_PERIODIC;
@@ -482,9 +491,27 @@ lbm_status lbm_step(lbm_ctx* c, int64_t nsteps) {
   if (nsteps < 0) return fail(LBM_EINVAL, "nsteps < 0");
   if (nsteps == 0) return LBM_OK;
   int64_t s = 0;
+  // With params.launch = LBM_LAUNCH_AUTO or LBM_LAUNCH_TRIPLES, the Zou & He
+  // outflow and FP32 or FP16 offsets, three steps run in each launch; the
+  // rest of the count as below.
+  const bool triples = (c->p.launch == LBM_LAUNCH_AUTO || c->p.launch == LBM_LAUNCH_TRIPLES) &&
+                       c->outflow == LBM_OUT_ZOUHE && tri_supported(c->p.precision);
+  if (nsteps >= 3 && triples) {
+    for (; s + 2 < nsteps; s += 3) {
+      const StepLaunch L = c->launch();
+      HIP_TRY(launch_triple(L, c->stream));
+      c->pend2 = c->pend1;
+      c->pend1 = true;
+      c->pcur ^= 1;
+      c->cur ^= 1;
+    }
+    StepLaunch F = c->launch();
+    HIP_TRY(launch_finalize_triple(F, c->stream));
+    c->pend1 = c->pend2 = false;
+  }
   // With params.launch other than LBM_LAUNCH_SINGLE, pairs of steps run in
   // one launch each (the same node arithmetic) whatever the outflow.
-  if (nsteps >= 2 && c->p.launch != LBM_LAUNCH_SINGLE) {
+  if (nsteps - s >= 2 && c->p.launch != LBM_LAUNCH_SINGLE) {
     for (; s + 1 < nsteps; s += 2) {
       const StepLaunch L = c->launch();
       HIP_TRY(launch_pair(L, c->stream));

@@ -106,6 +106,9 @@ struct StepLaunch {
   int pair_chunk;       // two-step launches: strip workgroups per chunk dealt to an XCD (0: eighths)
   int pair_rows;        // two-step launches: output rows per strip
   int pair_hold;        // two-step launches: step-(t+2) stores held one row (pair_hold)
+  int tri_nslots;       // three-step launches: waves (slots per step)
+  int tri_chunk;        // three-step launches: strip workgroups per chunk dealt to an XCD
+  int tri_rows;         // three-step launches: output rows per strip
   int nslots;           // partial slots written per step (waves of the
                         // neural and bulk workgroups)
   int xper, yper;
@@ -139,6 +142,13 @@ int pair_chunk(int pair_nx);
 int pair_outlet_cols();
 hipError_t launch_pair(const StepLaunch& L, hipStream_t s);
 hipError_t launch_finalize_pair(const StepLaunch& L, hipStream_t s);
+// Three steps per launch (Zou & He outflow, FP32 and FP16 offsets).
+int tri_waves(int nx, int ny, int rows);
+int tri_rows(int nx, int ny, int pitch_bytes);
+int tri_chunk(int nx);
+bool tri_supported(int precision);
+hipError_t launch_triple(const StepLaunch& L, hipStream_t s);
+hipError_t launch_finalize_triple(const StepLaunch& L, hipStream_t s);
 
 struct InitLaunch {
   int precision;

@@ -1300,9 +1300,11 @@ __device__ void cbc2_block(const StepLaunch& L, int nb, Cbc2Smem<typename Store<
   }
 }
 
-// Level 2 of a pair: both steps' kReducers sums, committed in step order.
-__device__ void pair_level2(const double* __restrict__ lvl, const StepLaunch& L) {
-  for (int h = 0; h < 2; ++h) {
+// Level 2 of a launch of K steps: each step's kReducers sums, committed in
+// step order.
+template <int K>
+__device__ void multi_level2(const double* __restrict__ lvl, const StepLaunch& L) {
+  for (int h = 0; h < K; ++h) {
     double s[4] = {0.0, 0.0, 0.0, 0.0}, t[4];
     if (threadIdx.x < kReducers) {
 #pragma unroll
@@ -1314,10 +1316,11 @@ __device__ void pair_level2(const double* __restrict__ lvl, const StepLaunch& L)
   }
 }
 
-// Level 1 of a pair: reducer r (of 2 kReducers) sums its slice of one step's slots.
+// Level 1 of a launch of K steps (n slots per step): reducer r (of
+// K kReducers) sums its slice of one step's slots.
 template <typename T>
-__device__ void pair_level1(const T* __restrict__ part, int r, const StepLaunch& L) {
-  const int h = r / kReducers, rr = r - h * kReducers, n = L.pair_nslots;
+__device__ void multi_level1(const T* __restrict__ part, int r, int n, const StepLaunch& L) {
+  const int h = r / kReducers, rr = r - h * kReducers;
   const int per = (n + kReducers - 1) / kReducers;
   const int b0 = min(rr * per, n), b1 = min(b0 + per, n);
   double t[4];
@@ -1338,9 +1341,9 @@ __global__ void __launch_bounds__(kBlock) k_step2(const StepLaunch L) {
   const int v = int(blockIdx.x);
   if (v < kPairSpecial) {
     if (v == 0) {
-      if (L.reduce2) pair_level2(L.lvl_r, L);
+      if (L.reduce2) multi_level2<2>(L.lvl_r, L);
     } else if (v <= 2 * kReducers && L.reduce1) {
-      pair_level1(static_cast<const double*>(L.part_r), v - 1, L);
+      multi_level1(static_cast<const double*>(L.part_r), v - 1, L.pair_nslots, L);
     }
     return;
   }
@@ -1373,15 +1376,17 @@ __global__ void __launch_bounds__(kBlock) k_step2(const StepLaunch L) {
 
 // Flush after the last pair: level 2 of the pair before, then both steps of
 // the last pair's slots in one workgroup.
-template <typename T>
-__global__ void __launch_bounds__(kBlock) k_finalize2(const StepLaunch L) {
-  if (L.reduce2) pair_level2(L.lvl_r, L);
+// Flush after the last launch of K steps (n slots per step): level 2 of the
+// launch before, then the K steps of the last launch's slots in one
+// workgroup.
+template <typename T, int K>
+__global__ void __launch_bounds__(kBlock) k_finalize_multi(const StepLaunch L, int n) {
+  if (L.reduce2) multi_level2<K>(L.lvl_r, L);
   __syncthreads();
   if (L.reduce1) {
-    for (int h = 0; h < 2; ++h) {
+    for (int h = 0; h < K; ++h) {
       double t[4];
-      sum_slots(static_cast<const T*>(L.part_r) + int64_t(kPartials) * h * L.pair_nslots, 0,
-                L.pair_nslots, t);
+      sum_slots(static_cast<const T*>(L.part_r) + int64_t(kPartials) * h * n, 0, n, t);
       if (threadIdx.x == 0) commit_step(t, L);
       __syncthreads();
     }
@@ -1408,6 +1413,214 @@ static hipError_t launch_pair_t(const StepLaunch& L, hipStream_t s) {
     if (L.pair_hold) return launch_pair_h<S, MRT, 1>(L, s);
   }
   return L.pair_hold ? hipErrorInvalidValue : launch_pair_h<S, MRT, 0>(L, s);
+}
+
+// ---- three time steps per launch (Zou & He outflow) --------------------------------
+//
+// The two-step strip walk carried one step further: every wave owns a strip
+// of kTriCols columns (lane l holds column x0 - 3 + l) and walks rows
+// y0 - 3 .. y0 + rows + 2, keeping the last three rows as read (R), after
+// the first collision (S) and after the second (U), and the next row's
+// loads (P).  Step t+1 is taken on lanes 1..62 and rows y0 - 2 .. y0 + rows
+// + 1, step t+2 on lanes 2..61 and rows y0 - 1 .. y0 + rows, step t+3 on the
+// strip's own 58 columns and rows, which are stored.  The states after the
+// first two steps are rounded to the storage precision as a store and
+// reload would round them, so a launch equals three single launches bit for
+// bit.  A launch reads and writes each population once for three steps:
+// 24 B per node and step at FP32.  Each step's force and mass terms are
+// summed over the nodes the strip owns (its columns and rows), FP64 per wave
+// and step.
+constexpr int kTriCols = 58;
+
+template <typename S>
+struct TriWave {
+  int lane, y0, ye, nrow;
+  int xl, xs;              // this lane's column, and where it is read
+  uint32_t off;            // byte offset of column xs within a row
+  bool col_in, out_col;
+
+  __device__ TriWave(const StepLaunch& L, int wave) {
+    lane = threadIdx.x & 63;
+    const int nstrip = (L.nx + kTriCols - 1) / kTriCols;
+    const int strip = wave % nstrip, seg = wave / nstrip;
+    const int x0 = strip * kTriCols;
+    y0 = seg * L.tri_rows;
+    xl = x0 - 3 + lane;
+    xs = xl;
+    if (L.xper) xs = xs < 0 ? xs + L.nx : (xs >= L.nx ? xs - L.nx : xs);
+    else xs = xs < 0 ? 0 : (xs >= L.nx ? L.nx - 1 : xs);
+    off = uint32_t(xs) * uint32_t(sizeof(S));
+    col_in = L.xper || (xl >= 0 && xl < L.nx);
+    out_col = lane >= 3 && lane < 3 + kTriCols && xl < L.nx;
+    ye = min(y0 + L.tri_rows, L.ny);
+    nrow = ye - y0 + 6;
+  }
+
+  __device__ int wrap_row(int y, const StepLaunch& L) const {
+    if (L.yper) return y < 0 ? y + L.ny : (y >= L.ny ? y - L.ny : y);
+    return y < 0 ? 0 : (y >= L.ny ? L.ny - 1 : y);
+  }
+};
+
+template <typename S, int MRT>
+__device__ __forceinline__ void tri_strip(const StepLaunch& L, int wave, double* part) {
+  using T = typename Store<S>::T;
+  const TriWave<S> w(L, wave);
+  const int y0 = w.y0, ye = w.ye, nrow = w.nrow;
+  const bool col_in = w.col_in, out_col = w.out_col;
+  const S* __restrict__ A = static_cast<const S*>(L.A);
+  S* __restrict__ B = static_cast<S*>(L.B);
+  T R0[9], R1[9], R2[9], S0[9], S1[9], S2[9], U0[9], U1[9], U2[9], P[9];
+  // link words of rows yr - 3 (KM), yr - 2 (K0), yr - 1 (K1), yr (K2) and
+  // the row being fetched (KP)
+  uint32_t KM = 0, K0 = 0, K1 = 0, K2 = 0, KP = 0;
+  double fx[3] = {0.0, 0.0, 0.0}, fy[3] = {0.0, 0.0, 0.0}, dm[3] = {0.0, 0.0, 0.0};
+  auto fetch = [&](int yr) {
+    const int ys = w.wrap_row(yr, L);
+    const int64_t row = int64_t(ys) * L.pitch;
+#pragma unroll
+    for (int q = 0; q < 9; ++q) {
+      P[q] = Store<S>::ld(reinterpret_cast<const S*>(
+          reinterpret_cast<const char*>(A + int64_t(q) * L.plane + row) + w.off));
+    }
+    KP = 0;
+    const bool row_in = L.yper || (yr >= 0 && yr < L.ny);
+    if (row_in && col_in && L.chunk[ys * L.nchunk + w.xs / kChunk]) KP = L.links[row + w.xs];
+  };
+  // one intermediate step at row y (absolute) from the rows lo, mid, hi of
+  // the state before it, own = mid; nodes outside the lattice, solid or in
+  // a column outside keep their values
+  auto inner = [&](const T lo[9], const T mid[9], const T hi[9], uint32_t lk, int y, int k, T out[9]) {
+    const bool in = L.yper || (y >= 0 && y < L.ny);
+    const bool cnt = out_col && y >= y0 && y < ye;
+    T g[9];
+    pair_pull(lo, mid, hi, g);
+    T fxk = T(0), fyk = T(0), dmk = T(0);
+    if (!(in && col_in && pair_node<T, MRT>(L, lk, w.wrap_row(y, L), mid, g, cnt, fxk, fyk, dmk))) {
+#pragma unroll
+      for (int q = 0; q < 9; ++q) g[q] = mid[q];
+    }
+    fx[k] += double(fxk);
+    fy[k] += double(fyk);
+    dm[k] += double(dmk);
+#pragma unroll
+    for (int q = 0; q < 9; ++q) out[q] = Store<S>::stored(g[q]);
+  };
+  fetch(y0 - 3);
+  for (int j = 0; j < nrow; ++j) {
+    const int yr = y0 - 3 + j;
+#pragma unroll
+    for (int q = 0; q < 9; ++q) R2[q] = P[q];
+    K2 = KP;
+    if (j + 1 < nrow) fetch(yr + 1);
+    if (j >= 2) {
+      inner(R0, R1, R2, K1, yr - 1, 0, S2);               // step t+1 at row yr - 1
+      if (j >= 4) {
+        inner(S0, S1, S2, K0, yr - 2, 1, U2);             // step t+2 at row yr - 2
+        if (j >= 6) {
+          // step t+3 at row yr - 3 (one of the strip's rows)
+          const int y3 = yr - 3;
+          T g[9];
+          pair_pull(U0, U1, U2, g);
+          const uint32_t o3 = uint32_t(y3) * uint32_t(L.pitch) * uint32_t(sizeof(S)) + w.off;
+          T fx3 = T(0), fy3 = T(0), dm3 = T(0);
+          if (out_col && pair_node<T, MRT>(L, KM, y3, U1, g, true, fx3, fy3, dm3)) {
+#pragma unroll
+            for (int q = 0; q < 9; ++q)
+              Store<S>::st_cached(
+                  reinterpret_cast<S*>(reinterpret_cast<char*>(B + int64_t(q) * L.plane) + o3), g[q]);
+          }
+          fx[2] += double(fx3);
+          fy[2] += double(fy3);
+          dm[2] += double(dm3);
+        }
+#pragma unroll
+        for (int q = 0; q < 9; ++q) {
+          U0[q] = U1[q];
+          U1[q] = U2[q];
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < 9; ++q) {
+        S0[q] = S1[q];
+        S1[q] = S2[q];
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < 9; ++q) {
+      R0[q] = R1[q];
+      R1[q] = R2[q];
+    }
+    KM = K0;
+    K0 = K1;
+    K1 = K2;
+  }
+  // one slot per wave and step: [k n, (k + 1) n) for step k
+  const int n = L.tri_nslots;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const double a = wave_sum(fx[k]), b = wave_sum(fy[k]), c = wave_sum(dm[k]);
+    if (w.lane == 0) {
+      double* o = part + int64_t(kPartials) * (int64_t(k) * n + wave);
+      o[0] = a; o[1] = b; o[2] = c; o[3] = 0.0;
+    }
+  }
+}
+
+constexpr int kTriSpecial = (1 + 3 * kReducers + 7) / 8 * 8;
+
+template <typename S, int MRT>
+__global__ void __launch_bounds__(kBlock) k_step3(const StepLaunch L) {
+  const int v = int(blockIdx.x);
+  if (v < kTriSpecial) {
+    if (v == 0) {
+      if (L.reduce2) multi_level2<3>(L.lvl_r, L);
+    } else if (v <= 3 * kReducers && L.reduce1) {
+      multi_level1(static_cast<const double*>(L.part_r), v - 1, L.tri_nslots, L);
+    }
+    return;
+  }
+  int sb = v - kTriSpecial;
+  const int nsb = int(gridDim.x) - kTriSpecial;
+  sb = L.tri_chunk > 0 ? xcd_remap_chunks(sb, nsb, L.tri_chunk) : xcd_remap(sb, nsb);
+  const int wave = __builtin_amdgcn_readfirstlane(sb * kWaves + int(threadIdx.x >> 6));
+  if (wave >= L.tri_nslots) return;                  // whole wave
+  tri_strip<S, MRT>(L, wave, static_cast<double*>(L.part_w));
+}
+
+template <typename S, int MRT>
+static hipError_t launch_tri_t(const StepLaunch& L, hipStream_t s) {
+  const int blocks = kTriSpecial + (L.tri_nslots + kWaves - 1) / kWaves;
+  hipLaunchKernelGGL((k_step3<S, MRT>), dim3(blocks), dim3(kBlock), 0, s, L);
+  return hipGetLastError();
+}
+
+int tri_waves(int nx, int ny, int rows) {
+  return ((nx + kTriCols - 1) / kTriCols) * ((ny + rows - 1) / rows);
+}
+
+int strip_rows(int nx, int ny, int pitch_bytes, int cols);   // below (the strip-height rule)
+
+int tri_rows(int nx, int ny, int pitch_bytes) { return strip_rows(nx, ny, pitch_bytes, kTriCols); }
+
+int tri_chunk(int nx) { return ((nx + kTriCols - 1) / kTriCols + kWaves - 1) / kWaves; }
+
+// FP32 and FP16 offsets (the FP64 variant would need twice the registers).
+bool tri_supported(int precision) { return precision != LBM_FP64; }
+
+hipError_t launch_triple(const StepLaunch& L, hipStream_t s) {
+  switch (L.precision * 2 + L.collision) {
+    case LBM_FP32_OFFSET * 2 + LBM_BGK: return launch_tri_t<float, 0>(L, s);
+    case LBM_FP32_OFFSET * 2 + LBM_MRT: return launch_tri_t<float, 1>(L, s);
+    case LBM_FP16_OFFSET * 2 + LBM_BGK: return launch_tri_t<__half, 0>(L, s);
+    case LBM_FP16_OFFSET * 2 + LBM_MRT: return launch_tri_t<__half, 1>(L, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_finalize_triple(const StepLaunch& L, hipStream_t s) {
+  hipLaunchKernelGGL((k_finalize_multi<double, 3>), dim3(1), dim3(kBlock), 0, s, L, L.tri_nslots);
+  return hipGetLastError();
 }
 
 // Whether the strips hold their step-(t+2) stores back by one row (with
@@ -1443,14 +1656,16 @@ int pair_waves(int nx, int ny, int rows) {
 // 16384 x 4096 17 rows 114.0k (16: 115.0k, 24: 110.6k); FP16 4096 x 1024
 // 143.7k (24: 127.6k); FP64 4096 x 1024 52.2k (24: 53.2k).
 constexpr int kSimds = 256 * 4;      // the MI355X's 256 CUs of four SIMDs each
-int pair_rows(int nx, int ny, int pitch_bytes) {
-  const int strips = (nx + kPairCols - 1) / kPairCols;
+int strip_rows(int nx, int ny, int pitch_bytes, int cols) {
+  const int strips = (nx + cols - 1) / cols;
   const int bands = std::max(1, 4 * kSimds / strips);
   int rows = std::min(std::max((ny + bands - 1) / bands, kPairRowsMin), kPairRowsMax);
   if (rows > kPairRowsMin && (int64_t(rows) * pitch_bytes) % 65536 == 0)
     rows += rows < kPairRowsMax ? 1 : -1;
   return rows;
 }
+
+int pair_rows(int nx, int ny, int pitch_bytes) { return strip_rows(nx, ny, pitch_bytes, kPairCols); }
 
 int pair_outlet_blocks(int ny) { return (ny + kOutRows - 1) / kOutRows; }
 
@@ -1481,7 +1696,8 @@ hipError_t launch_pair(const StepLaunch& L, hipStream_t s) {
 }
 
 hipError_t launch_finalize_pair(const StepLaunch& L, hipStream_t s) {
-  hipLaunchKernelGGL((k_finalize2<double>), dim3(1), dim3(kBlock), 0, s, L);   // FP64 slots
+  hipLaunchKernelGGL((k_finalize_multi<double, 2>), dim3(1), dim3(kBlock), 0, s, L,
+                     L.pair_nslots);   // FP64 slots
   return hipGetLastError();
 }
 

@@ -31,7 +31,7 @@ def test_every_declared_symbol_is_exported():
 
 def _params(**kw):
     p = lbm.lbm_params(200, 80, lbm.LBM_FP32_OFFSET, lbm.LBM_MRT, lbm.LBM_LATERAL_WALLS,
-                       lbm.LBM_X_INOUT, lbm.LBM_LAUNCH_PAIRS, lbm.LBM_PATH_AUTO,
+                       lbm.LBM_X_INOUT, lbm.LBM_LAUNCH_AUTO, lbm.LBM_PATH_AUTO,
                        0.56, 1.0, 1.0, 0.0, 0.05, 1.0, 1e-4, 1, 100, None)
     for k, v in kw.items():
         setattr(p, k, v)
@@ -58,7 +58,7 @@ def test_workspace_size_scales_with_precision():
 @pytest.mark.parametrize("field,value", [("tau", 0.5), ("tau", float("nan")), ("nx", 4),
                                          ("precision", 7), ("collision", 3), ("u_in", 0.6),
                                          ("rho_out", 0.0), ("history_cap", -1),
-                                         ("launch", 4), ("launch", -1), ("bulk_path", 3),
+                                         ("launch", 6), ("launch", -1), ("bulk_path", 3),
                                          ("bulk_path", -1)])
 def test_bad_parameters_are_rejected(field, value):
     with pytest.raises(lbm.LbmError) as e:
@@ -77,6 +77,14 @@ def test_two_step_walks_can_be_forced():
     with pytest.raises(lbm.LbmError) as e:
         lbm.lbm_workspace_bytes(_params(launch=lbm.LBM_LAUNCH_PAIRS_HELD,
                                         precision=lbm.LBM_FP16_OFFSET))
+    assert e.value.status == lbm.LBM_EINVAL
+
+
+def test_three_step_launches_have_no_fp64_form():
+    for prec in (lbm.LBM_FP32_OFFSET, lbm.LBM_FP16_OFFSET):
+        assert lbm.lbm_workspace_bytes(_params(launch=lbm.LBM_LAUNCH_TRIPLES, precision=prec)) > 0
+    with pytest.raises(lbm.LbmError) as e:
+        lbm.lbm_workspace_bytes(_params(launch=lbm.LBM_LAUNCH_TRIPLES, precision=lbm.LBM_FP64))
     assert e.value.status == lbm.LBM_EINVAL
 
 

@@ -1,6 +1,7 @@
-"""GPU parity of the two-steps-per-launch path of the step (the default,
-params.launch = LBM_LAUNCH_PAIRS; LBM_LAUNCH_SINGLE gives one launch per
-step).  Every node takes the single-step node code in registers with the
+"""GPU parity of the two-steps-per-launch path of the step
+(params.launch = LBM_LAUNCH_PAIRS, and the default for the outflows and
+precisions without a three-step form; LBM_LAUNCH_SINGLE gives one launch
+per step).  Every node takes the single-step node code in registers with the
 same explicit fused multiply-adds, and the state between the two steps is
 rounded to the storage precision as a store and reload would round it, so
 the populations equal those of one launch per step bit for bit in FP64,

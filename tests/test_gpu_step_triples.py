@@ -1,0 +1,90 @@
+"""GPU parity of three steps per launch (params.launch = LBM_LAUNCH_TRIPLES,
+Zou & He outflow, FP32 and FP16 offsets).  Every node takes the
+single-step node code, and the states after the first two steps of a
+launch are rounded to the storage precision as a store and reload would
+round them, so the populations equal those of one launch per step bit for
+bit, over step counts that leave one or two steps for two-step and single
+launches and over read-outs in between.  The force and mass terms are
+summed in other groups (strips of the three-step kernel, tiles of the
+one-step kernel, which adds a wave's terms in FP32 first): the force
+history agrees to 1e-5 of its scale.  Against the oracle as the other
+schedules: the full-size bench lattice from the same smooth fields."""
+import numpy as np
+import pytest
+
+import cases
+from oracle.solver import Lattice as Oracle
+from paper_2506_05293_amd import lbm, workloads
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print("[gpu case]", *a, flush=True)
+
+
+def _gpu(case, precision, history_cap, launch):
+    return lbm.Lattice(case["mask"], case["tau"], precision=precision,
+                       collision=case["collision"], lateral=case["lateral"],
+                       u_in=case["u_in"], noise_amp=case["noise_amp"], seed=case["seed"],
+                       history_cap=history_cap, launch=launch)
+
+
+@pytest.mark.parametrize("name,precision", [("c1_bgk", "fp32"), ("ragged_mrt_periodic", "fp32"),
+                                            ("ragged_mrt_walls", "fp16"), ("c1_mrt", "fp32"),
+                                            ("c1_mrt", "fp16")])
+def test_triples_equal_single_steps(name, precision):
+    case = {"c1_bgk": cases.c1(75.0), "ragged_mrt_periodic": cases.ragged("mrt", "periodic"),
+            "ragged_mrt_walls": cases.ragged("mrt", "walls"), "c1_mrt": cases.c1(100.0, "mrt")}[name]
+    _say("triples vs single steps", name, precision)
+    chunks = (40, 7, 34, 2, 3)          # remainders of one and two steps, read-outs between
+    out = {}
+    for launch in ("triples", "single"):
+        g = _gpu(case, precision, 86, launch)
+        for n in chunks:
+            g.step(n)
+        out[launch] = (g.populations(), g.force_history())
+    (f1, (fx1, fy1)), (f0, (fx0, fy0)) = out["triples"], out["single"]
+    print("triples vs single: populations that differ", np.count_nonzero(f1 != f0), flush=True)
+    np.testing.assert_array_equal(f1, f0)
+    assert len(fx1) == 86
+    scale = max(np.max(np.abs(fx0)), 1e-9)
+    print("force history: max difference / scale", np.max(np.abs(fx1 - fx0)) / scale, flush=True)
+    np.testing.assert_allclose(fx1, fx0, rtol=0, atol=1e-5 * scale)
+    np.testing.assert_allclose(fy1, fy0, rtol=0, atol=1e-5 * scale)
+
+
+def test_triples_full_size_c2_against_oracle():
+    # the bench lattice, FP32 offsets, MRT: six steps (two launches) from the
+    # same smooth fields as the oracle
+    case = cases.c2()
+    _say("triples c2 full size fp32")
+    rho, u = workloads.smooth_fields(case["mask"].shape, case["u_in"], amp=0.02, seed=17)
+    g = _gpu(case, "fp32", 6, "triples")
+    g.init_fields(rho, u[0], u[1])
+    g.step(6)
+    o = Oracle(case["mask"], **cases.oracle_kwargs(case))
+    o.set_equilibrium(rho, u[0], u[1])
+    o.step(6)
+    fl = case["mask"] == 0
+    err = np.max(np.abs(g.populations()[:, fl] - o.post_collision()[:, fl]))
+    print("c2 six-step max abs error", err, flush=True)
+    assert err < 5e-8
+    fx, fy = g.force_history()
+    np.testing.assert_allclose(fx, o.fx_hist, rtol=1e-5, atol=1e-9)
+    np.testing.assert_allclose(fy, o.fy_hist, rtol=1e-5, atol=1e-7)
+
+
+def test_triples_with_the_neural_outflow_fall_back_to_pairs():
+    # other outflows have no three-step form: the same bits as two-step launches
+    case = cases.ragged("mrt", "periodic")
+    P = {k: np.asarray(v, np.float32).astype(np.float64)
+         for k, v in cases.random_params(3, w_scale=0.5, out_sd=2e-4).items()}
+    _say("triples with the neural outflow")
+    out = {}
+    for launch in ("triples", "pairs"):
+        g = _gpu(case, "fp32", 20, launch)
+        g.set_outflow_nn(P, mass_bound=3e-4)
+        g.step(20)
+        out[launch] = g.populations()
+    np.testing.assert_array_equal(out["triples"], out["pairs"])
