@@ -106,7 +106,9 @@ struct StepLaunch {
   int pair_chunk;       // two-step launches: strip workgroups per chunk dealt to an XCD (0: eighths)
   int pair_rows;        // two-step launches: output rows per strip
   int pair_hold;        // two-step launches: step-(t+2) stores held one row (pair_hold)
-  int tri_nslots;       // three-step launches: waves (slots per step)
+  int tri_nslots;       // three-step launches: waves (slots per step), outlet blocks first
+  int tri_nx;           // three-step launches: columns the strips write
+  int tri_out;          // three-step launches: neural outlet blocks (0: Zou & He in the strips)
   int tri_chunk;        // three-step launches: strip workgroups per chunk dealt to an XCD
   int tri_rows;         // three-step launches: output rows per strip
   int nslots;           // partial slots written per step (waves of the
@@ -145,7 +147,8 @@ hipError_t launch_finalize_pair(const StepLaunch& L, hipStream_t s);
 // Three steps per launch (Zou & He outflow, FP32 and FP16 offsets).
 int tri_waves(int nx, int ny, int rows);
 int tri_rows(int nx, int ny, int pitch_bytes);
-int tri_chunk(int nx);
+int tri_chunk(int tri_nx);
+int tri_outlet_blocks(int ny);
 bool tri_supported(int precision);
 hipError_t launch_triple(const StepLaunch& L, hipStream_t s);
 hipError_t launch_finalize_triple(const StepLaunch& L, hipStream_t s);

@@ -1441,7 +1441,7 @@ struct TriWave {
 
   __device__ TriWave(const StepLaunch& L, int wave) {
     lane = threadIdx.x & 63;
-    const int nstrip = (L.nx + kTriCols - 1) / kTriCols;
+    const int nstrip = (L.tri_nx + kTriCols - 1) / kTriCols;
     const int strip = wave % nstrip, seg = wave / nstrip;
     const int x0 = strip * kTriCols;
     y0 = seg * L.tri_rows;
@@ -1451,7 +1451,7 @@ struct TriWave {
     else xs = xs < 0 ? 0 : (xs >= L.nx ? L.nx - 1 : xs);
     off = uint32_t(xs) * uint32_t(sizeof(S));
     col_in = L.xper || (xl >= 0 && xl < L.nx);
-    out_col = lane >= 3 && lane < 3 + kTriCols && xl < L.nx;
+    out_col = lane >= 3 && lane < 3 + kTriCols && xl < L.tri_nx;
     ye = min(y0 + L.tri_rows, L.ny);
     nrow = ye - y0 + 6;
   }
@@ -1463,7 +1463,7 @@ struct TriWave {
 };
 
 template <typename S, int MRT>
-__device__ __forceinline__ void tri_strip(const StepLaunch& L, int wave, double* part) {
+__device__ __forceinline__ void tri_strip(const StepLaunch& L, int wave, int slot, double* part) {
   using T = typename Store<S>::T;
   const TriWave<S> w(L, wave);
   const int y0 = w.y0, ye = w.ye, nrow = w.nrow;
@@ -1561,15 +1561,292 @@ __device__ __forceinline__ void tri_strip(const StepLaunch& L, int wave, double*
   for (int k = 0; k < 3; ++k) {
     const double a = wave_sum(fx[k]), b = wave_sum(fy[k]), c = wave_sum(dm[k]);
     if (w.lane == 0) {
-      double* o = part + int64_t(kPartials) * (int64_t(k) * n + wave);
+      double* o = part + int64_t(kPartials) * (int64_t(k) * n + slot);
       o[0] = a; o[1] = b; o[2] = c; o[3] = 0.0;
+    }
+  }
+}
+
+// ---- three steps per launch at the neural outlet (Sec. 3.1, Eq. 16) -----------
+// An outlet block takes the three steps of the last kOutCols columns (nx-4 ..
+// nx-1) for kOutRows3 rows y0 .. y0+55; the strips stop at column nx-5 and
+// never read what the block computes (their cone stays three columns short
+// of the outlet).  The block stages A_t over columns nx-7 .. nx-1 and rows
+// y0-3 .. y0+58, takes step t+1 on columns nx-6 .. nx-1 for rows y0-2 ..
+// y0+57, step t+2 on columns nx-5 .. nx-1 for rows y0-1 .. y0+56, and step
+// t+3 on its own columns and rows; the outlet column of each step through
+// the network (one 64-row tile per step, the rows past a step's own unused).
+// 56 rows keep the block's LDS under 40 KB: the strips of the same launch
+// reserve it too, and four workgroups per CU is what their registers allow.
+// Measured at 4096 x 1024 FP32 with a 27-64-64-3 network: 118.1 us per
+// launch (97.6 us with the network's three tiles taken out), against 90 us
+// for the Zou & He strips alone and 2 x 37.9 us for two-step launches with
+// the neural outlet: the block's chain of three steps is the launch's
+// critical path, so only LBM_LAUNCH_TRIPLES selects it.  Every node runs the single-step
+// node code and the states between the steps are rounded as a store would
+// round them, so the result is that of three single steps.  Force, mass and
+// fallbacks of each step are counted on the block's own rows and columns.
+template <typename S>
+using T_of = typename Store<S>::T;
+constexpr int kOutRows3 = kNnRows - 8;      // rows per three-step outlet block
+constexpr int kSt3Rows = kOutRows3 + 6;     // staged rows y0-3 .. y0+58
+constexpr int kSt3Cols = kOutCols + 3;      // staged columns nx-7 .. nx-1
+constexpr int kT1Rows = kOutRows3 + 4;      // step t+1 rows y0-2 .. y0+57
+constexpr int kT1Cols = kOutCols + 2;       // step t+1 columns nx-6 .. nx-1
+constexpr int kT2Rows = kOutRows3 + 2;      // step t+2 rows y0-1 .. y0+56
+constexpr int kT2Cols = kOutCols + 1;       // step t+2 columns nx-5 .. nx-1
+static_assert(kT1Rows <= kNnRows, "one network tile per step");
+
+template <typename T>
+struct alignas(16) Nn3Smem {
+  // A_t is dead once step t+1 has pulled it; the post-collision state of
+  // step t+2 and the network activations (live together) then take its
+  // memory, side by side
+  union {
+    T st[9 * kSt3Rows * kSt3Cols];
+    struct {
+      T t2[9 * kT2Rows * kT2Cols];
+      MlpH H;
+    } late;
+  } u;
+  T t1[9 * kT1Rows * kT1Cols];       // post-collision state of step t+1
+  MlpX X;
+  T prev[kNnRows * 4];               // g3, g6, g7, density offset at x = L-1
+};
+static_assert(sizeof(Nn3Smem<float>) <= 40 * 1024, "four workgroups per CU");
+
+// One intermediate step of an outlet block: the interior column c (of the
+// source tile src[R][C], whose last column is the outlet) for block row j
+// (tile row j + 1 of src), result into dst[q][j][c - 1]; features of the
+// columns L-1 .. L-3 and prev at L-1 for the network.  `own`: count force and
+// mass (the block's own rows and columns).
+template <typename S, int MRT, int R, int C, int DR, int DC>
+__device__ __forceinline__ void nn3_interior(const StepLaunch& L, const MlpDev* w, const T_of<S>* src,
+                                             T_of<S>* dst, MlpX& X, T_of<S>* prev, int j, int c,
+                                             uint32_t lk, bool own, double& fx, double& fy, double& dm) {
+  using T = T_of<S>;
+  T g[9];
+  tile_pull<T, R, C>(src, j + 1, c, lk, g);
+  const bool live = !(lk & LINK_SOLID);
+  const int jc = C - 2 - c;                   // column x = L-1-jc
+  if (jc >= 0 && jc <= 2) {
+#pragma unroll
+    for (int q = 0; q < 9; ++q)
+      X.x[j * kXPitch + 9 * jc + q] = live ? feature_bf16(w, 9 * jc + q, float(g[q])) : 0;
+    if (jc == 0) {
+      prev[j * 4 + 0] = g[3];
+      prev[j * 4 + 1] = g[6];
+      prev[j * 4 + 2] = g[7];
+      prev[j * 4 + 3] = macro(g).drho;
+    }
+  }
+  if (live) {
+    if (own) {
+      T fxk = T(0), fyk = T(0);
+      add_force(lk, g, fxk, fyk);
+      fx += double(fxk);
+      fy += double(fyk);
+      dm += double(macro(g).drho);
+    }
+    collide<T, MRT>(g, L);
+  } else {
+#pragma unroll
+    for (int q = 0; q < 9; ++q) g[q] = src[(q * R + j + 1) * C + c];
+  }
+#pragma unroll
+  for (int q = 0; q < 9; ++q) dst[(q * DR + j) * DC + c - 1] = Store<S>::stored(g[q]);
+}
+
+// The outlet node of block row j of an intermediate step: the pull of its
+// known populations from src (whose last column is the outlet).
+template <typename T, int R, int C>
+__device__ __forceinline__ void nn3_outlet_pull(const T* src, int j, uint32_t lko, T go[9]) {
+  tile_pull<T, R, C>(src, j + 1, C - 1, lko, go);
+  if (lko & LINK_SOLID) {
+#pragma unroll
+    for (int q = 0; q < 9; ++q) go[q] = src[(q * R + j + 1) * C + C - 1];
+  }
+}
+
+template <typename S, int MRT>
+__device__ void nn3_block(const StepLaunch& L, int nb, Nn3Smem<T_of<S>>& sm, double* part, int slot) {
+  using T = T_of<S>;
+  const S* __restrict__ A = static_cast<const S*>(L.A);
+  S* __restrict__ B = static_cast<S*>(L.B);
+  const MlpDev* __restrict__ w = L.mlp;
+  const int y0 = nb * kOutRows3;
+  const int xs0 = L.nx - kSt3Cols;           // first staged column
+  const int tid = threadIdx.x;
+  const int j = tid & 63, k = tid >> 6;
+  double fx[3] = {0, 0, 0}, fy[3] = {0, 0, 0}, dm[3] = {0, 0, 0}, nf[3] = {0, 0, 0};
+
+  // the link words of this thread's nodes in the three steps, loaded with
+  // the stage below (the block's chain of steps is its latency): step t+1
+  // rows y0-2+j, columns nx-7+c for c = 5-k (and c = 1, k = 0); step t+2
+  // rows y0-1+j, column nx-6+(4-k); the outlet column (k = 0); step t+3 row
+  // y0+j, column nx-4+k
+  auto link_at = [&](int yrel, int x) -> uint32_t {
+    const int yb = block_row(L, y0 + yrel);
+    return yb >= 0 ? L.links[int64_t(yb) * L.pitch + x] : LINK_SOLID;
+  };
+  uint32_t lk1[2] = {LINK_SOLID, LINK_SOLID}, lk2[2] = {LINK_SOLID, LINK_SOLID};
+  uint32_t lko[2] = {LINK_SOLID, LINK_SOLID};
+  if (j < kT1Rows) {
+    lk1[0] = link_at(j - 2, L.nx - 7 + (5 - k));
+    if (k == 0) {
+      lk1[1] = link_at(j - 2, L.nx - 7 + 1);
+      lko[0] = link_at(j - 2, L.nx - 1);
+    }
+  }
+  if (j < kT2Rows) {
+    lk2[0] = link_at(j - 1, L.nx - 6 + (4 - k));
+    if (k == 0) lko[1] = link_at(j - 1, L.nx - 1);
+  }
+  const bool row_ok = j < kOutRows3 && y0 + j < L.ny;
+  const uint32_t lk3 = row_ok ? L.links[int64_t(y0 + j) * L.pitch + L.nx - 4 + k] : LINK_SOLID;
+
+  // 1. stage A_t[q][y0-3 .. y0+58][nx-7 .. nx-1], every load of a thread
+  // issued before the first is waited for
+  constexpr int kStN = 9 * kSt3Rows * kSt3Cols;
+#pragma unroll
+  for (int it = 0; it < (kStN + kBlock - 1) / kBlock; ++it) {
+    const int i = tid + it * kBlock;
+    if (i < kStN) {
+      const int q = i / (kSt3Rows * kSt3Cols);
+      const int rem = i - q * (kSt3Rows * kSt3Cols);
+      const int r = rem / kSt3Cols, c = rem - r * kSt3Cols;
+      int y = y0 - 3 + r;
+      y = L.yper ? (y + 3 * L.ny) % L.ny : min(max(y, 0), L.ny - 1);   // clamped rows: never pulled
+      sm.u.st[i] = Store<S>::ld(A + int64_t(q) * L.plane + int64_t(y) * L.pitch + xs0 + c);
+    }
+  }
+  __syncthreads();
+
+  // One intermediate step (step index h) from tile src (R x C, outlet last)
+  // into dst (DR x DC): interior columns 1 .. C-2 of src, then the outlet
+  // through the network.  Block rows j = 0 .. DR-1 are rows y0 - (2 - h) + j.
+  auto step = [&](auto src, auto dst, auto Rc, auto Cc, auto DRc, auto DCc, int h,
+                  const uint32_t* lki, uint32_t lkout) {
+    constexpr int R = decltype(Rc)::value, C = decltype(Cc)::value;
+    constexpr int DR = decltype(DRc)::value, DC = decltype(DCc)::value;
+    const int yrel = j - (2 - h);                        // row relative to y0
+    const bool row_in = j < DR;
+    const bool own_row = row_in && yrel >= 0 && yrel < kOutRows3 && y0 + yrel < L.ny;
+    // interior columns 1 .. C-2: thread k takes columns C-2-k, C-6-k, ...
+    int it = 0;
+    for (int c = (C - 2) - k; c >= 1; c -= 4, ++it) {
+      if (row_in) {
+        const bool own = own_row && c >= C - kOutCols;  // own columns nx-4 .. nx-2
+        nn3_interior<S, MRT, R, C, DR, DC>(L, w, src, dst, sm.X, sm.prev, j, c, lki[it], own,
+                                           fx[h], fy[h], dm[h]);
+      } else if (c >= C - 4) {
+        // rows past the step's own rows: no features for the tile
+        const int jc = C - 2 - c;
+#pragma unroll
+        for (int q = 0; q < 9; ++q) sm.X.x[j * kXPitch + 9 * jc + q] = 0;
+      }
+    }
+    if (k == 0) {
+#pragma unroll
+      for (int f = 27; f < 32; ++f) sm.X.x[j * kXPitch + f] = 0;
+    }
+    T go[9];
+    if (k == 0 && row_in) nn3_outlet_pull<T, R, C>(src, j, lkout, go);
+    __syncthreads();                      // features, prev
+    mlp_tile(w, sm.X, sm.u.late.H);
+    if (k == 0 && row_in) {
+      if (!(lkout & LINK_SOLID)) {
+        T fxk = T(0), fyk = T(0);
+        if (own_row) add_force(lkout, go, fxk, fyk);
+        const bool kept = nn_reconstruct(w, &sm.u.late.H.o[j * 4], &sm.prev[j * 4], go,
+                                         T(L.one_minus_rho_out));
+        if (own_row) {
+          fx[h] += double(fxk);
+          fy[h] += double(fyk);
+          dm[h] += double(macro(go).drho);
+          nf[h] += kept ? 0.0 : 1.0;
+        }
+        collide<T, MRT>(go, L);
+      }
+#pragma unroll
+      for (int q = 0; q < 9; ++q) dst[(q * DR + j) * DC + DC - 1] = Store<S>::stored(go[q]);
+    }
+    __syncthreads();                      // dst complete; H read
+  };
+  step(sm.u.st, sm.t1, std::integral_constant<int, kSt3Rows>{}, std::integral_constant<int, kSt3Cols>{},
+       std::integral_constant<int, kT1Rows>{}, std::integral_constant<int, kT1Cols>{}, 0, lk1,
+       lko[0]);
+  step(sm.t1, sm.u.late.t2, std::integral_constant<int, kT1Rows>{}, std::integral_constant<int, kT1Cols>{},
+       std::integral_constant<int, kT2Rows>{}, std::integral_constant<int, kT2Cols>{}, 1, lk2,
+       lko[1]);
+
+  // 3. step t+3 on the block's own rows y0 + j (j < 56): columns nx-4 .. nx-2
+  // (k = 0 .. 2), the outlet column (k = 3)
+  const int y = y0 + j;
+  const uint32_t lk = lk3;
+  T g[9];
+  // rows j >= kOutRows3 are no output rows: their (unused) pull stays inside t2
+  tile_pull<T, kT2Rows, kT2Cols>(sm.u.late.t2, min(j, kOutRows3 - 1) + 1, k + 1, lk, g);
+  const bool live = row_ok && !(lk & LINK_SOLID);
+  if (k < 3) {
+    const int jc = 2 - k;
+#pragma unroll
+    for (int q = 0; q < 9; ++q)
+      sm.X.x[j * kXPitch + 9 * jc + q] = live ? feature_bf16(w, 9 * jc + q, float(g[q])) : 0;
+    if (k == 2) {
+      sm.prev[j * 4 + 0] = g[3];
+      sm.prev[j * 4 + 1] = g[6];
+      sm.prev[j * 4 + 2] = g[7];
+      sm.prev[j * 4 + 3] = macro(g).drho;
+    }
+    if (live) {
+      T fxk = T(0), fyk = T(0);
+      add_force(lk, g, fxk, fyk);
+      fx[2] += double(fxk);
+      fy[2] += double(fyk);
+      dm[2] += double(macro(g).drho);
+      collide<T, MRT>(g, L);
+      const int64_t row = int64_t(y) * L.pitch + L.nx - 4 + k;
+#pragma unroll
+      for (int q = 0; q < 9; ++q) Store<S>::st(B + int64_t(q) * L.plane + row, g[q]);
+    }
+  } else {
+#pragma unroll
+    for (int f = 27; f < 32; ++f) sm.X.x[j * kXPitch + f] = 0;
+  }
+  __syncthreads();
+  mlp_tile(w, sm.X, sm.u.late.H);
+  if (k == 3 && live) {
+    T fxk = T(0), fyk = T(0);
+    add_force(lk, g, fxk, fyk);
+    const bool kept = nn_reconstruct(w, &sm.u.late.H.o[j * 4], &sm.prev[j * 4], g,
+                                     T(L.one_minus_rho_out));
+    fx[2] += double(fxk);
+    fy[2] += double(fyk);
+    dm[2] += double(macro(g).drho);
+    nf[2] += kept ? 0.0 : 1.0;
+    collide<T, MRT>(g, L);
+    const int64_t row = int64_t(y) * L.pitch + L.nx - 1;
+#pragma unroll
+    for (int q = 0; q < 9; ++q) Store<S>::st(B + int64_t(q) * L.plane + row, g[q]);
+  }
+  // one slot per wave and step, as the strips
+  const int n = L.tri_nslots;
+#pragma unroll
+  for (int h = 0; h < 3; ++h) {
+    const double a = wave_sum(fx[h]), b = wave_sum(fy[h]), c = wave_sum(dm[h]), d = wave_sum(nf[h]);
+    if (j == 0) {
+      double* o = part + int64_t(kPartials) * (int64_t(h) * n + slot + k);
+      o[0] = a; o[1] = b; o[2] = c; o[3] = d;
     }
   }
 }
 
 constexpr int kTriSpecial = (1 + 3 * kReducers + 7) / 8 * 8;
 
-template <typename S, int MRT>
+// OUT: 0 the Zou & He outlet inside the strips; OUTLET_NN the neural outlet
+// blocks (the first tri_out workgroups after the reducers).
+template <typename S, int MRT, int OUT>
 __global__ void __launch_bounds__(kBlock) k_step3(const StepLaunch L) {
   const int v = int(blockIdx.x);
   if (v < kTriSpecial) {
@@ -1580,18 +1857,32 @@ __global__ void __launch_bounds__(kBlock) k_step3(const StepLaunch L) {
     }
     return;
   }
-  int sb = v - kTriSpecial;
-  const int nsb = int(gridDim.x) - kTriSpecial;
+  const int b = v - kTriSpecial;
+  double* part = static_cast<double*>(L.part_w);
+  if constexpr (OUT == OUTLET_NN) {
+    if (b < L.tri_out) {
+      __shared__ Nn3Smem<T_of<S>> sm;
+      nn3_block<S, MRT>(L, b, sm, part, b * kWaves);
+      return;
+    }
+  }
+  int sb = b - L.tri_out;
+  const int nsb = int(gridDim.x) - kTriSpecial - L.tri_out;
   sb = L.tri_chunk > 0 ? xcd_remap_chunks(sb, nsb, L.tri_chunk) : xcd_remap(sb, nsb);
-  const int wave = __builtin_amdgcn_readfirstlane(sb * kWaves + int(threadIdx.x >> 6));
-  if (wave >= L.tri_nslots) return;                  // whole wave
-  tri_strip<S, MRT>(L, wave, static_cast<double*>(L.part_w));
+  const int slot = __builtin_amdgcn_readfirstlane((L.tri_out + sb) * kWaves + int(threadIdx.x >> 6));
+  if (slot >= L.tri_nslots) return;                  // whole wave
+  tri_strip<S, MRT>(L, slot - L.tri_out * kWaves, slot, part);
 }
 
 template <typename S, int MRT>
 static hipError_t launch_tri_t(const StepLaunch& L, hipStream_t s) {
   const int blocks = kTriSpecial + (L.tri_nslots + kWaves - 1) / kWaves;
-  hipLaunchKernelGGL((k_step3<S, MRT>), dim3(blocks), dim3(kBlock), 0, s, L);
+  if (L.tri_out > 0 && L.outlet == OUTLET_NN)
+    hipLaunchKernelGGL((k_step3<S, MRT, OUTLET_NN>), dim3(blocks), dim3(kBlock), 0, s, L);
+  else if (L.tri_out == 0)
+    hipLaunchKernelGGL((k_step3<S, MRT, 0>), dim3(blocks), dim3(kBlock), 0, s, L);
+  else
+    return hipErrorInvalidValue;
   return hipGetLastError();
 }
 
@@ -1603,7 +1894,9 @@ int strip_rows(int nx, int ny, int pitch_bytes, int cols);   // below (the strip
 
 int tri_rows(int nx, int ny, int pitch_bytes) { return strip_rows(nx, ny, pitch_bytes, kTriCols); }
 
-int tri_chunk(int nx) { return ((nx + kTriCols - 1) / kTriCols + kWaves - 1) / kWaves; }
+int tri_chunk(int tri_nx) { return ((tri_nx + kTriCols - 1) / kTriCols + kWaves - 1) / kWaves; }
+
+int tri_outlet_blocks(int ny) { return (ny + kOutRows3 - 1) / kOutRows3; }
 
 // FP32 and FP16 offsets (the FP64 variant would need twice the registers).
 bool tri_supported(int precision) { return precision != LBM_FP64; }

@@ -1,5 +1,5 @@
-"""GPU parity of three steps per launch (params.launch = LBM_LAUNCH_TRIPLES,
-Zou & He outflow, FP32 and FP16 offsets).  Every node takes the
+"""GPU parity of three steps per launch (params.launch = LBM_LAUNCH_TRIPLES
+or the default, Zou & He and neural outflows, FP32 and FP16 offsets).  Every node takes the
 single-step node code, and the states after the first two steps of a
 launch are rounded to the storage precision as a store and reload would
 round them, so the populations equal those of one launch per step bit for
@@ -75,16 +75,59 @@ def test_triples_full_size_c2_against_oracle():
     np.testing.assert_allclose(fy, o.fy_hist, rtol=1e-5, atol=1e-7)
 
 
-def test_triples_with_the_neural_outflow_fall_back_to_pairs():
-    # other outflows have no three-step form: the same bits as two-step launches
+@pytest.mark.parametrize("precision,mass_bound", [("fp32", 1e9), ("fp32", 3e-4), ("fp16", 3e-4)])
+def test_triples_with_the_neural_outflow_equal_single_steps(precision, mass_bound):
+    # the three-step outlet blocks run the single-step node code and Eq. 16
+    # with its fallback on the same network tiles: the same populations bit
+    # for bit and the same fallback counts, over counts that leave one or
+    # two steps for other launches
     case = cases.ragged("mrt", "periodic")
     P = {k: np.asarray(v, np.float32).astype(np.float64)
          for k, v in cases.random_params(3, w_scale=0.5, out_sd=2e-4).items()}
-    _say("triples with the neural outflow")
+    _say("nn triples vs single steps", precision, mass_bound)
+    out = {}
+    for launch in ("triples", "single"):
+        g = _gpu(case, precision, 86, launch)
+        g.set_outflow_nn(P, mass_bound=mass_bound)
+        for n in (40, 7, 34, 2, 3):
+            g.step(n)
+        out[launch] = (g.populations(), g.forces().n_fallback, g.force_history())
+    (f1, n1, (fx1, _)), (f0, n0, (fx0, _)) = out["triples"], out["single"]
+    print("nn triples vs single: populations that differ", np.count_nonzero(f1 != f0),
+          "fallbacks", n1, n0, flush=True)
+    np.testing.assert_array_equal(f1, f0)
+    assert n1 == n0
+    if mass_bound < 1:
+        assert 0.1 * 86 * 77 < n0 < 0.9 * 86 * 77      # partial fallback
+    np.testing.assert_allclose(fx1, fx0, rtol=0, atol=1e-5 * np.max(np.abs(fx0)) + 1e-15)
+
+
+def test_triples_with_the_neural_outflow_on_a_tall_lattice():
+    # several outlet blocks of 56 rows and a ragged last one, walls
+    case = cases.c1(100.0, "mrt")
+    mask = np.pad(case["mask"], ((0, 131 - case["mask"].shape[0]), (0, 0)))
+    case = dict(case, mask=mask)
+    P = {k: np.asarray(v, np.float32).astype(np.float64)
+         for k, v in cases.random_params(4, w_scale=0.5, out_sd=2e-4).items()}
+    _say("nn triples, 131 rows")
+    out = {}
+    for launch in ("triples", "single"):
+        g = _gpu(case, "fp32", 30, launch)
+        g.set_outflow_nn(P, mass_bound=1e-2)
+        g.step(30)
+        out[launch] = g.populations()
+    np.testing.assert_array_equal(out["triples"], out["single"])
+
+
+def test_triples_with_the_characteristic_outflow_take_pairs():
+    # the characteristic outlet has no three-step form: two-step launches,
+    # the same bits as LBM_LAUNCH_PAIRS
+    case = cases.ragged("mrt", "periodic")
+    _say("triples with the characteristic outflow")
     out = {}
     for launch in ("triples", "pairs"):
         g = _gpu(case, "fp32", 20, launch)
-        g.set_outflow_nn(P, mass_bound=3e-4)
+        g.set_outflow_cbc(sigma=0.25, kappa2=0.1, mach=0.1 / 3 ** -0.5)
         g.step(20)
         out[launch] = g.populations()
     np.testing.assert_array_equal(out["triples"], out["pairs"])
