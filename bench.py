@@ -590,10 +590,9 @@ def main():
               "zouhe_pairs_mlups": nodes / (ms_two * 1e-3) / 1e6,
               "zouhe_single_mlups": nodes / (ms_single * 1e-3) / 1e6,
               "weights": "random-init 27-64-64-3", "fallback_nodes": int(out_nn.n_fallback),
-              "note": "the neural outflow runs two steps per launch (its three-step form is "
-                      "slower); ratio_to_zouhe: against the Zou & He lattice on the timed "
-                      "schedule; ratio_to_zouhe_pairs: against Zou & He at two steps per "
-                      "launch, the same schedule; ratio_to_zouhe_single: one launch per step"}
+              "note": "ratio_to_zouhe: against the Zou & He lattice on the timed schedule "
+                      "(three steps per launch for both); ratio_to_zouhe_pairs: against Zou & "
+                      "He at two steps per launch; ratio_to_zouhe_single: one launch per step"}
     else:
         del lat
     cbc = None

@@ -160,7 +160,7 @@ Layout make_layout(const lbm_params& p) {
                           2 * (pair_waves(p.nx, p.ny, pair_rows(p.nx, p.ny, row_bytes)) +
                                pair_outlet_blocks(p.ny) * kWaves));
   if (tri_supported(p.precision))
-    L.nslots_max = std::max(L.nslots_max, 3 * (tri_waves(p.nx, p.ny, tri_rows(p.nx, p.ny, row_bytes)) +
+    L.nslots_max = std::max(L.nslots_max, 3 * (tri_waves(p.nx, p.ny, tri_rows(p.nx, p.ny, row_bytes, 0)) +
                                                tri_outlet_blocks(p.ny) * kWaves));
   L.plane = padded_plane(int64_t(p.ny) * L.pitch, elem_size(p.precision));
   const size_t pop = size_t(9) * size_t(L.plane) * elem_size(p.precision);
@@ -310,7 +310,7 @@ struct lbm_ctx {
     // and come first (the characteristic outlet has no three-step form)
     L.tri_out = outflow == LBM_OUT_NN ? tri_outlet_blocks(p.ny) : 0;
     L.tri_nx = L.tri_out ? p.nx - pair_outlet_cols() : p.nx;
-    L.tri_rows = tri_rows(p.nx, p.ny, lay.pitch * int(elem_size(p.precision)));
+    L.tri_rows = tri_rows(L.tri_nx, p.ny, lay.pitch * int(elem_size(p.precision)), L.tri_out);
     L.tri_nslots = tri_waves(L.tri_nx, p.ny, L.tri_rows) + L.tri_out * kWaves;
     L.tri_chunk = tri_chunk(L.tri_nx);
     L.nslots = (L.nspecial - 1 - kReducers + lay.ntx * lay.nty) * kWaves;
@@ -496,16 +496,11 @@ lbm_status lbm_step(lbm_ctx* c, int64_t nsteps) {
   if (nsteps < 0) return fail(LBM_EINVAL, "nsteps < 0");
   if (nsteps == 0) return LBM_OK;
   int64_t s = 0;
-  // Three steps run in each launch with params.launch = LBM_LAUNCH_AUTO and
-  // the Zou & He outflow, or LBM_LAUNCH_TRIPLES and the Zou & He or the
-  // neural outflow, at FP32 and FP16 offsets; the rest of the count as
-  // below.  (The neural outlet's three-step blocks are slower than its
-  // two-step launches, so the default keeps two for it.)
-  const bool triples = tri_supported(c->p.precision) &&
-                       (c->outflow == LBM_OUT_ZOUHE ? c->p.launch == LBM_LAUNCH_AUTO ||
-                                                          c->p.launch == LBM_LAUNCH_TRIPLES
-                                                    : c->outflow == LBM_OUT_NN &&
-                                                          c->p.launch == LBM_LAUNCH_TRIPLES);
+  // With params.launch = LBM_LAUNCH_AUTO or LBM_LAUNCH_TRIPLES, the Zou & He
+  // or the neural outflow and FP32 or FP16 offsets, three steps run in each
+  // launch; the rest of the count as below.
+  const bool triples = (c->p.launch == LBM_LAUNCH_AUTO || c->p.launch == LBM_LAUNCH_TRIPLES) &&
+                       c->outflow != LBM_OUT_CBC && tri_supported(c->p.precision);
   if (nsteps >= 3 && triples) {
     for (; s + 2 < nsteps; s += 3) {
       const StepLaunch L = c->launch();

@@ -146,7 +146,9 @@ hipError_t launch_pair(const StepLaunch& L, hipStream_t s);
 hipError_t launch_finalize_pair(const StepLaunch& L, hipStream_t s);
 // Three steps per launch (Zou & He outflow, FP32 and FP16 offsets).
 int tri_waves(int nx, int ny, int rows);
-int tri_rows(int nx, int ny, int pitch_bytes);
+// Output rows per strip of the three-step kernel; the strips and the
+// outlet blocks of one launch share the four waves per SIMD of the rule.
+int tri_rows(int nx, int ny, int pitch_bytes, int outlet_blocks);
 int tri_chunk(int tri_nx);
 int tri_outlet_blocks(int ny);
 bool tri_supported(int precision);

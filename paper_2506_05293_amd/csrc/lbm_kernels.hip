@@ -1578,11 +1578,10 @@ __device__ __forceinline__ void tri_strip(const StepLaunch& L, int wave, int slo
 // the network (one 64-row tile per step, the rows past a step's own unused).
 // 56 rows keep the block's LDS under 40 KB: the strips of the same launch
 // reserve it too, and four workgroups per CU is what their registers allow.
-// Measured at 4096 x 1024 FP32 with a 27-64-64-3 network: 118.1 us per
-// launch (97.6 us with the network's three tiles taken out), against 90 us
-// for the Zou & He strips alone and 2 x 37.9 us for two-step launches with
-// the neural outlet: the block's chain of three steps is the launch's
-// critical path, so only LBM_LAUNCH_TRIPLES selects it.  Every node runs the single-step
+// The strip-height rule counts the blocks' waves (tri_rows): at 4096 x 1024
+// the 18-row strips and the 19 blocks overfilled four waves per SIMD, seven
+// strip workgroups waited for a second round, and a launch took 118.1 us
+// (134.7k MLUPS with 19-row strips, 0.96 of the Zou & He step).  Every node runs the single-step
 // node code and the states between the steps are rounded as a store would
 // round them, so the result is that of three single steps.  Force, mass and
 // fallbacks of each step are counted on the block's own rows and columns.
@@ -1890,9 +1889,13 @@ int tri_waves(int nx, int ny, int rows) {
   return ((nx + kTriCols - 1) / kTriCols) * ((ny + rows - 1) / rows);
 }
 
-int strip_rows(int nx, int ny, int pitch_bytes, int cols);   // below (the strip-height rule)
+int strip_rows(int nx, int ny, int pitch_bytes, int cols, int reserved_waves, int max_rows);   // below
 
-int tri_rows(int nx, int ny, int pitch_bytes) { return strip_rows(nx, ny, pitch_bytes, kTriCols); }
+constexpr int kTriRowsMax = 24;
+
+int tri_rows(int nx, int ny, int pitch_bytes, int outlet_blocks) {
+  return strip_rows(nx, ny, pitch_bytes, kTriCols, outlet_blocks * kWaves, kTriRowsMax);
+}
 
 int tri_chunk(int tri_nx) { return ((tri_nx + kTriCols - 1) / kTriCols + kWaves - 1) / kWaves; }
 
@@ -1938,7 +1941,10 @@ int pair_waves(int nx, int ny, int rows) {
 
 // Output rows per strip.  The shortest strips (least halo per wave is the
 // longest) that keep the grid within four waves per SIMD (4096 waves: all
-// resident at once with room to spare), between 12 and 18 rows; a height
+// resident at once with room to spare; outlet blocks of the same launch,
+// reserved_waves, count against them, since they last as long as a strip),
+// between 12 and max_rows rows (18 for two steps per launch, 24 for three:
+// with the neural outlet's 76 waves the 4096 x 1024 grid needs 19); a height
 // above 12 whose band stride (rows x row bytes) is a multiple of 64 KiB is
 // moved by one row, since bands that start on such strides met the same
 // HBM channels (4096 x 1024 FP32: 16 rows 104.9k, 18 rows 111.7k MLUPS).
@@ -1949,16 +1955,18 @@ int pair_waves(int nx, int ny, int rows) {
 // 16384 x 4096 17 rows 114.0k (16: 115.0k, 24: 110.6k); FP16 4096 x 1024
 // 143.7k (24: 127.6k); FP64 4096 x 1024 52.2k (24: 53.2k).
 constexpr int kSimds = 256 * 4;      // the MI355X's 256 CUs of four SIMDs each
-int strip_rows(int nx, int ny, int pitch_bytes, int cols) {
+int strip_rows(int nx, int ny, int pitch_bytes, int cols, int reserved_waves, int max_rows) {
   const int strips = (nx + cols - 1) / cols;
-  const int bands = std::max(1, 4 * kSimds / strips);
-  int rows = std::min(std::max((ny + bands - 1) / bands, kPairRowsMin), kPairRowsMax);
+  const int bands = std::max(1, (4 * kSimds - reserved_waves) / strips);
+  int rows = std::min(std::max((ny + bands - 1) / bands, kPairRowsMin), max_rows);
   if (rows > kPairRowsMin && (int64_t(rows) * pitch_bytes) % 65536 == 0)
-    rows += rows < kPairRowsMax ? 1 : -1;
+    rows += rows < max_rows ? 1 : -1;
   return rows;
 }
 
-int pair_rows(int nx, int ny, int pitch_bytes) { return strip_rows(nx, ny, pitch_bytes, kPairCols); }
+int pair_rows(int nx, int ny, int pitch_bytes) {
+  return strip_rows(nx, ny, pitch_bytes, kPairCols, 0, kPairRowsMax);
+}
 
 int pair_outlet_blocks(int ny) { return (ny + kOutRows - 1) / kOutRows; }
 
