@@ -161,7 +161,7 @@ Layout make_layout(const lbm_params& p) {
                                pair_outlet_blocks(p.ny) * kWaves));
   if (tri_supported(p.precision))
     L.nslots_max = std::max(L.nslots_max, 3 * (tri_waves(p.nx, p.ny, tri_rows(p.nx, p.ny, row_bytes, 0)) +
-                                               tri_outlet_blocks(p.ny) * kWaves));
+                                               tri_outlet_blocks(p.ny, true) * kWaves));
   L.plane = padded_plane(int64_t(p.ny) * L.pitch, elem_size(p.precision));
   const size_t pop = size_t(9) * size_t(L.plane) * elem_size(p.precision);
   size_t o = 0;
@@ -306,9 +306,9 @@ struct lbm_ctx {
                                                        : pair_hold(p.precision, 9 * lay.plane * int64_t(elem_size(p.precision)));
     L.pair_nslots = pair_waves(L.pair_nx, p.ny, L.pair_rows) + L.pair_out * kWaves;
     L.pair_chunk = pair_chunk(L.pair_nx);
-    // three-step launches: the neural outlet's blocks take the last columns
-    // and come first (the characteristic outlet has no three-step form)
-    L.tri_out = outflow == LBM_OUT_NN ? tri_outlet_blocks(p.ny) : 0;
+    // three-step launches: the neural or characteristic outlet's blocks take
+    // the last columns and come first
+    L.tri_out = outflow == LBM_OUT_ZOUHE ? 0 : tri_outlet_blocks(p.ny, outflow == LBM_OUT_CBC);
     L.tri_nx = L.tri_out ? p.nx - pair_outlet_cols() : p.nx;
     L.tri_rows = tri_rows(L.tri_nx, p.ny, lay.pitch * int(elem_size(p.precision)), L.tri_out);
     L.tri_nslots = tri_waves(L.tri_nx, p.ny, L.tri_rows) + L.tri_out * kWaves;
@@ -496,11 +496,11 @@ lbm_status lbm_step(lbm_ctx* c, int64_t nsteps) {
   if (nsteps < 0) return fail(LBM_EINVAL, "nsteps < 0");
   if (nsteps == 0) return LBM_OK;
   int64_t s = 0;
-  // With params.launch = LBM_LAUNCH_AUTO or LBM_LAUNCH_TRIPLES, the Zou & He
-  // or the neural outflow and FP32 or FP16 offsets, three steps run in each
-  // launch; the rest of the count as below.
+  // With params.launch = LBM_LAUNCH_AUTO or LBM_LAUNCH_TRIPLES and FP32 or
+  // FP16 offsets, three steps run in each launch (any outflow); the rest of
+  // the count as below.
   const bool triples = (c->p.launch == LBM_LAUNCH_AUTO || c->p.launch == LBM_LAUNCH_TRIPLES) &&
-                       c->outflow != LBM_OUT_CBC && tri_supported(c->p.precision);
+                       tri_supported(c->p.precision);
   if (nsteps >= 3 && triples) {
     for (; s + 2 < nsteps; s += 3) {
       const StepLaunch L = c->launch();
@@ -509,6 +509,7 @@ lbm_status lbm_step(lbm_ctx* c, int64_t nsteps) {
       c->pend1 = true;
       c->pcur ^= 1;
       c->cur ^= 1;
+      if (c->outflow == LBM_OUT_CBC) c->dtcur ^= 1;    // the launch wrote the other buffer
     }
     StepLaunch F = c->launch();
     HIP_TRY(launch_finalize_triple(F, c->stream));

@@ -150,7 +150,8 @@ int tri_waves(int nx, int ny, int rows);
 // outlet blocks of one launch share the four waves per SIMD of the rule.
 int tri_rows(int nx, int ny, int pitch_bytes, int outlet_blocks);
 int tri_chunk(int tri_nx);
-int tri_outlet_blocks(int ny);
+// Outlet blocks of a three-step launch for ny rows (neural, or characteristic).
+int tri_outlet_blocks(int ny, bool cbc);
 bool tri_supported(int precision);
 hipError_t launch_triple(const StepLaunch& L, hipStream_t s);
 hipError_t launch_finalize_triple(const StepLaunch& L, hipStream_t s);

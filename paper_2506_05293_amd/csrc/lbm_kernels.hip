@@ -1,6 +1,11 @@
 // HIP kernels of the D2Q9 time step for gfx950.
 //
-// One launch advances the lattice by one step (Sec. 2.1 Eq. 1 in pull form):
+// Three kernels take the step: k_step3 advances three steps per launch
+// (Zou & He or neural outflow, FP32 and FP16 offsets; the default), k_step2
+// two (every outflow and precision), k_step one (described first below).
+// All run the same node code, so the populations agree bit for bit.
+//
+// One launch of k_step advances the lattice by one step (Sec. 2.1 Eq. 1 in pull form):
 // every fluid node gathers the post-collision populations of its neighbours
 // from buffer A (half-way bounce-back where the source is a wall or a solid,
 // Eq. 12), completes the inlet / outlet column (Sec. 2.2; Sec. 3.1 Eq. 16;
@@ -1841,6 +1846,230 @@ __device__ void nn3_block(const StepLaunch& L, int nb, Nn3Smem<T_of<S>>& sm, dou
   }
 }
 
+// ---- three steps per launch at the characteristic outlet (Sec. 4) --------------
+// The geometry of the three-step neural blocks with kCbRows3 own rows: A_t
+// staged over columns nx-7 .. nx-1 and rows y0-3 .. y0+50 (rows wrapped:
+// periodic laterals), step t+1 on columns nx-6 .. nx-1 for rows y0-2 ..
+// y0+49, step t+2 on columns nx-5 .. nx-1 for rows y0-1 .. y0+48, step t+3
+// on the own columns and rows.  The outlet column of each step takes the
+// LODI update of the moments of the state before it (columns nx-3 .. nx-1),
+// the tuning network's features taking the time derivatives of the step
+// before: from L.cbc_dt for step t+1, from LDS for the next two; step t+3's
+// derivatives of the own rows go to L.cbc_dt_w.  48 rows keep the block's
+// LDS under 40 KB (four workgroups per CU, as for the strips).
+constexpr int kCbRows3 = 48;
+constexpr int kCSt3Rows = kCbRows3 + 6;     // staged rows y0-3 .. y0+50
+constexpr int kCT1Rows = kCbRows3 + 4;      // step t+1 rows y0-2 .. y0+49
+constexpr int kCT2Rows = kCbRows3 + 2;      // step t+2 rows y0-1 .. y0+48
+static_assert(kCT1Rows <= kNnRows, "one network tile per step");
+
+template <typename T>
+struct alignas(16) Cbc3Smem {
+  union {
+    T st[9 * kCSt3Rows * kSt3Cols];  // A_t (dead once step t+1 is done)
+    T t2[9 * kCT2Rows * kT2Cols];    // post-collision state of step t+2
+  } u;
+  T t1[9 * kCT1Rows * kT1Cols];      // post-collision state of step t+1
+  T mo[3 * 3 * kCSt3Rows];           // moments of the last three columns of the state in use
+  T dt[2][kNnRows * 3];              // p_t, u_t, v_t of steps t+1 and t+2 per block row
+  CbcNetSmem<T> net;
+};
+static_assert(sizeof(Cbc3Smem<float>) <= 40 * 1024, "four workgroups per CU");
+
+template <typename S, int MRT>
+__device__ void cbc3_block(const StepLaunch& L, int nb, Cbc3Smem<T_of<S>>& sm, double* part, int slot) {
+  using T = T_of<S>;
+  const S* __restrict__ A = static_cast<const S*>(L.A);
+  S* __restrict__ B = static_cast<S*>(L.B);
+  const CbcDev* __restrict__ c = L.cbc;
+  const int y0 = nb * kCbRows3;
+  const int xs0 = L.nx - kSt3Cols;
+  const int tid = threadIdx.x;
+  const int j = tid & 63, k = tid >> 6;
+  double fx[3] = {0, 0, 0}, fy[3] = {0, 0, 0}, dm[3] = {0, 0, 0};
+
+  // 1. stage A_t[q][y0-3 .. y0+50][nx-7 .. nx-1] (rows wrapped)
+  constexpr int kStN = 9 * kCSt3Rows * kSt3Cols;
+#pragma unroll
+  for (int it = 0; it < (kStN + kBlock - 1) / kBlock; ++it) {
+    const int i = tid + it * kBlock;
+    if (i < kStN) {
+      const int q = i / (kCSt3Rows * kSt3Cols);
+      const int rem = i - q * (kCSt3Rows * kSt3Cols);
+      const int r = rem / kSt3Cols, cc = rem - r * kSt3Cols;
+      const int y = (y0 - 3 + r + 3 * L.ny) % L.ny;
+      sm.u.st[i] = Store<S>::ld(A + int64_t(q) * L.plane + int64_t(y) * L.pitch + xs0 + cc);
+    }
+  }
+  __syncthreads();
+
+  // One intermediate step (index h) from tile src (R x C, outlet last) into
+  // dst (DR x DC): block rows j = 0 .. DR-1 are rows y0 - (2 - h) + j; the
+  // moments of src's last three columns are taken first; the outlet's
+  // previous time derivatives come from prevdt (NULL: L.cbc_dt), its new
+  // ones go to sm.dt[h].
+  auto step = [&](const T* src, T* dst, auto Rc, auto Cc, auto DRc, auto DCc, int h) {
+    constexpr int R = decltype(Rc)::value, C = decltype(Cc)::value;
+    constexpr int DR = decltype(DRc)::value, DC = decltype(DCc)::value;
+    tile_moments<T, R, C>(src, C - 3, sm.mo);
+    const int yrel = j - (2 - h);
+    const bool row_in = j < DR;
+    const int yb = (y0 + yrel + 2 * L.ny) % L.ny;
+    const bool own_row = row_in && yrel >= 0 && yrel < kCbRows3 && y0 + yrel < L.ny;
+    // interior columns 1 .. C-2: thread k takes columns C-2-k, C-6-k, ...
+    for (int cc = (C - 2) - k; cc >= 1; cc -= 4) {
+      if (!row_in) continue;
+      const int x = L.nx - C + cc;
+      const uint32_t lk = L.links[int64_t(yb) * L.pitch + x];
+      const bool own = own_row && cc >= C - kOutCols;
+      T g[9];
+      tile_pull<T, R, C>(src, j + 1, cc, lk, g);
+      if (!(lk & LINK_SOLID)) {
+        if (own) {
+          T fxk = T(0), fyk = T(0);
+          add_force(lk, g, fxk, fyk);
+          fx[h] += double(fxk);
+          fy[h] += double(fyk);
+          dm[h] += double(macro(g).drho);
+        }
+        collide<T, MRT>(g, L);
+      } else {
+#pragma unroll
+        for (int q = 0; q < 9; ++q) g[q] = src[(q * R + j + 1) * C + cc];
+      }
+#pragma unroll
+      for (int q = 0; q < 9; ++q) dst[(q * DR + j) * DC + cc - 1] = Store<S>::stored(g[q]);
+    }
+    __syncthreads();                      // moments of src
+    T sigma = T(c->sigma), kappa2 = T(c->kappa2);
+    if (c->has_net) {
+      if (tid < kNnRows) {
+        const int r = min(j, DR - 1) + 1;   // rows past the step's own: unused
+        T g6[6];
+        cbc_gradients<T, R>(sm.mo, r, g6);
+        T prev[3];
+        if (h == 0) {
+          const double* d = L.cbc_dt + 4 * int64_t((y0 + min(j, DR - 1) - 2 + 2 * L.ny) % L.ny);
+          prev[0] = T(d[0]); prev[1] = T(d[1]); prev[2] = T(d[2]);
+        } else {
+          // the previous step's rows are shifted by one against this step's
+          const int rp = min(j, DR - 1) + 1;
+          prev[0] = sm.dt[h - 1][rp * 3 + 0];
+          prev[1] = sm.dt[h - 1][rp * 3 + 1];
+          prev[2] = sm.dt[h - 1][rp * 3 + 2];
+        }
+        cbc_features(c, g6, prev, &sm.net.feat[j * kCbcIn]);
+      }
+      cbc_network(c, sm.net, sigma, kappa2);
+    }
+    if (tid < kNnRows && row_in) {
+      const uint32_t lk = L.links[int64_t(yb) * L.pitch + L.nx - 1];
+      T g[9];
+      tile_pull<T, R, C>(src, j + 1, C - 1, lk, g);
+      if (!(lk & LINK_SOLID)) {
+        const int r = j + 1;
+        T g6[6], nst[3], dtn[3];
+        cbc_gradients<T, R>(sm.mo, r, g6);
+        cbc_lodi(c, g6, sm.mo[(0 * 3 + 2) * R + r], sm.mo[(1 * 3 + 2) * R + r],
+                 sm.mo[(2 * 3 + 2) * R + r], sigma, kappa2, nst, dtn);
+        sm.dt[h][j * 3 + 0] = dtn[0];
+        sm.dt[h][j * 3 + 1] = dtn[1];
+        sm.dt[h][j * 3 + 2] = dtn[2];
+        outlet_state(g, nst[0], nst[1], nst[2]);
+        if (own_row) {
+          T fxk = T(0), fyk = T(0);
+          add_force(lk, g, fxk, fyk);
+          fx[h] += double(fxk);
+          fy[h] += double(fyk);
+          dm[h] += double(macro(g).drho);
+        }
+        collide<T, MRT>(g, L);
+      } else {
+#pragma unroll
+        for (int q = 0; q < 9; ++q) g[q] = src[(q * R + j + 1) * C + C - 1];
+        sm.dt[h][j * 3 + 0] = sm.dt[h][j * 3 + 1] = sm.dt[h][j * 3 + 2] = T(0);
+      }
+#pragma unroll
+      for (int q = 0; q < 9; ++q) dst[(q * DR + j) * DC + DC - 1] = Store<S>::stored(g[q]);
+    }
+    __syncthreads();                      // dst complete; the moments and src read
+  };
+  step(sm.u.st, sm.t1, std::integral_constant<int, kCSt3Rows>{}, std::integral_constant<int, kSt3Cols>{},
+       std::integral_constant<int, kCT1Rows>{}, std::integral_constant<int, kT1Cols>{}, 0);
+  step(sm.t1, sm.u.t2, std::integral_constant<int, kCT1Rows>{}, std::integral_constant<int, kT1Cols>{},
+       std::integral_constant<int, kCT2Rows>{}, std::integral_constant<int, kT2Cols>{}, 1);
+
+  // 3. step t+3 on the own rows y0 + j (j < 48): columns nx-4 .. nx-2 (k < 3)
+  tile_moments<T, kCT2Rows, kT2Cols>(sm.u.t2, kT2Cols - 3, sm.mo);
+  const int y = y0 + j;
+  const bool row_ok = j < kCbRows3 && y < L.ny;
+  if (k < 3 && row_ok) {
+    const uint32_t lk = L.links[int64_t(y) * L.pitch + L.nx - 4 + k];
+    if (!(lk & LINK_SOLID)) {
+      T g[9];
+      tile_pull<T, kCT2Rows, kT2Cols>(sm.u.t2, j + 1, k + 1, lk, g);
+      T fxk = T(0), fyk = T(0);
+      add_force(lk, g, fxk, fyk);
+      fx[2] += double(fxk);
+      fy[2] += double(fyk);
+      dm[2] += double(macro(g).drho);
+      collide<T, MRT>(g, L);
+      const int64_t off = int64_t(y) * L.pitch + L.nx - 4 + k;
+#pragma unroll
+      for (int q = 0; q < 9; ++q) Store<S>::st(B + int64_t(q) * L.plane + off, g[q]);
+    }
+  }
+  __syncthreads();                      // moments of step t+2
+  T sigma = T(c->sigma), kappa2 = T(c->kappa2);
+  if (c->has_net) {
+    if (tid < kNnRows) {
+      const int r = min(j, kCbRows3 - 1) + 1;    // rows j >= 48: unused
+      T g6[6];
+      cbc_gradients<T, kCT2Rows>(sm.mo, r, g6);
+      const T prev[3] = {sm.dt[1][r * 3 + 0], sm.dt[1][r * 3 + 1], sm.dt[1][r * 3 + 2]};
+      cbc_features(c, g6, prev, &sm.net.feat[j * kCbcIn]);
+    }
+    cbc_network(c, sm.net, sigma, kappa2);
+  }
+  if (tid < kNnRows && row_ok) {
+    const uint32_t lk = L.links[int64_t(y) * L.pitch + L.nx - 1];
+    if (!(lk & LINK_SOLID)) {
+      const int r = j + 1;
+      T g[9], g6[6], nst[3], dtn[3];
+      tile_pull<T, kCT2Rows, kT2Cols>(sm.u.t2, r, kT2Cols - 1, lk, g);
+      cbc_gradients<T, kCT2Rows>(sm.mo, r, g6);
+      cbc_lodi(c, g6, sm.mo[(0 * 3 + 2) * kCT2Rows + r], sm.mo[(1 * 3 + 2) * kCT2Rows + r],
+               sm.mo[(2 * 3 + 2) * kCT2Rows + r], sigma, kappa2, nst, dtn);
+      double* d = L.cbc_dt_w + 4 * int64_t(y);
+      d[0] = double(dtn[0]);
+      d[1] = double(dtn[1]);
+      d[2] = double(dtn[2]);
+      outlet_state(g, nst[0], nst[1], nst[2]);
+      T fxk = T(0), fyk = T(0);
+      add_force(lk, g, fxk, fyk);
+      fx[2] += double(fxk);
+      fy[2] += double(fyk);
+      dm[2] += double(macro(g).drho);
+      collide<T, MRT>(g, L);
+      const int64_t off = int64_t(y) * L.pitch + L.nx - 1;
+#pragma unroll
+      for (int q = 0; q < 9; ++q) Store<S>::st(B + int64_t(q) * L.plane + off, g[q]);
+    } else {
+      double* d = L.cbc_dt_w + 4 * int64_t(y);
+      d[0] = d[1] = d[2] = 0.0;
+    }
+  }
+  const int n = L.tri_nslots;
+#pragma unroll
+  for (int h = 0; h < 3; ++h) {
+    const double a = wave_sum(fx[h]), b = wave_sum(fy[h]), cc = wave_sum(dm[h]);
+    if (j == 0) {
+      double* o = part + int64_t(kPartials) * (int64_t(h) * n + slot + k);
+      o[0] = a; o[1] = b; o[2] = cc; o[3] = 0.0;
+    }
+  }
+}
+
 constexpr int kTriSpecial = (1 + 3 * kReducers + 7) / 8 * 8;
 
 // OUT: 0 the Zou & He outlet inside the strips; OUTLET_NN the neural outlet
@@ -1864,6 +2093,12 @@ __global__ void __launch_bounds__(kBlock) k_step3(const StepLaunch L) {
       nn3_block<S, MRT>(L, b, sm, part, b * kWaves);
       return;
     }
+  } else if constexpr (OUT == OUTLET_CBC) {
+    if (b < L.tri_out) {
+      __shared__ Cbc3Smem<T_of<S>> sm;
+      cbc3_block<S, MRT>(L, b, sm, part, b * kWaves);
+      return;
+    }
   }
   int sb = b - L.tri_out;
   const int nsb = int(gridDim.x) - kTriSpecial - L.tri_out;
@@ -1878,6 +2113,8 @@ static hipError_t launch_tri_t(const StepLaunch& L, hipStream_t s) {
   const int blocks = kTriSpecial + (L.tri_nslots + kWaves - 1) / kWaves;
   if (L.tri_out > 0 && L.outlet == OUTLET_NN)
     hipLaunchKernelGGL((k_step3<S, MRT, OUTLET_NN>), dim3(blocks), dim3(kBlock), 0, s, L);
+  else if (L.tri_out > 0 && L.outlet == OUTLET_CBC)
+    hipLaunchKernelGGL((k_step3<S, MRT, OUTLET_CBC>), dim3(blocks), dim3(kBlock), 0, s, L);
   else if (L.tri_out == 0)
     hipLaunchKernelGGL((k_step3<S, MRT, 0>), dim3(blocks), dim3(kBlock), 0, s, L);
   else
@@ -1899,7 +2136,10 @@ int tri_rows(int nx, int ny, int pitch_bytes, int outlet_blocks) {
 
 int tri_chunk(int tri_nx) { return ((tri_nx + kTriCols - 1) / kTriCols + kWaves - 1) / kWaves; }
 
-int tri_outlet_blocks(int ny) { return (ny + kOutRows3 - 1) / kOutRows3; }
+int tri_outlet_blocks(int ny, bool cbc) {
+  const int rows = cbc ? kCbRows3 : kOutRows3;
+  return (ny + rows - 1) / rows;
+}
 
 // FP32 and FP16 offsets (the FP64 variant would need twice the registers).
 bool tri_supported(int precision) { return precision != LBM_FP64; }

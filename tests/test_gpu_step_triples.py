@@ -1,5 +1,6 @@
 """GPU parity of three steps per launch (params.launch = LBM_LAUNCH_TRIPLES
-or the default, Zou & He and neural outflows, FP32 and FP16 offsets).  Every node takes the
+or the default; Zou & He, neural and characteristic outflows; FP32 and FP16
+offsets).  Every node takes the
 single-step node code, and the states after the first two steps of a
 launch are rounded to the storage precision as a store and reload would
 round them, so the populations equal those of one launch per step bit for
@@ -119,15 +120,30 @@ def test_triples_with_the_neural_outflow_on_a_tall_lattice():
     np.testing.assert_array_equal(out["triples"], out["single"])
 
 
-def test_triples_with_the_characteristic_outflow_take_pairs():
-    # the characteristic outlet has no three-step form: two-step launches,
-    # the same bits as LBM_LAUNCH_PAIRS
-    case = cases.ragged("mrt", "periodic")
-    _say("triples with the characteristic outflow")
+@pytest.mark.parametrize("net", [False, True])
+def test_triples_with_the_characteristic_outflow_equal_single_steps(net):
+    # the three-step outlet blocks of the characteristic outflow run the
+    # single-step arithmetic (LODI update, Eq. 29 reconstruction, the
+    # tuning network) and carry the time derivatives of each step to the
+    # next in LDS: the same populations bit for bit in FP32, over counts that
+    # leave one or two steps for other launches and a lattice taller than
+    # one outlet block
+    from test_gpu_cbc import FIXED, random_net, vortex_fields
+    from paper_2506_05293_amd import geometry
+    _say("cbc triples vs single steps", "network" if net else "fixed")
+    cbc = dict(FIXED, net=random_net(3)) if net else FIXED
+    nx, ny = 61, 107
+    mask = geometry.cylinder(nx, ny, 14.3, 50.6, 9.0)
     out = {}
-    for launch in ("triples", "pairs"):
-        g = _gpu(case, "fp32", 20, launch)
-        g.set_outflow_cbc(sigma=0.25, kappa2=0.1, mach=0.1 / 3 ** -0.5)
-        g.step(20)
-        out[launch] = g.populations()
-    np.testing.assert_array_equal(out["triples"], out["pairs"])
+    for launch in ("triples", "single"):
+        g = lbm.Lattice(mask, 0.58, precision="fp32", collision="mrt", lateral="periodic",
+                        u_in=0.1, noise_amp=0.0, seed=1, launch=launch, history_cap=86)
+        g.init_fields(*vortex_fields(nx, ny, 0.1, nx - 14.5, ny / 2 - 0.3))
+        g.set_outflow_cbc(**cbc)
+        for n in (40, 7, 34, 2, 3):
+            g.step(n)
+        out[launch] = (g.populations(), g.force_history()[0])
+    (f1, fx1), (f0, fx0) = out["triples"], out["single"]
+    print("cbc triples vs single: populations that differ", np.count_nonzero(f1 != f0), flush=True)
+    np.testing.assert_array_equal(f1, f0)
+    np.testing.assert_allclose(fx1, fx0, rtol=0, atol=1e-5 * np.max(np.abs(fx0)))
