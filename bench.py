@@ -615,8 +615,9 @@ def main():
                "zouhe_mlups": nodes / (ms_zh * 1e-3) / 1e6,
                "zouhe_pairs_mlups": nodes / (ms_zh2 * 1e-3) / 1e6,
                "setting": "same lattice with periodic laterals; characteristic outflow, "
-                          "sigma 0.25, kappa_2 = Ma; two steps per launch (no three-step "
-                          "form), ratio_to_zouhe_pairs against Zou & He on that schedule"}
+                          "sigma 0.25, kappa_2 = Ma; ratio_to_zouhe against Zou & He on the "
+                          "timed schedule (three steps per launch for both), "
+                          "ratio_to_zouhe_pairs against Zou & He at two steps per launch"}
     big = None
     if not args.no_big:
         bx, by = 16384, 4096

@@ -89,11 +89,10 @@ enum { LBM_PATH_AUTO = 0, LBM_PATH_SCALAR = 1, LBM_PATH_VECTOR = 2 };
  *                x = nx-1 (Zou & He pressure or neural); LBM_X_PERIODIC:
  *                periodic in x (no inlet, no outlet).
  *   launch       LBM_LAUNCH_AUTO (0, the default): three time steps per
- *                kernel launch with the Zou & He and the neural outflow at
- *                FP32 and FP16 offsets, two per launch otherwise (the
- *                characteristic outflow, FP64), the rest of a count in
- *                two-step and single launches.  LBM_LAUNCH_TRIPLES: the
- *                same, rejected with LBM_FP64.  LBM_LAUNCH_PAIRS: two steps
+ *                kernel launch at FP32 and FP16 offsets (any outflow), two
+ *                per launch at FP64, the rest of a count in two-step and
+ *                single launches.  LBM_LAUNCH_TRIPLES: the same, rejected
+ *                with LBM_FP64.  LBM_LAUNCH_PAIRS: two steps
  *                per launch only.
  *                LBM_LAUNCH_SINGLE: one launch per time step.  Two-step
  *                launches walk their strips in one of two orders, chosen by
