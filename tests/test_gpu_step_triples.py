@@ -147,3 +147,28 @@ def test_triples_with_the_characteristic_outflow_equal_single_steps(net):
     print("cbc triples vs single: populations that differ", np.count_nonzero(f1 != f0), flush=True)
     np.testing.assert_array_equal(f1, f0)
     np.testing.assert_allclose(fx1, fx0, rtol=0, atol=1e-5 * np.max(np.abs(fx0)))
+
+
+@pytest.mark.parametrize("outflow", ["nn", "cbc"])
+def test_triples_on_a_lattice_shorter_than_an_outlet_block(outflow):
+    # 60 x 16 with periodic laterals: an outlet block's staged rows wrap round
+    # the lattice about four times; three-step and single launches agree bit
+    # for bit
+    from test_gpu_cbc import FIXED
+    from paper_2506_05293_amd import geometry
+    nx, ny = 60, 16
+    mask = geometry.cylinder(nx, ny, 15, 7.5, 5.0)
+    _say("triples on 60 x 16 periodic,", outflow)
+    out = {}
+    for launch in ("triples", "single"):
+        g = lbm.Lattice(mask, 0.6, precision="fp32", collision="bgk", lateral="periodic",
+                        u_in=0.05, noise_amp=1e-3, seed=3, launch=launch)
+        if outflow == "nn":
+            P = {k: np.asarray(v, np.float32).astype(np.float64)
+                 for k, v in cases.random_params(8, w_scale=0.5, out_sd=2e-4).items()}
+            g.set_outflow_nn(P, mass_bound=1e9)
+        else:
+            g.set_outflow_cbc(**dict(FIXED, length=60.0))
+        g.step(31)
+        out[launch] = g.populations()
+    np.testing.assert_array_equal(out["triples"], out["single"])
