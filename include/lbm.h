@@ -68,7 +68,8 @@ enum { LBM_OUT_ZOUHE = 0, LBM_OUT_NN = 1, LBM_OUT_CBC = 2 };
 /* Kernel schedule of lbm_step (the populations agree bit for bit, see
  * lbm_step). */
 enum { LBM_LAUNCH_AUTO = 0, LBM_LAUNCH_SINGLE = 1, LBM_LAUNCH_PAIRS_PLAIN = 2,
-       LBM_LAUNCH_PAIRS_HELD = 3, LBM_LAUNCH_TRIPLES = 4, LBM_LAUNCH_PAIRS = 5 };
+       LBM_LAUNCH_PAIRS_HELD = 3, LBM_LAUNCH_TRIPLES = 4, LBM_LAUNCH_PAIRS = 5,
+       LBM_LAUNCH_TRIPLES_PLAIN = 6, LBM_LAUNCH_TRIPLES_HELD = 7 };
 /* Bulk tile of the one-step kernel: chosen by lattice size, or forced. */
 enum { LBM_PATH_AUTO = 0, LBM_PATH_SCALAR = 1, LBM_PATH_VECTOR = 2 };
 
@@ -94,14 +95,15 @@ enum { LBM_PATH_AUTO = 0, LBM_PATH_SCALAR = 1, LBM_PATH_VECTOR = 2 };
  *                single launches.  LBM_LAUNCH_TRIPLES: the same, rejected
  *                with LBM_FP64.  LBM_LAUNCH_PAIRS: two steps
  *                per launch only.
- *                LBM_LAUNCH_SINGLE: one launch per time step.  Two-step
- *                launches walk their strips in one of two orders, chosen by
- *                lattice size (the stores of a row held back by one row
- *                above 200 MB per population buffer, FP32 and FP64 only);
- *                LBM_LAUNCH_PAIRS_PLAIN and LBM_LAUNCH_PAIRS_HELD take
- *                two-step launches with one of them (HELD: not with
- *                LBM_FP16_OFFSET).  Every schedule gives the same
- *                populations bit for bit.
+ *                LBM_LAUNCH_SINGLE: one launch per time step.  Two- and
+ *                three-step launches walk their strips in one of two
+ *                orders, chosen by lattice size (the stores of a row held
+ *                back by one row above 200 MB per population buffer, FP32
+ *                and FP64 only); LBM_LAUNCH_PAIRS_PLAIN / _HELD and
+ *                LBM_LAUNCH_TRIPLES_PLAIN / _HELD take two- or three-step
+ *                launches with one of them (HELD: not with
+ *                LBM_FP16_OFFSET; TRIPLES: not with LBM_FP64).  Every
+ *                schedule gives the same populations bit for bit.
  *   bulk_path    tile of the one-step kernel: LBM_PATH_AUTO (0: one node per
  *                thread below 12M nodes, four per lane above), or forced
  *                LBM_PATH_SCALAR / LBM_PATH_VECTOR.  Same results.

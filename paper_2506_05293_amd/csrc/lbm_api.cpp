@@ -202,12 +202,14 @@ lbm_status check_params(const lbm_params* p) {
   if (p->lateral != LBM_LATERAL_WALLS && p->lateral != LBM_LATERAL_PERIODIC)
     return fail(LBM_EINVAL, "bad lateral %d", p->lateral);
   if (p->xbc != LBM_X_INOUT && p->xbc != LBM_X_PERIODIC) return fail(LBM_EINVAL, "bad xbc %d", p->xbc);
-  if (p->launch < LBM_LAUNCH_AUTO || p->launch > LBM_LAUNCH_PAIRS)
+  if (p->launch < LBM_LAUNCH_AUTO || p->launch > LBM_LAUNCH_TRIPLES_HELD)
     return fail(LBM_EINVAL, "bad launch %d", p->launch);
-  if (p->launch == LBM_LAUNCH_TRIPLES && !tri_supported(p->precision))
-    return fail(LBM_EINVAL, "LBM_LAUNCH_TRIPLES needs LBM_FP32_OFFSET or LBM_FP16_OFFSET");
-  if (p->launch == LBM_LAUNCH_PAIRS_HELD && p->precision == LBM_FP16_OFFSET)
-    return fail(LBM_EINVAL, "LBM_LAUNCH_PAIRS_HELD needs LBM_FP64 or LBM_FP32_OFFSET");
+  if ((p->launch == LBM_LAUNCH_TRIPLES || p->launch == LBM_LAUNCH_TRIPLES_PLAIN ||
+       p->launch == LBM_LAUNCH_TRIPLES_HELD) && !tri_supported(p->precision))
+    return fail(LBM_EINVAL, "three-step launches need LBM_FP32_OFFSET or LBM_FP16_OFFSET");
+  if ((p->launch == LBM_LAUNCH_PAIRS_HELD || p->launch == LBM_LAUNCH_TRIPLES_HELD) &&
+      p->precision == LBM_FP16_OFFSET)
+    return fail(LBM_EINVAL, "the held walk needs LBM_FP64 or LBM_FP32_OFFSET");
   if (p->bulk_path < LBM_PATH_AUTO || p->bulk_path > LBM_PATH_VECTOR)
     return fail(LBM_EINVAL, "bad bulk_path %d", p->bulk_path);
   if (!(p->tau > 0.5) || !std::isfinite(p->tau)) return fail(LBM_EINVAL, "tau must be > 0.5 (got %g)", p->tau);
@@ -313,6 +315,9 @@ struct lbm_ctx {
     L.tri_rows = tri_rows(L.tri_nx, p.ny, lay.pitch * int(elem_size(p.precision)), L.tri_out);
     L.tri_nslots = tri_waves(L.tri_nx, p.ny, L.tri_rows) + L.tri_out * kWaves;
     L.tri_chunk = tri_chunk(L.tri_nx);
+    L.tri_hold = p.launch == LBM_LAUNCH_TRIPLES_HELD    ? 1
+                 : p.launch == LBM_LAUNCH_TRIPLES_PLAIN ? 0
+                                                        : pair_hold(p.precision, 9 * lay.plane * int64_t(elem_size(p.precision)));
     L.nslots = (L.nspecial - 1 - kReducers + lay.ntx * lay.nty) * kWaves;
     L.xper = p.xbc == LBM_X_PERIODIC;
     L.yper = p.lateral == LBM_LATERAL_PERIODIC;
@@ -499,7 +504,8 @@ lbm_status lbm_step(lbm_ctx* c, int64_t nsteps) {
   // With params.launch = LBM_LAUNCH_AUTO or LBM_LAUNCH_TRIPLES and FP32 or
   // FP16 offsets, three steps run in each launch (any outflow); the rest of
   // the count as below.
-  const bool triples = (c->p.launch == LBM_LAUNCH_AUTO || c->p.launch == LBM_LAUNCH_TRIPLES) &&
+  const bool triples = (c->p.launch == LBM_LAUNCH_AUTO || c->p.launch == LBM_LAUNCH_TRIPLES ||
+                        c->p.launch == LBM_LAUNCH_TRIPLES_PLAIN || c->p.launch == LBM_LAUNCH_TRIPLES_HELD) &&
                        tri_supported(c->p.precision);
   if (nsteps >= 3 && triples) {
     for (; s + 2 < nsteps; s += 3) {

@@ -111,6 +111,7 @@ struct StepLaunch {
   int tri_out;          // three-step launches: neural outlet blocks (0: Zou & He in the strips)
   int tri_chunk;        // three-step launches: strip workgroups per chunk dealt to an XCD
   int tri_rows;         // three-step launches: output rows per strip
+  int tri_hold;         // three-step launches: step-(t+3) stores held one row (pair_hold's rule)
   int nslots;           // partial slots written per step (waves of the
                         // neural and bulk workgroups)
   int xper, yper;

@@ -1436,6 +1436,7 @@ static hipError_t launch_pair_t(const StepLaunch& L, hipStream_t s) {
 // summed over the nodes the strip owns (its columns and rows), FP64 per wave
 // and step.
 constexpr int kTriCols = 58;
+constexpr int kTriRowsMax = 24;   // strip heights of the three-step walk (tri_rows)
 
 template <typename S>
 struct TriWave {
@@ -1467,7 +1468,7 @@ struct TriWave {
   }
 };
 
-template <typename S, int MRT>
+template <typename S, int MRT, int HOLD>
 __device__ __forceinline__ void tri_strip(const StepLaunch& L, int wave, int slot, double* part) {
   using T = typename Store<S>::T;
   const TriWave<S> w(L, wave);
@@ -1480,6 +1481,22 @@ __device__ __forceinline__ void tri_strip(const StepLaunch& L, int wave, int slo
   // the row being fetched (KP)
   uint32_t KM = 0, K0 = 0, K1 = 0, K2 = 0, KP = 0;
   double fx[3] = {0.0, 0.0, 0.0}, fy[3] = {0.0, 0.0, 0.0}, dm[3] = {0.0, 0.0, 0.0};
+  // HOLD: the link-chunk flags of all the strip's rows first, and a row's
+  // stores issued one row late (the held walk of pair_strip)
+  static_assert(kTriRowsMax + 6 <= 32, "one flag bit per strip row");
+  uint32_t lmask = 0;
+  if constexpr (HOLD) {
+    uint8_t fl[kTriRowsMax + 6];
+#pragma unroll
+    for (int jj = 0; jj < kTriRowsMax + 6; ++jj) {
+      const int yr = y0 - 3 + jj;
+      const bool row_in = L.yper || (yr >= 0 && yr < L.ny);
+      fl[jj] = (jj < nrow && row_in && col_in) ? L.chunk[w.wrap_row(yr, L) * L.nchunk + w.xs / kChunk]
+                                                : uint8_t(0);
+    }
+#pragma unroll
+    for (int jj = 0; jj < kTriRowsMax + 6; ++jj) lmask |= uint32_t(fl[jj] != 0) << jj;
+  }
   auto fetch = [&](int yr) {
     const int ys = w.wrap_row(yr, L);
     const int64_t row = int64_t(ys) * L.pitch;
@@ -1489,8 +1506,24 @@ __device__ __forceinline__ void tri_strip(const StepLaunch& L, int wave, int slo
           reinterpret_cast<const char*>(A + int64_t(q) * L.plane + row) + w.off));
     }
     KP = 0;
-    const bool row_in = L.yper || (yr >= 0 && yr < L.ny);
-    if (row_in && col_in && L.chunk[ys * L.nchunk + w.xs / kChunk]) KP = L.links[row + w.xs];
+    if constexpr (HOLD) {
+      if ((lmask >> (yr - (y0 - 3))) & 1u) KP = L.links[row + w.xs];
+    } else {
+      const bool row_in = L.yper || (yr >= 0 && yr < L.ny);
+      if (row_in && col_in && L.chunk[ys * L.nchunk + w.xs / kChunk]) KP = L.links[row + w.xs];
+    }
+  };
+  T H[9];
+  uint32_t oh = 0;
+  bool held = false;
+  auto flush = [&]() {
+    if (held) {
+#pragma unroll
+      for (int q = 0; q < 9; ++q)
+        Store<S>::st_cached(reinterpret_cast<S*>(reinterpret_cast<char*>(B + int64_t(q) * L.plane) + oh),
+                            H[q]);
+    }
+    held = false;
   };
   // one intermediate step at row y (absolute) from the rows lo, mid, hi of
   // the state before it, own = mid; nodes outside the lattice, solid or in
@@ -1518,6 +1551,7 @@ __device__ __forceinline__ void tri_strip(const StepLaunch& L, int wave, int slo
     for (int q = 0; q < 9; ++q) R2[q] = P[q];
     K2 = KP;
     if (j + 1 < nrow) fetch(yr + 1);
+    if constexpr (HOLD) flush();
     if (j >= 2) {
       inner(R0, R1, R2, K1, yr - 1, 0, S2);               // step t+1 at row yr - 1
       if (j >= 4) {
@@ -1530,10 +1564,17 @@ __device__ __forceinline__ void tri_strip(const StepLaunch& L, int wave, int slo
           const uint32_t o3 = uint32_t(y3) * uint32_t(L.pitch) * uint32_t(sizeof(S)) + w.off;
           T fx3 = T(0), fy3 = T(0), dm3 = T(0);
           if (out_col && pair_node<T, MRT>(L, KM, y3, U1, g, true, fx3, fy3, dm3)) {
+            if constexpr (HOLD) {
 #pragma unroll
-            for (int q = 0; q < 9; ++q)
-              Store<S>::st_cached(
-                  reinterpret_cast<S*>(reinterpret_cast<char*>(B + int64_t(q) * L.plane) + o3), g[q]);
+              for (int q = 0; q < 9; ++q) H[q] = g[q];
+              oh = o3;
+              held = true;
+            } else {
+#pragma unroll
+              for (int q = 0; q < 9; ++q)
+                Store<S>::st_cached(
+                    reinterpret_cast<S*>(reinterpret_cast<char*>(B + int64_t(q) * L.plane) + o3), g[q]);
+            }
           }
           fx[2] += double(fx3);
           fy[2] += double(fy3);
@@ -1560,6 +1601,7 @@ __device__ __forceinline__ void tri_strip(const StepLaunch& L, int wave, int slo
     K0 = K1;
     K1 = K2;
   }
+  if constexpr (HOLD) flush();
   // one slot per wave and step: [k n, (k + 1) n) for step k
   const int n = L.tri_nslots;
 #pragma unroll
@@ -2074,7 +2116,7 @@ constexpr int kTriSpecial = (1 + 3 * kReducers + 7) / 8 * 8;
 
 // OUT: 0 the Zou & He outlet inside the strips; OUTLET_NN the neural outlet
 // blocks (the first tri_out workgroups after the reducers).
-template <typename S, int MRT, int OUT>
+template <typename S, int MRT, int OUT, int HOLD>
 __global__ void __launch_bounds__(kBlock) k_step3(const StepLaunch L) {
   const int v = int(blockIdx.x);
   if (v < kTriSpecial) {
@@ -2105,21 +2147,29 @@ __global__ void __launch_bounds__(kBlock) k_step3(const StepLaunch L) {
   sb = L.tri_chunk > 0 ? xcd_remap_chunks(sb, nsb, L.tri_chunk) : xcd_remap(sb, nsb);
   const int slot = __builtin_amdgcn_readfirstlane((L.tri_out + sb) * kWaves + int(threadIdx.x >> 6));
   if (slot >= L.tri_nslots) return;                  // whole wave
-  tri_strip<S, MRT>(L, slot - L.tri_out * kWaves, slot, part);
+  tri_strip<S, MRT, HOLD>(L, slot - L.tri_out * kWaves, slot, part);
+}
+
+template <typename S, int MRT, int HOLD>
+static hipError_t launch_tri_h(const StepLaunch& L, hipStream_t s) {
+  const int blocks = kTriSpecial + (L.tri_nslots + kWaves - 1) / kWaves;
+  if (L.tri_out > 0 && L.outlet == OUTLET_NN)
+    hipLaunchKernelGGL((k_step3<S, MRT, OUTLET_NN, HOLD>), dim3(blocks), dim3(kBlock), 0, s, L);
+  else if (L.tri_out > 0 && L.outlet == OUTLET_CBC)
+    hipLaunchKernelGGL((k_step3<S, MRT, OUTLET_CBC, HOLD>), dim3(blocks), dim3(kBlock), 0, s, L);
+  else if (L.tri_out == 0)
+    hipLaunchKernelGGL((k_step3<S, MRT, 0, HOLD>), dim3(blocks), dim3(kBlock), 0, s, L);
+  else
+    return hipErrorInvalidValue;
+  return hipGetLastError();
 }
 
 template <typename S, int MRT>
 static hipError_t launch_tri_t(const StepLaunch& L, hipStream_t s) {
-  const int blocks = kTriSpecial + (L.tri_nslots + kWaves - 1) / kWaves;
-  if (L.tri_out > 0 && L.outlet == OUTLET_NN)
-    hipLaunchKernelGGL((k_step3<S, MRT, OUTLET_NN>), dim3(blocks), dim3(kBlock), 0, s, L);
-  else if (L.tri_out > 0 && L.outlet == OUTLET_CBC)
-    hipLaunchKernelGGL((k_step3<S, MRT, OUTLET_CBC>), dim3(blocks), dim3(kBlock), 0, s, L);
-  else if (L.tri_out == 0)
-    hipLaunchKernelGGL((k_step3<S, MRT, 0>), dim3(blocks), dim3(kBlock), 0, s, L);
-  else
-    return hipErrorInvalidValue;
-  return hipGetLastError();
+  if constexpr (!std::is_same_v<S, __half>) {
+    if (L.tri_hold) return launch_tri_h<S, MRT, 1>(L, s);
+  }
+  return L.tri_hold ? hipErrorInvalidValue : launch_tri_h<S, MRT, 0>(L, s);
 }
 
 int tri_waves(int nx, int ny, int rows) {
@@ -2127,8 +2177,6 @@ int tri_waves(int nx, int ny, int rows) {
 }
 
 int strip_rows(int nx, int ny, int pitch_bytes, int cols, int reserved_waves, int max_rows);   // below
-
-constexpr int kTriRowsMax = 24;
 
 int tri_rows(int nx, int ny, int pitch_bytes, int outlet_blocks) {
   return strip_rows(nx, ny, pitch_bytes, kTriCols, outlet_blocks * kWaves, kTriRowsMax);

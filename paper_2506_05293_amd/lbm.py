@@ -23,7 +23,7 @@ LBM_LATERAL_WALLS, LBM_LATERAL_PERIODIC = 0, 1
 LBM_X_INOUT, LBM_X_PERIODIC = 0, 1
 LBM_OUT_ZOUHE, LBM_OUT_NN, LBM_OUT_CBC = 0, 1, 2
 LBM_LAUNCH_AUTO, LBM_LAUNCH_SINGLE, LBM_LAUNCH_PAIRS_PLAIN, LBM_LAUNCH_PAIRS_HELD = 0, 1, 2, 3
-LBM_LAUNCH_TRIPLES, LBM_LAUNCH_PAIRS = 4, 5
+LBM_LAUNCH_TRIPLES, LBM_LAUNCH_PAIRS, LBM_LAUNCH_TRIPLES_PLAIN, LBM_LAUNCH_TRIPLES_HELD = 4, 5, 6, 7
 LBM_PATH_AUTO, LBM_PATH_SCALAR, LBM_PATH_VECTOR = 0, 1, 2
 LBM_BATCH_PER_STEP, LBM_BATCH_PERSISTENT = 0, 1
 
@@ -972,7 +972,8 @@ _LAUNCH = {"persistent": LBM_BATCH_PERSISTENT, "per_step": LBM_BATCH_PER_STEP}
 
 _STEP_LAUNCH = {"auto": LBM_LAUNCH_AUTO, "pairs": LBM_LAUNCH_PAIRS, "single": LBM_LAUNCH_SINGLE,
                 "pairs_plain": LBM_LAUNCH_PAIRS_PLAIN, "pairs_held": LBM_LAUNCH_PAIRS_HELD,
-                "triples": LBM_LAUNCH_TRIPLES}
+                "triples": LBM_LAUNCH_TRIPLES, "triples_plain": LBM_LAUNCH_TRIPLES_PLAIN,
+                "triples_held": LBM_LAUNCH_TRIPLES_HELD}
 _PATH = {"auto": LBM_PATH_AUTO, "scalar": LBM_PATH_SCALAR, "vector": LBM_PATH_VECTOR}
 # Kernel schedule of Lattice objects created without explicit launch /
 # bulk_path arguments (passed to the library in lbm_params).

@@ -58,7 +58,7 @@ def test_workspace_size_scales_with_precision():
 @pytest.mark.parametrize("field,value", [("tau", 0.5), ("tau", float("nan")), ("nx", 4),
                                          ("precision", 7), ("collision", 3), ("u_in", 0.6),
                                          ("rho_out", 0.0), ("history_cap", -1),
-                                         ("launch", 6), ("launch", -1), ("bulk_path", 3),
+                                         ("launch", 8), ("launch", -1), ("bulk_path", 3),
                                          ("bulk_path", -1)])
 def test_bad_parameters_are_rejected(field, value):
     with pytest.raises(lbm.LbmError) as e:
@@ -86,6 +86,13 @@ def test_three_step_launches_have_no_fp64_form():
     with pytest.raises(lbm.LbmError) as e:
         lbm.lbm_workspace_bytes(_params(launch=lbm.LBM_LAUNCH_TRIPLES, precision=lbm.LBM_FP64))
     assert e.value.status == lbm.LBM_EINVAL
+    for launch, prec in ((lbm.LBM_LAUNCH_TRIPLES_PLAIN, lbm.LBM_FP64),
+                         (lbm.LBM_LAUNCH_TRIPLES_HELD, lbm.LBM_FP64),
+                         (lbm.LBM_LAUNCH_TRIPLES_HELD, lbm.LBM_FP16_OFFSET)):
+        with pytest.raises(lbm.LbmError) as e:
+            lbm.lbm_workspace_bytes(_params(launch=launch, precision=prec))
+        assert e.value.status == lbm.LBM_EINVAL
+    assert lbm.lbm_workspace_bytes(_params(launch=lbm.LBM_LAUNCH_TRIPLES_HELD)) > 0
 
 
 def test_create_checks_workspace_without_touching_it():

@@ -172,3 +172,29 @@ def test_triples_on_a_lattice_shorter_than_an_outlet_block(outflow):
         g.step(31)
         out[launch] = g.populations()
     np.testing.assert_array_equal(out["triples"], out["single"])
+
+
+@pytest.mark.parametrize("outflow", ["zouhe", "nn", "cbc"])
+def test_held_triple_walk_equals_plain_walk(outflow):
+    # the two walks of the three-step strips differ only in when a row's
+    # stores are issued and how the link flags are read: the same
+    # populations and force partials bit for bit
+    from test_gpu_cbc import FIXED
+    case = cases.ragged("mrt", "periodic")
+    _say("held vs plain three-step walk,", outflow)
+    out = {}
+    for launch in ("triples_held", "triples_plain"):
+        g = _gpu(case, "fp32", 86, launch)
+        if outflow == "nn":
+            P = {k: np.asarray(v, np.float32).astype(np.float64)
+                 for k, v in cases.random_params(3, w_scale=0.5, out_sd=2e-4).items()}
+            g.set_outflow_nn(P, mass_bound=3e-4)
+        elif outflow == "cbc":
+            g.set_outflow_cbc(**dict(FIXED, length=float(case["mask"].shape[1])))
+        for n in (40, 7, 34, 2, 3):
+            g.step(n)
+        out[launch] = (g.populations(), g.force_history())
+    (f1, (fx1, fy1)), (f0, (fx0, fy0)) = out["triples_held"], out["triples_plain"]
+    np.testing.assert_array_equal(f1, f0)
+    np.testing.assert_array_equal(fx1, fx0)
+    np.testing.assert_array_equal(fy1, fy0)
